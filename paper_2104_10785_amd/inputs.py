@@ -1,0 +1,197 @@
+"""Seeded synthetic inputs for the partial-SVD / numerical-rank workloads.
+
+This module only draws random numbers and builds test matrices; it holds none
+of the Golub-Kahan arithmetic. Both the CPU oracle side and the GPU side of the
+tests and of the benchmark take their inputs from here, so that the two are
+always fed bit-identical data.
+
+Workloads (all synthetic, every seed fixed):
+
+* ``svd_matrix``      A = Q1 diag(s) Q2^T with Haar-random orthonormal factors
+                      (a matrix with a prescribed spectrum, so every singular
+                      value is known in closed form).
+* ``product_matrix``  A = M N with Gaussian M (m x l), N (l x n): the exact
+                      rank-l inputs of the paper's experiments (Section 5).
+* ``lowrank_noise``   A = U_f diag(decay^i) V_f^T + E, E iid Gaussian: the
+                      large low-rank-plus-noise matrix, built in row blocks
+                      with one child seed per block so the result does not
+                      depend on the number of threads.
+* ``start_vector``    the N(2, 1) start vector of Algorithm 1.
+* ``batch_problems``  many small uneven matrices with geometric spectra.
+* ``drift_sequence``  a slowly changing matrix sequence A_t = A_{t-1} + dA_t.
+"""
+from __future__ import annotations
+
+import concurrent.futures as _cf
+import os
+
+import numpy as np
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def haar(rng: np.random.Generator, m: int, n: int) -> np.ndarray:
+    """m x n (n <= m) matrix with orthonormal columns, Haar-distributed.
+
+    QR of a Gaussian matrix with each column multiplied by the sign of the
+    matching diagonal entry of R (Mezzadri's correction), so the distribution
+    is exactly Haar and the result is a deterministic function of the draw.
+    """
+    if n > m:
+        raise ValueError("haar: need n <= m")
+    g = rng.standard_normal((m, n))
+    q, r = np.linalg.qr(g)
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1.0
+    return q * d[None, :]
+
+
+def geometric_spectrum(count: int, ratio: float, first_power: int = 1) -> np.ndarray:
+    """s_i = ratio ** (i - 1 + first_power) for i = 1..count."""
+    return ratio ** np.arange(first_power, first_power + count, dtype=np.float64)
+
+
+def decade_spectrum(count: int = 1000, per_decade: float = 100.0) -> np.ndarray:
+    """s_i = 10 ** (-i / per_decade), i = 1..count (1-based index)."""
+    i = np.arange(1, count + 1, dtype=np.float64)
+    return 10.0 ** (-i / per_decade)
+
+
+def svd_matrix(m: int, n: int, s: np.ndarray, seed: int):
+    """A = Q1 diag(s) Q2^T in float64, with Q1 (m x p), Q2 (n x p), p = len(s).
+
+    Returns (A, Q1, Q2). The singular values of A are s (up to rounding) and
+    its singular vectors are the columns of Q1 and Q2.
+    """
+    s = np.asarray(s, dtype=np.float64)
+    p = s.shape[0]
+    if p > min(m, n):
+        raise ValueError("svd_matrix: len(s) > min(m, n)")
+    rng = _rng(seed)
+    q1 = haar(rng, m, p)
+    q2 = haar(rng, n, p)
+    a = (q1 * s[None, :]) @ q2.T
+    return a, q1, q2
+
+
+def product_matrix(m: int, n: int, l: int, seed: int) -> np.ndarray:
+    """A = M N, M (m x l) and N (l x n) iid standard Gaussian: rank exactly l."""
+    rng = _rng(seed)
+    mm = rng.standard_normal((m, l))
+    nn = rng.standard_normal((l, n))
+    return mm @ nn
+
+
+def start_vector(m: int, seed: int, mean: float = 2.0, std: float = 1.0) -> np.ndarray:
+    """The start vector q ~ N(2, 1)^m of Algorithm 1 (float64, unnormalised)."""
+    return _rng(seed).normal(mean, std, m)
+
+
+def _threads() -> int:
+    n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def lowrank_noise(m: int, n: int, rank: int, decay: float, noise_std: float,
+                  seed: int, dtype=np.float32, block_rows: int = 1000,
+                  threads: int | None = None):
+    """A = U_f diag(decay^i)_{i=1..rank} V_f^T + E, stored in `dtype`.
+
+    U_f (m x rank) and V_f (n x rank) are Haar; E has iid N(0, noise_std^2)
+    entries. The low-rank part and the noise are formed in float64 row block
+    by row block, then rounded once to `dtype`. Each row block draws its noise
+    from its own child seed, so the matrix is the same for any thread count.
+
+    Returns (A, s, U_f, V_f) with s the prescribed spectrum of the low-rank
+    part.
+    """
+    root = np.random.SeedSequence(seed)
+    kid_factors, kid_noise = root.spawn(2)
+    frng = np.random.default_rng(kid_factors)
+    uf = haar(frng, m, rank)
+    vf = haar(frng, n, rank)
+    s = decay ** np.arange(1, rank + 1, dtype=np.float64)
+    us = uf * s[None, :]
+    vft = np.ascontiguousarray(vf.T)
+    nblk = (m + block_rows - 1) // block_rows
+    seeds = kid_noise.spawn(nblk)
+    out = np.empty((m, n), dtype=dtype)
+
+    def work(b):
+        r0 = b * block_rows
+        r1 = min(m, r0 + block_rows)
+        blk = us[r0:r1] @ vft
+        if noise_std != 0.0:
+            g = np.random.default_rng(seeds[b]).standard_normal((r1 - r0, n))
+            blk += noise_std * g
+        out[r0:r1] = blk.astype(dtype)
+
+    nt = threads or _threads()
+    if nt == 1:
+        for b in range(nblk):
+            work(b)
+    else:
+        with _cf.ThreadPoolExecutor(nt) as ex:
+            list(ex.map(work, range(nblk)))
+    return out, s, uf, vf
+
+
+def batch_problems(count: int, seed: int, m_range=(500, 4000), n_range=(200, 2000),
+                   ratio_range=(0.8, 0.99), r_range=(5, 20), dtype=np.float32,
+                   materialize: bool = True):
+    """Many small uneven dense problems with geometric spectra.
+
+    Problem i has m_i ~ U{m_range}, n_i ~ U{n_range}, ratio rho_i ~ U[ratio_range),
+    r_i ~ U{r_range}, and A_i = Q1 diag(rho_i^(j-1))_{j=1..n_i} Q2^T (m_i >= n_i is
+    not required; the spectrum has min(m_i, n_i) entries).
+
+    Returns a list of dicts {m, n, rho, r, seed, A (if materialize)}.
+    """
+    rng = _rng(seed)
+    specs = []
+    for i in range(count):
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        rho = float(rng.uniform(ratio_range[0], ratio_range[1]))
+        r = int(rng.integers(r_range[0], r_range[1] + 1))
+        specs.append({"m": m, "n": n, "rho": rho, "r": r, "seed": seed * 100003 + i})
+    if materialize:
+        for sp in specs:
+            sp["A"] = batch_matrix(sp, dtype)
+    return specs
+
+
+def batch_matrix(spec, dtype=np.float32) -> np.ndarray:
+    """Materialise one problem of `batch_problems`."""
+    m, n, rho = spec["m"], spec["n"], spec["rho"]
+    p = min(m, n)
+    s = rho ** np.arange(p, dtype=np.float64)
+    a, _, _ = svd_matrix(m, n, s, spec["seed"])
+    return a.astype(dtype)
+
+
+def drift_base(m: int, n: int, ratio: float, seed: int, dtype=np.float32):
+    """A_0 = Q1 diag(ratio^(i-1))_{i=1..n} Q2^T (float64 factors, rounded once)."""
+    s = ratio ** np.arange(min(m, n), dtype=np.float64)
+    a, _, _ = svd_matrix(m, n, s, seed)
+    return a.astype(dtype), s
+
+
+def drift_update(m: int, n: int, rank: int, scale: float, seed: int, step: int) -> np.ndarray:
+    """dA_t = scale * G1 G2^T with G1 ~ N(0, 1/m) (m x rank), G2 ~ N(0, 1/n) (n x rank).
+
+    The 1/m and 1/n variances make ||dA_t||_2 about `scale`, so the sequence
+    changes slowly relative to a unit top singular value.
+    """
+    ss = np.random.SeedSequence([seed, step])
+    rng = np.random.default_rng(ss)
+    g1 = rng.standard_normal((m, rank)) / np.sqrt(m)
+    g2 = rng.standard_normal((n, rank)) / np.sqrt(n)
+    return scale * (g1 @ g2.T)
+
+
+def sketch_matrix(n: int, width: int, seed: int, dtype=np.float32) -> np.ndarray:
+    """Gaussian test matrix Omega (n x width) for the sketch A Omega."""
+    return _rng(seed).standard_normal((n, width)).astype(dtype)

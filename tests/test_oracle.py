@@ -1,0 +1,247 @@
+"""Pins for the float64 oracle: closed forms, brute force, invariants, special cases.
+
+Nothing here touches the GPU or the HIP library. Each test checks the oracle
+against something other than itself: a prescribed spectrum (A = Q1 diag(s) Q2^T),
+a brute-force Jacobi SVD, an exact-rank product, the Golub-Kahan full reduction,
+or the relations of eq. 2.4.
+"""
+import numpy as np
+import pytest
+
+from oracle import checks, gk, jacobi, rank
+from paper_2104_10785_amd import inputs
+
+
+def rel(a, b):
+    return np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b)))
+
+
+# ----------------------------------------------------------------- Jacobi pin
+def test_jacobi_prescribed_spectrum():
+    s = np.array([5.0, 3.0, 2.5, 1.0, 0.5, 1e-3, 1e-6, 1e-9])
+    A, Q1, Q2 = inputs.svd_matrix(20, 8, s, seed=11)
+    U, sj, V = jacobi.jacobi_svd(A)
+    # absolute accuracy ~ eps * ||A||; tiny sigma only to that level
+    assert np.max(np.abs(sj - s)) < 50 * np.finfo(float).eps * s[0]
+    assert np.max(np.abs(sj[:5] - s[:5]) / s[:5]) < 1e-14
+    assert checks.orth_error(U[:, :6]) < 1e-13 and checks.orth_error(V) < 1e-13
+    assert np.max(np.abs((U * sj) @ V.T - A)) < 1e-14 * s[0] * 20
+
+
+def test_jacobi_wide_and_against_lapack():
+    rng = np.random.default_rng(4)
+    for shape in [(48, 32), (17, 29), (1, 6), (6, 1)]:
+        A = rng.standard_normal(shape)
+        U, sj, V = jacobi.jacobi_svd(A)
+        sl = np.linalg.svd(A, compute_uv=False)
+        assert np.max(np.abs(sj[: sl.size] - sl)) < 1e-13 * sl[0]
+        assert np.max(np.abs((U * sj) @ V.T - A)) < 1e-13 * sl[0]
+
+
+# ------------------------------------------------------- GK: exact reduction
+def test_full_dimension_reduction_gives_all_singular_values():
+    # Golub-Kahan run to k = min(m, n) without restart reduces A completely:
+    # the singular values of B are those of A (closed form here).
+    s = np.geomspace(10.0, 0.01, 40)
+    A, _, _ = inputs.svd_matrix(60, 40, s, seed=2)
+    q = inputs.start_vector(60, seed=3)
+    eps = gk.BreakThreshold(1e-14, True)
+    fac = gk.first_cycle(A, q, 40, eps, 2)
+    sb = np.linalg.svd(fac.H, compute_uv=False)
+    assert rel(sb[:40], s) < 1e-12
+
+
+def test_projected_matrix_equals_explicit_projection():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((50, 30))
+    q = inputs.start_vector(50, seed=1)
+    fac = gk.first_cycle(A, q, 12, gk.BreakThreshold(1e-12, True), 2)
+    # H = Q^T A P (eq. 2.4 with orthonormal bases)
+    assert np.max(np.abs(fac.Q.T @ A @ fac.P - fac.H)) < 1e-13 * np.linalg.norm(A, 2)
+    assert checks.relation_error(A, fac.P, fac.Q, fac.H) < 1e-15 * 50
+    assert checks.transpose_relation_error(A, fac.P, fac.Q, fac.H, fac.alpha_res, fac.p_res) < 1e-14
+    assert checks.orth_error(fac.P) < 1e-14 and checks.orth_error(fac.Q) < 1e-14
+    # lower bidiagonal with non-negative entries (eq. 2.3)
+    H = fac.H
+    assert np.all(np.diag(H) > 0) and np.all(np.diag(H, -1) > 0)
+    assert np.count_nonzero(np.triu(H, 1)) == 0 and np.count_nonzero(np.tril(H, -2)) == 0
+
+
+def test_against_jacobi_tiny_random_graded_and_deficient():
+    rng = np.random.default_rng(9)
+    cases = [rng.standard_normal((30, 20)),
+             rng.standard_normal((24, 16)) * np.geomspace(1, 1e-8, 16)[None, :],
+             inputs.product_matrix(28, 18, 4, seed=3)]
+    for A in cases:
+        m, n = A.shape
+        Uj, sj, Vj = jacobi.jacobi_svd(A)
+        r = 4
+        out = gk.partial_svd(A, r, n, 1e-12, 0, inputs.start_vector(m, seed=7))
+        assert out["status"] == gk.OK
+        assert np.max(np.abs(out["sigma"] - sj[:r])) < 1e-13 * sj[0]
+        al = checks.alignment(Uj[:, :r], Vj[:, :r], out["U"], out["V"])
+        assert np.min(al) > 1 - 1e-10
+
+
+# --------------------------------------------------- the CPU-sized workload
+@pytest.fixture(scope="module")
+def c1():
+    s = inputs.decade_spectrum(1000)
+    A, Q1, Q2 = inputs.svd_matrix(2000, 1000, s, seed=0)
+    q = inputs.start_vector(2000, seed=1)
+    return A, Q1, Q2, s, q
+
+
+def test_c1_top10_closed_form(c1):
+    A, Q1, Q2, s, q = c1
+    out = gk.partial_svd(A, 10, 30, 1e-10, 50, q, record=True)
+    assert out["status"] == gk.OK and out["nconv"] == 10
+    assert rel(out["sigma"], s[:10]) < 1e-12
+    # Davis-Kahan/Wedin: sin(angle) <= residual / gap, gap(sigma_10) ~ 2.3 %
+    al = checks.alignment(Q1[:, :10], Q2[:, :10], out["U"], out["V"])
+    assert np.min(al) > 1 - 1e-8
+    r1, r2 = checks.triplet_residuals(A, out["sigma"], out["U"], out["V"])
+    assert np.max(r1) < 1e-13
+    assert np.max(r2) <= 1e-10 * s[0] * (1 + 1e-6)
+    # the residual estimate is the true residual (third relation of eq. 2.4)
+    assert np.max(np.abs(r2 - out["res_est"])) < 1e-13
+    # relations hold on every cycle, including restarted ones
+    assert len(out["cycles"]) >= 2
+    for c in out["cycles"]:
+        assert checks.relation_error(A, c["P"], c["Q"], c["H"]) < 1e-13
+        assert checks.transpose_relation_error(A, c["P"], c["Q"], c["H"], c["alpha_res"],
+                                               c["p_res"]) < 1e-13
+        assert checks.orth_error(c["P"]) < 1e-13 and checks.orth_error(c["Q"]) < 1e-13
+    # metrics of the experiments section
+    assert checks.err_rel(A, out["sigma"], out["U"], out["V"]) < 1e-10
+
+
+def test_restart_keeps_exact_relations():
+    s = np.geomspace(1.0, 1e-3, 120)
+    A, _, _ = inputs.svd_matrix(200, 150, s, seed=8)
+    q = inputs.start_vector(200, seed=9)
+    eps = gk.BreakThreshold(1e-12, True)
+    fac = gk.first_cycle(A, q, 20, eps, 2)
+    X, sv, Y = gk.ritz(fac.H)
+    l = 12
+    Pt = fac.P @ Y[:, :l]
+    Qt = fac.Q @ X[:, :l]
+    rho = fac.alpha_res * X[-1, :l]
+    # A P~ = Q~ Sigma_l and Q~^T A p_{l+1} = rho
+    assert np.max(np.abs(A @ Pt - Qt * sv[None, :l])) < 1e-14 * 200
+    assert np.max(np.abs(Qt.T @ (A @ fac.p_res) - rho)) < 1e-14 * 200
+    fac2 = gk.restart_cycle(A, fac, X, sv, Y, l, 20, eps, 2)
+    H = fac2.H
+    assert H.shape == (20, 20)
+    assert np.allclose(np.diag(H)[:l], sv[:l]) and np.allclose(H[:l, l], rho)
+    assert checks.relation_error(A, fac2.P, fac2.Q, H) < 1e-14 * 10
+    assert checks.transpose_relation_error(A, fac2.P, fac2.Q, H, fac2.alpha_res, fac2.p_res) < 1e-13
+    assert np.max(np.abs(fac2.Q.T @ A @ fac2.P - H)) < 1e-13
+
+
+def test_restarts_converge_to_closed_form():
+    s = np.concatenate([np.geomspace(1.0, 0.5, 8), np.geomspace(0.45, 0.01, 92)])
+    A, Q1, Q2 = inputs.svd_matrix(300, 100, s, seed=21)
+    out = gk.partial_svd(A, 8, 14, 1e-11, 200, inputs.start_vector(300, seed=22))
+    assert out["restarts"] > 0 and out["status"] == gk.OK
+    assert rel(out["sigma"], s[:8]) < 1e-12
+    assert np.min(checks.alignment(Q1[:, :8], Q2[:, :8], out["U"], out["V"])) > 1 - 1e-9
+
+
+def test_wide_matrix():
+    s = np.geomspace(3.0, 0.1, 40)
+    A, Q1, Q2 = inputs.svd_matrix(40, 90, s, seed=31)
+    out = gk.partial_svd(A, 5, 25, 1e-12, 50, inputs.start_vector(40, seed=1))
+    assert out["status"] == gk.OK and rel(out["sigma"], s[:5]) < 1e-12
+
+
+# ----------------------------------------------------------- special cases
+def test_rank_one():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(40)
+    y = rng.standard_normal(25)
+    A = np.outer(x, y)
+    out = gk.partial_svd(A, 1, 3, 1e-12, 0, inputs.start_vector(40, seed=2))
+    assert out["status"] == gk.OK
+    assert abs(out["sigma"][0] - np.linalg.norm(x) * np.linalg.norm(y)) < 1e-13 * out["sigma"][0]
+    assert abs(abs(out["U"][:, 0] @ x) / np.linalg.norm(x) - 1) < 1e-14
+    assert out["breakdown"] is not None and out["matvecs"] <= 4
+    rr = rank.numerical_rank(A, 1e-8, inputs.start_vector(40, seed=2))
+    assert rr["rank"] == 1 and rr["rank_sturm"] == 1 and rr["steps"] == 1
+
+
+def test_lucky_breakdown_rank_deficient():
+    A = inputs.product_matrix(50, 30, 3, seed=4)
+    out = gk.partial_svd(A, 5, 10, 1e-10, 3, inputs.start_vector(50, seed=5))
+    assert out["status"] == gk.RANK_DEFICIENT and out["sigma"].size == 3
+    sl = np.linalg.svd(A, compute_uv=False)
+    assert rel(out["sigma"], sl[:3]) < 1e-13
+    r1, r2 = checks.triplet_residuals(A, out["sigma"], out["U"], out["V"])
+    assert max(r1.max(), r2.max()) < 1e-11 * sl[0]
+
+
+def test_zero_matrix():
+    A = np.zeros((10, 6))
+    out = gk.partial_svd(A, 2, 4, 1e-10, 1, inputs.start_vector(10, seed=1))
+    assert out["status"] == gk.RANK_DEFICIENT and out["sigma"].size == 0
+    rr = rank.numerical_rank(A, 1e-6, inputs.start_vector(10, seed=1))
+    assert rr["rank"] == 0
+
+
+def test_argument_validation():
+    A = np.ones((5, 4))
+    q = np.ones(5)
+    for r, k in [(0, 2), (3, 2), (2, 5)]:
+        with pytest.raises(ValueError):
+            gk.partial_svd(A, r, k, 1e-8, 0, q)
+    with pytest.raises(ValueError):
+        gk.partial_svd(A, 1, 2, -1.0, 0, q)
+
+
+def test_nan_input_raises():
+    A = np.ones((6, 5))
+    A[2, 3] = np.nan
+    with pytest.raises(FloatingPointError):
+        gk.partial_svd(A, 1, 3, 1e-8, 0, np.ones(6))
+
+
+# ------------------------------------------------------------------- rank
+def test_sturm_count_against_explicit_tridiagonal():
+    rng = np.random.default_rng(3)
+    for size in [1, 2, 7, 40, 101]:
+        e = np.abs(rng.standard_normal(size)) * np.geomspace(1, 1e-6, size)
+        T = np.diag(e, 1) + np.diag(e, -1)
+        lam = np.linalg.eigvalsh(T)
+        for tau in [1e-7, 1e-4, 0.1, 0.5, 2.0]:
+            assert rank.count_above(e, tau) == int(np.count_nonzero(lam > tau))
+
+
+@pytest.mark.parametrize("l", [1, 5, 37])
+def test_rank_of_exact_products(l):
+    A = inputs.product_matrix(300, 200, l, seed=5)
+    rr = rank.numerical_rank(A, 1e-8, inputs.start_vector(300, seed=2))
+    assert rr["rank"] == l and rr["rank_sturm"] == l
+    assert l <= rr["steps"] <= l + 3
+    r_paper, kp = gk.paper_rank(A, inputs.start_vector(300, seed=2))
+    assert r_paper == l and l <= kp <= l + 3
+
+
+def test_rank_c1_log_midpoints(c1):
+    A, _, _, s, q = c1
+    # s_i = 10^(-i/100); tau relative to sigma_1 = s_1. The literal 1e-6 * s_1
+    # equals s_601, so the exact test uses the two log-midpoints around it.
+    for tau, want in [(10 ** -6.005, 601), (10 ** -5.995, 600)]:
+        rr = rank.numerical_rank(A, tau, q)
+        assert rr["rank"] == want and rr["rank_sturm"] == want
+        assert want == int(np.count_nonzero(s > tau * s[0]))
+
+
+# ------------------------------------------------------- paper-faithful forms
+def test_paper_fsvd_matches_closed_form(c1):
+    A, Q1, Q2, s, q = c1
+    sigma, U, V, kp = gk.paper_fsvd(A, q, 60, 10, eps=1e-10)
+    assert kp == 60
+    # the eig(B^T B) route squares the condition number: sigma accurate to
+    # ~eps * sigma_1^2 / sigma_i, vectors to the Krylov residual.
+    assert rel(sigma, s[:10]) < 1e-10
+    assert np.min(checks.alignment(Q1[:, :10], Q2[:, :10], U, V)) > 1 - 1e-8
