@@ -1,0 +1,59 @@
+/*
+ * gkb_kernels.h -- building blocks of the Golub-Kahan path, exposed on their
+ * own so each can be checked and timed in isolation.  Same conventions as
+ * gkb.h: device pointers unless stated, caller-owned memory, all work on
+ * `stream`, validation before any device work.
+ */
+#ifndef GKB_KERNELS_H
+#define GKB_KERNELS_H
+
+#include "gkb.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Workspace bytes for gkb_matvec with trans = 1 (0 if A is invalid). */
+size_t gkb_matvec_workspace_size(const gkb_matrix* A);
+
+/*
+ * The two products of Bidiag 1 (eq. (2.2); Algorithm 1's A p and A^T q):
+ *   trans = 0:  y (m doubles) = A x,   x: n elements
+ *   trans = 1:  y (n doubles) = A^T x, x: m elements, through the workspace
+ *               (deterministic two-phase reduction over row blocks).
+ * x is double for GKB_F64 and float for GKB_F32 / GKB_BF16; products
+ * accumulate in the matrix's precision class (double for GKB_F64, float
+ * otherwise) and the final sums are converted to double.
+ */
+gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, void* workspace,
+                      size_t ws_bytes, void* stream);
+
+/*
+ * C (M x N) = A (M x K) B (K x N), all column-major with leading dimensions
+ * lda >= M, ldb >= K, ldc >= M, on the 16x16x4 MFMA (float64 or float32).
+ * This is the Ritz-vector product V = P Y, U = Q X of Algorithm 2 (and the
+ * restart products).  dtype is GKB_F64 or GKB_F32.
+ */
+gkb_status gkb_gemm_tall(gkb_dtype dtype, const void* A, int64_t lda, int64_t M, int K, const void* B,
+                         int64_t ldb, int N, void* C, int64_t ldc, void* stream);
+
+/*
+ * bfloat16 storage of a float32 matrix: dst = RNE(src), row-major m x n
+ * (leading dimensions lds, ldd >= n).  NaN stays NaN (quiet).
+ */
+gkb_status gkb_cast_bf16(const float* src, int64_t lds, int64_t m, int64_t n, uint16_t* dst, int64_t ldd,
+                         void* stream);
+
+/*
+ * The random start of Algorithm 1, q ~ N(2, 1)^m, drawn on the device:
+ * Philox4x32-10 (Salmon et al., SC 2011) with counter (i, 0, 0, 0) and key
+ * (seed low, seed high) gives 32-bit words x0, x1; u_j = (x_j + 1) 2^-32;
+ * q_i = 2 + sqrt(-2 ln u0) cos(2 pi u1).  This is what gkb_partial_svd and
+ * gkb_numerical_rank use when opt->q1 is NULL.
+ */
+gkb_status gkb_start_vector(double* q, int64_t m, uint64_t seed, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GKB_KERNELS_H */

@@ -1,0 +1,696 @@
+// Host driver behind the C ABI (include/gkb.h): argument checks, workspace
+// layout, the Golub-Kahan cycle loop, thick restart, convergence test and the
+// final Ritz-vector GEMMs.  All device work is launched on the caller's stream;
+// the host synchronises once per cycle to read the bidiagonal coefficients.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gkb.h"
+#include "../../include/gkb_kernels.h"
+#include "gkb_internal.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+gkb_status fail(gkb_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define GKB_HIP(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(GKB_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline int64_t round64(int64_t x) { return (x + 63) / 64 * 64; }
+
+int basis_bytes(gkb_dtype d) { return d == GKB_F64 ? 8 : 4; }
+int elem_bytes(gkb_dtype d) { return d == GKB_F64 ? 8 : (d == GKB_F32 ? 4 : 2); }
+
+// Device workspace layout.  Offsets are 256-byte aligned.
+struct Layout {
+  int64_t ldm = 0, ldn = 0, ldpart = 0;
+  int ldh = 0, kcols = 0;
+  size_t Q[2] = {0, 0}, P[2] = {0, 0};
+  size_t w = 0, z = 0, part = 0, hpart = 0, h = 0, normpart = 0;
+  size_t qcoef = 0, pcoef = 0, sig = 0, flag = 0, Xs = 0, Ys = 0, rho = 0, q1 = 0;
+  size_t total = 0;
+};
+
+Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool small) {
+  Layout L;
+  const size_t tb = basis_bytes(dt);
+  const size_t acc = dt == GKB_F64 ? 8 : 4;
+  L.ldm = round64(m);
+  L.ldn = round64(n);
+  L.kcols = k + 1;
+  L.ldh = (int)round64(L.kcols);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L.Q[0] = take((size_t)L.kcols * L.ldm * tb);
+  L.P[0] = take((size_t)L.kcols * L.ldn * tb);
+  if (restart) {
+    L.Q[1] = take((size_t)L.kcols * L.ldm * tb);
+    L.P[1] = take((size_t)L.kcols * L.ldn * tb);
+  } else {
+    L.Q[1] = L.Q[0];
+    L.P[1] = L.P[0];
+  }
+  L.w = take((size_t)L.ldm * 8);
+  L.z = take((size_t)L.ldn * 8);
+  gkb::GemvTShape sh = gkb::gemv_t_shape(m, n, elem_bytes(dt));
+  // the scalar gemv_t path uses 256-column tiles with the same row blocking
+  L.ldpart = L.ldn;
+  L.part = take((size_t)sh.nb * L.ldpart * acc);
+  const int nch = std::max(gkb::dots_chunks(m), gkb::dots_chunks(n));
+  L.hpart = take((size_t)nch * L.ldh * 8);
+  L.h = take((size_t)L.ldh * 8);
+  L.normpart = take((size_t)std::max(gkb::update_blocks(m), gkb::update_blocks(n)) * 8);
+  L.qcoef = take((size_t)(L.kcols + 1) * 8);
+  L.pcoef = take((size_t)(L.kcols + 1) * 8);
+  L.sig = take((size_t)(2 * L.kcols + 8) * 8);
+  L.flag = take(4 * sizeof(int));
+  if (small) {
+    L.Xs = take((size_t)L.kcols * L.kcols * tb);
+    L.Ys = take((size_t)L.kcols * L.kcols * tb);
+    L.rho = take((size_t)L.ldh * 8);
+  }
+  L.q1 = take((size_t)L.ldm * 8);
+  L.total = off;
+  return L;
+}
+
+gkb_status check_matrix(const gkb_matrix* A) {
+  if (A == nullptr) return fail(GKB_ERR_INVALID, "A is NULL");
+  if (A->m < 1 || A->n < 1) return fail(GKB_ERR_INVALID, "need m >= 1 and n >= 1");
+  if (A->lda < A->n) return fail(GKB_ERR_INVALID, "need lda >= n");
+  if (A->dtype != GKB_F64 && A->dtype != GKB_F32 && A->dtype != GKB_BF16)
+    return fail(GKB_ERR_INVALID, "unknown dtype");
+  if (A->data == nullptr) return fail(GKB_ERR_INVALID, "A->data is NULL");
+  if (A->m > (int64_t)1 << 31 || A->n > (int64_t)1 << 31)
+    return fail(GKB_ERR_INVALID, "m and n must be below 2^31");
+  return GKB_OK;
+}
+
+gkb_status check_workspace(void* ws, size_t bytes, size_t need) {
+  if (ws == nullptr) return fail(GKB_ERR_WORKSPACE, "workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+    return fail(GKB_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < need)
+    return fail(GKB_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  return GKB_OK;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// Projected matrix of one cycle, as read back from the device.
+struct Proj {
+  int nq = 0, np = 0;
+  std::vector<double> H;  // nq x np row-major
+  double alpha_res = 0.0;
+  int breakdown = 0;      // 0 none, 1 beta, 2 alpha
+  double sig_seen = 0.0;  // largest accepted coefficient of the cycle
+  int64_t matvecs = 0;
+};
+
+template <typename TB>
+struct Solver {
+  gkb::MatrixRef A;
+  hipStream_t st;
+  Layout L;
+  char* ws;
+  int cur = 0;
+  double eps = 0.0;
+  int relative = 1;
+  int nsig = 0;
+
+  TB* Q(int b) { return reinterpret_cast<TB*>(ws + L.Q[b]); }
+  TB* P(int b) { return reinterpret_cast<TB*>(ws + L.P[b]); }
+  TB* Qc(int j) { return Q(cur) + (int64_t)j * L.ldm; }
+  TB* Pc(int j) { return P(cur) + (int64_t)j * L.ldn; }
+  double* w() { return reinterpret_cast<double*>(ws + L.w); }
+  double* z() { return reinterpret_cast<double*>(ws + L.z); }
+  void* part() { return ws + L.part; }
+  double* hpart() { return reinterpret_cast<double*>(ws + L.hpart); }
+  double* h() { return reinterpret_cast<double*>(ws + L.h); }
+  double* normpart() { return reinterpret_cast<double*>(ws + L.normpart); }
+  double* qcoef() { return reinterpret_cast<double*>(ws + L.qcoef); }
+  double* pcoef() { return reinterpret_cast<double*>(ws + L.pcoef); }
+  double* sig() { return reinterpret_cast<double*>(ws + L.sig); }
+  int* flag() { return reinterpret_cast<int*>(ws + L.flag); }
+  TB* Xs() { return reinterpret_cast<TB*>(ws + L.Xs); }
+  TB* Ys() { return reinterpret_cast<TB*>(ws + L.Ys); }
+  double* rho() { return reinterpret_cast<double*>(ws + L.rho); }
+  double* q1buf() { return reinterpret_cast<double*>(ws + L.q1); }
+
+  // Two classical Gram-Schmidt passes of x against V[:, 0..t); the last
+  // update leaves the partial sums of ||x||^2 in normpart.
+  hipError_t cgs2(const TB* V, int64_t ldv, int t, int64_t len, double* x) {
+    hipError_t e;
+    for (int pass = 0; pass < 2; ++pass) {
+      double* np_out = pass == 1 ? normpart() : nullptr;
+      if (t > 0) {
+        e = gkb::launch_dots<TB>(V, ldv, t, len, x, hpart(), L.ldh, h(), flag(), st);
+        if (e != hipSuccess) return e;
+        e = gkb::launch_update<TB>(V, ldv, t, len, x, h(), np_out, flag(), st);
+        if (e != hipSuccess) return e;
+      } else if (pass == 1) {
+        e = gkb::launch_update<TB>(V, ldv, 0, len, x, h(), np_out, flag(), st);
+        if (e != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
+  }
+
+  hipError_t normalize(const double* x, int64_t len, TB* out, double* coef_out, int track, int code,
+                       int index, bool test) {
+    hipError_t e = gkb::launch_normalize<TB>(x, len, normpart(), gkb::update_blocks(len), out, coef_out,
+                                             sig() + nsig, sig() + nsig + 1, test ? eps : 0.0, relative,
+                                             track, flag(), code, index, st);
+    ++nsig;
+    return e;
+  }
+
+  // Read flag and coefficients after a cycle (one host synchronisation).
+  gkb_status read_back(int ncoef, std::vector<double>& qc, std::vector<double>& pc, int* fl) {
+    qc.assign(ncoef, 0.0);
+    pc.assign(ncoef, 0.0);
+    GKB_HIP(hipMemcpyAsync(qc.data(), qcoef(), ncoef * sizeof(double), hipMemcpyDeviceToHost, st));
+    GKB_HIP(hipMemcpyAsync(pc.data(), pcoef(), ncoef * sizeof(double), hipMemcpyDeviceToHost, st));
+    GKB_HIP(hipMemcpyAsync(fl, flag(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    GKB_HIP(hipStreamSynchronize(st));
+    return GKB_OK;
+  }
+
+  // Start: Q[:,0] = q/||q||, z = A^T q_1, P[:,0] = z/||z||.
+  gkb_status start(const double* q1) {
+    nsig = 0;
+    GKB_HIP(gkb::launch_init_cycle(flag(), sig(), 0.0, st));
+    GKB_HIP(hipMemcpyAsync(w(), q1, (size_t)A.m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.m, w(), h(), normpart(), flag(), st));
+    GKB_HIP(normalize(w(), A.m, Qc(0), qcoef(), 0, 1, 0, false));
+    GKB_HIP(gkb::launch_gemv_t<TB>(A, Qc(0), nullptr, nullptr, 0, z(), part(), L.ldpart, flag(), st));
+    GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.n, z(), h(), normpart(), flag(), st));
+    GKB_HIP(normalize(z(), A.n, Pc(0), pcoef(), 1, 2, 0, false));
+    return GKB_OK;
+  }
+
+  // One Bidiag 1 step of the first cycle, s = 0-based step:
+  //   w = A p_s - alpha_s q_s -> CGS2 vs Q[0..s] -> q_{s+1}, beta
+  //   z = A^T q_{s+1} - beta p_s -> CGS2 vs P[0..s] -> p_{s+1}, alpha
+  gkb_status first_step(int s) {
+    GKB_HIP(gkb::launch_gemv_n<TB>(A, Pc(s), Qc(s), pcoef(), s, w(), flag(), st));
+    GKB_HIP(cgs2(Q(cur), L.ldm, s + 1, A.m, w()));
+    GKB_HIP(normalize(w(), A.m, Qc(s + 1), qcoef() + s + 1, 1, 1, s + 1, true));
+    GKB_HIP(gkb::launch_gemv_t<TB>(A, Qc(s + 1), Pc(s), qcoef(), s + 1, z(), part(), L.ldpart, flag(), st));
+    GKB_HIP(cgs2(P(cur), L.ldn, s + 1, A.n, z()));
+    GKB_HIP(normalize(z(), A.n, Pc(s + 1), pcoef() + s + 1, 1, 2, s + 1, true));
+    return GKB_OK;
+  }
+
+  // Assemble the first cycle's lower bidiagonal from the coefficients.
+  gkb_status assemble_first(int k, const std::vector<double>& qc, const std::vector<double>& pc,
+                            const int* fl, Proj& pr) {
+    int code = fl[0], idx = fl[1];
+    if (code == 3) return fail(GKB_ERR_NUMERIC, "NaN or Inf in a norm (non-finite input?)");
+    if (code == 1 && idx == 0) return fail(GKB_ERR_INVALID, "start vector is zero");
+    int nq, np;
+    if (code == 0) {
+      nq = k + 1;
+      np = k;
+      pr.matvecs = 1 + 2 * (int64_t)k;
+    } else if (code == 1) {
+      nq = np = idx;
+      pr.matvecs = 2 * (int64_t)idx;
+    } else {
+      np = idx;
+      nq = idx == 0 ? 1 : idx + 1;
+      pr.matvecs = 1 + 2 * (int64_t)idx;
+    }
+    pr.nq = nq;
+    pr.np = np;
+    pr.breakdown = code;
+    pr.H.assign((size_t)nq * std::max(np, 1), 0.0);
+    pr.sig_seen = 0.0;
+    for (int j = 0; j < np; ++j) {
+      pr.H[(size_t)j * np + j] = pc[j];
+      pr.sig_seen = std::max(pr.sig_seen, pc[j]);
+      if (j + 1 < nq) {
+        pr.H[(size_t)(j + 1) * np + j] = qc[j + 1];
+        pr.sig_seen = std::max(pr.sig_seen, qc[j + 1]);
+      }
+    }
+    pr.alpha_res = code == 0 ? pc[k] : 0.0;
+    if (code == 0) pr.sig_seen = std::max(pr.sig_seen, pc[k]);
+    return GKB_OK;
+  }
+};
+
+struct Ritz {
+  int kk = 0;
+  std::vector<double> s, X, Y;  // X nq x kk, Y np x kk row-major
+};
+
+gkb_status host_svd(const Proj& pr, Ritz& rz) {
+  rz.kk = std::min(pr.nq, pr.np);
+  rz.s.assign(std::max(rz.kk, 1), 0.0);
+  rz.X.assign((size_t)pr.nq * std::max(rz.kk, 1), 0.0);
+  rz.Y.assign((size_t)std::max(pr.np, 1) * std::max(rz.kk, 1), 0.0);
+  if (rz.kk == 0) return GKB_OK;
+  if (!gkb::dense_svd(pr.nq, pr.np, pr.H.data(), rz.s.data(), rz.X.data(), rz.Y.data()))
+    return fail(GKB_ERR_NUMERIC, "small SVD did not converge");
+  return GKB_OK;
+}
+
+template <typename TB>
+void to_colmajor(const std::vector<double>& M, int rows, int ldrow, int cols, std::vector<TB>& out) {
+  out.assign((size_t)rows * std::max(cols, 1), TB(0));
+  for (int c = 0; c < cols; ++c)
+    for (int i = 0; i < rows; ++i) out[(size_t)c * rows + i] = (TB)M[(size_t)i * ldrow + c];
+}
+
+template <typename TB>
+gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int max_restarts,
+                           const gkb_options& opt, void* workspace, double* sigma, TB* U, TB* V,
+                           gkb_stats* stats, hipStream_t st) {
+  const double t0 = now_ms();
+  double ms_host = 0.0;
+  Solver<TB> S;
+  S.A = {Am->data, Am->m, Am->n, Am->lda, (int)Am->dtype};
+  S.st = st;
+  int l = opt.keep ? opt.keep : std::min(r + (k - r) / 2, k - 1);
+  if (k == r) max_restarts = 0;
+  S.L = make_layout(Am->m, Am->n, Am->dtype, k, k > r, true);
+  S.ws = reinterpret_cast<char*>(workspace);
+  S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
+  S.relative = opt.eps_relative ? 1 : 0;
+  const double* q1 = opt.q1;
+  if (q1 == nullptr) {
+    GKB_HIP(gkb::launch_philox_start(S.q1buf(), Am->m, opt.seed, st));
+    q1 = S.q1buf();
+  }
+  gkb_status rc = S.start(q1);
+  if (rc != GKB_OK) return rc;
+  for (int s = 0; s < k; ++s) {
+    rc = S.first_step(s);
+    if (rc != GKB_OK) return rc;
+  }
+  std::vector<double> qc, pc;
+  int fl[2] = {0, 0};
+  rc = S.read_back(k + 2, qc, pc, fl);
+  if (rc != GKB_OK) return rc;
+  Proj pr;
+  rc = S.assemble_first(k, qc, pc, fl, pr);
+  if (rc != GKB_OK) return rc;
+  double sig_est = pr.sig_seen;
+  int64_t matvecs = pr.matvecs;
+  int restarts = 0;
+  Ritz rz;
+  std::vector<double> res;
+  int r_eff = 0, nconv = 0;
+  while (true) {
+    const double th0 = now_ms();
+    rc = host_svd(pr, rz);
+    ms_host += now_ms() - th0;
+    if (rc != GKB_OK) return rc;
+    const double thr = S.relative ? S.eps * sig_est : S.eps;
+    int avail = 0;
+    for (int i = 0; i < rz.kk; ++i)
+      if (rz.s[i] > thr) ++avail;
+    r_eff = std::min(r, avail);
+    res.assign(std::max(rz.kk, 1), 0.0);
+    for (int i = 0; i < rz.kk; ++i) res[i] = pr.alpha_res * std::fabs(rz.X[(size_t)(pr.nq - 1) * rz.kk + i]);
+    nconv = 0;
+    const double s0 = rz.kk ? rz.s[0] : 0.0;
+    for (int i = 0; i < r_eff; ++i)
+      if (res[i] <= tol * s0) ++nconv;
+    const bool done = pr.breakdown != 0 || (r_eff == r && nconv == r);
+    if (done || restarts >= max_restarts) break;
+    sig_est = std::max(sig_est, s0);
+    // ---- thick restart: P~ = P Y_l, Q~ = Q X_l, p_{l+1} = p_res, rho = alpha_res X[last, :l]
+    std::vector<TB> Xh, Yh;
+    to_colmajor<TB>(rz.X, pr.nq, rz.kk, l, Xh);
+    to_colmajor<TB>(rz.Y, pr.np, rz.kk, l, Yh);
+    std::vector<double> rho(l);
+    for (int i = 0; i < l; ++i) rho[i] = pr.alpha_res * rz.X[(size_t)(pr.nq - 1) * rz.kk + i];
+    GKB_HIP(hipMemcpyAsync(S.Xs(), Xh.data(), Xh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
+    GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
+    GKB_HIP(hipMemcpyAsync(S.rho(), rho.data(), l * sizeof(double), hipMemcpyHostToDevice, st));
+    const int nb = 1 - S.cur;
+    GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, S.Ys(), pr.np, l, S.P(nb), S.L.ldn,
+                                      st));
+    GKB_HIP(gkb::launch_gemm_tall<TB>(S.Q(S.cur), S.L.ldm, Am->m, pr.nq, S.Xs(), pr.nq, l, S.Q(nb), S.L.ldm,
+                                      st));
+    GKB_HIP(gkb::launch_copy_vec<TB>(S.P(S.cur) + (int64_t)pr.np * S.L.ldn, Am->n,
+                                     S.P(nb) + (int64_t)l * S.L.ldn, st));
+    S.cur = nb;
+    S.nsig = 0;
+    GKB_HIP(gkb::launch_init_cycle(S.flag(), S.sig(), sig_est, st));
+    for (int j = l; j < k; ++j) {
+      // w = A p_j - (j == l ? Q~ rho : alpha_j q_{j-1})
+      GKB_HIP(gkb::launch_gemv_n<TB>(S.A, S.Pc(j), j == l ? nullptr : S.Qc(j - 1), S.pcoef(), j, S.w(),
+                                     S.flag(), st));
+      if (j == l)
+        GKB_HIP(gkb::launch_update<TB>(S.Q(S.cur), S.L.ldm, l, Am->m, S.w(), S.rho(), nullptr, S.flag(), st));
+      GKB_HIP(S.cgs2(S.Q(S.cur), S.L.ldm, j, Am->m, S.w()));
+      GKB_HIP(S.normalize(S.w(), Am->m, S.Qc(j), S.qcoef() + j, 1, 1, j, true));
+      GKB_HIP(gkb::launch_gemv_t<TB>(S.A, S.Qc(j), S.Pc(j), S.qcoef(), j, S.z(), S.part(), S.L.ldpart,
+                                     S.flag(), st));
+      GKB_HIP(S.cgs2(S.P(S.cur), S.L.ldn, j + 1, Am->n, S.z()));
+      GKB_HIP(S.normalize(S.z(), Am->n, S.Pc(j + 1), S.pcoef() + j + 1, 1, 2, j + 1, true));
+    }
+    rc = S.read_back(k + 2, qc, pc, fl);
+    if (rc != GKB_OK) return rc;
+    if (fl[0] == 3) return fail(GKB_ERR_NUMERIC, "NaN or Inf in a norm");
+    // assemble the restarted k x k upper-triangular H
+    Proj np2;
+    int nq2 = k, npp = k;
+    if (fl[0] == 1) {
+      nq2 = fl[1];
+      npp = fl[1] + 1;
+      np2.matvecs = 2 * (int64_t)(fl[1] - l) + 1;
+    } else if (fl[0] == 2) {
+      nq2 = npp = fl[1];
+      np2.matvecs = 2 * (int64_t)(fl[1] - l);
+    } else {
+      np2.matvecs = 2 * (int64_t)(k - l);
+    }
+    np2.nq = nq2;
+    np2.np = npp;
+    np2.breakdown = fl[0];
+    np2.H.assign((size_t)nq2 * npp, 0.0);
+    double seen = 0.0;
+    for (int i = 0; i < l && i < nq2; ++i) {
+      if (i < npp) np2.H[(size_t)i * npp + i] = rz.s[i];
+      if (l < npp) np2.H[(size_t)i * npp + l] = rho[i];
+    }
+    for (int j = l; j < nq2; ++j) {
+      np2.H[(size_t)j * npp + j] = qc[j];
+      seen = std::max(seen, qc[j]);
+      if (j + 1 < npp) {
+        np2.H[(size_t)j * npp + j + 1] = pc[j + 1];
+        seen = std::max(seen, pc[j + 1]);
+      }
+    }
+    np2.alpha_res = fl[0] == 0 ? pc[k] : 0.0;
+    if (fl[0] == 0) seen = std::max(seen, pc[k]);
+    sig_est = std::max(sig_est, seen);
+    matvecs += np2.matvecs;
+    pr = np2;
+    ++restarts;
+  }
+  // ---- Ritz vectors: V = P Y_r, U = Q X_r
+  for (int i = 0; i < r; ++i) sigma[i] = i < r_eff ? rz.s[i] : 0.0;
+  if (r_eff > 0) {
+    std::vector<TB> Xh, Yh;
+    to_colmajor<TB>(rz.X, pr.nq, rz.kk, r_eff, Xh);
+    to_colmajor<TB>(rz.Y, pr.np, rz.kk, r_eff, Yh);
+    TB* Xd = S.Xs();
+    TB* Yd = S.Ys();
+    GKB_HIP(hipMemcpyAsync(Xd, Xh.data(), Xh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
+    GKB_HIP(hipMemcpyAsync(Yd, Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
+    GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, Yd, pr.np, r_eff, V, Am->n, st));
+    GKB_HIP(gkb::launch_gemm_tall<TB>(S.Q(S.cur), S.L.ldm, Am->m, pr.nq, Xd, pr.nq, r_eff, U, Am->m, st));
+    GKB_HIP(hipStreamSynchronize(st));
+  }
+  if (stats) {
+    stats->nconv = nconv;
+    stats->restarts = restarts;
+    stats->breakdown = pr.breakdown;
+    stats->returned = r_eff;
+    stats->matvecs = matvecs;
+    double mr = 0.0;
+    for (int i = 0; i < r_eff; ++i) mr = std::max(mr, res[i]);
+    stats->max_res_est = mr;
+    stats->sigma1_est = rz.kk ? rz.s[0] : 0.0;
+    stats->ms_total = now_ms() - t0;
+    stats->ms_host = ms_host;
+  }
+  if (r_eff < r) return GKB_RANK_DEFICIENT;
+  return nconv == r ? GKB_OK : GKB_NOT_CONVERGED;
+}
+
+template <typename TB>
+gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, const gkb_options& opt,
+                    void* workspace, int64_t* rank, int64_t* rank_sturm, double* sigma_out, int* nsigma,
+                    gkb_stats* stats, hipStream_t st) {
+  const double t0 = now_ms();
+  Solver<TB> S;
+  S.A = {Am->data, Am->m, Am->n, Am->lda, (int)Am->dtype};
+  S.st = st;
+  S.L = make_layout(Am->m, Am->n, Am->dtype, k, false, false);
+  S.ws = reinterpret_cast<char*>(workspace);
+  S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
+  S.relative = opt.eps_relative ? 1 : 0;
+  const double* q1 = opt.q1;
+  if (q1 == nullptr) {
+    GKB_HIP(gkb::launch_philox_start(S.q1buf(), Am->m, opt.seed, st));
+    q1 = S.q1buf();
+  }
+  gkb_status rc = S.start(q1);
+  if (rc != GKB_OK) return rc;
+  // launch in chunks; stop launching once a breakdown flag is seen
+  const int chunk = 32;
+  int fl[2] = {0, 0};
+  for (int s0 = 0; s0 < k; s0 += chunk) {
+    const int s1 = std::min(k, s0 + chunk);
+    for (int s = s0; s < s1; ++s) {
+      rc = S.first_step(s);
+      if (rc != GKB_OK) return rc;
+    }
+    if (s1 < k) {
+      GKB_HIP(hipMemcpyAsync(fl, S.flag(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      GKB_HIP(hipStreamSynchronize(st));
+      if (fl[0] != 0) break;
+    }
+  }
+  std::vector<double> qc, pc;
+  rc = S.read_back(k + 2, qc, pc, fl);
+  if (rc != GKB_OK) return rc;
+  Proj pr;
+  rc = S.assemble_first(k, qc, pc, fl, pr);
+  if (rc != GKB_OK) return rc;
+  const int np = pr.np, nq = pr.nq;
+  std::vector<double> alpha(std::max(np, 1)), beta(std::max(nq, 1)), s(std::max(np, 1));
+  for (int j = 0; j < np; ++j) alpha[j] = pc[j];
+  for (int j = 0; j + 1 < nq; ++j) beta[j] = qc[j + 1];
+  const double th = now_ms();
+  if (np > 0 && !gkb::bidiag_singular_values(nq, np, alpha.data(), beta.data(), s.data()))
+    return fail(GKB_ERR_NUMERIC, "bidiagonal SVD did not converge");
+  const double ms_host = now_ms() - th;
+  const double thr = np > 0 ? (tau_relative ? tau * s[0] : tau) : tau;
+  int64_t cnt = 0;
+  for (int j = 0; j < np; ++j)
+    if (s[j] > thr) ++cnt;
+  *rank = cnt;
+  if (rank_sturm) *rank_sturm = np > 0 ? gkb::bidiag_count_above(nq, np, alpha.data(), beta.data(), thr) : 0;
+  if (sigma_out)
+    for (int j = 0; j < np; ++j) sigma_out[j] = s[j];
+  if (nsigma) *nsigma = np;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->breakdown = pr.breakdown;
+    stats->returned = np;
+    stats->matvecs = pr.matvecs;
+    stats->sigma1_est = np > 0 ? s[0] : 0.0;
+    stats->ms_total = now_ms() - t0;
+    stats->ms_host = ms_host;
+  }
+  return GKB_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+void gkb_default_options(gkb_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->eps_relative = 1;
+  opt->seed = 0;
+}
+
+size_t gkb_workspace_size(const gkb_matrix* A, int r, int k, const gkb_options* opt) {
+  (void)opt;
+  if (check_matrix(A) != GKB_OK) return 0;
+  if (r < 1 || k < r || k > std::min(A->m, A->n)) return 0;
+  return make_layout(A->m, A->n, A->dtype, k, k > r, true).total;
+}
+
+gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
+                           const gkb_options* opt_in, void* workspace, size_t ws_bytes, double* sigma,
+                           void* U, void* V, gkb_stats* stats, void* stream) {
+  g_err.clear();
+  gkb_status rc = check_matrix(A);
+  if (rc != GKB_OK) return rc;
+  if (r < 1 || r > k) return fail(GKB_ERR_INVALID, "need 1 <= r <= k");
+  if (k > std::min(A->m, A->n)) return fail(GKB_ERR_INVALID, "need k <= min(m, n)");
+  if (!(tol >= 0.0)) return fail(GKB_ERR_INVALID, "need tol >= 0");
+  if (max_restarts < 0) return fail(GKB_ERR_INVALID, "need max_restarts >= 0");
+  if (sigma == nullptr || U == nullptr || V == nullptr)
+    return fail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
+  gkb_options opt;
+  gkb_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.keep != 0 && (opt.keep < r || opt.keep >= k))
+    return fail(GKB_ERR_INVALID, "need r <= keep < k");
+  if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
+  rc = check_workspace(workspace, ws_bytes, gkb_workspace_size(A, r, k, &opt));
+  if (rc != GKB_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (A->dtype == GKB_F64)
+    return run_partial_svd<double>(A, r, k, tol, max_restarts, opt, workspace, sigma,
+                                   reinterpret_cast<double*>(U), reinterpret_cast<double*>(V), stats, st);
+  return run_partial_svd<float>(A, r, k, tol, max_restarts, opt, workspace, sigma,
+                                reinterpret_cast<float*>(U), reinterpret_cast<float*>(V), stats, st);
+}
+
+size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options* opt) {
+  (void)opt;
+  if (check_matrix(A) != GKB_OK) return 0;
+  const int64_t kmin = std::min(A->m, A->n);
+  const int64_t k = k_max ? k_max : kmin;
+  if (k < 1 || k > kmin) return 0;
+  return make_layout(A->m, A->n, A->dtype, (int)k, false, false).total;
+}
+
+gkb_status gkb_numerical_rank(const gkb_matrix* A, double tau, int tau_relative, int k_max,
+                              const gkb_options* opt_in, void* workspace, size_t ws_bytes, int64_t* rank,
+                              int64_t* rank_sturm, double* sigma_out, int* nsigma, gkb_stats* stats,
+                              void* stream) {
+  g_err.clear();
+  gkb_status rc = check_matrix(A);
+  if (rc != GKB_OK) return rc;
+  if (!(tau > 0.0)) return fail(GKB_ERR_INVALID, "need tau > 0");
+  const int64_t kmin = std::min(A->m, A->n);
+  const int64_t k = k_max ? k_max : kmin;
+  if (k < 1 || k > kmin) return fail(GKB_ERR_INVALID, "need 0 <= k_max <= min(m, n)");
+  if (rank == nullptr) return fail(GKB_ERR_INVALID, "rank must be non-NULL");
+  gkb_options opt;
+  gkb_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
+  rc = check_workspace(workspace, ws_bytes, gkb_rank_workspace_size(A, (int)k, &opt));
+  if (rc != GKB_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (A->dtype == GKB_F64)
+    return run_rank<double>(A, tau, tau_relative, (int)k, opt, workspace, rank, rank_sturm, sigma_out, nsigma,
+                            stats, st);
+  return run_rank<float>(A, tau, tau_relative, (int)k, opt, workspace, rank, rank_sturm, sigma_out, nsigma,
+                         stats, st);
+}
+
+const char* gkb_status_string(gkb_status s) {
+  switch (s) {
+    case GKB_OK: return "GKB_OK";
+    case GKB_NOT_CONVERGED: return "GKB_NOT_CONVERGED";
+    case GKB_RANK_DEFICIENT: return "GKB_RANK_DEFICIENT";
+    case GKB_ERR_INVALID: return "GKB_ERR_INVALID";
+    case GKB_ERR_HIP: return "GKB_ERR_HIP";
+    case GKB_ERR_NUMERIC: return "GKB_ERR_NUMERIC";
+    case GKB_ERR_WORKSPACE: return "GKB_ERR_WORKSPACE";
+  }
+  return "unknown";
+}
+
+const char* gkb_last_error(void) { return g_err.c_str(); }
+
+gkb_status gkb_host_dense_svd(int nq, int np, const double* H, double* s, double* X, double* Y) {
+  g_err.clear();
+  if (nq < 1 || np < 1 || !H || !s || !X || !Y) return fail(GKB_ERR_INVALID, "bad arguments");
+  if (!gkb::dense_svd(nq, np, H, s, X, Y)) return fail(GKB_ERR_NUMERIC, "no convergence or non-finite input");
+  return GKB_OK;
+}
+
+int64_t gkb_host_bidiag_count_above(int nq, int np, const double* alpha, const double* beta, double tau) {
+  if (np < 1 || (nq != np && nq != np + 1) || !alpha || (nq > 1 && !beta) || !(tau > 0)) return -1;
+  return gkb::bidiag_count_above(nq, np, alpha, beta, tau);
+}
+
+// ------------------------------------------------------------ building blocks
+size_t gkb_matvec_workspace_size(const gkb_matrix* A) {
+  if (check_matrix(A) != GKB_OK) return 0;
+  gkb::GemvTShape sh = gkb::gemv_t_shape(A->m, A->n, elem_bytes(A->dtype));
+  return align256((size_t)sh.nb * round64(A->n) * (A->dtype == GKB_F64 ? 8 : 4));
+}
+
+gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  g_err.clear();
+  gkb_status rc = check_matrix(A);
+  if (rc != GKB_OK) return rc;
+  if (!x || !y) return fail(GKB_ERR_INVALID, "x and y must be non-NULL");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  gkb::MatrixRef R{A->data, A->m, A->n, A->lda, (int)A->dtype};
+  if (trans == 0) {
+    if (A->dtype == GKB_F64)
+      GKB_HIP(gkb::launch_gemv_n<double>(R, (const double*)x, nullptr, nullptr, 0, y, nullptr, st));
+    else
+      GKB_HIP(gkb::launch_gemv_n<float>(R, (const float*)x, nullptr, nullptr, 0, y, nullptr, st));
+    return GKB_OK;
+  }
+  rc = check_workspace(workspace, ws_bytes, gkb_matvec_workspace_size(A));
+  if (rc != GKB_OK) return rc;
+  const int64_t ldpart = round64(A->n);
+  if (A->dtype == GKB_F64)
+    GKB_HIP(gkb::launch_gemv_t<double>(R, (const double*)x, nullptr, nullptr, 0, y, workspace, ldpart, nullptr,
+                                       st));
+  else
+    GKB_HIP(gkb::launch_gemv_t<float>(R, (const float*)x, nullptr, nullptr, 0, y, workspace, ldpart, nullptr,
+                                      st));
+  return GKB_OK;
+}
+
+gkb_status gkb_gemm_tall(gkb_dtype dtype, const void* A, int64_t lda, int64_t M, int K, const void* B,
+                         int64_t ldb, int N, void* C, int64_t ldc, void* stream) {
+  g_err.clear();
+  if (dtype != GKB_F64 && dtype != GKB_F32) return fail(GKB_ERR_INVALID, "dtype must be F64 or F32");
+  if (M < 0 || K < 0 || N < 0 || lda < M || ldb < K || ldc < M)
+    return fail(GKB_ERR_INVALID, "bad GEMM shape");
+  if ((M > 0 && N > 0) && (!A || !B || !C)) return fail(GKB_ERR_INVALID, "NULL operand");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (dtype == GKB_F64)
+    GKB_HIP(gkb::launch_gemm_tall<double>((const double*)A, lda, M, K, (const double*)B, ldb, N, (double*)C, ldc,
+                                          st));
+  else
+    GKB_HIP(gkb::launch_gemm_tall<float>((const float*)A, lda, M, K, (const float*)B, ldb, N, (float*)C, ldc,
+                                         st));
+  return GKB_OK;
+}
+
+gkb_status gkb_cast_bf16(const float* src, int64_t lds, int64_t m, int64_t n, uint16_t* dst, int64_t ldd,
+                         void* stream) {
+  g_err.clear();
+  if (!src || !dst || m < 1 || n < 1 || lds < n || ldd < n) return fail(GKB_ERR_INVALID, "bad cast arguments");
+  GKB_HIP(gkb::launch_cast_bf16(src, lds, m, n, dst, ldd, reinterpret_cast<hipStream_t>(stream)));
+  return GKB_OK;
+}
+
+gkb_status gkb_start_vector(double* q, int64_t m, uint64_t seed, void* stream) {
+  g_err.clear();
+  if (!q || m < 1) return fail(GKB_ERR_INVALID, "bad start-vector arguments");
+  GKB_HIP(gkb::launch_philox_start(q, m, seed, reinterpret_cast<hipStream_t>(stream)));
+  return GKB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,723 @@
+// HIP kernels for gfx950 (CDNA4): the Golub-Kahan bidiagonalization hot path.
+//
+//   gemv_n        w = A p - alpha q           (Bidiag 1, eq. 2.2, first line)
+//   gemv_t        z = A^T q - beta p          (eq. 2.2, second line), two
+//                 deterministic phases: per-row-block partial sums, then a
+//                 column reduction with the recurrence term fused in
+//   dots/update   classical Gram-Schmidt projection x <- x - V (V^T x)
+//                 (Algorithm 1's reorthogonalisation), float64 coefficients
+//   normalize     norm, breakdown test, scaling into the basis
+//   gemm_tall     C = A B for a tall column-major A and a small B on MFMA
+//                 (Ritz vectors V = P Y, U = Q X, and the restart GEMMs)
+//   cast_bf16     float32 -> bfloat16, round to nearest even
+//   philox_start  q ~ N(2, 1)^m from Philox4x32-10 + Box-Muller
+//
+// A is row-major (m x n, lda).  Bases are column-major with each vector
+// contiguous.  Every reduction has a fixed order (no float atomics), so two
+// runs on the same input are bitwise identical.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace gkb {
+
+// ---------------------------------------------------------------- types
+template <typename TA> struct Acc;
+template <> struct Acc<double> { using type = double; };
+template <> struct Acc<float> { using type = float; };
+template <> struct Acc<bf16> { using type = float; };
+
+__device__ __forceinline__ double to_acc(double x) { return x; }
+__device__ __forceinline__ float to_acc(float x) { return x; }
+__device__ __forceinline__ float to_acc(bf16 x) { return __uint_as_float(((uint32_t)x.bits) << 16); }
+
+// Unpack a 16-byte load into VN accumulator values.
+template <typename TA> struct Pack;
+template <> struct Pack<double> {
+  static constexpr int VN = 2;
+  __device__ __forceinline__ static void unpack(const uint4& u, double* o) {
+    o[0] = __hiloint2double((int)u.y, (int)u.x);
+    o[1] = __hiloint2double((int)u.w, (int)u.z);
+  }
+};
+template <> struct Pack<float> {
+  static constexpr int VN = 4;
+  __device__ __forceinline__ static void unpack(const uint4& u, float* o) {
+    o[0] = __uint_as_float(u.x);
+    o[1] = __uint_as_float(u.y);
+    o[2] = __uint_as_float(u.z);
+    o[3] = __uint_as_float(u.w);
+  }
+};
+template <> struct Pack<bf16> {
+  static constexpr int VN = 8;
+  __device__ __forceinline__ static void unpack(const uint4& u, float* o) {
+    o[0] = __uint_as_float(u.x << 16);
+    o[1] = __uint_as_float(u.x & 0xffff0000u);
+    o[2] = __uint_as_float(u.y << 16);
+    o[3] = __uint_as_float(u.y & 0xffff0000u);
+    o[4] = __uint_as_float(u.z << 16);
+    o[5] = __uint_as_float(u.z & 0xffff0000u);
+    o[6] = __uint_as_float(u.w << 16);
+    o[7] = __uint_as_float(u.w & 0xffff0000u);
+  }
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_stream(const void* p) {
+  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block (256 threads) sum in a fixed order; result valid in every thread.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = (red[0] + red[1]) + (red[2] + red[3]);
+  return t;
+}
+
+// ---------------------------------------------------------------- gemv_n
+// w[i] = sum_j A[i, j] p[j] - coef[cidx] * qprev[i]  (qprev may be null).
+// One wave owns R consecutive rows; lanes stride the row with 16-byte loads
+// (VECTOR) or scalars, and p is loaded once per column chunk for all R rows.
+template <typename TA, typename TB, int R, bool VECTOR>
+__global__ __launch_bounds__(256) void k_gemv_n(const TA* __restrict__ A, int64_t lda, int64_t m,
+                                                int64_t n, const TB* __restrict__ p,
+                                                const TB* __restrict__ qprev,
+                                                const double* __restrict__ coef, int cidx,
+                                                double* __restrict__ w, const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  using ACC = typename Acc<TA>::type;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * R;
+  if (row0 >= m) return;
+  const TA* rows[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) rows[r] = A + (row0 + r < m ? row0 + r : m - 1) * lda;
+  ACC acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0;
+  int64_t jtail = 0;
+  if (VECTOR) {
+    constexpr int VN = Pack<TA>::VN;
+    const int64_t nv = n / VN;
+    constexpr int U = 2;
+    for (int64_t v0 = lane; v0 < nv; v0 += 64 * U) {
+      uint4 a[U][R];
+      ACC pv[U][VN];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t v = v0 + 64 * u;
+        const bool ok = v < nv;
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[u][r] = ok ? ld_stream(rows[r] + v * VN) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) pv[u][e] = ok ? (ACC)p[v * VN + e] : (ACC)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ACC av[VN];
+          Pack<TA>::unpack(a[u][r], av);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) acc[r] += av[e] * pv[u][e];
+        }
+      }
+    }
+    jtail = nv * VN;
+  }
+  for (int64_t j = jtail + lane; j < n; j += 64) {
+    const ACC pj = (ACC)p[j];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += to_acc(rows[r][j]) * pj;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = wave_sum(acc[r]);
+  const double c = (qprev != nullptr) ? coef[cidx] : 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = row0 + r;
+    if (lane == r && i < m) {
+      double v = (double)acc[r];
+      if (qprev != nullptr) v -= c * (double)qprev[i];
+      w[i] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- gemv_t
+// Phase 1: part[b * ldpart + j] = sum_{i in row block b} A[i, j] q[i].
+// A block of 256 threads owns 256 * VN consecutive columns; rows of the
+// block's row range are streamed U at a time (U loads in flight per lane).
+template <typename TA, typename TB, bool VECTOR>
+__global__ __launch_bounds__(256) void k_gemv_t_part(const TA* __restrict__ A, int64_t lda, int64_t m,
+                                                     int64_t n, const TB* __restrict__ q,
+                                                     int64_t rows_per_block,
+                                                     typename Acc<TA>::type* __restrict__ part,
+                                                     int64_t ldpart, const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  using ACC = typename Acc<TA>::type;
+  constexpr int VN = VECTOR ? Pack<TA>::VN : 1;
+  constexpr int U = VECTOR ? 8 : 4;
+  const int64_t col0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * VN;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
+  int64_t r1 = r0 + rows_per_block;
+  if (r1 > m) r1 = m;
+  ACC acc[VN];
+#pragma unroll
+  for (int e = 0; e < VN; ++e) acc[e] = 0;
+  if (col0 < n) {
+    const bool full = col0 + VN <= n;
+    for (int64_t i = r0; i < r1; i += U) {
+      if (VECTOR && full) {
+        uint4 a[U];
+        ACC qv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool ok = i + u < r1;
+          a[u] = ok ? ld_stream(A + (i + u) * lda + col0) : make_uint4(0, 0, 0, 0);
+          qv[u] = ok ? (ACC)q[i + u] : (ACC)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          ACC av[Pack<TA>::VN];
+          Pack<TA>::unpack(a[u], av);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) acc[e] += av[e] * qv[u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (i + u < r1) {
+            const ACC qi = (ACC)q[i + u];
+            const TA* row = A + (i + u) * lda;
+#pragma unroll
+            for (int e = 0; e < VN; ++e)
+              if (col0 + e < n) acc[e] += to_acc(row[col0 + e]) * qi;
+          }
+        }
+      }
+    }
+  }
+  ACC* out = part + (int64_t)blockIdx.y * ldpart;
+#pragma unroll
+  for (int e = 0; e < VN; ++e)
+    if (col0 + e < n) out[col0 + e] = acc[e];
+}
+
+// Phase 2: z[j] = sum_b part[b][j] - coef[cidx] * pprev[j]  (pprev may be null).
+template <typename ACC, typename TB>
+__global__ __launch_bounds__(256) void k_gemv_t_reduce(const ACC* __restrict__ part, int64_t ldpart,
+                                                       int nb, int64_t n, const TB* __restrict__ pprev,
+                                                       const double* __restrict__ coef, int cidx,
+                                                       double* __restrict__ z,
+                                                       const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += (double)part[(int64_t)b * ldpart + j];
+  if (pprev != nullptr) s -= coef[cidx] * (double)pprev[j];
+  z[j] = s;
+}
+
+// ---------------------------------------------------------------- CGS
+// hpart[c * ldh + j] = sum_{i in chunk c} V[j * ldv + i] x[i]  for j < t.
+// Chunk = 64 * DE rows; each lane keeps its DE entries of x in registers and
+// each wave reduces one column at a time.
+constexpr int DE = 16;
+constexpr int DCOLS = 16;  // columns per block (4 per wave)
+template <typename TB>
+__global__ __launch_bounds__(256) void k_dots(const TB* __restrict__ V, int64_t ldv, int t, int64_t len,
+                                              const double* __restrict__ x, double* __restrict__ hpart,
+                                              int ldh, const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * 64 * DE;
+  double xr[DE];
+#pragma unroll
+  for (int e = 0; e < DE; ++e) {
+    const int64_t i = base + e * 64 + lane;
+    xr[e] = i < len ? x[i] : 0.0;
+  }
+  const int j0 = blockIdx.y * DCOLS;
+  int j1 = j0 + DCOLS;
+  if (j1 > t) j1 = t;
+  for (int j = j0 + wave; j < j1; j += 4) {
+    const TB* col = V + (int64_t)j * ldv;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < DE; ++e) {
+      const int64_t i = base + e * 64 + lane;
+      if (i < len) acc += (double)col[i] * xr[e];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) hpart[(int64_t)blockIdx.x * ldh + j] = acc;
+  }
+}
+
+// h[j] = sum_c hpart[c * ldh + j]; optionally hacc[j] += h[j] (record).
+__global__ __launch_bounds__(256) void k_dots_reduce(const double* __restrict__ hpart, int ldh,
+                                                     int nchunks, int t, double* __restrict__ h,
+                                                     const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= t) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += hpart[(int64_t)c * ldh + j];
+  h[j] = s;
+}
+
+// x[i] -= sum_{j<t} V[j * ldv + i] h[j]; if normpart, normpart[block] =
+// sum over the block's rows of x[i]^2 (after the update).
+constexpr int UE = 4;  // rows per thread in the update
+template <typename TB>
+__global__ __launch_bounds__(256) void k_update(const TB* __restrict__ V, int64_t ldv, int t, int64_t len,
+                                                double* __restrict__ x, const double* __restrict__ h,
+                                                double* __restrict__ normpart,
+                                                const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  __shared__ double red[4];
+  const int64_t base = (int64_t)blockIdx.x * 256 * UE + threadIdx.x;
+  double xr[UE];
+#pragma unroll
+  for (int e = 0; e < UE; ++e) {
+    const int64_t i = base + e * 256;
+    xr[e] = i < len ? x[i] : 0.0;
+  }
+  int j = 0;
+  for (; j + 4 <= t; j += 4) {
+    const double h0 = h[j], h1 = h[j + 1], h2 = h[j + 2], h3 = h[j + 3];
+    const TB* c0 = V + (int64_t)j * ldv;
+    const TB* c1 = c0 + ldv;
+    const TB* c2 = c1 + ldv;
+    const TB* c3 = c2 + ldv;
+#pragma unroll
+    for (int e = 0; e < UE; ++e) {
+      const int64_t i = base + e * 256;
+      if (i < len) {
+        xr[e] -= (double)c0[i] * h0;
+        xr[e] -= (double)c1[i] * h1;
+        xr[e] -= (double)c2[i] * h2;
+        xr[e] -= (double)c3[i] * h3;
+      }
+    }
+  }
+  for (; j < t; ++j) {
+    const double hj = h[j];
+    const TB* cj = V + (int64_t)j * ldv;
+#pragma unroll
+    for (int e = 0; e < UE; ++e) {
+      const int64_t i = base + e * 256;
+      if (i < len) xr[e] -= (double)cj[i] * hj;
+    }
+  }
+  double ss = 0.0;
+#pragma unroll
+  for (int e = 0; e < UE; ++e) {
+    const int64_t i = base + e * 256;
+    if (i < len) {
+      x[i] = xr[e];
+      ss += xr[e] * xr[e];
+    }
+  }
+  if (normpart != nullptr) {
+    const double tot = block_sum256(ss, red);
+    if (threadIdx.x == 0) normpart[blockIdx.x] = tot;
+  }
+}
+
+// nrm = sqrt(sum normpart).  Breakdown if nrm <= thr (thr = eps * sig_in or
+// eps), NaN/Inf -> numeric flag.  Otherwise out[i] = x[i] / nrm.  Block 0
+// records coef_out = nrm and sig_out = max(sig_in, nrm) (or sig_in when
+// !track).  Every block computes nrm identically, so all take the same branch.
+template <typename TB>
+__global__ __launch_bounds__(256) void k_normalize(const double* __restrict__ x, int64_t len,
+                                                   const double* __restrict__ normpart, int nparts,
+                                                   TB* __restrict__ out, double* __restrict__ coef_out,
+                                                   const double* __restrict__ sig_in,
+                                                   double* __restrict__ sig_out, double eps,
+                                                   int relative, int track, int* __restrict__ flag,
+                                                   int code, int index) {
+  if (flag[0] != 0) return;
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += 256) s += normpart[p];
+  const double tot = block_sum256(s, red);
+  const double nrm = sqrt(tot);
+  const double sin = *sig_in;
+  const double thr = relative ? eps * sin : eps;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(nrm < INFINITY)) {  // NaN or Inf
+    if (lead) {
+      flag[0] = 3;
+      flag[1] = index;
+      *coef_out = nrm;
+    }
+    return;
+  }
+  if (nrm <= thr) {
+    if (lead) {
+      flag[0] = code;
+      flag[1] = index;
+      *coef_out = nrm;
+      *sig_out = sin;
+    }
+    return;
+  }
+  if (lead) {
+    *coef_out = nrm;
+    *sig_out = track ? fmax(sin, nrm) : sin;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256)
+    out[i] = (TB)(x[i] / nrm);
+}
+
+__global__ void k_init_cycle(int* flag, double* sig0, double v) {
+  if (threadIdx.x == 0) {
+    flag[0] = 0;
+    flag[1] = 0;
+    *sig0 = v;
+  }
+}
+
+template <typename TB>
+__global__ __launch_bounds__(256) void k_copy_to_f64(const TB* __restrict__ src, int64_t len,
+                                                     double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < len) dst[i] = (double)src[i];
+}
+
+template <typename TB>
+__global__ __launch_bounds__(256) void k_copy_vec(const TB* __restrict__ src, int64_t len,
+                                                  TB* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < len) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- MFMA GEMM
+// C (M x N, column-major, ldc) = A (M x K, column-major, lda) * B (K x N,
+// column-major, ldb).  One wave computes a 16 x (16 * NT) tile with the
+// 16x16x4 MFMA: lane l supplies A[r0 + l % 16][k0 + l / 16] and
+// B[k0 + l / 16][c0 + l % 16].  Accumulator element v of lane l holds
+// D[row][l % 16] with row = 4 * (l / 16) + v for the float32 instruction and
+// row = 4 * v + l / 16 for the float64 one (lane layouts checked on gfx950).
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct V4;
+template <> struct V4<double> {
+  using type = v4d;
+  __device__ __forceinline__ static int row(int lk, int v) { return 4 * v + lk; }
+};
+template <> struct V4<float> {
+  using type = v4f;
+  __device__ __forceinline__ static int row(int lk, int v) { return 4 * lk + v; }
+};
+
+constexpr int GEMM_NT = 4;
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_tall(const T* __restrict__ A, int64_t lda, int64_t M, int K,
+                                                   const T* __restrict__ B, int64_t ldb, int N,
+                                                   T* __restrict__ C, int64_t ldc) {
+  using VT = typename V4<T>::type;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (r0 >= M) return;
+  const int c0 = blockIdx.y * 16 * GEMM_NT;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t arow = r0 + li;
+  VT acc[GEMM_NT];
+#pragma unroll
+  for (int t = 0; t < GEMM_NT; ++t) acc[t] = VT{0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int kk = k0 + lk;
+    const T a = (arow < M && kk < K) ? A[(int64_t)kk * lda + arow] : (T)0;
+#pragma unroll
+    for (int t = 0; t < GEMM_NT; ++t) {
+      const int col = c0 + t * 16 + li;
+      const T b = (kk < K && col < N) ? B[(int64_t)col * ldb + kk] : (T)0;
+      acc[t] = mfma16(a, b, acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < GEMM_NT; ++t) {
+    const int col = c0 + t * 16 + li;
+    if (col < N) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + V4<T>::row(lk, v);
+        if (row < M) C[(int64_t)col * ldc + row] = acc[t][v];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- bf16 cast
+// Round to nearest even; NaN stays NaN (quiet bit forced).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ src, int64_t lds, int64_t m,
+                                                   int64_t n, uint16_t* __restrict__ dst, int64_t ldd) {
+  const int64_t row = blockIdx.y;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
+    dst[row * ldd + j] = f32_to_bf16_rne(src[row * lds + j]);
+}
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+// as 1, 2, 3", SC 2011): counter (i, 0, 0, 0), key = seed.  Uniforms
+// u = (x + 1) * 2^-32 in (0, 1]; Box-Muller on (u0, u1):
+// g = sqrt(-2 ln u0) cos(2 pi u1); q_i = 2 + g.
+__device__ __forceinline__ void philox_round(uint32_t* c, const uint32_t* k) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+  uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+  uint32_t n0 = hi1 ^ c[1] ^ k[0];
+  uint32_t n1 = lo1;
+  uint32_t n2 = hi0 ^ c[3] ^ k[1];
+  uint32_t n3 = lo0;
+  c[0] = n0;
+  c[1] = n1;
+  c[2] = n2;
+  c[3] = n3;
+}
+
+__global__ __launch_bounds__(256) void k_philox_start(double* __restrict__ q, int64_t m, uint64_t seed,
+                                                      double mean, double stdv) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  uint32_t c[4] = {(uint32_t)(i & 0xffffffffu), (uint32_t)((uint64_t)i >> 32), 0u, 0u};
+  uint32_t k[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k);
+    if (r < 9) {
+      k[0] += 0x9E3779B9u;
+      k[1] += 0xBB67AE85u;
+    }
+  }
+  const double two32 = 4294967296.0;
+  const double u0 = ((double)c[0] + 1.0) / two32;
+  const double u1 = ((double)c[1] + 1.0) / two32;
+  const double g = sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
+  q[i] = mean + stdv * g;
+}
+
+// ================================================================ launchers
+static inline unsigned nblocks(int64_t work, int64_t per) { return (unsigned)((work + per - 1) / per); }
+
+template <typename TA, typename TB>
+hipError_t launch_gemv_n_t(const TA* A, int64_t lda, int64_t m, int64_t n, const TB* p, const TB* qprev,
+                           const double* coef, int cidx, double* w, const int* flag, hipStream_t st) {
+  constexpr int R = 4;
+  const bool vec = ((lda % Pack<TA>::VN) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  dim3 grid(nblocks(m, 4 * R));
+  if (vec)
+    hipLaunchKernelGGL((k_gemv_n<TA, TB, R, true>), grid, dim3(256), 0, st, A, lda, m, n, p, qprev, coef,
+                       cidx, w, flag);
+  else
+    hipLaunchKernelGGL((k_gemv_n<TA, TB, R, false>), grid, dim3(256), 0, st, A, lda, m, n, p, qprev, coef,
+                       cidx, w, flag);
+  return hipGetLastError();
+}
+
+GemvTShape gemv_t_shape(int64_t m, int64_t n, int dtype_bytes) {
+  GemvTShape s;
+  const int vn = 16 / dtype_bytes;
+  s.col_tiles = nblocks(n, 256 * (int64_t)vn);
+  int64_t want = (2048 + s.col_tiles - 1) / s.col_tiles;
+  int64_t maxnb = (m + 63) / 64;
+  if (want > maxnb) want = maxnb;
+  if (want < 1) want = 1;
+  if (want > 512) want = 512;
+  s.rows_per_block = (m + want - 1) / want;
+  s.nb = (int)((m + s.rows_per_block - 1) / s.rows_per_block);
+  return s;
+}
+
+template <typename TA, typename TB>
+hipError_t launch_gemv_t_t(const TA* A, int64_t lda, int64_t m, int64_t n, const TB* q, const TB* pprev,
+                           const double* coef, int cidx, double* z, void* part, int64_t ldpart,
+                           const int* flag, hipStream_t st) {
+  using ACC = typename Acc<TA>::type;
+  const bool vec = ((lda % Pack<TA>::VN) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  GemvTShape s = gemv_t_shape(m, n, (int)sizeof(TA));
+  ACC* pa = reinterpret_cast<ACC*>(part);
+  if (vec) {
+    dim3 grid(s.col_tiles, s.nb);
+    hipLaunchKernelGGL((k_gemv_t_part<TA, TB, true>), grid, dim3(256), 0, st, A, lda, m, n, q,
+                       s.rows_per_block, pa, ldpart, flag);
+  } else {
+    dim3 grid(nblocks(n, 256), s.nb);
+    hipLaunchKernelGGL((k_gemv_t_part<TA, TB, false>), grid, dim3(256), 0, st, A, lda, m, n, q,
+                       s.rows_per_block, pa, ldpart, flag);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gemv_t_reduce<ACC, TB>), dim3(nblocks(n, 256)), dim3(256), 0, st, pa, ldpart, s.nb,
+                     n, pprev, coef, cidx, z, flag);
+  return hipGetLastError();
+}
+
+template <typename TB>
+hipError_t launch_gemv_n(const MatrixRef& A, const TB* p, const TB* qprev, const double* coef, int cidx,
+                         double* w, const int* flag, hipStream_t st) {
+  switch (A.dtype) {
+    case 0:
+      return launch_gemv_n_t<double, TB>((const double*)A.data, A.lda, A.m, A.n, p, qprev, coef, cidx, w,
+                                         flag, st);
+    case 1:
+      return launch_gemv_n_t<float, TB>((const float*)A.data, A.lda, A.m, A.n, p, qprev, coef, cidx, w,
+                                        flag, st);
+    default:
+      return launch_gemv_n_t<bf16, TB>((const bf16*)A.data, A.lda, A.m, A.n, p, qprev, coef, cidx, w,
+                                       flag, st);
+  }
+}
+
+template <typename TB>
+hipError_t launch_gemv_t(const MatrixRef& A, const TB* q, const TB* pprev, const double* coef, int cidx,
+                         double* z, void* part, int64_t ldpart, const int* flag, hipStream_t st) {
+  switch (A.dtype) {
+    case 0:
+      return launch_gemv_t_t<double, TB>((const double*)A.data, A.lda, A.m, A.n, q, pprev, coef, cidx, z,
+                                         part, ldpart, flag, st);
+    case 1:
+      return launch_gemv_t_t<float, TB>((const float*)A.data, A.lda, A.m, A.n, q, pprev, coef, cidx, z,
+                                        part, ldpart, flag, st);
+    default:
+      return launch_gemv_t_t<bf16, TB>((const bf16*)A.data, A.lda, A.m, A.n, q, pprev, coef, cidx, z,
+                                       part, ldpart, flag, st);
+  }
+}
+
+int dots_chunks(int64_t len) { return (int)nblocks(len, 64 * DE); }
+int update_blocks(int64_t len) { return (int)nblocks(len, 256 * UE); }
+
+template <typename TB>
+hipError_t launch_dots(const TB* V, int64_t ldv, int t, int64_t len, const double* x, double* hpart,
+                       int ldh, double* h, const int* flag, hipStream_t st) {
+  if (t <= 0) return hipSuccess;
+  const int nch = dots_chunks(len);
+  dim3 grid(nch, nblocks(t, DCOLS));
+  hipLaunchKernelGGL((k_dots<TB>), grid, dim3(256), 0, st, V, ldv, t, len, x, hpart, ldh, flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dots_reduce, dim3(nblocks(t, 256)), dim3(256), 0, st, hpart, ldh, nch, t, h, flag);
+  return hipGetLastError();
+}
+
+template <typename TB>
+hipError_t launch_update(const TB* V, int64_t ldv, int t, int64_t len, double* x, const double* h,
+                         double* normpart, const int* flag, hipStream_t st) {
+  hipLaunchKernelGGL((k_update<TB>), dim3(update_blocks(len)), dim3(256), 0, st, V, ldv, t, len, x, h,
+                     normpart, flag);
+  return hipGetLastError();
+}
+
+template <typename TB>
+hipError_t launch_normalize(const double* x, int64_t len, const double* normpart, int nparts, TB* out,
+                            double* coef_out, const double* sig_in, double* sig_out, double eps,
+                            int relative, int track, int* flag, int code, int index, hipStream_t st) {
+  int64_t blocks = nblocks(len, 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL((k_normalize<TB>), dim3((unsigned)blocks), dim3(256), 0, st, x, len, normpart, nparts,
+                     out, coef_out, sig_in, sig_out, eps, relative, track, flag, code, index);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_cycle(int* flag, double* sig0, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_cycle, dim3(1), dim3(64), 0, st, flag, sig0, v);
+  return hipGetLastError();
+}
+
+template <typename TB>
+hipError_t launch_copy_to_f64(const TB* src, int64_t len, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy_to_f64<TB>), dim3(nblocks(len, 256)), dim3(256), 0, st, src, len, dst);
+  return hipGetLastError();
+}
+
+template <typename TB>
+hipError_t launch_copy_vec(const TB* src, int64_t len, TB* dst, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy_vec<TB>), dim3(nblocks(len, 256)), dim3(256), 0, st, src, len, dst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gemm_tall(const T* A, int64_t lda, int64_t M, int K, const T* B, int64_t ldb, int N, T* C,
+                            int64_t ldc, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid(nblocks(M, 64), nblocks(N, 16 * GEMM_NT));
+  hipLaunchKernelGGL((k_gemm_tall<T>), grid, dim3(256), 0, st, A, lda, M, K, B, ldb, N, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t m, int64_t n, uint16_t* dst, int64_t ldd,
+                            hipStream_t st) {
+  int64_t gx = nblocks(n, 256);
+  if (gx > 64) gx = 64;
+  // one grid row per matrix row; gridDim.y limit is 65535, so split if needed
+  for (int64_t r0 = 0; r0 < m; r0 += 65535) {
+    int64_t rows = m - r0 < 65535 ? m - r0 : 65535;
+    hipLaunchKernelGGL(k_cast_bf16, dim3((unsigned)gx, (unsigned)rows), dim3(256), 0, st, src + r0 * lds,
+                       lds, rows, n, dst + r0 * ldd, ldd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_philox_start(double* q, int64_t m, uint64_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_philox_start, dim3(nblocks(m, 256)), dim3(256), 0, st, q, m, seed, 2.0, 1.0);
+  return hipGetLastError();
+}
+
+// explicit instantiations for the two basis types
+#define GKB_INST(TB)                                                                                      \
+  template hipError_t launch_gemv_n<TB>(const MatrixRef&, const TB*, const TB*, const double*, int,       \
+                                        double*, const int*, hipStream_t);                                \
+  template hipError_t launch_gemv_t<TB>(const MatrixRef&, const TB*, const TB*, const double*, int,       \
+                                        double*, void*, int64_t, const int*, hipStream_t);                \
+  template hipError_t launch_dots<TB>(const TB*, int64_t, int, int64_t, const double*, double*, int,      \
+                                      double*, const int*, hipStream_t);                                  \
+  template hipError_t launch_update<TB>(const TB*, int64_t, int, int64_t, double*, const double*,         \
+                                        double*, const int*, hipStream_t);                                \
+  template hipError_t launch_normalize<TB>(const double*, int64_t, const double*, int, TB*, double*,      \
+                                           const double*, double*, double, int, int, int*, int, int,      \
+                                           hipStream_t);                                                  \
+  template hipError_t launch_copy_to_f64<TB>(const TB*, int64_t, double*, hipStream_t);                   \
+  template hipError_t launch_copy_vec<TB>(const TB*, int64_t, TB*, hipStream_t);                          \
+  template hipError_t launch_gemm_tall<TB>(const TB*, int64_t, int64_t, int, const TB*, int64_t, int, TB*, \
+                                           int64_t, hipStream_t);
+GKB_INST(double)
+GKB_INST(float)
+#undef GKB_INST
+
+}  // namespace gkb

@@ -1,0 +1,321 @@
+"""Python binding of libgkb.so (ctypes): argument marshalling only.
+
+Every step of the computation runs in the HIP library; PyTorch supplies device
+memory (tensors) and the stream.  If the library is not built, every call
+raises: there is no fallback.
+
+Function names follow the C ABI in include/gkb.h and include/gkb_kernels.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgkb.so")
+
+GKB_F64, GKB_F32, GKB_BF16 = 0, 1, 2
+STATUS = {0: "GKB_OK", 1: "GKB_NOT_CONVERGED", 2: "GKB_RANK_DEFICIENT", -1: "GKB_ERR_INVALID",
+          -2: "GKB_ERR_HIP", -3: "GKB_ERR_NUMERIC", -4: "GKB_ERR_WORKSPACE"}
+
+
+class GkbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class GkbMatrix(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("lda", C.c_int64), ("dtype", C.c_int),
+                ("data", C.c_void_p), ("refine_f32", C.c_void_p), ("lda_refine", C.c_int64)]
+
+
+class GkbOptions(C.Structure):
+    _fields_ = [("keep", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
+                ("q1", C.c_void_p), ("seed", C.c_uint64), ("refine_dim", C.c_int)]
+
+
+class GkbStats(C.Structure):
+    _fields_ = [("nconv", C.c_int), ("restarts", C.c_int), ("breakdown", C.c_int), ("returned", C.c_int),
+                ("matvecs", C.c_int64), ("max_res_est", C.c_double), ("sigma1_est", C.c_double),
+                ("ms_total", C.c_double), ("ms_host", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_rank_workspace_size",
+           "gkb_numerical_rank", "gkb_status_string", "gkb_last_error", "gkb_host_dense_svd",
+           "gkb_host_bidiag_count_above", "gkb_matvec_workspace_size", "gkb_matvec", "gkb_gemm_tall",
+           "gkb_cast_bf16", "gkb_start_vector"]
+
+
+def lib():
+    """Load libgkb.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(python -m paper_2104_10785_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    L.gkb_default_options.argtypes = [P(GkbOptions)]
+    L.gkb_default_options.restype = None
+    L.gkb_workspace_size.argtypes = [P(GkbMatrix), C.c_int, C.c_int, P(GkbOptions)]
+    L.gkb_workspace_size.restype = C.c_size_t
+    L.gkb_partial_svd.argtypes = [P(GkbMatrix), C.c_int, C.c_int, C.c_double, C.c_int, P(GkbOptions),
+                                  C.c_void_p, C.c_size_t, P(C.c_double), C.c_void_p, C.c_void_p,
+                                  P(GkbStats), C.c_void_p]
+    L.gkb_partial_svd.restype = C.c_int
+    L.gkb_rank_workspace_size.argtypes = [P(GkbMatrix), C.c_int, P(GkbOptions)]
+    L.gkb_rank_workspace_size.restype = C.c_size_t
+    L.gkb_numerical_rank.argtypes = [P(GkbMatrix), C.c_double, C.c_int, C.c_int, P(GkbOptions), C.c_void_p,
+                                     C.c_size_t, P(C.c_int64), P(C.c_int64), P(C.c_double), P(C.c_int),
+                                     P(GkbStats), C.c_void_p]
+    L.gkb_numerical_rank.restype = C.c_int
+    L.gkb_status_string.argtypes = [C.c_int]
+    L.gkb_status_string.restype = C.c_char_p
+    L.gkb_last_error.argtypes = []
+    L.gkb_last_error.restype = C.c_char_p
+    L.gkb_host_dense_svd.argtypes = [C.c_int, C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
+                                     P(C.c_double)]
+    L.gkb_host_dense_svd.restype = C.c_int
+    L.gkb_host_bidiag_count_above.argtypes = [C.c_int, C.c_int, P(C.c_double), P(C.c_double), C.c_double]
+    L.gkb_host_bidiag_count_above.restype = C.c_int64
+    L.gkb_matvec_workspace_size.argtypes = [P(GkbMatrix)]
+    L.gkb_matvec_workspace_size.restype = C.c_size_t
+    L.gkb_matvec.argtypes = [P(GkbMatrix), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.gkb_matvec.restype = C.c_int
+    L.gkb_gemm_tall.argtypes = [C.c_int, C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int64,
+                                C.c_int, C.c_void_p, C.c_int64, C.c_void_p]
+    L.gkb_gemm_tall.restype = C.c_int
+    L.gkb_cast_bf16.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                                C.c_void_p]
+    L.gkb_cast_bf16.restype = C.c_int
+    L.gkb_start_vector.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p]
+    L.gkb_start_vector.restype = C.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().gkb_last_error().decode()
+
+
+def _check(status: int, allow_positive: bool = True) -> int:
+    if status < 0 or (status > 0 and not allow_positive):
+        raise GkbError(status, last_error())
+    return status
+
+
+# ------------------------------------------------------------------ helpers
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return GKB_F64
+    if t.dtype == torch.float32:
+        return GKB_F32
+    if t.dtype == torch.bfloat16:
+        return GKB_BF16
+    raise TypeError(f"unsupported matrix dtype {t.dtype}")
+
+
+def basis_dtype(code: int):
+    torch = _torch()
+    return torch.float64 if code == GKB_F64 else torch.float32
+
+
+def make_matrix(A, refine=None) -> GkbMatrix:
+    """Describe a 2-D device tensor (row-major, unit column stride)."""
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor with unit column stride")
+    mat = GkbMatrix(A.shape[0], A.shape[1], max(A.stride(0), A.shape[1]), _dtype_code(A), A.data_ptr(), None, 0)
+    if refine is not None:
+        if refine.dtype != _torch().float32 or refine.shape != A.shape or refine.stride(1) != 1:
+            raise ValueError("refine must be a float32 device tensor shaped like A")
+        mat.refine_f32 = refine.data_ptr()
+        mat.lda_refine = max(refine.stride(0), refine.shape[1])
+    return mat
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_options(q1=None, seed=0, keep=0, eps_break=0.0, eps_relative=True, refine_dim=0) -> GkbOptions:
+    o = GkbOptions()
+    lib().gkb_default_options(C.byref(o))
+    o.keep = keep
+    o.eps_relative = 1 if eps_relative else 0
+    o.eps_break = eps_break
+    o.seed = seed
+    o.refine_dim = refine_dim
+    if q1 is not None:
+        if q1.dtype != _torch().float64 or not q1.is_cuda or not q1.is_contiguous():
+            raise ValueError("q1 must be a contiguous float64 device tensor")
+        o.q1 = q1.data_ptr()
+    return o
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------ ABI calls
+def gkb_workspace_size(A, r, k, refine=None, **opts) -> int:
+    mat = make_matrix(A, refine)
+    o = make_options(**opts)
+    return int(lib().gkb_workspace_size(C.byref(mat), r, k, C.byref(o)))
+
+
+def gkb_partial_svd(A, r, k, tol, max_restarts, refine=None, workspace=None, stream=None, **opts):
+    """Top-r singular triplets of the device matrix A.
+
+    Returns (sigma, Ut, Vt, status, stats): sigma a numpy array (r, descending),
+    Ut (r x m) and Vt (r x n) device tensors whose rows are the singular
+    vectors (float64 for a float64 A, float32 otherwise).
+    """
+    torch = _torch()
+    mat = make_matrix(A, refine)
+    o = make_options(**opts)
+    L = lib()
+    need = L.gkb_workspace_size(C.byref(mat), r, k, C.byref(o))
+    if need == 0:
+        _check(L.gkb_partial_svd(C.byref(mat), r, k, tol, max_restarts, C.byref(o), None, 0,
+                                 (C.c_double * max(r, 1))(), None, None, None, None), False)
+    if workspace is None:
+        workspace = _workspace(need, A.device)
+    bt = basis_dtype(mat.dtype)
+    Ut = torch.empty((r, A.shape[0]), dtype=bt, device=A.device)
+    Vt = torch.empty((r, A.shape[1]), dtype=bt, device=A.device)
+    sig = (C.c_double * r)()
+    st = GkbStats()
+    status = L.gkb_partial_svd(C.byref(mat), r, k, float(tol), int(max_restarts), C.byref(o),
+                               C.c_void_p(workspace.data_ptr()), workspace.numel(), sig,
+                               C.c_void_p(Ut.data_ptr()), C.c_void_p(Vt.data_ptr()), C.byref(st),
+                               _stream(stream))
+    _check(status)
+    return np.array(sig[:], dtype=np.float64), Ut, Vt, status, st.as_dict()
+
+
+def gkb_rank_workspace_size(A, k_max=0, **opts) -> int:
+    mat = make_matrix(A)
+    o = make_options(**opts)
+    return int(lib().gkb_rank_workspace_size(C.byref(mat), k_max, C.byref(o)))
+
+
+def gkb_numerical_rank(A, tau, tau_relative=True, k_max=0, workspace=None, stream=None, **opts):
+    """Numerical rank of the device matrix A.
+
+    Returns (rank, rank_sturm, sigma (numpy, singular values of B), status, stats).
+    """
+    mat = make_matrix(A)
+    o = make_options(**opts)
+    L = lib()
+    kk = k_max if k_max else min(A.shape)
+    need = L.gkb_rank_workspace_size(C.byref(mat), k_max, C.byref(o))
+    if workspace is None:
+        workspace = _workspace(need, A.device)
+    rank = C.c_int64()
+    rank_s = C.c_int64()
+    sig = (C.c_double * max(kk, 1))()
+    ns = C.c_int()
+    st = GkbStats()
+    status = L.gkb_numerical_rank(C.byref(mat), float(tau), 1 if tau_relative else 0, int(k_max), C.byref(o),
+                                  C.c_void_p(workspace.data_ptr()), workspace.numel(), C.byref(rank),
+                                  C.byref(rank_s), sig, C.byref(ns), C.byref(st), _stream(stream))
+    _check(status)
+    return rank.value, rank_s.value, np.array(sig[: ns.value]), status, st.as_dict()
+
+
+def gkb_matvec(A, x, trans, y=None, workspace=None, stream=None):
+    """y = A x (trans=0) or A^T x (trans=1) with the library's streaming kernels (y float64)."""
+    torch = _torch()
+    mat = make_matrix(A)
+    L = lib()
+    out_len = A.shape[1] if trans else A.shape[0]
+    if y is None:
+        y = torch.empty(out_len, dtype=torch.float64, device=A.device)
+    if workspace is None and trans:
+        workspace = _workspace(L.gkb_matvec_workspace_size(C.byref(mat)), A.device)
+    wsp = C.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    wsz = workspace.numel() if workspace is not None else 0
+    _check(L.gkb_matvec(C.byref(mat), int(trans), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), wsp, wsz,
+                        _stream(stream)), False)
+    return y
+
+
+def gkb_gemm_tall(A, B, C_out=None, stream=None):
+    """C = A B on MFMA for column-major operands given as transposed tensors:
+    A as (K, M) row-major (= M x K column-major), B as (N, K), result (N, M)."""
+    torch = _torch()
+    K, M = A.shape
+    N, K2 = B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    code = GKB_F64 if A.dtype == torch.float64 else GKB_F32
+    if C_out is None:
+        C_out = torch.empty((N, M), dtype=A.dtype, device=A.device)
+    _check(lib().gkb_gemm_tall(code, C.c_void_p(A.data_ptr()), A.stride(0), M, K, C.c_void_p(B.data_ptr()),
+                               B.stride(0), N, C.c_void_p(C_out.data_ptr()), C_out.stride(0), _stream(stream)),
+           False)
+    return C_out
+
+
+def gkb_cast_bf16(src, dst=None, stream=None):
+    """Round a float32 device matrix to bfloat16 (nearest even)."""
+    torch = _torch()
+    m, n = src.shape
+    if dst is None:
+        dst = torch.empty((m, n), dtype=torch.bfloat16, device=src.device)
+    _check(lib().gkb_cast_bf16(C.c_void_p(src.data_ptr()), src.stride(0), m, n, C.c_void_p(dst.data_ptr()),
+                               dst.stride(0), _stream(stream)), False)
+    return dst
+
+
+def gkb_start_vector(m, seed, device="cuda", stream=None):
+    """q ~ N(2, 1)^m from the device Philox generator (float64)."""
+    torch = _torch()
+    q = torch.empty(m, dtype=torch.float64, device=device)
+    _check(lib().gkb_start_vector(C.c_void_p(q.data_ptr()), m, seed, _stream(stream)), False)
+    return q
+
+
+def gkb_host_dense_svd(H: np.ndarray):
+    """Host float64 SVD used per cycle (no device work)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    nq, np_ = H.shape
+    kk = min(nq, np_)
+    s = np.zeros(kk)
+    X = np.zeros((nq, kk))
+    Y = np.zeros((np_, kk))
+    dp = C.POINTER(C.c_double)
+    _check(lib().gkb_host_dense_svd(nq, np_, H.ctypes.data_as(dp), s.ctypes.data_as(dp), X.ctypes.data_as(dp),
+                                    Y.ctypes.data_as(dp)), False)
+    return X, s, Y
+
+
+def gkb_host_bidiag_count_above(alpha, beta, nq, tau) -> int:
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta if len(beta) else [0.0], dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    return int(lib().gkb_host_bidiag_count_above(nq, a.size, a.ctypes.data_as(dp), b.ctypes.data_as(dp), tau))
+
+
+def gkb_matvec_workspace_size(A) -> int:
+    mat = make_matrix(A)
+    return int(lib().gkb_matvec_workspace_size(C.byref(mat)))

@@ -1,0 +1,196 @@
+"""Partial SVD and numerical rank through the C ABI against the float64 oracle.
+
+Both sides get the same seeded inputs (the input generator module) and the
+same start vector.  Float64 mode: singular values within 1e-10 relative of
+the oracle; vectors compared with the sign-invariant alignment metric of
+Figure 1; ranks exactly equal.
+"""
+import numpy as np
+import pytest
+
+from oracle import checks, gk, philox
+from oracle import rank as orank
+from paper_2104_10785_amd import gkb, inputs
+
+from .gpu_util import banner, device, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def run_gpu(A, r, k, tol, restarts, q=None, dtype=None, **kw):
+    import torch
+    Ad = to_dev(A) if dtype is None else to_dev(A).to(dtype)
+    qd = to_dev(q) if q is not None else None
+    sigma, Ut, Vt, status, stats = gkb.gkb_partial_svd(Ad, r, k, tol, restarts, q1=qd, **kw)
+    torch.cuda.synchronize()
+    return sigma, to_host(Ut).T.astype(np.float64), to_host(Vt).T.astype(np.float64), status, stats
+
+
+@pytest.fixture(scope="module")
+def c1():
+    s = inputs.decade_spectrum(1000)
+    A, Q1, Q2 = inputs.svd_matrix(2000, 1000, s, seed=0)
+    q = inputs.start_vector(2000, seed=1)
+    return A, Q1, Q2, s, q
+
+
+def test_c1_partial_svd_f64(c1):
+    device()
+    A, Q1, Q2, s, q = c1
+    banner("c1 2000x1000 f64 r=10 k=30 tol=1e-10")
+    ref = gk.partial_svd(A, 10, 30, 1e-10, 50, q)
+    sigma, U, V, status, stats = run_gpu(A, 10, 30, 1e-10, 50, q)
+    assert status == 0 and stats["nconv"] == 10
+    assert np.max(np.abs(sigma - ref["sigma"]) / ref["sigma"]) <= 1e-10
+    assert np.max(np.abs(sigma - s[:10]) / s[:10]) <= 1e-10
+    assert np.min(checks.alignment(ref["U"], ref["V"], U, V)) >= 1 - 1e-8
+    r1, r2 = checks.triplet_residuals(A, sigma, U, V)
+    assert np.max(r1) < 1e-12 and np.max(r2) <= 1.01e-10 * sigma[0]
+    assert abs(stats["restarts"] - ref["restarts"]) <= 1
+    assert checks.orth_error(U) < 1e-12 and checks.orth_error(V) < 1e-12
+
+
+def test_c1_one_shot_algorithm2(c1):
+    device()
+    A, Q1, Q2, s, q = c1
+    banner("c1 f64 max_restarts=0 k=60")
+    ref = gk.partial_svd(A, 10, 60, 1e-10, 0, q)
+    sigma, U, V, status, stats = run_gpu(A, 10, 60, 1e-10, 0, q)
+    assert status == ref["status"] and stats["nconv"] == ref["nconv"]
+    assert np.max(np.abs(sigma - ref["sigma"]) / ref["sigma"]) <= 1e-10
+    assert stats["matvecs"] == 121 and stats["restarts"] == 0
+
+
+def test_many_restarts_match_oracle():
+    device()
+    banner("300x100 f64 r=8 k=14 many restarts")
+    s = np.concatenate([np.geomspace(1.0, 0.5, 8), np.geomspace(0.45, 0.01, 92)])
+    A, Q1, Q2 = inputs.svd_matrix(300, 100, s, seed=21)
+    q = inputs.start_vector(300, seed=22)
+    ref = gk.partial_svd(A, 8, 14, 1e-11, 200, q)
+    sigma, U, V, status, stats = run_gpu(A, 8, 14, 1e-11, 200, q)
+    assert status == 0 and ref["status"] == 0
+    assert abs(stats["restarts"] - ref["restarts"]) <= 1
+    assert np.max(np.abs(sigma - s[:8]) / s[:8]) <= 1e-10
+    assert np.min(checks.alignment(Q1[:, :8], Q2[:, :8], U, V)) >= 1 - 1e-8
+
+
+@pytest.mark.parametrize("tau,want", [(10 ** -6.005, 601), (10 ** -5.995, 600)])
+def test_c1_rank(c1, tau, want):
+    device()
+    A, _, _, s, q = c1
+    banner(f"c1 rank tau={tau:.3e}")
+    ref = orank.numerical_rank(A, tau, q)
+    rank, rank_s, sig, status, stats = gkb.gkb_numerical_rank(to_dev(A), tau, q1=to_dev(q))
+    assert rank == want and rank_s == want and ref["rank"] == want
+    assert sig.size == ref["sigma"].size
+    top = ref["sigma"] > 1e-6
+    assert np.max(np.abs(sig[top] - ref["sigma"][top]) / ref["sigma"][top]) < 1e-10
+
+
+@pytest.mark.parametrize("l", [1, 5, 37, 100])
+def test_rank_exact_products(l):
+    device()
+    banner(f"rank of product l={l}")
+    A = inputs.product_matrix(600, 400, l, seed=5)
+    q = inputs.start_vector(600, seed=2)
+    ref = orank.numerical_rank(A, 1e-8, q)
+    rank, rank_s, sig, status, stats = gkb.gkb_numerical_rank(to_dev(A), 1e-8, q1=to_dev(q))
+    assert rank == l and rank_s == l and ref["rank"] == l
+    assert abs(sig.size - ref["steps"]) <= 1
+
+
+def test_rank_one_and_zero():
+    device()
+    banner("rank-1 and zero matrices")
+    rng = np.random.default_rng(1)
+    x, y = rng.standard_normal(300), rng.standard_normal(200)
+    A = np.outer(x, y)
+    q = inputs.start_vector(300, seed=2)
+    sigma, U, V, status, stats = run_gpu(A, 1, 3, 1e-12, 0, q)
+    assert status == 0
+    assert abs(sigma[0] - np.linalg.norm(x) * np.linalg.norm(y)) < 1e-13 * sigma[0]
+    assert abs(abs(U[:, 0] @ x) / np.linalg.norm(x) - 1) < 1e-13
+    Z = np.zeros((50, 40))
+    sigma, U, V, status, stats = run_gpu(Z, 2, 4, 1e-10, 1, inputs.start_vector(50, seed=1))
+    assert status == 2 and stats["returned"] == 0 and np.all(sigma == 0)
+    rank, rank_s, sig, status, stats = gkb.gkb_numerical_rank(to_dev(Z), 1e-6, q1=to_dev(inputs.start_vector(50, 1)))
+    assert rank == 0
+
+
+def test_rank_deficient_returns_exact_triplets():
+    device()
+    banner("rank-3 product with r=5")
+    A = inputs.product_matrix(500, 300, 3, seed=4)
+    q = inputs.start_vector(500, seed=5)
+    ref = gk.partial_svd(A, 5, 10, 1e-10, 3, q)
+    sigma, U, V, status, stats = run_gpu(A, 5, 10, 1e-10, 3, q)
+    assert status == 2 and ref["status"] == 2 and stats["returned"] == 3
+    assert np.max(np.abs(sigma[:3] - ref["sigma"]) / ref["sigma"]) < 1e-12
+    r1, r2 = checks.triplet_residuals(A, sigma[:3], U[:, :3], V[:, :3])
+    assert max(r1.max(), r2.max()) < 1e-11 * sigma[0]
+
+
+def test_wide_and_full_dimension():
+    device()
+    banner("wide 40x90 and k=min(m,n)")
+    s = np.geomspace(3.0, 0.1, 40)
+    A, Q1, Q2 = inputs.svd_matrix(40, 90, s, seed=31)
+    q = inputs.start_vector(40, seed=1)
+    sigma, U, V, status, stats = run_gpu(A, 5, 25, 1e-12, 50, q)
+    assert status == 0 and np.max(np.abs(sigma - s[:5]) / s[:5]) < 1e-12
+    sigma, U, V, status, stats = run_gpu(A, 40, 40, 1e-12, 0, q)
+    assert np.max(np.abs(sigma - s) / s) < 1e-12
+
+
+def test_nan_input_reports_numeric_error():
+    device()
+    banner("NaN input")
+    A = np.ones((64, 32))
+    A[3, 5] = np.nan
+    with pytest.raises(gkb.GkbError) as ei:
+        run_gpu(A, 2, 4, 1e-8, 0, np.ones(64))
+    assert ei.value.status == -3
+
+
+def test_device_start_vector_path(c1):
+    device()
+    A, Q1, Q2, s, q = c1
+    banner("c1 with device Philox start (q1=NULL)")
+    qp = philox.start_vector(2000, 12345)
+    ref = gk.partial_svd(A, 10, 30, 1e-10, 50, qp)
+    sigma, U, V, status, stats = run_gpu(A, 10, 30, 1e-10, 50, None, seed=12345)
+    assert status == 0
+    assert np.max(np.abs(sigma - ref["sigma"]) / ref["sigma"]) <= 1e-10
+    assert np.min(checks.alignment(ref["U"], ref["V"], U, V)) >= 1 - 1e-8
+
+
+def test_f32_lowrank_noise_midsize():
+    import torch
+    device()
+    m, n = 6000, 2500
+    banner(f"f32 low-rank+noise {m}x{n} r=20 k=60")
+    A32, s, _, _ = inputs.lowrank_noise(m, n, 200, 0.95, 1e-6, seed=7, dtype=np.float32)
+    q = inputs.start_vector(m, seed=8)
+    ref = gk.partial_svd(A32.astype(np.float64), 20, 60, 1e-6, 20, q, eps_break=1e-6)
+    sigma, U, V, status, stats = run_gpu(A32, 20, 60, 1e-6, 20, q)
+    assert status == 0
+    # float32 products: each matvec carries an error of about sqrt(n) u ||A||
+    # (random-walk rounding); the Ritz values inherit it (Weyl).
+    err = np.abs(sigma - ref["sigma"])
+    print("f32 sigma abs err max", err.max(), "rel", (err / ref["sigma"]).max(), flush=True)
+    bound = 8.0 * np.sqrt(max(m, n)) * 2.0 ** -24 * ref["sigma"][0]
+    assert np.all(err <= bound)
+    al = checks.alignment(ref["U"], ref["V"], U, V)
+    print("f32 alignment min", al.min(), flush=True)
+    r1, r2 = checks.triplet_residuals(A32.astype(np.float64), sigma, U, V)
+    assert np.max(r1) <= bound * 10 and np.max(r2) <= 1e-6 * sigma[0] + bound * 10
+
+
+def test_determinism(c1):
+    device()
+    A, Q1, Q2, s, q = c1
+    banner("determinism: two runs bitwise equal")
+    a = run_gpu(A, 10, 30, 1e-10, 50, q)
+    b = run_gpu(A, 10, 30, 1e-10, 50, q)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
