@@ -88,6 +88,12 @@ typedef struct {
   uint64_t seed;
   int refine_dim;      /* GKB_BF16 with refine_f32: subspace size of the       */
                        /* refinement; 0 = min(k, 2 r)                           */
+  int check_every;     /* > 0: also test convergence inside a cycle, after     */
+                       /* every check_every right vectors once there are >= r  */
+                       /* of them, and stop the cycle when the r largest Ritz  */
+                       /* triplets pass (one host synchronisation per test);   */
+                       /* 0 = test only at the end of a cycle (fixed k, as the */
+                       /* paper's Algorithm 2)                                 */
 } gkb_options;
 
 typedef struct {
@@ -100,6 +106,8 @@ typedef struct {
   double sigma1_est;   /* largest Ritz value                                   */
   double ms_total;     /* wall time of the call                                */
   double ms_host;      /* of which host small SVDs                             */
+  int checks;          /* in-cycle convergence tests performed                 */
+  int krylov_dim;      /* right basis vectors in the final projected matrix    */
 } gkb_stats;
 
 /* Fill *opt with the defaults above. */

@@ -99,12 +99,16 @@ class Factorization:
 
 
 def first_cycle(A: np.ndarray, q: np.ndarray, k: int, eps: BreakThreshold,
-                passes: int = 2) -> Factorization:
+                passes: int = 2, stop=None) -> Factorization:
     """k steps of Bidiag 1 from the start vector q (eq. 2.1-2.3, Algorithm 1).
 
     Step t (1-based) uses p_t, alpha_t, q_t and produces beta_{t+1} q_{t+1} and
     then alpha_{t+1} p_{t+1}. After k steps, H = B_{k+1,k} and p_{k+1} with
     alpha_{k+1} is the residual direction. Matvecs: 1 + 2k.
+
+    `stop`, if given, is called as stop(H, alpha_res) after steps whose
+    column count np satisfies its schedule (see `ConvergenceCheck`); when it
+    returns True the cycle ends there with H = B_{np+1,np}.
     """
     m, n = A.shape
     Q = np.zeros((m, k + 1))
@@ -161,6 +165,12 @@ def first_cycle(A: np.ndarray, q: np.ndarray, k: int, eps: BreakThreshold,
         eps.seen(alpha)
         alphas.append(alpha)
         P[:, t + 1] = z / alpha
+        np_ = t + 1
+        if stop is not None and np_ < k and stop.due(np_):
+            H = bidiag(np_ + 1, np_)
+            if stop(H, alpha):
+                return Factorization(P[:, :np_], Q[:, : np_ + 1], H, alpha, P[:, np_].copy(), None,
+                                     matvecs, {"alpha": alphas, "beta": betas, "early": True})
     return Factorization(P[:, :k], Q[:, : k + 1], bidiag(k + 1, k), alphas[k], P[:, k].copy(),
                          None, matvecs, {"alpha": alphas, "beta": betas})
 
@@ -178,7 +188,7 @@ def ritz(H: np.ndarray):
 
 def restart_cycle(A: np.ndarray, fac: Factorization, X: np.ndarray, s: np.ndarray,
                   Y: np.ndarray, l: int, k: int, eps: BreakThreshold,
-                  passes: int = 2) -> Factorization:
+                  passes: int = 2, stop=None) -> Factorization:
     """Thick restart keeping l Ritz pairs, then continue to k vectors.
 
     With P~ = P Y_l, Q~ = Q X_l, rho = alpha_res X[last, :l] and p_{l+1} = p_res:
@@ -233,11 +243,56 @@ def restart_cycle(A: np.ndarray, fac: Factorization, X: np.ndarray, s: np.ndarra
                                  None, "alpha", fac.matvecs + matvecs)
         eps.seen(alpha)
         Pn[:, j + 1] = z / alpha
+        np_ = j + 1
+        if stop is not None and np_ < k and stop.due(np_):
+            Hp = H[:np_, :np_].copy()
+            if stop(Hp, alpha):
+                return Factorization(Pn[:, :np_], Qn[:, :np_], Hp, alpha, Pn[:, np_].copy(), None,
+                                     fac.matvecs + matvecs, {"early": True})
         if j + 1 < k:
             H[j, j + 1] = alpha
         alpha_prev = alpha
     return Factorization(Pn[:, :k], Qn[:, :k], H, alpha_prev, Pn[:, k].copy(), None,
                          fac.matvecs + matvecs)
+
+
+def top_r_converged(H: np.ndarray, alpha_res: float, r: int, tol: float, thr: float):
+    """The convergence test on a projected matrix H (nq x np).
+
+    Ritz values above the breakdown threshold `thr` count as available; the r
+    largest must all be available and satisfy alpha_res |X[last, i]| <=
+    tol * sigma_1(H). Returns (converged, r_eff, nconv, X, s, Y, res).
+    """
+    nq, np_ = H.shape
+    if np_ == 0:
+        return False, 0, 0, np.zeros((nq, 0)), np.zeros(0), np.zeros((0, 0)), np.zeros(0)
+    X, s, Y = ritz(H)
+    res = alpha_res * np.abs(X[nq - 1, :])
+    avail = int(np.count_nonzero(s > thr))
+    r_eff = min(r, avail)
+    conv = res[:r_eff] <= tol * s[0]
+    nconv = int(np.count_nonzero(conv))
+    return (r_eff == r and nconv == r), r_eff, nconv, X, s, Y, res
+
+
+class ConvergenceCheck:
+    """In-cycle convergence test (not in the paper, which runs a fixed k).
+
+    Due after every `every` right basis vectors once there are at least r of
+    them (np >= r and np % every == 0); the cycle then stops as soon as the r
+    largest Ritz triplets pass the residual test.
+    """
+
+    def __init__(self, r: int, tol: float, every: int, eps: BreakThreshold):
+        self.r, self.tol, self.every, self.eps = r, tol, every, eps
+        self.checks = 0
+
+    def due(self, np_: int) -> bool:
+        return self.every > 0 and np_ >= self.r and np_ % self.every == 0
+
+    def __call__(self, H, alpha_res) -> bool:
+        self.checks += 1
+        return top_r_converged(H, alpha_res, self.r, self.tol, self.eps())[0]
 
 
 def default_keep(r: int, k: int) -> int:
@@ -252,13 +307,16 @@ def default_eps_break(dtype_name: str = "f64") -> float:
 
 def partial_svd(A, r: int, k: int, tol: float, max_restarts: int, q: np.ndarray,
                 keep: int = 0, eps_break: float | None = None, eps_relative: bool = True,
-                passes: int = 2, left_from_matvec: bool = False, record: bool = False):
+                passes: int = 2, left_from_matvec: bool = False, record: bool = False,
+                check_every: int = 0):
     """Top-r singular triplets of A by restarted Golub-Kahan (Algorithm 2 + restart).
 
     Algorithm 2 is the case max_restarts = 0: run Algorithm 1 for k steps, take
     the Ritz triplets of B. With max_restarts > 0 the factorization is restarted
     (keeping `keep` Ritz pairs) until the r largest Ritz triplets all pass the
     residual test or the restarts are used up.
+
+    check_every > 0 adds the in-cycle convergence test of `ConvergenceCheck`.
 
     Returns a dict: sigma (r'), U (m x r'), V (n x r'), res_est (r'), nconv,
     restarts, matvecs, status, breakdown, cycles (per-cycle H if `record`).
@@ -279,7 +337,8 @@ def partial_svd(A, r: int, k: int, tol: float, max_restarts: int, q: np.ndarray,
         else:
             raise ValueError("need r <= keep < k")
     eps = BreakThreshold(default_eps_break() if eps_break is None else eps_break, eps_relative)
-    fac = first_cycle(A, q, k, eps, passes)
+    stop = ConvergenceCheck(r, tol, check_every, eps) if check_every > 0 else None
+    fac = first_cycle(A, q, k, eps, passes, stop)
     restarts = 0
     cycles = []
     while True:
@@ -304,7 +363,7 @@ def partial_svd(A, r: int, k: int, tol: float, max_restarts: int, q: np.ndarray,
         if done or restarts >= max_restarts:
             break
         eps.seen(s[0])
-        fac = restart_cycle(A, fac, X, s, Y, l, k, eps, passes)
+        fac = restart_cycle(A, fac, X, s, Y, l, k, eps, passes, stop)
         restarts += 1
     sigma = s[:r_eff].copy()
     V = fac.P @ Y[:, :r_eff] if r_eff else np.zeros((n, 0))
@@ -321,7 +380,8 @@ def partial_svd(A, r: int, k: int, tol: float, max_restarts: int, q: np.ndarray,
         status = NOT_CONVERGED
     return {"sigma": sigma, "U": U, "V": V, "res_est": res[:r_eff].copy(), "nconv": nconv,
             "restarts": restarts, "matvecs": fac.matvecs, "status": status,
-            "breakdown": fac.breakdown, "keep": l, "cycles": cycles, "factorization": fac}
+            "breakdown": fac.breakdown, "keep": l, "cycles": cycles, "factorization": fac,
+            "checks": stop.checks if stop else 0}
 
 
 # ---------------------------------------------------------------------------

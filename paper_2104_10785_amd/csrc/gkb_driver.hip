@@ -227,42 +227,6 @@ struct Solver {
     return GKB_OK;
   }
 
-  // Assemble the first cycle's lower bidiagonal from the coefficients.
-  gkb_status assemble_first(int k, const std::vector<double>& qc, const std::vector<double>& pc,
-                            const int* fl, Proj& pr) {
-    int code = fl[0], idx = fl[1];
-    if (code == 3) return fail(GKB_ERR_NUMERIC, "NaN or Inf in a norm (non-finite input?)");
-    if (code == 1 && idx == 0) return fail(GKB_ERR_INVALID, "start vector is zero");
-    int nq, np;
-    if (code == 0) {
-      nq = k + 1;
-      np = k;
-      pr.matvecs = 1 + 2 * (int64_t)k;
-    } else if (code == 1) {
-      nq = np = idx;
-      pr.matvecs = 2 * (int64_t)idx;
-    } else {
-      np = idx;
-      nq = idx == 0 ? 1 : idx + 1;
-      pr.matvecs = 1 + 2 * (int64_t)idx;
-    }
-    pr.nq = nq;
-    pr.np = np;
-    pr.breakdown = code;
-    pr.H.assign((size_t)nq * std::max(np, 1), 0.0);
-    pr.sig_seen = 0.0;
-    for (int j = 0; j < np; ++j) {
-      pr.H[(size_t)j * np + j] = pc[j];
-      pr.sig_seen = std::max(pr.sig_seen, pc[j]);
-      if (j + 1 < nq) {
-        pr.H[(size_t)(j + 1) * np + j] = qc[j + 1];
-        pr.sig_seen = std::max(pr.sig_seen, qc[j + 1]);
-      }
-    }
-    pr.alpha_res = code == 0 ? pc[k] : 0.0;
-    if (code == 0) pr.sig_seen = std::max(pr.sig_seen, pc[k]);
-    return GKB_OK;
-  }
 };
 
 struct Ritz {
@@ -288,6 +252,104 @@ void to_colmajor(const std::vector<double>& M, int rows, int ldrow, int cols, st
     for (int i = 0; i < rows; ++i) out[(size_t)c * rows + i] = (TB)M[(size_t)i * ldrow + c];
 }
 
+// Convergence test on a projected matrix (same rule as the oracle): the r
+// largest Ritz values above the breakdown threshold must all satisfy
+// alpha_res |X[last, i]| <= tol * sigma_1.
+struct ConvTest {
+  bool converged = false;
+  int r_eff = 0, nconv = 0;
+  std::vector<double> res;
+};
+
+void convergence(const Proj& pr, const Ritz& rz, int r, double tol, double thr, ConvTest& ct) {
+  int avail = 0;
+  for (int i = 0; i < rz.kk; ++i)
+    if (rz.s[i] > thr) ++avail;
+  ct.r_eff = std::min(r, avail);
+  ct.res.assign(std::max(rz.kk, 1), 0.0);
+  for (int i = 0; i < rz.kk; ++i) ct.res[i] = pr.alpha_res * std::fabs(rz.X[(size_t)(pr.nq - 1) * rz.kk + i]);
+  ct.nconv = 0;
+  const double s0 = rz.kk ? rz.s[0] : 0.0;
+  for (int i = 0; i < ct.r_eff; ++i)
+    if (ct.res[i] <= tol * s0) ++ct.nconv;
+  ct.converged = ct.r_eff == r && ct.nconv == r;
+}
+
+// Restart data carried into a restarted cycle.
+struct RestartIn {
+  int l = 0;
+  std::vector<double> s, rho;
+};
+
+// Projected matrix after `np` right vectors of a cycle (no breakdown), or at a
+// breakdown recorded in fl.  first: lower bidiagonal; else restarted form.
+gkb_status assemble(bool first, int np_now, const RestartIn& rs, const std::vector<double>& qc,
+                    const std::vector<double>& pc, const int* fl, Proj& pr) {
+  const int code = fl[0], idx = fl[1];
+  if (code == 3) return fail(GKB_ERR_NUMERIC, "NaN or Inf in a norm (non-finite input?)");
+  if (first && code == 1 && idx == 0) return fail(GKB_ERR_INVALID, "start vector is zero");
+  int nq, np;
+  const int l = rs.l;
+  if (first) {
+    if (code == 0) {
+      np = np_now;
+      nq = np + 1;
+      pr.matvecs = 1 + 2 * (int64_t)np;
+    } else if (code == 1) {
+      nq = np = idx;
+      pr.matvecs = 2 * (int64_t)idx;
+    } else {
+      np = idx;
+      nq = idx == 0 ? 1 : idx + 1;
+      pr.matvecs = 1 + 2 * (int64_t)idx;
+    }
+  } else {
+    if (code == 0) {
+      nq = np = np_now;
+      pr.matvecs = 2 * (int64_t)(np_now - l);
+    } else if (code == 1) {
+      nq = idx;
+      np = idx + 1;
+      pr.matvecs = 2 * (int64_t)(idx - l) + 1;
+    } else {
+      nq = np = idx;
+      pr.matvecs = 2 * (int64_t)(idx - l);
+    }
+  }
+  pr.nq = nq;
+  pr.np = np;
+  pr.breakdown = code;
+  pr.H.assign((size_t)nq * std::max(np, 1), 0.0);
+  double seen = 0.0;
+  if (first) {
+    for (int j = 0; j < np; ++j) {
+      pr.H[(size_t)j * np + j] = pc[j];
+      seen = std::max(seen, pc[j]);
+      if (j + 1 < nq) {
+        pr.H[(size_t)(j + 1) * np + j] = qc[j + 1];
+        seen = std::max(seen, qc[j + 1]);
+      }
+    }
+  } else {
+    for (int i = 0; i < l && i < nq; ++i) {
+      if (i < np) pr.H[(size_t)i * np + i] = rs.s[i];
+      if (l < np) pr.H[(size_t)i * np + l] = rs.rho[i];
+    }
+    for (int j = l; j < nq; ++j) {
+      pr.H[(size_t)j * np + j] = qc[j];
+      seen = std::max(seen, qc[j]);
+      if (j + 1 < np) {
+        pr.H[(size_t)j * np + j + 1] = pc[j + 1];
+        seen = std::max(seen, pc[j + 1]);
+      }
+    }
+  }
+  pr.alpha_res = code == 0 ? pc[np] : 0.0;
+  if (code == 0) seen = std::max(seen, pc[np]);
+  pr.sig_seen = seen;
+  return GKB_OK;
+}
+
 template <typename TB>
 gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int max_restarts,
                            const gkb_options& opt, void* workspace, double* sigma, TB* U, TB* V,
@@ -297,8 +359,9 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   Solver<TB> S;
   S.A = {Am->data, Am->m, Am->n, Am->lda, (int)Am->dtype};
   S.st = st;
-  int l = opt.keep ? opt.keep : std::min(r + (k - r) / 2, k - 1);
+  const int l = opt.keep ? opt.keep : std::min(r + (k - r) / 2, k - 1);
   if (k == r) max_restarts = 0;
+  const int every = opt.check_every > 0 ? opt.check_every : 0;
   S.L = make_layout(Am->m, Am->n, Am->dtype, k, k > r, true);
   S.ws = reinterpret_cast<char*>(workspace);
   S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
@@ -310,51 +373,87 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   }
   gkb_status rc = S.start(q1);
   if (rc != GKB_OK) return rc;
-  for (int s = 0; s < k; ++s) {
-    rc = S.first_step(s);
-    if (rc != GKB_OK) return rc;
-  }
+
+  double sig_est = 0.0;  // largest accepted coefficient / Ritz value so far
+  int64_t matvecs = 0;
+  int restarts = 0, checks = 0;
+  Proj pr;
+  Ritz rz;
+  ConvTest ct;
+  RestartIn rs;
   std::vector<double> qc, pc;
   int fl[2] = {0, 0};
-  rc = S.read_back(k + 2, qc, pc, fl);
-  if (rc != GKB_OK) return rc;
-  Proj pr;
-  rc = S.assemble_first(k, qc, pc, fl, pr);
-  if (rc != GKB_OK) return rc;
-  double sig_est = pr.sig_seen;
-  int64_t matvecs = pr.matvecs;
-  int restarts = 0;
-  Ritz rz;
-  std::vector<double> res;
-  int r_eff = 0, nconv = 0;
+  bool first = true;
   while (true) {
-    const double th0 = now_ms();
-    rc = host_svd(pr, rz);
-    ms_host += now_ms() - th0;
-    if (rc != GKB_OK) return rc;
-    const double thr = S.relative ? S.eps * sig_est : S.eps;
-    int avail = 0;
-    for (int i = 0; i < rz.kk; ++i)
-      if (rz.s[i] > thr) ++avail;
-    r_eff = std::min(r, avail);
-    res.assign(std::max(rz.kk, 1), 0.0);
-    for (int i = 0; i < rz.kk; ++i) res[i] = pr.alpha_res * std::fabs(rz.X[(size_t)(pr.nq - 1) * rz.kk + i]);
-    nconv = 0;
-    const double s0 = rz.kk ? rz.s[0] : 0.0;
-    for (int i = 0; i < r_eff; ++i)
-      if (res[i] <= tol * s0) ++nconv;
-    const bool done = pr.breakdown != 0 || (r_eff == r && nconv == r);
+    // ---- one cycle: steps jstart..k-1, with optional in-cycle checks
+    const int jstart = first ? 0 : l;
+    bool early = false;
+    for (int j = jstart; j < k; ++j) {
+      if (first) {
+        rc = S.first_step(j);
+        if (rc != GKB_OK) return rc;
+      } else {
+        // w = A p_j - (j == l ? Q~ rho : alpha_j q_{j-1})
+        GKB_HIP(gkb::launch_gemv_n<TB>(S.A, S.Pc(j), j == l ? nullptr : S.Qc(j - 1), S.pcoef(), j, S.w(),
+                                       S.flag(), st));
+        if (j == l)
+          GKB_HIP(gkb::launch_update<TB>(S.Q(S.cur), S.L.ldm, l, Am->m, S.w(), S.rho(), nullptr, S.flag(), st));
+        GKB_HIP(S.cgs2(S.Q(S.cur), S.L.ldm, j, Am->m, S.w()));
+        GKB_HIP(S.normalize(S.w(), Am->m, S.Qc(j), S.qcoef() + j, 1, 1, j, true));
+        GKB_HIP(gkb::launch_gemv_t<TB>(S.A, S.Qc(j), S.Pc(j), S.qcoef(), j, S.z(), S.part(), S.L.ldpart,
+                                       S.flag(), st));
+        GKB_HIP(S.cgs2(S.P(S.cur), S.L.ldn, j + 1, Am->n, S.z()));
+        GKB_HIP(S.normalize(S.z(), Am->n, S.Pc(j + 1), S.pcoef() + j + 1, 1, 2, j + 1, true));
+      }
+      const int np_now = j + 1;
+      if (every > 0 && np_now < k && np_now >= r && np_now % every == 0) {
+        rc = S.read_back(k + 2, qc, pc, fl);
+        if (rc != GKB_OK) return rc;
+        if (fl[0] != 0) break;  // breakdown: assembled below
+        Proj part;
+        rc = assemble(first, np_now, rs, qc, pc, fl, part);
+        if (rc != GKB_OK) return rc;
+        const double th0 = now_ms();
+        rc = host_svd(part, rz);
+        ms_host += now_ms() - th0;
+        if (rc != GKB_OK) return rc;
+        ++checks;
+        const double se = std::max(sig_est, part.sig_seen);
+        convergence(part, rz, r, tol, S.relative ? S.eps * se : S.eps, ct);
+        if (ct.converged) {
+          pr = part;
+          early = true;
+          break;
+        }
+      }
+    }
+    if (!early) {
+      rc = S.read_back(k + 2, qc, pc, fl);
+      if (rc != GKB_OK) return rc;
+      rc = assemble(first, k, rs, qc, pc, fl, pr);
+      if (rc != GKB_OK) return rc;
+      const double th0 = now_ms();
+      rc = host_svd(pr, rz);
+      ms_host += now_ms() - th0;
+      if (rc != GKB_OK) return rc;
+    }
+    sig_est = std::max(sig_est, pr.sig_seen);
+    matvecs += pr.matvecs;
+    convergence(pr, rz, r, tol, S.relative ? S.eps * sig_est : S.eps, ct);
+    const bool done = pr.breakdown != 0 || ct.converged;
     if (done || restarts >= max_restarts) break;
-    sig_est = std::max(sig_est, s0);
     // ---- thick restart: P~ = P Y_l, Q~ = Q X_l, p_{l+1} = p_res, rho = alpha_res X[last, :l]
+    sig_est = std::max(sig_est, rz.s[0]);
     std::vector<TB> Xh, Yh;
     to_colmajor<TB>(rz.X, pr.nq, rz.kk, l, Xh);
     to_colmajor<TB>(rz.Y, pr.np, rz.kk, l, Yh);
-    std::vector<double> rho(l);
-    for (int i = 0; i < l; ++i) rho[i] = pr.alpha_res * rz.X[(size_t)(pr.nq - 1) * rz.kk + i];
+    rs.l = l;
+    rs.s.assign(rz.s.begin(), rz.s.begin() + l);
+    rs.rho.assign(l, 0.0);
+    for (int i = 0; i < l; ++i) rs.rho[i] = pr.alpha_res * rz.X[(size_t)(pr.nq - 1) * rz.kk + i];
     GKB_HIP(hipMemcpyAsync(S.Xs(), Xh.data(), Xh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
     GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
-    GKB_HIP(hipMemcpyAsync(S.rho(), rho.data(), l * sizeof(double), hipMemcpyHostToDevice, st));
+    GKB_HIP(hipMemcpyAsync(S.rho(), rs.rho.data(), l * sizeof(double), hipMemcpyHostToDevice, st));
     const int nb = 1 - S.cur;
     GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, S.Ys(), pr.np, l, S.P(nb), S.L.ldn,
                                       st));
@@ -365,88 +464,39 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     S.cur = nb;
     S.nsig = 0;
     GKB_HIP(gkb::launch_init_cycle(S.flag(), S.sig(), sig_est, st));
-    for (int j = l; j < k; ++j) {
-      // w = A p_j - (j == l ? Q~ rho : alpha_j q_{j-1})
-      GKB_HIP(gkb::launch_gemv_n<TB>(S.A, S.Pc(j), j == l ? nullptr : S.Qc(j - 1), S.pcoef(), j, S.w(),
-                                     S.flag(), st));
-      if (j == l)
-        GKB_HIP(gkb::launch_update<TB>(S.Q(S.cur), S.L.ldm, l, Am->m, S.w(), S.rho(), nullptr, S.flag(), st));
-      GKB_HIP(S.cgs2(S.Q(S.cur), S.L.ldm, j, Am->m, S.w()));
-      GKB_HIP(S.normalize(S.w(), Am->m, S.Qc(j), S.qcoef() + j, 1, 1, j, true));
-      GKB_HIP(gkb::launch_gemv_t<TB>(S.A, S.Qc(j), S.Pc(j), S.qcoef(), j, S.z(), S.part(), S.L.ldpart,
-                                     S.flag(), st));
-      GKB_HIP(S.cgs2(S.P(S.cur), S.L.ldn, j + 1, Am->n, S.z()));
-      GKB_HIP(S.normalize(S.z(), Am->n, S.Pc(j + 1), S.pcoef() + j + 1, 1, 2, j + 1, true));
-    }
-    rc = S.read_back(k + 2, qc, pc, fl);
-    if (rc != GKB_OK) return rc;
-    if (fl[0] == 3) return fail(GKB_ERR_NUMERIC, "NaN or Inf in a norm");
-    // assemble the restarted k x k upper-triangular H
-    Proj np2;
-    int nq2 = k, npp = k;
-    if (fl[0] == 1) {
-      nq2 = fl[1];
-      npp = fl[1] + 1;
-      np2.matvecs = 2 * (int64_t)(fl[1] - l) + 1;
-    } else if (fl[0] == 2) {
-      nq2 = npp = fl[1];
-      np2.matvecs = 2 * (int64_t)(fl[1] - l);
-    } else {
-      np2.matvecs = 2 * (int64_t)(k - l);
-    }
-    np2.nq = nq2;
-    np2.np = npp;
-    np2.breakdown = fl[0];
-    np2.H.assign((size_t)nq2 * npp, 0.0);
-    double seen = 0.0;
-    for (int i = 0; i < l && i < nq2; ++i) {
-      if (i < npp) np2.H[(size_t)i * npp + i] = rz.s[i];
-      if (l < npp) np2.H[(size_t)i * npp + l] = rho[i];
-    }
-    for (int j = l; j < nq2; ++j) {
-      np2.H[(size_t)j * npp + j] = qc[j];
-      seen = std::max(seen, qc[j]);
-      if (j + 1 < npp) {
-        np2.H[(size_t)j * npp + j + 1] = pc[j + 1];
-        seen = std::max(seen, pc[j + 1]);
-      }
-    }
-    np2.alpha_res = fl[0] == 0 ? pc[k] : 0.0;
-    if (fl[0] == 0) seen = std::max(seen, pc[k]);
-    sig_est = std::max(sig_est, seen);
-    matvecs += np2.matvecs;
-    pr = np2;
     ++restarts;
+    first = false;
   }
   // ---- Ritz vectors: V = P Y_r, U = Q X_r
+  const int r_eff = ct.r_eff;
   for (int i = 0; i < r; ++i) sigma[i] = i < r_eff ? rz.s[i] : 0.0;
   if (r_eff > 0) {
     std::vector<TB> Xh, Yh;
     to_colmajor<TB>(rz.X, pr.nq, rz.kk, r_eff, Xh);
     to_colmajor<TB>(rz.Y, pr.np, rz.kk, r_eff, Yh);
-    TB* Xd = S.Xs();
-    TB* Yd = S.Ys();
-    GKB_HIP(hipMemcpyAsync(Xd, Xh.data(), Xh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
-    GKB_HIP(hipMemcpyAsync(Yd, Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
-    GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, Yd, pr.np, r_eff, V, Am->n, st));
-    GKB_HIP(gkb::launch_gemm_tall<TB>(S.Q(S.cur), S.L.ldm, Am->m, pr.nq, Xd, pr.nq, r_eff, U, Am->m, st));
+    GKB_HIP(hipMemcpyAsync(S.Xs(), Xh.data(), Xh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
+    GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
+    GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, S.Ys(), pr.np, r_eff, V, Am->n, st));
+    GKB_HIP(gkb::launch_gemm_tall<TB>(S.Q(S.cur), S.L.ldm, Am->m, pr.nq, S.Xs(), pr.nq, r_eff, U, Am->m, st));
     GKB_HIP(hipStreamSynchronize(st));
   }
   if (stats) {
-    stats->nconv = nconv;
+    stats->nconv = ct.nconv;
     stats->restarts = restarts;
     stats->breakdown = pr.breakdown;
     stats->returned = r_eff;
     stats->matvecs = matvecs;
     double mr = 0.0;
-    for (int i = 0; i < r_eff; ++i) mr = std::max(mr, res[i]);
+    for (int i = 0; i < r_eff; ++i) mr = std::max(mr, ct.res[i]);
     stats->max_res_est = mr;
     stats->sigma1_est = rz.kk ? rz.s[0] : 0.0;
     stats->ms_total = now_ms() - t0;
     stats->ms_host = ms_host;
+    stats->checks = checks;
+    stats->krylov_dim = pr.np;
   }
   if (r_eff < r) return GKB_RANK_DEFICIENT;
-  return nconv == r ? GKB_OK : GKB_NOT_CONVERGED;
+  return ct.nconv == r ? GKB_OK : GKB_NOT_CONVERGED;
 }
 
 template <typename TB>
@@ -487,7 +537,8 @@ gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, c
   rc = S.read_back(k + 2, qc, pc, fl);
   if (rc != GKB_OK) return rc;
   Proj pr;
-  rc = S.assemble_first(k, qc, pc, fl, pr);
+  RestartIn none;
+  rc = assemble(true, k, none, qc, pc, fl, pr);
   if (rc != GKB_OK) return rc;
   const int np = pr.np, nq = pr.nq;
   std::vector<double> alpha(std::max(np, 1)), beta(std::max(nq, 1)), s(std::max(np, 1));

@@ -71,6 +71,24 @@ __device__ __forceinline__ uint4 ld_stream(const void* p) {
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// n consecutive basis values from a 16-byte aligned address, as the
+// accumulator type (zeros when !ok).
+template <typename TB, int VN, typename ACC>
+__device__ __forceinline__ void load_vec(const TB* ptr, bool ok, ACC* out) {
+  if constexpr ((VN * sizeof(TB)) % 16 == 0) {
+    constexpr int NQ = VN * sizeof(TB) / 16;
+    uint4 raw[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) raw[i] = ok ? reinterpret_cast<const uint4*>(ptr)[i] : make_uint4(0, 0, 0, 0);
+    const TB* vals = reinterpret_cast<const TB*>(raw);
+#pragma unroll
+    for (int e = 0; e < VN; ++e) out[e] = (ACC)vals[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < VN; ++e) out[e] = ok ? (ACC)ptr[e] : (ACC)0;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -125,8 +143,7 @@ __global__ __launch_bounds__(256) void k_gemv_n(const TA* __restrict__ A, int64_
         const bool ok = v < nv;
 #pragma unroll
         for (int r = 0; r < R; ++r) a[u][r] = ok ? ld_stream(rows[r] + v * VN) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-        for (int e = 0; e < VN; ++e) pv[u][e] = ok ? (ACC)p[v * VN + e] : (ACC)0;
+        load_vec<TB, VN>(p + v * VN, ok, pv[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -230,8 +247,16 @@ __global__ __launch_bounds__(256) void k_gemv_t_reduce(const ACC* __restrict__ p
   if (flag != nullptr && flag[0] != 0) return;
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += (double)part[(int64_t)b * ldpart + j];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int b = 0;
+  for (; b + 4 <= nb; b += 4) {
+    s0 += (double)part[(int64_t)b * ldpart + j];
+    s1 += (double)part[(int64_t)(b + 1) * ldpart + j];
+    s2 += (double)part[(int64_t)(b + 2) * ldpart + j];
+    s3 += (double)part[(int64_t)(b + 3) * ldpart + j];
+  }
+  for (; b < nb; ++b) s0 += (double)part[(int64_t)b * ldpart + j];
+  double s = (s0 + s1) + (s2 + s3);
   if (pprev != nullptr) s -= coef[cidx] * (double)pprev[j];
   z[j] = s;
 }
@@ -271,74 +296,68 @@ __global__ __launch_bounds__(256) void k_dots(const TB* __restrict__ V, int64_t 
   }
 }
 
-// h[j] = sum_c hpart[c * ldh + j]; optionally hacc[j] += h[j] (record).
-__global__ __launch_bounds__(256) void k_dots_reduce(const double* __restrict__ hpart, int ldh,
-                                                     int nchunks, int t, double* __restrict__ h,
-                                                     const int* __restrict__ flag) {
+// h[j] = sum_c hpart[c * ldh + j]: one wave per column, lanes stride the
+// chunks, then a fixed-order wave reduction.
+__global__ __launch_bounds__(64) void k_dots_reduce(const double* __restrict__ hpart, int ldh, int nchunks,
+                                                    int t, double* __restrict__ h,
+                                                    const int* __restrict__ flag) {
   if (flag != nullptr && flag[0] != 0) return;
-  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.x;
   if (j >= t) return;
   double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += hpart[(int64_t)c * ldh + j];
-  h[j] = s;
+  for (int c = threadIdx.x; c < nchunks; c += 64) s += hpart[(int64_t)c * ldh + j];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) h[j] = s;
 }
 
-// x[i] -= sum_{j<t} V[j * ldv + i] h[j]; if normpart, normpart[block] =
-// sum over the block's rows of x[i]^2 (after the update).
-constexpr int UE = 4;  // rows per thread in the update
+// x[i] -= sum_{j<t} V[j * ldv + i] h[j] for the block's 64 rows (lane = row).
+// The four waves take contiguous quarters of the columns and their partial
+// corrections are added in a fixed order through LDS.  If normpart is
+// non-null, normpart[block] = sum over the block's rows of the updated x^2.
+constexpr int UROWS = 64;
 template <typename TB>
 __global__ __launch_bounds__(256) void k_update(const TB* __restrict__ V, int64_t ldv, int t, int64_t len,
                                                 double* __restrict__ x, const double* __restrict__ h,
                                                 double* __restrict__ normpart,
                                                 const int* __restrict__ flag) {
   if (flag != nullptr && flag[0] != 0) return;
-  __shared__ double red[4];
-  const int64_t base = (int64_t)blockIdx.x * 256 * UE + threadIdx.x;
-  double xr[UE];
-#pragma unroll
-  for (int e = 0; e < UE; ++e) {
-    const int64_t i = base + e * 256;
-    xr[e] = i < len ? x[i] : 0.0;
-  }
-  int j = 0;
-  for (; j + 4 <= t; j += 4) {
-    const double h0 = h[j], h1 = h[j + 1], h2 = h[j + 2], h3 = h[j + 3];
-    const TB* c0 = V + (int64_t)j * ldv;
-    const TB* c1 = c0 + ldv;
-    const TB* c2 = c1 + ldv;
-    const TB* c3 = c2 + ldv;
-#pragma unroll
-    for (int e = 0; e < UE; ++e) {
-      const int64_t i = base + e * 256;
-      if (i < len) {
-        xr[e] -= (double)c0[i] * h0;
-        xr[e] -= (double)c1[i] * h1;
-        xr[e] -= (double)c2[i] * h2;
-        xr[e] -= (double)c3[i] * h3;
-      }
+  __shared__ double part[3][UROWS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * UROWS + lane;
+  const bool in = i < len;
+  const int per = (t + 3) / 4;
+  const int j0 = wave * per;
+  int j1 = j0 + per;
+  if (j1 > t) j1 = t;
+  double c0 = 0.0, c1 = 0.0;
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    const TB* v0 = V + (int64_t)j * ldv;
+    const TB* v1 = v0 + ldv;
+    const TB* v2 = v1 + ldv;
+    const TB* v3 = v2 + ldv;
+    if (in) {
+      c0 += (double)v0[i] * h[j];
+      c1 += (double)v1[i] * h[j + 1];
+      c0 += (double)v2[i] * h[j + 2];
+      c1 += (double)v3[i] * h[j + 3];
     }
   }
-  for (; j < t; ++j) {
-    const double hj = h[j];
-    const TB* cj = V + (int64_t)j * ldv;
-#pragma unroll
-    for (int e = 0; e < UE; ++e) {
-      const int64_t i = base + e * 256;
-      if (i < len) xr[e] -= (double)cj[i] * hj;
+  for (; j < j1; ++j)
+    if (in) c0 += (double)V[(int64_t)j * ldv + i] * h[j];
+  const double c = c0 + c1;
+  if (wave > 0) part[wave - 1][lane] = c;
+  __syncthreads();
+  if (wave == 0) {
+    double xi = 0.0;
+    if (in) {
+      xi = x[i] - (((c + part[0][lane]) + part[1][lane]) + part[2][lane]);
+      x[i] = xi;
     }
-  }
-  double ss = 0.0;
-#pragma unroll
-  for (int e = 0; e < UE; ++e) {
-    const int64_t i = base + e * 256;
-    if (i < len) {
-      x[i] = xr[e];
-      ss += xr[e] * xr[e];
+    if (normpart != nullptr) {
+      const double ss = wave_sum(xi * xi);
+      if (lane == 0) normpart[blockIdx.x] = ss;
     }
-  }
-  if (normpart != nullptr) {
-    const double tot = block_sum256(ss, red);
-    if (threadIdx.x == 0) normpart[blockIdx.x] = tot;
   }
 }
 
@@ -537,7 +556,8 @@ template <typename TA, typename TB>
 hipError_t launch_gemv_n_t(const TA* A, int64_t lda, int64_t m, int64_t n, const TB* p, const TB* qprev,
                            const double* coef, int cidx, double* w, const int* flag, hipStream_t st) {
   constexpr int R = 4;
-  const bool vec = ((lda % Pack<TA>::VN) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  const bool vec = ((lda % Pack<TA>::VN) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
   dim3 grid(nblocks(m, 4 * R));
   if (vec)
     hipLaunchKernelGGL((k_gemv_n<TA, TB, R, true>), grid, dim3(256), 0, st, A, lda, m, n, p, qprev, coef,
@@ -619,7 +639,7 @@ hipError_t launch_gemv_t(const MatrixRef& A, const TB* q, const TB* pprev, const
 }
 
 int dots_chunks(int64_t len) { return (int)nblocks(len, 64 * DE); }
-int update_blocks(int64_t len) { return (int)nblocks(len, 256 * UE); }
+int update_blocks(int64_t len) { return (int)nblocks(len, UROWS); }
 
 template <typename TB>
 hipError_t launch_dots(const TB* V, int64_t ldv, int t, int64_t len, const double* x, double* hpart,
@@ -630,7 +650,7 @@ hipError_t launch_dots(const TB* V, int64_t ldv, int t, int64_t len, const doubl
   hipLaunchKernelGGL((k_dots<TB>), grid, dim3(256), 0, st, V, ldv, t, len, x, hpart, ldh, flag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dots_reduce, dim3(nblocks(t, 256)), dim3(256), 0, st, hpart, ldh, nch, t, h, flag);
+  hipLaunchKernelGGL(k_dots_reduce, dim3(t), dim3(64), 0, st, hpart, ldh, nch, t, h, flag);
   return hipGetLastError();
 }
 

@@ -34,13 +34,14 @@ class GkbMatrix(C.Structure):
 
 class GkbOptions(C.Structure):
     _fields_ = [("keep", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
-                ("q1", C.c_void_p), ("seed", C.c_uint64), ("refine_dim", C.c_int)]
+                ("q1", C.c_void_p), ("seed", C.c_uint64), ("refine_dim", C.c_int), ("check_every", C.c_int)]
 
 
 class GkbStats(C.Structure):
     _fields_ = [("nconv", C.c_int), ("restarts", C.c_int), ("breakdown", C.c_int), ("returned", C.c_int),
                 ("matvecs", C.c_int64), ("max_res_est", C.c_double), ("sigma1_est", C.c_double),
-                ("ms_total", C.c_double), ("ms_host", C.c_double)]
+                ("ms_total", C.c_double), ("ms_host", C.c_double), ("checks", C.c_int),
+                ("krylov_dim", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -155,7 +156,8 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def make_options(q1=None, seed=0, keep=0, eps_break=0.0, eps_relative=True, refine_dim=0) -> GkbOptions:
+def make_options(q1=None, seed=0, keep=0, eps_break=0.0, eps_relative=True, refine_dim=0,
+                 check_every=0) -> GkbOptions:
     o = GkbOptions()
     lib().gkb_default_options(C.byref(o))
     o.keep = keep
@@ -163,6 +165,7 @@ def make_options(q1=None, seed=0, keep=0, eps_break=0.0, eps_relative=True, refi
     o.eps_break = eps_break
     o.seed = seed
     o.refine_dim = refine_dim
+    o.check_every = check_every
     if q1 is not None:
         if q1.dtype != _torch().float64 or not q1.is_cuda or not q1.is_contiguous():
             raise ValueError("q1 must be a contiguous float64 device tensor")

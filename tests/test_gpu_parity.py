@@ -194,3 +194,86 @@ def test_determinism(c1):
     a = run_gpu(A, 10, 30, 1e-10, 50, q)
     b = run_gpu(A, 10, 30, 1e-10, 50, q)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_c1_in_cycle_checks_match_oracle(c1):
+    device()
+    A, Q1, Q2, s, q = c1
+    banner("c1 f64 with check_every=5")
+    ref = gk.partial_svd(A, 10, 30, 1e-10, 50, q, check_every=5)
+    sigma, U, V, status, stats = run_gpu(A, 10, 30, 1e-10, 50, q, check_every=5)
+    assert status == 0 and ref["status"] == 0
+    assert np.max(np.abs(sigma - ref["sigma"]) / ref["sigma"]) <= 1e-10
+    assert np.min(checks.alignment(ref["U"], ref["V"], U, V)) >= 1 - 1e-8
+    assert stats["krylov_dim"] == ref["factorization"].H.shape[1]
+    assert stats["matvecs"] == ref["matvecs"] and stats["restarts"] == ref["restarts"]
+    assert stats["matvecs"] < 101  # fewer than without in-cycle checks
+
+
+def test_restarted_cycle_with_checks():
+    device()
+    banner("300x100 f64 r=8 k=20 check_every=3 with restarts")
+    s = np.concatenate([np.geomspace(1.0, 0.5, 8), np.geomspace(0.45, 0.01, 92)])
+    A, Q1, Q2 = inputs.svd_matrix(300, 100, s, seed=21)
+    q = inputs.start_vector(300, seed=22)
+    ref = gk.partial_svd(A, 8, 20, 1e-11, 200, q, check_every=3)
+    sigma, U, V, status, stats = run_gpu(A, 8, 20, 1e-11, 200, q, check_every=3)
+    assert status == 0 and ref["status"] == 0 and ref["restarts"] > 0
+    assert abs(stats["restarts"] - ref["restarts"]) <= 1
+    assert np.max(np.abs(sigma - s[:8]) / s[:8]) <= 1e-10
+    assert np.min(checks.alignment(Q1[:, :8], Q2[:, :8], U, V)) >= 1 - 1e-8
+
+
+def _host_residuals(A32, sigma, U, V, rows=2000):
+    """||A v_i - sigma_i u_i|| and ||A^T u_i - sigma_i v_i|| in float64, A in row blocks."""
+    m, n = A32.shape
+    AV = np.zeros((m, V.shape[1]))
+    ATU = np.zeros((n, U.shape[1]))
+    for r0 in range(0, m, rows):
+        blk = A32[r0:r0 + rows].astype(np.float64)
+        AV[r0:r0 + rows] = blk @ V
+        ATU += blk.T @ U[r0:r0 + rows]
+    return (np.linalg.norm(AV - U * sigma[None, :], axis=0),
+            np.linalg.norm(ATU - V * sigma[None, :], axis=0))
+
+
+@pytest.mark.parametrize("check_every", [0, 10])
+def test_c2_fullsize_f32_against_stored_oracle(check_every):
+    """50000 x 20000 float32 at the benchmark's launch configuration.
+
+    Expected values: tests/golden/c2_oracle_top50.json, written by
+    tests/golden/make_c2_reference.py from the float64 oracle on the exact
+    upcast of the same float32 matrix.  Tolerance on sigma: the float32
+    products carry a rounding error of about sqrt(n) u ||A||_F per matvec
+    (random-walk accumulation), which bounds the Ritz-value perturbation.
+    """
+    import json
+    import os
+    import torch
+    device()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_top50.json")))
+    banner(f"c2 full size 50000x20000 f32 r=50 k=120 check_every={check_every}")
+    A32, s, _, _ = inputs.lowrank_noise(50000, 20000, 200, 0.95, 1e-6, seed=2, dtype=np.float32)
+    q = inputs.start_vector(50000, seed=1)
+    Ad = torch.from_numpy(A32).to("cuda:0")
+    sigma, Ut, Vt, status, stats = gkb.gkb_partial_svd(Ad, 50, 120, 1e-6, 20, q1=to_dev(q),
+                                                       check_every=check_every)
+    torch.cuda.synchronize()
+    del Ad
+    assert status == 0 and stats["nconv"] == 50
+    want = np.array(ref["sigma"])
+    fro = float(np.sqrt(np.sum(s ** 2) + 1e-12 * A32.size))
+    bound = np.sqrt(20000) * 2.0 ** -24 * fro
+    err = np.abs(sigma - want)
+    print(f"c2 sigma max abs err {err.max():.3e} (bound {bound:.3e}), max rel {np.max(err / want):.3e}, "
+          f"matvecs {stats['matvecs']} (oracle {ref['matvecs']})", flush=True)
+    assert np.all(err <= bound)
+    if check_every == 0:
+        assert stats["matvecs"] == ref["matvecs"]
+    U = to_host(Ut).T.astype(np.float64)
+    V = to_host(Vt).T.astype(np.float64)
+    idx = [0, 1, 24, 48, 49]
+    r1, r2 = _host_residuals(A32, sigma[idx], U[:, idx], V[:, idx])
+    print(f"c2 residuals ||Av-su|| {r1.max():.3e} ||A^T u - s v|| {r2.max():.3e}", flush=True)
+    assert np.max(r1) <= 10 * bound and np.max(r2) <= 1e-6 * sigma[0] + 10 * bound
+    assert checks.orth_error(V[:, idx]) < 1e-5 and checks.orth_error(U[:, idx]) < 1e-5
