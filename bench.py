@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 M, N, RANK, DECAY, NOISE, SEED, QSEED = 50000, 20000, 200, 0.95, 1e-6, 2, 1
 R, K, TOL, RESTARTS = 50, 120, 1e-6, 20
+CHECK_EVERY = 10
 HBM_PEAK_GBS = 8000.0
 
 
@@ -89,6 +90,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the Golub-Kahan path on a single "
@@ -110,8 +112,9 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    def step():
-        return gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream)
+    def step(check_every=args.check_every):
+        return gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
+                                   check_every=check_every)
 
     for i in range(args.warmup):
         out = step()
@@ -128,6 +131,13 @@ def main():
     ms_per_step = dt * 1000.0 / args.steps
     value = nconv / dt
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, stats={stats}")
+
+    # the same solve with the test only at the end of the cycle (fixed k = 120)
+    t1 = time.perf_counter()
+    fixed = step(check_every=0)
+    torch.cuda.synchronize()
+    fixed_ms = (time.perf_counter() - t1) * 1000.0
+    log(f"fixed-k solve: {fixed_ms:.2f} ms, stats={fixed[4]}")
 
     # ---- dominant kernels: the two A-streaming matvecs, timed live with HIP events
     mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=dev)
@@ -160,12 +170,16 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "gk_partial_svd low-rank(200, 0.95^i)+noise(1e-6) 50000x20000 f32",
-                   "r": R, "k": K, "tol": TOL, "max_restarts": RESTARTS, "parallelism": "single-gpu"},
+                   "r": R, "k": K, "tol": TOL, "max_restarts": RESTARTS, "check_every": args.check_every,
+                   "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "matvec": {"gemv_n_ms": ms_n, "gemv_n_GBps": gbs_n, "gemv_t_ms": ms_t, "gemv_t_GBps": gbs_t},
         "solve": {"nconv": stats["nconv"], "matvecs": stats["matvecs"], "restarts": stats["restarts"],
+                  "krylov_dim": stats["krylov_dim"], "checks": stats["checks"],
                   "ms_host_svd": stats["ms_host"], "sigma1": float(sigma[0]), "sigma50": float(sigma[-1])},
+        "fixed_k_solve": {"ms": fixed_ms, "triplets_per_s": fixed[4]["nconv"] / (fixed_ms / 1000.0),
+                          "matvecs": fixed[4]["matvecs"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

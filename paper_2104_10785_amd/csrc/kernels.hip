@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_gemv_t_reduce(const ACC* __restrict__ p
 // hpart[c * ldh + j] = sum_{i in chunk c} V[j * ldv + i] x[i]  for j < t.
 // Chunk = 64 * DE rows; each lane keeps its DE entries of x in registers and
 // each wave reduces one column at a time.
-constexpr int DE = 16;
+constexpr int DE = 4;
 constexpr int DCOLS = 16;  // columns per block (4 per wave)
 template <typename TB>
 __global__ __launch_bounds__(256) void k_dots(const TB* __restrict__ V, int64_t ldv, int t, int64_t len,
