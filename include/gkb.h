@@ -108,6 +108,9 @@ typedef struct {
   double ms_host;      /* of which host small SVDs                             */
   int checks;          /* in-cycle convergence tests performed                 */
   int krylov_dim;      /* right basis vectors in the final projected matrix    */
+  int refined;         /* bfloat16 refinement: 1 done, 0 not requested,        */
+                       /* -1 skipped (subspace numerically rank deficient)     */
+  double ms_refine;    /* wall time of the refinement                          */
 } gkb_stats;
 
 /* Fill *opt with the defaults above. */
@@ -130,6 +133,12 @@ size_t gkb_workspace_size(const gkb_matrix* A, int r, int k, const gkb_options* 
  *   V        device, column-major n x r, same element type.
  *   stats    host, optional (NULL).
  * Singular vectors are determined up to a common sign of (u_i, v_i).
+ * GKB_BF16 with A->refine_f32: the Golub-Kahan cycles run on the bfloat16
+ * matrix; the top d = refine_dim (default 2r, at most the Krylov dimension)
+ * Ritz vectors then span a Rayleigh-Ritz projection with the float32 matrix
+ * (eq. (5)): W = A32 V_d (MFMA), W^T W = R^T R (float64 Cholesky), R = X S Y^T,
+ * sigma = S, V = V_d Y, U = W R^-1 X.  Convergence status refers to the
+ * bfloat16 solve.
  */
 gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
                            const gkb_options* opt, void* workspace, size_t ws_bytes,

@@ -38,6 +38,25 @@ gkb_status gkb_gemm_tall(gkb_dtype dtype, const void* A, int64_t lda, int64_t M,
                          int64_t ldb, int N, void* C, int64_t ldc, void* stream);
 
 /*
+ * C (M x N, column-major, ldc >= M) = A (M x K, row-major, lda >= K) *
+ * B (K x N, column-major, ldb >= K), float32 on the 16x16x4 MFMA with the
+ * A and B tiles staged in LDS.  The block product of the Rayleigh-Ritz
+ * refinement (W = A V, eq. (5)) and of the sketch A Omega.
+ */
+gkb_status gkb_gemm_rowmajor(const float* A, int64_t lda, int64_t M, int64_t K, const float* B, int64_t ldb,
+                             int N, float* C, int64_t ldc, void* stream);
+
+/* Workspace bytes (float64 partial sums) for gkb_gram. */
+size_t gkb_gram_workspace_size(int64_t m, int d);
+
+/*
+ * G (d x d, row-major float64) = W^T W for a column-major float32 W (m x d,
+ * ldw >= m); float64 products and sums on the MFMA, deterministic order.
+ */
+gkb_status gkb_gram(const float* W, int64_t ldw, int64_t m, int d, double* G, void* workspace, size_t ws_bytes,
+                    void* stream);
+
+/*
  * bfloat16 storage of a float32 matrix: dst = RNE(src), row-major m x n
  * (leading dimensions lds, ldd >= n).  NaN stays NaN (quiet).
  */

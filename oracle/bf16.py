@@ -39,3 +39,25 @@ def rayleigh_ritz(A, Vl, r: int):
     Qw, R = np.linalg.qr(W)
     X, s, Yt = np.linalg.svd(R)
     return s[:r], Qw @ X[:, :r], Vl @ Yt.T[:, :r]
+
+
+def refined_partial_svd(A32, r: int, k: int, tol: float, max_restarts: int, q, refine_dim: int = 0,
+                        check_every: int = 0, eps_break: float = 1e-6):
+    """The bfloat16 storage form followed by the float32 refinement.
+
+    Golub-Kahan partial SVD (oracle.gk.partial_svd, float64 arithmetic) of the
+    bfloat16 rounding of A32; the top d Ritz vectors of its final projected
+    matrix (d = refine_dim, default 2 r, at most the Krylov dimension) then
+    span the Rayleigh-Ritz projection with A32 itself (eq. (5)).
+    Returns (unrefined result dict, (sigma, U, V) refined, d).
+    """
+    from . import gk
+    A32 = np.asarray(A32, dtype=np.float32)
+    A16 = from_bf16_bits(to_bf16_bits(A32))
+    out = gk.partial_svd(A16, r, k, tol, max_restarts, q, eps_break=eps_break, check_every=check_every)
+    fac = out["factorization"]
+    X, s, Y = gk.ritz(fac.H)
+    d = refine_dim if refine_dim > 0 else 2 * r
+    d = max(out["sigma"].size, min(d, s.size))
+    Vd = fac.P @ Y[:, :d]
+    return out, rayleigh_ritz(A32.astype(np.float64), Vd, out["sigma"].size), d

@@ -46,10 +46,11 @@ struct Layout {
   size_t Q[2] = {0, 0}, P[2] = {0, 0};
   size_t w = 0, z = 0, part = 0, hpart = 0, h = 0, normpart = 0;
   size_t qcoef = 0, pcoef = 0, sig = 0, flag = 0, Xs = 0, Ys = 0, rho = 0, q1 = 0;
+  size_t Vd = 0, Wr = 0, Gpart = 0, G = 0;  // bfloat16 refinement
   size_t total = 0;
 };
 
-Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool small) {
+Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool small, bool refine = false) {
   Layout L;
   const size_t tb = basis_bytes(dt);
   const size_t acc = dt == GKB_F64 ? 8 : 4;
@@ -92,6 +93,12 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
     L.rho = take((size_t)L.ldh * 8);
   }
   L.q1 = take((size_t)L.ldm * 8);
+  if (refine) {
+    L.Vd = take((size_t)L.ldn * L.kcols * 4);
+    L.Wr = take((size_t)L.ldm * L.kcols * 4);
+    L.Gpart = take((size_t)gkb::gram_chunks(m) * L.kcols * L.kcols * 8);
+    L.G = take((size_t)L.kcols * L.kcols * 8);
+  }
   L.total = off;
   return L;
 }
@@ -350,6 +357,87 @@ gkb_status assemble(bool first, int np_now, const RestartIn& rs, const std::vect
   return GKB_OK;
 }
 
+// Cholesky G = R^T R (R upper, row-major d x d).  False if G is not
+// numerically positive definite.
+bool cholesky_upper(int d, const std::vector<double>& G, std::vector<double>& R) {
+  R.assign((size_t)d * d, 0.0);
+  for (int j = 0; j < d; ++j) {
+    double s = G[(size_t)j * d + j];
+    for (int k = 0; k < j; ++k) s -= R[(size_t)k * d + j] * R[(size_t)k * d + j];
+    if (!(s > 0.0)) return false;
+    const double rjj = std::sqrt(s);
+    R[(size_t)j * d + j] = rjj;
+    for (int i = j + 1; i < d; ++i) {
+      double t = G[(size_t)j * d + i];
+      for (int k = 0; k < j; ++k) t -= R[(size_t)k * d + j] * R[(size_t)k * d + i];
+      R[(size_t)j * d + i] = t / rjj;
+    }
+  }
+  return true;
+}
+
+// Rayleigh-Ritz refinement on the float32 matrix (eq. (5) for A^T A on the
+// subspace of the top d Ritz vectors V_d found with the bfloat16 matrix):
+//   W = A32 V_d,  W^T W = R^T R (Cholesky, float64),  R = Xr diag(s) Yr^T,
+//   sigma = s,  V = V_d Yr,  U = W R^{-1} Xr (= A32 V / sigma).
+template <typename TB>
+gkb_status refine_bf16(Solver<TB>& S, const gkb_matrix* Am, const Proj& pr, const Ritz& rz, int r, int d,
+                       double* sigma, TB* U, TB* V, int* refined) {
+  static_assert(sizeof(TB) == 4, "refinement runs on float32 bases");
+  hipStream_t st = S.st;
+  float* Vd = reinterpret_cast<float*>(S.ws + S.L.Vd);
+  float* W = reinterpret_cast<float*>(S.ws + S.L.Wr);
+  double* Gpart = reinterpret_cast<double*>(S.ws + S.L.Gpart);
+  double* Gd = reinterpret_cast<double*>(S.ws + S.L.G);
+  const int64_t m = Am->m, n = Am->n;
+  std::vector<float> Yh;
+  to_colmajor<float>(rz.Y, pr.np, rz.kk, d, Yh);
+  GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  GKB_HIP(gkb::launch_gemm_tall<float>(reinterpret_cast<const float*>(S.P(S.cur)), S.L.ldn, n, pr.np,
+                                       reinterpret_cast<const float*>(S.Ys()), pr.np, d, Vd, S.L.ldn, st));
+  GKB_HIP(gkb::launch_gemm_rm(Am->refine_f32, Am->lda_refine, m, n, Vd, S.L.ldn, d, W, S.L.ldm, st));
+  GKB_HIP(gkb::launch_gram(W, S.L.ldm, m, d, Gpart, Gd, st));
+  std::vector<double> G((size_t)d * d), R;
+  GKB_HIP(hipMemcpyAsync(G.data(), Gd, G.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  GKB_HIP(hipStreamSynchronize(st));
+  for (double g : G)
+    if (!std::isfinite(g)) return fail(GKB_ERR_NUMERIC, "non-finite Gram matrix in the refinement");
+  if (!cholesky_upper(d, G, R)) {
+    *refined = -1;  // subspace numerically rank deficient: keep the unrefined triplets
+    return GKB_OK;
+  }
+  std::vector<double> sr(d), Xr((size_t)d * d), Yr((size_t)d * d);
+  if (!gkb::dense_svd(d, d, R.data(), sr.data(), Xr.data(), Yr.data()))
+    return fail(GKB_ERR_NUMERIC, "refinement SVD did not converge");
+  // Mr = R^{-1} Xr[:, :r] by back substitution (R upper triangular)
+  std::vector<double> Mr((size_t)d * r);
+  for (int c = 0; c < r; ++c)
+    for (int i = d - 1; i >= 0; --i) {
+      double t = Xr[(size_t)i * d + c];
+      for (int k2 = i + 1; k2 < d; ++k2) t -= R[(size_t)i * d + k2] * Mr[(size_t)k2 * r + c];
+      Mr[(size_t)i * r + c] = t / R[(size_t)i * d + i];
+    }
+  std::vector<float> Mh, Yrh;
+  to_colmajor<float>(Mr, d, r, r, Mh);
+  to_colmajor<float>(Yr, d, d, r, Yrh);
+  GKB_HIP(hipMemcpyAsync(S.Xs(), Mh.data(), Mh.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  GKB_HIP(hipMemcpyAsync(S.Ys(), Yrh.data(), Yrh.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  GKB_HIP(gkb::launch_gemm_tall<float>(Vd, S.L.ldn, n, d, reinterpret_cast<const float*>(S.Ys()), d, r,
+                                       reinterpret_cast<float*>(V), n, st));
+  GKB_HIP(gkb::launch_gemm_tall<float>(W, S.L.ldm, m, d, reinterpret_cast<const float*>(S.Xs()), d, r,
+                                       reinterpret_cast<float*>(U), m, st));
+  GKB_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < r; ++i) sigma[i] = sr[i];
+  *refined = 1;
+  return GKB_OK;
+}
+
+template <>
+gkb_status refine_bf16<double>(Solver<double>&, const gkb_matrix*, const Proj&, const Ritz&, int, int, double*,
+                               double*, double*, int*) {
+  return fail(GKB_ERR_INVALID, "refinement needs a bfloat16 matrix");
+}
+
 template <typename TB>
 gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int max_restarts,
                            const gkb_options& opt, void* workspace, double* sigma, TB* U, TB* V,
@@ -362,7 +450,8 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   const int l = opt.keep ? opt.keep : std::min(r + (k - r) / 2, k - 1);
   if (k == r) max_restarts = 0;
   const int every = opt.check_every > 0 ? opt.check_every : 0;
-  S.L = make_layout(Am->m, Am->n, Am->dtype, k, k > r, true);
+  const bool refine = Am->dtype == GKB_BF16 && Am->refine_f32 != nullptr;
+  S.L = make_layout(Am->m, Am->n, Am->dtype, k, k > r, true, refine);
   S.ws = reinterpret_cast<char*>(workspace);
   S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
   S.relative = opt.eps_relative ? 1 : 0;
@@ -470,7 +559,17 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   // ---- Ritz vectors: V = P Y_r, U = Q X_r
   const int r_eff = ct.r_eff;
   for (int i = 0; i < r; ++i) sigma[i] = i < r_eff ? rz.s[i] : 0.0;
-  if (r_eff > 0) {
+  int refined = 0;
+  double ms_refine = 0.0;
+  if (r_eff > 0 && refine) {
+    const double tr0 = now_ms();
+    int d = opt.refine_dim > 0 ? opt.refine_dim : 2 * r;
+    d = std::max(r_eff, std::min(d, rz.kk));
+    rc = refine_bf16<TB>(S, Am, pr, rz, r_eff, d, sigma, U, V, &refined);
+    if (rc != GKB_OK) return rc;
+    ms_refine = now_ms() - tr0;
+  }
+  if (r_eff > 0 && !refined) {
     std::vector<TB> Xh, Yh;
     to_colmajor<TB>(rz.X, pr.nq, rz.kk, r_eff, Xh);
     to_colmajor<TB>(rz.Y, pr.np, rz.kk, r_eff, Yh);
@@ -494,6 +593,8 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     stats->ms_host = ms_host;
     stats->checks = checks;
     stats->krylov_dim = pr.np;
+    stats->refined = refined;
+    stats->ms_refine = ms_refine;
   }
   if (r_eff < r) return GKB_RANK_DEFICIENT;
   return ct.nconv == r ? GKB_OK : GKB_NOT_CONVERGED;
@@ -585,7 +686,8 @@ size_t gkb_workspace_size(const gkb_matrix* A, int r, int k, const gkb_options* 
   (void)opt;
   if (check_matrix(A) != GKB_OK) return 0;
   if (r < 1 || k < r || k > std::min(A->m, A->n)) return 0;
-  return make_layout(A->m, A->n, A->dtype, k, k > r, true).total;
+  return make_layout(A->m, A->n, A->dtype, k, k > r, true,
+                     A->dtype == GKB_BF16 && A->refine_f32 != nullptr).total;
 }
 
 gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
@@ -606,6 +708,12 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
   if (opt.keep != 0 && (opt.keep < r || opt.keep >= k))
     return fail(GKB_ERR_INVALID, "need r <= keep < k");
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
+  if (opt.check_every < 0) return fail(GKB_ERR_INVALID, "need check_every >= 0");
+  if (opt.refine_dim < 0) return fail(GKB_ERR_INVALID, "need refine_dim >= 0");
+  if (A->refine_f32 != nullptr) {
+    if (A->dtype != GKB_BF16) return fail(GKB_ERR_INVALID, "refine_f32 is only used with GKB_BF16");
+    if (A->lda_refine < A->n) return fail(GKB_ERR_INVALID, "need lda_refine >= n");
+  }
   rc = check_workspace(workspace, ws_bytes, gkb_workspace_size(A, r, k, &opt));
   if (rc != GKB_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -726,6 +834,31 @@ gkb_status gkb_gemm_tall(gkb_dtype dtype, const void* A, int64_t lda, int64_t M,
   else
     GKB_HIP(gkb::launch_gemm_tall<float>((const float*)A, lda, M, K, (const float*)B, ldb, N, (float*)C, ldc,
                                          st));
+  return GKB_OK;
+}
+
+gkb_status gkb_gemm_rowmajor(const float* A, int64_t lda, int64_t M, int64_t K, const float* B, int64_t ldb,
+                             int N, float* C, int64_t ldc, void* stream) {
+  g_err.clear();
+  if (M < 0 || K < 0 || N < 0 || lda < K || ldb < K || ldc < M) return fail(GKB_ERR_INVALID, "bad GEMM shape");
+  if ((M > 0 && N > 0) && (!A || !B || !C)) return fail(GKB_ERR_INVALID, "NULL operand");
+  GKB_HIP(gkb::launch_gemm_rm(A, lda, M, K, B, ldb, N, C, ldc, reinterpret_cast<hipStream_t>(stream)));
+  return GKB_OK;
+}
+
+size_t gkb_gram_workspace_size(int64_t m, int d) {
+  if (m < 1 || d < 1) return 0;
+  return align256((size_t)gkb::gram_chunks(m) * d * d * 8);
+}
+
+gkb_status gkb_gram(const float* W, int64_t ldw, int64_t m, int d, double* G, void* workspace, size_t ws_bytes,
+                    void* stream) {
+  g_err.clear();
+  if (!W || !G || m < 1 || d < 1 || ldw < m) return fail(GKB_ERR_INVALID, "bad Gram arguments");
+  gkb_status rc = check_workspace(workspace, ws_bytes, gkb_gram_workspace_size(m, d));
+  if (rc != GKB_OK) return rc;
+  GKB_HIP(gkb::launch_gram(W, ldw, m, d, reinterpret_cast<double*>(workspace), G,
+                           reinterpret_cast<hipStream_t>(stream)));
   return GKB_OK;
 }
 

@@ -68,6 +68,15 @@ template <typename T>
 hipError_t launch_gemm_tall(const T* A, int64_t lda, int64_t M, int K, const T* B, int64_t ldb, int N, T* C,
                             int64_t ldc, hipStream_t st);
 
+// C (M x N, col-major) = A (M x K, row-major float32) * B (K x N, col-major float32), MFMA
+hipError_t launch_gemm_rm(const float* A, int64_t lda, int64_t M, int64_t K, const float* B, int64_t ldb, int N,
+                          float* C, int64_t ldc, hipStream_t st);
+
+// G (d x d, row-major float64) = W^T W for W col-major float32 (m x d), via
+// gram_chunks(m) x d*d float64 partials in Gpart
+int gram_chunks(int64_t m);
+hipError_t launch_gram(const float* W, int64_t ldw, int64_t m, int d, double* Gpart, double* G, hipStream_t st);
+
 hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t m, int64_t n, uint16_t* dst, int64_t ldd,
                             hipStream_t st);
 

@@ -493,6 +493,143 @@ __global__ __launch_bounds__(256) void k_gemm_tall(const T* __restrict__ A, int6
   }
 }
 
+// ---------------------------------------------------------------- row-major GEMM
+// C (M x N, column-major, ldc) = A (M x K, row-major, lda, float32) *
+// B (K x N, column-major, ldb, float32), on the float32 16x16x4 MFMA.
+// A block (4 waves) computes a 128 x 64 tile of C: wave w owns rows
+// [32w, 32w + 32) (two 16-row MFMA tiles) and the block's 64 columns (four
+// 16-column tiles).  K advances in chunks of 32: the A chunk (128 x 32, each
+// row 128 contiguous bytes) and the B chunk (32 x 64, each column 128
+// contiguous bytes) are staged in LDS with coalesced loads (row stride padded
+// to 36 floats), then read by the MFMAs.  Used for the Rayleigh-Ritz block
+// product W = A V and the sketch S = A Omega.
+constexpr int RM_BM = 128, RM_BN = 64, RM_BK = 32, RM_LD = RM_BK + 4;
+__global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, int64_t lda, int64_t M, int64_t K,
+                                                 const float* __restrict__ B, int64_t ldb, int N,
+                                                 float* __restrict__ C, int64_t ldc) {
+  __shared__ float As[RM_BM * RM_LD];
+  __shared__ float Bs[RM_BN * RM_LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * RM_BM;
+  const int n0 = blockIdx.y * RM_BN;
+  const int li = lane & 15, lk = lane >> 4;
+  v4f acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
+  const bool avec = ((lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  const bool bvec = ((ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+  for (int64_t k0 = 0; k0 < K; k0 += RM_BK) {
+    // A chunk: 128 rows x 32 k = 1024 float4 -> 4 per thread
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = tid + it * 256;
+      const int r = idx >> 3, c4 = (idx & 7) * 4;
+      const int64_t gr = m0 + r, gk = k0 + c4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gr < M) {
+        const float* src = A + gr * lda + gk;
+        if (avec && gk + 4 <= K) {
+          const uint4 u = ld_stream(src);
+          v = make_float4(__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w));
+        } else {
+          if (gk < K) v.x = src[0];
+          if (gk + 1 < K) v.y = src[1];
+          if (gk + 2 < K) v.z = src[2];
+          if (gk + 3 < K) v.w = src[3];
+        }
+      }
+      float* dst = As + r * RM_LD + c4;
+      dst[0] = v.x;
+      dst[1] = v.y;
+      dst[2] = v.z;
+      dst[3] = v.w;
+    }
+    // B chunk: 64 columns x 32 k = 512 float4 -> 2 per thread
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int idx = tid + it * 256;
+      const int c = idx >> 3, k4 = (idx & 7) * 4;
+      const int gc = n0 + c;
+      const int64_t gk = k0 + k4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gc < N) {
+        const float* src = B + (int64_t)gc * ldb + gk;
+        if (bvec && gk + 4 <= K) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else {
+          if (gk < K) v.x = src[0];
+          if (gk + 1 < K) v.y = src[1];
+          if (gk + 2 < K) v.z = src[2];
+          if (gk + 3 < K) v.w = src[3];
+        }
+      }
+      float* dst = Bs + c * RM_LD + k4;
+      dst[0] = v.x;
+      dst[1] = v.y;
+      dst[2] = v.z;
+      dst[3] = v.w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < RM_BK; kk += 4) {
+      float a0 = As[(wave * 32 + li) * RM_LD + kk + lk];
+      float a1 = As[(wave * 32 + 16 + li) * RM_LD + kk + lk];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const float bv = Bs[(b * 16 + li) * RM_LD + kk + lk];
+        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][b], 0, 0, 0);
+        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = n0 + b * 16 + li;
+      if (col < N) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = m0 + wave * 32 + a * 16 + 4 * lk + v;
+          if (row < M) C[(int64_t)col * ldc + row] = acc[a][b][v];
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------- Gram matrix
+// Gpart[c * ldg + a * d + b] = sum_{i in chunk c} W[i][a] W[i][b] for a 16 x 16
+// tile (a0.., b0..) per block, W column-major float32 (m x d, ldw), products
+// and sums in float64 on the 16x16x4 MFMA.  Chunk = GRAM_ROWS rows.
+constexpr int GRAM_ROWS = 2048;
+__global__ __launch_bounds__(64) void k_gram(const float* __restrict__ W, int64_t ldw, int64_t m, int d,
+                                             double* __restrict__ Gpart, int64_t ldg) {
+  const int lane = threadIdx.x;
+  const int c = blockIdx.x;
+  const int a0 = blockIdx.y * 16, b0 = blockIdx.z * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)c * GRAM_ROWS;
+  int64_t r1 = r0 + GRAM_ROWS;
+  if (r1 > m) r1 = m;
+  v4d acc = {0, 0, 0, 0};
+  const int ca = a0 + li, cb = b0 + li;
+  for (int64_t i0 = r0; i0 < r1; i0 += 4) {
+    const int64_t i = i0 + lk;
+    const double av = (i < r1 && ca < d) ? (double)W[(int64_t)ca * ldw + i] : 0.0;
+    const double bv = (i < r1 && cb < d) ? (double)W[(int64_t)cb * ldw + i] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  // float64 layout: element v of lane l is row 4v + l/16, column l % 16
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int ra = a0 + 4 * v + lk;
+    if (ra < d && cb < d) Gpart[(int64_t)c * ldg + (int64_t)ra * d + cb] = acc[v];
+  }
+}
+
 // ---------------------------------------------------------------- bf16 cast
 // Round to nearest even; NaN stays NaN (quiet bit forced).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
@@ -712,6 +849,28 @@ hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t m, int64_t n,
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_gemm_rm(const float* A, int64_t lda, int64_t M, int64_t K, const float* B, int64_t ldb, int N,
+                          float* C, int64_t ldc, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid(nblocks(M, RM_BM), nblocks(N, RM_BN));
+  hipLaunchKernelGGL(k_gemm_rm, grid, dim3(256), 0, st, A, lda, M, K, B, ldb, N, C, ldc);
+  return hipGetLastError();
+}
+
+int gram_chunks(int64_t m) { return (int)nblocks(m, GRAM_ROWS); }
+
+hipError_t launch_gram(const float* W, int64_t ldw, int64_t m, int d, double* Gpart, double* G, hipStream_t st) {
+  const int nch = gram_chunks(m);
+  const int64_t ldg = (int64_t)d * d;
+  dim3 grid(nch, nblocks(d, 16), nblocks(d, 16));
+  hipLaunchKernelGGL(k_gram, grid, dim3(64), 0, st, W, ldw, m, d, Gpart, ldg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dots_reduce, dim3((unsigned)ldg), dim3(64), 0, st, Gpart, (int)ldg, nch, (int)ldg, G,
+                     nullptr);
+  return hipGetLastError();
 }
 
 hipError_t launch_philox_start(double* q, int64_t m, uint64_t seed, hipStream_t st) {

@@ -41,7 +41,7 @@ class GkbStats(C.Structure):
     _fields_ = [("nconv", C.c_int), ("restarts", C.c_int), ("breakdown", C.c_int), ("returned", C.c_int),
                 ("matvecs", C.c_int64), ("max_res_est", C.c_double), ("sigma1_est", C.c_double),
                 ("ms_total", C.c_double), ("ms_host", C.c_double), ("checks", C.c_int),
-                ("krylov_dim", C.c_int)]
+                ("krylov_dim", C.c_int), ("refined", C.c_int), ("ms_refine", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -52,7 +52,7 @@ _lib = None
 EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_rank_workspace_size",
            "gkb_numerical_rank", "gkb_status_string", "gkb_last_error", "gkb_host_dense_svd",
            "gkb_host_bidiag_count_above", "gkb_matvec_workspace_size", "gkb_matvec", "gkb_gemm_tall",
-           "gkb_cast_bf16", "gkb_start_vector"]
+           "gkb_cast_bf16", "gkb_start_vector", "gkb_gemm_rowmajor", "gkb_gram_workspace_size", "gkb_gram"]
 
 
 def lib():
@@ -100,6 +100,14 @@ def lib():
     L.gkb_cast_bf16.restype = C.c_int
     L.gkb_start_vector.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p]
     L.gkb_start_vector.restype = C.c_int
+    L.gkb_gemm_rowmajor.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int,
+                                    C.c_void_p, C.c_int64, C.c_void_p]
+    L.gkb_gemm_rowmajor.restype = C.c_int
+    L.gkb_gram_workspace_size.argtypes = [C.c_int64, C.c_int]
+    L.gkb_gram_workspace_size.restype = C.c_size_t
+    L.gkb_gram.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
+                           C.c_void_p]
+    L.gkb_gram.restype = C.c_int
     _lib = L
     return L
 
@@ -322,3 +330,30 @@ def gkb_host_bidiag_count_above(alpha, beta, nq, tau) -> int:
 def gkb_matvec_workspace_size(A) -> int:
     mat = make_matrix(A)
     return int(lib().gkb_matvec_workspace_size(C.byref(mat)))
+
+
+def gkb_gemm_rowmajor(A, Bt, C_out=None, stream=None):
+    """C = A B with A a row-major float32 (M, K) device tensor and B given as
+    Bt (N, K) (= K x N column-major).  Returns Ct (N, M) (= M x N column-major)."""
+    torch = _torch()
+    M, K = A.shape
+    N, K2 = Bt.shape
+    if K != K2 or A.dtype != torch.float32 or Bt.dtype != torch.float32:
+        raise ValueError("need float32 operands with matching inner dimension")
+    if C_out is None:
+        C_out = torch.empty((N, M), dtype=torch.float32, device=A.device)
+    _check(lib().gkb_gemm_rowmajor(C.c_void_p(A.data_ptr()), A.stride(0), M, K, C.c_void_p(Bt.data_ptr()),
+                                   Bt.stride(0), N, C.c_void_p(C_out.data_ptr()), C_out.stride(0),
+                                   _stream(stream)), False)
+    return C_out
+
+
+def gkb_gram(Wt, stream=None):
+    """G = W^T W (float64, d x d) for W given as Wt (d, m) float32 (= m x d column-major)."""
+    torch = _torch()
+    d, m = Wt.shape
+    G = torch.empty((d, d), dtype=torch.float64, device=Wt.device)
+    ws = _workspace(lib().gkb_gram_workspace_size(m, d), Wt.device)
+    _check(lib().gkb_gram(C.c_void_p(Wt.data_ptr()), Wt.stride(0), m, d, C.c_void_p(G.data_ptr()),
+                          C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), False)
+    return G

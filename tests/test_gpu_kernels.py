@@ -112,3 +112,37 @@ def test_device_start_vector_matches_oracle():
         ref = philox.start_vector(m, seed)
         # same integers, same formula; only log/cos rounding may differ
         assert np.max(np.abs(q - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("MKN", [(1000, 777, 50), (513, 1, 7), (2000, 1030, 100), (130, 33, 64), (64, 64, 65),
+                                 (20000, 5000, 32)])
+@pytest.mark.parametrize("pad", [0, 1])
+def test_gemm_rowmajor(MKN, pad):
+    device()
+    M, K, N = MKN
+    banner(f"gemm_rowmajor {MKN} pad={pad}")
+    rng = np.random.default_rng(M + K + N + pad)
+    A = rng.standard_normal((M, K + pad)).astype(np.float32)
+    Bt = rng.standard_normal((N, K + pad)).astype(np.float32)
+    Ad = to_dev(A)[:, :K]
+    Bd = to_dev(Bt)[:, :K]
+    Ct = to_host(gkb.gkb_gemm_rowmajor(Ad, Bd))
+    A64 = A[:, :K].astype(np.float64)
+    B64 = Bt[:, :K].astype(np.float64).T
+    ref = (A64 @ B64).T
+    bound = K * U32 * (np.abs(B64).T @ np.abs(A64).T) + 1e-300
+    assert np.all(np.abs(Ct - ref) <= bound)
+
+
+@pytest.mark.parametrize("md", [(5000, 100), (3000, 17), (1, 3), (4097, 64)])
+def test_gram(md):
+    device()
+    m, d = md
+    banner(f"gram {md}")
+    rng = np.random.default_rng(m + d)
+    Wt = rng.standard_normal((d, m)).astype(np.float32)
+    G = to_host(gkb.gkb_gram(to_dev(Wt)))
+    W64 = Wt.astype(np.float64)
+    ref = W64 @ W64.T
+    bound = m * U64 * (np.abs(W64) @ np.abs(W64).T) + 1e-300
+    assert np.all(np.abs(G - ref) <= bound)

@@ -277,3 +277,90 @@ def test_c2_fullsize_f32_against_stored_oracle(check_every):
     print(f"c2 residuals ||Av-su|| {r1.max():.3e} ||A^T u - s v|| {r2.max():.3e}", flush=True)
     assert np.max(r1) <= 10 * bound and np.max(r2) <= 1e-6 * sigma[0] + 10 * bound
     assert checks.orth_error(V[:, idx]) < 1e-5 and checks.orth_error(U[:, idx]) < 1e-5
+
+
+def test_bf16_storage_with_refinement_midsize():
+    """bfloat16 storage + float32 Rayleigh-Ritz refinement, per-triplet errors
+    against the float64 oracle on the float32 matrix.
+
+    Unrefined (bfloat16 solve): Weyl, |sigma_i(A16) - sigma_i(A32)| <= ||A16 - A32||_2.
+    Refined: the Rayleigh-Ritz values from a subspace at angle ~ ||E||/gap from
+    the exact one are off by ~ ||E||^2 / gap (gap = sigma_r - sigma_{d+1}),
+    plus the float32 product rounding sqrt(n) u ||A||_F.
+    """
+    import torch
+    from oracle import bf16 as obf16
+    device()
+    m, n, r, k = 6000, 2500, 20, 60
+    banner(f"bf16 + refinement {m}x{n} r={r} k={k}")
+    A32, s, _, _ = inputs.lowrank_noise(m, n, 200, 0.95, 1e-6, seed=7, dtype=np.float32)
+    q = inputs.start_vector(m, seed=8)
+    exact = gk.partial_svd(A32.astype(np.float64), 60, 120, 1e-13, 50, q)["sigma"]
+    ref_un, (ref_sig, ref_U, ref_V), d = obf16.refined_partial_svd(A32, r, k, 1e-6, 20, q)
+    A16 = obf16.from_bf16_bits(obf16.to_bf16_bits(A32))
+    E = A16 - A32.astype(np.float64)
+    normE = gk.partial_svd(E, 1, 30, 1e-8, 20, inputs.start_vector(m, 3))["sigma"][0]
+    A32d = torch.from_numpy(A32).to("cuda:0")
+    A16d = gkb.gkb_cast_bf16(A32d)
+    qd = to_dev(q)
+    sig_u, Ut_u, Vt_u, st_u, stats_u = gkb.gkb_partial_svd(A16d, r, k, 1e-6, 20, q1=qd)
+    sig, Ut, Vt, status, stats = gkb.gkb_partial_svd(A16d, r, k, 1e-6, 20, q1=qd, refine=A32d)
+    torch.cuda.synchronize()
+    assert st_u == 0 and status == 0 and stats["refined"] == 1
+    err_un = np.abs(sig_u - exact[:r])
+    err_ref = np.abs(sig - exact[:r])
+    gap = exact[r - 1] - exact[d]
+    fp32 = np.sqrt(n) * 2.0 ** -24 * np.sqrt(np.sum(exact ** 2))
+    print(f"bf16 ||E||_2={normE:.3e}; unrefined max err {err_un.max():.3e}; refined max err "
+          f"{err_ref.max():.3e} (bound {normE ** 2 / gap + fp32:.3e}); oracle refined err "
+          f"{np.max(np.abs(ref_sig - exact[:r])):.3e}", flush=True)
+    for i in range(r):
+        print(f"  triplet {i}: sigma {exact[i]:.6e} unrefined {err_un[i]:.2e} refined {err_ref[i]:.2e}",
+              flush=True)
+    assert np.all(err_un <= normE + fp32)
+    assert np.all(err_ref <= normE ** 2 / gap + fp32)
+    U = to_host(Ut).T.astype(np.float64)
+    V = to_host(Vt).T.astype(np.float64)
+    assert np.min(checks.alignment(ref_U, ref_V, U, V)) >= 1 - 1e-6
+    r1, r2 = checks.triplet_residuals(A32.astype(np.float64), sig, U, V)
+    r1u, r2u = checks.triplet_residuals(A32.astype(np.float64), sig_u, to_host(Ut_u).T.astype(np.float64),
+                                        to_host(Vt_u).T.astype(np.float64))
+    print(f"  residual ||A^T u - s v|| max: unrefined {r2u.max():.3e}, refined {r2.max():.3e}", flush=True)
+    # Rayleigh-Ritz fixes the values to second order; the vectors keep the
+    # subspace's first-order error ~ ||E|| / gap, so the residual does not grow
+    assert r2.max() <= 1.05 * r2u.max()
+
+
+def test_c3_fullsize_bf16_refined_against_stored_oracle():
+    """bfloat16 storage of the 50000 x 20000 matrix, float32 refinement; the
+    refined singular values against the oracle's values for the float32 matrix
+    (tests/golden/c2_oracle_top50.json).  Bound: ||E||^2/gap + sqrt(n) u ||A||_F
+    with ||E||_2 <= 2^-9 ||A||_F... estimated as 2^-9 * (entry RMS) * (sqrt(m) + sqrt(n))."""
+    import json
+    import os
+    import torch
+    device()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_top50.json")))
+    banner("c3 full size 50000x20000 bf16 + f32 refinement r=50 k=120 check_every=10")
+    A32, s, _, _ = inputs.lowrank_noise(50000, 20000, 200, 0.95, 1e-6, seed=2, dtype=np.float32)
+    q = inputs.start_vector(50000, seed=1)
+    A32d = torch.from_numpy(A32).to("cuda:0")
+    A16d = gkb.gkb_cast_bf16(A32d)
+    qd = to_dev(q)
+    sig_u, _, _, st_u, stats_u = gkb.gkb_partial_svd(A16d, 50, 120, 1e-6, 20, q1=qd, check_every=10)
+    sig, Ut, Vt, status, stats = gkb.gkb_partial_svd(A16d, 50, 120, 1e-6, 20, q1=qd, check_every=10, refine=A32d)
+    torch.cuda.synchronize()
+    del A32d, A16d
+    want = np.array(ref["sigma"])
+    fro = float(np.sqrt(np.sum(s ** 2)))
+    rms = fro / np.sqrt(A32.size)
+    normE = 2.0 ** -9 * rms * (np.sqrt(50000) + np.sqrt(20000))
+    gap = want[-1] * (1 - 0.95 ** 50)  # sigma_50 - sigma_100 of the 0.95^i spectrum
+    bound = normE ** 2 / gap + np.sqrt(20000) * 2.0 ** -24 * fro
+    err_u = np.abs(sig_u - want)
+    err = np.abs(sig - want)
+    print(f"c3 bf16 unrefined max err {err_u.max():.3e}; refined max err {err.max():.3e} (bound {bound:.3e}); "
+          f"matvecs {stats['matvecs']} refine {stats['ms_refine']:.2f} ms", flush=True)
+    assert status == 0 and stats["refined"] == 1
+    assert np.all(err <= bound) and np.all(err_u <= normE)
+    assert err.max() < err_u.max()

@@ -245,3 +245,43 @@ def test_paper_fsvd_matches_closed_form(c1):
     # ~eps * sigma_1^2 / sigma_i, vectors to the Krylov residual.
     assert rel(sigma, s[:10]) < 1e-10
     assert np.min(checks.alignment(Q1[:, :10], Q2[:, :10], U, V)) > 1 - 1e-8
+
+
+# -------------------------------------------------- bfloat16 and refinement
+def test_bf16_rounding_pins():
+    import torch
+    from oracle import bf16
+    rng = np.random.default_rng(5)
+    with np.errstate(over="ignore", under="ignore"):
+        x = (rng.standard_normal(20000) * 10.0 ** rng.integers(-45, 39, 20000)).astype(np.float32)
+    # library routine: torch's float32 -> bfloat16 conversion rounds to nearest even
+    want = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    got = bf16.to_bf16_bits(x)
+    ok = ~np.isnan(x)
+    assert np.array_equal(got[ok], want[ok])
+    # ties to even, exact cases, specials
+    cases = {1.0: 0x3F80, 1.0 + 2 ** -8: 0x3F80, 1.0 + 3 * 2 ** -8: 0x3F82, -2.0: 0xC000,
+             float("inf"): 0x7F80, -0.0: 0x8000}
+    for v, bits in cases.items():
+        assert int(bf16.to_bf16_bits(np.array([v], dtype=np.float32))[0]) == bits
+    assert np.isnan(bf16.from_bf16_bits(bf16.to_bf16_bits(np.array([np.nan], dtype=np.float32))))[0]
+    assert np.all(bf16.from_bf16_bits(got[ok]) == bf16.from_bf16_bits(want[ok]))
+
+
+def test_rayleigh_ritz_pins():
+    from oracle import bf16
+    s = np.geomspace(2.0, 0.01, 30)
+    A, Q1, Q2 = inputs.svd_matrix(80, 50, s, seed=4)
+    # exact singular subspace -> exact triplets
+    sig, U, V = bf16.rayleigh_ritz(A, Q2[:, :6], 6)
+    assert rel(sig, s[:6]) < 1e-13
+    assert np.min(checks.alignment(Q1[:, :6], Q2[:, :6], U, V)) > 1 - 1e-12
+    # whole space -> the full SVD
+    sig, U, V = bf16.rayleigh_ritz(A, np.eye(50), 30)
+    assert rel(sig, s) < 1e-12
+    # any subspace: Ritz values interlace from below (Courant-Fischer)
+    Vr = np.linalg.qr(np.random.default_rng(1).standard_normal((50, 10)))[0]
+    sig, U, V = bf16.rayleigh_ritz(A, Vr, 10)
+    assert np.all(sig <= s[:10] * (1 + 1e-12))
+    r1, _ = checks.triplet_residuals(A, sig, U, V)
+    assert np.max(r1) < 1e-13  # A v = sigma u holds by construction
