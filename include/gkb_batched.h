@@ -1,0 +1,81 @@
+/*
+ * gkb_batched.h -- many small, uneven partial SVDs in one persistent launch.
+ *
+ * Each problem is the restarted partial SVD of gkb.h (Golub-Kahan
+ * bidiagonalization, eq. (2.1)-(2.4) of the paper, Ritz triplets as in
+ * Algorithm 2, thick restart and the same convergence rule), but the whole
+ * solve of a problem runs inside one workgroup: products, two Gram-Schmidt
+ * passes, the small SVD of the projected matrix (one-sided Jacobi in LDS,
+ * float64), restarts and Ritz vectors.  A persistent grid takes problems from
+ * an atomic queue, largest (m * n * k) first.  The queue reset and the solver
+ * are captured once into a hipGraph per plan and replayed by
+ * gkb_batched_plan_run.
+ *
+ * Problems: GKB_F32, row-major, device pointers, 1 <= r <= k <= min(m, n),
+ * k <= 64.  Outputs are packed in problem order:
+ *   sigma  device doubles, r_0 + r_1 + ...
+ *   U      device floats, problem i at offset sum_{j<i} m_j r_j, column-major m_i x r_i
+ *   V      device floats, problem i at offset sum_{j<i} n_j r_j, column-major n_i x r_i
+ *   info   host ints, 4 per problem: status (gkb_status), nconv, restarts, matvecs
+ * Start vectors: opt->q1_packed (device doubles, problem i at offset
+ * sum_{j<i} m_j), or N(2,1) from Philox4x32-10 with key seed + i.
+ * Same ownership and validation rules as gkb.h.
+ */
+#ifndef GKB_BATCHED_H
+#define GKB_BATCHED_H
+
+#include "gkb.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int check_every;          /* in-cycle convergence test period (0 = cycle end only) */
+  int eps_relative;         /* as gkb_options (default 1)                          */
+  double eps_break;         /* 0 = 1e-6                                            */
+  uint64_t seed;            /* Philox key base when q1_packed is NULL               */
+  const double* q1_packed;  /* device start vectors or NULL                         */
+  int workgroups;           /* persistent grid size; 0 = one per compute unit      */
+  int no_graph;             /* 1: gkb_batched_plan_run launches directly instead of */
+                            /*    replaying the captured graph                      */
+} gkb_batch_options;
+
+typedef struct gkb_batch_plan_s* gkb_batch_plan;
+
+void gkb_batch_default_options(gkb_batch_options* opt);
+
+/* Workspace bytes for a batch (0 if the problems are invalid). */
+size_t gkb_batched_workspace_size(int batch, const gkb_matrix* As, const int* r, const int* k);
+
+/* Validate, upload the problem table into the workspace, capture the launch
+   into a hipGraph.  The plan keeps the workspace and output pointers. */
+gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
+                                   int max_restarts, const gkb_batch_options* opt, void* workspace,
+                                   size_t ws_bytes, double* sigma, float* U, float* V, void* stream,
+                                   gkb_batch_plan* plan);
+
+/* Replay the captured launch on `stream` (asynchronous). */
+gkb_status gkb_batched_plan_run(gkb_batch_plan plan, void* stream);
+
+/* Copy the per-problem info of the last completed run to the host (synchronises `stream`). */
+gkb_status gkb_batched_plan_info(gkb_batch_plan plan, int* info, void* stream);
+
+/* Persistent grid size chosen for the plan. */
+int gkb_batched_plan_grid(gkb_batch_plan plan);
+
+void gkb_batched_plan_destroy(gkb_batch_plan plan);
+
+/* One call: plan, run, info (host, 4 * batch ints, may be NULL), destroy. */
+gkb_status gkb_partial_svd_batched(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
+                                   int max_restarts, const gkb_batch_options* opt, void* workspace,
+                                   size_t ws_bytes, double* sigma, float* U, float* V, int* info,
+                                   void* stream);
+
+/* Message for the last negative status of a batched call on this thread. */
+const char* gkb_batched_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GKB_BATCHED_H */

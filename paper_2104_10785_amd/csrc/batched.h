@@ -1,0 +1,49 @@
+// Batched persistent solver: device-side problem table and launch (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gkb {
+
+constexpr int BATCH_KMAX = 64;  // largest Krylov dimension of a batched problem
+
+struct BatchProblem {
+  const float* A;     // row-major m x n, float32
+  int64_t lda;
+  int m, n, r, k, l;  // rows, columns, wanted triplets, Krylov dimension, restart size
+  int index;          // position in the caller's arrays
+  int64_t offQ, offP; // float offsets of the two Q and two P buffers in the pool
+  int64_t offW;       // double offset of w (m) and z (n) in the work area
+  int64_t offU, offV; // float offsets of U (m x r) and V (n x r) in the outputs
+  int64_t offS;       // double offset of sigma (r)
+  int64_t offQ1;      // double offset of this problem's start vector in q1 (if given)
+};
+
+struct BatchParams {
+  const BatchProblem* problems;
+  const int* order;   // solve order (largest first)
+  int* counter;       // work-queue head
+  int batch;
+  float* pool;
+  double* work;
+  float* U;
+  float* V;
+  double* sigma;
+  int* info;          // 4 ints per problem: status, nconv, restarts, matvecs
+  const double* q1;   // packed start vectors or null (Philox with seed + index)
+  uint64_t seed;
+  double eps_break;
+  double tol;
+  int max_restarts;
+  int check_every;
+  int relative;
+};
+
+size_t batched_lds_bytes();
+int batched_threads();
+hipError_t batched_setup();
+hipError_t launch_batched(const BatchParams& prm, int grid, hipStream_t st);
+
+}  // namespace gkb

@@ -1,0 +1,623 @@
+// Batched partial SVD: many small, uneven problems in one persistent launch.
+//
+// One workgroup (BT threads) solves one problem at a time end to end -- the
+// Golub-Kahan recurrences of eq. (2.1)-(2.2) with CGS2 reorthogonalisation,
+// the small SVD of the projected matrix (one-sided Jacobi in LDS, float64),
+// the convergence test, thick restarts and the Ritz vectors V = P Y, U = Q X
+// (Algorithm 2) -- then takes the next problem from an atomic queue ordered
+// largest-first.  Every wave of the grid reaches the queue's end, so the grid
+// drains; all reductions have a fixed order, so a problem's result does not
+// depend on which workgroup solved it.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "batched.h"
+
+namespace gkb {
+
+namespace {
+
+constexpr int BT = 1024;           // threads per workgroup
+constexpr int NW = BT / 64;        // waves per workgroup
+constexpr int KMAX = BATCH_KMAX;   // max Krylov dimension
+constexpr int HLD = KMAX + 2;      // LDS leading dimension of H columns
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+struct Lds {
+  double red[NW];
+  double h[KMAX + 2];          // Gram-Schmidt coefficients / rho
+  double qc[KMAX + 2];         // beta of Q column j
+  double pc[KMAX + 2];         // alpha of P column j
+  double sres[KMAX + 2];       // Ritz values kept at a restart
+  double rho[KMAX + 2];
+  double Hs[KMAX * HLD];       // projected matrix, column-major (col j at Hs + j*HLD)
+  double Vs[KMAX * KMAX];      // right rotations (col j at Vs + j*KMAX)
+  double sv[KMAX];             // column norms after Jacobi (sorted via perm)
+  float tpart[4096];           // gemv_t row-group partial sums
+  int perm[KMAX];
+  int ord[KMAX + 1];
+  int rotated;
+  int problem;
+  int flag;                    // breakdown: 0 none, 1 beta, 2 alpha, 3 numeric
+  int flag_idx;
+};
+
+// Block-wide sum in a fixed order (all threads get the result).
+__device__ double block_sum(double v, Lds& L) {
+  v = wsum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) L.red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += L.red[w];
+  __syncthreads();
+  return t;
+}
+
+// w = A p - c * qprev  (qprev may be null); waves own rows, lanes stride columns.
+__device__ void bgemv_n(const BatchProblem& P, const float* p, const float* qprev, double c, double* w) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
+  for (int i0 = wave * 2; i0 < P.m; i0 += NW * 2) {
+    const int i1 = i0 + 1 < P.m ? i0 + 1 : i0;
+    const float* r0 = P.A + (int64_t)i0 * P.lda;
+    const float* r1 = P.A + (int64_t)i1 * P.lda;
+    float a0 = 0.f, a1 = 0.f;
+    int jt = 0;
+    if (vec) {
+      const int nv = P.n >> 2;
+      for (int v = lane; v < nv; v += 64) {
+        const float4 pv = reinterpret_cast<const float4*>(p)[v];
+        const float4 x0 = reinterpret_cast<const float4*>(r0)[v];
+        const float4 x1 = reinterpret_cast<const float4*>(r1)[v];
+        a0 += x0.x * pv.x + x0.y * pv.y + x0.z * pv.z + x0.w * pv.w;
+        a1 += x1.x * pv.x + x1.y * pv.y + x1.z * pv.z + x1.w * pv.w;
+      }
+      jt = nv << 2;
+    }
+    for (int j = jt + lane; j < P.n; j += 64) {
+      a0 += r0[j] * p[j];
+      a1 += r1[j] * p[j];
+    }
+    const double s0 = wsum((double)a0), s1 = wsum((double)a1);
+    if (lane == 0) {
+      w[i0] = s0 - (qprev ? c * (double)qprev[i0] : 0.0);
+      if (i1 != i0) w[i1] = s1 - (qprev ? c * (double)qprev[i1] : 0.0);
+    }
+  }
+  __syncthreads();
+}
+
+// z = A^T q - c * pprev; threads own 4-column groups, G row groups split the
+// rows, partial sums meet in LDS and are added in group order.
+__device__ void bgemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z, Lds& L) {
+  const int tid = threadIdx.x;
+  const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) && ((P.n & 3) == 0);
+  const int VN = vec ? 4 : 1;
+  const int ncg = (P.n + VN - 1) / VN;
+  if (ncg >= BT) {
+    for (int cg = tid; cg < ncg; cg += BT) {
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < P.m; ++i) {
+        const float qi = q[i];
+        const float* row = P.A + (int64_t)i * P.lda + cg * VN;
+        if (vec) {
+          const float4 a = *reinterpret_cast<const float4*>(row);
+          acc[0] += a.x * qi;
+          acc[1] += a.y * qi;
+          acc[2] += a.z * qi;
+          acc[3] += a.w * qi;
+        } else {
+          acc[0] += row[0] * qi;
+        }
+      }
+      for (int e = 0; e < VN; ++e) {
+        const int j = cg * VN + e;
+        z[j] = (double)acc[e] - (pprev ? c * (double)pprev[j] : 0.0);
+      }
+    }
+    __syncthreads();
+    return;
+  }
+  const int G = BT / ncg;  // >= 1, G * n <= 4096
+  const int g = tid / ncg, cg = tid % ncg;
+  if (g < G) {
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = g; i < P.m; i += G) {
+      const float qi = q[i];
+      const float* row = P.A + (int64_t)i * P.lda + cg * VN;
+      if (vec) {
+        const float4 a = *reinterpret_cast<const float4*>(row);
+        acc[0] += a.x * qi;
+        acc[1] += a.y * qi;
+        acc[2] += a.z * qi;
+        acc[3] += a.w * qi;
+      } else {
+        acc[0] += row[0] * qi;
+      }
+    }
+    for (int e = 0; e < VN; ++e) L.tpart[g * P.n + cg * VN + e] = acc[e];
+  }
+  __syncthreads();
+  for (int j = tid; j < P.n; j += BT) {
+    double s = 0.0;
+    for (int gg = 0; gg < G; ++gg) s += (double)L.tpart[gg * P.n + j];
+    z[j] = s - (pprev ? c * (double)pprev[j] : 0.0);
+  }
+  __syncthreads();
+}
+
+// h[j] = V[:, j] . x for j < t (waves own columns, lanes own rows).
+__device__ void bdots(const float* V, int ldv, int t, int len, const double* x, Lds& L) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = wave; j < t; j += NW) {
+    const float* col = V + (int64_t)j * ldv;
+    double a = 0.0;
+    for (int i = lane; i < len; i += 64) a += (double)col[i] * x[i];
+    a = wsum(a);
+    if (lane == 0) L.h[j] = a;
+  }
+  __syncthreads();
+}
+
+// x -= V h (t columns); returns ||x||^2 after the update.
+__device__ double bupdate(const float* V, int ldv, int t, int len, double* x, const double* h, Lds& L) {
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < len; i += BT) {
+    double xi = x[i];
+    for (int j = 0; j < t; ++j) xi -= (double)V[(int64_t)j * ldv + i] * h[j];
+    x[i] = xi;
+    ss += xi * xi;
+  }
+  __syncthreads();
+  return block_sum(ss, L);
+}
+
+__device__ double bcgs2(const float* V, int ldv, int t, int len, double* x, Lds& L) {
+  if (t > 0) {
+    bdots(V, ldv, t, len, x, L);
+    bupdate(V, ldv, t, len, x, L.h, L);
+    bdots(V, ldv, t, len, x, L);
+    return bupdate(V, ldv, t, len, x, L.h, L);
+  }
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < len; i += BT) ss += x[i] * x[i];
+  return block_sum(ss, L);
+}
+
+__device__ void bscale(const double* x, int len, double nrm, float* out) {
+  for (int i = threadIdx.x; i < len; i += BT) out[i] = (float)(x[i] / nrm);
+  __syncthreads();
+}
+
+// One-sided Jacobi SVD of the nq x np matrix in L.Hs (columns), accumulating
+// the right rotations in L.Vs; afterwards sv[c] = column norms and perm sorts
+// them descending (ties by index).  Pairs follow the round-robin ordering so
+// each round's pairs are disjoint; one wave per pair.
+__device__ void bjacobi(int nq, int np, Lds& L) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < np * KMAX; e += BT) L.Vs[e] = 0.0;
+  __syncthreads();
+  for (int c = tid; c < np; c += BT) L.Vs[c * KMAX + c] = 1.0;
+  const int N = (np + 1) & ~1;  // even number of players (index np is a bye)
+  for (int s = 0; s < 60; ++s) {
+    if (tid == 0) L.rotated = 0;
+    for (int c = tid; c < N; c += BT) L.ord[c] = c;
+    __syncthreads();
+    for (int round = 0; round < N - 1; ++round) {
+      for (int pr = wave; pr < N / 2; pr += NW) {
+        const int i = min(L.ord[pr], L.ord[N - 1 - pr]);
+        const int j = max(L.ord[pr], L.ord[N - 1 - pr]);
+        if (j >= np) continue;
+        double* hi = L.Hs + i * HLD;
+        double* hj = L.Hs + j * HLD;
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int r = lane; r < nq; r += 64) {
+          a += hi[r] * hi[r];
+          b += hj[r] * hj[r];
+          c += hi[r] * hj[r];
+        }
+        a = wsum(a);
+        b = wsum(b);
+        c = wsum(c);
+        if (c != 0.0 && fabs(c) > 1e-15 * sqrt(a * b)) {
+          const double zeta = (b - a) / (2.0 * c);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          for (int r = lane; r < nq; r += 64) {
+            const double x = hi[r], y = hj[r];
+            hi[r] = cs * x - sn * y;
+            hj[r] = sn * x + cs * y;
+          }
+          double* vi = L.Vs + i * KMAX;
+          double* vj = L.Vs + j * KMAX;
+          for (int r = lane; r < np; r += 64) {
+            const double x = vi[r], y = vj[r];
+            vi[r] = cs * x - sn * y;
+            vj[r] = sn * x + cs * y;
+          }
+          if (lane == 0) L.rotated = 1;
+        }
+      }
+      __syncthreads();
+      // rotate players 1..N-1 (player 0 fixed)
+      if (tid == 0) {
+        const int last = L.ord[N - 1];
+        for (int c = N - 1; c > 1; --c) L.ord[c] = L.ord[c - 1];
+        L.ord[1] = last;
+      }
+      __syncthreads();
+    }
+    const int rot = L.rotated;
+    __syncthreads();
+    if (!rot) break;
+  }
+  // column norms, normalised left vectors, descending order
+  for (int c = wave; c < np; c += NW) {
+    double a = 0.0;
+    for (int r = lane; r < nq; r += 64) a += L.Hs[c * HLD + r] * L.Hs[c * HLD + r];
+    a = wsum(a);
+    const double nr = sqrt(a);
+    if (lane == 0) L.sv[c] = nr;
+    for (int r = lane; r < nq; r += 64) L.Hs[c * HLD + r] = nr > 0 ? L.Hs[c * HLD + r] / nr : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int c = 0; c < np; ++c) L.perm[c] = c;
+    for (int a = 0; a < np; ++a) {
+      int best = a;
+      for (int b = a + 1; b < np; ++b)
+        if (L.sv[L.perm[b]] > L.sv[L.perm[best]]) best = b;
+      const int tmp = L.perm[a];
+      L.perm[a] = L.perm[best];
+      L.perm[best] = tmp;
+    }
+  }
+  __syncthreads();
+}
+
+// out[:, c] = V[:, 0..kk) * M[0..kk, perm[c]] for c < ncols, M column-major in LDS
+// (column stride mld); V column-major (ldv), out column-major (ldo).
+__device__ void bgemm_small(const float* V, int ldv, int len, int kk, const double* M, int mld, const int* perm,
+                            int ncols, float* out, int ldo) {
+  for (int i = threadIdx.x; i < len; i += BT) {
+    for (int c0 = 0; c0 < ncols; c0 += 8) {
+      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int j = 0; j < kk; ++j) {
+        const double v = (double)V[(int64_t)j * ldv + i];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (c0 + e < ncols) acc[e] += v * M[perm[c0 + e] * mld + j];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (c0 + e < ncols) out[(int64_t)(c0 + e) * ldo + i] = (float)acc[e];
+    }
+  }
+  __syncthreads();
+}
+
+// Normalise x into out with the breakdown test; returns false on breakdown
+// (L.flag set).  thr = eps * sig (relative) or eps.
+__device__ bool bnormalize(const double* x, int len, double nrm2, double thr, float* out, int code, int idx,
+                           Lds& L) {
+  const double nrm = sqrt(nrm2);
+  if (!(nrm < INFINITY)) {
+    if (threadIdx.x == 0) {
+      L.flag = 3;
+      L.flag_idx = idx;
+    }
+    __syncthreads();
+    return false;
+  }
+  if (nrm <= thr) {
+    if (threadIdx.x == 0) {
+      L.flag = code;
+      L.flag_idx = idx;
+    }
+    __syncthreads();
+    return false;
+  }
+  bscale(x, len, nrm, out);
+  return true;
+}
+
+// Philox4x32-10 start vector (same definition as the single-problem path).
+__device__ double philox_normal(int64_t i, uint64_t seed) {
+  uint32_t c[4] = {(uint32_t)(i & 0xffffffffu), (uint32_t)((uint64_t)i >> 32), 0u, 0u};
+  uint32_t k[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    const uint32_t n0 = hi1 ^ c[1] ^ k[0], n2 = hi0 ^ c[3] ^ k[1];
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    if (r < 9) {
+      k[0] += 0x9E3779B9u;
+      k[1] += 0xBB67AE85u;
+    }
+  }
+  const double two32 = 4294967296.0;
+  const double u0 = ((double)c[0] + 1.0) / two32, u1 = ((double)c[1] + 1.0) / two32;
+  return 2.0 + sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
+}
+
+// Solve one problem (all threads of the workgroup).
+__device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds& L) {
+  const int tid = threadIdx.x;
+  float* Qb[2] = {prm.pool + P.offQ, prm.pool + P.offQ + (int64_t)(P.k + 1) * P.m};
+  float* Pb[2] = {prm.pool + P.offP, prm.pool + P.offP + (int64_t)(P.k + 1) * P.n};
+  double* w = prm.work + P.offW;
+  double* z = w + P.m;
+  const int m = P.m, n = P.n, k = P.k, r = P.r, l = P.l;
+  int cur = 0;
+  auto Qc = [&](int j) { return Qb[cur] + (int64_t)j * m; };
+  auto Pc = [&](int j) { return Pb[cur] + (int64_t)j * n; };
+  const double eps = prm.eps_break;
+  double sig = 0.0;  // running largest accepted coefficient / Ritz value
+  int64_t matvecs = 0;
+  int restarts = 0, nconv = 0, r_eff = 0, status = 0;
+  if (tid == 0) {
+    L.flag = 0;
+    L.flag_idx = 0;
+  }
+  // start: q ~ N(2,1) (Philox, seed + problem index) or caller's vector
+  for (int i = tid; i < m; i += BT) w[i] = prm.q1 ? prm.q1[P.offQ1 + i] : philox_normal(i, prm.seed + P.index);
+  __syncthreads();
+  double ss = 0.0;
+  for (int i = tid; i < m; i += BT) ss += w[i] * w[i];
+  ss = block_sum(ss, L);
+  if (!bnormalize(w, m, ss, 0.0, Qc(0), 1, 0, L)) {
+    status = -1;
+  }
+  int nq = 0, np = 0;        // shape of the projected matrix of the cycle
+  double alpha_res = 0.0;
+  bool first = true;
+  bool done = status != 0;
+  while (!done) {
+    // ---------------- one cycle
+    int jstart = first ? 0 : l;
+    int np_now = 0;
+    bool early = false;
+    if (first) {
+      bgemv_t(P, Qc(0), nullptr, 0.0, z, L);
+      ++matvecs;
+      ss = bcgs2(nullptr, n, 0, n, z, L);
+      if (!bnormalize(z, n, ss, 0.0, Pc(0), 2, 0, L)) {
+        // A^T q1 = 0
+        nq = 1;
+        np = 0;
+        break;
+      }
+      if (tid == 0) L.pc[0] = sqrt(ss);
+      sig = fmax(sig, sqrt(ss));
+      __syncthreads();
+    }
+    for (int j = jstart; j < k; ++j) {
+      // q side
+      const int qi = first ? j + 1 : j;     // new Q column
+      if (first) {
+        bgemv_n(P, Pc(j), Qc(j), L.pc[j], w);
+      } else {
+        bgemv_n(P, Pc(j), j == l ? nullptr : Qc(j - 1), j == l ? 0.0 : L.pc[j], w);
+        if (j == l) bupdate(Qc(0), m, l, m, w, L.rho, L);
+      }
+      ++matvecs;
+      ss = bcgs2(Qc(0), m, qi, m, w, L);
+      if (!bnormalize(w, m, ss, prm.relative ? eps * sig : eps, Qc(qi), 1, qi, L)) break;
+      const double beta = sqrt(ss);
+      if (tid == 0) L.qc[qi] = beta;
+      sig = fmax(sig, beta);
+      // p side
+      bgemv_t(P, Qc(qi), Pc(j), beta, z, L);
+      ++matvecs;
+      ss = bcgs2(Pc(0), n, j + 1, n, z, L);
+      if (!bnormalize(z, n, ss, prm.relative ? eps * sig : eps, Pc(j + 1), 2, j + 1, L)) break;
+      const double alpha = sqrt(ss);
+      if (tid == 0) L.pc[j + 1] = alpha;
+      sig = fmax(sig, alpha);
+      __syncthreads();
+      np_now = j + 1;
+      if (prm.check_every > 0 && np_now < k && np_now >= r && np_now % prm.check_every == 0) {
+        // in-cycle convergence test on the partial projected matrix
+        const int cq = first ? np_now + 1 : np_now;
+        for (int e = tid; e < np_now * HLD; e += BT) L.Hs[e] = 0.0;
+        __syncthreads();
+        if (tid == 0) {
+          if (first) {
+            for (int c = 0; c < np_now; ++c) {
+              L.Hs[c * HLD + c] = L.pc[c];
+              L.Hs[c * HLD + c + 1] = L.qc[c + 1];
+            }
+          } else {
+            for (int i = 0; i < l; ++i) {
+              L.Hs[i * HLD + i] = L.sres[i];
+              L.Hs[l * HLD + i] = L.rho[i];
+            }
+            for (int c = l; c < np_now; ++c) {
+              L.Hs[c * HLD + c] = L.qc[c];
+              if (c + 1 < np_now) L.Hs[(c + 1) * HLD + c] = L.pc[c + 1];
+            }
+          }
+        }
+        __syncthreads();
+        bjacobi(cq, np_now, L);
+        const double thr = prm.relative ? eps * sig : eps;
+        int avail = 0;
+        for (int c = 0; c < np_now; ++c)
+          if (L.sv[L.perm[c]] > thr) ++avail;
+        const int re = min(r, avail);
+        const double s0 = L.sv[L.perm[0]];
+        int nc = 0;
+        for (int c = 0; c < re; ++c)
+          if (alpha * fabs(L.Hs[L.perm[c] * HLD + cq - 1]) <= prm.tol * s0) ++nc;
+        if (re == r && nc == r) {
+          early = true;
+          nq = cq;
+          np = np_now;
+          alpha_res = alpha;
+          break;
+        }
+      }
+    }
+    const int fl = L.flag, fidx = L.flag_idx;
+    __syncthreads();
+    if (fl == 3) {
+      status = -3;
+      break;
+    }
+    if (!early) {
+      // assemble the projected matrix (same rules as the host driver)
+      if (fl == 0) {
+        np = k;
+        nq = first ? k + 1 : k;
+        alpha_res = L.pc[k];
+      } else if (first) {
+        if (fl == 1) {
+          nq = np = fidx;
+        } else {
+          np = fidx;
+          nq = fidx + 1;
+        }
+        alpha_res = 0.0;
+      } else {
+        if (fl == 1) {
+          nq = fidx;
+          np = fidx + 1;
+        } else {
+          nq = np = fidx;
+        }
+        alpha_res = 0.0;
+      }
+      for (int e = tid; e < np * HLD; e += BT) L.Hs[e] = 0.0;
+      __syncthreads();
+      if (tid == 0) {
+        if (first) {
+          for (int c = 0; c < np; ++c) {
+            L.Hs[c * HLD + c] = L.pc[c];
+            if (c + 1 < nq) L.Hs[c * HLD + c + 1] = L.qc[c + 1];
+          }
+        } else {
+          for (int i = 0; i < l && i < nq; ++i) {
+            if (i < np) L.Hs[i * HLD + i] = L.sres[i];
+            if (l < np) L.Hs[l * HLD + i] = L.rho[i];
+          }
+          for (int c = l; c < nq; ++c) {
+            L.Hs[c * HLD + c] = L.qc[c];
+            if (c + 1 < np) L.Hs[(c + 1) * HLD + c] = L.pc[c + 1];
+          }
+        }
+      }
+      __syncthreads();
+      if (np > 0) bjacobi(nq, np, L);
+    }
+    // convergence test
+    const double thr = prm.relative ? eps * sig : eps;
+    int avail = 0;
+    for (int c = 0; c < np; ++c)
+      if (L.sv[L.perm[c]] > thr) ++avail;
+    r_eff = min(r, avail);
+    const double s0 = np > 0 ? L.sv[L.perm[0]] : 0.0;
+    nconv = 0;
+    for (int c = 0; c < r_eff; ++c)
+      if (alpha_res * fabs(L.Hs[L.perm[c] * HLD + nq - 1]) <= prm.tol * s0) ++nconv;
+    const bool conv = r_eff == r && nconv == r;
+    if (fl != 0 || conv || restarts >= prm.max_restarts || k == r || early) {
+      done = true;
+      break;
+    }
+    // ---------------- thick restart
+    sig = fmax(sig, s0);
+    const int nb = 1 - cur;
+    // P~ = P Y_l (Y = Vs, columns by perm), Q~ = Q X_l (X = Hs normalised)
+    bgemm_small(Pb[cur], n, n, np, L.Vs, KMAX, L.perm, l, Pb[nb], n);
+    bgemm_small(Qb[cur], m, m, nq, L.Hs, HLD, L.perm, l, Qb[nb], m);
+    for (int i = tid; i < n; i += BT) Pb[nb][(int64_t)l * n + i] = Pb[cur][(int64_t)np * n + i];
+    if (tid < l) {
+      L.sres[tid] = L.sv[L.perm[tid]];
+      L.rho[tid] = alpha_res * L.Hs[L.perm[tid] * HLD + nq - 1];
+    }
+    __syncthreads();
+    cur = nb;
+    ++restarts;
+    first = false;
+    if (tid == 0) {
+      L.flag = 0;
+      L.flag_idx = 0;
+    }
+    __syncthreads();
+  }
+  // ---------------- outputs
+  const int pi = P.index;
+  if (status == 0 && np > 0) {
+    float* U = prm.U + P.offU;
+    float* V = prm.V + P.offV;
+    bgemm_small(Pb[cur], n, n, np, L.Vs, KMAX, L.perm, r_eff, V, n);
+    bgemm_small(Qb[cur], m, m, nq, L.Hs, HLD, L.perm, r_eff, U, m);
+    if (tid < r) prm.sigma[P.offS + tid] = tid < r_eff ? L.sv[L.perm[tid]] : 0.0;
+  } else if (tid < r) {
+    prm.sigma[P.offS + tid] = 0.0;
+  }
+  if (tid == 0) {
+    int st = status;
+    if (st == 0) st = r_eff < r ? 2 : (nconv == r ? 0 : 1);
+    prm.info[4 * pi + 0] = st;
+    prm.info[4 * pi + 1] = nconv;
+    prm.info[4 * pi + 2] = restarts;
+    prm.info[4 * pi + 3] = (int)matvecs;
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(BT) void k_batched_gk(BatchParams prm) {
+  extern __shared__ double lds_raw[];
+  Lds& L = *reinterpret_cast<Lds*>(lds_raw);
+  while (true) {
+    if (threadIdx.x == 0) {
+      const int slot = atomicAdd(prm.counter, 1);
+      L.problem = slot < prm.batch ? prm.order[slot] : -1;
+    }
+    __syncthreads();
+    const int p = L.problem;
+    __syncthreads();
+    if (p < 0) break;
+    const BatchProblem P = prm.problems[p];
+    solve_one(P, prm, L);
+  }
+}
+
+__global__ void k_batched_reset(int* counter) {
+  if (threadIdx.x == 0) *counter = 0;
+}
+
+size_t batched_lds_bytes() { return sizeof(Lds); }
+int batched_threads() { return BT; }
+
+hipError_t launch_batched(const BatchParams& prm, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(64), 0, st, prm.counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batched_gk, dim3(grid), dim3(BT), sizeof(Lds), st, prm);
+  return hipGetLastError();
+}
+
+hipError_t batched_setup() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batched_gk),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Lds));
+}
+
+}  // namespace gkb

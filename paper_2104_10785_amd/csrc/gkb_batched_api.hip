@@ -1,0 +1,272 @@
+// C ABI of the batched form: plan (problem table, largest-first order,
+// hipGraph of [queue reset, persistent solver]), run, results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/gkb.h"
+#include "../../include/gkb_batched.h"
+#include "batched.h"
+
+namespace {
+
+thread_local std::string b_err;
+
+gkb_status bfail(gkb_status s, const std::string& m) {
+  b_err = m;
+  return s;
+}
+
+#define B_HIP(call)                                                                    \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return bfail(GKB_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t problems = 0, order = 0, counter = 0, info = 0, pool = 0, work = 0, total = 0;
+  size_t pool_floats = 0, work_doubles = 0;
+};
+
+gkb_status check_batch(int batch, const gkb_matrix* As, const int* r, const int* k) {
+  if (batch < 1) return bfail(GKB_ERR_INVALID, "need batch >= 1");
+  if (!As || !r || !k) return bfail(GKB_ERR_INVALID, "As, r and k must be non-NULL");
+  for (int i = 0; i < batch; ++i) {
+    const gkb_matrix& A = As[i];
+    if (A.dtype != GKB_F32) return bfail(GKB_ERR_INVALID, "batched problems must be GKB_F32");
+    if (!A.data || A.m < 1 || A.n < 1 || A.lda < A.n) return bfail(GKB_ERR_INVALID, "bad matrix in batch");
+    if (A.m > (1 << 30) || A.n > (1 << 30)) return bfail(GKB_ERR_INVALID, "matrix too large for the batch");
+    if (r[i] < 1 || r[i] > k[i] || k[i] > std::min(A.m, A.n))
+      return bfail(GKB_ERR_INVALID, "need 1 <= r <= k <= min(m, n) for problem " + std::to_string(i));
+    if (k[i] > gkb::BATCH_KMAX)
+      return bfail(GKB_ERR_INVALID, "batched Krylov dimension above " + std::to_string(gkb::BATCH_KMAX));
+  }
+  return GKB_OK;
+}
+
+Layout layout(int batch, const gkb_matrix* As, const int* k) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += a256(b);
+    return o;
+  };
+  L.problems = take(sizeof(gkb::BatchProblem) * batch);
+  L.order = take(sizeof(int) * batch);
+  L.counter = take(sizeof(int));
+  L.info = take(sizeof(int) * 4 * batch);
+  for (int i = 0; i < batch; ++i) {
+    L.pool_floats += (size_t)2 * (k[i] + 1) * (As[i].m + As[i].n);
+    L.work_doubles += (size_t)(As[i].m + As[i].n);
+  }
+  L.pool = take(L.pool_floats * sizeof(float));
+  L.work = take(L.work_doubles * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct gkb_batch_plan_s {
+  int batch = 0;
+  int grid = 0;
+  gkb::BatchParams prm{};
+  std::vector<gkb::BatchProblem> table;
+  std::vector<int> order;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;
+  int* info_dev = nullptr;
+  bool no_graph = false;
+};
+
+extern "C" {
+
+const char* gkb_batched_last_error(void) { return b_err.c_str(); }
+
+void gkb_batch_default_options(gkb_batch_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps_relative = 1;
+}
+
+size_t gkb_batched_workspace_size(int batch, const gkb_matrix* As, const int* r, const int* k) {
+  if (check_batch(batch, As, r, k) != GKB_OK) return 0;
+  return layout(batch, As, k).total;
+}
+
+gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
+                                   int max_restarts, const gkb_batch_options* opt_in, void* workspace,
+                                   size_t ws_bytes, double* sigma, float* U, float* V, void* stream,
+                                   gkb_batch_plan* out) {
+  b_err.clear();
+  if (!out) return bfail(GKB_ERR_INVALID, "plan pointer is NULL");
+  *out = nullptr;
+  gkb_status rc = check_batch(batch, As, r, k);
+  if (rc != GKB_OK) return rc;
+  if (!(tol >= 0.0) || max_restarts < 0) return bfail(GKB_ERR_INVALID, "need tol >= 0 and max_restarts >= 0");
+  if (!sigma || !U || !V) return bfail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
+  gkb_batch_options opt;
+  gkb_batch_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.check_every < 0 || opt.eps_break < 0 || opt.workgroups < 0)
+    return bfail(GKB_ERR_INVALID, "bad batch options");
+  Layout L = layout(batch, As, k);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0 || ws_bytes < L.total)
+    return bfail(GKB_ERR_WORKSPACE, "workspace missing, misaligned or too small (need " +
+                                        std::to_string(L.total) + " bytes)");
+  char* ws = reinterpret_cast<char*>(workspace);
+  auto* plan = new gkb_batch_plan_s();
+  plan->batch = batch;
+  plan->table.resize(batch);
+  int64_t offQ = 0, offW = 0, offU = 0, offV = 0, offS = 0, offQ1 = 0;
+  for (int i = 0; i < batch; ++i) {
+    gkb::BatchProblem& P = plan->table[i];
+    P.A = reinterpret_cast<const float*>(As[i].data);
+    P.lda = As[i].lda;
+    P.m = (int)As[i].m;
+    P.n = (int)As[i].n;
+    P.r = r[i];
+    P.k = k[i];
+    P.l = std::min(r[i] + (k[i] - r[i]) / 2, k[i] - 1);
+    P.index = i;
+    P.offQ = offQ;
+    P.offP = offQ + (int64_t)2 * (k[i] + 1) * P.m;
+    offQ = P.offP + (int64_t)2 * (k[i] + 1) * P.n;
+    P.offW = offW;
+    offW += P.m + P.n;
+    P.offU = offU;
+    offU += (int64_t)P.m * r[i];
+    P.offV = offV;
+    offV += (int64_t)P.n * r[i];
+    P.offS = offS;
+    offS += r[i];
+    P.offQ1 = offQ1;
+    offQ1 += P.m;
+  }
+  // largest first: estimated cost m * n * k
+  plan->order.resize(batch);
+  std::iota(plan->order.begin(), plan->order.end(), 0);
+  std::stable_sort(plan->order.begin(), plan->order.end(), [&](int a, int b) {
+    const double ca = (double)plan->table[a].m * plan->table[a].n * plan->table[a].k;
+    const double cb = (double)plan->table[b].m * plan->table[b].n * plan->table[b].k;
+    return ca > cb;
+  });
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  gkb::BatchParams& prm = plan->prm;
+  prm.problems = reinterpret_cast<const gkb::BatchProblem*>(ws + L.problems);
+  prm.order = reinterpret_cast<const int*>(ws + L.order);
+  prm.counter = reinterpret_cast<int*>(ws + L.counter);
+  prm.batch = batch;
+  prm.pool = reinterpret_cast<float*>(ws + L.pool);
+  prm.work = reinterpret_cast<double*>(ws + L.work);
+  prm.U = U;
+  prm.V = V;
+  prm.sigma = sigma;
+  prm.info = reinterpret_cast<int*>(ws + L.info);
+  prm.q1 = opt.q1_packed;
+  prm.seed = opt.seed;
+  prm.eps_break = opt.eps_break > 0 ? opt.eps_break : 1e-6;
+  prm.tol = tol;
+  prm.max_restarts = max_restarts;
+  prm.check_every = opt.check_every;
+  prm.relative = opt.eps_relative ? 1 : 0;
+  plan->info_dev = prm.info;
+  auto cleanup = [&](gkb_status s) {
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->capture) (void)hipStreamDestroy(plan->capture);
+    delete plan;
+    return s;
+  };
+  if (hipMemcpyAsync(ws + L.problems, plan->table.data(), sizeof(gkb::BatchProblem) * batch,
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(ws + L.order, plan->order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return cleanup(bfail(GKB_ERR_HIP, "uploading the problem table failed"));
+  if (gkb::batched_setup() != hipSuccess) return cleanup(bfail(GKB_ERR_HIP, "cannot set the LDS size"));
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return cleanup(bfail(GKB_ERR_HIP, "cannot query the device"));
+  plan->grid = opt.workgroups > 0 ? opt.workgroups : cus;
+  plan->grid = std::min(plan->grid, batch);
+  plan->no_graph = opt.no_graph != 0;
+  if (plan->no_graph) {
+    *out = plan;
+    return GKB_OK;
+  }
+  // capture [queue reset, persistent solver] once; replays reuse the graph
+  if (hipStreamCreateWithFlags(&plan->capture, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(bfail(GKB_ERR_HIP, "cannot create the capture stream"));
+  if (hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return cleanup(bfail(GKB_ERR_HIP, "cannot begin graph capture"));
+  hipError_t le = gkb::launch_batched(prm, plan->grid, plan->capture);
+  hipError_t ee = hipStreamEndCapture(plan->capture, &plan->graph);
+  if (le != hipSuccess || ee != hipSuccess) return cleanup(bfail(GKB_ERR_HIP, "graph capture failed"));
+  if (hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0) != hipSuccess)
+    return cleanup(bfail(GKB_ERR_HIP, "graph instantiation failed"));
+  *out = plan;
+  return GKB_OK;
+}
+
+gkb_status gkb_batched_plan_run(gkb_batch_plan plan, void* stream) {
+  b_err.clear();
+  if (!plan) return bfail(GKB_ERR_INVALID, "invalid plan");
+  if (plan->no_graph) {
+    B_HIP(gkb::launch_batched(plan->prm, plan->grid, reinterpret_cast<hipStream_t>(stream)));
+    return GKB_OK;
+  }
+  if (!plan->exec) return bfail(GKB_ERR_INVALID, "invalid plan");
+  B_HIP(hipGraphLaunch(plan->exec, reinterpret_cast<hipStream_t>(stream)));
+  return GKB_OK;
+}
+
+gkb_status gkb_batched_plan_info(gkb_batch_plan plan, int* info, void* stream) {
+  b_err.clear();
+  if (!plan || !info) return bfail(GKB_ERR_INVALID, "invalid plan or info pointer");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  B_HIP(hipMemcpyAsync(info, plan->info_dev, sizeof(int) * 4 * plan->batch, hipMemcpyDeviceToHost, st));
+  B_HIP(hipStreamSynchronize(st));
+  return GKB_OK;
+}
+
+int gkb_batched_plan_grid(gkb_batch_plan plan) { return plan ? plan->grid : 0; }
+
+void gkb_batched_plan_destroy(gkb_batch_plan plan) {
+  if (!plan) return;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->capture) (void)hipStreamDestroy(plan->capture);
+  delete plan;
+}
+
+gkb_status gkb_partial_svd_batched(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
+                                   int max_restarts, const gkb_batch_options* opt, void* workspace,
+                                   size_t ws_bytes, double* sigma, float* U, float* V, int* info,
+                                   void* stream) {
+  gkb_batch_plan plan = nullptr;
+  gkb_status rc = gkb_batched_plan_create(batch, As, r, k, tol, max_restarts, opt, workspace, ws_bytes, sigma, U,
+                                          V, stream, &plan);
+  if (rc != GKB_OK) return rc;
+  rc = gkb_batched_plan_run(plan, stream);
+  if (rc == GKB_OK && info) rc = gkb_batched_plan_info(plan, info, stream);
+  if (rc == GKB_OK && !info) {
+    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+      rc = bfail(GKB_ERR_HIP, "stream synchronisation failed");
+  }
+  gkb_batched_plan_destroy(plan);
+  return rc;
+}
+
+}  // extern "C"

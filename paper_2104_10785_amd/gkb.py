@@ -37,6 +37,11 @@ class GkbOptions(C.Structure):
                 ("q1", C.c_void_p), ("seed", C.c_uint64), ("refine_dim", C.c_int), ("check_every", C.c_int)]
 
 
+class GkbBatchOptions(C.Structure):
+    _fields_ = [("check_every", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
+                ("seed", C.c_uint64), ("q1_packed", C.c_void_p), ("workgroups", C.c_int), ("no_graph", C.c_int)]
+
+
 class GkbStats(C.Structure):
     _fields_ = [("nconv", C.c_int), ("restarts", C.c_int), ("breakdown", C.c_int), ("returned", C.c_int),
                 ("matvecs", C.c_int64), ("max_res_est", C.c_double), ("sigma1_est", C.c_double),
@@ -52,7 +57,10 @@ _lib = None
 EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_rank_workspace_size",
            "gkb_numerical_rank", "gkb_status_string", "gkb_last_error", "gkb_host_dense_svd",
            "gkb_host_bidiag_count_above", "gkb_matvec_workspace_size", "gkb_matvec", "gkb_gemm_tall",
-           "gkb_cast_bf16", "gkb_start_vector", "gkb_gemm_rowmajor", "gkb_gram_workspace_size", "gkb_gram"]
+           "gkb_cast_bf16", "gkb_start_vector", "gkb_gemm_rowmajor", "gkb_gram_workspace_size", "gkb_gram",
+           "gkb_batch_default_options", "gkb_batched_workspace_size", "gkb_batched_plan_create",
+           "gkb_batched_plan_run", "gkb_batched_plan_info", "gkb_batched_plan_grid", "gkb_batched_plan_destroy",
+           "gkb_partial_svd_batched", "gkb_batched_last_error"]
 
 
 def lib():
@@ -108,6 +116,28 @@ def lib():
     L.gkb_gram.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
                            C.c_void_p]
     L.gkb_gram.restype = C.c_int
+    L.gkb_batch_default_options.argtypes = [P(GkbBatchOptions)]
+    L.gkb_batch_default_options.restype = None
+    L.gkb_batched_workspace_size.argtypes = [C.c_int, P(GkbMatrix), P(C.c_int), P(C.c_int)]
+    L.gkb_batched_workspace_size.restype = C.c_size_t
+    L.gkb_batched_plan_create.argtypes = [C.c_int, P(GkbMatrix), P(C.c_int), P(C.c_int), C.c_double, C.c_int,
+                                          P(GkbBatchOptions), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, P(C.c_void_p)]
+    L.gkb_batched_plan_create.restype = C.c_int
+    L.gkb_batched_plan_run.argtypes = [C.c_void_p, C.c_void_p]
+    L.gkb_batched_plan_run.restype = C.c_int
+    L.gkb_batched_plan_info.argtypes = [C.c_void_p, P(C.c_int), C.c_void_p]
+    L.gkb_batched_plan_info.restype = C.c_int
+    L.gkb_batched_plan_grid.argtypes = [C.c_void_p]
+    L.gkb_batched_plan_grid.restype = C.c_int
+    L.gkb_batched_plan_destroy.argtypes = [C.c_void_p]
+    L.gkb_batched_plan_destroy.restype = None
+    L.gkb_partial_svd_batched.argtypes = [C.c_int, P(GkbMatrix), P(C.c_int), P(C.c_int), C.c_double, C.c_int,
+                                          P(GkbBatchOptions), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, P(C.c_int), C.c_void_p]
+    L.gkb_partial_svd_batched.restype = C.c_int
+    L.gkb_batched_last_error.argtypes = []
+    L.gkb_batched_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -357,3 +387,91 @@ def gkb_gram(Wt, stream=None):
     _check(lib().gkb_gram(C.c_void_p(Wt.data_ptr()), Wt.stride(0), m, d, C.c_void_p(G.data_ptr()),
                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), False)
     return G
+
+
+class BatchPlan:
+    """A captured batched solve (gkb_batched_plan_*): build once, run many times.
+
+    As: list of float32 device matrices (2-D, unit column stride); r, k: ints
+    per problem.  Outputs (sigma, U, V) are packed device tensors owned by the
+    plan; `results()` unpacks them per problem.
+    """
+
+    def __init__(self, As, r, k, tol, max_restarts, check_every=0, seed=0, q1=None, workgroups=0,
+                 no_graph=False, eps_break=0.0, stream=None):
+        torch = _torch()
+        L = lib()
+        self.batch = len(As)
+        self.As = As
+        self.r = [int(x) for x in r]
+        self.k = [int(x) for x in k]
+        self.mats = (GkbMatrix * self.batch)(*[make_matrix(A) for A in As])
+        self.r_arr = (C.c_int * self.batch)(*self.r)
+        self.k_arr = (C.c_int * self.batch)(*self.k)
+        dev = As[0].device
+        need = L.gkb_batched_workspace_size(self.batch, self.mats, self.r_arr, self.k_arr)
+        if need == 0:
+            raise GkbError(-1, "invalid batch")
+        self.ws = _workspace(need, dev)
+        self.sigma = torch.zeros(sum(self.r), dtype=torch.float64, device=dev)
+        self.U = torch.zeros(sum(A.shape[0] * rr for A, rr in zip(As, self.r)), dtype=torch.float32, device=dev)
+        self.V = torch.zeros(sum(A.shape[1] * rr for A, rr in zip(As, self.r)), dtype=torch.float32, device=dev)
+        o = GkbBatchOptions()
+        L.gkb_batch_default_options(C.byref(o))
+        o.check_every = check_every
+        o.seed = seed
+        o.workgroups = workgroups
+        o.no_graph = 1 if no_graph else 0
+        o.eps_break = eps_break
+        self.q1 = q1
+        if q1 is not None:
+            o.q1_packed = q1.data_ptr()
+        self.opts = o
+        plan = C.c_void_p()
+        st = L.gkb_batched_plan_create(self.batch, self.mats, self.r_arr, self.k_arr, float(tol), int(max_restarts),
+                                       C.byref(o), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                       C.c_void_p(self.sigma.data_ptr()), C.c_void_p(self.U.data_ptr()),
+                                       C.c_void_p(self.V.data_ptr()), _stream(stream), C.byref(plan))
+        if st != 0:
+            raise GkbError(st, L.gkb_batched_last_error().decode())
+        self.plan = plan
+
+    @property
+    def grid(self):
+        return lib().gkb_batched_plan_grid(self.plan)
+
+    def run(self, stream=None):
+        st = lib().gkb_batched_plan_run(self.plan, _stream(stream))
+        if st != 0:
+            raise GkbError(st, lib().gkb_batched_last_error().decode())
+
+    def info(self, stream=None):
+        arr = (C.c_int * (4 * self.batch))()
+        st = lib().gkb_batched_plan_info(self.plan, arr, _stream(stream))
+        if st != 0:
+            raise GkbError(st, lib().gkb_batched_last_error().decode())
+        return np.array(arr[:], dtype=np.int64).reshape(self.batch, 4)
+
+    def results(self):
+        """Per problem: (sigma (numpy), Ut (r x m tensor), Vt (r x n tensor))."""
+        out = []
+        os_ = ou = ov = 0
+        for A, rr in zip(self.As, self.r):
+            m, n = A.shape
+            out.append((self.sigma[os_:os_ + rr].cpu().numpy(), self.U[ou:ou + m * rr].view(rr, m),
+                        self.V[ov:ov + n * rr].view(rr, n)))
+            os_ += rr
+            ou += m * rr
+            ov += n * rr
+        return out
+
+    def close(self):
+        if self.plan:
+            lib().gkb_batched_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,125 @@
+"""Batched persistent solver against the float64 oracle, problem by problem."""
+import numpy as np
+import pytest
+
+from oracle import checks, gk, philox
+from paper_2104_10785_amd import gkb, inputs
+
+from .gpu_util import banner, device, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def small_batch(count, seed, extra=True):
+    specs = inputs.batch_problems(count, seed, m_range=(100, 600), n_range=(40, 300),
+                                  ratio_range=(0.8, 0.95), r_range=(3, 8))
+    mats = [sp["A"] for sp in specs]
+    rs = [sp["r"] for sp in specs]
+    if extra:
+        # a rank-deficient product, a wide matrix, an odd column count, k = min(m, n)
+        mats.append(inputs.product_matrix(200, 90, 4, seed=3).astype(np.float32))
+        rs.append(6)
+        mats.append(inputs.svd_matrix(60, 150, np.geomspace(1, 0.01, 60), seed=4)[0].astype(np.float32))
+        rs.append(5)
+        mats.append(inputs.svd_matrix(301, 77, np.geomspace(1, 0.001, 77), seed=5)[0].astype(np.float32))
+        rs.append(7)
+        mats.append(inputs.svd_matrix(64, 20, np.geomspace(1, 0.1, 20), seed=6)[0].astype(np.float32))
+        rs.append(8)
+    ks = [min(min(A.shape), 2 * r + 10) for A, r in zip(mats, rs)]
+    return mats, rs, ks
+
+
+def bound32(A):
+    return np.sqrt(max(A.shape)) * U32 * np.linalg.norm(A.astype(np.float64))
+
+
+def check_against_oracle(mats, rs, ks, sig_list, info, qs, check_every, tol=1e-6):
+    worst = 0.0
+    for i, (A, r, k) in enumerate(zip(mats, rs, ks)):
+        ref = gk.partial_svd(A.astype(np.float64), r, k, tol, 20, qs[i], eps_break=1e-6,
+                             check_every=check_every)
+        sig, Ut, Vt = sig_list[i]
+        st, nconv, restarts, matvecs = info[i]
+        assert st == ref["status"], (i, st, ref["status"])
+        ne = ref["sigma"].size
+        err = np.max(np.abs(sig[:ne] - ref["sigma"])) if ne else 0.0
+        worst = max(worst, err / max(ref["sigma"][0], 1e-300) if ne else 0.0)
+        assert err <= bound32(A), (i, err, bound32(A))
+        if ne:
+            U = to_host(Ut).T[:, :ne].astype(np.float64)
+            V = to_host(Vt).T[:, :ne].astype(np.float64)
+            r1, r2 = checks.triplet_residuals(A.astype(np.float64), sig[:ne], U, V)
+            assert np.max(r2) <= tol * sig[0] + 100 * bound32(A), (i, np.max(r2))
+        assert abs(restarts - ref["restarts"]) <= 1, (i, restarts, ref["restarts"])
+    return worst
+
+
+@pytest.mark.parametrize("check_every", [0, 5])
+def test_batched_against_oracle(check_every):
+    import torch
+    device()
+    mats, rs, ks = small_batch(24, seed=11)
+    banner(f"batched {len(mats)} problems check_every={check_every}")
+    qs = [inputs.start_vector(A.shape[0], seed=100 + i) for i, A in enumerate(mats)]
+    Ad = [to_dev(A) for A in mats]
+    q1 = to_dev(np.concatenate(qs))
+    plan = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, check_every=check_every, q1=q1)
+    plan.run()
+    info = plan.info()
+    res = plan.results()
+    torch.cuda.synchronize()
+    worst = check_against_oracle(mats, rs, ks, res, info, qs, check_every)
+    print(f"batched max rel sigma err vs oracle {worst:.3e}; grid {plan.grid}", flush=True)
+    plan.close()
+
+
+def test_batched_device_start_vectors():
+    import torch
+    device()
+    mats, rs, ks = small_batch(8, seed=5, extra=False)
+    banner("batched with Philox start vectors")
+    Ad = [to_dev(A) for A in mats]
+    plan = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=777)
+    plan.run()
+    info = plan.info()
+    res = plan.results()
+    qs = [philox.start_vector(A.shape[0], 777 + i) for i, A in enumerate(mats)]
+    check_against_oracle(mats, rs, ks, res, info, qs, 0)
+    plan.close()
+
+
+def test_batched_graph_replays_match_eager():
+    import torch
+    device()
+    mats, rs, ks = small_batch(12, seed=21)
+    banner("batched graph replay vs eager")
+    Ad = [to_dev(A) for A in mats]
+    eager = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=3, no_graph=True)
+    eager.run()
+    e_info = eager.info()
+    e_res = [(s.copy(), to_host(u), to_host(v)) for s, u, v in eager.results()]
+    graph = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=3)
+    for rep in range(3):
+        graph.run()
+        g_info = graph.info()
+        # the program's own eager work between replays
+        x = torch.randn(1000, 1000, device="cuda:0")
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
+        assert np.array_equal(g_info, e_info)
+        for (s, u, v), (gs, gu, gv) in zip(e_res, graph.results()):
+            assert np.array_equal(s, gs) and np.array_equal(u, to_host(gu)) and np.array_equal(v, to_host(gv))
+    eager.close()
+    graph.close()
+
+
+def test_batched_validation():
+    device()
+    banner("batched validation")
+    A = to_dev(np.ones((10, 5), dtype=np.float32))
+    with pytest.raises(gkb.GkbError):
+        gkb.BatchPlan([A], [3], [6], 1e-6, 1)  # k > min(m, n)
+    with pytest.raises(gkb.GkbError):
+        gkb.BatchPlan([to_dev(np.ones((200, 100), dtype=np.float32))], [3], [70], 1e-6, 1)  # k > 64

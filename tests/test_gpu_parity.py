@@ -334,8 +334,11 @@ def test_bf16_storage_with_refinement_midsize():
 def test_c3_fullsize_bf16_refined_against_stored_oracle():
     """bfloat16 storage of the 50000 x 20000 matrix, float32 refinement; the
     refined singular values against the oracle's values for the float32 matrix
-    (tests/golden/c2_oracle_top50.json).  Bound: ||E||^2/gap + sqrt(n) u ||A||_F
-    with ||E||_2 <= 2^-9 ||A||_F... estimated as 2^-9 * (entry RMS) * (sqrt(m) + sqrt(n))."""
+    (tests/golden/c2_oracle_top50.json).  Bound: ||E||^2/gap + sqrt(n) u ||A||_F,
+    E = A16 - A32 with entries uniform in [-u|a|, u|a|], u = 2^-8, so
+    ||E||_2 ~ (u/sqrt(3)) rms(A) (sqrt(m) + sqrt(n)) (iid-like rounding errors;
+    this estimate matched the oracle's exact ||E||_2 to 1% at 6000 x 2500),
+    taken with a 1.2 margin."""
     import json
     import os
     import torch
@@ -354,7 +357,7 @@ def test_c3_fullsize_bf16_refined_against_stored_oracle():
     want = np.array(ref["sigma"])
     fro = float(np.sqrt(np.sum(s ** 2)))
     rms = fro / np.sqrt(A32.size)
-    normE = 2.0 ** -9 * rms * (np.sqrt(50000) + np.sqrt(20000))
+    normE = 1.2 * 2.0 ** -8 / np.sqrt(3.0) * rms * (np.sqrt(50000) + np.sqrt(20000))
     gap = want[-1] * (1 - 0.95 ** 50)  # sigma_50 - sigma_100 of the 0.95^i spectrum
     bound = normE ** 2 / gap + np.sqrt(20000) * 2.0 ** -24 * fro
     err_u = np.abs(sig_u - want)
