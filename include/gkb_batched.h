@@ -39,6 +39,7 @@ typedef struct {
   int workgroups;           /* persistent grid size; 0 = one per compute unit      */
   int no_graph;             /* 1: gkb_batched_plan_run launches directly instead of */
                             /*    replaying the captured graph                      */
+  int threads;              /* workgroup size, 512 or 1024; 0 = 1024               */
 } gkb_batch_options;
 
 typedef struct gkb_batch_plan_s* gkb_batch_plan;
@@ -65,6 +66,21 @@ gkb_status gkb_batched_plan_info(gkb_batch_plan plan, int* info, void* stream);
 int gkb_batched_plan_grid(gkb_batch_plan plan);
 
 void gkb_batched_plan_destroy(gkb_batch_plan plan);
+
+/*
+ * Project autotuner for the batched launch: times every candidate
+ * (workgroup size 512 or 1024, 1 or 2 workgroups per compute unit where the
+ * LDS allows) on this batch with hipEvents on `stream`, after one untimed run
+ * each, and returns the fastest in *best_threads / *best_workgroups.
+ * times_ms (optional, *ncand entries) receives every candidate's time, in the
+ * order (1024, 1/CU), (512, 1/CU), (512, 2/CU).  The outputs are written by
+ * the runs.  Callers cache the choice (the Python binding keeps a JSON cache
+ * keyed by device and batch shape).
+ */
+gkb_status gkb_batched_autotune(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
+                                int max_restarts, const gkb_batch_options* opt, void* workspace,
+                                size_t ws_bytes, double* sigma, float* U, float* V, void* stream,
+                                int* best_threads, int* best_workgroups, double* times_ms, int* ncand);
 
 /* One call: plan, run, info (host, 4 * batch ints, may be NULL), destroy. */
 gkb_status gkb_partial_svd_batched(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,

@@ -41,9 +41,9 @@ struct BatchParams {
   int relative;
 };
 
-size_t batched_lds_bytes();
-int batched_threads();
+// threads per workgroup: 512 or 1024
+size_t batched_lds_bytes(int threads);
 hipError_t batched_setup();
-hipError_t launch_batched(const BatchParams& prm, int grid, hipStream_t st);
+hipError_t launch_batched(const BatchParams& prm, int grid, int threads, hipStream_t st);
 
 }  // namespace gkb

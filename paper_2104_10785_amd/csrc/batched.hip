@@ -18,8 +18,6 @@ namespace gkb {
 
 namespace {
 
-constexpr int BT = 1024;           // threads per workgroup
-constexpr int NW = BT / 64;        // waves per workgroup
 constexpr int KMAX = BATCH_KMAX;   // max Krylov dimension
 constexpr int HLD = KMAX + 2;      // LDS leading dimension of H columns
 
@@ -29,7 +27,10 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
+// BT = threads per workgroup (512 or 1024), NW = waves per workgroup.
+template <int BT>
 struct Lds {
+  static constexpr int NW = BT / 64;
   double red[NW];
   double h[KMAX + 2];          // Gram-Schmidt coefficients / rho
   double qc[KMAX + 2];         // beta of Q column j
@@ -39,7 +40,7 @@ struct Lds {
   double Hs[KMAX * HLD];       // projected matrix, column-major (col j at Hs + j*HLD)
   double Vs[KMAX * KMAX];      // right rotations (col j at Vs + j*KMAX)
   double sv[KMAX];             // column norms after Jacobi (sorted via perm)
-  float tpart[4096];           // gemv_t row-group partial sums
+  float tpart[4 * BT];         // gemv_t row-group partial sums
   int perm[KMAX];
   int ord[KMAX + 1];
   int rotated;
@@ -49,8 +50,10 @@ struct Lds {
 };
 
 // Block-wide sum in a fixed order (all threads get the result).
-__device__ double block_sum(double v, Lds& L) {
+template <int BT>
+__device__ double block_sum(double v, Lds<BT>& L) {
   v = wsum(v);
+  constexpr int NW = BT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) L.red[wave] = v;
@@ -63,7 +66,9 @@ __device__ double block_sum(double v, Lds& L) {
 }
 
 // w = A p - c * qprev  (qprev may be null); waves own rows, lanes stride columns.
+template <int BT>
 __device__ void bgemv_n(const BatchProblem& P, const float* p, const float* qprev, double c, double* w) {
+  constexpr int NW = BT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
@@ -99,7 +104,8 @@ __device__ void bgemv_n(const BatchProblem& P, const float* p, const float* qpre
 
 // z = A^T q - c * pprev; threads own 4-column groups, G row groups split the
 // rows, partial sums meet in LDS and are added in group order.
-__device__ void bgemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z, Lds& L) {
+template <int BT>
+__device__ void bgemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z, Lds<BT>& L) {
   const int tid = threadIdx.x;
   const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) && ((P.n & 3) == 0);
   const int VN = vec ? 4 : 1;
@@ -157,7 +163,9 @@ __device__ void bgemv_t(const BatchProblem& P, const float* q, const float* ppre
 }
 
 // h[j] = V[:, j] . x for j < t (waves own columns, lanes own rows).
-__device__ void bdots(const float* V, int ldv, int t, int len, const double* x, Lds& L) {
+template <int BT>
+__device__ void bdots(const float* V, int ldv, int t, int len, const double* x, Lds<BT>& L) {
+  constexpr int NW = BT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j = wave; j < t; j += NW) {
     const float* col = V + (int64_t)j * ldv;
@@ -170,7 +178,8 @@ __device__ void bdots(const float* V, int ldv, int t, int len, const double* x, 
 }
 
 // x -= V h (t columns); returns ||x||^2 after the update.
-__device__ double bupdate(const float* V, int ldv, int t, int len, double* x, const double* h, Lds& L) {
+template <int BT>
+__device__ double bupdate(const float* V, int ldv, int t, int len, double* x, const double* h, Lds<BT>& L) {
   double ss = 0.0;
   for (int i = threadIdx.x; i < len; i += BT) {
     double xi = x[i];
@@ -182,7 +191,8 @@ __device__ double bupdate(const float* V, int ldv, int t, int len, double* x, co
   return block_sum(ss, L);
 }
 
-__device__ double bcgs2(const float* V, int ldv, int t, int len, double* x, Lds& L) {
+template <int BT>
+__device__ double bcgs2(const float* V, int ldv, int t, int len, double* x, Lds<BT>& L) {
   if (t > 0) {
     bdots(V, ldv, t, len, x, L);
     bupdate(V, ldv, t, len, x, L.h, L);
@@ -194,6 +204,7 @@ __device__ double bcgs2(const float* V, int ldv, int t, int len, double* x, Lds&
   return block_sum(ss, L);
 }
 
+template <int BT>
 __device__ void bscale(const double* x, int len, double nrm, float* out) {
   for (int i = threadIdx.x; i < len; i += BT) out[i] = (float)(x[i] / nrm);
   __syncthreads();
@@ -203,7 +214,9 @@ __device__ void bscale(const double* x, int len, double nrm, float* out) {
 // the right rotations in L.Vs; afterwards sv[c] = column norms and perm sorts
 // them descending (ties by index).  Pairs follow the round-robin ordering so
 // each round's pairs are disjoint; one wave per pair.
-__device__ void bjacobi(int nq, int np, Lds& L) {
+template <int BT>
+__device__ void bjacobi(int nq, int np, Lds<BT>& L) {
+  constexpr int NW = BT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < np * KMAX; e += BT) L.Vs[e] = 0.0;
   __syncthreads();
@@ -287,6 +300,7 @@ __device__ void bjacobi(int nq, int np, Lds& L) {
 
 // out[:, c] = V[:, 0..kk) * M[0..kk, perm[c]] for c < ncols, M column-major in LDS
 // (column stride mld); V column-major (ldv), out column-major (ldo).
+template <int BT>
 __device__ void bgemm_small(const float* V, int ldv, int len, int kk, const double* M, int mld, const int* perm,
                             int ncols, float* out, int ldo) {
   for (int i = threadIdx.x; i < len; i += BT) {
@@ -308,8 +322,9 @@ __device__ void bgemm_small(const float* V, int ldv, int len, int kk, const doub
 
 // Normalise x into out with the breakdown test; returns false on breakdown
 // (L.flag set).  thr = eps * sig (relative) or eps.
+template <int BT>
 __device__ bool bnormalize(const double* x, int len, double nrm2, double thr, float* out, int code, int idx,
-                           Lds& L) {
+                           Lds<BT>& L) {
   const double nrm = sqrt(nrm2);
   if (!(nrm < INFINITY)) {
     if (threadIdx.x == 0) {
@@ -327,7 +342,7 @@ __device__ bool bnormalize(const double* x, int len, double nrm2, double thr, fl
     __syncthreads();
     return false;
   }
-  bscale(x, len, nrm, out);
+  bscale<BT>(x, len, nrm, out);
   return true;
 }
 
@@ -355,7 +370,8 @@ __device__ double philox_normal(int64_t i, uint64_t seed) {
 }
 
 // Solve one problem (all threads of the workgroup).
-__device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds& L) {
+template <int BT>
+__device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>& L) {
   const int tid = threadIdx.x;
   float* Qb[2] = {prm.pool + P.offQ, prm.pool + P.offQ + (int64_t)(P.k + 1) * P.m};
   float* Pb[2] = {prm.pool + P.offP, prm.pool + P.offP + (int64_t)(P.k + 1) * P.n};
@@ -409,9 +425,9 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds& L)
       // q side
       const int qi = first ? j + 1 : j;     // new Q column
       if (first) {
-        bgemv_n(P, Pc(j), Qc(j), L.pc[j], w);
+        bgemv_n<BT>(P, Pc(j), Qc(j), L.pc[j], w);
       } else {
-        bgemv_n(P, Pc(j), j == l ? nullptr : Qc(j - 1), j == l ? 0.0 : L.pc[j], w);
+        bgemv_n<BT>(P, Pc(j), j == l ? nullptr : Qc(j - 1), j == l ? 0.0 : L.pc[j], w);
         if (j == l) bupdate(Qc(0), m, l, m, w, L.rho, L);
       }
       ++matvecs;
@@ -542,8 +558,8 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds& L)
     sig = fmax(sig, s0);
     const int nb = 1 - cur;
     // P~ = P Y_l (Y = Vs, columns by perm), Q~ = Q X_l (X = Hs normalised)
-    bgemm_small(Pb[cur], n, n, np, L.Vs, KMAX, L.perm, l, Pb[nb], n);
-    bgemm_small(Qb[cur], m, m, nq, L.Hs, HLD, L.perm, l, Qb[nb], m);
+    bgemm_small<BT>(Pb[cur], n, n, np, L.Vs, KMAX, L.perm, l, Pb[nb], n);
+    bgemm_small<BT>(Qb[cur], m, m, nq, L.Hs, HLD, L.perm, l, Qb[nb], m);
     for (int i = tid; i < n; i += BT) Pb[nb][(int64_t)l * n + i] = Pb[cur][(int64_t)np * n + i];
     if (tid < l) {
       L.sres[tid] = L.sv[L.perm[tid]];
@@ -564,8 +580,8 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds& L)
   if (status == 0 && np > 0) {
     float* U = prm.U + P.offU;
     float* V = prm.V + P.offV;
-    bgemm_small(Pb[cur], n, n, np, L.Vs, KMAX, L.perm, r_eff, V, n);
-    bgemm_small(Qb[cur], m, m, nq, L.Hs, HLD, L.perm, r_eff, U, m);
+    bgemm_small<BT>(Pb[cur], n, n, np, L.Vs, KMAX, L.perm, r_eff, V, n);
+    bgemm_small<BT>(Qb[cur], m, m, nq, L.Hs, HLD, L.perm, r_eff, U, m);
     if (tid < r) prm.sigma[P.offS + tid] = tid < r_eff ? L.sv[L.perm[tid]] : 0.0;
   } else if (tid < r) {
     prm.sigma[P.offS + tid] = 0.0;
@@ -583,9 +599,10 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds& L)
 
 }  // namespace
 
+template <int BT>
 __global__ __launch_bounds__(BT) void k_batched_gk(BatchParams prm) {
   extern __shared__ double lds_raw[];
-  Lds& L = *reinterpret_cast<Lds*>(lds_raw);
+  Lds<BT>& L = *reinterpret_cast<Lds<BT>*>(lds_raw);
   while (true) {
     if (threadIdx.x == 0) {
       const int slot = atomicAdd(prm.counter, 1);
@@ -604,20 +621,25 @@ __global__ void k_batched_reset(int* counter) {
   if (threadIdx.x == 0) *counter = 0;
 }
 
-size_t batched_lds_bytes() { return sizeof(Lds); }
-int batched_threads() { return BT; }
+size_t batched_lds_bytes(int threads) { return threads == 512 ? sizeof(Lds<512>) : sizeof(Lds<1024>); }
 
-hipError_t launch_batched(const BatchParams& prm, int grid, hipStream_t st) {
+hipError_t launch_batched(const BatchParams& prm, int grid, int threads, hipStream_t st) {
   hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(64), 0, st, prm.counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batched_gk, dim3(grid), dim3(BT), sizeof(Lds), st, prm);
+  if (threads == 512)
+    hipLaunchKernelGGL(k_batched_gk<512>, dim3(grid), dim3(512), sizeof(Lds<512>), st, prm);
+  else
+    hipLaunchKernelGGL(k_batched_gk<1024>, dim3(grid), dim3(1024), sizeof(Lds<1024>), st, prm);
   return hipGetLastError();
 }
 
 hipError_t batched_setup() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batched_gk),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Lds));
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batched_gk<512>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Lds<512>));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batched_gk<1024>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Lds<1024>));
 }
 
 }  // namespace gkb

@@ -87,6 +87,7 @@ struct gkb_batch_plan_s {
   hipStream_t capture = nullptr;
   int* info_dev = nullptr;
   bool no_graph = false;
+  int threads = 1024;
 };
 
 extern "C" {
@@ -120,6 +121,8 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   if (opt_in) opt = *opt_in;
   if (opt.check_every < 0 || opt.eps_break < 0 || opt.workgroups < 0)
     return bfail(GKB_ERR_INVALID, "bad batch options");
+  if (opt.threads != 0 && opt.threads != 512 && opt.threads != 1024)
+    return bfail(GKB_ERR_INVALID, "threads must be 0, 512 or 1024");
   Layout L = layout(batch, As, k);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0 || ws_bytes < L.total)
     return bfail(GKB_ERR_WORKSPACE, "workspace missing, misaligned or too small (need " +
@@ -199,6 +202,7 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return cleanup(bfail(GKB_ERR_HIP, "cannot query the device"));
+  plan->threads = opt.threads ? opt.threads : 1024;
   plan->grid = opt.workgroups > 0 ? opt.workgroups : cus;
   plan->grid = std::min(plan->grid, batch);
   plan->no_graph = opt.no_graph != 0;
@@ -211,7 +215,7 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
     return cleanup(bfail(GKB_ERR_HIP, "cannot create the capture stream"));
   if (hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return cleanup(bfail(GKB_ERR_HIP, "cannot begin graph capture"));
-  hipError_t le = gkb::launch_batched(prm, plan->grid, plan->capture);
+  hipError_t le = gkb::launch_batched(prm, plan->grid, plan->threads, plan->capture);
   hipError_t ee = hipStreamEndCapture(plan->capture, &plan->graph);
   if (le != hipSuccess || ee != hipSuccess) return cleanup(bfail(GKB_ERR_HIP, "graph capture failed"));
   if (hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0) != hipSuccess)
@@ -224,7 +228,7 @@ gkb_status gkb_batched_plan_run(gkb_batch_plan plan, void* stream) {
   b_err.clear();
   if (!plan) return bfail(GKB_ERR_INVALID, "invalid plan");
   if (plan->no_graph) {
-    B_HIP(gkb::launch_batched(plan->prm, plan->grid, reinterpret_cast<hipStream_t>(stream)));
+    B_HIP(gkb::launch_batched(plan->prm, plan->grid, plan->threads, reinterpret_cast<hipStream_t>(stream)));
     return GKB_OK;
   }
   if (!plan->exec) return bfail(GKB_ERR_INVALID, "invalid plan");
@@ -249,6 +253,69 @@ void gkb_batched_plan_destroy(gkb_batch_plan plan) {
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
   if (plan->capture) (void)hipStreamDestroy(plan->capture);
   delete plan;
+}
+
+gkb_status gkb_batched_autotune(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
+                                int max_restarts, const gkb_batch_options* opt_in, void* workspace,
+                                size_t ws_bytes, double* sigma, float* U, float* V, void* stream,
+                                int* best_threads, int* best_workgroups, double* times_ms, int* ncand) {
+  b_err.clear();
+  if (!best_threads || !best_workgroups) return bfail(GKB_ERR_INVALID, "output pointers are NULL");
+  gkb_batch_options opt;
+  gkb_batch_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  int dev = 0, cus = 0;
+  B_HIP(hipGetDevice(&dev));
+  B_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  size_t lds_max = 0;
+  {
+    int v = 0;
+    B_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+    lds_max = (size_t)v;
+  }
+  const int cand_threads[3] = {1024, 512, 512};
+  const int cand_per_cu[3] = {1, 1, 2};
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  B_HIP(hipEventCreate(&e0));
+  B_HIP(hipEventCreate(&e1));
+  double best = 1e300;
+  int n = 0;
+  gkb_status rc = GKB_OK;
+  for (int c = 0; c < 3; ++c) {
+    double t = -1.0;
+    if (gkb::batched_lds_bytes(cand_threads[c]) * cand_per_cu[c] <= lds_max) {
+      gkb_batch_options o = opt;
+      o.threads = cand_threads[c];
+      o.workgroups = cus * cand_per_cu[c];
+      o.no_graph = 1;
+      gkb_batch_plan plan = nullptr;
+      rc = gkb_batched_plan_create(batch, As, r, k, tol, max_restarts, &o, workspace, ws_bytes, sigma, U, V,
+                                   stream, &plan);
+      if (rc != GKB_OK) break;
+      rc = gkb_batched_plan_run(plan, stream);  // untimed
+      if (rc == GKB_OK && hipEventRecord(e0, st) != hipSuccess) rc = bfail(GKB_ERR_HIP, "event record");
+      if (rc == GKB_OK) rc = gkb_batched_plan_run(plan, stream);
+      if (rc == GKB_OK && hipEventRecord(e1, st) != hipSuccess) rc = bfail(GKB_ERR_HIP, "event record");
+      if (rc == GKB_OK && hipEventSynchronize(e1) != hipSuccess) rc = bfail(GKB_ERR_HIP, "event sync");
+      float ms = 0.f;
+      if (rc == GKB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = bfail(GKB_ERR_HIP, "event time");
+      gkb_batched_plan_destroy(plan);
+      if (rc != GKB_OK) break;
+      t = ms;
+      if (t < best) {
+        best = t;
+        *best_threads = cand_threads[c];
+        *best_workgroups = o.workgroups;
+      }
+    }
+    if (times_ms) times_ms[n] = t;
+    ++n;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ncand) *ncand = n;
+  return rc;
 }
 
 gkb_status gkb_partial_svd_batched(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,

@@ -39,7 +39,8 @@ class GkbOptions(C.Structure):
 
 class GkbBatchOptions(C.Structure):
     _fields_ = [("check_every", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
-                ("seed", C.c_uint64), ("q1_packed", C.c_void_p), ("workgroups", C.c_int), ("no_graph", C.c_int)]
+                ("seed", C.c_uint64), ("q1_packed", C.c_void_p), ("workgroups", C.c_int), ("no_graph", C.c_int),
+                ("threads", C.c_int)]
 
 
 class GkbStats(C.Structure):
@@ -60,7 +61,7 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_cast_bf16", "gkb_start_vector", "gkb_gemm_rowmajor", "gkb_gram_workspace_size", "gkb_gram",
            "gkb_batch_default_options", "gkb_batched_workspace_size", "gkb_batched_plan_create",
            "gkb_batched_plan_run", "gkb_batched_plan_info", "gkb_batched_plan_grid", "gkb_batched_plan_destroy",
-           "gkb_partial_svd_batched", "gkb_batched_last_error"]
+           "gkb_partial_svd_batched", "gkb_batched_last_error", "gkb_batched_autotune"]
 
 
 def lib():
@@ -136,6 +137,10 @@ def lib():
                                           P(GkbBatchOptions), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                           C.c_void_p, P(C.c_int), C.c_void_p]
     L.gkb_partial_svd_batched.restype = C.c_int
+    L.gkb_batched_autotune.argtypes = [C.c_int, P(GkbMatrix), P(C.c_int), P(C.c_int), C.c_double, C.c_int,
+                                       P(GkbBatchOptions), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, P(C.c_int), P(C.c_int), P(C.c_double), P(C.c_int)]
+    L.gkb_batched_autotune.restype = C.c_int
     L.gkb_batched_last_error.argtypes = []
     L.gkb_batched_last_error.restype = C.c_char_p
     _lib = L
@@ -398,7 +403,7 @@ class BatchPlan:
     """
 
     def __init__(self, As, r, k, tol, max_restarts, check_every=0, seed=0, q1=None, workgroups=0,
-                 no_graph=False, eps_break=0.0, stream=None):
+                 no_graph=False, eps_break=0.0, threads=0, stream=None, tune=False, tune_cache=None):
         torch = _torch()
         L = lib()
         self.batch = len(As)
@@ -423,10 +428,15 @@ class BatchPlan:
         o.workgroups = workgroups
         o.no_graph = 1 if no_graph else 0
         o.eps_break = eps_break
+        o.threads = threads
         self.q1 = q1
         if q1 is not None:
             o.q1_packed = q1.data_ptr()
         self.opts = o
+        self.tuning = None
+        if tune:
+            self.tuning = self._autotune(tol, max_restarts, stream, tune_cache)
+            o.threads, o.workgroups = self.tuning["threads"], self.tuning["workgroups"]
         plan = C.c_void_p()
         st = L.gkb_batched_plan_create(self.batch, self.mats, self.r_arr, self.k_arr, float(tol), int(max_restarts),
                                        C.byref(o), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
@@ -435,6 +445,44 @@ class BatchPlan:
         if st != 0:
             raise GkbError(st, L.gkb_batched_last_error().decode())
         self.plan = plan
+
+    def signature(self):
+        """Cache key: device name and the sorted problem shapes."""
+        torch = _torch()
+        shapes = sorted((int(A.shape[0]), int(A.shape[1]), rr, kk) for A, rr, kk in zip(self.As, self.r, self.k))
+        import hashlib
+        h = hashlib.sha1(repr(shapes).encode()).hexdigest()[:16]
+        return f"{torch.cuda.get_device_properties(self.As[0].device).gcnArchName}:{len(shapes)}:{h}"
+
+    def _autotune(self, tol, max_restarts, stream, cache_path):
+        import json
+        key = self.signature()
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            try:
+                cache = json.load(open(cache_path))
+            except (OSError, ValueError):
+                cache = {}
+        if key in cache:
+            return dict(cache[key], cached=True)
+        L = lib()
+        bt, bw, n = C.c_int(), C.c_int(), C.c_int()
+        times = (C.c_double * 8)()
+        st = L.gkb_batched_autotune(self.batch, self.mats, self.r_arr, self.k_arr, float(tol), int(max_restarts),
+                                    C.byref(self.opts), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                    C.c_void_p(self.sigma.data_ptr()), C.c_void_p(self.U.data_ptr()),
+                                    C.c_void_p(self.V.data_ptr()), _stream(stream), C.byref(bt), C.byref(bw), times,
+                                    C.byref(n))
+        if st != 0:
+            raise GkbError(st, L.gkb_batched_last_error().decode())
+        res = {"threads": bt.value, "workgroups": bw.value, "times_ms": list(times[: n.value])}
+        if cache_path:
+            cache[key] = res
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1)
+            os.replace(tmp, cache_path)
+        return dict(res, cached=False)
 
     @property
     def grid(self):

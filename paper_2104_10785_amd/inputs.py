@@ -195,3 +195,32 @@ def drift_update(m: int, n: int, rank: int, scale: float, seed: int, step: int) 
 def sketch_matrix(n: int, width: int, seed: int, dtype=np.float32) -> np.ndarray:
     """Gaussian test matrix Omega (n x width) for the sketch A Omega."""
     return _rng(seed).standard_normal((n, width)).astype(dtype)
+
+
+def batch_matrix_torch(spec, device, dtype=None):
+    """Materialise one problem of `batch_problems` on a GPU with torch.
+
+    Same construction as `batch_matrix` (Haar factors from the QR of a
+    Gaussian with the sign correction, spectrum rho^(j-1)), drawn from torch's
+    device generator seeded with the problem's seed, in float64, rounded once
+    to float32.  Used where hundreds of large problems must be generated
+    quickly; the matrix is a deterministic function of (seed, device type).
+    """
+    import torch
+    dtype = dtype or torch.float32
+    m, n, rho = spec["m"], spec["n"], spec["rho"]
+    p = min(m, n)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(spec["seed"]))
+
+    def haar_t(rows):
+        z = torch.randn(rows, p, generator=g, device=device, dtype=torch.float64)
+        q, r = torch.linalg.qr(z)
+        d = torch.sign(torch.diagonal(r))
+        d[d == 0] = 1.0
+        return q * d[None, :]
+
+    q1 = haar_t(m)
+    q2 = haar_t(n)
+    s = rho ** torch.arange(p, device=device, dtype=torch.float64)
+    return ((q1 * s[None, :]) @ q2.T).to(dtype).contiguous()

@@ -123,3 +123,72 @@ def test_batched_validation():
         gkb.BatchPlan([A], [3], [6], 1e-6, 1)  # k > min(m, n)
     with pytest.raises(gkb.GkbError):
         gkb.BatchPlan([to_dev(np.ones((200, 100), dtype=np.float32))], [3], [70], 1e-6, 1)  # k > 64
+
+
+def test_batched_autotuner_picks_a_valid_config(tmp_path):
+    import json
+    import torch
+    device()
+    mats, rs, ks = small_batch(16, seed=31, extra=False)
+    banner("batched autotuner")
+    Ad = [to_dev(A) for A in mats]
+    cache = str(tmp_path / "tune.json")
+    plan = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=9, tune=True, tune_cache=cache)
+    t = plan.tuning
+    assert t["threads"] in (512, 1024) and t["workgroups"] > 0 and not t["cached"]
+    assert len(t["times_ms"]) == 3 and min(x for x in t["times_ms"] if x > 0) > 0
+    plan.run()
+    info = plan.info()
+    res = plan.results()
+    qs = [philox.start_vector(A.shape[0], 9 + i) for i, A in enumerate(mats)]
+    check_against_oracle(mats, rs, ks, res, info, qs, 0)
+    plan.close()
+    # second plan on the same shapes reads the cache
+    plan2 = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=9, tune=True, tune_cache=cache)
+    assert plan2.tuning["cached"] and plan2.tuning["threads"] == t["threads"]
+    assert json.load(open(cache))
+    plan2.close()
+    # both workgroup sizes give the same results (per-problem work is identical)
+    p512 = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=9, threads=512, no_graph=True)
+    p1024 = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=9, threads=1024, no_graph=True)
+    p512.run()
+    p1024.run()
+    i512, i1024 = p512.info(), p1024.info()
+    assert np.array_equal(i512[:, 0], i1024[:, 0])
+    for (s1, _, _), (s2, _, _) in zip(p512.results(), p1024.results()):
+        assert np.max(np.abs(s1 - s2)) <= 1e-6 * max(s1[0], 1e-30)
+    p512.close()
+    p1024.close()
+
+
+def test_batched_fullsize_sample_against_oracle():
+    """The 512-problem batch (m in [500, 4000], n in [200, 2000], geometric
+    spectra rho in [0.8, 0.99], r in [5, 20], k = min(n, 2r + 10)) solved in one
+    launch; 6 problems (largest, smallest, and 4 drawn at random) re-solved by
+    the oracle."""
+    import torch
+    device()
+    banner("batched 512 problems full configuration")
+    specs = inputs.batch_problems(512, seed=2, materialize=False)
+    As = [inputs.batch_matrix_torch(sp, "cuda:0") for sp in specs]
+    rs = [sp["r"] for sp in specs]
+    ks = [min(sp["n"], sp["m"], 2 * sp["r"] + 10) for sp in specs]
+    torch.cuda.synchronize()
+    plan = gkb.BatchPlan(As, rs, ks, 1e-6, 50, seed=5, check_every=5)
+    plan.run()
+    info = plan.info()
+    res = plan.results()
+    assert np.all(info[:, 0] == 0), np.unique(info[:, 0], return_counts=True)
+    sizes = np.array([sp["m"] * sp["n"] for sp in specs])
+    rng = np.random.default_rng(0)
+    pick = sorted(set([int(np.argmax(sizes)), int(np.argmin(sizes))] + list(rng.choice(512, 4, replace=False))))
+    for i in pick:
+        A = to_host(As[i])
+        q = philox.start_vector(A.shape[0], 5 + i)
+        ref = gk.partial_svd(A.astype(np.float64), rs[i], ks[i], 1e-6, 50, q, eps_break=1e-6, check_every=5)
+        sig = res[i][0]
+        err = np.max(np.abs(sig - ref["sigma"]))
+        print(f"  problem {i} ({A.shape[0]}x{A.shape[1]}, r={rs[i]}): sigma err {err:.2e}, "
+              f"restarts {info[i, 2]} vs oracle {ref['restarts']}", flush=True)
+        assert err <= bound32(A)
+    plan.close()
