@@ -83,6 +83,97 @@ def cpu_baseline(A32, q, budget_s=20.0):
                       f"underestimates the oracle's time); upcast took {t_up:.1f} s"}
 
 
+def bf16_leg(gkb, torch, Ad, qd, stream, steps):
+    """bfloat16 storage + float32 Rayleigh-Ritz refinement of the same matrix."""
+    A16 = gkb.gkb_cast_bf16(Ad)
+    ws = torch.empty(gkb.gkb_workspace_size(A16, R, K, refine=Ad), dtype=torch.uint8, device=Ad.device)
+    run = lambda: gkb.gkb_partial_svd(A16, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
+                                      check_every=CHECK_EVERY, refine=Ad)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sig, _, _, status, st = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    un = gkb.gkb_partial_svd(A16, R, K, TOL, RESTARTS, q1=qd, stream=stream, check_every=CHECK_EVERY)[0]
+    out = {"ms": ms, "triplets_per_s": st["nconv"] / (ms / 1000.0), "matvecs": st["matvecs"],
+           "ms_refine": st["ms_refine"], "refined": st["refined"]}
+    ref_path = os.path.join(ROOT, "tests", "golden", "c2_oracle_top50.json")
+    if os.path.exists(ref_path):
+        want = np.array(json.load(open(ref_path))["sigma"])
+        e_ref = np.abs(sig - want) / want
+        e_un = np.abs(un - want) / want
+        out["sigma_rel_err_vs_f64_oracle"] = {
+            "unrefined_max": float(e_un.max()), "unrefined_median": float(np.median(e_un)),
+            "refined_max": float(e_ref.max()), "refined_median": float(np.median(e_ref)),
+            "refined_per_triplet": [float(x) for x in e_ref]}
+    xn = torch.randn(N, dtype=torch.float32, device=Ad.device)
+    xm = torch.randn(M, dtype=torch.float32, device=Ad.device)
+    yn = torch.empty(M, dtype=torch.float64, device=Ad.device)
+    ym = torch.empty(N, dtype=torch.float64, device=Ad.device)
+    mws = torch.empty(gkb.gkb_matvec_workspace_size(A16), dtype=torch.uint8, device=Ad.device)
+    ms_n = time_kernel(lambda: gkb.gkb_matvec(A16, xn, 0, y=yn, stream=stream), 20, stream)
+    ms_t = time_kernel(lambda: gkb.gkb_matvec(A16, xm, 1, y=ym, workspace=mws, stream=stream), 20, stream)
+    out["gemv_n_bf16_GBps"] = (M * N * 2 + N * 4 + M * 8) / (ms_n * 1e-3) / 1e9
+    out["gemv_t_bf16_GBps"] = (M * N * 2 + M * 4 + N * 8) / (ms_t * 1e-3) / 1e9
+    del A16, ws
+    return out
+
+
+def rank_leg(gkb, inputs, torch, dev, stream):
+    """Numerical rank at the gap after index 200: the same construction with
+    noise std 1e-10, threshold 1e-6 * sigma_1."""
+    A32, s, _, _ = inputs.lowrank_noise(M, N, RANK, DECAY, 1e-10, seed=SEED, dtype=np.float32)
+    Ad = torch.from_numpy(A32).to(dev)
+    del A32
+    q = torch.from_numpy(inputs.start_vector(M, seed=QSEED)).to(dev)
+    ws = torch.empty(gkb.gkb_rank_workspace_size(Ad, 400), dtype=torch.uint8, device=dev)
+    gkb.gkb_numerical_rank(Ad, 1e-6, k_max=400, q1=q, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rank, rank_s, sig, status, st = gkb.gkb_numerical_rank(Ad, 1e-6, k_max=400, q1=q, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0
+    del Ad, ws
+    return {"workload": "low-rank(200, 0.95^i) + noise(1e-10) 50000x20000 f32, tau = 1e-6 sigma_1",
+            "rank": rank, "rank_sturm": rank_s, "expected": 200, "steps": len(sig), "matvecs": st["matvecs"],
+            "ms": ms}
+
+
+def batched_leg(gkb, inputs, torch, dev, stream):
+    """512 uneven problems in one persistent, graph-captured launch."""
+    specs = inputs.batch_problems(512, seed=2, materialize=False)
+    As = [inputs.batch_matrix_torch(sp, dev) for sp in specs]
+    rs = [sp["r"] for sp in specs]
+    ks = [min(sp["n"], sp["m"], 2 * sp["r"] + 10) for sp in specs]
+    torch.cuda.synchronize()
+    plan = gkb.BatchPlan(As, rs, ks, 1e-6, 50, seed=5, check_every=5, tune=True, stream=stream)
+    plan.run(stream)
+    plan.info(stream)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    plan.run(stream)
+    end.record(stream)
+    end.synchronize()
+    ms = start.elapsed_time(end)
+    info = plan.info(stream)
+    byts = sum(int(info[i, 3]) * sp["m"] * sp["n"] * 4 for i, sp in enumerate(specs))
+    out = {"workload": "512 problems, m U[500,4000], n U[200,2000], rho U[0.8,0.99], r U[5,20], k=min(n,2r+10), "
+                       "tol 1e-6, f32",
+           "ms": ms, "problems_per_s": 512 / (ms / 1000.0),
+           "triplets_per_s": int(info[:, 1].sum()) / (ms / 1000.0),
+           "converged_problems": int((info[:, 0] == 0).sum()), "matvecs": int(info[:, 3].sum()),
+           "A_bytes_GB": sum(sp["m"] * sp["n"] * 4 for sp in specs) / 1e9,
+           "streamed_GBps": byts / (ms * 1e-3) / 1e9,
+           "threads": plan.tuning["threads"], "workgroups": plan.tuning["workgroups"],
+           "autotune_ms": plan.tuning["times_ms"]}
+    plan.close()
+    del As
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +182,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
+    ap.add_argument("--legs", default="bf16,rank,batched",
+                    help="extra legs after the main timing (comma list; empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the Golub-Kahan path on a single "
@@ -158,6 +251,17 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     log(f"gemv_n {ms_n:.4f} ms {gbs_n:.0f} GB/s; gemv_t {ms_t:.4f} ms {gbs_t:.0f} GB/s")
 
+    legs = {}
+    for leg in [x for x in args.legs.split(",") if x]:
+        log(f"leg {leg}")
+        if leg == "bf16":
+            legs["bf16_refined"] = bf16_leg(gkb, torch, Ad, qd, stream, args.steps)
+        elif leg == "rank":
+            legs["rank_gapped"] = rank_leg(gkb, inputs, torch, dev, stream)
+        elif leg == "batched":
+            legs["batched"] = batched_leg(gkb, inputs, torch, dev, stream)
+        log(f"leg {leg} done: {json.dumps(legs)[-300:]}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -182,6 +286,7 @@ def main():
                           "matvecs": fixed[4]["matvecs"]},
         "cpu_baseline": cpu,
     }
+    line.update(legs)
     print(json.dumps(line), flush=True)
 
 
