@@ -174,6 +174,16 @@ def batched_leg(gkb, inputs, torch, dev, stream):
     return out
 
 
+def learned_leg(dev):
+    """Learned start on the drifting 20000 x 5000 sequence (train on solves 1-100,
+    evaluate on 101-200 against the random and the heuristic start)."""
+    from paper_2104_10785_amd import learned
+    out = learned.run(m=20000, n=5000, r=30, k=70, tol=1e-8, t_train=100, t_eval=100, ws=32, hidden=256,
+                      epochs=20, lr=1e-3, check_every=2, seed=3, device=dev, log=log)
+    out.pop("per_t", None)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +192,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
-    ap.add_argument("--legs", default="bf16,rank,batched",
+    ap.add_argument("--legs", default="bf16,rank,batched,learned",
                     help="extra legs after the main timing (comma list; empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -260,6 +270,8 @@ def main():
             legs["rank_gapped"] = rank_leg(gkb, inputs, torch, dev, stream)
         elif leg == "batched":
             legs["batched"] = batched_leg(gkb, inputs, torch, dev, stream)
+        elif leg == "learned":
+            legs["learned_start"] = learned_leg(dev)
         log(f"leg {leg} done: {json.dumps(legs)[-300:]}")
 
     cpu = None

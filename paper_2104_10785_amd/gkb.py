@@ -61,7 +61,10 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_cast_bf16", "gkb_start_vector", "gkb_gemm_rowmajor", "gkb_gram_workspace_size", "gkb_gram",
            "gkb_batch_default_options", "gkb_batched_workspace_size", "gkb_batched_plan_create",
            "gkb_batched_plan_run", "gkb_batched_plan_info", "gkb_batched_plan_grid", "gkb_batched_plan_destroy",
-           "gkb_partial_svd_batched", "gkb_batched_last_error", "gkb_batched_autotune"]
+           "gkb_partial_svd_batched", "gkb_batched_last_error", "gkb_batched_autotune",
+           "gkb_mlp_param_count", "gkb_mlp_feature_stride", "gkb_mlp_workspace_size", "gkb_mlp_features",
+           "gkb_mlp_forward", "gkb_mlp_loss_grad", "gkb_adam_step", "gkb_mlp_start_vector",
+           "gkb_learned_last_error"]
 
 
 def lib():
@@ -143,6 +146,28 @@ def lib():
     L.gkb_batched_autotune.restype = C.c_int
     L.gkb_batched_last_error.argtypes = []
     L.gkb_batched_last_error.restype = C.c_char_p
+    L.gkb_mlp_param_count.argtypes = [C.c_int, C.c_int]
+    L.gkb_mlp_param_count.restype = C.c_int64
+    L.gkb_mlp_feature_stride.argtypes = []
+    L.gkb_mlp_feature_stride.restype = C.c_int
+    L.gkb_mlp_workspace_size.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int]
+    L.gkb_mlp_workspace_size.restype = C.c_size_t
+    L.gkb_mlp_features.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                   C.c_void_p, C.c_size_t, C.c_void_p]
+    L.gkb_mlp_features.restype = C.c_int
+    L.gkb_mlp_forward.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    L.gkb_mlp_forward.restype = C.c_int
+    L.gkb_mlp_loss_grad.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.gkb_mlp_loss_grad.restype = C.c_int
+    L.gkb_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                C.c_double, C.c_double, C.c_int, C.c_void_p]
+    L.gkb_adam_step.restype = C.c_int
+    L.gkb_mlp_start_vector.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_size_t, C.c_void_p]
+    L.gkb_mlp_start_vector.restype = C.c_int
+    L.gkb_learned_last_error.argtypes = []
+    L.gkb_learned_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -523,3 +548,70 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ learned start
+def _lcheck(status):
+    if status != 0:
+        raise GkbError(status, lib().gkb_learned_last_error().decode())
+
+
+def gkb_mlp_param_count(n_in, hidden) -> int:
+    return int(lib().gkb_mlp_param_count(n_in, hidden))
+
+
+def gkb_mlp_features(St, Ut_prev, stream=None):
+    """Features X (m x stride) from the sketch St (ws x m, i.e. m x ws column-major)
+    and the previous left vectors Ut_prev (r x m)."""
+    torch = _torch()
+    ws, m = St.shape
+    r = Ut_prev.shape[0] if Ut_prev is not None else 0
+    X = torch.empty((m, lib().gkb_mlp_feature_stride()), dtype=torch.float32, device=St.device)
+    wk = _workspace(4 * (r + 1) + 256, St.device)
+    _lcheck(lib().gkb_mlp_features(C.c_void_p(St.data_ptr()), St.stride(0), m, ws,
+                                   C.c_void_p(Ut_prev.data_ptr()) if r else None, r, C.c_void_p(X.data_ptr()),
+                                   C.c_void_p(wk.data_ptr()), wk.numel(), _stream(stream)))
+    return X
+
+
+def gkb_mlp_forward(params, n_in, hidden, X, stream=None):
+    torch = _torch()
+    z = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _lcheck(lib().gkb_mlp_forward(C.c_void_p(params.data_ptr()), n_in, hidden, C.c_void_p(X.data_ptr()),
+                                  X.shape[0], C.c_void_p(z.data_ptr()), _stream(stream)))
+    return z
+
+
+def gkb_mlp_loss_grad(params, n_in, hidden, X, Ut, grad=None, loss=None, workspace=None, stream=None):
+    """(grad, loss) device tensors for the target left vectors Ut (r x m)."""
+    torch = _torch()
+    m = X.shape[0]
+    r = Ut.shape[0]
+    if grad is None:
+        grad = torch.empty(gkb_mlp_param_count(n_in, hidden), dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=X.device)
+    if workspace is None:
+        workspace = _workspace(lib().gkb_mlp_workspace_size(m, n_in, hidden, r), X.device)
+    _lcheck(lib().gkb_mlp_loss_grad(C.c_void_p(params.data_ptr()), n_in, hidden, C.c_void_p(X.data_ptr()), m,
+                                    C.c_void_p(Ut.data_ptr()), r, C.c_void_p(grad.data_ptr()),
+                                    C.c_void_p(loss.data_ptr()), C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                    _stream(stream)))
+    return grad, loss
+
+
+def gkb_adam_step(params, grad, m1, m2, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _lcheck(lib().gkb_adam_step(C.c_void_p(params.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                C.c_void_p(m1.data_ptr()), C.c_void_p(m2.data_ptr()), params.numel(), lr, beta1,
+                                beta2, eps, step, _stream(stream)))
+
+
+def gkb_mlp_start_vector(params, n_in, hidden, X, stream=None):
+    torch = _torch()
+    m = X.shape[0]
+    q = torch.empty(m, dtype=torch.float64, device=X.device)
+    wk = _workspace(4 * m + 256, X.device)
+    _lcheck(lib().gkb_mlp_start_vector(C.c_void_p(params.data_ptr()), n_in, hidden, C.c_void_p(X.data_ptr()), m,
+                                       C.c_void_p(q.data_ptr()), C.c_void_p(wk.data_ptr()), wk.numel(),
+                                       _stream(stream)))
+    return q

@@ -224,3 +224,46 @@ def batch_matrix_torch(spec, device, dtype=None):
     q2 = haar_t(n)
     s = rho ** torch.arange(p, device=device, dtype=torch.float64)
     return ((q1 * s[None, :]) @ q2.T).to(dtype).contiguous()
+
+
+def drift_base_torch(m: int, n: int, ratio: float, seed: int, device, dtype=None):
+    """A_0 = Q1 diag(ratio^(i-1))_{i=1..min(m,n)} Q2^T on a GPU (Haar factors
+    from torch's seeded device generator, float64, rounded once)."""
+    import torch
+    dtype = dtype or torch.float32
+    p = min(m, n)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+
+    def haar_t(rows):
+        z = torch.randn(rows, p, generator=g, device=device, dtype=torch.float64)
+        q, r = torch.linalg.qr(z)
+        d = torch.sign(torch.diagonal(r))
+        d[d == 0] = 1.0
+        return q * d[None, :]
+
+    q1 = haar_t(m)
+    q2 = haar_t(n)
+    s = ratio ** torch.arange(p, device=device, dtype=torch.float64)
+    return ((q1 * s[None, :]) @ q2.T).to(dtype).contiguous()
+
+
+def drift_update_torch(m: int, n: int, rank: int, scale: float, seed: int, step: int, device, dtype=None):
+    """dA_t = scale * G1 G2^T with G1 ~ N(0, 1/m) (m x rank), G2 ~ N(0, 1/n)
+    (n x rank), drawn on a GPU from a generator seeded by (seed, step)."""
+    import torch
+    dtype = dtype or torch.float32
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + int(step))
+    g1 = torch.randn(m, rank, generator=g, device=device, dtype=torch.float64) / np.sqrt(m)
+    g2 = torch.randn(n, rank, generator=g, device=device, dtype=torch.float64) / np.sqrt(n)
+    return (scale * (g1 @ g2.T)).to(dtype)
+
+
+def mlp_init(n_in: int, hidden: int, seed: int) -> np.ndarray:
+    """Initial network parameters [W1 | b1 | w2 | b2] (float32): W1 ~ N(0, 2/n_in)
+    (He), w2 ~ N(0, 1/hidden), biases 0."""
+    rng = _rng(seed)
+    w1 = rng.standard_normal(hidden * n_in) * np.sqrt(2.0 / n_in)
+    w2 = rng.standard_normal(hidden) * np.sqrt(1.0 / hidden)
+    return np.concatenate([w1, np.zeros(hidden), w2, [0.0]]).astype(np.float32)

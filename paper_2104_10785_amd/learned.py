@@ -1,0 +1,157 @@
+"""Learned start vectors on a drifting matrix sequence: training and evaluation.
+
+Sequence: A_0 = Q1 diag(ratio^(i-1)) Q2^T, A_t = A_{t-1} + scale * G1 G2^T
+(rank-`rank` Gaussian update with entries of G1 ~ N(0, 1/m), G2 ~ N(0, 1/n), so
+||dA_t||_2 ~ scale).  For each t the top r triplets are computed by
+gkb_partial_svd (Krylov dimension k, tolerance tol, in-cycle checks every
+`check_every` vectors).  All arithmetic runs in the library's kernels; this
+module only sequences the calls.
+
+Training (t = 1..t_train): solve with the random start q ~ N(2, 1) (device
+Philox, key t); the pair (features from S_t = A_t Omega and U_{t-1}, target
+U_t) is kept.  The network is trained with the library's forward/backward and
+Adam kernels.  Evaluation (t = t_train+1 .. t_train+t_eval): three solves per t
+from the same A_t -- random start, learned start (one sketch product counted as
+one matvec, random-start fallback if the learned start does not converge) and
+the heuristic q = sum_j s_j u_j(t-1) -- and their matvec counts.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import gkb, inputs
+
+
+def _heuristic_params(ws: int, r: int, n_in: int):
+    """Parameters under which the network computes z = sum of the previous-vector
+    features: hidden units relu(+x_j) and relu(-x_j), output weights +1 / -1."""
+    hidden = 2 * r
+    W1 = np.zeros((hidden, n_in), dtype=np.float32)
+    for j in range(r):
+        W1[2 * j, ws + j] = 1.0
+        W1[2 * j + 1, ws + j] = -1.0
+    w2 = np.tile(np.array([1.0, -1.0], dtype=np.float32), r)
+    return np.concatenate([W1.ravel(), np.zeros(hidden, np.float32), w2, [0.0]]).astype(np.float32), hidden
+
+
+class DriftSequence:
+    def __init__(self, m, n, ratio, rank, scale, seed, device):
+        self.m, self.n, self.rank, self.scale, self.seed, self.device = m, n, rank, scale, seed, device
+        self.A = inputs.drift_base_torch(m, n, ratio, seed, device)
+        self.t = 0
+
+    def advance(self):
+        self.t += 1
+        self.A += inputs.drift_update_torch(self.m, self.n, self.rank, self.scale, self.seed, self.t, self.device)
+        return self.A
+
+
+def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t_train=100, t_eval=100,
+        ws=32, hidden=256, epochs=20, lr=1e-3, check_every=2, max_restarts=50, seed=3, device="cuda:0",
+        log=None):
+    import torch
+    say = log or (lambda msg: None)
+    t0 = time.time()
+    seq = DriftSequence(m, n, ratio, rank, scale, seed, device)
+    omega_t = torch.from_numpy(np.ascontiguousarray(inputs.sketch_matrix(n, ws, seed + 1).T)).to(device)
+    n_in = ws + r
+    ws_svd = torch.empty(gkb.gkb_workspace_size(seq.A, r, k), dtype=torch.uint8, device=device)
+
+    def solve(q1=None, key=0):
+        return gkb.gkb_partial_svd(seq.A, r, k, tol, max_restarts, q1=q1, seed=key, workspace=ws_svd,
+                                   check_every=check_every)
+
+    def features(U_prev):
+        St = gkb.gkb_gemm_rowmajor(seq.A, omega_t)   # (ws, m) = m x ws column-major
+        return gkb.gkb_mlp_features(St, U_prev)
+
+    # t = 0
+    _, U_prev, _, st0, _ = solve(key=10_000)
+    data = []
+    train_mv = []
+    for t in range(1, t_train + 1):
+        seq.advance()
+        X = features(U_prev)
+        sig, Ut, _, status, stats = solve(key=t)
+        train_mv.append(stats["matvecs"])
+        data.append((X, Ut.clone()))
+        U_prev = Ut
+    say(f"training data: {t_train} solves, mean matvecs {np.mean(train_mv):.1f}, {time.time() - t0:.1f} s")
+
+    # ---- training on the device
+    params = torch.from_numpy(inputs.mlp_init(n_in, hidden, seed + 2)).to(device)
+    m1 = torch.zeros_like(params)
+    m2 = torch.zeros_like(params)
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float64, device=device)
+    wsp = torch.empty(gkb.lib().gkb_mlp_workspace_size(m, n_in, hidden, r), dtype=torch.uint8, device=device)
+    rng = np.random.default_rng(seed + 3)
+    losses = []
+    step = 0
+    t1 = time.time()
+    for ep in range(epochs):
+        ep_loss = []
+        for t in rng.permutation(t_train):
+            X, Ut = data[t]
+            gkb.gkb_mlp_loss_grad(params, n_in, hidden, X, Ut, grad=grad, loss=loss, workspace=wsp)
+            step += 1
+            gkb.gkb_adam_step(params, grad, m1, m2, lr, step)
+            ep_loss.append(loss.clone())
+        losses.append(float(torch.cat(ep_loss).mean().item()) if ep_loss else 0.0)
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    say(f"trained {epochs} epochs in {train_s:.2f} s; loss by epoch {['%.4f' % x for x in losses]}")
+
+    # ---- evaluation
+    hparams, hhidden = _heuristic_params(ws, r, n_in)
+    hparams = torch.from_numpy(hparams).to(device)
+    rows = []
+    for t in range(t_train + 1, t_train + t_eval + 1):
+        seq.advance()
+        X = features(U_prev)
+        # random start
+        sig_r, Ut_r, _, st_r, s_r = solve(key=t)
+        # learned start (+1 matvec for the sketch), random fallback
+        q_l = gkb.gkb_mlp_start_vector(params, n_in, hidden, X)
+        fallback = False
+        try:
+            sig_l, Ut_l, _, st_l, s_l = solve(q1=q_l)
+            mv_l = s_l["matvecs"] + 1
+            ok = st_l == 0
+        except gkb.GkbError:
+            ok, mv_l = False, 1
+        if not ok:
+            fallback = True
+            sig_l, Ut_l, _, st_l, s_l2 = solve(key=t)
+            mv_l += s_l2["matvecs"]
+        # heuristic start
+        q_h = gkb.gkb_mlp_start_vector(hparams, n_in, hhidden, X)
+        try:
+            sig_h, _, _, st_h, s_h = solve(q1=q_h)
+            mv_h = s_h["matvecs"]
+        except gkb.GkbError:
+            st_h, mv_h = -1, -1
+        rows.append({"t": t, "random": s_r["matvecs"], "learned": mv_l, "heuristic": mv_h, "fallback": fallback,
+                     "status_random": st_r, "status_learned": st_l, "status_heuristic": st_h,
+                     "sigma_diff": float(np.max(np.abs(sig_l - sig_r)))})
+        U_prev = Ut_l
+    mv_r = np.array([x["random"] for x in rows], dtype=float)
+    mv_l = np.array([x["learned"] for x in rows], dtype=float)
+    mv_h = np.array([x["heuristic"] for x in rows], dtype=float)
+    out = {
+        "m": m, "n": n, "r": r, "k": k, "tol": tol, "t_train": t_train, "t_eval": t_eval, "hidden": hidden,
+        "sketch_width": ws, "epochs": epochs, "check_every": check_every,
+        "train_loss_by_epoch": losses, "train_seconds": train_s,
+        "matvecs_random": {"mean": mv_r.mean(), "median": float(np.median(mv_r))},
+        "matvecs_learned": {"mean": mv_l.mean(), "median": float(np.median(mv_l))},
+        "matvecs_heuristic": {"mean": mv_h.mean(), "median": float(np.median(mv_h))},
+        "learned_over_random_ratio_mean": float(np.mean(mv_l / mv_r)),
+        "learned_win_fraction": float(np.mean(mv_l < mv_r)),
+        "fallbacks": int(sum(x["fallback"] for x in rows)),
+        "max_sigma_diff_learned_vs_random": float(max(x["sigma_diff"] for x in rows)),
+        "seconds": time.time() - t0,
+        "per_t": rows,
+    }
+    return out
