@@ -1,6 +1,7 @@
 """Benchmark: partial SVD of the large float32 low-rank-plus-noise matrix.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --kernels-only      # only the two matvecs and a 1 GiB copy
 
 Workload: A = U_f diag(0.95^i)_{i=1..200} V_f^T + E, 50000 x 20000 float32,
 E iid N(0, (1e-6)^2) (synthetic, seeded); top 50 triplets, Krylov dimension
@@ -13,8 +14,10 @@ roofline of the dominant kernel (the A-streaming matvecs), and the CPU oracle
 timed on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +30,12 @@ M, N, RANK, DECAY, NOISE, SEED, QSEED = 50000, 20000, 200, 0.95, 1e-6, 2, 1
 R, K, TOL, RESTARTS = 50, 120, 1e-6, 20
 CHECK_EVERY = 10
 HBM_PEAK_GBS = 8000.0
+F32_MFMA_PEAK_TFLOPS = 157.3
+# HBM traffic per launch of the matvec kernels, measured with hardware counters
+# (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy); valid only for
+# the kernel sources whose digest the summary records.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gemv_c2_f32_hbm_traffic.md")
+KERNEL_SOURCES = ["paper_2104_10785_amd/csrc/kernels.hip", "paper_2104_10785_amd/csrc/kernels.h"]
 
 
 def log(msg):
@@ -46,6 +55,73 @@ def time_kernel(fn, reps, stream):
     end.record(stream)
     end.synchronize()
     return start.elapsed_time(end) / reps
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` ("gemv_n" or "gemv_t") from the committed
+    counter summary, or None when it is absent or was taken on other sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            m = re.match(r"^\s*([a-z_]+):\s*(\S+)\s*$", line)
+            if m:
+                vals[m.group(1)] = m.group(2)
+    if vals.get("source_digest") != kernel_source_digest() or f"{kernel}_bytes" not in vals:
+        return None
+    return float(vals[f"{kernel}_bytes"])
+
+
+def matvec_operands(torch, Ad, dev):
+    xn = torch.randn(N, dtype=torch.float32, device=dev)
+    xm = torch.randn(M, dtype=torch.float32, device=dev)
+    yn = torch.empty(M, dtype=torch.float64, device=dev)
+    ym = torch.empty(N, dtype=torch.float64, device=dev)
+    return xn, xm, yn, ym
+
+
+def kernels_only(gkb, torch, Ad, dev, stream, reps):
+    """The two A-streaming matvecs alone (reps launches each) and a plain 1 GiB
+    device copy (3 launches) whose counter readings calibrate the traffic figures."""
+    mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=dev)
+    xn, xm, yn, ym = matvec_operands(torch, Ad, dev)
+    ms_n = time_kernel(lambda: gkb.gkb_matvec(Ad, xn, 0, y=yn, stream=stream), reps, stream)
+    ms_t = time_kernel(lambda: gkb.gkb_matvec(Ad, xm, 1, y=ym, workspace=mws, stream=stream), reps, stream)
+    ritz = ritz_gemms(gkb, torch, dev, stream, reps)
+    src = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels_only": True, "gemv_n_ms": ms_n, "gemv_t_ms": ms_t, "reps": reps,
+                      "ritz_gemms": ritz, "copy_bytes": 2 ** 30, "source_digest": kernel_source_digest()}),
+          flush=True)
+
+
+def ritz_gemms(gkb, torch, dev, stream, reps):
+    """The Ritz-vector products of the workload at their real shapes on the float32
+    MFMA: U = Q_k X_r (m x k times k x r) and V = P_k Y_r (n x k times k x r)."""
+    out = {}
+    for name, rows in (("U=QX", M), ("V=PY", N)):
+        Bt = torch.randn(K, rows, dtype=torch.float32, device=dev)   # basis, column-major rows x K
+        Xt = torch.randn(R, K, dtype=torch.float32, device=dev)      # small factor, column-major K x R
+        Ct = torch.empty(R, rows, dtype=torch.float32, device=dev)
+        ms = time_kernel(lambda: gkb.gkb_gemm_tall(Bt, Xt, C_out=Ct, stream=stream), reps, stream)
+        flops = 2.0 * rows * K * R
+        byts = 4.0 * (rows * K + K * R + rows * R)
+        out[name] = {"ms": ms, "TFLOPs": flops / (ms * 1e-3) / 1e12, "GBps": byts / (ms * 1e-3) / 1e9,
+                     "mfma_frac_of_f32_peak": flops / (ms * 1e-3) / 1e12 / F32_MFMA_PEAK_TFLOPS,
+                     "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 def cpu_baseline(A32, q, budget_s=20.0):
@@ -194,6 +270,8 @@ def main():
     ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
     ap.add_argument("--legs", default="bf16,rank,batched,learned",
                     help="extra legs after the main timing (comma list; empty for none)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="time only the two matvec kernels and a 1 GiB copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the Golub-Kahan path on a single "
@@ -214,6 +292,9 @@ def main():
     ws = torch.empty(gkb.gkb_workspace_size(Ad, R, K), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+    if args.kernels_only:
+        kernels_only(gkb, torch, Ad, dev, stream, args.kernel_reps)
+        return
 
     def step(check_every=args.check_every):
         return gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
@@ -244,10 +325,7 @@ def main():
 
     # ---- dominant kernels: the two A-streaming matvecs, timed live with HIP events
     mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=dev)
-    xn = torch.randn(N, dtype=torch.float32, device=dev)
-    xm = torch.randn(M, dtype=torch.float32, device=dev)
-    yn = torch.empty(M, dtype=torch.float64, device=dev)
-    ym = torch.empty(N, dtype=torch.float64, device=dev)
+    xn, xm, yn, ym = matvec_operands(torch, Ad, dev)
     ms_n = time_kernel(lambda: gkb.gkb_matvec(Ad, xn, 0, y=yn, stream=stream), args.kernel_reps, stream)
     ms_t = time_kernel(lambda: gkb.gkb_matvec(Ad, xm, 1, y=ym, workspace=mws, stream=stream), args.kernel_reps,
                        stream)
@@ -260,6 +338,8 @@ def main():
     dom_ms, dom_bytes, dom_name = (ms_t, bytes_t, "gemv_t") if ms_t >= ms_n else (ms_n, bytes_n, "gemv_n")
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     log(f"gemv_n {ms_n:.4f} ms {gbs_n:.0f} GB/s; gemv_t {ms_t:.4f} ms {gbs_t:.0f} GB/s")
+    ritz = ritz_gemms(gkb, torch, dev, stream, args.kernel_reps)
+    log(f"Ritz GEMMs: {ritz}")
 
     legs = {}
     for leg in [x for x in args.legs.split(",") if x]:
@@ -289,8 +369,10 @@ def main():
                    "r": R, "k": K, "tol": TOL, "max_restarts": RESTARTS, "check_every": args.check_every,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom_name),
+                     "algorithmic_bytes": dom_bytes, "kernel_ms": dom_ms},
         "matvec": {"gemv_n_ms": ms_n, "gemv_n_GBps": gbs_n, "gemv_t_ms": ms_t, "gemv_t_GBps": gbs_t},
+        "ritz_gemm": ritz,
         "solve": {"nconv": stats["nconv"], "matvecs": stats["matvecs"], "restarts": stats["restarts"],
                   "krylov_dim": stats["krylov_dim"], "checks": stats["checks"],
                   "ms_host_svd": stats["ms_host"], "sigma1": float(sigma[0]), "sigma50": float(sigma[-1])},

@@ -65,101 +65,117 @@ __device__ double block_sum(double v, Lds<BT>& L) {
   return t;
 }
 
-// w = A p - c * qprev  (qprev may be null); waves own rows, lanes stride columns.
+// w = A p - c * qprev  (qprev may be null); each wave owns 4 rows at a time,
+// lanes stride the columns with 16-byte loads (4 rows x 2 vectors in flight).
 template <int BT>
 __device__ void bgemv_n(const BatchProblem& P, const float* p, const float* qprev, double c, double* w) {
   constexpr int NW = BT / 64;
+  constexpr int R = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
-  for (int i0 = wave * 2; i0 < P.m; i0 += NW * 2) {
-    const int i1 = i0 + 1 < P.m ? i0 + 1 : i0;
-    const float* r0 = P.A + (int64_t)i0 * P.lda;
-    const float* r1 = P.A + (int64_t)i1 * P.lda;
-    float a0 = 0.f, a1 = 0.f;
+  for (int i0 = wave * R; i0 < P.m; i0 += NW * R) {
+    const float* rows[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rows[r] = P.A + (int64_t)min(i0 + r, P.m - 1) * P.lda;
+    float a[R] = {0.f, 0.f, 0.f, 0.f};
     int jt = 0;
     if (vec) {
       const int nv = P.n >> 2;
-      for (int v = lane; v < nv; v += 64) {
-        const float4 pv = reinterpret_cast<const float4*>(p)[v];
-        const float4 x0 = reinterpret_cast<const float4*>(r0)[v];
-        const float4 x1 = reinterpret_cast<const float4*>(r1)[v];
-        a0 += x0.x * pv.x + x0.y * pv.y + x0.z * pv.z + x0.w * pv.w;
-        a1 += x1.x * pv.x + x1.y * pv.y + x1.z * pv.z + x1.w * pv.w;
+      for (int v0 = lane; v0 < nv; v0 += 128) {
+        const int v1 = v0 + 64;
+        const bool ok1 = v1 < nv;
+        const float4 p0 = reinterpret_cast<const float4*>(p)[v0];
+        const float4 p1 = ok1 ? reinterpret_cast<const float4*>(p)[v1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 x0[R], x1[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          x0[r] = reinterpret_cast<const float4*>(rows[r])[v0];
+          x1[r] = ok1 ? reinterpret_cast<const float4*>(rows[r])[v1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          a[r] += x0[r].x * p0.x + x0[r].y * p0.y + x0[r].z * p0.z + x0[r].w * p0.w +
+                  x1[r].x * p1.x + x1[r].y * p1.y + x1[r].z * p1.z + x1[r].w * p1.w;
       }
       jt = nv << 2;
     }
     for (int j = jt + lane; j < P.n; j += 64) {
-      a0 += r0[j] * p[j];
-      a1 += r1[j] * p[j];
+      const float pj = p[j];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] += rows[r][j] * pj;
     }
-    const double s0 = wsum((double)a0), s1 = wsum((double)a1);
-    if (lane == 0) {
-      w[i0] = s0 - (qprev ? c * (double)qprev[i0] : 0.0);
-      if (i1 != i0) w[i1] = s1 - (qprev ? c * (double)qprev[i1] : 0.0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double sr = wsum((double)a[r]);
+      if (lane == 0 && i0 + r < P.m) w[i0 + r] = sr - (qprev ? c * (double)qprev[i0 + r] : 0.0);
     }
   }
   __syncthreads();
 }
 
 // z = A^T q - c * pprev; threads own 4-column groups, G row groups split the
-// rows, partial sums meet in LDS and are added in group order.
+// rows (4 rows in flight per thread), partial sums meet in LDS and are added
+// in group order.
 template <int BT>
-__device__ void bgemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z, Lds<BT>& L) {
+__device__ void bgemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z,
+                        Lds<BT>& L) {
   const int tid = threadIdx.x;
   const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) && ((P.n & 3) == 0);
   const int VN = vec ? 4 : 1;
   const int ncg = (P.n + VN - 1) / VN;
-  if (ncg >= BT) {
-    for (int cg = tid; cg < ncg; cg += BT) {
-      float acc[4] = {0.f, 0.f, 0.f, 0.f};
-      for (int i = 0; i < P.m; ++i) {
-        const float qi = q[i];
-        const float* row = P.A + (int64_t)i * P.lda + cg * VN;
-        if (vec) {
-          const float4 a = *reinterpret_cast<const float4*>(row);
-          acc[0] += a.x * qi;
-          acc[1] += a.y * qi;
-          acc[2] += a.z * qi;
-          acc[3] += a.w * qi;
-        } else {
-          acc[0] += row[0] * qi;
-        }
+  const int G = ncg >= BT ? 1 : BT / ncg;  // G * n <= 4 * BT
+  const int g = ncg >= BT ? 0 : tid / ncg;
+  for (int cg = ncg >= BT ? tid : tid % ncg; cg < ncg && g < G; cg += (ncg >= BT ? BT : ncg)) {
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const float* base = P.A + cg * VN;
+    int i = g;
+    for (; i + 3 * G < P.m; i += 4 * G) {
+      const float q0 = q[i], q1 = q[i + G], q2 = q[i + 2 * G], q3 = q[i + 3 * G];
+      if (vec) {
+        const float4 a0 = *reinterpret_cast<const float4*>(base + (int64_t)i * P.lda);
+        const float4 a1 = *reinterpret_cast<const float4*>(base + (int64_t)(i + G) * P.lda);
+        const float4 a2 = *reinterpret_cast<const float4*>(base + (int64_t)(i + 2 * G) * P.lda);
+        const float4 a3 = *reinterpret_cast<const float4*>(base + (int64_t)(i + 3 * G) * P.lda);
+        acc[0] += a0.x * q0 + a1.x * q1 + a2.x * q2 + a3.x * q3;
+        acc[1] += a0.y * q0 + a1.y * q1 + a2.y * q2 + a3.y * q3;
+        acc[2] += a0.z * q0 + a1.z * q1 + a2.z * q2 + a3.z * q3;
+        acc[3] += a0.w * q0 + a1.w * q1 + a2.w * q2 + a3.w * q3;
+      } else {
+        acc[0] += base[(int64_t)i * P.lda] * q0 + base[(int64_t)(i + G) * P.lda] * q1 +
+                  base[(int64_t)(i + 2 * G) * P.lda] * q2 + base[(int64_t)(i + 3 * G) * P.lda] * q3;
       }
+    }
+    for (; i < P.m; i += G) {
+      const float qi = q[i];
+      if (vec) {
+        const float4 a0 = *reinterpret_cast<const float4*>(base + (int64_t)i * P.lda);
+        acc[0] += a0.x * qi;
+        acc[1] += a0.y * qi;
+        acc[2] += a0.z * qi;
+        acc[3] += a0.w * qi;
+      } else {
+        acc[0] += base[(int64_t)i * P.lda] * qi;
+      }
+    }
+    if (ncg >= BT) {
       for (int e = 0; e < VN; ++e) {
         const int j = cg * VN + e;
         z[j] = (double)acc[e] - (pprev ? c * (double)pprev[j] : 0.0);
       }
+    } else {
+      for (int e = 0; e < VN; ++e) L.tpart[g * P.n + cg * VN + e] = acc[e];
+    }
+  }
+  __syncthreads();
+  if (ncg < BT) {
+    for (int j = tid; j < P.n; j += BT) {
+      double s = 0.0;
+      for (int gg = 0; gg < G; ++gg) s += (double)L.tpart[gg * P.n + j];
+      z[j] = s - (pprev ? c * (double)pprev[j] : 0.0);
     }
     __syncthreads();
-    return;
   }
-  const int G = BT / ncg;  // >= 1, G * n <= 4096
-  const int g = tid / ncg, cg = tid % ncg;
-  if (g < G) {
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int i = g; i < P.m; i += G) {
-      const float qi = q[i];
-      const float* row = P.A + (int64_t)i * P.lda + cg * VN;
-      if (vec) {
-        const float4 a = *reinterpret_cast<const float4*>(row);
-        acc[0] += a.x * qi;
-        acc[1] += a.y * qi;
-        acc[2] += a.z * qi;
-        acc[3] += a.w * qi;
-      } else {
-        acc[0] += row[0] * qi;
-      }
-    }
-    for (int e = 0; e < VN; ++e) L.tpart[g * P.n + cg * VN + e] = acc[e];
-  }
-  __syncthreads();
-  for (int j = tid; j < P.n; j += BT) {
-    double s = 0.0;
-    for (int gg = 0; gg < G; ++gg) s += (double)L.tpart[gg * P.n + j];
-    z[j] = s - (pprev ? c * (double)pprev[j] : 0.0);
-  }
-  __syncthreads();
 }
 
 // h[j] = V[:, j] . x for j < t (waves own columns, lanes own rows).

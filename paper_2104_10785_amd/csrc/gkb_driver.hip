@@ -75,10 +75,11 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
   }
   L.w = take((size_t)L.ldm * 8);
   L.z = take((size_t)L.ldn * 8);
-  gkb::GemvTShape sh = gkb::gemv_t_shape(m, n, elem_bytes(dt));
-  // the scalar gemv_t path uses 256-column tiles with the same row blocking
+  // gemv_t partial sums: at most GEMV_T_MAX_BLOCKS row blocks, and no more
+  // than one per 64 rows (the launch never uses more)
+  const int64_t part_rows = std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (m + 63) / 64);
   L.ldpart = L.ldn;
-  L.part = take((size_t)sh.nb * L.ldpart * acc);
+  L.part = take((size_t)part_rows * L.ldpart * acc);
   const int nch = std::max(gkb::dots_chunks(m), gkb::dots_chunks(n));
   L.hpart = take((size_t)nch * L.ldh * 8);
   L.h = take((size_t)L.ldh * 8);
@@ -789,8 +790,8 @@ int64_t gkb_host_bidiag_count_above(int nq, int np, const double* alpha, const d
 // ------------------------------------------------------------ building blocks
 size_t gkb_matvec_workspace_size(const gkb_matrix* A) {
   if (check_matrix(A) != GKB_OK) return 0;
-  gkb::GemvTShape sh = gkb::gemv_t_shape(A->m, A->n, elem_bytes(A->dtype));
-  return align256((size_t)sh.nb * round64(A->n) * (A->dtype == GKB_F64 ? 8 : 4));
+  const int64_t part_rows = std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (A->m + 63) / 64);
+  return align256((size_t)part_rows * round64(A->n) * (A->dtype == GKB_F64 ? 8 : 4));
 }
 
 gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, void* workspace,

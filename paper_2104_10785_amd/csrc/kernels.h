@@ -20,6 +20,12 @@ struct MatrixRef {
   int dtype;
 };
 
+// Most row blocks (partial sums) the gemv_t launch uses.
+constexpr int GEMV_T_MAX_BLOCKS = 512;
+
+// Compute units of the current device (256 if it cannot be queried).
+int device_cus();
+
 struct GemvTShape {
   int64_t rows_per_block;
   int nb;         // row blocks = partial vectors

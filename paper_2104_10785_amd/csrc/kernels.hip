@@ -179,8 +179,12 @@ __global__ __launch_bounds__(256) void k_gemv_n(const TA* __restrict__ A, int64_
 
 // ---------------------------------------------------------------- gemv_t
 // Phase 1: part[b * ldpart + j] = sum_{i in row block b} A[i, j] q[i].
-// A block of 256 threads owns 256 * VN consecutive columns; rows of the
-// block's row range are streamed U at a time (U loads in flight per lane).
+// A block of 256 threads owns a tile of 256 * VN * VPT consecutive columns:
+// thread t reads the VN-element vectors at tile + v * 256 * VN + t * VN for
+// v < VPT, so each of the VPT loads of a row is one contiguous 256 * 16-byte
+// segment per block.  U rows are in flight per lane.  Few, tall row blocks
+// (about two blocks per compute unit in total) keep each block's stream long.
+// The vector form needs n to be a multiple of VN (the launcher checks).
 template <typename TA, typename TB, bool VECTOR>
 __global__ __launch_bounds__(256) void k_gemv_t_part(const TA* __restrict__ A, int64_t lda, int64_t m,
                                                      int64_t n, const TB* __restrict__ q,
@@ -190,32 +194,47 @@ __global__ __launch_bounds__(256) void k_gemv_t_part(const TA* __restrict__ A, i
   if (flag != nullptr && flag[0] != 0) return;
   using ACC = typename Acc<TA>::type;
   constexpr int VN = VECTOR ? Pack<TA>::VN : 1;
-  constexpr int U = VECTOR ? 8 : 4;
-  const int64_t col0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * VN;
+  constexpr int VPT = VECTOR ? 2 : 1;
+  constexpr int U = VECTOR ? 4 : 4;
+  const int64_t tile0 = (int64_t)blockIdx.x * 256 * VN * VPT;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
   int64_t r1 = r0 + rows_per_block;
   if (r1 > m) r1 = m;
-  ACC acc[VN];
+  ACC acc[VPT][VN];
 #pragma unroll
-  for (int e = 0; e < VN; ++e) acc[e] = 0;
-  if (col0 < n) {
-    const bool full = col0 + VN <= n;
+  for (int v = 0; v < VPT; ++v)
+#pragma unroll
+    for (int e = 0; e < VN; ++e) acc[v][e] = 0;
+  int64_t col[VPT];
+  bool full[VPT], any = false;
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) {
+    col[v] = tile0 + (int64_t)v * 256 * VN + (int64_t)threadIdx.x * VN;
+    full[v] = col[v] + VN <= n;
+    any = any || col[v] < n;
+  }
+  if (any) {
     for (int64_t i = r0; i < r1; i += U) {
-      if (VECTOR && full) {
-        uint4 a[U];
+      if (VECTOR) {
+        uint4 a[U][VPT];
         ACC qv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool ok = i + u < r1;
-          a[u] = ok ? ld_stream(A + (i + u) * lda + col0) : make_uint4(0, 0, 0, 0);
           qv[u] = ok ? (ACC)q[i + u] : (ACC)0;
+#pragma unroll
+          for (int v = 0; v < VPT; ++v)
+            a[u][v] = (ok && full[v]) ? ld_stream(A + (i + u) * lda + col[v]) : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          ACC av[Pack<TA>::VN];
-          Pack<TA>::unpack(a[u], av);
 #pragma unroll
-          for (int e = 0; e < VN; ++e) acc[e] += av[e] * qv[u];
+          for (int v = 0; v < VPT; ++v) {
+            ACC av[Pack<TA>::VN];
+            Pack<TA>::unpack(a[u][v], av);
+#pragma unroll
+            for (int e = 0; e < VN; ++e) acc[v][e] += av[e] * qv[u];
+          }
         }
       } else {
 #pragma unroll
@@ -224,8 +243,10 @@ __global__ __launch_bounds__(256) void k_gemv_t_part(const TA* __restrict__ A, i
             const ACC qi = (ACC)q[i + u];
             const TA* row = A + (i + u) * lda;
 #pragma unroll
-            for (int e = 0; e < VN; ++e)
-              if (col0 + e < n) acc[e] += to_acc(row[col0 + e]) * qi;
+            for (int v = 0; v < VPT; ++v)
+#pragma unroll
+              for (int e = 0; e < VN; ++e)
+                if (col[v] + e < n) acc[v][e] += to_acc(row[col[v] + e]) * qi;
           }
         }
       }
@@ -233,8 +254,10 @@ __global__ __launch_bounds__(256) void k_gemv_t_part(const TA* __restrict__ A, i
   }
   ACC* out = part + (int64_t)blockIdx.y * ldpart;
 #pragma unroll
-  for (int e = 0; e < VN; ++e)
-    if (col0 + e < n) out[col0 + e] = acc[e];
+  for (int v = 0; v < VPT; ++v)
+#pragma unroll
+    for (int e = 0; e < VN; ++e)
+      if (col[v] + e < n) out[col[v] + e] = acc[v][e];
 }
 
 // Phase 2: z[j] = sum_b part[b][j] - coef[cidx] * pprev[j]  (pprev may be null).
@@ -705,15 +728,29 @@ hipError_t launch_gemv_n_t(const TA* A, int64_t lda, int64_t m, int64_t n, const
   return hipGetLastError();
 }
 
+int device_cus() {
+  static int cached = 0;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    cached = cus;
+  else
+    return 256;
+  return cached;
+}
+
 GemvTShape gemv_t_shape(int64_t m, int64_t n, int dtype_bytes) {
   GemvTShape s;
   const int vn = 16 / dtype_bytes;
-  s.col_tiles = nblocks(n, 256 * (int64_t)vn);
-  int64_t want = (2048 + s.col_tiles - 1) / s.col_tiles;
+  s.col_tiles = nblocks(n, 256 * 2 * (int64_t)vn);
+  // Two blocks per compute unit in total (never more), so every CU streams
+  // the same amount: an extra partial wave of blocks would leave a tail.
+  int64_t want = (2 * (int64_t)device_cus()) / s.col_tiles;
   int64_t maxnb = (m + 63) / 64;
   if (want > maxnb) want = maxnb;
+  if (want > GEMV_T_MAX_BLOCKS) want = GEMV_T_MAX_BLOCKS;
   if (want < 1) want = 1;
-  if (want > 512) want = 512;
   s.rows_per_block = (m + want - 1) / want;
   s.nb = (int)((m + s.rows_per_block - 1) / s.rows_per_block);
   return s;
@@ -724,7 +761,8 @@ hipError_t launch_gemv_t_t(const TA* A, int64_t lda, int64_t m, int64_t n, const
                            const double* coef, int cidx, double* z, void* part, int64_t ldpart,
                            const int* flag, hipStream_t st) {
   using ACC = typename Acc<TA>::type;
-  const bool vec = ((lda % Pack<TA>::VN) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  const bool vec = ((lda % Pack<TA>::VN) == 0) && ((n % Pack<TA>::VN) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   GemvTShape s = gemv_t_shape(m, n, (int)sizeof(TA));
   ACC* pa = reinterpret_cast<ACC*>(part);
   if (vec) {
