@@ -35,7 +35,8 @@ F32_MFMA_PEAK_TFLOPS = 157.3
 # (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy); valid only for
 # the kernel sources whose digest the summary records.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gemv_c2_f32_hbm_traffic.md")
-KERNEL_SOURCES = ["paper_2104_10785_amd/csrc/kernels.hip", "paper_2104_10785_amd/csrc/kernels.h"]
+KERNEL_SOURCES = ["paper_2104_10785_amd/csrc/gemv.hip", "paper_2104_10785_amd/csrc/gemv.h",
+                  "paper_2104_10785_amd/csrc/device_common.h"]
 
 
 def log(msg):

@@ -32,7 +32,11 @@ gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, 
  * C (M x N) = A (M x K) B (K x N), all column-major with leading dimensions
  * lda >= M, ldb >= K, ldc >= M, on the 16x16x4 MFMA (float64 or float32).
  * This is the Ritz-vector product V = P Y, U = Q X of Algorithm 2 (and the
- * restart products).  dtype is GKB_F64 or GKB_F32.
+ * restart products).  dtype is GKB_F64 or GKB_F32.  All pointers are device
+ * pointers owned by the caller; A and B may be NULL when K = 0 (C is then
+ * zero-filled).  Columns whose start is 16-byte aligned (lda, ldc multiples
+ * of 16 bytes and aligned base pointers) are moved with 16-byte accesses.
+ * Returns GKB_ERR_INVALID for negative sizes or too-small leading dimensions.
  */
 gkb_status gkb_gemm_tall(gkb_dtype dtype, const void* A, int64_t lda, int64_t M, int K, const void* B,
                          int64_t ldb, int N, void* C, int64_t ldc, void* stream);

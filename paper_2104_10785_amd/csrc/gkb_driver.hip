@@ -827,7 +827,7 @@ gkb_status gkb_gemm_tall(gkb_dtype dtype, const void* A, int64_t lda, int64_t M,
   if (dtype != GKB_F64 && dtype != GKB_F32) return fail(GKB_ERR_INVALID, "dtype must be F64 or F32");
   if (M < 0 || K < 0 || N < 0 || lda < M || ldb < K || ldc < M)
     return fail(GKB_ERR_INVALID, "bad GEMM shape");
-  if ((M > 0 && N > 0) && (!A || !B || !C)) return fail(GKB_ERR_INVALID, "NULL operand");
+  if ((M > 0 && N > 0) && (!C || (K > 0 && (!A || !B)))) return fail(GKB_ERR_INVALID, "NULL operand");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (dtype == GKB_F64)
     GKB_HIP(gkb::launch_gemm_tall<double>((const double*)A, lda, M, K, (const double*)B, ldb, N, (double*)C, ldc,

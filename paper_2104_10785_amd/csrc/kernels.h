@@ -6,45 +6,12 @@
 
 #include <cstdint>
 
+#include "gemv.h"
+
 namespace gkb {
-
-struct bf16 {
-  uint16_t bits;
-};
-
-// A, row-major m x n, leading dimension lda; dtype 0 = double, 1 = float,
-// 2 = bfloat16.
-struct MatrixRef {
-  const void* data;
-  int64_t m, n, lda;
-  int dtype;
-};
-
-// Most row blocks (partial sums) the gemv_t launch uses.
-constexpr int GEMV_T_MAX_BLOCKS = 512;
-
-// Compute units of the current device (256 if it cannot be queried).
-int device_cus();
-
-struct GemvTShape {
-  int64_t rows_per_block;
-  int nb;         // row blocks = partial vectors
-  int col_tiles;  // blocks along n (vector path)
-};
-GemvTShape gemv_t_shape(int64_t m, int64_t n, int dtype_bytes);
 
 int dots_chunks(int64_t len);
 int update_blocks(int64_t len);
-
-// w = A p - coef[cidx] * qprev   (qprev == nullptr: no recurrence term)
-template <typename TB>
-hipError_t launch_gemv_n(const MatrixRef& A, const TB* p, const TB* qprev, const double* coef, int cidx,
-                         double* w, const int* flag, hipStream_t st);
-
-// z = A^T q - coef[cidx] * pprev, through `part` (nb x ldpart accumulators)
-template <typename TB>
-hipError_t launch_gemv_t(const MatrixRef& A, const TB* q, const TB* pprev, const double* coef, int cidx,
-                         double* z, void* part, int64_t ldpart, const int* flag, hipStream_t st);
 
 // h[0..t) = V^T x through hpart (dots_chunks(len) x ldh)
 template <typename TB>
@@ -73,6 +40,17 @@ hipError_t launch_copy_vec(const TB* src, int64_t len, TB* dst, hipStream_t st);
 template <typename T>
 hipError_t launch_gemm_tall(const T* A, int64_t lda, int64_t M, int K, const T* B, int64_t ldb, int N, T* C,
                             int64_t ldc, hipStream_t st);
+
+// Split-K form for long K (K-range slices summed in a fixed order): partial
+// must hold gemm_split(M, K, N).slices * M * N elements.
+struct GemmSplit {
+  int kchunk;
+  int slices;
+};
+GemmSplit gemm_split(int64_t M, int64_t K, int N);
+template <typename T>
+hipError_t launch_gemm_tall_splitk(const T* A, int64_t lda, int64_t M, int K, const T* B, int64_t ldb, int N,
+                                   T* C, int64_t ldc, T* partial, hipStream_t st);
 
 // C (M x N, col-major) = A (M x K, row-major float32) * B (K x N, col-major float32), MFMA
 hipError_t launch_gemm_rm(const float* A, int64_t lda, int64_t M, int64_t K, const float* B, int64_t ldb, int N,

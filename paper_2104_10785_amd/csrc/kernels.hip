@@ -1,9 +1,6 @@
-// HIP kernels for gfx950 (CDNA4): the Golub-Kahan bidiagonalization hot path.
+// HIP kernels for gfx950 (CDNA4): the Golub-Kahan bidiagonalization hot path
+// apart from the two products of eq. 2.2 (those are in gemv.hip).
 //
-//   gemv_n        w = A p - alpha q           (Bidiag 1, eq. 2.2, first line)
-//   gemv_t        z = A^T q - beta p          (eq. 2.2, second line), two
-//                 deterministic phases: per-row-block partial sums, then a
-//                 column reduction with the recurrence term fused in
 //   dots/update   classical Gram-Schmidt projection x <- x - V (V^T x)
 //                 (Algorithm 1's reorthogonalisation), float64 coefficients
 //   normalize     norm, breakdown test, scaling into the basis
@@ -17,272 +14,13 @@
 // runs on the same input are bitwise identical.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
+#include "device_common.h"
 #include "kernels.h"
 
 namespace gkb {
-
-// ---------------------------------------------------------------- types
-template <typename TA> struct Acc;
-template <> struct Acc<double> { using type = double; };
-template <> struct Acc<float> { using type = float; };
-template <> struct Acc<bf16> { using type = float; };
-
-__device__ __forceinline__ double to_acc(double x) { return x; }
-__device__ __forceinline__ float to_acc(float x) { return x; }
-__device__ __forceinline__ float to_acc(bf16 x) { return __uint_as_float(((uint32_t)x.bits) << 16); }
-
-// Unpack a 16-byte load into VN accumulator values.
-template <typename TA> struct Pack;
-template <> struct Pack<double> {
-  static constexpr int VN = 2;
-  __device__ __forceinline__ static void unpack(const uint4& u, double* o) {
-    o[0] = __hiloint2double((int)u.y, (int)u.x);
-    o[1] = __hiloint2double((int)u.w, (int)u.z);
-  }
-};
-template <> struct Pack<float> {
-  static constexpr int VN = 4;
-  __device__ __forceinline__ static void unpack(const uint4& u, float* o) {
-    o[0] = __uint_as_float(u.x);
-    o[1] = __uint_as_float(u.y);
-    o[2] = __uint_as_float(u.z);
-    o[3] = __uint_as_float(u.w);
-  }
-};
-template <> struct Pack<bf16> {
-  static constexpr int VN = 8;
-  __device__ __forceinline__ static void unpack(const uint4& u, float* o) {
-    o[0] = __uint_as_float(u.x << 16);
-    o[1] = __uint_as_float(u.x & 0xffff0000u);
-    o[2] = __uint_as_float(u.y << 16);
-    o[3] = __uint_as_float(u.y & 0xffff0000u);
-    o[4] = __uint_as_float(u.z << 16);
-    o[5] = __uint_as_float(u.z & 0xffff0000u);
-    o[6] = __uint_as_float(u.w << 16);
-    o[7] = __uint_as_float(u.w & 0xffff0000u);
-  }
-};
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ uint4 ld_stream(const void* p) {
-  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
-  return make_uint4(v.x, v.y, v.z, v.w);
-}
-
-// n consecutive basis values from a 16-byte aligned address, as the
-// accumulator type (zeros when !ok).
-template <typename TB, int VN, typename ACC>
-__device__ __forceinline__ void load_vec(const TB* ptr, bool ok, ACC* out) {
-  if constexpr ((VN * sizeof(TB)) % 16 == 0) {
-    constexpr int NQ = VN * sizeof(TB) / 16;
-    uint4 raw[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) raw[i] = ok ? reinterpret_cast<const uint4*>(ptr)[i] : make_uint4(0, 0, 0, 0);
-    const TB* vals = reinterpret_cast<const TB*>(raw);
-#pragma unroll
-    for (int e = 0; e < VN; ++e) out[e] = (ACC)vals[e];
-  } else {
-#pragma unroll
-    for (int e = 0; e < VN; ++e) out[e] = ok ? (ACC)ptr[e] : (ACC)0;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Block (256 threads) sum in a fixed order; result valid in every thread.
-__device__ __forceinline__ double block_sum256(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double t = (red[0] + red[1]) + (red[2] + red[3]);
-  return t;
-}
-
-// ---------------------------------------------------------------- gemv_n
-// w[i] = sum_j A[i, j] p[j] - coef[cidx] * qprev[i]  (qprev may be null).
-// One wave owns R consecutive rows; lanes stride the row with 16-byte loads
-// (VECTOR) or scalars, and p is loaded once per column chunk for all R rows.
-template <typename TA, typename TB, int R, bool VECTOR>
-__global__ __launch_bounds__(256) void k_gemv_n(const TA* __restrict__ A, int64_t lda, int64_t m,
-                                                int64_t n, const TB* __restrict__ p,
-                                                const TB* __restrict__ qprev,
-                                                const double* __restrict__ coef, int cidx,
-                                                double* __restrict__ w, const int* __restrict__ flag) {
-  if (flag != nullptr && flag[0] != 0) return;
-  using ACC = typename Acc<TA>::type;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * R;
-  if (row0 >= m) return;
-  const TA* rows[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) rows[r] = A + (row0 + r < m ? row0 + r : m - 1) * lda;
-  ACC acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0;
-  int64_t jtail = 0;
-  if (VECTOR) {
-    constexpr int VN = Pack<TA>::VN;
-    const int64_t nv = n / VN;
-    constexpr int U = 2;
-    for (int64_t v0 = lane; v0 < nv; v0 += 64 * U) {
-      uint4 a[U][R];
-      ACC pv[U][VN];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t v = v0 + 64 * u;
-        const bool ok = v < nv;
-#pragma unroll
-        for (int r = 0; r < R; ++r) a[u][r] = ok ? ld_stream(rows[r] + v * VN) : make_uint4(0, 0, 0, 0);
-        load_vec<TB, VN>(p + v * VN, ok, pv[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          ACC av[VN];
-          Pack<TA>::unpack(a[u][r], av);
-#pragma unroll
-          for (int e = 0; e < VN; ++e) acc[r] += av[e] * pv[u][e];
-        }
-      }
-    }
-    jtail = nv * VN;
-  }
-  for (int64_t j = jtail + lane; j < n; j += 64) {
-    const ACC pj = (ACC)p[j];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += to_acc(rows[r][j]) * pj;
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = wave_sum(acc[r]);
-  const double c = (qprev != nullptr) ? coef[cidx] : 0.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int64_t i = row0 + r;
-    if (lane == r && i < m) {
-      double v = (double)acc[r];
-      if (qprev != nullptr) v -= c * (double)qprev[i];
-      w[i] = v;
-    }
-  }
-}
-
-// ---------------------------------------------------------------- gemv_t
-// Phase 1: part[b * ldpart + j] = sum_{i in row block b} A[i, j] q[i].
-// A block of 256 threads owns a tile of 256 * VN * VPT consecutive columns:
-// thread t reads the VN-element vectors at tile + v * 256 * VN + t * VN for
-// v < VPT, so each of the VPT loads of a row is one contiguous 256 * 16-byte
-// segment per block.  U rows are in flight per lane.  Few, tall row blocks
-// (about two blocks per compute unit in total) keep each block's stream long.
-// The vector form needs n to be a multiple of VN (the launcher checks).
-template <typename TA, typename TB, bool VECTOR>
-__global__ __launch_bounds__(256) void k_gemv_t_part(const TA* __restrict__ A, int64_t lda, int64_t m,
-                                                     int64_t n, const TB* __restrict__ q,
-                                                     int64_t rows_per_block,
-                                                     typename Acc<TA>::type* __restrict__ part,
-                                                     int64_t ldpart, const int* __restrict__ flag) {
-  if (flag != nullptr && flag[0] != 0) return;
-  using ACC = typename Acc<TA>::type;
-  constexpr int VN = VECTOR ? Pack<TA>::VN : 1;
-  constexpr int VPT = VECTOR ? 2 : 1;
-  constexpr int U = VECTOR ? 4 : 4;
-  const int64_t tile0 = (int64_t)blockIdx.x * 256 * VN * VPT;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
-  int64_t r1 = r0 + rows_per_block;
-  if (r1 > m) r1 = m;
-  ACC acc[VPT][VN];
-#pragma unroll
-  for (int v = 0; v < VPT; ++v)
-#pragma unroll
-    for (int e = 0; e < VN; ++e) acc[v][e] = 0;
-  int64_t col[VPT];
-  bool full[VPT], any = false;
-#pragma unroll
-  for (int v = 0; v < VPT; ++v) {
-    col[v] = tile0 + (int64_t)v * 256 * VN + (int64_t)threadIdx.x * VN;
-    full[v] = col[v] + VN <= n;
-    any = any || col[v] < n;
-  }
-  if (any) {
-    for (int64_t i = r0; i < r1; i += U) {
-      if (VECTOR) {
-        uint4 a[U][VPT];
-        ACC qv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const bool ok = i + u < r1;
-          qv[u] = ok ? (ACC)q[i + u] : (ACC)0;
-#pragma unroll
-          for (int v = 0; v < VPT; ++v)
-            a[u][v] = (ok && full[v]) ? ld_stream(A + (i + u) * lda + col[v]) : make_uint4(0, 0, 0, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-          for (int v = 0; v < VPT; ++v) {
-            ACC av[Pack<TA>::VN];
-            Pack<TA>::unpack(a[u][v], av);
-#pragma unroll
-            for (int e = 0; e < VN; ++e) acc[v][e] += av[e] * qv[u];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (i + u < r1) {
-            const ACC qi = (ACC)q[i + u];
-            const TA* row = A + (i + u) * lda;
-#pragma unroll
-            for (int v = 0; v < VPT; ++v)
-#pragma unroll
-              for (int e = 0; e < VN; ++e)
-                if (col[v] + e < n) acc[v][e] += to_acc(row[col[v] + e]) * qi;
-          }
-        }
-      }
-    }
-  }
-  ACC* out = part + (int64_t)blockIdx.y * ldpart;
-#pragma unroll
-  for (int v = 0; v < VPT; ++v)
-#pragma unroll
-    for (int e = 0; e < VN; ++e)
-      if (col[v] + e < n) out[col[v] + e] = acc[v][e];
-}
-
-// Phase 2: z[j] = sum_b part[b][j] - coef[cidx] * pprev[j]  (pprev may be null).
-template <typename ACC, typename TB>
-__global__ __launch_bounds__(256) void k_gemv_t_reduce(const ACC* __restrict__ part, int64_t ldpart,
-                                                       int nb, int64_t n, const TB* __restrict__ pprev,
-                                                       const double* __restrict__ coef, int cidx,
-                                                       double* __restrict__ z,
-                                                       const int* __restrict__ flag) {
-  if (flag != nullptr && flag[0] != 0) return;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int b = 0;
-  for (; b + 4 <= nb; b += 4) {
-    s0 += (double)part[(int64_t)b * ldpart + j];
-    s1 += (double)part[(int64_t)(b + 1) * ldpart + j];
-    s2 += (double)part[(int64_t)(b + 2) * ldpart + j];
-    s3 += (double)part[(int64_t)(b + 3) * ldpart + j];
-  }
-  for (; b < nb; ++b) s0 += (double)part[(int64_t)b * ldpart + j];
-  double s = (s0 + s1) + (s2 + s3);
-  if (pprev != nullptr) s -= coef[cidx] * (double)pprev[j];
-  z[j] = s;
-}
 
 // ---------------------------------------------------------------- CGS
 // hpart[c * ldh + j] = sum_{i in chunk c} V[j * ldv + i] x[i]  for j < t.
@@ -478,42 +216,138 @@ template <> struct V4<float> {
   __device__ __forceinline__ static int row(int lk, int v) { return 4 * lk + v; }
 };
 
-constexpr int GEMM_NT = 4;
+// Tall-skinny product C = A B with M >> K, N.  A block (4 waves) owns a
+// 64 x 64 tile of C; wave w computes rows [16w, 16w + 16) of it as four
+// 16 x 16 MFMA tiles.  K advances in chunks of GT_KC: the A chunk (64 rows x
+// GT_KC columns; each column slice is 64 contiguous elements, loaded 16 bytes
+// per lane) and the B chunk (GT_KC x 64) are staged in LDS; the next chunk's
+// loads are issued into registers before the MFMAs of the current one, so a
+// block keeps one chunk in flight while it computes.  (Measured on gfx950 at
+// 50000 x 120 x 50: this form beats both a 64-wide chunk and direct register
+// loads of A.)
+constexpr int GT_BM = 64, GT_BN = 64, GT_KC = 32;
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int E = 4;
+};
+template <> struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int E = 2;
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_tall(const T* __restrict__ A, int64_t lda, int64_t M, int K,
                                                    const T* __restrict__ B, int64_t ldb, int N,
-                                                   T* __restrict__ C, int64_t ldc) {
+                                                   T* __restrict__ C, int64_t ldc, int vec_a, int vec_c,
+                                                   int kchunk, int64_t cslice) {
   using VT = typename V4<T>::type;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  if (r0 >= M) return;
-  const int c0 = blockIdx.y * 16 * GEMM_NT;
+  using V16 = typename Vec16<T>::type;
+  constexpr int E = Vec16<T>::E;
+  constexpr int APAD = 64 / (int)sizeof(T);        // row padding of the LDS tiles
+  constexpr int GROUPS = GT_BM / E;                 // 16-byte groups per A column slice
+  constexpr int NA = GT_KC * GROUPS / 256;          // A vectors per thread per chunk
+  constexpr int NB = GT_KC * GT_BN / 256;           // B elements per thread per chunk
+  __shared__ __align__(16) T As[GT_KC][GT_BM + APAD];
+  __shared__ __align__(16) T Bs[GT_KC][GT_BN + APAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * GT_BM;
+  const int c0 = blockIdx.y * GT_BN;
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t arow = r0 + li;
-  VT acc[GEMM_NT];
+  // split-K: slice z sums k in [kb, ke) into its own copy of C
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  C += blockIdx.z * cslice;
+
+  V16 ra[NA];
+  T rb[NB];
+  auto load_chunk = [&](int k0) {
 #pragma unroll
-  for (int t = 0; t < GEMM_NT; ++t) acc[t] = VT{0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int kk = k0 + lk;
-    const T a = (arow < M && kk < K) ? A[(int64_t)kk * lda + arow] : (T)0;
+    for (int i = 0; i < NA; ++i) {
+      const int idx = tid + i * 256;
+      const int kk = idx / GROUPS, g = idx % GROUPS;
+      const int k = k0 + kk;
+      const int64_t row = r0 + g * E;
+      V16 v;
+      if (k < ke && vec_a && row + E <= M) {
+        v = *reinterpret_cast<const V16*>(A + (int64_t)k * lda + row);
+      } else {
 #pragma unroll
-    for (int t = 0; t < GEMM_NT; ++t) {
-      const int col = c0 + t * 16 + li;
-      const T b = (kk < K && col < N) ? B[(int64_t)col * ldb + kk] : (T)0;
-      acc[t] = mfma16(a, b, acc[t]);
+        for (int e = 0; e < E; ++e) v[e] = (k < ke && row + e < M) ? A[(int64_t)k * lda + row + e] : (T)0;
+      }
+      ra[i] = v;
     }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int idx = tid + i * 256;
+      const int c = idx / GT_KC, kk = idx % GT_KC;   // consecutive threads walk down a column of B
+      const int col = c0 + c, k = k0 + kk;
+      rb[i] = (col < N && k < ke) ? B[(int64_t)col * ldb + k] : (T)0;
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int idx = tid + i * 256;
+      const int kk = idx / GROUPS, g = idx % GROUPS;
+      *reinterpret_cast<V16*>(&As[kk][g * E]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int idx = tid + i * 256;
+      Bs[idx % GT_KC][idx / GT_KC] = rb[i];
+    }
+  };
+
+  VT acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = VT{0, 0, 0, 0};
+  load_chunk(kb);
+  for (int k0 = kb; k0 < ke; k0 += GT_KC) {
+    store_chunk();
+    __syncthreads();
+    if (k0 + GT_KC < ke) load_chunk(k0 + GT_KC);
+#pragma unroll
+    for (int ks = 0; ks < GT_KC; ks += 4) {
+      const T a = As[ks + lk][wave * 16 + li];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = mfma16(a, Bs[ks + lk][t * 16 + li], acc[t]);
+    }
+    __syncthreads();
   }
+
+  const int64_t rw = r0 + wave * 16;
 #pragma unroll
-  for (int t = 0; t < GEMM_NT; ++t) {
+  for (int t = 0; t < 4; ++t) {
     const int col = c0 + t * 16 + li;
-    if (col < N) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + V4<T>::row(lk, v);
-        if (row < M) C[(int64_t)col * ldc + row] = acc[t][v];
+    if (col >= N) continue;
+    T* cc = C + (int64_t)col * ldc;
+    if constexpr (sizeof(T) == 4) {
+      // float32 layout: lane (li, lk) holds rows 4 lk .. 4 lk + 3 of column li
+      const int64_t row = rw + 4 * lk;
+      if (vec_c && row + 4 <= M) {
+        *reinterpret_cast<v4f*>(cc + row) = acc[t];
+        continue;
       }
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = rw + V4<T>::row(lk, v);
+      if (row < M) cc[row] = acc[t][v];
+    }
   }
+}
+
+// C[col * ldc + row] = sum over s of P[s * M * N + col * M + row], in slice order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_slices(const T* __restrict__ P, int S, int64_t M, int N,
+                                                    T* __restrict__ C, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t col = e / M, row = e % M;
+  T acc = 0;
+  for (int s2 = 0; s2 < S; ++s2) acc += P[(int64_t)s2 * M * N + e];
+  C[col * ldc + row] = acc;
 }
 
 // ---------------------------------------------------------------- row-major GEMM
@@ -710,109 +544,6 @@ __global__ __launch_bounds__(256) void k_philox_start(double* __restrict__ q, in
 }
 
 // ================================================================ launchers
-static inline unsigned nblocks(int64_t work, int64_t per) { return (unsigned)((work + per - 1) / per); }
-
-template <typename TA, typename TB>
-hipError_t launch_gemv_n_t(const TA* A, int64_t lda, int64_t m, int64_t n, const TB* p, const TB* qprev,
-                           const double* coef, int cidx, double* w, const int* flag, hipStream_t st) {
-  constexpr int R = 4;
-  const bool vec = ((lda % Pack<TA>::VN) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
-  dim3 grid(nblocks(m, 4 * R));
-  if (vec)
-    hipLaunchKernelGGL((k_gemv_n<TA, TB, R, true>), grid, dim3(256), 0, st, A, lda, m, n, p, qprev, coef,
-                       cidx, w, flag);
-  else
-    hipLaunchKernelGGL((k_gemv_n<TA, TB, R, false>), grid, dim3(256), 0, st, A, lda, m, n, p, qprev, coef,
-                       cidx, w, flag);
-  return hipGetLastError();
-}
-
-int device_cus() {
-  static int cached = 0;
-  if (cached > 0) return cached;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-    cached = cus;
-  else
-    return 256;
-  return cached;
-}
-
-GemvTShape gemv_t_shape(int64_t m, int64_t n, int dtype_bytes) {
-  GemvTShape s;
-  const int vn = 16 / dtype_bytes;
-  s.col_tiles = nblocks(n, 256 * 2 * (int64_t)vn);
-  // Two blocks per compute unit in total (never more), so every CU streams
-  // the same amount: an extra partial wave of blocks would leave a tail.
-  int64_t want = (2 * (int64_t)device_cus()) / s.col_tiles;
-  int64_t maxnb = (m + 63) / 64;
-  if (want > maxnb) want = maxnb;
-  if (want > GEMV_T_MAX_BLOCKS) want = GEMV_T_MAX_BLOCKS;
-  if (want < 1) want = 1;
-  s.rows_per_block = (m + want - 1) / want;
-  s.nb = (int)((m + s.rows_per_block - 1) / s.rows_per_block);
-  return s;
-}
-
-template <typename TA, typename TB>
-hipError_t launch_gemv_t_t(const TA* A, int64_t lda, int64_t m, int64_t n, const TB* q, const TB* pprev,
-                           const double* coef, int cidx, double* z, void* part, int64_t ldpart,
-                           const int* flag, hipStream_t st) {
-  using ACC = typename Acc<TA>::type;
-  const bool vec = ((lda % Pack<TA>::VN) == 0) && ((n % Pack<TA>::VN) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  GemvTShape s = gemv_t_shape(m, n, (int)sizeof(TA));
-  ACC* pa = reinterpret_cast<ACC*>(part);
-  if (vec) {
-    dim3 grid(s.col_tiles, s.nb);
-    hipLaunchKernelGGL((k_gemv_t_part<TA, TB, true>), grid, dim3(256), 0, st, A, lda, m, n, q,
-                       s.rows_per_block, pa, ldpart, flag);
-  } else {
-    dim3 grid(nblocks(n, 256), s.nb);
-    hipLaunchKernelGGL((k_gemv_t_part<TA, TB, false>), grid, dim3(256), 0, st, A, lda, m, n, q,
-                       s.rows_per_block, pa, ldpart, flag);
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gemv_t_reduce<ACC, TB>), dim3(nblocks(n, 256)), dim3(256), 0, st, pa, ldpart, s.nb,
-                     n, pprev, coef, cidx, z, flag);
-  return hipGetLastError();
-}
-
-template <typename TB>
-hipError_t launch_gemv_n(const MatrixRef& A, const TB* p, const TB* qprev, const double* coef, int cidx,
-                         double* w, const int* flag, hipStream_t st) {
-  switch (A.dtype) {
-    case 0:
-      return launch_gemv_n_t<double, TB>((const double*)A.data, A.lda, A.m, A.n, p, qprev, coef, cidx, w,
-                                         flag, st);
-    case 1:
-      return launch_gemv_n_t<float, TB>((const float*)A.data, A.lda, A.m, A.n, p, qprev, coef, cidx, w,
-                                        flag, st);
-    default:
-      return launch_gemv_n_t<bf16, TB>((const bf16*)A.data, A.lda, A.m, A.n, p, qprev, coef, cidx, w,
-                                       flag, st);
-  }
-}
-
-template <typename TB>
-hipError_t launch_gemv_t(const MatrixRef& A, const TB* q, const TB* pprev, const double* coef, int cidx,
-                         double* z, void* part, int64_t ldpart, const int* flag, hipStream_t st) {
-  switch (A.dtype) {
-    case 0:
-      return launch_gemv_t_t<double, TB>((const double*)A.data, A.lda, A.m, A.n, q, pprev, coef, cidx, z,
-                                         part, ldpart, flag, st);
-    case 1:
-      return launch_gemv_t_t<float, TB>((const float*)A.data, A.lda, A.m, A.n, q, pprev, coef, cidx, z,
-                                        part, ldpart, flag, st);
-    default:
-      return launch_gemv_t_t<bf16, TB>((const bf16*)A.data, A.lda, A.m, A.n, q, pprev, coef, cidx, z,
-                                       part, ldpart, flag, st);
-  }
-}
-
 int dots_chunks(int64_t len) { return (int)nblocks(len, 64 * DE); }
 int update_blocks(int64_t len) { return (int)nblocks(len, UROWS); }
 
@@ -869,10 +600,45 @@ template <typename T>
 hipError_t launch_gemm_tall(const T* A, int64_t lda, int64_t M, int K, const T* B, int64_t ldb, int N, T* C,
                             int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid(nblocks(M, 64), nblocks(N, 16 * GEMM_NT));
-  hipLaunchKernelGGL((k_gemm_tall<T>), grid, dim3(256), 0, st, A, lda, M, K, B, ldb, N, C, ldc);
+  dim3 grid(nblocks(M, GT_BM), nblocks(N, GT_BN));
+  // 16-byte accesses need 16-byte aligned column starts
+  const int vec_a = (lda % (16 / (int64_t)sizeof(T)) == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
+  const int vec_c = (ldc % (16 / (int64_t)sizeof(T)) == 0) && (reinterpret_cast<uintptr_t>(C) % 16 == 0);
+  hipLaunchKernelGGL((k_gemm_tall<T>), grid, dim3(256), 0, st, A, lda, M, K, B, ldb, N, C, ldc, vec_a, vec_c,
+                     K, (int64_t)0);
   return hipGetLastError();
 }
+
+GemmSplit gemm_split(int64_t M, int64_t K, int N) {
+  GemmSplit g;
+  const int64_t tiles = nblocks(M, GT_BM) * nblocks(N, GT_BN);
+  int64_t want = (2 * (int64_t)device_cus()) / std::max<int64_t>(tiles, 1);
+  want = std::max<int64_t>(1, std::min<int64_t>({want, nblocks(K, GT_KC), 1024}));
+  const int64_t chunk = nblocks(nblocks(K, want), GT_KC) * GT_KC;
+  g.kchunk = (int)std::max<int64_t>(chunk, GT_KC);
+  g.slices = (int)std::max<int64_t>(1, nblocks(K, g.kchunk));
+  return g;
+}
+
+template <typename T>
+hipError_t launch_gemm_tall_splitk(const T* A, int64_t lda, int64_t M, int K, const T* B, int64_t ldb, int N,
+                                   T* C, int64_t ldc, T* partial, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const GemmSplit g = gemm_split(M, K, N);
+  if (g.slices == 1) return launch_gemm_tall<T>(A, lda, M, K, B, ldb, N, C, ldc, st);
+  dim3 grid(nblocks(M, GT_BM), nblocks(N, GT_BN), g.slices);
+  const int vec_a = (lda % (16 / (int64_t)sizeof(T)) == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
+  const int vec_c = (M % (16 / (int64_t)sizeof(T)) == 0) && (reinterpret_cast<uintptr_t>(partial) % 16 == 0);
+  hipLaunchKernelGGL((k_gemm_tall<T>), grid, dim3(256), 0, st, A, lda, M, K, B, ldb, N, partial, M, vec_a, vec_c,
+                     g.kchunk, M * (int64_t)N);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sum_slices<T>), dim3(nblocks(M * (int64_t)N, 256)), dim3(256), 0, st, partial, g.slices, M, N,
+                     C, ldc);
+  return hipGetLastError();
+}
+template hipError_t launch_gemm_tall_splitk<float>(const float*, int64_t, int64_t, int, const float*, int64_t, int,
+                                                   float*, int64_t, float*, hipStream_t);
 
 hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t m, int64_t n, uint16_t* dst, int64_t ldd,
                             hipStream_t st) {
@@ -918,10 +684,6 @@ hipError_t launch_philox_start(double* q, int64_t m, uint64_t seed, hipStream_t 
 
 // explicit instantiations for the two basis types
 #define GKB_INST(TB)                                                                                      \
-  template hipError_t launch_gemv_n<TB>(const MatrixRef&, const TB*, const TB*, const double*, int,       \
-                                        double*, const int*, hipStream_t);                                \
-  template hipError_t launch_gemv_t<TB>(const MatrixRef&, const TB*, const TB*, const double*, int,       \
-                                        double*, void*, int64_t, const int*, hipStream_t);                \
   template hipError_t launch_dots<TB>(const TB*, int64_t, int, int64_t, const double*, double*, int,      \
                                       double*, const int*, hipStream_t);                                  \
   template hipError_t launch_update<TB>(const TB*, int64_t, int, int64_t, double*, const double*,         \

@@ -14,6 +14,7 @@
 // Adam.  Every reduction has a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(256) void k_to_double(const float* __restrict__ z, 
 
 // workspace layout for loss_grad / start vector
 struct MlpWs {
-  size_t z, dz, DH, H, stats, G1, G2, total;
+  size_t z, dz, DH, H, stats, G1, G2, Gpart, total;
   int hld;
 };
 
@@ -250,6 +251,9 @@ MlpWs mlp_ws(int64_t m, int hidden, int r) {
   w.stats = take((size_t)(r + 1) * 8);
   w.G1 = take((size_t)XLD * hidden * 4);
   w.G2 = take((size_t)w.hld * 4);
+  // split-K partial sums of the two gradient products (reused one after the other)
+  const GemmSplit s1 = gemm_split(XLD, m, hidden), s2 = gemm_split(w.hld, m, 1);
+  w.Gpart = take(std::max((size_t)s1.slices * XLD * hidden, (size_t)s2.slices * w.hld) * 4);
   w.total = off;
   return w;
 }
@@ -343,9 +347,10 @@ gkb_status gkb_mlp_loss_grad(const float* params, int in, int hidden, const floa
   hipLaunchKernelGGL(k_mlp_bwd_rows, dim3(nblk(m, 256)), dim3(256), 0, st, params, in, hidden, X, m, z, Ut, r, stats,
                      dz, DH, loss);
   L_HIP(hipGetLastError());
-  // G1 = X^T DH (XLD x hidden), G2 = H^T dz (hld x 1): sums over the rows on MFMA
-  L_HIP(launch_gemm_tall<float>(X, XLD, XLD, (int)m, DH, m, hidden, G1, XLD, st));
-  L_HIP(launch_gemm_tall<float>(H, w.hld, w.hld, (int)m, dz, m, 1, G2, w.hld, st));
+  // G1 = X^T DH (XLD x hidden), G2 = H^T dz (hld x 1): sums over the rows on MFMA, split over row ranges
+  float* Gpart = reinterpret_cast<float*>(b + w.Gpart);
+  L_HIP(launch_gemm_tall_splitk<float>(X, XLD, XLD, (int)m, DH, m, hidden, G1, XLD, Gpart, st));
+  L_HIP(launch_gemm_tall_splitk<float>(H, w.hld, w.hld, (int)m, dz, m, 1, G2, w.hld, Gpart, st));
   const int64_t P = gkb_mlp_param_count(in, hidden);
   hipLaunchKernelGGL(k_pack_grad, dim3(nblk(P, 256)), dim3(256), 0, st, G1, G2, in, hidden, grad);
   L_HIP(hipGetLastError());

@@ -71,16 +71,25 @@ def test_matvec(dtype, shape, pad):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("MKN", [(1000, 30, 10), (20000, 121, 50), (17, 5, 3), (333, 64, 64), (64, 1, 100),
-                                 (5000, 86, 85)])
-def test_gemm_tall(dtype, MKN):
+@pytest.mark.parametrize("MKN,pad", [((1000, 30, 10), 0), ((20000, 121, 50), 0), ((17, 5, 3), 0),
+                                     ((333, 64, 64), 0), ((64, 1, 100), 0), ((5000, 86, 85), 0),
+                                     ((50000, 121, 50), 48), ((4099, 200, 13), 5), ((130, 33, 129), 3),
+                                     ((1001, 0, 4), 0)])
+def test_gemm_tall(dtype, MKN, pad):
+    """Against a float64 product; several 64 x 64 tiles, ragged M, K and N, K
+    across several 32-wide chunks, padded leading dimensions (unaligned ones take
+    the element-wise path) and K = 0."""
+    import torch
     device()
     M, K, N = MKN
-    banner(f"gemm {dtype.__name__} {MKN}")
+    banner(f"gemm {dtype.__name__} {MKN} pad={pad}")
     rng = np.random.default_rng(M + K + N)
     At = rng.standard_normal((K, M)).astype(dtype)  # column-major M x K
     Bt = rng.standard_normal((N, K)).astype(dtype)  # column-major K x N
-    Ct = to_host(gkb.gkb_gemm_tall(to_dev(At), to_dev(Bt)))  # (N, M)
+    Ad = torch.zeros((K, M + pad), dtype=torch.float64 if dtype == np.float64 else torch.float32,
+                     device="cuda:0")
+    Ad[:, :M] = to_dev(At)
+    Ct = to_host(gkb.gkb_gemm_tall(Ad[:, :M], to_dev(Bt)))  # (N, M)
     ref = (At.T.astype(np.float64) @ Bt.T.astype(np.float64)).T
     u = U64 if dtype == np.float64 else U32
     bound = K * u * (np.abs(Bt.astype(np.float64)) @ np.abs(At.astype(np.float64))) + 1e-300

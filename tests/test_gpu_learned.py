@@ -23,11 +23,14 @@ def _setup(m=3000, ws=32, r=30, hidden=256, seed=0):
     return S, Up, U, params, n_in, hidden
 
 
-def test_features_forward_loss_grad_adam_vs_oracle():
+@pytest.mark.parametrize("m", [1001, 3000, 20000])
+def test_features_forward_loss_grad_adam_vs_oracle(m):
+    """m = 20000 is the drifting sequence's row count; 1001 gives a ragged last
+    row range in the split-K gradient products."""
     import torch
     device()
-    banner("learned: features/forward/loss/grad/adam vs oracle")
-    S, Up, U, params, n_in, hidden = _setup()
+    banner(f"learned: features/forward/loss/grad/adam vs oracle m={m}")
+    S, Up, U, params, n_in, hidden = _setup(m=m)
     m = S.shape[0]
     X = gkb.gkb_mlp_features(to_dev(np.ascontiguousarray(S.T)), to_dev(np.ascontiguousarray(Up.T)))
     Xh = to_host(X)
