@@ -10,15 +10,26 @@ namespace gkb {
 constexpr int BATCH_KMAX = 64;  // largest Krylov dimension of a batched problem
 
 struct BatchProblem {
-  const float* A;     // row-major m x n, float32
+  const float* A;     // row-major m x n, float32 (the caller's, or its staged copy)
   int64_t lda;
   int m, n, r, k, l;  // rows, columns, wanted triplets, Krylov dimension, restart size
   int index;          // position in the caller's arrays
+  int ldq, ldp;       // column strides of the Q and P bases (multiples of 4)
+  int padded;         // 1: A is a staged copy whose rows are zero-padded to a multiple of 4
   int64_t offQ, offP; // float offsets of the two Q and two P buffers in the pool
   int64_t offW;       // double offset of w (m) and z (n) in the work area
   int64_t offU, offV; // float offsets of U (m x r) and V (n x r) in the outputs
   int64_t offS;       // double offset of sigma (r)
   int64_t offQ1;      // double offset of this problem's start vector in q1 (if given)
+};
+
+// One matrix to stage: rows [row_start, row_start + m) of the flattened row
+// range; src (lds) -> dst (ldd = 4 ceil(n / 4), zero padding).
+struct StageCopy {
+  const float* src;
+  float* dst;
+  int64_t lds, ldd, row_start;
+  int m, n;
 };
 
 struct BatchParams {
@@ -39,6 +50,9 @@ struct BatchParams {
   int max_restarts;
   int check_every;
   int relative;
+  const StageCopy* stage;  // matrices copied to aligned rows before the solves
+  int nstage;
+  int64_t stage_rows;
 };
 
 // threads per workgroup: 512 or 1024

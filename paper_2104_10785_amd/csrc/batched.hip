@@ -10,6 +10,7 @@
 // depend on which workgroup solved it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "batched.h"
@@ -121,10 +122,14 @@ template <int BT>
 __device__ void bgemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z,
                         Lds<BT>& L) {
   const int tid = threadIdx.x;
-  const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) && ((P.n & 3) == 0);
+  // 16-byte loads need aligned rows; columns n .. 4 ceil(n / 4) - 1 must be
+  // readable (the plan stages every matrix that does not satisfy this)
+  const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) &&
+                   (((P.n & 3) == 0) || P.padded);
   const int VN = vec ? 4 : 1;
   const int ncg = (P.n + VN - 1) / VN;
-  const int G = ncg >= BT ? 1 : BT / ncg;  // G * n <= 4 * BT
+  const int npad = ncg * VN;               // row stride of the partial sums
+  const int G = ncg >= BT ? 1 : BT / ncg;  // G * npad <= 4 * BT
   const int g = ncg >= BT ? 0 : tid / ncg;
   for (int cg = ncg >= BT ? tid : tid % ncg; cg < ncg && g < G; cg += (ncg >= BT ? BT : ncg)) {
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -161,17 +166,17 @@ __device__ void bgemv_t(const BatchProblem& P, const float* q, const float* ppre
     if (ncg >= BT) {
       for (int e = 0; e < VN; ++e) {
         const int j = cg * VN + e;
-        z[j] = (double)acc[e] - (pprev ? c * (double)pprev[j] : 0.0);
+        if (j < P.n) z[j] = (double)acc[e] - (pprev ? c * (double)pprev[j] : 0.0);
       }
     } else {
-      for (int e = 0; e < VN; ++e) L.tpart[g * P.n + cg * VN + e] = acc[e];
+      for (int e = 0; e < VN; ++e) L.tpart[g * npad + cg * VN + e] = acc[e];
     }
   }
   __syncthreads();
   if (ncg < BT) {
     for (int j = tid; j < P.n; j += BT) {
       double s = 0.0;
-      for (int gg = 0; gg < G; ++gg) s += (double)L.tpart[gg * P.n + j];
+      for (int gg = 0; gg < G; ++gg) s += (double)L.tpart[gg * npad + j];
       z[j] = s - (pprev ? c * (double)pprev[j] : 0.0);
     }
     __syncthreads();
@@ -389,14 +394,15 @@ __device__ double philox_normal(int64_t i, uint64_t seed) {
 template <int BT>
 __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>& L) {
   const int tid = threadIdx.x;
-  float* Qb[2] = {prm.pool + P.offQ, prm.pool + P.offQ + (int64_t)(P.k + 1) * P.m};
-  float* Pb[2] = {prm.pool + P.offP, prm.pool + P.offP + (int64_t)(P.k + 1) * P.n};
+  const int ldq = P.ldq, ldp = P.ldp;   // basis column strides (multiples of 4: 16-byte aligned columns)
+  float* Qb[2] = {prm.pool + P.offQ, prm.pool + P.offQ + (int64_t)(P.k + 1) * ldq};
+  float* Pb[2] = {prm.pool + P.offP, prm.pool + P.offP + (int64_t)(P.k + 1) * ldp};
   double* w = prm.work + P.offW;
   double* z = w + P.m;
   const int m = P.m, n = P.n, k = P.k, r = P.r, l = P.l;
   int cur = 0;
-  auto Qc = [&](int j) { return Qb[cur] + (int64_t)j * m; };
-  auto Pc = [&](int j) { return Pb[cur] + (int64_t)j * n; };
+  auto Qc = [&](int j) { return Qb[cur] + (int64_t)j * ldq; };
+  auto Pc = [&](int j) { return Pb[cur] + (int64_t)j * ldp; };
   const double eps = prm.eps_break;
   double sig = 0.0;  // running largest accepted coefficient / Ritz value
   int64_t matvecs = 0;
@@ -444,10 +450,10 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
         bgemv_n<BT>(P, Pc(j), Qc(j), L.pc[j], w);
       } else {
         bgemv_n<BT>(P, Pc(j), j == l ? nullptr : Qc(j - 1), j == l ? 0.0 : L.pc[j], w);
-        if (j == l) bupdate(Qc(0), m, l, m, w, L.rho, L);
+        if (j == l) bupdate(Qc(0), ldq, l, m, w, L.rho, L);
       }
       ++matvecs;
-      ss = bcgs2(Qc(0), m, qi, m, w, L);
+      ss = bcgs2(Qc(0), ldq, qi, m, w, L);
       if (!bnormalize(w, m, ss, prm.relative ? eps * sig : eps, Qc(qi), 1, qi, L)) break;
       const double beta = sqrt(ss);
       if (tid == 0) L.qc[qi] = beta;
@@ -455,7 +461,7 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
       // p side
       bgemv_t(P, Qc(qi), Pc(j), beta, z, L);
       ++matvecs;
-      ss = bcgs2(Pc(0), n, j + 1, n, z, L);
+      ss = bcgs2(Pc(0), ldp, j + 1, n, z, L);
       if (!bnormalize(z, n, ss, prm.relative ? eps * sig : eps, Pc(j + 1), 2, j + 1, L)) break;
       const double alpha = sqrt(ss);
       if (tid == 0) L.pc[j + 1] = alpha;
@@ -574,9 +580,9 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
     sig = fmax(sig, s0);
     const int nb = 1 - cur;
     // P~ = P Y_l (Y = Vs, columns by perm), Q~ = Q X_l (X = Hs normalised)
-    bgemm_small<BT>(Pb[cur], n, n, np, L.Vs, KMAX, L.perm, l, Pb[nb], n);
-    bgemm_small<BT>(Qb[cur], m, m, nq, L.Hs, HLD, L.perm, l, Qb[nb], m);
-    for (int i = tid; i < n; i += BT) Pb[nb][(int64_t)l * n + i] = Pb[cur][(int64_t)np * n + i];
+    bgemm_small<BT>(Pb[cur], ldp, n, np, L.Vs, KMAX, L.perm, l, Pb[nb], ldp);
+    bgemm_small<BT>(Qb[cur], ldq, m, nq, L.Hs, HLD, L.perm, l, Qb[nb], ldq);
+    for (int i = tid; i < n; i += BT) Pb[nb][(int64_t)l * ldp + i] = Pb[cur][(int64_t)np * ldp + i];
     if (tid < l) {
       L.sres[tid] = L.sv[L.perm[tid]];
       L.rho[tid] = alpha_res * L.Hs[L.perm[tid] * HLD + nq - 1];
@@ -596,8 +602,8 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
   if (status == 0 && np > 0) {
     float* U = prm.U + P.offU;
     float* V = prm.V + P.offV;
-    bgemm_small<BT>(Pb[cur], n, n, np, L.Vs, KMAX, L.perm, r_eff, V, n);
-    bgemm_small<BT>(Qb[cur], m, m, nq, L.Hs, HLD, L.perm, r_eff, U, m);
+    bgemm_small<BT>(Pb[cur], ldp, n, np, L.Vs, KMAX, L.perm, r_eff, V, n);
+    bgemm_small<BT>(Qb[cur], ldq, m, nq, L.Hs, HLD, L.perm, r_eff, U, m);
     if (tid < r) prm.sigma[P.offS + tid] = tid < r_eff ? L.sv[L.perm[tid]] : 0.0;
   } else if (tid < r) {
     prm.sigma[P.offS + tid] = 0.0;
@@ -637,12 +643,41 @@ __global__ void k_batched_reset(int* counter) {
   if (threadIdx.x == 0) *counter = 0;
 }
 
+// Copy the matrices listed in the stage table into 16-byte aligned rows of
+// 4 ceil(n / 4) floats with zero padding: one wave per row, rows of all
+// entries numbered consecutively (row_start is the prefix sum of m).
+__global__ __launch_bounds__(256) void k_batched_stage(const StageCopy* __restrict__ tab, int ntab,
+                                                        int64_t total_rows) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < total_rows; row += nwaves) {
+    int lo = 0, hi = ntab - 1;  // last entry with row_start <= row
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab[mid].row_start <= row) lo = mid;
+      else hi = mid - 1;
+    }
+    const StageCopy& t = tab[lo];
+    const int64_t i = row - t.row_start;
+    const float* src = t.src + i * t.lds;
+    float* dst = t.dst + i * t.ldd;
+    for (int j = lane; j < t.ldd; j += 64) dst[j] = j < t.n ? src[j] : 0.f;
+  }
+}
+
 size_t batched_lds_bytes(int threads) { return threads == 512 ? sizeof(Lds<512>) : sizeof(Lds<1024>); }
 
 hipError_t launch_batched(const BatchParams& prm, int grid, int threads, hipStream_t st) {
   hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(64), 0, st, prm.counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (prm.nstage > 0) {
+    const int64_t blocks = std::min<int64_t>((prm.stage_rows + 3) / 4, 8192);
+    hipLaunchKernelGGL(k_batched_stage, dim3((unsigned)blocks), dim3(256), 0, st, prm.stage, prm.nstage,
+                       prm.stage_rows);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (threads == 512)
     hipLaunchKernelGGL(k_batched_gk<512>, dim3(grid), dim3(512), sizeof(Lds<512>), st, prm);
   else

@@ -1,5 +1,6 @@
 // C ABI of the batched form: plan (problem table, largest-first order,
-// hipGraph of [queue reset, persistent solver]), run, results.
+// hipGraph of [queue reset, staging copy of unaligned matrices, persistent
+// solver]), run, results.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,9 +33,19 @@ gkb_status bfail(gkb_status s, const std::string& m) {
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t problems = 0, order = 0, counter = 0, info = 0, pool = 0, work = 0, total = 0;
-  size_t pool_floats = 0, work_doubles = 0;
+  size_t problems = 0, order = 0, counter = 0, info = 0, pool = 0, work = 0, stage_tab = 0, stage = 0, total = 0;
+  size_t pool_floats = 0, work_doubles = 0, stage_floats = 0;
+  int nstage = 0;
 };
+
+inline int64_t round4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
+// The persistent kernel streams A with 16-byte loads; a matrix whose rows are
+// not 16-byte aligned, or whose column count is not a multiple of 4, is first
+// copied (inside the same graph) into zero-padded rows of round4(n) floats.
+bool needs_stage(const gkb_matrix& A) {
+  return (A.lda & 3) != 0 || (A.n & 3) != 0 || (reinterpret_cast<uintptr_t>(A.data) & 15) != 0;
+}
 
 gkb_status check_batch(int batch, const gkb_matrix* As, const int* r, const int* k) {
   if (batch < 1) return bfail(GKB_ERR_INVALID, "need batch >= 1");
@@ -65,11 +76,17 @@ Layout layout(int batch, const gkb_matrix* As, const int* k) {
   L.counter = take(sizeof(int));
   L.info = take(sizeof(int) * 4 * batch);
   for (int i = 0; i < batch; ++i) {
-    L.pool_floats += (size_t)2 * (k[i] + 1) * (As[i].m + As[i].n);
+    L.pool_floats += (size_t)2 * (k[i] + 1) * (round4(As[i].m) + round4(As[i].n));
     L.work_doubles += (size_t)(As[i].m + As[i].n);
+    if (needs_stage(As[i])) {
+      ++L.nstage;
+      L.stage_floats += a256((size_t)As[i].m * round4(As[i].n) * sizeof(float)) / sizeof(float);
+    }
   }
   L.pool = take(L.pool_floats * sizeof(float));
   L.work = take(L.work_doubles * sizeof(double));
+  L.stage_tab = take(sizeof(gkb::StageCopy) * std::max(L.nstage, 1));
+  L.stage = take(L.stage_floats * sizeof(float));
   L.total = off;
   return L;
 }
@@ -131,20 +148,41 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   auto* plan = new gkb_batch_plan_s();
   plan->batch = batch;
   plan->table.resize(batch);
-  int64_t offQ = 0, offW = 0, offU = 0, offV = 0, offS = 0, offQ1 = 0;
+  int64_t offQ = 0, offW = 0, offU = 0, offV = 0, offS = 0, offQ1 = 0, offStage = 0, stage_rows = 0;
+  std::vector<gkb::StageCopy> stage;
+  float* stage_base = reinterpret_cast<float*>(ws + L.stage);
   for (int i = 0; i < batch; ++i) {
     gkb::BatchProblem& P = plan->table[i];
     P.A = reinterpret_cast<const float*>(As[i].data);
     P.lda = As[i].lda;
     P.m = (int)As[i].m;
     P.n = (int)As[i].n;
+    P.padded = 0;
+    if (needs_stage(As[i])) {
+      gkb::StageCopy c;
+      c.src = P.A;
+      c.lds = P.lda;
+      c.m = P.m;
+      c.n = P.n;
+      c.ldd = round4(P.n);
+      c.dst = stage_base + offStage;
+      c.row_start = stage_rows;
+      stage.push_back(c);
+      stage_rows += P.m;
+      offStage += (int64_t)(a256((size_t)P.m * c.ldd * sizeof(float)) / sizeof(float));
+      P.A = c.dst;
+      P.lda = c.ldd;
+      P.padded = 1;
+    }
     P.r = r[i];
     P.k = k[i];
     P.l = std::min(r[i] + (k[i] - r[i]) / 2, k[i] - 1);
     P.index = i;
+    P.ldq = (int)round4(P.m);
+    P.ldp = (int)round4(P.n);
     P.offQ = offQ;
-    P.offP = offQ + (int64_t)2 * (k[i] + 1) * P.m;
-    offQ = P.offP + (int64_t)2 * (k[i] + 1) * P.n;
+    P.offP = offQ + (int64_t)2 * (k[i] + 1) * P.ldq;
+    offQ = P.offP + (int64_t)2 * (k[i] + 1) * P.ldp;
     P.offW = offW;
     offW += P.m + P.n;
     P.offU = offU;
@@ -183,6 +221,9 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   prm.max_restarts = max_restarts;
   prm.check_every = opt.check_every;
   prm.relative = opt.eps_relative ? 1 : 0;
+  prm.stage = reinterpret_cast<const gkb::StageCopy*>(ws + L.stage_tab);
+  prm.nstage = (int)stage.size();
+  prm.stage_rows = stage_rows;
   plan->info_dev = prm.info;
   auto cleanup = [&](gkb_status s) {
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
@@ -195,6 +236,8 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
                      hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(ws + L.order, plan->order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, st) !=
           hipSuccess ||
+      (!stage.empty() && hipMemcpyAsync(ws + L.stage_tab, stage.data(), sizeof(gkb::StageCopy) * stage.size(),
+                                        hipMemcpyHostToDevice, st) != hipSuccess) ||
       hipStreamSynchronize(st) != hipSuccess)
     return cleanup(bfail(GKB_ERR_HIP, "uploading the problem table failed"));
   if (gkb::batched_setup() != hipSuccess) return cleanup(bfail(GKB_ERR_HIP, "cannot set the LDS size"));
