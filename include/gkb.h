@@ -54,7 +54,8 @@ typedef enum {
   GKB_ERR_INVALID = -1,      /* bad argument (see gkb_last_error)             */
   GKB_ERR_HIP = -2,          /* a HIP runtime call failed                     */
   GKB_ERR_NUMERIC = -3,      /* NaN or Inf appeared in a norm                 */
-  GKB_ERR_WORKSPACE = -4     /* workspace missing, too small or misaligned    */
+  GKB_ERR_WORKSPACE = -4,    /* workspace missing, too small or misaligned    */
+  GKB_ERR_TIMEOUT = -5       /* batched form: a team barrier waited too long  */
 } gkb_status;
 
 typedef enum {

@@ -4,12 +4,18 @@
  * Each problem is the restarted partial SVD of gkb.h (Golub-Kahan
  * bidiagonalization, eq. (2.1)-(2.4) of the paper, Ritz triplets as in
  * Algorithm 2, thick restart and the same convergence rule), but the whole
- * solve of a problem runs inside one workgroup: products, two Gram-Schmidt
- * passes, the small SVD of the projected matrix (one-sided Jacobi in LDS,
- * float64), restarts and Ritz vectors.  A persistent grid takes problems from
- * an atomic queue, largest (m * n * k) first.  The queue reset and the solver
- * are captured once into a hipGraph per plan and replayed by
- * gkb_batched_plan_run.
+ * solve of a problem runs inside one workgroup -- or, for a problem whose
+ * cost m * n * k exceeds half of the average per-workgroup share of the batch,
+ * inside a team of up to max_team workgroups that split its rows and columns
+ * and meet at bounded team barriers: products, two Gram-Schmidt passes, the
+ * small SVD of the projected matrix (one-sided Jacobi in LDS, float64),
+ * restarts and Ritz vectors.  A persistent grid takes (problem, member)
+ * tickets from an atomic queue, largest per-member cost first.  Matrices
+ * whose rows are not 16-byte aligned or whose n is not a multiple of 4 are
+ * first copied into zero-padded rows inside the workspace.  The queue reset,
+ * the copy and the solver are captured once into a hipGraph per plan and
+ * replayed by gkb_batched_plan_run.  A team barrier that waits too long
+ * (about 10 s) ends that problem with info status GKB_ERR_TIMEOUT.
  *
  * Problems: GKB_F32, row-major, device pointers, 1 <= r <= k <= min(m, n),
  * k <= 64.  Outputs are packed in problem order:
@@ -40,6 +46,8 @@ typedef struct {
   int no_graph;             /* 1: gkb_batched_plan_run launches directly instead of */
                             /*    replaying the captured graph                      */
   int threads;              /* workgroup size, 512 or 1024; 0 = 1024               */
+  int max_team;             /* largest team of workgroups on one problem (1..8);   */
+                            /*    0 = 8, 1 = every problem on one workgroup         */
 } gkb_batch_options;
 
 typedef struct gkb_batch_plan_s* gkb_batch_plan;

@@ -8,6 +8,7 @@
 namespace gkb {
 
 constexpr int BATCH_KMAX = 64;  // largest Krylov dimension of a batched problem
+constexpr int BATCH_TEAM_NMAX = 4096;  // largest n of a problem solved by a team of workgroups
 
 struct BatchProblem {
   const float* A;     // row-major m x n, float32 (the caller's, or its staged copy)
@@ -16,6 +17,9 @@ struct BatchProblem {
   int index;          // position in the caller's arrays
   int ldq, ldp;       // column strides of the Q and P bases (multiples of 4)
   int padded;         // 1: A is a staged copy whose rows are zero-padded to a multiple of 4
+  int team;           // workgroups solving this problem together (1 = alone)
+  int team_id;        // index of its barrier counter (teams of more than one)
+  int64_t offTeam;    // double offset of its team buffers: T x n partial products, 2 x T x (KMAX + 4) dots
   int64_t offQ, offP; // float offsets of the two Q and two P buffers in the pool
   int64_t offW;       // double offset of w (m) and z (n) in the work area
   int64_t offU, offV; // float offsets of U (m x r) and V (n x r) in the outputs
@@ -34,9 +38,11 @@ struct StageCopy {
 
 struct BatchParams {
   const BatchProblem* problems;
-  const int* order;   // solve order (largest first)
+  const int* order;   // ticket -> problem (largest per-member cost first, a team's tickets adjacent)
+  const int* member;  // ticket -> member index within the problem's team
   int* counter;       // work-queue head
   int batch;
+  int ntickets;
   float* pool;
   double* work;
   float* U;
@@ -53,6 +59,9 @@ struct BatchParams {
   const StageCopy* stage;  // matrices copied to aligned rows before the solves
   int nstage;
   int64_t stage_rows;
+  int* team_cnt;           // barrier counters, one per team (zeroed before each run)
+  int nteams;
+  double* team_buf;        // team reduction buffers
 };
 
 // threads per workgroup: 512 or 1024

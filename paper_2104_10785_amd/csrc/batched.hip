@@ -1,18 +1,26 @@
 // Batched partial SVD: many small, uneven problems in one persistent launch.
 //
-// One workgroup (BT threads) solves one problem at a time end to end -- the
-// Golub-Kahan recurrences of eq. (2.1)-(2.2) with CGS2 reorthogonalisation,
-// the small SVD of the projected matrix (one-sided Jacobi in LDS, float64),
-// the convergence test, thick restarts and the Ritz vectors V = P Y, U = Q X
-// (Algorithm 2) -- then takes the next problem from an atomic queue ordered
-// largest-first.  Every wave of the grid reaches the queue's end, so the grid
-// drains; all reductions have a fixed order, so a problem's result does not
-// depend on which workgroup solved it.
+// A problem is solved end to end -- the Golub-Kahan recurrences of
+// eq. (2.1)-(2.2) with CGS2 reorthogonalisation, the small SVD of the
+// projected matrix (one-sided Jacobi in LDS, float64), the convergence test,
+// thick restarts and the Ritz vectors V = P Y, U = Q X (Algorithm 2) -- by a
+// team of T workgroups (T = 1 for most problems).  Member j of a team owns
+// rows [j m / T, (j + 1) m / T) of A, Q, w and U and entries
+// [j n / T, (j + 1) n / T) of P, z and V; the partial sums of the products
+// and of the Gram-Schmidt dots meet in a per-team buffer and are added in
+// member order after a team barrier, so every member holds the same
+// coefficients and takes the same decisions (and runs the same small SVD).
+// Workgroups take (problem, member) tickets from an atomic queue ordered by
+// per-member cost, largest first.  Every wait is bounded; every wave of the
+// grid reaches the queue's end, so the grid drains; all reductions have a
+// fixed order, so a result does not depend on which workgroups solved it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
+#include "../../include/gkb.h"
 #include "batched.h"
 
 namespace gkb {
@@ -21,6 +29,25 @@ namespace {
 
 constexpr int KMAX = BATCH_KMAX;   // max Krylov dimension
 constexpr int HLD = KMAX + 2;      // LDS leading dimension of H columns
+constexpr int SLD = KMAX + 4;      // per-member stride of the small team reduction buffers
+// Bound on the polls of a team barrier (each poll sleeps ~100 cycles and
+// reads the counter from memory): about 10 s, far beyond any legitimate wait.
+constexpr long TEAM_SPIN_LIMIT = 1L << 23;
+
+// Pointers taken from the problem table are generic; the hot loops cast them
+// to the global (or LDS) address space so that the compiler emits global
+// loads with a scalar base instead of flat loads.
+#define GMEM __attribute__((address_space(1)))
+#define LMEM __attribute__((address_space(3)))
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ const GMEM T* gc(const T* p) {
+  return (const GMEM T*)p;
+}
+template <typename T>
+__device__ __forceinline__ GMEM T* gw(T* p) {
+  return (GMEM T*)p;
+}
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -41,13 +68,17 @@ struct Lds {
   double Hs[KMAX * HLD];       // projected matrix, column-major (col j at Hs + j*HLD)
   double Vs[KMAX * KMAX];      // right rotations (col j at Vs + j*KMAX)
   double sv[KMAX];             // column norms after Jacobi (sorted via perm)
+  double scal;                 // team-reduced scalar
   float tpart[4 * BT];         // gemv_t row-group partial sums
+  float pvec[BATCH_TEAM_NMAX]; // a team's current p (read from the coherence point)
   int perm[KMAX];
   int ord[KMAX + 1];
   int rotated;
   int problem;
+  int member;
   int flag;                    // breakdown: 0 none, 1 beta, 2 alpha, 3 numeric
   int flag_idx;
+  int team_fail;               // a team barrier timed out
 };
 
 // Block-wide sum in a fixed order (all threads get the result).
@@ -66,19 +97,108 @@ __device__ double block_sum(double v, Lds<BT>& L) {
   return t;
 }
 
-// w = A p - c * qprev  (qprev may be null); each wave owns 4 rows at a time,
-// lanes stride the columns with 16-byte loads (4 rows x 2 vectors in flight).
+// ---------------------------------------------------------------- teams
+struct Team {
+  int T, member;
+  int* cnt;        // arrivals at this team's barriers (zeroed before the launch)
+  double* zpart;   // T x n partial sums of A^T q
+  double* small;   // 2 x T x SLD partial dots / norms (alternating regions)
+  int nbar;        // barriers this member has passed
+  int parity;
+};
+
+// Data that members exchange (partial sums, the entries of p) is written and
+// read with device-scope accesses (cst / ldc below), which go to the device's
+// coherence point instead of an XCD's own L2.  A barrier: every wave waits
+// until its own stores have completed, the workgroup meets, one thread counts
+// the arrival and polls until all T members have arrived (or the wait timed
+// out, which marks the solve as failed and makes every later barrier return
+// at once), and the workgroup meets again.  (A full agent-scope fence per
+// barrier -- an L2 write-back and invalidate -- costs ~70 us here; this form
+// costs 4-11 us for teams of 2-8.)
+__device__ __forceinline__ void cst(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cst(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ldc(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ldc(const float* p) {
+  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int BT>
-__device__ void bgemv_n(const BatchProblem& P, const float* p, const float* qprev, double c, double* w) {
+__device__ void team_barrier(Team& tm, Lds<BT>& L) {
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have completed
+  __syncthreads();
+  ++tm.nbar;
+  if (threadIdx.x == 0 && !L.team_fail) {
+    __hip_atomic_fetch_add(tm.cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int target = tm.nbar * tm.T;
+    long polls = 0;
+    while (__hip_atomic_load(tm.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++polls > TEAM_SPIN_LIMIT) {
+        L.team_fail = 1;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// v[0..len) (LDS, this member's partial sums) <- the sum over members, in member order.
+template <int BT>
+__device__ void team_sum(double* v, int len, Team& tm, Lds<BT>& L) {
+  if (tm.T == 1) return;
+  double* region = tm.small + (int64_t)tm.parity * tm.T * SLD;
+  for (int i = threadIdx.x; i < len; i += BT) cst(region + tm.member * SLD + i, v[i]);
+  team_barrier(tm, L);
+  for (int i = threadIdx.x; i < len; i += BT) {
+    double s = 0.0;
+    for (int mm = 0; mm < tm.T; ++mm) s += ldc(region + mm * SLD + i);
+    v[i] = s;
+  }
+  tm.parity ^= 1;
+  __syncthreads();
+}
+
+template <int BT>
+__device__ double team_sum_scalar(double x, Team& tm, Lds<BT>& L) {
+  if (tm.T == 1) return x;
+  if (threadIdx.x == 0) L.scal = x;
+  __syncthreads();
+  team_sum(&L.scal, 1, tm, L);
+  const double r = L.scal;
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- products
+// w[i] = A[i, :] p - c * qprev[i] for rows i in [lo, hi) (qprev may be null);
+// each wave owns 4 rows at a time, lanes stride the columns with 16-byte
+// loads (4 rows x 2 vectors in flight).
+// p is in LDS (PLDS, a team's copy) or in global memory.
+template <int BT, bool PLDS>
+__device__ void bgemv_n(const BatchProblem& P, const float* p_, const float* qprev_, double c, double* w_, int lo,
+                        int hi) {
   constexpr int NW = BT / 64;
   constexpr int R = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
-  for (int i0 = wave * R; i0 < P.m; i0 += NW * R) {
-    const float* rows[R];
+                   ((reinterpret_cast<uintptr_t>(p_) & 15) == 0);
+  using PT = typename std::conditional<PLDS, const LMEM float*, const GMEM float*>::type;
+  using P4 = typename std::conditional<PLDS, const LMEM f4*, const GMEM f4*>::type;
+  const PT p = (PT)p_;
+  const GMEM float* qprev = gc(qprev_);
+  GMEM double* w = gw(w_);
+  const GMEM float* A = gc(P.A);
+  for (int i0 = lo + wave * R; i0 < hi; i0 += NW * R) {
+    const GMEM float* rows[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) rows[r] = P.A + (int64_t)min(i0 + r, P.m - 1) * P.lda;
+    for (int r = 0; r < R; ++r) rows[r] = A + (int64_t)min(i0 + r, hi - 1) * P.lda;
     float a[R] = {0.f, 0.f, 0.f, 0.f};
     int jt = 0;
     if (vec) {
@@ -86,13 +206,15 @@ __device__ void bgemv_n(const BatchProblem& P, const float* p, const float* qpre
       for (int v0 = lane; v0 < nv; v0 += 128) {
         const int v1 = v0 + 64;
         const bool ok1 = v1 < nv;
-        const float4 p0 = reinterpret_cast<const float4*>(p)[v0];
-        const float4 p1 = ok1 ? reinterpret_cast<const float4*>(p)[v1] : make_float4(0.f, 0.f, 0.f, 0.f);
-        float4 x0[R], x1[R];
+        const f4 p0 = ((P4)p)[v0];
+        f4 p1 = {0.f, 0.f, 0.f, 0.f};
+        if (ok1) p1 = ((P4)p)[v1];
+        f4 x0[R], x1[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          x0[r] = reinterpret_cast<const float4*>(rows[r])[v0];
-          x1[r] = ok1 ? reinterpret_cast<const float4*>(rows[r])[v1] : make_float4(0.f, 0.f, 0.f, 0.f);
+          x0[r] = ((const GMEM f4*)rows[r])[v0];
+          x1[r] = f4{0.f, 0.f, 0.f, 0.f};
+          if (ok1) x1[r] = ((const GMEM f4*)rows[r])[v1];
         }
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -109,19 +231,22 @@ __device__ void bgemv_n(const BatchProblem& P, const float* p, const float* qpre
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double sr = wsum((double)a[r]);
-      if (lane == 0 && i0 + r < P.m) w[i0 + r] = sr - (qprev ? c * (double)qprev[i0 + r] : 0.0);
+      if (lane == 0 && i0 + r < hi) w[i0 + r] = sr - (qprev_ ? c * (double)qprev[i0 + r] : 0.0);
     }
   }
   __syncthreads();
 }
 
-// z = A^T q - c * pprev; threads own 4-column groups, G row groups split the
-// rows (4 rows in flight per thread), partial sums meet in LDS and are added
+// out[j] = sum_{i in [lo, hi)} A[i, j] q[i] - c * pprev[j] for all j < n
+// (pprev may be null); threads own 4-column groups, G row groups split the
+// rows (8 rows in flight per thread), partial sums meet in LDS and are added
 // in group order.
-template <int BT>
-__device__ void bgemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z,
-                        Lds<BT>& L) {
+template <int BT, bool COHERENT = false>
+__device__ void bgemv_t(const BatchProblem& P, const float* q_, const float* pprev_, double c, double* out, int lo,
+                        int hi, Lds<BT>& L) {
   const int tid = threadIdx.x;
+  const GMEM float* q = gc(q_);
+  const GMEM float* pprev = gc(pprev_);
   // 16-byte loads need aligned rows; columns n .. 4 ceil(n / 4) - 1 must be
   // readable (the plan stages every matrix that does not satisfy this)
   const bool vec = ((P.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(P.A) & 15) == 0) &&
@@ -133,40 +258,49 @@ __device__ void bgemv_t(const BatchProblem& P, const float* q, const float* ppre
   const int g = ncg >= BT ? 0 : tid / ncg;
   for (int cg = ncg >= BT ? tid : tid % ncg; cg < ncg && g < G; cg += (ncg >= BT ? BT : ncg)) {
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    const float* base = P.A + cg * VN;
-    int i = g;
-    for (; i + 3 * G < P.m; i += 4 * G) {
-      const float q0 = q[i], q1 = q[i + G], q2 = q[i + 2 * G], q3 = q[i + 3 * G];
-      if (vec) {
-        const float4 a0 = *reinterpret_cast<const float4*>(base + (int64_t)i * P.lda);
-        const float4 a1 = *reinterpret_cast<const float4*>(base + (int64_t)(i + G) * P.lda);
-        const float4 a2 = *reinterpret_cast<const float4*>(base + (int64_t)(i + 2 * G) * P.lda);
-        const float4 a3 = *reinterpret_cast<const float4*>(base + (int64_t)(i + 3 * G) * P.lda);
-        acc[0] += a0.x * q0 + a1.x * q1 + a2.x * q2 + a3.x * q3;
-        acc[1] += a0.y * q0 + a1.y * q1 + a2.y * q2 + a3.y * q3;
-        acc[2] += a0.z * q0 + a1.z * q1 + a2.z * q2 + a3.z * q3;
-        acc[3] += a0.w * q0 + a1.w * q1 + a2.w * q2 + a3.w * q3;
-      } else {
-        acc[0] += base[(int64_t)i * P.lda] * q0 + base[(int64_t)(i + G) * P.lda] * q1 +
-                  base[(int64_t)(i + 2 * G) * P.lda] * q2 + base[(int64_t)(i + 3 * G) * P.lda] * q3;
+    const GMEM float* base = gc(P.A) + cg * VN;
+    int i = lo + g;
+    if (vec) {
+      // 8 rows in flight per thread (128 bytes): enough outstanding loads
+      // per CU to keep streaming when every CU competes for HBM
+      for (; i + 7 * G < hi; i += 8 * G) {
+        f4 a[8];
+        float qq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          qq[u] = q[i + u * G];
+          a[u] = *(const GMEM f4*)(base + (int64_t)(i + u * G) * P.lda);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          acc[0] += a[u].x * qq[u];
+          acc[1] += a[u].y * qq[u];
+          acc[2] += a[u].z * qq[u];
+          acc[3] += a[u].w * qq[u];
+        }
       }
-    }
-    for (; i < P.m; i += G) {
-      const float qi = q[i];
-      if (vec) {
-        const float4 a0 = *reinterpret_cast<const float4*>(base + (int64_t)i * P.lda);
+      for (; i < hi; i += G) {
+        const float qi = q[i];
+        const f4 a0 = *(const GMEM f4*)(base + (int64_t)i * P.lda);
         acc[0] += a0.x * qi;
         acc[1] += a0.y * qi;
         acc[2] += a0.z * qi;
         acc[3] += a0.w * qi;
-      } else {
-        acc[0] += base[(int64_t)i * P.lda] * qi;
       }
+    } else {
+      for (; i + 3 * G < hi; i += 4 * G)
+        acc[0] += base[(int64_t)i * P.lda] * q[i] + base[(int64_t)(i + G) * P.lda] * q[i + G] +
+                  base[(int64_t)(i + 2 * G) * P.lda] * q[i + 2 * G] + base[(int64_t)(i + 3 * G) * P.lda] * q[i + 3 * G];
+      for (; i < hi; i += G) acc[0] += base[(int64_t)i * P.lda] * q[i];
     }
     if (ncg >= BT) {
       for (int e = 0; e < VN; ++e) {
         const int j = cg * VN + e;
-        if (j < P.n) z[j] = (double)acc[e] - (pprev ? c * (double)pprev[j] : 0.0);
+        if (j < P.n) {
+          const double o = (double)acc[e] - (pprev_ ? c * (double)pprev[j] : 0.0);
+          if (COHERENT) cst(out + j, o);
+          else out[j] = o;
+        }
       }
     } else {
       for (int e = 0; e < VN; ++e) L.tpart[g * npad + cg * VN + e] = acc[e];
@@ -177,32 +311,59 @@ __device__ void bgemv_t(const BatchProblem& P, const float* q, const float* ppre
     for (int j = tid; j < P.n; j += BT) {
       double s = 0.0;
       for (int gg = 0; gg < G; ++gg) s += (double)L.tpart[gg * npad + j];
-      z[j] = s - (pprev ? c * (double)pprev[j] : 0.0);
+      const double o = s - (pprev_ ? c * (double)pprev[j] : 0.0);
+      if (COHERENT) cst(out + j, o);
+      else out[j] = o;
     }
     __syncthreads();
   }
 }
 
-// h[j] = V[:, j] . x for j < t (waves own columns, lanes own rows).
+// z[j] = (A^T q)[j] - c * pprev[j] for this member's entries j in [plo, phi);
+// q is read on the member's rows [qlo, qhi) only.
 template <int BT>
-__device__ void bdots(const float* V, int ldv, int t, int len, const double* x, Lds<BT>& L) {
+__device__ void team_gemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z,
+                            int qlo, int qhi, int plo, int phi, Team& tm, Lds<BT>& L) {
+  if (tm.T == 1) {
+    bgemv_t<BT>(P, q, pprev, c, z, 0, P.m, L);
+    return;
+  }
+  double* mine = tm.zpart + (int64_t)tm.member * P.n;
+  bgemv_t<BT, true>(P, q, nullptr, 0.0, mine, qlo, qhi, L);
+  team_barrier(tm, L);
+  for (int j = plo + threadIdx.x; j < phi; j += BT) {
+    double s = 0.0;
+    for (int mm = 0; mm < tm.T; ++mm) s += ldc(tm.zpart + (int64_t)mm * P.n + j);
+    z[j] = s - (pprev ? c * (double)pprev[j] : 0.0);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- Gram-Schmidt
+// L.h[j] = V[lo:hi, j] . x[lo:hi] for j < t (waves own columns, lanes own rows).
+template <int BT>
+__device__ void bdots(const float* V_, int ldv, int t, int lo, int hi, const double* x_, Lds<BT>& L) {
   constexpr int NW = BT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const GMEM float* V = gc(V_);
+  const GMEM double* x = gc(x_);
   for (int j = wave; j < t; j += NW) {
-    const float* col = V + (int64_t)j * ldv;
+    const GMEM float* col = V + (int64_t)j * ldv;
     double a = 0.0;
-    for (int i = lane; i < len; i += 64) a += (double)col[i] * x[i];
+    for (int i = lo + lane; i < hi; i += 64) a += (double)col[i] * x[i];
     a = wsum(a);
     if (lane == 0) L.h[j] = a;
   }
   __syncthreads();
 }
 
-// x -= V h (t columns); returns ||x||^2 after the update.
+// x[lo:hi] -= V[lo:hi, 0:t] h; returns the member's part of ||x||^2 after the update.
 template <int BT>
-__device__ double bupdate(const float* V, int ldv, int t, int len, double* x, const double* h, Lds<BT>& L) {
+__device__ double bupdate(const float* V_, int ldv, int t, int lo, int hi, double* x_, const double* h, Lds<BT>& L) {
+  const GMEM float* V = gc(V_);
+  GMEM double* x = gw(x_);
   double ss = 0.0;
-  for (int i = threadIdx.x; i < len; i += BT) {
+  for (int i = lo + threadIdx.x; i < hi; i += BT) {
     double xi = x[i];
     for (int j = 0; j < t; ++j) xi -= (double)V[(int64_t)j * ldv + i] * h[j];
     x[i] = xi;
@@ -212,23 +373,45 @@ __device__ double bupdate(const float* V, int ldv, int t, int len, double* x, co
   return block_sum(ss, L);
 }
 
+// Two classical Gram-Schmidt passes of x against V[:, 0:t] on the member's
+// range; returns the team-wide ||x||^2.
 template <int BT>
-__device__ double bcgs2(const float* V, int ldv, int t, int len, double* x, Lds<BT>& L) {
+__device__ double bcgs2(const float* V, int ldv, int t, int lo, int hi, double* x, Team& tm, Lds<BT>& L) {
+  double ss;
   if (t > 0) {
-    bdots(V, ldv, t, len, x, L);
-    bupdate(V, ldv, t, len, x, L.h, L);
-    bdots(V, ldv, t, len, x, L);
-    return bupdate(V, ldv, t, len, x, L.h, L);
+    bdots(V, ldv, t, lo, hi, x, L);
+    team_sum(L.h, t, tm, L);
+    bupdate(V, ldv, t, lo, hi, x, L.h, L);
+    bdots(V, ldv, t, lo, hi, x, L);
+    team_sum(L.h, t, tm, L);
+    ss = bupdate(V, ldv, t, lo, hi, x, L.h, L);
+  } else {
+    ss = 0.0;
+    const GMEM double* xg = gc(x);
+    for (int i = lo + threadIdx.x; i < hi; i += BT) ss += xg[i] * xg[i];
+    ss = block_sum(ss, L);
   }
-  double ss = 0.0;
-  for (int i = threadIdx.x; i < len; i += BT) ss += x[i] * x[i];
-  return block_sum(ss, L);
+  return team_sum_scalar(ss, tm, L);
 }
 
 template <int BT>
-__device__ void bscale(const double* x, int len, double nrm, float* out) {
-  for (int i = threadIdx.x; i < len; i += BT) out[i] = (float)(x[i] / nrm);
+__device__ void bscale(const double* x_, int lo, int hi, double nrm, float* out, bool coherent) {
+  const GMEM double* x = gc(x_);
+  if (coherent) {
+    for (int i = lo + threadIdx.x; i < hi; i += BT) cst(out + i, (float)(x[i] / nrm));
+  } else {
+    GMEM float* o = gw(out);
+    for (int i = lo + threadIdx.x; i < hi; i += BT) o[i] = (float)(x[i] / nrm);
+  }
   __syncthreads();
+}
+
+// The team's current p, read from the coherence point into LDS (n <= BATCH_TEAM_NMAX).
+template <int BT>
+__device__ const float* team_load_p(const float* p, int n, Lds<BT>& L) {
+  for (int j = threadIdx.x; j < n; j += BT) L.pvec[j] = ldc(p + j);
+  __syncthreads();
+  return L.pvec;
 }
 
 // One-sided Jacobi SVD of the nq x np matrix in L.Hs (columns), accumulating
@@ -319,12 +502,14 @@ __device__ void bjacobi(int nq, int np, Lds<BT>& L) {
   __syncthreads();
 }
 
-// out[:, c] = V[:, 0..kk) * M[0..kk, perm[c]] for c < ncols, M column-major in LDS
+// out[lo:hi, c] = V[lo:hi, 0..kk) * M[0..kk, perm[c]] for c < ncols, M column-major in LDS
 // (column stride mld); V column-major (ldv), out column-major (ldo).
 template <int BT>
-__device__ void bgemm_small(const float* V, int ldv, int len, int kk, const double* M, int mld, const int* perm,
-                            int ncols, float* out, int ldo) {
-  for (int i = threadIdx.x; i < len; i += BT) {
+__device__ void bgemm_small(const float* V_, int ldv, int lo, int hi, int kk, const double* M, int mld,
+                            const int* perm, int ncols, float* out_, int ldo) {
+  const GMEM float* V = gc(V_);
+  GMEM float* out = gw(out_);
+  for (int i = lo + threadIdx.x; i < hi; i += BT) {
     for (int c0 = 0; c0 < ncols; c0 += 8) {
       double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       for (int j = 0; j < kk; ++j) {
@@ -341,11 +526,12 @@ __device__ void bgemm_small(const float* V, int ldv, int len, int kk, const doub
   __syncthreads();
 }
 
-// Normalise x into out with the breakdown test; returns false on breakdown
+// Normalise x[lo:hi] into out with the breakdown test (nrm2 is the team-wide
+// squared norm, so every member decides alike); returns false on breakdown
 // (L.flag set).  thr = eps * sig (relative) or eps.
 template <int BT>
-__device__ bool bnormalize(const double* x, int len, double nrm2, double thr, float* out, int code, int idx,
-                           Lds<BT>& L) {
+__device__ bool bnormalize(const double* x, int lo, int hi, double nrm2, double thr, float* out, int code, int idx,
+                           Lds<BT>& L, bool coherent = false) {
   const double nrm = sqrt(nrm2);
   if (!(nrm < INFINITY)) {
     if (threadIdx.x == 0) {
@@ -363,7 +549,7 @@ __device__ bool bnormalize(const double* x, int len, double nrm2, double thr, fl
     __syncthreads();
     return false;
   }
-  bscale<BT>(x, len, nrm, out);
+  bscale<BT>(x, lo, hi, nrm, out, coherent);
   return true;
 }
 
@@ -390,9 +576,9 @@ __device__ double philox_normal(int64_t i, uint64_t seed) {
   return 2.0 + sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
 }
 
-// Solve one problem (all threads of the workgroup).
+// Solve one problem as member `member` of its team (all threads of the workgroup).
 template <int BT>
-__device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>& L) {
+__device__ void solve_one(const BatchProblem& P, int member, const BatchParams& prm, Lds<BT>& L) {
   const int tid = threadIdx.x;
   const int ldq = P.ldq, ldp = P.ldp;   // basis column strides (multiples of 4: 16-byte aligned columns)
   float* Qb[2] = {prm.pool + P.offQ, prm.pool + P.offQ + (int64_t)(P.k + 1) * ldq};
@@ -400,6 +586,16 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
   double* w = prm.work + P.offW;
   double* z = w + P.m;
   const int m = P.m, n = P.n, k = P.k, r = P.r, l = P.l;
+  Team tm;
+  tm.T = P.team;
+  tm.member = member;
+  tm.cnt = prm.team_cnt + (P.team > 1 ? P.team_id : 0);
+  tm.zpart = prm.team_buf + P.offTeam;
+  tm.small = tm.zpart + (int64_t)P.team * n;
+  tm.nbar = 0;
+  tm.parity = 0;
+  const int qlo = (int)((int64_t)member * m / tm.T), qhi = (int)((int64_t)(member + 1) * m / tm.T);
+  const int plo = (int)((int64_t)member * n / tm.T), phi = (int)((int64_t)(member + 1) * n / tm.T);
   int cur = 0;
   auto Qc = [&](int j) { return Qb[cur] + (int64_t)j * ldq; };
   auto Pc = [&](int j) { return Pb[cur] + (int64_t)j * ldp; };
@@ -410,14 +606,16 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
   if (tid == 0) {
     L.flag = 0;
     L.flag_idx = 0;
+    L.team_fail = 0;
   }
+  __syncthreads();
   // start: q ~ N(2,1) (Philox, seed + problem index) or caller's vector
-  for (int i = tid; i < m; i += BT) w[i] = prm.q1 ? prm.q1[P.offQ1 + i] : philox_normal(i, prm.seed + P.index);
+  for (int i = qlo + tid; i < qhi; i += BT) w[i] = prm.q1 ? prm.q1[P.offQ1 + i] : philox_normal(i, prm.seed + P.index);
   __syncthreads();
   double ss = 0.0;
-  for (int i = tid; i < m; i += BT) ss += w[i] * w[i];
-  ss = block_sum(ss, L);
-  if (!bnormalize(w, m, ss, 0.0, Qc(0), 1, 0, L)) {
+  for (int i = qlo + tid; i < qhi; i += BT) ss += w[i] * w[i];
+  ss = team_sum_scalar(block_sum(ss, L), tm, L);
+  if (!bnormalize(w, qlo, qhi, ss, 0.0, Qc(0), 1, 0, L)) {
     status = -1;
   }
   int nq = 0, np = 0;        // shape of the projected matrix of the cycle
@@ -430,10 +628,10 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
     int np_now = 0;
     bool early = false;
     if (first) {
-      bgemv_t(P, Qc(0), nullptr, 0.0, z, L);
+      team_gemv_t(P, Qc(0), nullptr, 0.0, z, qlo, qhi, plo, phi, tm, L);
       ++matvecs;
-      ss = bcgs2(nullptr, n, 0, n, z, L);
-      if (!bnormalize(z, n, ss, 0.0, Pc(0), 2, 0, L)) {
+      ss = bcgs2(nullptr, ldp, 0, plo, phi, z, tm, L);
+      if (!bnormalize(z, plo, phi, ss, 0.0, Pc(0), 2, 0, L, tm.T > 1)) {
         // A^T q1 = 0
         nq = 1;
         np = 0;
@@ -441,31 +639,37 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
       }
       if (tid == 0) L.pc[0] = sqrt(ss);
       sig = fmax(sig, sqrt(ss));
+      if (tm.T > 1) team_barrier(tm, L);   // p_1 complete before A p_1
       __syncthreads();
     }
     for (int j = jstart; j < k; ++j) {
+      if (L.team_fail) break;
       // q side
       const int qi = first ? j + 1 : j;     // new Q column
-      if (first) {
-        bgemv_n<BT>(P, Pc(j), Qc(j), L.pc[j], w);
-      } else {
-        bgemv_n<BT>(P, Pc(j), j == l ? nullptr : Qc(j - 1), j == l ? 0.0 : L.pc[j], w);
-        if (j == l) bupdate(Qc(0), ldq, l, m, w, L.rho, L);
+      const float* qprev = first ? Qc(j) : (j == l ? nullptr : Qc(j - 1));
+      const double cprev = (first || j != l) ? L.pc[j] : 0.0;
+      if (tm.T > 1)
+        bgemv_n<BT, true>(P, team_load_p(Pc(j), n, L), qprev, cprev, w, qlo, qhi);
+      else
+        bgemv_n<BT, false>(P, Pc(j), qprev, cprev, w, qlo, qhi);
+      if (!first) {
+        if (j == l) bupdate(Qc(0), ldq, l, qlo, qhi, w, L.rho, L);
       }
       ++matvecs;
-      ss = bcgs2(Qc(0), ldq, qi, m, w, L);
-      if (!bnormalize(w, m, ss, prm.relative ? eps * sig : eps, Qc(qi), 1, qi, L)) break;
+      ss = bcgs2(Qc(0), ldq, qi, qlo, qhi, w, tm, L);
+      if (!bnormalize(w, qlo, qhi, ss, prm.relative ? eps * sig : eps, Qc(qi), 1, qi, L)) break;
       const double beta = sqrt(ss);
       if (tid == 0) L.qc[qi] = beta;
       sig = fmax(sig, beta);
       // p side
-      bgemv_t(P, Qc(qi), Pc(j), beta, z, L);
+      team_gemv_t(P, Qc(qi), Pc(j), beta, z, qlo, qhi, plo, phi, tm, L);
       ++matvecs;
-      ss = bcgs2(Pc(0), ldp, j + 1, n, z, L);
-      if (!bnormalize(z, n, ss, prm.relative ? eps * sig : eps, Pc(j + 1), 2, j + 1, L)) break;
+      ss = bcgs2(Pc(0), ldp, j + 1, plo, phi, z, tm, L);
+      if (!bnormalize(z, plo, phi, ss, prm.relative ? eps * sig : eps, Pc(j + 1), 2, j + 1, L, tm.T > 1)) break;
       const double alpha = sqrt(ss);
       if (tid == 0) L.pc[j + 1] = alpha;
       sig = fmax(sig, alpha);
+      if (tm.T > 1) team_barrier(tm, L);   // p_{j+2} complete before the next A p
       __syncthreads();
       np_now = j + 1;
       if (prm.check_every > 0 && np_now < k && np_now >= r && np_now % prm.check_every == 0) {
@@ -512,6 +716,10 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
     }
     const int fl = L.flag, fidx = L.flag_idx;
     __syncthreads();
+    if (L.team_fail) {
+      status = GKB_ERR_TIMEOUT;
+      break;
+    }
     if (fl == 3) {
       status = -3;
       break;
@@ -576,18 +784,19 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
       done = true;
       break;
     }
-    // ---------------- thick restart
+    // ---------------- thick restart (each member its own rows of Q and entries of P)
     sig = fmax(sig, s0);
     const int nb = 1 - cur;
     // P~ = P Y_l (Y = Vs, columns by perm), Q~ = Q X_l (X = Hs normalised)
-    bgemm_small<BT>(Pb[cur], ldp, n, np, L.Vs, KMAX, L.perm, l, Pb[nb], ldp);
-    bgemm_small<BT>(Qb[cur], ldq, m, nq, L.Hs, HLD, L.perm, l, Qb[nb], ldq);
-    for (int i = tid; i < n; i += BT) Pb[nb][(int64_t)l * ldp + i] = Pb[cur][(int64_t)np * ldp + i];
+    bgemm_small<BT>(Pb[cur], ldp, plo, phi, np, L.Vs, KMAX, L.perm, l, Pb[nb], ldp);
+    bgemm_small<BT>(Qb[cur], ldq, qlo, qhi, nq, L.Hs, HLD, L.perm, l, Qb[nb], ldq);
+    for (int i = plo + tid; i < phi; i += BT) cst(Pb[nb] + (int64_t)l * ldp + i, Pb[cur][(int64_t)np * ldp + i]);
     if (tid < l) {
       L.sres[tid] = L.sv[L.perm[tid]];
       L.rho[tid] = alpha_res * L.Hs[L.perm[tid] * HLD + nq - 1];
     }
     __syncthreads();
+    if (tm.T > 1) team_barrier(tm, L);   // the new P complete before A p_{l+1}
     cur = nb;
     ++restarts;
     first = false;
@@ -597,18 +806,18 @@ __device__ void solve_one(const BatchProblem& P, const BatchParams& prm, Lds<BT>
     }
     __syncthreads();
   }
-  // ---------------- outputs
+  // ---------------- outputs (each member its rows of U and entries of V)
   const int pi = P.index;
   if (status == 0 && np > 0) {
     float* U = prm.U + P.offU;
     float* V = prm.V + P.offV;
-    bgemm_small<BT>(Pb[cur], ldp, n, np, L.Vs, KMAX, L.perm, r_eff, V, n);
-    bgemm_small<BT>(Qb[cur], ldq, m, nq, L.Hs, HLD, L.perm, r_eff, U, m);
-    if (tid < r) prm.sigma[P.offS + tid] = tid < r_eff ? L.sv[L.perm[tid]] : 0.0;
-  } else if (tid < r) {
+    bgemm_small<BT>(Pb[cur], ldp, plo, phi, np, L.Vs, KMAX, L.perm, r_eff, V, n);
+    bgemm_small<BT>(Qb[cur], ldq, qlo, qhi, nq, L.Hs, HLD, L.perm, r_eff, U, m);
+    if (member == 0 && tid < r) prm.sigma[P.offS + tid] = tid < r_eff ? L.sv[L.perm[tid]] : 0.0;
+  } else if (member == 0 && tid < r) {
     prm.sigma[P.offS + tid] = 0.0;
   }
-  if (tid == 0) {
+  if (member == 0 && tid == 0) {
     int st = status;
     if (st == 0) st = r_eff < r ? 2 : (nconv == r ? 0 : 1);
     prm.info[4 * pi + 0] = st;
@@ -628,19 +837,22 @@ __global__ __launch_bounds__(BT) void k_batched_gk(BatchParams prm) {
   while (true) {
     if (threadIdx.x == 0) {
       const int slot = atomicAdd(prm.counter, 1);
-      L.problem = slot < prm.batch ? prm.order[slot] : -1;
+      L.problem = slot < prm.ntickets ? prm.order[slot] : -1;
+      L.member = slot < prm.ntickets ? prm.member[slot] : 0;
     }
     __syncthreads();
-    const int p = L.problem;
+    const int p = L.problem, mem = L.member;
     __syncthreads();
     if (p < 0) break;
     const BatchProblem P = prm.problems[p];
-    solve_one(P, prm, L);
+    solve_one(P, mem, prm, L);
   }
 }
 
-__global__ void k_batched_reset(int* counter) {
-  if (threadIdx.x == 0) *counter = 0;
+// Zero the queue head and the team barrier counters.
+__global__ void k_batched_reset(int* counter, int* team_cnt, int nteams) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nteams; i += gridDim.x * blockDim.x) team_cnt[i] = 0;
 }
 
 // Copy the matrices listed in the stage table into 16-byte aligned rows of
@@ -668,7 +880,7 @@ __global__ __launch_bounds__(256) void k_batched_stage(const StageCopy* __restri
 size_t batched_lds_bytes(int threads) { return threads == 512 ? sizeof(Lds<512>) : sizeof(Lds<1024>); }
 
 hipError_t launch_batched(const BatchParams& prm, int grid, int threads, hipStream_t st) {
-  hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(64), 0, st, prm.counter);
+  hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(256), 0, st, prm.counter, prm.team_cnt, prm.nteams);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (prm.nstage > 0) {

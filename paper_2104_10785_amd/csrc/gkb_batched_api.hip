@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -32,11 +33,18 @@ gkb_status bfail(gkb_status s, const std::string& m) {
 
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int TEAM_MAX = 8;   // largest team of workgroups on one problem
+
 struct Layout {
-  size_t problems = 0, order = 0, counter = 0, info = 0, pool = 0, work = 0, stage_tab = 0, stage = 0, total = 0;
-  size_t pool_floats = 0, work_doubles = 0, stage_floats = 0;
+  size_t problems = 0, order = 0, member = 0, counter = 0, info = 0, pool = 0, work = 0, stage_tab = 0, stage = 0,
+         team_cnt = 0, team_buf = 0, total = 0;
+  size_t pool_floats = 0, work_doubles = 0, stage_floats = 0, team_doubles = 0;
   int nstage = 0;
 };
+
+// Team buffers of one problem for a team of T: T x n partial products and two
+// alternating T x (KMAX + 4) regions for the partial dots and norms.
+inline size_t team_doubles(int T, int64_t n) { return (size_t)T * n + 2 * (size_t)T * (gkb::BATCH_KMAX + 4); }
 
 inline int64_t round4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
@@ -72,7 +80,8 @@ Layout layout(int batch, const gkb_matrix* As, const int* k) {
     return o;
   };
   L.problems = take(sizeof(gkb::BatchProblem) * batch);
-  L.order = take(sizeof(int) * batch);
+  L.order = take(sizeof(int) * batch * TEAM_MAX);
+  L.member = take(sizeof(int) * batch * TEAM_MAX);
   L.counter = take(sizeof(int));
   L.info = take(sizeof(int) * 4 * batch);
   for (int i = 0; i < batch; ++i) {
@@ -82,11 +91,14 @@ Layout layout(int batch, const gkb_matrix* As, const int* k) {
       ++L.nstage;
       L.stage_floats += a256((size_t)As[i].m * round4(As[i].n) * sizeof(float)) / sizeof(float);
     }
+    L.team_doubles += team_doubles(TEAM_MAX, As[i].n);   // room for the largest team
   }
   L.pool = take(L.pool_floats * sizeof(float));
   L.work = take(L.work_doubles * sizeof(double));
   L.stage_tab = take(sizeof(gkb::StageCopy) * std::max(L.nstage, 1));
   L.stage = take(L.stage_floats * sizeof(float));
+  L.team_cnt = take(sizeof(int) * batch);
+  L.team_buf = take(L.team_doubles * sizeof(double));
   L.total = off;
   return L;
 }
@@ -140,6 +152,11 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
     return bfail(GKB_ERR_INVALID, "bad batch options");
   if (opt.threads != 0 && opt.threads != 512 && opt.threads != 1024)
     return bfail(GKB_ERR_INVALID, "threads must be 0, 512 or 1024");
+  if (opt.max_team < 0) return bfail(GKB_ERR_INVALID, "max_team must be >= 0");
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return bfail(GKB_ERR_HIP, "cannot query the device");
   Layout L = layout(batch, As, k);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0 || ws_bytes < L.total)
     return bfail(GKB_ERR_WORKSPACE, "workspace missing, misaligned or too small (need " +
@@ -194,20 +211,59 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
     P.offQ1 = offQ1;
     offQ1 += P.m;
   }
-  // largest first: estimated cost m * n * k
-  plan->order.resize(batch);
-  std::iota(plan->order.begin(), plan->order.end(), 0);
-  std::stable_sort(plan->order.begin(), plan->order.end(), [&](int a, int b) {
-    const double ca = (double)plan->table[a].m * plan->table[a].n * plan->table[a].k;
-    const double cb = (double)plan->table[b].m * plan->table[b].n * plan->table[b].k;
-    return ca > cb;
-  });
+  // persistent grid: one workgroup per compute unit unless asked otherwise
+  plan->threads = opt.threads ? opt.threads : 1024;
+  plan->grid = opt.workgroups > 0 ? opt.workgroups : cus;
+  // Teams: a problem whose estimated cost (m n k) exceeds half of the average
+  // per-workgroup share of the whole batch is split over
+  // T = ceil(cost / (share / 2)) workgroups (at most max_team, the grid, m / 256
+  // and n / 64), so that no single problem outlasts the rest of the batch.
+  const int max_team = std::min(opt.max_team > 0 ? opt.max_team : TEAM_MAX, TEAM_MAX);
+  std::vector<double> cost(batch);
+  double total = 0.0;
+  for (int i = 0; i < batch; ++i) {
+    cost[i] = (double)plan->table[i].m * plan->table[i].n * plan->table[i].k;
+    total += cost[i];
+  }
+  const double half_share = 0.5 * total / plan->grid;
+  int nteams = 0;
+  int64_t offTeam = 0;
+  int ntickets = 0;
+  for (int i = 0; i < batch; ++i) {
+    gkb::BatchProblem& P = plan->table[i];
+    int T = (int)std::ceil(cost[i] / std::max(half_share, 1.0));
+    T = std::min({T, max_team, plan->grid, std::max(1, P.m / 256), std::max(1, P.n / 64)});
+    if (P.n > gkb::BATCH_TEAM_NMAX) T = 1;   // a team keeps p in LDS
+    T = std::max(T, 1);
+    P.team = T;
+    P.team_id = T > 1 ? nteams++ : 0;
+    P.offTeam = offTeam;
+    offTeam += (int64_t)team_doubles(T, P.n);
+    ntickets += T;
+  }
+  // tickets: largest per-member cost first, a team's members adjacent
+  std::vector<int> byp(batch);
+  std::iota(byp.begin(), byp.end(), 0);
+  std::stable_sort(byp.begin(), byp.end(),
+                   [&](int a, int b) { return cost[a] / plan->table[a].team > cost[b] / plan->table[b].team; });
+  plan->order.clear();
+  std::vector<int> members;
+  for (int i : byp)
+    for (int j = 0; j < plan->table[i].team; ++j) {
+      plan->order.push_back(i);
+      members.push_back(j);
+    }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   gkb::BatchParams& prm = plan->prm;
   prm.problems = reinterpret_cast<const gkb::BatchProblem*>(ws + L.problems);
   prm.order = reinterpret_cast<const int*>(ws + L.order);
+  prm.member = reinterpret_cast<const int*>(ws + L.member);
   prm.counter = reinterpret_cast<int*>(ws + L.counter);
   prm.batch = batch;
+  prm.ntickets = ntickets;
+  prm.team_cnt = reinterpret_cast<int*>(ws + L.team_cnt);
+  prm.nteams = nteams;
+  prm.team_buf = reinterpret_cast<double*>(ws + L.team_buf);
   prm.pool = reinterpret_cast<float*>(ws + L.pool);
   prm.work = reinterpret_cast<double*>(ws + L.work);
   prm.U = U;
@@ -234,20 +290,16 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   };
   if (hipMemcpyAsync(ws + L.problems, plan->table.data(), sizeof(gkb::BatchProblem) * batch,
                      hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(ws + L.order, plan->order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, st) !=
+      hipMemcpyAsync(ws + L.order, plan->order.data(), sizeof(int) * ntickets, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(ws + L.member, members.data(), sizeof(int) * ntickets, hipMemcpyHostToDevice, st) !=
           hipSuccess ||
       (!stage.empty() && hipMemcpyAsync(ws + L.stage_tab, stage.data(), sizeof(gkb::StageCopy) * stage.size(),
                                         hipMemcpyHostToDevice, st) != hipSuccess) ||
       hipStreamSynchronize(st) != hipSuccess)
     return cleanup(bfail(GKB_ERR_HIP, "uploading the problem table failed"));
   if (gkb::batched_setup() != hipSuccess) return cleanup(bfail(GKB_ERR_HIP, "cannot set the LDS size"));
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return cleanup(bfail(GKB_ERR_HIP, "cannot query the device"));
-  plan->threads = opt.threads ? opt.threads : 1024;
-  plan->grid = opt.workgroups > 0 ? opt.workgroups : cus;
-  plan->grid = std::min(plan->grid, batch);
+  plan->grid = std::min(plan->grid, ntickets);
   plan->no_graph = opt.no_graph != 0;
   if (plan->no_graph) {
     *out = plan;

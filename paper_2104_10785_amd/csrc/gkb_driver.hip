@@ -769,6 +769,7 @@ const char* gkb_status_string(gkb_status s) {
     case GKB_ERR_HIP: return "GKB_ERR_HIP";
     case GKB_ERR_NUMERIC: return "GKB_ERR_NUMERIC";
     case GKB_ERR_WORKSPACE: return "GKB_ERR_WORKSPACE";
+    case GKB_ERR_TIMEOUT: return "GKB_ERR_TIMEOUT";
   }
   return "unknown";
 }

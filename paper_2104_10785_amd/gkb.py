@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgkb.so")
 
 GKB_F64, GKB_F32, GKB_BF16 = 0, 1, 2
 STATUS = {0: "GKB_OK", 1: "GKB_NOT_CONVERGED", 2: "GKB_RANK_DEFICIENT", -1: "GKB_ERR_INVALID",
-          -2: "GKB_ERR_HIP", -3: "GKB_ERR_NUMERIC", -4: "GKB_ERR_WORKSPACE"}
+          -2: "GKB_ERR_HIP", -3: "GKB_ERR_NUMERIC", -4: "GKB_ERR_WORKSPACE", -5: "GKB_ERR_TIMEOUT"}
 
 
 class GkbError(RuntimeError):
@@ -40,7 +40,7 @@ class GkbOptions(C.Structure):
 class GkbBatchOptions(C.Structure):
     _fields_ = [("check_every", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
                 ("seed", C.c_uint64), ("q1_packed", C.c_void_p), ("workgroups", C.c_int), ("no_graph", C.c_int),
-                ("threads", C.c_int)]
+                ("threads", C.c_int), ("max_team", C.c_int)]
 
 
 class GkbStats(C.Structure):
@@ -428,7 +428,7 @@ class BatchPlan:
     """
 
     def __init__(self, As, r, k, tol, max_restarts, check_every=0, seed=0, q1=None, workgroups=0,
-                 no_graph=False, eps_break=0.0, threads=0, stream=None, tune=False, tune_cache=None):
+                 no_graph=False, eps_break=0.0, threads=0, stream=None, tune=False, tune_cache=None, max_team=0):
         torch = _torch()
         L = lib()
         self.batch = len(As)
@@ -454,6 +454,7 @@ class BatchPlan:
         o.no_graph = 1 if no_graph else 0
         o.eps_break = eps_break
         o.threads = threads
+        o.max_team = max_team
         self.q1 = q1
         if q1 is not None:
             o.q1_packed = q1.data_ptr()
