@@ -300,6 +300,19 @@ def default_keep(r: int, k: int) -> int:
     return min(r + (k - r) // 2, k - 1)
 
 
+def as_operator(A):
+    """A in float64: a dense array, or a scipy.sparse matrix kept sparse (the
+    method touches A only through the products A x and A^T y, eq. (2.1)-(2.2),
+    so a sparse A goes through unchanged; the paper allows either kind)."""
+    try:
+        import scipy.sparse as sp
+        if sp.issparse(A):
+            return sp.csr_matrix(A, dtype=np.float64)
+    except ImportError:
+        pass
+    return np.asarray(A, dtype=np.float64)
+
+
 def default_eps_break(dtype_name: str = "f64") -> float:
     """Relative breakdown threshold: 1e-12 for float64 work, 1e-6 for float32."""
     return 1e-12 if dtype_name == "f64" else 1e-6
@@ -323,7 +336,7 @@ def partial_svd(A, r: int, k: int, tol: float, max_restarts: int, q: np.ndarray,
     r' = r unless A has fewer than r singular values above the breakdown
     threshold (status RANK_DEFICIENT).
     """
-    A = np.asarray(A, dtype=np.float64)
+    A = as_operator(A)
     q = np.asarray(q, dtype=np.float64)
     m, n = A.shape
     if not (1 <= r <= k <= min(m, n)):

@@ -10,12 +10,14 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/gkb.h"
 #include "../../include/gkb_kernels.h"
 #include "gkb_internal.h"
 #include "kernels.h"
+#include "sparse.h"
 
 namespace {
 
@@ -50,7 +52,8 @@ struct Layout {
   size_t total = 0;
 };
 
-Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool small, bool refine = false) {
+Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool small, bool refine = false,
+                   bool dense = true) {
   Layout L;
   const size_t tb = basis_bytes(dt);
   const size_t acc = dt == GKB_F64 ? 8 : 4;
@@ -77,7 +80,7 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
   L.z = take((size_t)L.ldn * 8);
   // gemv_t partial sums: at most GEMV_T_MAX_BLOCKS row blocks, and no more
   // than one per 64 rows (the launch never uses more)
-  const int64_t part_rows = std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (m + 63) / 64);
+  const int64_t part_rows = dense ? std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (m + 63) / 64) : 0;
   L.ldpart = L.ldn;
   L.part = take((size_t)part_rows * L.ldpart * acc);
   const int nch = std::max(gkb::dots_chunks(m), gkb::dots_chunks(n));
@@ -143,6 +146,7 @@ struct Proj {
 template <typename TB>
 struct Solver {
   gkb::MatrixRef A;
+  const gkb::SparseRef* sp = nullptr;   // sparse A: products through the CSR kernels
   hipStream_t st;
   Layout L;
   char* ws;
@@ -169,6 +173,20 @@ struct Solver {
   TB* Ys() { return reinterpret_cast<TB*>(ws + L.Ys); }
   double* rho() { return reinterpret_cast<double*>(ws + L.rho); }
   double* q1buf() { return reinterpret_cast<double*>(ws + L.q1); }
+
+  // w = A p - coef[cidx] qprev and z = A^T q - coef[cidx] pprev (dense or sparse A)
+  hipError_t prod_n(const TB* p, const TB* qprev, const double* coef, int cidx, double* out) {
+    if constexpr (std::is_same<TB, float>::value) {
+      if (sp) return gkb::launch_spmv(sp->fwd, p, qprev, coef, cidx, out, flag(), st);
+    }
+    return gkb::launch_gemv_n<TB>(A, p, qprev, coef, cidx, out, flag(), st);
+  }
+  hipError_t prod_t(const TB* q, const TB* pprev, const double* coef, int cidx, double* out) {
+    if constexpr (std::is_same<TB, float>::value) {
+      if (sp) return gkb::launch_spmv(sp->tr, q, pprev, coef, cidx, out, flag(), st);
+    }
+    return gkb::launch_gemv_t<TB>(A, q, pprev, coef, cidx, out, part(), L.ldpart, flag(), st);
+  }
 
   // Two classical Gram-Schmidt passes of x against V[:, 0..t); the last
   // update leaves the partial sums of ||x||^2 in normpart.
@@ -216,7 +234,7 @@ struct Solver {
     GKB_HIP(hipMemcpyAsync(w(), q1, (size_t)A.m * sizeof(double), hipMemcpyDeviceToDevice, st));
     GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.m, w(), h(), normpart(), flag(), st));
     GKB_HIP(normalize(w(), A.m, Qc(0), qcoef(), 0, 1, 0, false));
-    GKB_HIP(gkb::launch_gemv_t<TB>(A, Qc(0), nullptr, nullptr, 0, z(), part(), L.ldpart, flag(), st));
+    GKB_HIP(prod_t(Qc(0), nullptr, nullptr, 0, z()));
     GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.n, z(), h(), normpart(), flag(), st));
     GKB_HIP(normalize(z(), A.n, Pc(0), pcoef(), 1, 2, 0, false));
     return GKB_OK;
@@ -226,10 +244,10 @@ struct Solver {
   //   w = A p_s - alpha_s q_s -> CGS2 vs Q[0..s] -> q_{s+1}, beta
   //   z = A^T q_{s+1} - beta p_s -> CGS2 vs P[0..s] -> p_{s+1}, alpha
   gkb_status first_step(int s) {
-    GKB_HIP(gkb::launch_gemv_n<TB>(A, Pc(s), Qc(s), pcoef(), s, w(), flag(), st));
+    GKB_HIP(prod_n(Pc(s), Qc(s), pcoef(), s, w()));
     GKB_HIP(cgs2(Q(cur), L.ldm, s + 1, A.m, w()));
     GKB_HIP(normalize(w(), A.m, Qc(s + 1), qcoef() + s + 1, 1, 1, s + 1, true));
-    GKB_HIP(gkb::launch_gemv_t<TB>(A, Qc(s + 1), Pc(s), qcoef(), s + 1, z(), part(), L.ldpart, flag(), st));
+    GKB_HIP(prod_t(Qc(s + 1), Pc(s), qcoef(), s + 1, z()));
     GKB_HIP(cgs2(P(cur), L.ldn, s + 1, A.n, z()));
     GKB_HIP(normalize(z(), A.n, Pc(s + 1), pcoef() + s + 1, 1, 2, s + 1, true));
     return GKB_OK;
@@ -442,17 +460,18 @@ gkb_status refine_bf16<double>(Solver<double>&, const gkb_matrix*, const Proj&, 
 template <typename TB>
 gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int max_restarts,
                            const gkb_options& opt, void* workspace, double* sigma, TB* U, TB* V,
-                           gkb_stats* stats, hipStream_t st) {
+                           gkb_stats* stats, hipStream_t st, const gkb::SparseRef* sp = nullptr) {
   const double t0 = now_ms();
   double ms_host = 0.0;
   Solver<TB> S;
   S.A = {Am->data, Am->m, Am->n, Am->lda, (int)Am->dtype};
+  S.sp = sp;
   S.st = st;
   const int l = opt.keep ? opt.keep : std::min(r + (k - r) / 2, k - 1);
   if (k == r) max_restarts = 0;
   const int every = opt.check_every > 0 ? opt.check_every : 0;
   const bool refine = Am->dtype == GKB_BF16 && Am->refine_f32 != nullptr;
-  S.L = make_layout(Am->m, Am->n, Am->dtype, k, k > r, true, refine);
+  S.L = make_layout(Am->m, Am->n, Am->dtype, k, k > r, true, refine, sp == nullptr);
   S.ws = reinterpret_cast<char*>(workspace);
   S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
   S.relative = opt.eps_relative ? 1 : 0;
@@ -484,14 +503,12 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
         if (rc != GKB_OK) return rc;
       } else {
         // w = A p_j - (j == l ? Q~ rho : alpha_j q_{j-1})
-        GKB_HIP(gkb::launch_gemv_n<TB>(S.A, S.Pc(j), j == l ? nullptr : S.Qc(j - 1), S.pcoef(), j, S.w(),
-                                       S.flag(), st));
+        GKB_HIP(S.prod_n(S.Pc(j), j == l ? nullptr : S.Qc(j - 1), S.pcoef(), j, S.w()));
         if (j == l)
           GKB_HIP(gkb::launch_update<TB>(S.Q(S.cur), S.L.ldm, l, Am->m, S.w(), S.rho(), nullptr, S.flag(), st));
         GKB_HIP(S.cgs2(S.Q(S.cur), S.L.ldm, j, Am->m, S.w()));
         GKB_HIP(S.normalize(S.w(), Am->m, S.Qc(j), S.qcoef() + j, 1, 1, j, true));
-        GKB_HIP(gkb::launch_gemv_t<TB>(S.A, S.Qc(j), S.Pc(j), S.qcoef(), j, S.z(), S.part(), S.L.ldpart,
-                                       S.flag(), st));
+        GKB_HIP(S.prod_t(S.Qc(j), S.Pc(j), S.qcoef(), j, S.z()));
         GKB_HIP(S.cgs2(S.P(S.cur), S.L.ldn, j + 1, Am->n, S.z()));
         GKB_HIP(S.normalize(S.z(), Am->n, S.Pc(j + 1), S.pcoef() + j + 1, 1, 2, j + 1, true));
       }
@@ -758,6 +775,40 @@ gkb_status gkb_numerical_rank(const gkb_matrix* A, double tau, int tau_relative,
                             stats, st);
   return run_rank<float>(A, tau, tau_relative, (int)k, opt, workspace, rank, rank_sturm, sigma_out, nsigma,
                          stats, st);
+}
+
+size_t gkb_sparse_workspace_size(gkb_sparse_plan plan, int r, int k) {
+  if (!plan) return 0;
+  const gkb::SparseRef& R = plan->ref;
+  if (r < 1 || k < r || k > std::min(R.m, R.n)) return 0;
+  return make_layout(R.m, R.n, GKB_F32, k, k > r, true, false, false).total;
+}
+
+gkb_status gkb_partial_svd_sparse(gkb_sparse_plan plan, int r, int k, double tol, int max_restarts,
+                                  const gkb_options* opt_in, void* workspace, size_t ws_bytes, double* sigma,
+                                  float* U, float* V, gkb_stats* stats, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(GKB_ERR_INVALID, "sparse plan is NULL");
+  const gkb::SparseRef& R = plan->ref;
+  if (r < 1 || k < r || k > std::min(R.m, R.n)) return fail(GKB_ERR_INVALID, "need 1 <= r <= k <= min(m, n)");
+  if (!(tol >= 0.0) || max_restarts < 0) return fail(GKB_ERR_INVALID, "need tol >= 0 and max_restarts >= 0");
+  if (!sigma || !U || !V) return fail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
+  gkb_options opt;
+  gkb_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.keep != 0 && (opt.keep < r || opt.keep >= k)) return fail(GKB_ERR_INVALID, "need r <= keep < k");
+  if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
+  if (opt.check_every < 0) return fail(GKB_ERR_INVALID, "need check_every >= 0");
+  gkb_status rc = check_workspace(workspace, ws_bytes, gkb_sparse_workspace_size(plan, r, k));
+  if (rc != GKB_OK) return rc;
+  // the dense descriptor only carries the shape and the float32 basis type
+  gkb_matrix Am{};
+  Am.m = R.m;
+  Am.n = R.n;
+  Am.lda = R.n;
+  Am.dtype = GKB_F32;
+  return run_partial_svd<float>(&Am, r, k, tol, max_restarts, opt, workspace, sigma, U, V, stats,
+                                reinterpret_cast<hipStream_t>(stream), &R);
 }
 
 const char* gkb_status_string(gkb_status s) {

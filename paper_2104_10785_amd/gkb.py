@@ -43,6 +43,12 @@ class GkbBatchOptions(C.Structure):
                 ("threads", C.c_int), ("max_team", C.c_int)]
 
 
+class GkbCsr(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p), ("col_ptr", C.c_void_p), ("row_idx", C.c_void_p),
+                ("val_t", C.c_void_p)]
+
+
 class GkbStats(C.Structure):
     _fields_ = [("nconv", C.c_int), ("restarts", C.c_int), ("breakdown", C.c_int), ("returned", C.c_int),
                 ("matvecs", C.c_int64), ("max_res_est", C.c_double), ("sigma1_est", C.c_double),
@@ -64,7 +70,9 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_partial_svd_batched", "gkb_batched_last_error", "gkb_batched_autotune",
            "gkb_mlp_param_count", "gkb_mlp_feature_stride", "gkb_mlp_workspace_size", "gkb_mlp_features",
            "gkb_mlp_forward", "gkb_mlp_loss_grad", "gkb_adam_step", "gkb_mlp_start_vector",
-           "gkb_learned_last_error"]
+           "gkb_learned_last_error", "gkb_sparse_plan_workspace_size", "gkb_sparse_plan_create",
+           "gkb_sparse_plan_destroy", "gkb_sparse_matvec", "gkb_sparse_workspace_size", "gkb_partial_svd_sparse",
+           "gkb_sparse_last_error"]
 
 
 def lib():
@@ -168,6 +176,22 @@ def lib():
     L.gkb_mlp_start_vector.restype = C.c_int
     L.gkb_learned_last_error.argtypes = []
     L.gkb_learned_last_error.restype = C.c_char_p
+    L.gkb_sparse_plan_workspace_size.argtypes = [P(GkbCsr)]
+    L.gkb_sparse_plan_workspace_size.restype = C.c_size_t
+    L.gkb_sparse_plan_create.argtypes = [P(GkbCsr), C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_void_p)]
+    L.gkb_sparse_plan_create.restype = C.c_int
+    L.gkb_sparse_plan_destroy.argtypes = [C.c_void_p]
+    L.gkb_sparse_plan_destroy.restype = None
+    L.gkb_sparse_matvec.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gkb_sparse_matvec.restype = C.c_int
+    L.gkb_sparse_workspace_size.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    L.gkb_sparse_workspace_size.restype = C.c_size_t
+    L.gkb_partial_svd_sparse.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int, P(GkbOptions),
+                                         C.c_void_p, C.c_size_t, P(C.c_double), C.c_void_p, C.c_void_p,
+                                         P(GkbStats), C.c_void_p]
+    L.gkb_partial_svd_sparse.restype = C.c_int
+    L.gkb_sparse_last_error.argtypes = []
+    L.gkb_sparse_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -616,3 +640,79 @@ def gkb_mlp_start_vector(params, n_in, hidden, X, stream=None):
                                        C.c_void_p(q.data_ptr()), C.c_void_p(wk.data_ptr()), wk.numel(),
                                        _stream(stream)))
     return q
+
+
+class SparsePlan:
+    """A sparse float32 matrix on the device (CSR of A and of A^T) with its row
+    bins (gkb_sparse_plan_*).  `arrays` holds row_ptr (int64), col_idx (int32),
+    val (float32), col_ptr, row_idx, val_t as numpy arrays or device tensors."""
+
+    def __init__(self, m, n, arrays, device="cuda:0", stream=None):
+        torch = _torch()
+        self.m, self.n = int(m), int(n)
+        self.t = {}
+        for key, dt in (("row_ptr", torch.int64), ("col_idx", torch.int32), ("val", torch.float32),
+                        ("col_ptr", torch.int64), ("row_idx", torch.int32), ("val_t", torch.float32)):
+            a = arrays[key]
+            if not torch.is_tensor(a):
+                a = torch.from_numpy(np.ascontiguousarray(a))
+            self.t[key] = a.to(device=device, dtype=dt).contiguous()
+        self.nnz = int(self.t["val"].numel())
+        self.csr = GkbCsr(self.m, self.n, self.nnz, *[C.c_void_p(self.t[k].data_ptr()) for k in
+                                                       ("row_ptr", "col_idx", "val", "col_ptr", "row_idx", "val_t")])
+        self.device = torch.device(device)
+        L = lib()
+        need = L.gkb_sparse_plan_workspace_size(C.byref(self.csr))
+        if need == 0:
+            raise GkbError(-1, "invalid sparse matrix")
+        self.ws = _workspace(need, self.device)
+        plan = C.c_void_p()
+        st = L.gkb_sparse_plan_create(C.byref(self.csr), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                      _stream(stream), C.byref(plan))
+        if st != 0:
+            raise GkbError(st, L.gkb_sparse_last_error().decode())
+        self.plan = plan
+
+    def matvec(self, x, trans=0, y=None, stream=None):
+        """y = A x (trans 0) or A^T x (trans 1); x float32, y float64 device tensors."""
+        torch = _torch()
+        if y is None:
+            y = torch.empty(self.n if trans else self.m, dtype=torch.float64, device=self.device)
+        st = lib().gkb_sparse_matvec(self.plan, int(trans), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                     _stream(stream))
+        if st != 0:
+            raise GkbError(st, lib().gkb_sparse_last_error().decode())
+        return y
+
+    def workspace_size(self, r, k):
+        return int(lib().gkb_sparse_workspace_size(self.plan, r, k))
+
+    def partial_svd(self, r, k, tol, max_restarts, workspace=None, stream=None, **opts):
+        """As gkb_partial_svd: (sigma, Ut, Vt, status, stats)."""
+        torch = _torch()
+        L = lib()
+        o = make_options(**opts)
+        need = self.workspace_size(r, k)
+        if workspace is None:
+            workspace = _workspace(need, self.device)
+        Ut = torch.empty((r, self.m), dtype=torch.float32, device=self.device)
+        Vt = torch.empty((r, self.n), dtype=torch.float32, device=self.device)
+        sig = (C.c_double * r)()
+        st = GkbStats()
+        status = L.gkb_partial_svd_sparse(self.plan, int(r), int(k), float(tol), int(max_restarts), C.byref(o),
+                                          C.c_void_p(workspace.data_ptr()), workspace.numel(), sig,
+                                          C.c_void_p(Ut.data_ptr()), C.c_void_p(Vt.data_ptr()), C.byref(st),
+                                          _stream(stream))
+        _check(status)
+        return np.array(sig[:], dtype=np.float64), Ut, Vt, status, st.as_dict()
+
+    def close(self):
+        if getattr(self, "plan", None):
+            lib().gkb_sparse_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

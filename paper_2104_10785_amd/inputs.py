@@ -19,6 +19,9 @@ Workloads (all synthetic, every seed fixed):
 * ``start_vector``    the N(2, 1) start vector of Algorithm 1.
 * ``batch_problems``  many small uneven matrices with geometric spectra.
 * ``drift_sequence``  a slowly changing matrix sequence A_t = A_{t-1} + dA_t.
+* ``sparse_powerlaw``  a sparse matrix with power-law row and column degrees
+                      (CSR of A and of A^T); ``sparse_permuted_diagonal`` a
+                      sparse matrix with a known spectrum.
 """
 from __future__ import annotations
 
@@ -267,3 +270,66 @@ def mlp_init(n_in: int, hidden: int, seed: int) -> np.ndarray:
     w1 = rng.standard_normal(hidden * n_in) * np.sqrt(2.0 / n_in)
     w2 = rng.standard_normal(hidden) * np.sqrt(1.0 / hidden)
     return np.concatenate([w1, np.zeros(hidden), w2, [0.0]]).astype(np.float32)
+
+
+def _csr_transpose(m: int, n: int, row_ptr: np.ndarray, col_idx: np.ndarray, val: np.ndarray):
+    """CSR arrays of A^T from those of A (entries of a row of A^T in increasing
+    row order of A; pure data movement)."""
+    rows = np.repeat(np.arange(m, dtype=np.int32), np.diff(row_ptr))
+    order = np.argsort(col_idx, kind="stable")
+    col_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(col_idx, minlength=n), out=col_ptr[1:])
+    return col_ptr, rows[order].astype(np.int32), val[order]
+
+
+def sparse_powerlaw(m: int, n: int, nnz: int, seed: int, row_exp: float = 0.6, col_exp: float = 0.5):
+    """A sparse m x n float32 matrix with power-law degrees, as CSR of A and of A^T.
+
+    Row i (in a random order) gets about nnz * w_i / sum(w) entries with
+    w_i = (rank + 1)^-row_exp (rounded down, so some rows are empty; the
+    remainder goes to the heaviest rows); the columns of the entries are drawn
+    independently with probability proportional to (rank + 1)^-col_exp over a
+    random order of the columns; values are N(0, 1).  Duplicate (row, column)
+    pairs can occur and stand for their sum.  Returns a dict with m, n, nnz,
+    row_ptr (int64), col_idx (int32), val (float32), col_ptr, row_idx, val_t.
+    """
+    rng = _rng(seed)
+    w = (np.arange(1, m + 1, dtype=np.float64)) ** (-row_exp)
+    deg = np.floor(nnz * w / w.sum()).astype(np.int64)
+    short = nnz - int(deg.sum())
+    deg[:short] += 1
+    deg = deg[rng.permutation(m)]
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    pc = (np.arange(1, n + 1, dtype=np.float64)) ** (-col_exp)
+    cdf = np.cumsum(pc / pc.sum())
+    cdf[-1] = 1.0
+    col_perm = rng.permutation(n).astype(np.int32)
+    col_idx = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float32)
+    step = 1 << 24
+    for a in range(0, nnz, step):
+        b = min(nnz, a + step)
+        col_idx[a:b] = col_perm[np.minimum(np.searchsorted(cdf, rng.random(b - a)), n - 1)]
+        val[a:b] = rng.standard_normal(b - a).astype(np.float32)
+    col_ptr, row_idx, val_t = _csr_transpose(m, n, row_ptr, col_idx, val)
+    return {"m": m, "n": n, "nnz": nnz, "row_ptr": row_ptr, "col_idx": col_idx, "val": val,
+            "col_ptr": col_ptr, "row_idx": row_idx, "val_t": val_t}
+
+
+def sparse_permuted_diagonal(m: int, n: int, s: np.ndarray, seed: int):
+    """A = P diag(s) Q^T with random permutations P, Q (s of length <= min(m, n)):
+    sparse, one entry per row and column at most, singular values |s| exactly."""
+    rng = _rng(seed)
+    s = np.asarray(s, dtype=np.float32)
+    k = s.size
+    rows = rng.permutation(m)[:k]
+    cols = rng.permutation(n)[:k].astype(np.int32)
+    order = np.argsort(rows, kind="stable")
+    rows, cols, vals = rows[order], cols[order], s[order]
+    deg = np.bincount(rows, minlength=m)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    col_ptr, row_idx, val_t = _csr_transpose(m, n, row_ptr, cols, vals)
+    return {"m": m, "n": n, "nnz": k, "row_ptr": row_ptr, "col_idx": cols, "val": vals,
+            "col_ptr": col_ptr, "row_idx": row_idx, "val_t": val_t}
