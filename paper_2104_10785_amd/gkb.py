@@ -72,7 +72,8 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_mlp_forward", "gkb_mlp_loss_grad", "gkb_adam_step", "gkb_mlp_start_vector",
            "gkb_learned_last_error", "gkb_sparse_plan_workspace_size", "gkb_sparse_plan_create",
            "gkb_sparse_plan_destroy", "gkb_sparse_matvec", "gkb_sparse_workspace_size", "gkb_partial_svd_sparse",
-           "gkb_sparse_last_error"]
+           "gkb_sparse_last_error", "gkb_rsgd_workspace_size", "gkb_rsgd_plan_create", "gkb_rsgd_plan_step",
+           "gkb_rsgd_plan_info", "gkb_rsgd_plan_destroy", "gkb_rsgd_weights", "gkb_rsgd_last_error"]
 
 
 def lib():
@@ -192,6 +193,22 @@ def lib():
     L.gkb_partial_svd_sparse.restype = C.c_int
     L.gkb_sparse_last_error.argtypes = []
     L.gkb_sparse_last_error.restype = C.c_char_p
+    L.gkb_rsgd_workspace_size.argtypes = [C.c_int] * 5
+    L.gkb_rsgd_workspace_size.restype = C.c_size_t
+    L.gkb_rsgd_plan_create.argtypes = [C.c_int] * 5 + [C.c_double, C.c_double] + [C.c_void_p] * 6 + \
+        [C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_void_p)]
+    L.gkb_rsgd_plan_create.restype = C.c_int
+    L.gkb_rsgd_plan_step.argtypes = [C.c_void_p, C.c_void_p]
+    L.gkb_rsgd_plan_step.restype = C.c_int
+    L.gkb_rsgd_plan_info.argtypes = [C.c_void_p, P(C.c_int), C.c_void_p]
+    L.gkb_rsgd_plan_info.restype = C.c_int
+    L.gkb_rsgd_plan_destroy.argtypes = [C.c_void_p]
+    L.gkb_rsgd_plan_destroy.restype = None
+    L.gkb_rsgd_weights.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
+    L.gkb_rsgd_weights.restype = C.c_int
+    L.gkb_rsgd_last_error.argtypes = []
+    L.gkb_rsgd_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -709,6 +726,81 @@ class SparsePlan:
     def close(self):
         if getattr(self, "plan", None):
             lib().gkb_sparse_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RsgdPlan:
+    """Riemannian mini-batch gradient descent on rank-r matrices (gkb_rsgd_*).
+
+    State (device): U (r x d1 float32, rows = the columns of the d1 x r factor),
+    s (r float64), Vt (r x d2 float32): W = U^T diag(s) Vt.  Batch buffers X
+    (b x d1), V (b x d2), y (b) are owned by the plan; `step(X, V, y)` copies a
+    batch in and replays the captured step."""
+
+    def __init__(self, d1, d2, r, k, b, eta, lam, U0, s0, V0, device="cuda:0", stream=None):
+        torch = _torch()
+        self.d1, self.d2, self.r, self.k, self.b = int(d1), int(d2), int(r), int(k), int(b)
+        dev = torch.device(device)
+        self.device = dev
+        self.X = torch.zeros((b, d1), dtype=torch.float32, device=dev)
+        self.V = torch.zeros((b, d2), dtype=torch.float32, device=dev)
+        self.y = torch.zeros(b, dtype=torch.float32, device=dev)
+        self.U = torch.as_tensor(np.ascontiguousarray(np.asarray(U0).T), dtype=torch.float32).to(dev).contiguous()
+        self.s = torch.as_tensor(np.asarray(s0, dtype=np.float64)).to(dev).contiguous()
+        self.Vt = torch.as_tensor(np.ascontiguousarray(np.asarray(V0).T), dtype=torch.float32).to(dev).contiguous()
+        L = lib()
+        need = L.gkb_rsgd_workspace_size(d1, d2, r, k, b)
+        if need == 0:
+            raise GkbError(-1, "invalid RSGD sizes")
+        self.ws = _workspace(need, dev)
+        plan = C.c_void_p()
+        st = L.gkb_rsgd_plan_create(d1, d2, r, k, b, float(eta), float(lam), C.c_void_p(self.X.data_ptr()),
+                                    C.c_void_p(self.V.data_ptr()), C.c_void_p(self.y.data_ptr()),
+                                    C.c_void_p(self.U.data_ptr()), C.c_void_p(self.s.data_ptr()),
+                                    C.c_void_p(self.Vt.data_ptr()), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                    _stream(stream), C.byref(plan))
+        if st != 0:
+            raise GkbError(st, L.gkb_rsgd_last_error().decode())
+        self.plan = plan
+
+    def load(self, X, V, y):
+        self.X.copy_(X, non_blocking=True)
+        self.V.copy_(V, non_blocking=True)
+        self.y.copy_(y, non_blocking=True)
+
+    def step(self, X=None, V=None, y=None, stream=None):
+        if X is not None:
+            self.load(X, V, y)
+        st = lib().gkb_rsgd_plan_step(self.plan, _stream(stream))
+        if st != 0:
+            raise GkbError(st, lib().gkb_rsgd_last_error().decode())
+
+    def info(self, stream=None):
+        out = (C.c_int * 4)()
+        st = lib().gkb_rsgd_plan_info(self.plan, out, _stream(stream))
+        if st != 0:
+            raise GkbError(st, lib().gkb_rsgd_last_error().decode())
+        return list(out)
+
+    def weights(self, stream=None):
+        torch = _torch()
+        W = torch.empty((self.d1, self.d2), dtype=torch.float32, device=self.device)
+        st = lib().gkb_rsgd_weights(self.d1, self.d2, self.r, C.c_void_p(self.U.data_ptr()),
+                                    C.c_void_p(self.s.data_ptr()), C.c_void_p(self.Vt.data_ptr()),
+                                    C.c_void_p(W.data_ptr()), _stream(stream))
+        if st != 0:
+            raise GkbError(st, lib().gkb_rsgd_last_error().decode())
+        return W
+
+    def close(self):
+        if getattr(self, "plan", None):
+            lib().gkb_rsgd_plan_destroy(self.plan)
             self.plan = None
 
     def __del__(self):

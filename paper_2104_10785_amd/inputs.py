@@ -22,6 +22,10 @@ Workloads (all synthetic, every seed fixed):
 * ``sparse_powerlaw``  a sparse matrix with power-law row and column degrees
                       (CSR of A and of A^T); ``sparse_permuted_diagonal`` a
                       sparse matrix with a known spectrum.
+* ``similarity_pairs`` labelled pairs (x, v, y) from two synthetic domains
+                      for the similarity-learning workload, and
+                      ``rank_r_point`` a point W = U diag(s) V^T of the
+                      rank-r manifold.
 """
 from __future__ import annotations
 
@@ -274,12 +278,18 @@ def mlp_init(n_in: int, hidden: int, seed: int) -> np.ndarray:
 
 def _csr_transpose(m: int, n: int, row_ptr: np.ndarray, col_idx: np.ndarray, val: np.ndarray):
     """CSR arrays of A^T from those of A (entries of a row of A^T in increasing
-    row order of A; pure data movement)."""
-    rows = np.repeat(np.arange(m, dtype=np.int32), np.diff(row_ptr))
-    order = np.argsort(col_idx, kind="stable")
-    col_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(np.bincount(col_idx, minlength=n), out=col_ptr[1:])
-    return col_ptr, rows[order].astype(np.int32), val[order]
+    row order of A, repeats kept; pure data movement by a counting sort)."""
+    try:
+        import scipy.sparse as sp
+        A = sp.csr_matrix((val, col_idx, row_ptr), shape=(m, n))
+        T = A.tocsc()          # stable counting sort; keeps repeated entries
+        return T.indptr.astype(np.int64), T.indices.astype(np.int32), T.data.astype(np.float32)
+    except ImportError:
+        rows = np.repeat(np.arange(m, dtype=np.int32), np.diff(row_ptr))
+        order = np.argsort(col_idx, kind="stable")
+        col_ptr = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(np.bincount(col_idx, minlength=n), out=col_ptr[1:])
+        return col_ptr, rows[order].astype(np.int32), val[order]
 
 
 def sparse_powerlaw(m: int, n: int, nnz: int, seed: int, row_exp: float = 0.6, col_exp: float = 0.5):
@@ -287,8 +297,9 @@ def sparse_powerlaw(m: int, n: int, nnz: int, seed: int, row_exp: float = 0.6, c
 
     Row i (in a random order) gets about nnz * w_i / sum(w) entries with
     w_i = (rank + 1)^-row_exp (rounded down, so some rows are empty; the
-    remainder goes to the heaviest rows); the columns of the entries are drawn
-    independently with probability proportional to (rank + 1)^-col_exp over a
+    remainder goes to the heaviest rows); the column of each entry is drawn
+    independently from the continuous power law with density proportional to
+    (x + 1)^-col_exp on [0, n) (inverse CDF, rounded down) mapped through a
     random order of the columns; values are N(0, 1).  Duplicate (row, column)
     pairs can occur and stand for their sum.  Returns a dict with m, n, nnz,
     row_ptr (int64), col_idx (int32), val (float32), col_ptr, row_idx, val_t.
@@ -301,17 +312,17 @@ def sparse_powerlaw(m: int, n: int, nnz: int, seed: int, row_exp: float = 0.6, c
     deg = deg[rng.permutation(m)]
     row_ptr = np.zeros(m + 1, dtype=np.int64)
     np.cumsum(deg, out=row_ptr[1:])
-    pc = (np.arange(1, n + 1, dtype=np.float64)) ** (-col_exp)
-    cdf = np.cumsum(pc / pc.sum())
-    cdf[-1] = 1.0
+    g = 1.0 - col_exp                       # col_exp < 1
+    span = (n + 1.0) ** g - 1.0
     col_perm = rng.permutation(n).astype(np.int32)
     col_idx = np.empty(nnz, dtype=np.int32)
     val = np.empty(nnz, dtype=np.float32)
     step = 1 << 24
     for a in range(0, nnz, step):
         b = min(nnz, a + step)
-        col_idx[a:b] = col_perm[np.minimum(np.searchsorted(cdf, rng.random(b - a)), n - 1)]
-        val[a:b] = rng.standard_normal(b - a).astype(np.float32)
+        x = (1.0 + rng.random(b - a) * span) ** (1.0 / g) - 1.0
+        col_idx[a:b] = col_perm[np.minimum(x.astype(np.int64), n - 1)]
+        val[a:b] = rng.standard_normal(b - a, dtype=np.float32)
     col_ptr, row_idx, val_t = _csr_transpose(m, n, row_ptr, col_idx, val)
     return {"m": m, "n": n, "nnz": nnz, "row_ptr": row_ptr, "col_idx": col_idx, "val": val,
             "col_ptr": col_ptr, "row_idx": row_idx, "val_t": val_t}
@@ -333,3 +344,36 @@ def sparse_permuted_diagonal(m: int, n: int, s: np.ndarray, seed: int):
     col_ptr, row_idx, val_t = _csr_transpose(m, n, row_ptr, cols, vals)
     return {"m": m, "n": n, "nnz": k, "row_ptr": row_ptr, "col_idx": cols, "val": vals,
             "col_ptr": col_ptr, "row_idx": row_idx, "val_t": val_t}
+
+
+def similarity_pairs(count: int, d1: int, d2: int, seed: int, proto_seed: int = 0, classes: int = 10,
+                     same: float = 0.5, noise: float = 1.0):
+    """Labelled pairs from two domains with shared classes (a synthetic stand-in
+    for two image datasets of different sizes).  Class c has a prototype with
+    N(0, 1/d) entries in each domain; a sample of class c is its prototype plus
+    noise * N(0, 1/d) per entry.  A pair takes a class for x and, with
+    probability `same`, the same class for v (label +1), else another class
+    (label -1).  The prototypes come from `proto_seed` (shared by a training
+    and a held-out draw), the samples from `seed`.  Returns X (count x d1),
+    V (count x d2), y (count,) as float32 and the two class vectors."""
+    prng = _rng(proto_seed)
+    px = prng.standard_normal((classes, d1)) / np.sqrt(d1)
+    pv = prng.standard_normal((classes, d2)) / np.sqrt(d2)
+    rng = _rng(seed)
+    cx = rng.integers(0, classes, count)
+    is_same = rng.random(count) < same
+    cv = np.where(is_same, cx, (cx + rng.integers(1, classes, count)) % classes)
+    X = px[cx] + noise * rng.standard_normal((count, d1)) / np.sqrt(d1)
+    V = pv[cv] + noise * rng.standard_normal((count, d2)) / np.sqrt(d2)
+    y = np.where(is_same, 1.0, -1.0)
+    return X.astype(np.float32), V.astype(np.float32), y.astype(np.float32), cx, cv
+
+
+def rank_r_point(d1: int, d2: int, r: int, seed: int, scale: float = 1.0):
+    """W = U diag(s) V^T on the rank-r manifold: Haar U (d1 x r), V (d2 x r),
+    s = scale * sorted |N(0, 1)| + scale (distinct, descending)."""
+    rng = _rng(seed)
+    U = haar(rng, d1, r)
+    V = haar(rng, d2, r)
+    s = scale * (np.sort(np.abs(rng.standard_normal(r)))[::-1] + 1.0)
+    return U, s, V

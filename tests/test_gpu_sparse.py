@@ -127,3 +127,39 @@ def test_sparse_partial_svd_against_oracle(name, r, k, check_every):
         want = np.geomspace(1, 1e-3, 800)[:r]
         assert np.max(np.abs(sig - want) / want) < 1e-6
     plan.close()
+
+
+def test_sparse_fullsize_against_stored_oracle():
+    """The full sparse workload (1000000 x 200000, 5e7 entries, power-law
+    degrees) against the oracle's stored top 20 (written by
+    tests/golden/make_sparse_reference.py from oracle code only), plus the
+    residuals of the returned triplets computed in float64 on the host."""
+    import json
+    import os
+    import scipy.sparse.linalg  # noqa: F401
+    device()
+    path = os.path.join(os.path.dirname(__file__), "golden", "sparse_oracle_top20.json")
+    ref = json.load(open(path))
+    banner("sparse full size 1000000x200000 nnz 5e7, r=20 k=60 check_every=5")
+    S = inputs.sparse_powerlaw(1000000, 200000, 50000000, seed=7)
+    plan = gkb.SparsePlan(1000000, 200000, S)
+    q = inputs.start_vector(1000000, seed=8)
+    sig, Ut, Vt, status, st = plan.partial_svd(20, 60, 1e-6, 50, q1=to_dev(q), check_every=5)
+    A = csr_of(S)
+    del S
+    want = np.array(ref["sigma"])
+    bound = bound32(A)
+    err = np.max(np.abs(sig - want))
+    print(f"  sparse full size: sigma err {err:.2e} (bound {bound:.2e}), matvecs {st['matvecs']} "
+          f"(oracle {ref['matvecs']}), restarts {st['restarts']} (oracle {ref['restarts']})", flush=True)
+    assert status == ref["status"] == 0
+    assert err <= bound
+    assert abs(st["restarts"] - ref["restarts"]) <= 1
+    U = to_host(Ut).T.astype(np.float64)
+    V = to_host(Vt).T.astype(np.float64)
+    r1 = np.linalg.norm(A @ V - U * sig, axis=0)
+    r2 = np.linalg.norm(A.T @ U - V * sig, axis=0)
+    print(f"  residuals ||Av - su|| {r1.max():.2e}, ||A^T u - s v|| {r2.max():.2e} (tol s1 {1e-6 * sig[0]:.2e})",
+          flush=True)
+    assert r1.max() <= 100 * bound and r2.max() <= 1e-6 * sig[0] + 100 * bound
+    plan.close()
