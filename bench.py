@@ -251,6 +251,88 @@ def batched_leg(gkb, inputs, torch, dev, stream):
     return out
 
 
+SPARSE_M, SPARSE_N, SPARSE_NNZ, SPARSE_SEED, SPARSE_QSEED = 1000000, 200000, 50000000, 7, 8
+SPARSE_R, SPARSE_K, SPARSE_EVERY = 20, 60, 5
+
+
+def sparse_leg(gkb, inputs, torch, dev, stream, steps):
+    """Sparse A (CSR of A and of A^T, power-law degrees): the partial SVD and the
+    two binned CSR products, timed with HIP events on the launch stream."""
+    S = inputs.sparse_powerlaw(SPARSE_M, SPARSE_N, SPARSE_NNZ, seed=SPARSE_SEED)
+    plan = gkb.SparsePlan(SPARSE_M, SPARSE_N, S, device=dev, stream=stream)
+    del S
+    q = torch.from_numpy(inputs.start_vector(SPARSE_M, seed=SPARSE_QSEED)).to(dev)
+    ws = torch.empty(plan.workspace_size(SPARSE_R, SPARSE_K), dtype=torch.uint8, device=dev)
+    run = lambda: plan.partial_svd(SPARSE_R, SPARSE_K, 1e-6, 50, workspace=ws, stream=stream, q1=q,
+                                   check_every=SPARSE_EVERY)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sig, _, _, status, st = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    xn = torch.randn(SPARSE_N, dtype=torch.float32, device=dev)
+    xm = torch.randn(SPARSE_M, dtype=torch.float32, device=dev)
+    yn = torch.empty(SPARSE_M, dtype=torch.float64, device=dev)
+    ym = torch.empty(SPARSE_N, dtype=torch.float64, device=dev)
+    ms_n = time_kernel(lambda: plan.matvec(xn, 0, y=yn, stream=stream), 20, stream)
+    ms_t = time_kernel(lambda: plan.matvec(xm, 1, y=ym, stream=stream), 20, stream)
+    # algorithmic bytes: every (index, value) pair once, the offsets, the output
+    # (float64) and the input vector once
+    b_n = SPARSE_NNZ * 8 + (SPARSE_M + 1) * 8 + SPARSE_M * 8 + SPARSE_N * 4
+    b_t = SPARSE_NNZ * 8 + (SPARSE_N + 1) * 8 + SPARSE_N * 8 + SPARSE_M * 4
+    out = {"workload": f"sparse power-law {SPARSE_M}x{SPARSE_N}, nnz {SPARSE_NNZ}, f32 CSR + CSR of A^T; "
+                       f"top {SPARSE_R}, k {SPARSE_K}, tol 1e-6, checks every {SPARSE_EVERY}",
+           "ms": ms, "triplets_per_s": st["nconv"] / (ms / 1000.0), "status": status, "matvecs": st["matvecs"],
+           "restarts": st["restarts"], "spmv_ms": ms_n, "spmv_GBps": b_n / (ms_n * 1e-3) / 1e9,
+           "spmv_t_ms": ms_t, "spmv_t_GBps": b_t / (ms_t * 1e-3) / 1e9, "sigma1": float(sig[0])}
+    plan.close()
+    return out
+
+
+RSGD_D1, RSGD_D2, RSGD_R, RSGD_B, RSGD_ETA, RSGD_LAM = 784, 256, 5, 64, 2.0, 1e-3
+
+
+def rsgd_leg(gkb, inputs, torch, dev, stream):
+    """Riemannian similarity learning (rank 5, 784 x 256, batches of 64): steps/s of
+    the captured step (projection products + batched-solver retraction) for
+    Krylov dimensions 20 and 35, held-out accuracy, and the float64 oracle's
+    time per step on the host for context."""
+    from oracle import rsgd
+    steps = 300
+    X, V, y, _, _ = inputs.similarity_pairs(steps * RSGD_B, RSGD_D1, RSGD_D2, seed=1)
+    Xt, Vt, yt, _, _ = inputs.similarity_pairs(4000, RSGD_D1, RSGD_D2, seed=2)
+    U0, s0, V0 = inputs.rank_r_point(RSGD_D1, RSGD_D2, RSGD_R, seed=3, scale=0.01)
+    Xd = torch.from_numpy(X).to(dev)
+    Vd = torch.from_numpy(V).to(dev)
+    yd = torch.from_numpy(y).to(dev)
+    out = {"workload": f"similarity learning, W {RSGD_D1}x{RSGD_D2} rank {RSGD_R}, batch {RSGD_B}, eta {RSGD_ETA}, "
+                       f"lambda {RSGD_LAM}, synthetic two-domain pairs (10 classes)"}
+    for k in (20, 35):
+        plan = gkb.RsgdPlan(RSGD_D1, RSGD_D2, RSGD_R, k, RSGD_B, RSGD_ETA, RSGD_LAM, U0, s0, V0, device=dev,
+                            stream=stream)
+        plan.step(Xd[:RSGD_B], Vd[:RSGD_B], yd[:RSGD_B], stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(1, steps):
+            sl = slice(t * RSGD_B, (t + 1) * RSGD_B)
+            plan.step(Xd[sl], Vd[sl], yd[sl], stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / (steps - 1)
+        W = plan.weights(stream=stream).double().cpu().numpy()
+        out[f"k{k}"] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms, "status": plan.info(stream)[0],
+                        "heldout_accuracy": rsgd.accuracy(Xt, Vt, yt, W)}
+        plan.close()
+    t0 = time.perf_counter()
+    U, s, Vf = U0, s0, V0
+    for t in range(5):
+        sl = slice(t * RSGD_B, (t + 1) * RSGD_B)
+        U, s, Vf, _, _ = rsgd.step(X[sl], V[sl], y[sl], U, s, Vf, RSGD_ETA, RSGD_LAM)
+    out["oracle_ms_per_step_host"] = (time.perf_counter() - t0) * 1000.0 / 5
+    return out
+
+
 def learned_leg(dev):
     """Learned start on the drifting 20000 x 5000 sequence (train on solves 1-100,
     evaluate on 101-200 against the random and the heuristic start)."""
@@ -269,7 +351,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
-    ap.add_argument("--legs", default="bf16,rank,batched,learned",
+    ap.add_argument("--legs", default="bf16,rank,batched,learned,sparse,rsgd",
                     help="extra legs after the main timing (comma list; empty for none)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the two matvec kernels and a 1 GiB copy (for counter runs)")
@@ -353,6 +435,10 @@ def main():
             legs["batched"] = batched_leg(gkb, inputs, torch, dev, stream)
         elif leg == "learned":
             legs["learned_start"] = learned_leg(dev)
+        elif leg == "sparse":
+            legs["sparse"] = sparse_leg(gkb, inputs, torch, dev, stream, args.steps)
+        elif leg == "rsgd":
+            legs["rsgd"] = rsgd_leg(gkb, inputs, torch, dev, stream)
         log(f"leg {leg} done: {json.dumps(legs)[-300:]}")
 
     cpu = None

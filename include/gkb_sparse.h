@@ -11,7 +11,7 @@
  * vectors, the convergence rule, statuses and statistics) is the float32
  * path of gkb_partial_svd (gkb.h).
  *
- * A plan bins the rows of A and of A^T by length (<= 16, <= 128, <= 1024,
+ * A plan bins the rows of A and of A^T by length (<= 32, <= 256, <= 2048,
  * longer) so that each bin runs with a matching number of lanes per row
  * (4, 16, 64 or a 256-thread workgroup); the bins keep row order.  Every row
  * sum has a fixed order, so results are bitwise reproducible.

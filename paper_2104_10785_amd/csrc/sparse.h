@@ -1,4 +1,5 @@
-// Sparse products (internal): row bins and the binned CSR product kernels.
+// Sparse products (internal): the row schedule of a CSR matrix and the
+// product kernels that follow it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,21 +10,30 @@
 
 namespace gkb {
 
-constexpr int SP_BINS = 4;          // row lengths <= 16, <= 128, <= 1024, longer
-constexpr int SP_CHUNK = 1024;      // rows per block of the binning kernels
+constexpr int SP_SHORT = 256;     // rows up to this length go through the stream blocks
+constexpr int SP_BLOCK_NNZ = 2048;  // entries of one stream block (at most SP_SHORT rows)
+constexpr int SP_HUGE = 4096;     // rows longer than this are split into chunks of this many entries
 
-// One direction: the CSR arrays of A (rows = m) or of A^T (rows = n), and its
-// rows listed bin by bin (row order kept inside a bin).
+// One direction: the CSR arrays of A (rows = m) or of A^T (rows = n) and its
+// schedule, built on the host from the row offsets when the plan is made:
+//  * stream blocks: runs of consecutive short rows holding at most
+//    SP_BLOCK_NNZ entries (first row, row count), one workgroup each;
+//  * wave rows: rows of SP_SHORT + 1 .. SP_HUGE entries, one wave each;
+//  * huge rows: longer rows, cut into chunks of SP_HUGE entries whose partial
+//    sums are added in chunk order.
 struct SparseDir {
   const int64_t* ptr = nullptr;
   const int32_t* idx = nullptr;
   const float* val = nullptr;
   int64_t rows = 0, cols = 0;
-  int32_t* list = nullptr;          // device, rows entries
-  int64_t* cnt = nullptr;           // device, chunks x SP_BINS counts, then offsets
-  int64_t* tot = nullptr;           // device, SP_BINS totals and the invalid-entry count
-  int64_t count[SP_BINS] = {0, 0, 0, 0};   // host copies of the bin sizes
-  int64_t base[SP_BINS] = {0, 0, 0, 0};
+  int32_t* sblk = nullptr;     // 2 x nsblk
+  int32_t* wrow = nullptr;     // nwrow
+  int32_t* hrow = nullptr;     // nhrow
+  int32_t* hfirst = nullptr;   // nhrow + 1: first chunk of each huge row
+  int32_t* crow = nullptr;     // nchunk: the huge row of each chunk
+  int64_t* cbeg = nullptr;     // nchunk: first entry of each chunk
+  float* part = nullptr;       // nchunk partial sums
+  int64_t nsblk = 0, nwrow = 0, nhrow = 0, nchunk = 0;
 };
 
 struct SparseRef {
@@ -31,13 +41,8 @@ struct SparseRef {
   SparseDir fwd, tr;
 };
 
-// bytes of one direction's bin arrays
-size_t sparse_dir_bytes(int64_t rows);
-// place a direction's arrays at ws (sparse_dir_bytes(rows) bytes)
-void sparse_dir_place(SparseDir& D, char* ws);
-// bin the rows of D on the device and count invalid offsets / indices into
-// tot[SP_BINS] (the bin totals go to tot[0 .. SP_BINS))
-hipError_t launch_sparse_bins(SparseDir& D, int64_t nnz, hipStream_t st);
+// upper bound of the device bytes of one direction's schedule
+size_t sparse_dir_bytes(int64_t rows, int64_t nnz);
 // y[row] = sum_j val[j] x[idx[j]] - coef[cidx] * prev[row] for every row
 // (prev may be null); skipped when flag[0] != 0
 hipError_t launch_spmv(const SparseDir& D, const float* x, const float* prev, const double* coef, int cidx,

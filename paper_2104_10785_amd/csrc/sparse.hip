@@ -1,19 +1,25 @@
-// Products with a sparse A (CSR of A for A p, CSR of A^T for A^T q) and the
-// row binning they use.  The bidiagonalization only touches A through these
-// two products (eq. (2.1)-(2.2)); the rest of the solver is shared with the
-// dense path.
+// Products with a sparse A (CSR of A for A p, CSR of A^T for A^T q).  The
+// bidiagonalization only touches A through these two products
+// (eq. (2.1)-(2.2)); the rest of the solver is shared with the dense path.
 //
-// A row of length L is summed by G lanes (G = 4, 16, 64 by bin, or a
-// 256-thread workgroup for the longest rows): lane l takes entries
-// l, l + G, ..., the G partial sums meet in a fixed butterfly, so the result
-// of a row does not depend on the launch.  Rows are listed bin by bin in row
-// order, so neighbouring lanes read neighbouring rows.
+// Schedule (built on the host from the row offsets when the plan is made):
+//  * short rows (<= SP_SHORT entries) are packed, in row order, into stream
+//    blocks of consecutive rows with at most SP_BLOCK_NNZ entries: a workgroup
+//    reads the block's index/value range with coalesced loads, gathers x and
+//    leaves the products in LDS, then one thread per row adds its products in
+//    order;
+//  * medium rows (<= SP_HUGE) get a wave each: lane l takes entries
+//    l, l + 64, ..., the 64 partial sums meet in a fixed butterfly;
+//  * huge rows are cut into chunks of SP_HUGE entries, one workgroup per chunk,
+//    and the chunk sums are added in chunk order.
+// Every row sum has a fixed order, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "sparse.h"
 
@@ -21,143 +27,141 @@ namespace gkb {
 
 namespace {
 
-constexpr int SP_T = 256;                    // threads per block
-constexpr int SP_RPT = SP_CHUNK / SP_T;      // rows per thread in the binning kernels (4)
+constexpr int SP_T = 256;   // threads per workgroup
+constexpr int SP_EPT = SP_BLOCK_NNZ / SP_T;   // entries per thread in a stream block (8)
 
-__device__ __forceinline__ int row_bin(int64_t len) {
-  return len <= 16 ? 0 : (len <= 128 ? 1 : (len <= 1024 ? 2 : 3));
-}
-
-constexpr int SP_COLS = SP_BINS + 1;          // per-chunk counts: the bins, then invalid rows
-
-// cnt[c * SP_COLS + b] = rows of chunk c in bin b; cnt[c * SP_COLS + SP_BINS] =
-// rows whose offsets are outside [0, nnz] or decreasing
-__global__ __launch_bounds__(SP_T) void k_bin_count(const int64_t* __restrict__ ptr, int64_t rows, int64_t nnz,
-                                                     int64_t* __restrict__ cnt) {
-  __shared__ int c[SP_COLS];
-  if (threadIdx.x < SP_COLS) c[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * SP_CHUNK + threadIdx.x * SP_RPT;
-  int mine[SP_COLS] = {0, 0, 0, 0, 0};
-  for (int u = 0; u < SP_RPT; ++u) {
-    const int64_t r = r0 + u;
-    if (r < rows) {
-      const int64_t b = ptr[r], e = ptr[r + 1];
-      ++mine[row_bin(e - b)];
-      if (b < 0 || e < b || e > nnz) ++mine[SP_BINS];
-    }
-  }
-  for (int b = 0; b < SP_COLS; ++b)
-    if (mine[b]) atomicAdd(&c[b], mine[b]);   // integer counts: order does not matter
-  __syncthreads();
-  if (threadIdx.x < SP_COLS) cnt[(int64_t)blockIdx.x * SP_COLS + threadIdx.x] = c[threadIdx.x];
-}
-
-// tot[SP_BINS] += indices outside [0, cols)
-__global__ __launch_bounds__(SP_T) void k_check_idx(const int32_t* __restrict__ idx, int64_t nnz, int64_t cols,
-                                                     int64_t* __restrict__ tot) {
-  int64_t bad = 0;
-  for (int64_t j = (int64_t)blockIdx.x * SP_T + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * SP_T)
-    bad += (idx[j] < 0 || idx[j] >= cols) ? 1 : 0;
-  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
-  if ((threadIdx.x & 63) == 0 && bad) atomicAdd((unsigned long long*)&tot[SP_BINS], (unsigned long long)bad);
-}
-
-// In place: cnt[c * SP_COLS + b] <- rows of bin b in chunks before c; tot[b] = rows of
-// bin b (b = SP_BINS: invalid rows).
-__global__ void k_bin_scan(int64_t* __restrict__ cnt, int64_t nchunks, int64_t* __restrict__ tot) {
-  const int b = threadIdx.x;
-  if (b >= SP_COLS) return;
-  int64_t s = 0;
-  for (int64_t c = 0; c < nchunks; ++c) {
-    const int64_t v = cnt[c * SP_COLS + b];
-    cnt[c * SP_COLS + b] = s;
-    s += v;
-  }
-  tot[b] = s;
-}
-
-// list[base_b + offset of chunk c in bin b + rank in the chunk] = row, rows in order.
-__global__ __launch_bounds__(SP_T) void k_bin_scatter(const int64_t* __restrict__ ptr, int64_t rows,
-                                                       const int64_t* __restrict__ cnt,
-                                                       const int64_t* __restrict__ tot,
-                                                       int32_t* __restrict__ list) {
-  __shared__ uint64_t wsum[SP_T / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * SP_CHUNK + threadIdx.x * SP_RPT;
-  int bins[SP_RPT];
-  uint64_t packed = 0;   // 16-bit count per bin (at most SP_CHUNK rows per chunk)
-  for (int u = 0; u < SP_RPT; ++u) {
-    const int64_t r = r0 + u;
-    bins[u] = r < rows ? row_bin(ptr[r + 1] - ptr[r]) : -1;
-    if (bins[u] >= 0) packed += (uint64_t)1 << (16 * bins[u]);
-  }
-  // exclusive scan of the packed counts over the block, in thread (= row) order
-  uint64_t incl = packed;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint64_t v = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += v;
-  }
-  if (lane == 63) wsum[wave] = incl;
-  __syncthreads();
-  uint64_t before = incl - packed;
-  for (int w = 0; w < wave; ++w) before += wsum[w];
-  int64_t base[SP_BINS];
-  int64_t acc = 0;
-  for (int b = 0; b < SP_BINS; ++b) {
-    base[b] = acc + cnt[(int64_t)blockIdx.x * SP_COLS + b] + (int64_t)((before >> (16 * b)) & 0xffff);
-    acc += tot[b];
-  }
-  for (int u = 0; u < SP_RPT; ++u)
-    if (bins[u] >= 0) list[base[bins[u]]++] = (int32_t)(r0 + u);
-}
-
-// Rows of one bin with G lanes per row (G <= 64).
-template <int G>
-__global__ __launch_bounds__(SP_T) void k_spmv_group(const int64_t* __restrict__ ptr,
-                                                      const int32_t* __restrict__ idx,
-                                                      const float* __restrict__ val,
-                                                      const int32_t* __restrict__ list, int64_t count,
-                                                      const float* __restrict__ x, const float* __restrict__ prev,
-                                                      const double* __restrict__ coef, int cidx,
-                                                      double* __restrict__ y, const int* __restrict__ flag) {
-  if (flag != nullptr && flag[0] != 0) return;
-  const int64_t g = ((int64_t)blockIdx.x * SP_T + threadIdx.x) / G;
-  const int l = threadIdx.x % G;
-  if (g >= count) return;   // uniform over the G lanes of a row
-  const int32_t row = list[g];
-  const int64_t b = ptr[row], e = ptr[row + 1];
-  float s = 0.f;
-  for (int64_t j = b + l; j < e; j += G) s += val[j] * x[idx[j]];
+__device__ __forceinline__ float wave_sum_f(float v) {
 #pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// sum over j = j0, j0 + G, ... < e of val[j] x[idx[j]], in that order; four
+// entries' index and value loads are issued before their gathers.
+__device__ __forceinline__ float strided_sum(const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                             const float* __restrict__ x, int64_t j, int64_t e, int G) {
+  float s = 0.f;
+  for (; j + 3 * G < e; j += 4 * G) {
+    const int32_t i0 = idx[j], i1 = idx[j + G], i2 = idx[j + 2 * G], i3 = idx[j + 3 * G];
+    const float v0 = val[j], v1 = val[j + G], v2 = val[j + 2 * G], v3 = val[j + 3 * G];
+    const float x0 = x[i0], x1 = x[i1], x2 = x[i2], x3 = x[i3];
+    s += v0 * x0;
+    s += v1 * x1;
+    s += v2 * x2;
+    s += v3 * x3;
+  }
+  for (; j < e; j += G) s += val[j] * x[idx[j]];
+  return s;
+}
+
+// Stream blocks: blk[2b] = first row, blk[2b + 1] = row count.
+__global__ __launch_bounds__(SP_T) void k_spmv_stream(const int64_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ idx,
+                                                       const float* __restrict__ val,
+                                                       const int32_t* __restrict__ blk,
+                                                       const float* __restrict__ x, const float* __restrict__ prev,
+                                                       const double* __restrict__ coef, int cidx,
+                                                       double* __restrict__ y, const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  __shared__ float prod[SP_BLOCK_NNZ];
+  __shared__ int64_t off[SP_SHORT + 1];
+  const int r0 = blk[2 * blockIdx.x], nr = blk[2 * blockIdx.x + 1];
+  for (int t = threadIdx.x; t <= nr; t += SP_T) off[t] = ptr[r0 + t];
+  __syncthreads();
+  const int64_t e0 = off[0];
+  const int cnt = (int)(off[nr] - e0);
+  int32_t ii[SP_EPT];
+  float vv[SP_EPT];
+#pragma unroll
+  for (int u = 0; u < SP_EPT; ++u) {
+    const int q = threadIdx.x + u * SP_T;
+    ii[u] = q < cnt ? idx[e0 + q] : 0;
+    vv[u] = q < cnt ? val[e0 + q] : 0.f;
+  }
+#pragma unroll
+  for (int u = 0; u < SP_EPT; ++u) {
+    const int q = threadIdx.x + u * SP_T;
+    if (q < cnt) prod[q] = vv[u] * x[ii[u]];
+  }
+  __syncthreads();
+  if (threadIdx.x < nr) {
+    const int b = (int)(off[threadIdx.x] - e0), e = (int)(off[threadIdx.x + 1] - e0);
+    float s = 0.f;
+    for (int q = b; q < e; ++q) s += prod[q];
+    const int row = r0 + threadIdx.x;
+    y[row] = (double)s - (prev ? coef[cidx] * (double)prev[row] : 0.0);
+  }
+}
+
+// Medium rows: one wave per row (4 rows per workgroup).
+__global__ __launch_bounds__(SP_T) void k_spmv_wave(const int64_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ idx,
+                                                     const float* __restrict__ val,
+                                                     const int32_t* __restrict__ rows, int64_t count,
+                                                     const float* __restrict__ x, const float* __restrict__ prev,
+                                                     const double* __restrict__ coef, int cidx,
+                                                     double* __restrict__ y, const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  const int64_t w = (int64_t)blockIdx.x * (SP_T / 64) + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (w >= count) return;   // uniform over the wave
+  const int32_t row = rows[w];
+  const float s = wave_sum_f(strided_sum(idx, val, x, ptr[row] + l, ptr[row + 1], 64));
   if (l == 0) y[row] = (double)s - (prev ? coef[cidx] * (double)prev[row] : 0.0);
 }
 
-// The longest rows: one workgroup per row.
-__global__ __launch_bounds__(SP_T) void k_spmv_block(const int64_t* __restrict__ ptr,
+// Huge rows, step 1: chunk c of row crow[c] covers entries
+// [cbeg[c], min(cbeg[c] + SP_HUGE, end of the row)); part[c] = its sum.
+__global__ __launch_bounds__(SP_T) void k_spmv_chunk(const int64_t* __restrict__ ptr,
                                                       const int32_t* __restrict__ idx,
                                                       const float* __restrict__ val,
-                                                      const int32_t* __restrict__ list,
-                                                      const float* __restrict__ x, const float* __restrict__ prev,
-                                                      const double* __restrict__ coef, int cidx,
-                                                      double* __restrict__ y, const int* __restrict__ flag) {
+                                                      const int32_t* __restrict__ crow,
+                                                      const int64_t* __restrict__ cbeg,
+                                                      const float* __restrict__ x, float* __restrict__ part,
+                                                      const int* __restrict__ flag) {
   if (flag != nullptr && flag[0] != 0) return;
   __shared__ float red[SP_T / 64];
-  const int32_t row = list[blockIdx.x];
-  const int64_t b = ptr[row], e = ptr[row + 1];
-  float s = 0.f;
-  for (int64_t j = b + threadIdx.x; j < e; j += SP_T) s += val[j] * x[idx[j]];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const int64_t b = cbeg[blockIdx.x];
+  const int64_t e = std::min<int64_t>(b + SP_HUGE, ptr[crow[blockIdx.x] + 1]);
+  const float s = wave_sum_f(strided_sum(idx, val, x, b + threadIdx.x, e, SP_T));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     float t = 0.f;
 #pragma unroll
     for (int w = 0; w < SP_T / 64; ++w) t += red[w];
-    y[row] = (double)t - (prev ? coef[cidx] * (double)prev[row] : 0.0);
+    part[blockIdx.x] = t;
   }
+}
+
+// Huge rows, step 2: y[row] = sum of its chunk sums in chunk order.
+__global__ __launch_bounds__(SP_T) void k_spmv_huge_sum(const int32_t* __restrict__ hrow,
+                                                         const int32_t* __restrict__ hfirst, int64_t nh,
+                                                         const float* __restrict__ part,
+                                                         const float* __restrict__ prev,
+                                                         const double* __restrict__ coef, int cidx,
+                                                         double* __restrict__ y, const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  const int64_t h = (int64_t)blockIdx.x * SP_T + threadIdx.x;
+  if (h >= nh) return;
+  float s = 0.f;
+  for (int c = hfirst[h]; c < hfirst[h + 1]; ++c) s += part[c];
+  const int32_t row = hrow[h];
+  y[row] = (double)s - (prev ? coef[cidx] * (double)prev[row] : 0.0);
+}
+
+// *bad += indices outside [0, cols)
+__global__ __launch_bounds__(SP_T) void k_check_idx(const int32_t* __restrict__ idx, int64_t nnz, int64_t cols,
+                                                     unsigned long long* __restrict__ bad) {
+  unsigned long long nb = 0;
+  for (int64_t j = (int64_t)blockIdx.x * SP_T + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * SP_T)
+    nb += (idx[j] < 0 || idx[j] >= cols) ? 1ull : 0ull;
+  for (int o = 32; o > 0; o >>= 1) nb += __shfl_xor(nb, o, 64);
+  if ((threadIdx.x & 63) == 0 && nb) atomicAdd(bad, nb);
+}
+
+__global__ void k_zero_u64(unsigned long long* p) {
+  if (threadIdx.x == 0) *p = 0ull;
 }
 
 inline unsigned nblk(int64_t work, int64_t per) { return (unsigned)((work + per - 1) / per); }
@@ -165,57 +169,70 @@ inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-size_t sparse_dir_bytes(int64_t rows) {
-  const int64_t chunks = (rows + SP_CHUNK - 1) / SP_CHUNK;
-  return a256((size_t)rows * 4) + a256((size_t)chunks * SP_COLS * 8) + a256(SP_COLS * 8);
+size_t sparse_dir_bytes(int64_t rows, int64_t nnz) {
+  const int64_t maxh = nnz / SP_HUGE + 1;              // rows longer than SP_HUGE
+  const int64_t maxc = 2 * (nnz / SP_HUGE) + 2;        // their chunks
+  return a256((size_t)rows * 8) + a256((size_t)rows * 4) + a256((size_t)maxh * 4) + a256((size_t)(maxh + 1) * 4) +
+         a256((size_t)maxc * 4) + a256((size_t)maxc * 8) + a256((size_t)maxc * 4) + 256;
 }
 
-void sparse_dir_place(SparseDir& D, char* ws) {
-  const int64_t chunks = (D.rows + SP_CHUNK - 1) / SP_CHUNK;
-  D.list = reinterpret_cast<int32_t*>(ws);
-  ws += a256((size_t)D.rows * 4);
-  D.cnt = reinterpret_cast<int64_t*>(ws);
-  ws += a256((size_t)chunks * SP_COLS * 8);
-  D.tot = reinterpret_cast<int64_t*>(ws);
-}
-
-hipError_t launch_sparse_bins(SparseDir& D, int64_t nnz, hipStream_t st) {
-  const int64_t chunks = (D.rows + SP_CHUNK - 1) / SP_CHUNK;
-  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)chunks), dim3(SP_T), 0, st, D.ptr, D.rows, nnz, D.cnt);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(64), 0, st, D.cnt, chunks, D.tot);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (nnz > 0) {
-    hipLaunchKernelGGL(k_check_idx, dim3((unsigned)std::min<int64_t>(nblk(nnz, SP_T), 4096)), dim3(SP_T), 0, st,
-                       D.idx, nnz, D.cols, D.tot);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+// Build the schedule of D on the host from its row offsets (validated here:
+// non-decreasing, within [0, nnz]); false if they are not.
+bool sparse_schedule(SparseDir& D, const std::vector<int64_t>& p, int64_t nnz, std::vector<int32_t>& sblk,
+                     std::vector<int32_t>& wrow, std::vector<int32_t>& hrow, std::vector<int32_t>& hfirst,
+                     std::vector<int32_t>& crow, std::vector<int64_t>& cbeg) {
+  if (p[0] != 0 || p[D.rows] != nnz) return false;
+  int32_t run0 = -1, runn = 0;
+  int64_t runnz = 0;
+  auto flush = [&]() {
+    if (runn > 0) {
+      sblk.push_back(run0);
+      sblk.push_back(runn);
+    }
+    runn = 0;
+    runnz = 0;
+  };
+  hfirst.push_back(0);
+  for (int64_t r = 0; r < D.rows; ++r) {
+    const int64_t len = p[r + 1] - p[r];
+    if (len < 0 || p[r + 1] > nnz) return false;
+    if (len <= SP_SHORT) {
+      if (runn == SP_SHORT || runnz + len > SP_BLOCK_NNZ) flush();
+      if (runn == 0) run0 = (int32_t)r;
+      ++runn;
+      runnz += len;
+    } else {
+      flush();
+      if (len <= SP_HUGE) {
+        wrow.push_back((int32_t)r);
+      } else {
+        hrow.push_back((int32_t)r);
+        for (int64_t b = p[r]; b < p[r + 1]; b += SP_HUGE) {
+          crow.push_back((int32_t)r);
+          cbeg.push_back(b);
+        }
+        hfirst.push_back((int32_t)crow.size());
+      }
+    }
   }
-  hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)chunks), dim3(SP_T), 0, st, D.ptr, D.rows, D.cnt, D.tot,
-                     D.list);
-  return hipGetLastError();
+  flush();
+  return true;
 }
 
 hipError_t launch_spmv(const SparseDir& D, const float* x, const float* prev, const double* coef, int cidx,
                        double* y, const int* flag, hipStream_t st) {
-  const int32_t* l0 = D.list + D.base[0];
-  const int32_t* l1 = D.list + D.base[1];
-  const int32_t* l2 = D.list + D.base[2];
-  const int32_t* l3 = D.list + D.base[3];
-  if (D.count[0] > 0)
-    hipLaunchKernelGGL(k_spmv_group<4>, dim3(nblk(D.count[0], SP_T / 4)), dim3(SP_T), 0, st, D.ptr, D.idx, D.val,
-                       l0, D.count[0], x, prev, coef, cidx, y, flag);
-  if (D.count[1] > 0)
-    hipLaunchKernelGGL(k_spmv_group<16>, dim3(nblk(D.count[1], SP_T / 16)), dim3(SP_T), 0, st, D.ptr, D.idx,
-                       D.val, l1, D.count[1], x, prev, coef, cidx, y, flag);
-  if (D.count[2] > 0)
-    hipLaunchKernelGGL(k_spmv_group<64>, dim3(nblk(D.count[2], SP_T / 64)), dim3(SP_T), 0, st, D.ptr, D.idx,
-                       D.val, l2, D.count[2], x, prev, coef, cidx, y, flag);
-  if (D.count[3] > 0)
-    hipLaunchKernelGGL(k_spmv_block, dim3((unsigned)D.count[3]), dim3(SP_T), 0, st, D.ptr, D.idx, D.val, l3, x,
+  if (D.nsblk > 0)
+    hipLaunchKernelGGL(k_spmv_stream, dim3((unsigned)D.nsblk), dim3(SP_T), 0, st, D.ptr, D.idx, D.val, D.sblk, x,
                        prev, coef, cidx, y, flag);
+  if (D.nwrow > 0)
+    hipLaunchKernelGGL(k_spmv_wave, dim3(nblk(D.nwrow, SP_T / 64)), dim3(SP_T), 0, st, D.ptr, D.idx, D.val, D.wrow,
+                       D.nwrow, x, prev, coef, cidx, y, flag);
+  if (D.nhrow > 0) {
+    hipLaunchKernelGGL(k_spmv_chunk, dim3((unsigned)D.nchunk), dim3(SP_T), 0, st, D.ptr, D.idx, D.val, D.crow,
+                       D.cbeg, x, D.part, flag);
+    hipLaunchKernelGGL(k_spmv_huge_sum, dim3(nblk(D.nhrow, SP_T)), dim3(SP_T), 0, st, D.hrow, D.hfirst, D.nhrow,
+                       D.part, prev, coef, cidx, y, flag);
+  }
   return hipGetLastError();
 }
 
@@ -246,8 +263,47 @@ static gkb_status check_csr(const gkb_csr* A) {
 
 size_t gkb_sparse_plan_workspace_size(const gkb_csr* A) {
   if (check_csr(A) != GKB_OK) return 0;
-  return gkb::sparse_dir_bytes(A->m) + gkb::sparse_dir_bytes(A->n);
+  return gkb::sparse_dir_bytes(A->m, A->nnz) + gkb::sparse_dir_bytes(A->n, A->nnz) + 256;
 }
+
+namespace {
+// Lay out a direction's schedule at w (at most sparse_dir_bytes bytes) and upload it.
+hipError_t place_schedule(gkb::SparseDir& D, char* w, const std::vector<int32_t>& sblk,
+                          const std::vector<int32_t>& wrow, const std::vector<int32_t>& hrow,
+                          const std::vector<int32_t>& hfirst, const std::vector<int32_t>& crow,
+                          const std::vector<int64_t>& cbeg, hipStream_t st) {
+  auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
+  D.sblk = reinterpret_cast<int32_t*>(w);
+  w += a(std::max<size_t>(sblk.size(), 1) * 4);
+  D.wrow = reinterpret_cast<int32_t*>(w);
+  w += a(std::max<size_t>(wrow.size(), 1) * 4);
+  D.hrow = reinterpret_cast<int32_t*>(w);
+  w += a(std::max<size_t>(hrow.size(), 1) * 4);
+  D.hfirst = reinterpret_cast<int32_t*>(w);
+  w += a(hfirst.size() * 4);
+  D.crow = reinterpret_cast<int32_t*>(w);
+  w += a(std::max<size_t>(crow.size(), 1) * 4);
+  D.cbeg = reinterpret_cast<int64_t*>(w);
+  w += a(std::max<size_t>(cbeg.size(), 1) * 8);
+  D.part = reinterpret_cast<float*>(w);
+  D.nsblk = (int64_t)sblk.size() / 2;
+  D.nwrow = (int64_t)wrow.size();
+  D.nhrow = (int64_t)hrow.size();
+  D.nchunk = (int64_t)crow.size();
+  hipError_t e = hipSuccess;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes > 0) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  up(D.sblk, sblk.data(), sblk.size() * 4);
+  up(D.wrow, wrow.data(), wrow.size() * 4);
+  up(D.hrow, hrow.data(), hrow.size() * 4);
+  up(D.hfirst, hfirst.data(), hfirst.size() * 4);
+  up(D.crow, crow.data(), crow.size() * 4);
+  up(D.cbeg, cbeg.data(), cbeg.size() * 8);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors go out of scope
+  return e;
+}
+}  // namespace
 
 gkb_status gkb_sparse_plan_create(const gkb_csr* A, void* ws, size_t ws_bytes, void* stream,
                                   gkb_sparse_plan* out) {
@@ -261,14 +317,12 @@ gkb_status gkb_sparse_plan_create(const gkb_csr* A, void* ws, size_t ws_bytes, v
     return sfail(GKB_ERR_WORKSPACE, "plan workspace missing, misaligned or too small (need " + std::to_string(need) +
                                         " bytes)");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  // the offsets must end at nnz (a cheap check of the two pointer arrays)
-  int64_t ends[2] = {-1, -1};
-  if (hipMemcpyAsync(&ends[0], A->row_ptr + A->m, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(&ends[1], A->col_ptr + A->n, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  // row offsets of both directions to the host: the schedule is built from them
+  std::vector<int64_t> pf((size_t)A->m + 1), pt((size_t)A->n + 1);
+  if (hipMemcpyAsync(pf.data(), A->row_ptr, pf.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(pt.data(), A->col_ptr, pt.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return sfail(GKB_ERR_HIP, "reading the row offsets failed");
-  if (ends[0] != A->nnz || ends[1] != A->nnz)
-    return sfail(GKB_ERR_INVALID, "row_ptr[m] and col_ptr[n] must equal nnz");
   auto* plan = new gkb_sparse_plan_s();
   gkb::SparseRef& R = plan->ref;
   R.m = A->m;
@@ -285,31 +339,40 @@ gkb_status gkb_sparse_plan_create(const gkb_csr* A, void* ws, size_t ws_bytes, v
   R.tr.rows = A->n;
   R.tr.cols = A->m;
   char* w = reinterpret_cast<char*>(ws);
-  gkb::sparse_dir_place(R.fwd, w);
-  gkb::sparse_dir_place(R.tr, w + gkb::sparse_dir_bytes(A->m));
-  int64_t tots[2][gkb::SP_BINS + 1];
-  if (gkb::launch_sparse_bins(R.fwd, A->nnz, st) != hipSuccess || gkb::launch_sparse_bins(R.tr, A->nnz, st) != hipSuccess ||
-      hipMemcpyAsync(tots[0], R.fwd.tot, sizeof(tots[0]), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(tots[1], R.tr.tot, sizeof(tots[1]), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess) {
-    delete plan;
-    return sfail(GKB_ERR_HIP, "binning the rows failed");
-  }
+  unsigned long long* bad = reinterpret_cast<unsigned long long*>(w);
+  w += 256;
   gkb::SparseDir* dirs[2] = {&R.fwd, &R.tr};
+  const std::vector<int64_t>* offs[2] = {&pf, &pt};
   for (int d = 0; d < 2; ++d) {
-    int64_t acc = 0;
-    for (int b = 0; b < gkb::SP_BINS; ++b) {
-      dirs[d]->count[b] = tots[d][b];
-      dirs[d]->base[b] = acc;
-      acc += tots[d][b];
-    }
-    if (acc != dirs[d]->rows || tots[d][gkb::SP_BINS] != 0) {
+    std::vector<int32_t> sblk, wrow, hrow, hfirst, crow;
+    std::vector<int64_t> cbeg;
+    if (!gkb::sparse_schedule(*dirs[d], *offs[d], A->nnz, sblk, wrow, hrow, hfirst, crow, cbeg)) {
       delete plan;
-      return sfail(GKB_ERR_INVALID, d == 0 ? "invalid row_ptr or col_idx (offsets must be non-decreasing within "
-                                             "[0, nnz], indices within [0, n))"
-                                           : "invalid col_ptr or row_idx (offsets must be non-decreasing within "
-                                             "[0, nnz], indices within [0, m))");
+      return sfail(GKB_ERR_INVALID, d == 0 ? "row_ptr must be non-decreasing from 0 to nnz"
+                                           : "col_ptr must be non-decreasing from 0 to nnz");
     }
+    if (place_schedule(*dirs[d], w, sblk, wrow, hrow, hfirst, crow, cbeg, st) != hipSuccess) {
+      delete plan;
+      return sfail(GKB_ERR_HIP, "uploading the schedule failed");
+    }
+    w += gkb::sparse_dir_bytes(dirs[d]->rows, A->nnz);
+  }
+  // every index in range (one pass over both index arrays)
+  unsigned long long nbad = 1;
+  hipLaunchKernelGGL(gkb::k_zero_u64, dim3(1), dim3(64), 0, st, bad);
+  if (A->nnz > 0) {
+    const unsigned g = (unsigned)std::min<int64_t>((A->nnz + 255) / 256, 4096);
+    hipLaunchKernelGGL(gkb::k_check_idx, dim3(g), dim3(256), 0, st, A->col_idx, A->nnz, A->n, bad);
+    hipLaunchKernelGGL(gkb::k_check_idx, dim3(g), dim3(256), 0, st, A->row_idx, A->nnz, A->m, bad);
+  }
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&nbad, bad, 8, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    delete plan;
+    return sfail(GKB_ERR_HIP, "checking the indices failed");
+  }
+  if (nbad != 0) {
+    delete plan;
+    return sfail(GKB_ERR_INVALID, "column indices must lie in [0, n) and row indices of A^T in [0, m)");
   }
   *out = plan;
   return GKB_OK;

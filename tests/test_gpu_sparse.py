@@ -19,7 +19,8 @@ def csr_of(S):
 
 
 def one_long_row(m, n, seed):
-    """Power-law rows plus one full row and one full column (longest-row bin)."""
+    """Power-law rows plus one full row and one full column (the medium-row
+    wave path, and the chunked path when a row has more than 4096 entries)."""
     S = inputs.sparse_powerlaw(m, n, 4 * m, seed=seed)
     A = csr_of(S).tolil()
     A[m // 2, :] = np.linspace(-1, 1, n)
@@ -45,6 +46,7 @@ CASES = {
     "wide": lambda: inputs.sparse_powerlaw(700, 3000, 40000, seed=2),
     "permuted_diagonal": lambda: inputs.sparse_permuted_diagonal(3000, 1000, np.geomspace(1, 1e-3, 800), seed=3),
     "long_rows": lambda: one_long_row(2500, 3000, seed=4),
+    "huge_row": lambda: one_long_row(600, 10000, seed=6),
     "empty": lambda: empty_matrix(300, 200),
 }
 
@@ -98,7 +100,7 @@ def bound32(A):
 
 @pytest.mark.parametrize("name,r,k,check_every", [("powerlaw", 10, 40, 0), ("powerlaw", 10, 40, 5),
                                                   ("wide", 6, 30, 3), ("permuted_diagonal", 5, 20, 0),
-                                                  ("long_rows", 8, 30, 4)])
+                                                  ("long_rows", 8, 30, 4), ("huge_row", 6, 25, 0)])
 def test_sparse_partial_svd_against_oracle(name, r, k, check_every):
     import scipy.sparse.linalg  # noqa: F401  (sp.linalg.norm)
     device()
