@@ -31,12 +31,16 @@ R, K, TOL, RESTARTS = 50, 120, 1e-6, 20
 CHECK_EVERY = 10
 HBM_PEAK_GBS = 8000.0
 F32_MFMA_PEAK_TFLOPS = 157.3
-# HBM traffic per launch of the matvec kernels, measured with hardware counters
-# (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy); valid only for
-# the kernel sources whose digest the summary records.
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gemv_c2_f32_hbm_traffic.md")
-KERNEL_SOURCES = ["paper_2104_10785_amd/csrc/gemv.hip", "paper_2104_10785_amd/csrc/gemv.h",
-                  "paper_2104_10785_amd/csrc/device_common.h"]
+# HBM traffic per launch of the A-streaming kernels, measured with hardware
+# counters (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy); each
+# summary is valid only for the kernel sources whose digest it records.
+TRAFFIC = {
+    "gemv_n": ("gemv_c2_f32_hbm_traffic.md", ["paper_2104_10785_amd/csrc/gemv.hip", "paper_2104_10785_amd/csrc/gemv.h",
+                                              "paper_2104_10785_amd/csrc/device_common.h"]),
+    "gemv_fused": ("gemv_fused_c2_f32_hbm_traffic.md", ["paper_2104_10785_amd/csrc/fused.hip",
+                                                        "paper_2104_10785_amd/csrc/fused.h"]),
+}
+TRAFFIC["gemv_t"] = TRAFFIC["gemv_n"]
 
 
 def log(msg):
@@ -58,26 +62,28 @@ def time_kernel(fn, reps, stream):
     return start.elapsed_time(end) / reps
 
 
-def kernel_source_digest():
+def kernel_source_digest(kernel="gemv_n"):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in TRAFFIC[kernel][1]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` ("gemv_n" or "gemv_t") from the committed
-    counter summary, or None when it is absent or was taken on other sources."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+    """HBM bytes per launch of `kernel` ("gemv_n", "gemv_t" or "gemv_fused") from
+    the committed counter summary, or None when it is absent or was taken on
+    other sources."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC[kernel][0])
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_SUMMARY) as f:
+    with open(path) as f:
         for line in f:
             m = re.match(r"^\s*([a-z_]+):\s*(\S+)\s*$", line)
             if m:
                 vals[m.group(1)] = m.group(2)
-    if vals.get("source_digest") != kernel_source_digest() or f"{kernel}_bytes" not in vals:
+    if vals.get("source_digest") != kernel_source_digest(kernel) or f"{kernel}_bytes" not in vals:
         return None
     return float(vals[f"{kernel}_bytes"])
 
@@ -90,22 +96,35 @@ def matvec_operands(torch, Ad, dev):
     return xn, xm, yn, ym
 
 
+def fused_operands(gkb, torch, Ad, dev):
+    p = torch.randn(N, dtype=torch.float32, device=dev)
+    w = torch.empty(M, dtype=torch.float64, device=dev)
+    y = torch.empty(N, dtype=torch.float64, device=dev)
+    ws = torch.empty(max(256, gkb.lib().gkb_matvec_fused_workspace_size(gkb.C.byref(gkb.make_matrix(Ad)))),
+                     dtype=torch.uint8, device=dev)
+    return p, w, y, ws
+
+
 def kernels_only(gkb, torch, Ad, dev, stream, reps):
-    """The two A-streaming matvecs alone (reps launches each) and a plain 1 GiB
-    device copy (3 launches) whose counter readings calibrate the traffic figures."""
+    """The A-streaming kernels alone (reps launches each: A p, A^T q, and the
+    one-sweep pair A p, A^T A p) and a plain 1 GiB device copy (3 launches)
+    whose counter readings calibrate the traffic figures."""
     mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=dev)
     xn, xm, yn, ym = matvec_operands(torch, Ad, dev)
     ms_n = time_kernel(lambda: gkb.gkb_matvec(Ad, xn, 0, y=yn, stream=stream), reps, stream)
     ms_t = time_kernel(lambda: gkb.gkb_matvec(Ad, xm, 1, y=ym, workspace=mws, stream=stream), reps, stream)
+    fp, fw, fy, fws = fused_operands(gkb, torch, Ad, dev)
+    ms_f = time_kernel(lambda: gkb.gkb_matvec_fused(Ad, fp, fw, fy, fws, stream=stream), reps, stream)
     ritz = ritz_gemms(gkb, torch, dev, stream, reps)
     src = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"kernels_only": True, "gemv_n_ms": ms_n, "gemv_t_ms": ms_t, "reps": reps,
-                      "ritz_gemms": ritz, "copy_bytes": 2 ** 30, "source_digest": kernel_source_digest()}),
-          flush=True)
+    print(json.dumps({"kernels_only": True, "gemv_n_ms": ms_n, "gemv_t_ms": ms_t, "gemv_fused_ms": ms_f,
+                      "reps": reps, "ritz_gemms": ritz, "copy_bytes": 2 ** 30,
+                      "source_digest": kernel_source_digest("gemv_n"),
+                      "fused_source_digest": kernel_source_digest("gemv_fused")}), flush=True)
 
 
 def ritz_gemms(gkb, torch, dev, stream, reps):
@@ -351,6 +370,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
+    ap.add_argument("--two-pass", action="store_true",
+                    help="time the two-product step (A read twice per step) instead of the one-sweep step")
     ap.add_argument("--legs", default="bf16,rank,batched,learned,sparse,rsgd",
                     help="extra legs after the main timing (comma list; empty for none)")
     ap.add_argument("--kernels-only", action="store_true",
@@ -372,16 +393,18 @@ def main():
     log(f"generated in {time.time() - t0:.1f} s; copying to device")
     Ad = torch.from_numpy(A32).to(dev)
     qd = torch.from_numpy(q).to(dev)
-    ws = torch.empty(gkb.gkb_workspace_size(Ad, R, K), dtype=torch.uint8, device=dev)
+    one_pass = not args.two_pass
+    ws = torch.empty(max(gkb.gkb_workspace_size(Ad, R, K), gkb.gkb_workspace_size(Ad, R, K, one_pass=True)),
+                     dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     if args.kernels_only:
         kernels_only(gkb, torch, Ad, dev, stream, args.kernel_reps)
         return
 
-    def step(check_every=args.check_every):
+    def step(check_every=args.check_every, one_pass=one_pass):
         return gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
-                                   check_every=check_every)
+                                   check_every=check_every, one_pass=one_pass)
 
     for i in range(args.warmup):
         out = step()
@@ -406,6 +429,13 @@ def main():
     fixed_ms = (time.perf_counter() - t1) * 1000.0
     log(f"fixed-k solve: {fixed_ms:.2f} ms, stats={fixed[4]}")
 
+    # the other step form at the same configuration, for comparison
+    t1 = time.perf_counter()
+    other = step(one_pass=not one_pass)
+    torch.cuda.synchronize()
+    other_ms = (time.perf_counter() - t1) * 1000.0
+    log(f"{'two-product' if one_pass else 'one-sweep'} solve: {other_ms:.2f} ms, stats={other[4]}")
+
     # ---- dominant kernels: the two A-streaming matvecs, timed live with HIP events
     mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=dev)
     xn, xm, yn, ym = matvec_operands(torch, Ad, dev)
@@ -418,9 +448,18 @@ def main():
     bytes_t = M * N * 4 + M * 4 + N * 8
     gbs_n = bytes_n / (ms_n * 1e-3) / 1e9
     gbs_t = bytes_t / (ms_t * 1e-3) / 1e9
-    dom_ms, dom_bytes, dom_name = (ms_t, bytes_t, "gemv_t") if ms_t >= ms_n else (ms_n, bytes_n, "gemv_n")
+    # the one-sweep pair: A once, p once, w and A^T w written once
+    fp, fw, fy, fws = fused_operands(gkb, torch, Ad, dev)
+    ms_f = time_kernel(lambda: gkb.gkb_matvec_fused(Ad, fp, fw, fy, fws, stream=stream), args.kernel_reps, stream)
+    bytes_f = M * N * 4 + N * 4 + M * 8 + N * 8
+    gbs_f = bytes_f / (ms_f * 1e-3) / 1e9
+    if one_pass:
+        dom_ms, dom_bytes, dom_name = ms_f, bytes_f, "gemv_fused"
+    else:
+        dom_ms, dom_bytes, dom_name = (ms_t, bytes_t, "gemv_t") if ms_t >= ms_n else (ms_n, bytes_n, "gemv_n")
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    log(f"gemv_n {ms_n:.4f} ms {gbs_n:.0f} GB/s; gemv_t {ms_t:.4f} ms {gbs_t:.0f} GB/s")
+    log(f"gemv_n {ms_n:.4f} ms {gbs_n:.0f} GB/s; gemv_t {ms_t:.4f} ms {gbs_t:.0f} GB/s; "
+        f"fused sweep {ms_f:.4f} ms {gbs_f:.0f} GB/s")
     ritz = ritz_gemms(gkb, torch, dev, stream, args.kernel_reps)
     log(f"Ritz GEMMs: {ritz}")
 
@@ -454,17 +493,22 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "gk_partial_svd low-rank(200, 0.95^i)+noise(1e-6) 50000x20000 f32",
                    "r": R, "k": K, "tol": TOL, "max_restarts": RESTARTS, "check_every": args.check_every,
-                   "parallelism": "single-gpu"},
+                   "step": "one_sweep" if one_pass else "two_product", "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom_name),
                      "algorithmic_bytes": dom_bytes, "kernel_ms": dom_ms},
-        "matvec": {"gemv_n_ms": ms_n, "gemv_n_GBps": gbs_n, "gemv_t_ms": ms_t, "gemv_t_GBps": gbs_t},
+        "matvec": {"gemv_n_ms": ms_n, "gemv_n_GBps": gbs_n, "gemv_t_ms": ms_t, "gemv_t_GBps": gbs_t,
+                   "gemv_fused_ms": ms_f, "gemv_fused_GBps": gbs_f},
         "ritz_gemm": ritz,
         "solve": {"nconv": stats["nconv"], "matvecs": stats["matvecs"], "restarts": stats["restarts"],
+                  "recomputed_columns": stats["refreshes"],
                   "krylov_dim": stats["krylov_dim"], "checks": stats["checks"],
                   "ms_host_svd": stats["ms_host"], "sigma1": float(sigma[0]), "sigma50": float(sigma[-1])},
         "fixed_k_solve": {"ms": fixed_ms, "triplets_per_s": fixed[4]["nconv"] / (fixed_ms / 1000.0),
                           "matvecs": fixed[4]["matvecs"]},
+        ("two_product_solve" if one_pass else "one_sweep_solve"): {
+            "ms": other_ms, "triplets_per_s": other[4]["nconv"] / (other_ms / 1000.0),
+            "matvecs": other[4]["matvecs"], "sigma1": float(other[0][0]), "sigma50": float(other[0][-1])},
         "cpu_baseline": cpu,
     }
     line.update(legs)

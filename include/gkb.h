@@ -95,6 +95,17 @@ typedef struct {
                        /* triplets pass (one host synchronisation per test);   */
                        /* 0 = test only at the end of a cycle (fixed k, as the */
                        /* paper's Algorithm 2)                                 */
+  int one_pass;        /* 1: read A once per step instead of twice (GKB_F32   */
+                       /* with n, lda multiples of 4, n <= 24576, A 16-byte    */
+                       /* aligned; else GKB_ERR_INVALID).  One sweep forms     */
+                       /* A p and A^T A p in float64; A^T q_{i+1} then follows */
+                       /* from eq. (2.2) as (A^T A p - (A^T Q) c) / beta, with */
+                       /* c the recurrence and Gram-Schmidt coefficients and   */
+                       /* A^T Q kept in float64 (n x (k + 1) more workspace).  */
+                       /* Bases are float64 so that A^T Q matches Q exactly;   */
+                       /* U, V are still float32.  Same statuses and stats     */
+                       /* (matvecs counts products, two per sweep).            */
+                       /* gkb_partial_svd only.                                 */
 } gkb_options;
 
 typedef struct {
@@ -112,6 +123,9 @@ typedef struct {
   int refined;         /* bfloat16 refinement: 1 done, 0 not requested,        */
                        /* -1 skipped (subspace numerically rank deficient)     */
   double ms_refine;    /* wall time of the refinement                          */
+  int refreshes;       /* one_pass: A^T q columns recomputed by a direct sweep */
+                       /* because their error bound grew too large (counted    */
+                       /* in matvecs as well)                                  */
 } gkb_stats;
 
 /* Fill *opt with the defaults above. */

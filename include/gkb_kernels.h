@@ -29,6 +29,20 @@ gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, 
                       size_t ws_bytes, void* stream);
 
 /*
+ * Both products of a Golub-Kahan step in one sweep of A: w = A p (m doubles)
+ * and y = A^T w (n doubles), every sum in float64 (A float32, row-major,
+ * lda and n multiples of 4, A 16-byte aligned, n <= 24576; p float32, n
+ * entries).  A workgroup streams a range of rows once, reducing each row's
+ * dot product before adding the row, scaled by it, into its partial of A^T w;
+ * the partials (gkb_matvec_fused_workspace_size bytes) are added in a fixed
+ * order.  A^T q of the next Lanczos vector then follows from y and the
+ * recurrence (eq. (2.2)).  Returns GKB_ERR_INVALID for other shapes.
+ */
+size_t gkb_matvec_fused_workspace_size(const gkb_matrix* A);
+gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, double* y, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+/*
  * C (M x N) = A (M x K) B (K x N), all column-major with leading dimensions
  * lda >= M, ldb >= K, ldc >= M, on the 16x16x4 MFMA (float64 or float32).
  * This is the Ritz-vector product V = P Y, U = Q X of Algorithm 2 (and the

@@ -1,0 +1,58 @@
+// One sweep of A for both products of a Golub-Kahan step, and the small
+// kernels of the one-pass step (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gkb {
+
+constexpr int64_t FUSED_NMAX = 24576;    // longest row (768 threads x 8 groups of 4 floats)
+// a recovered A^T q column is recomputed directly once its error bound
+// exceeds this fraction of the largest coefficient seen
+constexpr double ONEPASS_TAU = 1e-10;
+
+// true if A (float32, m x n, lda) can take the fused sweep
+bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A);
+// number of workgroups (= partial-sum rows) the sweep uses
+int fused_blocks(int64_t m, int64_t n);
+
+// With win == nullptr: w = A p (float64, m) and the partials of y = A^T w;
+// p is read as float32 (a float64 p is rounded to float32 once, so w and y
+// are the exact products with that float32 vector).  With win != nullptr: the
+// partials of y = A^T win (p, w unused).  All sums in float64; ypart holds
+// fused_blocks(m, n) x ldy doubles (ldy >= n); y (n doubles) gets their sum in
+// a fixed order unless y is null.  Skipped when flag[0] != 0, or when run_if
+// is given and run_if[0] == 0.
+template <typename TP>
+hipError_t launch_gemv_fused(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win,
+                             double* w, double* y, double* ypart, int64_t ldy, const int* flag, hipStream_t st,
+                             const int* run_if = nullptr);
+
+// The recovery of A^T q_tq after w = A p - Q[:, 0..t) c_tot has been
+// normalised to beta q_tq, with c_tot[j] = c[j] plus xc[j - x0] for
+// x0 <= j < x0 + nx (the recurrence term: alpha on one column, or rho on the
+// first l after a restart):
+//   g = (y - G[:, 0..t) c_tot) / beta[0], G[:, tq] = g, z = g - beta[0] pprev,
+// y summed from the sweep's partials.  Its guard (one thread):
+//   e = (sum_j |c_tot[j]| err[j] + eps0 (s^2 + s sum_j |c_tot[j]|)) / beta[0],
+//   s = sig[0]; if e > tau s: refresh[0] = 1, refresh[1] += 1,
+//   err[tq] = eps0 s (the column is then recomputed by a direct sweep); else
+//   refresh[0] = 0, err[tq] = e.
+hipError_t launch_onepass_recover(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int t,
+                                  const double* c, const double* xc, int x0, int nx, const double* beta, int tq,
+                                  const double* pprev, double* z, int64_t n, double* err, const double* sig,
+                                  double eps0, double tau, int* refresh, const int* flag, hipStream_t st);
+// err[idx] = eps0 * sig[0]
+hipError_t launch_err_set(double* err, int idx, const double* sig, double eps0, const int* flag, hipStream_t st);
+// dst[0..l) = sqrt(nq) * max(src[0..nq)) (columns of G X after a restart)
+hipError_t launch_err_restart(const double* src, int nq, double* dst, int l, hipStream_t st);
+// if refresh[0]: G[:, tq] = y (summed from the partials), z = y - beta[0] pprev
+hipError_t launch_onepass_fix(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int tq,
+                              const double* beta, const double* pprev, double* z, int64_t n, const int* flag,
+                              const int* refresh, hipStream_t st);
+// dst[i] = (float) src[i], i < len
+hipError_t launch_narrow(const double* src, int64_t len, float* dst, hipStream_t st);
+
+}  // namespace gkb

@@ -1,0 +1,377 @@
+// w = A p and y = A^T w in one sweep of A (float32 storage, float64 sums).
+//
+// A Golub-Kahan step needs A p_t and then A^T q_{t+1}; since q_{t+1} is
+// A p_t minus multiples of earlier q's (eq. (2.2) and the Gram-Schmidt
+// passes), A^T q_{t+1} follows from A^T A p_t and the stored A^T q_j of those
+// earlier vectors.  This kernel streams each row of A once: a workgroup owns a
+// contiguous range of rows, keeps p in LDS, and for each row forms
+// the dot product (float64, reduced across the workgroup in a fixed order)
+// and adds a_i * w_i into its float64 partial of A^T w held in registers,
+// while the next row is already loading.  The partials of
+// all workgroups are added in workgroup order by a second kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "fused.h"
+#include "gemv.h"
+
+namespace gkb {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+inline unsigned nblk(int64_t work, int64_t per) { return (unsigned)((work + per - 1) / per); }
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// T threads; U = 16-byte column groups per thread (thread t owns groups
+// t, t + T, ...); R rows per step, the next R rows already loading.  The
+// float64 partial of A^T w (4 U doubles per thread) stays in registers; the
+// rows are converted to float64 once for the dot products and again for the
+// update after the barrier, so that only their float32 form stays live across
+// it (fewer registers, more waves per CU).
+// GIVEN_W: w is an input (y = A^T win) and no row needs a reduction.
+template <int T, int U, int R, typename TP, bool GIVEN_W>
+__global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                  const TP* __restrict__ p, const double* __restrict__ win,
+                                                  int64_t rows_per_block, double* __restrict__ w,
+                                                  double* __restrict__ ypart, int64_t ldy,
+                                                  const int* __restrict__ flag, const int* __restrict__ run_if) {
+  constexpr int NWV = T / 64;
+  if (flag != nullptr && flag[0] != 0) return;
+  if (run_if != nullptr && run_if[0] == 0) return;
+  extern __shared__ float pl[];                  // p as float32, n entries (not GIVEN_W)
+  __shared__ double red[2][R][NWV];              // [parity][row][wave]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ng = n >> 2;                     // 16-byte groups per row
+  if constexpr (!GIVEN_W) {
+    for (int64_t j = tid; j < n; j += T) pl[j] = (float)p[j];
+    __syncthreads();
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = std::min<int64_t>(m, r0 + rows_per_block);
+  double y[U][4];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[u][e] = 0.0;
+  f4 cur[R][U], nxt[R][U];
+  auto load_rows = [&](int64_t i, f4 (&dst)[R][U]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool ok = i + r < r1;
+      const f4* row = reinterpret_cast<const f4*>(A + (ok ? i + r : r0) * lda);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t g = tid + (int64_t)u * T;
+        dst[r][u] = (ok && g < ng) ? __builtin_nontemporal_load(row + g) : f4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  };
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int u = 0; u < U; ++u) nxt[r][u] = f4{0.f, 0.f, 0.f, 0.f};
+  if (r0 < r1) load_rows(r0, cur);
+  int par = 0;
+  for (int64_t i = r0; i < r1; i += R) {
+    if (i + R < r1) load_rows(i + R, nxt);
+    double wi[R];
+    if constexpr (GIVEN_W) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) wi[r] = i + r < r1 ? win[i + r] : 0.0;
+    } else {
+      double d[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r] = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t g = tid + (int64_t)u * T;
+        if (g < ng) {
+          const f4 pv = reinterpret_cast<const f4*>(pl)[g];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double pe = (double)pv[e];
+#pragma unroll
+            for (int r = 0; r < R; ++r) d[r] += (double)cur[r][u][e] * pe;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        d[r] = wsum(d[r]);
+        if (lane == 0) red[par][r][wave] = d[r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < NWV; ++k) t += red[par][r][k];
+        wi[r] = t;   // rows past r1 were loaded as zeros: their wi is 0
+        if (tid == 0 && i + r < r1) w[i + r] = t;
+      }
+      par ^= 1;   // the next step writes the other half of red: one barrier per step
+      // an empty register constraint: the update below converts the rows anew
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int u = 0; u < U; ++u) asm volatile("" : "+v"(cur[r][u]));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[u][e] += (double)cur[r][u][e] * wi[r];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[r][u] = nxt[r][u];
+  }
+  double* yp = ypart + (int64_t)blockIdx.x * ldy;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t g = tid + (int64_t)u * T;
+    if (g < ng)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) yp[4 * g + e] = y[u][e];
+  }
+}
+
+// sum over workgroups b of ypart[b][j], always in the same order
+__device__ __forceinline__ double sum_partials(const double* __restrict__ ypart, int nb, int64_t ldy, int64_t j) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int b = 0;
+  for (; b + 3 < nb; b += 4) {
+    s0 += ypart[(int64_t)b * ldy + j];
+    s1 += ypart[(int64_t)(b + 1) * ldy + j];
+    s2 += ypart[(int64_t)(b + 2) * ldy + j];
+    s3 += ypart[(int64_t)(b + 3) * ldy + j];
+  }
+  for (; b < nb; ++b) s0 += ypart[(int64_t)b * ldy + j];
+  return (s0 + s1) + (s2 + s3);
+}
+
+__global__ __launch_bounds__(256) void k_fused_reduce(const double* __restrict__ ypart, int nb, int64_t ldy,
+                                                      int64_t n, double* __restrict__ y,
+                                                      const int* __restrict__ flag, const int* __restrict__ run_if) {
+  if (flag != nullptr && flag[0] != 0) return;
+  if (run_if != nullptr && run_if[0] == 0) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  y[j] = sum_partials(ypart, nb, ldy, j);
+}
+
+template <int T, int U, int R, typename TP, bool GIVEN_W>
+hipError_t launch_v(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
+                    double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st) {
+  static bool set = false;
+  if (!GIVEN_W && !set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, TP, GIVEN_W>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)(FUSED_NMAX * 4));
+    if (e != hipSuccess) return e;
+    set = true;
+  }
+  const int nb = fused_blocks(m, n);
+  const int64_t rpb = (m + nb - 1) / nb;
+  hipLaunchKernelGGL((k_gemv_fused<T, U, R, TP, GIVEN_W>), dim3(nb), dim3(T), GIVEN_W ? 0 : (size_t)n * 4, st, A,
+                     lda, m, n, p, win, rpb, w, ypart, ldy, flag, run_if);
+  return hipGetLastError();
+}
+
+template <int T, int U, int R, typename TP>
+hipError_t launch_u(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
+                    double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st) {
+  if (win != nullptr) return launch_v<T, U, R, TP, true>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+  return launch_v<T, U, R, TP, false>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+}
+
+// Launch shape by row length (measured on MI355X): short rows take several
+// rows per step and two or four workgroups per CU, so that enough bytes are
+// in flight per barrier; long rows take one row per step with up to 1024
+// threads, the per-thread share of A^T w held in registers without spills.
+struct FusedShape {
+  int T, U, R, bpc;
+};
+
+FusedShape fused_shape(int64_t n) {
+  const int64_t ng = n / 4;
+  if (ng <= 128) return {128, 1, 16, 4};
+  if (ng <= 256) return {256, 1, 8, 2};
+  if (ng <= 512) return {256, 2, 4, 2};
+  if (ng <= 1024) return {256, 4, 2, 2};
+  if (ng <= 2048) return {512, 4, 1, 2};
+  if (ng <= 5120) return {1024, (int)((ng + 1023) / 1024), 1, 1};
+  return {768, 8, 1, 1};
+}
+
+// Coefficient of column j in w = A p - Q c: the Gram-Schmidt sums c[j] plus
+// the recurrence term xc[j - x0] for x0 <= j < x0 + nx.
+__device__ __forceinline__ double coef_total(const double* __restrict__ c, int j, const double* __restrict__ xc,
+                                             int x0, int nx) {
+  const int k = j - x0;
+  return (k >= 0 && k < nx) ? c[j] + xc[k] : c[j];
+}
+
+// G's columns 0..t-1 are read and column tq (>= t) is written: no overlap.
+// Block 0 also runs the guard (it reads only coefficients and bounds).
+__global__ __launch_bounds__(256) void k_onepass_recover(const double* __restrict__ ypart, int nb, int64_t ldy,
+                                                         double* G, int64_t ldg, int t, const double* __restrict__ c,
+                                                         const double* __restrict__ xc, int x0, int nx,
+                                                         const double* __restrict__ beta, int tq,
+                                                         const double* __restrict__ pprev, double* __restrict__ z,
+                                                         int64_t n, double* __restrict__ err,
+                                                         const double* __restrict__ sig, double eps0, double tau,
+                                                         int* __restrict__ refresh, const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) refresh[0] = 0;
+    return;
+  }
+  const double b = beta[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double sce = 0.0, sc = 0.0;
+    for (int j = 0; j < t; ++j) {
+      const double a = fabs(coef_total(c, j, xc, x0, nx));
+      sce += a * err[j];
+      sc += a;
+    }
+    const double s = sig[0];
+    const double e = (sce + eps0 * (s * s + s * sc)) / b;
+    if (e > tau * s) {
+      refresh[0] = 1;
+      refresh[1] += 1;
+      err[tq] = eps0 * s;
+    } else {
+      refresh[0] = 0;
+      err[tq] = e;
+    }
+  }
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < t; ++j) acc += G[(int64_t)j * ldg + i] * coef_total(c, j, xc, x0, nx);
+  const double g = (sum_partials(ypart, nb, ldy, i) - acc) / b;
+  G[(int64_t)tq * ldg + i] = g;
+  z[i] = g - b * pprev[i];
+}
+
+__global__ void k_err_set(double* err, int idx, const double* __restrict__ sig, double eps0,
+                          const int* __restrict__ flag) {
+  if (threadIdx.x != 0 || (flag != nullptr && flag[0] != 0)) return;
+  err[idx] = eps0 * sig[0];
+}
+
+__global__ void k_err_restart(const double* __restrict__ src, int nq, double* __restrict__ dst, int l) {
+  __shared__ double mx;
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int j = 0; j < nq; ++j) v = fmax(v, src[j]);
+    mx = v * sqrt((double)nq);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < l; j += blockDim.x) dst[j] = mx;
+}
+
+__global__ __launch_bounds__(256) void k_onepass_fix(const double* __restrict__ ypart, int nb, int64_t ldy,
+                                                     double* G, int64_t ldg, int tq, const double* __restrict__ beta,
+                                                     const double* __restrict__ pprev, double* __restrict__ z,
+                                                     int64_t n, const int* __restrict__ flag,
+                                                     const int* __restrict__ refresh) {
+  if ((flag != nullptr && flag[0] != 0) || refresh[0] == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double g = sum_partials(ypart, nb, ldy, i);
+  G[(int64_t)tq * ldg + i] = g;
+  z[i] = g - beta[0] * pprev[i];
+}
+
+__global__ __launch_bounds__(256) void k_narrow(const double* __restrict__ src, int64_t len,
+                                                float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < len) dst[i] = (float)src[i];
+}
+
+}  // namespace
+
+bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A) {
+  return m >= 1 && n >= 4 && n <= FUSED_NMAX && (n & 3) == 0 && (lda & 3) == 0 &&
+         (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+}
+
+int fused_blocks(int64_t m, int64_t n) {
+  // bpc workgroups per compute unit, each an equal share of the rows
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)fused_shape(n).bpc * device_cus(), m));
+}
+
+template <typename TP>
+hipError_t launch_gemv_fused(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win,
+                             double* w, double* y, double* ypart, int64_t ldy, const int* flag, hipStream_t st,
+                             const int* run_if) {
+  const FusedShape fs = fused_shape(n);
+  hipError_t e;
+#define GKB_FUSED(T, U, R) e = launch_u<T, U, R, TP>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st)
+  if (fs.T == 128) GKB_FUSED(128, 1, 16);
+  else if (fs.T == 256 && fs.U == 1) GKB_FUSED(256, 1, 8);
+  else if (fs.T == 256 && fs.U == 2) GKB_FUSED(256, 2, 4);
+  else if (fs.T == 256) GKB_FUSED(256, 4, 2);
+  else if (fs.T == 512) GKB_FUSED(512, 4, 1);
+  else if (fs.T == 768) GKB_FUSED(768, 8, 1);
+  else if (fs.U <= 3) GKB_FUSED(1024, 3, 1);
+  else if (fs.U == 4) GKB_FUSED(1024, 4, 1);
+  else GKB_FUSED(1024, 5, 1);
+#undef GKB_FUSED
+  if (e != hipSuccess || y == nullptr) return e;
+  hipLaunchKernelGGL(k_fused_reduce, dim3(nblk(n, 256)), dim3(256), 0, st, ypart, fused_blocks(m, n), ldy, n, y,
+                     flag, run_if);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gemv_fused<float>(const float*, int64_t, int64_t, int64_t, const float*, const double*,
+                                             double*, double*, double*, int64_t, const int*, hipStream_t,
+                                             const int*);
+template hipError_t launch_gemv_fused<double>(const float*, int64_t, int64_t, int64_t, const double*,
+                                              const double*, double*, double*, double*, int64_t, const int*,
+                                              hipStream_t, const int*);
+
+hipError_t launch_onepass_recover(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int t,
+                                  const double* c, const double* xc, int x0, int nx, const double* beta, int tq,
+                                  const double* pprev, double* z, int64_t n, double* err, const double* sig,
+                                  double eps0, double tau, int* refresh, const int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_onepass_recover, dim3(nblk(n, 256)), dim3(256), 0, st, ypart, nb, ldy, G, ldg, t, c, xc, x0,
+                     nx, beta, tq, pprev, z, n, err, sig, eps0, tau, refresh, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_err_set(double* err, int idx, const double* sig, double eps0, const int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_err_set, dim3(1), dim3(64), 0, st, err, idx, sig, eps0, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_err_restart(const double* src, int nq, double* dst, int l, hipStream_t st) {
+  hipLaunchKernelGGL(k_err_restart, dim3(1), dim3(64), 0, st, src, nq, dst, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_onepass_fix(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int tq,
+                              const double* beta, const double* pprev, double* z, int64_t n, const int* flag,
+                              const int* refresh, hipStream_t st) {
+  hipLaunchKernelGGL(k_onepass_fix, dim3(nblk(n, 256)), dim3(256), 0, st, ypart, nb, ldy, G, ldg, tq, beta, pprev,
+                     z, n, flag, refresh);
+  return hipGetLastError();
+}
+
+hipError_t launch_narrow(const double* src, int64_t len, float* dst, hipStream_t st) {
+  if (len <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_narrow, dim3(nblk(len, 256)), dim3(256), 0, st, src, len, dst);
+  return hipGetLastError();
+}
+
+}  // namespace gkb

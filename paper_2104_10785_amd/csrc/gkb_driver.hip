@@ -18,6 +18,7 @@
 #include "gkb_internal.h"
 #include "kernels.h"
 #include "sparse.h"
+#include "fused.h"
 
 namespace {
 
@@ -49,13 +50,14 @@ struct Layout {
   size_t w = 0, z = 0, part = 0, hpart = 0, h = 0, normpart = 0;
   size_t qcoef = 0, pcoef = 0, sig = 0, flag = 0, Xs = 0, Ys = 0, rho = 0, q1 = 0;
   size_t Vd = 0, Wr = 0, Gpart = 0, G = 0;  // bfloat16 refinement
+  size_t GQ[2] = {0, 0}, y = 0, ypart = 0, csum = 0, Uo = 0, Vo = 0, err[2] = {0, 0}, refresh = 0;  // one-pass
   size_t total = 0;
 };
 
 Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool small, bool refine = false,
-                   bool dense = true) {
+                   bool dense = true, bool onepass = false) {
   Layout L;
-  const size_t tb = basis_bytes(dt);
+  const size_t tb = onepass ? 8 : basis_bytes(dt);
   const size_t acc = dt == GKB_F64 ? 8 : 4;
   L.ldm = round64(m);
   L.ldn = round64(n);
@@ -80,7 +82,7 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
   L.z = take((size_t)L.ldn * 8);
   // gemv_t partial sums: at most GEMV_T_MAX_BLOCKS row blocks, and no more
   // than one per 64 rows (the launch never uses more)
-  const int64_t part_rows = dense ? std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (m + 63) / 64) : 0;
+  const int64_t part_rows = dense && !onepass ? std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (m + 63) / 64) : 0;
   L.ldpart = L.ldn;
   L.part = take((size_t)part_rows * L.ldpart * acc);
   const int nch = std::max(gkb::dots_chunks(m), gkb::dots_chunks(n));
@@ -102,6 +104,20 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
     L.Wr = take((size_t)L.ldm * L.kcols * 4);
     L.Gpart = take((size_t)gkb::gram_chunks(m) * L.kcols * L.kcols * 8);
     L.G = take((size_t)L.kcols * L.kcols * 8);
+  }
+  if (onepass) {
+    // A^T Q (float64, n x (k + 1), one per Q buffer), A^T A p, its partial
+    // sums, the step's coefficient sums, float64 Ritz vectors before narrowing
+    L.GQ[0] = take((size_t)L.kcols * L.ldn * 8);
+    L.GQ[1] = restart ? take((size_t)L.kcols * L.ldn * 8) : L.GQ[0];
+    L.y = take((size_t)L.ldn * 8);
+    L.ypart = take((size_t)gkb::fused_blocks(m, n) * L.ldn * 8);
+    L.csum = take((size_t)L.ldh * 8);
+    L.err[0] = take((size_t)L.ldh * 8);
+    L.err[1] = take((size_t)L.ldh * 8);
+    L.refresh = take(4 * sizeof(int));
+    L.Uo = take((size_t)L.ldm * L.kcols * 8);
+    L.Vo = take((size_t)L.ldn * L.kcols * 8);
   }
   L.total = off;
   return L;
@@ -173,6 +189,14 @@ struct Solver {
   TB* Ys() { return reinterpret_cast<TB*>(ws + L.Ys); }
   double* rho() { return reinterpret_cast<double*>(ws + L.rho); }
   double* q1buf() { return reinterpret_cast<double*>(ws + L.q1); }
+  double* GQ(int b) { return reinterpret_cast<double*>(ws + L.GQ[b]); }
+  double* ybuf() { return reinterpret_cast<double*>(ws + L.y); }
+  double* ypart() { return reinterpret_cast<double*>(ws + L.ypart); }
+  double* csum() { return reinterpret_cast<double*>(ws + L.csum); }
+  double* err(int b) { return reinterpret_cast<double*>(ws + L.err[b]); }
+  int* refresh() { return reinterpret_cast<int*>(ws + L.refresh); }
+  double eps0() const { return std::ldexp(1.0, -52) * std::sqrt((double)(A.m + A.n)); }
+  bool onepass = false;  // dense float32 A, float64 bases, one sweep of A per step
 
   // w = A p - coef[cidx] qprev and z = A^T q - coef[cidx] pprev (dense or sparse A)
   hipError_t prod_n(const TB* p, const TB* qprev, const double* coef, int cidx, double* out) {
@@ -189,13 +213,14 @@ struct Solver {
   }
 
   // Two classical Gram-Schmidt passes of x against V[:, 0..t); the last
-  // update leaves the partial sums of ||x||^2 in normpart.
-  hipError_t cgs2(const TB* V, int64_t ldv, int t, int64_t len, double* x) {
+  // update leaves the partial sums of ||x||^2 in normpart.  If acc is given,
+  // acc[0..t) receives the sum of the coefficients of both passes.
+  hipError_t cgs2(const TB* V, int64_t ldv, int t, int64_t len, double* x, double* acc = nullptr) {
     hipError_t e;
     for (int pass = 0; pass < 2; ++pass) {
       double* np_out = pass == 1 ? normpart() : nullptr;
       if (t > 0) {
-        e = gkb::launch_dots<TB>(V, ldv, t, len, x, hpart(), L.ldh, h(), flag(), st);
+        e = gkb::launch_dots<TB>(V, ldv, t, len, x, hpart(), L.ldh, h(), flag(), st, acc, pass);
         if (e != hipSuccess) return e;
         e = gkb::launch_update<TB>(V, ldv, t, len, x, h(), np_out, flag(), st);
         if (e != hipSuccess) return e;
@@ -234,9 +259,20 @@ struct Solver {
     GKB_HIP(hipMemcpyAsync(w(), q1, (size_t)A.m * sizeof(double), hipMemcpyDeviceToDevice, st));
     GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.m, w(), h(), normpart(), flag(), st));
     GKB_HIP(normalize(w(), A.m, Qc(0), qcoef(), 0, 1, 0, false));
-    GKB_HIP(prod_t(Qc(0), nullptr, nullptr, 0, z()));
+    if (onepass) {
+      // z = A^T q_1 with float64 sums, kept as the first column of A^T Q
+      if constexpr (std::is_same<TB, double>::value) {
+        GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.lda, A.m, A.n, nullptr, Qc(0), nullptr, z(), ypart(), L.ldn,
+                                               flag(), st));
+        GKB_HIP(gkb::launch_copy_vec<double>(z(), A.n, GQ(cur), st));
+        GKB_HIP(hipMemsetAsync(refresh(), 0, 4 * sizeof(int), st));
+      }
+    } else {
+      GKB_HIP(prod_t(Qc(0), nullptr, nullptr, 0, z()));
+    }
     GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.n, z(), h(), normpart(), flag(), st));
     GKB_HIP(normalize(z(), A.n, Pc(0), pcoef(), 1, 2, 0, false));
+    if (onepass) GKB_HIP(gkb::launch_err_set(err(cur), 0, sig() + nsig, eps0(), flag(), st));
     return GKB_OK;
   }
 
@@ -251,6 +287,46 @@ struct Solver {
     GKB_HIP(cgs2(P(cur), L.ldn, s + 1, A.n, z()));
     GKB_HIP(normalize(z(), A.n, Pc(s + 1), pcoef() + s + 1, 1, 2, s + 1, true));
     return GKB_OK;
+  }
+
+  const float* fA() const { return reinterpret_cast<const float*>(A.data); }
+
+  // The same step with one sweep of A (float32 A, float64 bases).  From
+  // p = P[:, pi]: w = A p and y = A^T w in one pass; w loses the recurrence
+  // term (alpha_pi q_qp, or Q[:, 0..nqc) rho after a restart) and two
+  // Gram-Schmidt passes against Q[:, 0..nqc), which altogether subtract
+  // Q[:, 0..nqc) c.  Then beta q_qn = w, and because every column of Q has
+  // its A^T image in GQ, A^T q_qn = (y - GQ[:, 0..nqc) c) / beta (eq. (2.2)),
+  // which becomes GQ[:, qn]; the p side then continues as in the two-pass step.
+  // An error in a stored column reaches the next one multiplied by
+  // alpha / beta, so each column carries an error bound; one whose bound
+  // passes ONEPASS_TAU times the largest coefficient is recomputed by a
+  // direct sweep A^T q_qn instead (skipped on the device otherwise).
+  gkb_status onepass_step(int pi, int qp, int nqc, int qn, bool use_rho) {
+    if constexpr (std::is_same<TB, double>::value) {
+      const int nb = gkb::fused_blocks(A.m, A.n);
+      GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.lda, A.m, A.n, Pc(pi), nullptr, w(), nullptr, ypart(), L.ldn,
+                                             flag(), st));
+      if (use_rho)
+        GKB_HIP(gkb::launch_update<TB>(Q(cur), L.ldm, nqc, A.m, w(), rho(), nullptr, flag(), st));
+      else
+        GKB_HIP(gkb::launch_update<TB>(Qc(qp), L.ldm, 1, A.m, w(), pcoef() + pi, nullptr, flag(), st));
+      GKB_HIP(cgs2(Q(cur), L.ldm, nqc, A.m, w(), csum()));
+      GKB_HIP(normalize(w(), A.m, Qc(qn), qcoef() + qn, 1, 1, qn, true));
+      GKB_HIP(gkb::launch_onepass_recover(ypart(), nb, L.ldn, GQ(cur), L.ldn, nqc, csum(),
+                                          use_rho ? rho() : pcoef() + pi, use_rho ? 0 : qp, use_rho ? nqc : 1,
+                                          qcoef() + qn, qn, Pc(pi), z(), A.n, err(cur), sig() + nsig, eps0(),
+                                          gkb::ONEPASS_TAU, refresh(), flag(), st));
+      GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.lda, A.m, A.n, nullptr, Qc(qn), nullptr, nullptr, ypart(),
+                                             L.ldn, flag(), st, refresh()));
+      GKB_HIP(gkb::launch_onepass_fix(ypart(), nb, L.ldn, GQ(cur), L.ldn, qn, qcoef() + qn, Pc(pi), z(), A.n, flag(),
+                                      refresh(), st));
+      GKB_HIP(cgs2(P(cur), L.ldn, pi + 1, A.n, z()));
+      GKB_HIP(normalize(z(), A.n, Pc(pi + 1), pcoef() + pi + 1, 1, 2, pi + 1, true));
+      return GKB_OK;
+    } else {
+      return fail(GKB_ERR_INVALID, "the one-pass step runs on float64 bases");
+    }
   }
 
 };
@@ -457,10 +533,12 @@ gkb_status refine_bf16<double>(Solver<double>&, const gkb_matrix*, const Proj&, 
   return fail(GKB_ERR_INVALID, "refinement needs a bfloat16 matrix");
 }
 
-template <typename TB>
+// TO: type of U and V (TB, or float for the one-pass step on float64 bases)
+template <typename TB, typename TO = TB>
 gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int max_restarts,
-                           const gkb_options& opt, void* workspace, double* sigma, TB* U, TB* V,
+                           const gkb_options& opt, void* workspace, double* sigma, TO* U, TO* V,
                            gkb_stats* stats, hipStream_t st, const gkb::SparseRef* sp = nullptr) {
+  constexpr bool onepass = !std::is_same<TB, TO>::value;
   const double t0 = now_ms();
   double ms_host = 0.0;
   Solver<TB> S;
@@ -471,8 +549,9 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   if (k == r) max_restarts = 0;
   const int every = opt.check_every > 0 ? opt.check_every : 0;
   const bool refine = Am->dtype == GKB_BF16 && Am->refine_f32 != nullptr;
-  S.L = make_layout(Am->m, Am->n, Am->dtype, k, k > r, true, refine, sp == nullptr);
+  S.L = make_layout(Am->m, Am->n, Am->dtype, k, k > r, true, refine, sp == nullptr, onepass);
   S.ws = reinterpret_cast<char*>(workspace);
+  S.onepass = onepass;
   S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
   S.relative = opt.eps_relative ? 1 : 0;
   const double* q1 = opt.q1;
@@ -498,7 +577,10 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     const int jstart = first ? 0 : l;
     bool early = false;
     for (int j = jstart; j < k; ++j) {
-      if (first) {
+      if (onepass) {
+        rc = first ? S.onepass_step(j, j, j + 1, j + 1, false) : S.onepass_step(j, j - 1, j, j, j == l);
+        if (rc != GKB_OK) return rc;
+      } else if (first) {
         rc = S.first_step(j);
         if (rc != GKB_OK) return rc;
       } else {
@@ -568,6 +650,11 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
                                       st));
     GKB_HIP(gkb::launch_copy_vec<TB>(S.P(S.cur) + (int64_t)pr.np * S.L.ldn, Am->n,
                                      S.P(nb) + (int64_t)l * S.L.ldn, st));
+    if constexpr (onepass) {  // A^T Q~ = (A^T Q) X_l, with the error bounds of its columns
+      GKB_HIP(gkb::launch_gemm_tall<TB>(S.GQ(S.cur), S.L.ldn, Am->n, pr.nq, S.Xs(), pr.nq, l, S.GQ(nb), S.L.ldn,
+                                        st));
+      GKB_HIP(gkb::launch_err_restart(S.err(S.cur), pr.nq, S.err(nb), l, st));
+    }
     S.cur = nb;
     S.nsig = 0;
     GKB_HIP(gkb::launch_init_cycle(S.flag(), S.sig(), sig_est, st));
@@ -579,13 +666,15 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   for (int i = 0; i < r; ++i) sigma[i] = i < r_eff ? rz.s[i] : 0.0;
   int refined = 0;
   double ms_refine = 0.0;
-  if (r_eff > 0 && refine) {
-    const double tr0 = now_ms();
-    int d = opt.refine_dim > 0 ? opt.refine_dim : 2 * r;
-    d = std::max(r_eff, std::min(d, rz.kk));
-    rc = refine_bf16<TB>(S, Am, pr, rz, r_eff, d, sigma, U, V, &refined);
-    if (rc != GKB_OK) return rc;
-    ms_refine = now_ms() - tr0;
+  if constexpr (!onepass) {
+    if (r_eff > 0 && refine) {
+      const double tr0 = now_ms();
+      int d = opt.refine_dim > 0 ? opt.refine_dim : 2 * r;
+      d = std::max(r_eff, std::min(d, rz.kk));
+      rc = refine_bf16<TB>(S, Am, pr, rz, r_eff, d, sigma, U, V, &refined);
+      if (rc != GKB_OK) return rc;
+      ms_refine = now_ms() - tr0;
+    }
   }
   if (r_eff > 0 && !refined) {
     std::vector<TB> Xh, Yh;
@@ -593,8 +682,17 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     to_colmajor<TB>(rz.Y, pr.np, rz.kk, r_eff, Yh);
     GKB_HIP(hipMemcpyAsync(S.Xs(), Xh.data(), Xh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
     GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
-    GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, S.Ys(), pr.np, r_eff, V, Am->n, st));
-    GKB_HIP(gkb::launch_gemm_tall<TB>(S.Q(S.cur), S.L.ldm, Am->m, pr.nq, S.Xs(), pr.nq, r_eff, U, Am->m, st));
+    if constexpr (onepass) {
+      double* Vo = reinterpret_cast<double*>(S.ws + S.L.Vo);
+      double* Uo = reinterpret_cast<double*>(S.ws + S.L.Uo);
+      GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, S.Ys(), pr.np, r_eff, Vo, Am->n, st));
+      GKB_HIP(gkb::launch_gemm_tall<TB>(S.Q(S.cur), S.L.ldm, Am->m, pr.nq, S.Xs(), pr.nq, r_eff, Uo, Am->m, st));
+      GKB_HIP(gkb::launch_narrow(Vo, Am->n * r_eff, V, st));
+      GKB_HIP(gkb::launch_narrow(Uo, Am->m * r_eff, U, st));
+    } else {
+      GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, S.Ys(), pr.np, r_eff, V, Am->n, st));
+      GKB_HIP(gkb::launch_gemm_tall<TB>(S.Q(S.cur), S.L.ldm, Am->m, pr.nq, S.Xs(), pr.nq, r_eff, U, Am->m, st));
+    }
     GKB_HIP(hipStreamSynchronize(st));
   }
   if (stats) {
@@ -602,7 +700,13 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     stats->restarts = restarts;
     stats->breakdown = pr.breakdown;
     stats->returned = r_eff;
-    stats->matvecs = matvecs;
+    int refreshes = 0;
+    if constexpr (onepass) {
+      GKB_HIP(hipMemcpyAsync(&refreshes, S.refresh() + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+      GKB_HIP(hipStreamSynchronize(st));
+    }
+    stats->refreshes = refreshes;
+    stats->matvecs = matvecs + refreshes;
     double mr = 0.0;
     for (int i = 0; i < r_eff; ++i) mr = std::max(mr, ct.res[i]);
     stats->max_res_est = mr;
@@ -701,11 +805,13 @@ void gkb_default_options(gkb_options* opt) {
 }
 
 size_t gkb_workspace_size(const gkb_matrix* A, int r, int k, const gkb_options* opt) {
-  (void)opt;
   if (check_matrix(A) != GKB_OK) return 0;
   if (r < 1 || k < r || k > std::min(A->m, A->n)) return 0;
-  return make_layout(A->m, A->n, A->dtype, k, k > r, true,
-                     A->dtype == GKB_BF16 && A->refine_f32 != nullptr).total;
+  const bool onepass = opt != nullptr && opt->one_pass != 0;
+  if (onepass && (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data))) return 0;
+  return make_layout(A->m, A->n, A->dtype, k, k > r, true, A->dtype == GKB_BF16 && A->refine_f32 != nullptr,
+                     true, onepass)
+      .total;
 }
 
 gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
@@ -732,9 +838,17 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
     if (A->dtype != GKB_BF16) return fail(GKB_ERR_INVALID, "refine_f32 is only used with GKB_BF16");
     if (A->lda_refine < A->n) return fail(GKB_ERR_INVALID, "need lda_refine >= n");
   }
+  if (opt.one_pass) {
+    if (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data))
+      return fail(GKB_ERR_INVALID, "one_pass needs a float32 A with n and lda multiples of 4, n <= 24576, "
+                                   "16-byte aligned");
+  }
   rc = check_workspace(workspace, ws_bytes, gkb_workspace_size(A, r, k, &opt));
   if (rc != GKB_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (opt.one_pass)
+    return run_partial_svd<double, float>(A, r, k, tol, max_restarts, opt, workspace, sigma,
+                                          reinterpret_cast<float*>(U), reinterpret_cast<float*>(V), stats, st);
   if (A->dtype == GKB_F64)
     return run_partial_svd<double>(A, r, k, tol, max_restarts, opt, workspace, sigma,
                                    reinterpret_cast<double*>(U), reinterpret_cast<double*>(V), stats, st);
@@ -767,6 +881,7 @@ gkb_status gkb_numerical_rank(const gkb_matrix* A, double tau, int tau_relative,
   gkb_default_options(&opt);
   if (opt_in) opt = *opt_in;
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
+  if (opt.one_pass) return fail(GKB_ERR_INVALID, "one_pass is an option of gkb_partial_svd only");
   rc = check_workspace(workspace, ws_bytes, gkb_rank_workspace_size(A, (int)k, &opt));
   if (rc != GKB_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -799,6 +914,7 @@ gkb_status gkb_partial_svd_sparse(gkb_sparse_plan plan, int r, int k, double tol
   if (opt.keep != 0 && (opt.keep < r || opt.keep >= k)) return fail(GKB_ERR_INVALID, "need r <= keep < k");
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
   if (opt.check_every < 0) return fail(GKB_ERR_INVALID, "need check_every >= 0");
+  if (opt.one_pass) return fail(GKB_ERR_INVALID, "one_pass needs a dense float32 A");
   gkb_status rc = check_workspace(workspace, ws_bytes, gkb_sparse_workspace_size(plan, r, k));
   if (rc != GKB_OK) return rc;
   // the dense descriptor only carries the shape and the float32 basis type
@@ -844,6 +960,28 @@ size_t gkb_matvec_workspace_size(const gkb_matrix* A) {
   if (check_matrix(A) != GKB_OK) return 0;
   const int64_t part_rows = std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (A->m + 63) / 64);
   return align256((size_t)part_rows * round64(A->n) * (A->dtype == GKB_F64 ? 8 : 4));
+}
+
+size_t gkb_matvec_fused_workspace_size(const gkb_matrix* A) {
+  if (check_matrix(A) != GKB_OK || A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data)) return 0;
+  return align256((size_t)gkb::fused_blocks(A->m, A->n) * round64(A->n) * 8);
+}
+
+gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, double* y, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  g_err.clear();
+  gkb_status rc = check_matrix(A);
+  if (rc != GKB_OK) return rc;
+  if (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data))
+    return fail(GKB_ERR_INVALID, "the fused sweep needs float32 A, lda and n multiples of 4, n <= 24576, "
+                                 "16-byte aligned");
+  if (!p || !w || !y) return fail(GKB_ERR_INVALID, "p, w and y must be non-NULL");
+  rc = check_workspace(workspace, ws_bytes, gkb_matvec_fused_workspace_size(A));
+  if (rc != GKB_OK) return rc;
+  GKB_HIP(gkb::launch_gemv_fused<float>(reinterpret_cast<const float*>(A->data), A->lda, A->m, A->n, p, nullptr,
+                                        w, y, reinterpret_cast<double*>(workspace), round64(A->n), nullptr,
+                                        reinterpret_cast<hipStream_t>(stream)));
+  return GKB_OK;
 }
 
 gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, void* workspace,

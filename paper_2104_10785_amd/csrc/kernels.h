@@ -13,10 +13,12 @@ namespace gkb {
 int dots_chunks(int64_t len);
 int update_blocks(int64_t len);
 
-// h[0..t) = V^T x through hpart (dots_chunks(len) x ldh)
+// h[0..t) = V^T x through hpart (dots_chunks(len) x ldh); if acc is given,
+// acc[0..t) = h (acc_add = 0) or acc[0..t) += h (acc_add = 1)
 template <typename TB>
 hipError_t launch_dots(const TB* V, int64_t ldv, int t, int64_t len, const double* x, double* hpart,
-                       int ldh, double* h, const int* flag, hipStream_t st);
+                       int ldh, double* h, const int* flag, hipStream_t st, double* acc = nullptr,
+                       int acc_add = 0);
 
 // x -= V h; normpart[b] = partial sums of x^2 (update_blocks(len) entries) if non-null
 template <typename TB>

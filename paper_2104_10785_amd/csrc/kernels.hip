@@ -59,16 +59,22 @@ __global__ __launch_bounds__(256) void k_dots(const TB* __restrict__ V, int64_t 
 
 // h[j] = sum_c hpart[c * ldh + j]: one wave per column, lanes stride the
 // chunks, then a fixed-order wave reduction.
+// h[j] = sum of the chunk partials; acc (if given) gets h (acc_add = 0) or
+// adds it (acc_add = 1).
 __global__ __launch_bounds__(64) void k_dots_reduce(const double* __restrict__ hpart, int ldh, int nchunks,
                                                     int t, double* __restrict__ h,
-                                                    const int* __restrict__ flag) {
+                                                    const int* __restrict__ flag, double* __restrict__ acc,
+                                                    int acc_add) {
   if (flag != nullptr && flag[0] != 0) return;
   const int j = blockIdx.x;
   if (j >= t) return;
   double s = 0.0;
   for (int c = threadIdx.x; c < nchunks; c += 64) s += hpart[(int64_t)c * ldh + j];
   s = wave_sum(s);
-  if (threadIdx.x == 0) h[j] = s;
+  if (threadIdx.x == 0) {
+    h[j] = s;
+    if (acc != nullptr) acc[j] = acc_add ? acc[j] + s : s;
+  }
 }
 
 // x[i] -= sum_{j<t} V[j * ldv + i] h[j] for the block's 64 rows (lane = row).
@@ -549,14 +555,14 @@ int update_blocks(int64_t len) { return (int)nblocks(len, UROWS); }
 
 template <typename TB>
 hipError_t launch_dots(const TB* V, int64_t ldv, int t, int64_t len, const double* x, double* hpart,
-                       int ldh, double* h, const int* flag, hipStream_t st) {
+                       int ldh, double* h, const int* flag, hipStream_t st, double* acc, int acc_add) {
   if (t <= 0) return hipSuccess;
   const int nch = dots_chunks(len);
   dim3 grid(nch, nblocks(t, DCOLS));
   hipLaunchKernelGGL((k_dots<TB>), grid, dim3(256), 0, st, V, ldv, t, len, x, hpart, ldh, flag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dots_reduce, dim3(t), dim3(64), 0, st, hpart, ldh, nch, t, h, flag);
+  hipLaunchKernelGGL(k_dots_reduce, dim3(t), dim3(64), 0, st, hpart, ldh, nch, t, h, flag, acc, acc_add);
   return hipGetLastError();
 }
 
@@ -673,7 +679,7 @@ hipError_t launch_gram(const float* W, int64_t ldw, int64_t m, int d, double* Gp
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dots_reduce, dim3((unsigned)ldg), dim3(64), 0, st, Gpart, (int)ldg, nch, (int)ldg, G,
-                     nullptr);
+                     (const int*)nullptr, (double*)nullptr, 0);
   return hipGetLastError();
 }
 
@@ -685,7 +691,7 @@ hipError_t launch_philox_start(double* q, int64_t m, uint64_t seed, hipStream_t 
 // explicit instantiations for the two basis types
 #define GKB_INST(TB)                                                                                      \
   template hipError_t launch_dots<TB>(const TB*, int64_t, int, int64_t, const double*, double*, int,      \
-                                      double*, const int*, hipStream_t);                                  \
+                                      double*, const int*, hipStream_t, double*, int);                    \
   template hipError_t launch_update<TB>(const TB*, int64_t, int, int64_t, double*, const double*,         \
                                         double*, const int*, hipStream_t);                                \
   template hipError_t launch_normalize<TB>(const double*, int64_t, const double*, int, TB*, double*,      \

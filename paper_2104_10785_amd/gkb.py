@@ -34,7 +34,8 @@ class GkbMatrix(C.Structure):
 
 class GkbOptions(C.Structure):
     _fields_ = [("keep", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
-                ("q1", C.c_void_p), ("seed", C.c_uint64), ("refine_dim", C.c_int), ("check_every", C.c_int)]
+                ("q1", C.c_void_p), ("seed", C.c_uint64), ("refine_dim", C.c_int), ("check_every", C.c_int),
+                ("one_pass", C.c_int)]
 
 
 class GkbBatchOptions(C.Structure):
@@ -53,7 +54,8 @@ class GkbStats(C.Structure):
     _fields_ = [("nconv", C.c_int), ("restarts", C.c_int), ("breakdown", C.c_int), ("returned", C.c_int),
                 ("matvecs", C.c_int64), ("max_res_est", C.c_double), ("sigma1_est", C.c_double),
                 ("ms_total", C.c_double), ("ms_host", C.c_double), ("checks", C.c_int),
-                ("krylov_dim", C.c_int), ("refined", C.c_int), ("ms_refine", C.c_double)]
+                ("krylov_dim", C.c_int), ("refined", C.c_int), ("ms_refine", C.c_double),
+                ("refreshes", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -73,7 +75,8 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_learned_last_error", "gkb_sparse_plan_workspace_size", "gkb_sparse_plan_create",
            "gkb_sparse_plan_destroy", "gkb_sparse_matvec", "gkb_sparse_workspace_size", "gkb_partial_svd_sparse",
            "gkb_sparse_last_error", "gkb_rsgd_workspace_size", "gkb_rsgd_plan_create", "gkb_rsgd_plan_step",
-           "gkb_rsgd_plan_info", "gkb_rsgd_plan_destroy", "gkb_rsgd_weights", "gkb_rsgd_last_error"]
+           "gkb_rsgd_plan_info", "gkb_rsgd_plan_destroy", "gkb_rsgd_weights", "gkb_rsgd_last_error",
+           "gkb_matvec_fused_workspace_size", "gkb_matvec_fused"]
 
 
 def lib():
@@ -209,6 +212,11 @@ def lib():
     L.gkb_rsgd_weights.restype = C.c_int
     L.gkb_rsgd_last_error.argtypes = []
     L.gkb_rsgd_last_error.restype = C.c_char_p
+    L.gkb_matvec_fused_workspace_size.argtypes = [P(GkbMatrix)]
+    L.gkb_matvec_fused_workspace_size.restype = C.c_size_t
+    L.gkb_matvec_fused.argtypes = [P(GkbMatrix), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                   C.c_void_p]
+    L.gkb_matvec_fused.restype = C.c_int
     _lib = L
     return L
 
@@ -266,7 +274,7 @@ def _stream(stream):
 
 
 def make_options(q1=None, seed=0, keep=0, eps_break=0.0, eps_relative=True, refine_dim=0,
-                 check_every=0) -> GkbOptions:
+                 check_every=0, one_pass=False) -> GkbOptions:
     o = GkbOptions()
     lib().gkb_default_options(C.byref(o))
     o.keep = keep
@@ -275,6 +283,7 @@ def make_options(q1=None, seed=0, keep=0, eps_break=0.0, eps_relative=True, refi
     o.seed = seed
     o.refine_dim = refine_dim
     o.check_every = check_every
+    o.one_pass = 1 if one_pass else 0
     if q1 is not None:
         if q1.dtype != _torch().float64 or not q1.is_cuda or not q1.is_contiguous():
             raise ValueError("q1 must be a contiguous float64 device tensor")
@@ -386,6 +395,24 @@ def gkb_gemm_tall(A, B, C_out=None, stream=None):
                                B.stride(0), N, C.c_void_p(C_out.data_ptr()), C_out.stride(0), _stream(stream)),
            False)
     return C_out
+
+
+def gkb_matvec_fused(A, p, w=None, y=None, workspace=None, stream=None):
+    """(w, y) = (A p, A^T A p) in one sweep of the float32 device matrix A."""
+    torch = _torch()
+    mat = make_matrix(A)
+    L = lib()
+    need = L.gkb_matvec_fused_workspace_size(C.byref(mat))
+    if w is None:
+        w = torch.empty(A.shape[0], dtype=torch.float64, device=A.device)
+    if y is None:
+        y = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+    if workspace is None:
+        workspace = _workspace(need, A.device)
+    _check(L.gkb_matvec_fused(C.byref(mat), C.c_void_p(p.data_ptr()), C.c_void_p(w.data_ptr()),
+                              C.c_void_p(y.data_ptr()), C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                              _stream(stream)), False)
+    return w, y
 
 
 def gkb_cast_bf16(src, dst=None, stream=None):

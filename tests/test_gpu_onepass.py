@@ -1,0 +1,163 @@
+"""The one-pass step (option one_pass: A read once per Golub-Kahan step)
+through the C ABI against the float64 oracle.
+
+The oracle runs the standard two-product recurrence on the exact float64
+upcast of the same float32 matrix with the same start vector; the one-pass
+path computes the same factorisation (see oracle.onepass and its pins), so
+the Ritz values must agree to the float32 storage level: the only float32
+rounding left is that of p before the product (float64 bases, float64 sums),
+which perturbs the relations of eq. (2.4) by about u32 ||A||, hence the
+sigma bound 8 sqrt(k) u32 sigma_1 (Weyl).  Vectors are compared with the
+sign-invariant alignment metric of Figure 1.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import checks, gk
+from paper_2104_10785_amd import gkb, inputs
+
+from .gpu_util import banner, device, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def run(A32, r, k, tol, restarts, q, **kw):
+    import torch
+    sigma, Ut, Vt, status, stats = gkb.gkb_partial_svd(to_dev(A32), r, k, tol, restarts, q1=to_dev(q), **kw)
+    torch.cuda.synchronize()
+    return sigma, to_host(Ut).T.astype(np.float64), to_host(Vt).T.astype(np.float64), status, stats
+
+
+def _check_against(ref, sigma, U, V, k, align=1 - 1e-5):
+    bound = 8.0 * np.sqrt(k) * U32 * ref["sigma"][0]
+    err = np.abs(sigma - ref["sigma"])
+    print(f"one-pass sigma max abs err {err.max():.3e} (bound {bound:.3e})", flush=True)
+    assert np.all(err <= bound)
+    al = checks.alignment(ref["U"], ref["V"], U, V)
+    print(f"one-pass alignment min {al.min():.9f}", flush=True)
+    assert np.min(al) >= align
+
+
+def test_onepass_lowrank_noise_midsize():
+    device()
+    m, n = 6000, 2500
+    banner(f"one-pass f32 low-rank+noise {m}x{n} r=20 k=60")
+    A32, s, _, _ = inputs.lowrank_noise(m, n, 200, 0.95, 1e-6, seed=7, dtype=np.float32)
+    q = inputs.start_vector(m, seed=8)
+    ref = gk.partial_svd(A32.astype(np.float64), 20, 60, 1e-6, 20, q, eps_break=1e-6)
+    sigma, U, V, status, stats = run(A32, 20, 60, 1e-6, 20, q, one_pass=True)
+    print("stats", stats, flush=True)
+    assert status == 0 and ref["status"] == 0
+    _check_against(ref, sigma, U, V, 60)
+    assert abs(stats["restarts"] - ref["restarts"]) <= 1
+    # two products per sweep, plus one per recomputed column
+    two = run(A32, 20, 60, 1e-6, 20, q)
+    assert stats["matvecs"] - stats["refreshes"] == two[4]["matvecs"] or stats["restarts"] != two[4]["restarts"]
+    r1, r2 = checks.triplet_residuals(A32.astype(np.float64), sigma, U, V)
+    assert np.max(r2) <= 1e-6 * sigma[0] + 1e-5 * sigma[0]
+
+
+def test_onepass_flat_spectrum_recomputes_columns():
+    """Square, ten separated values above a bulk in [0.5, 1]: there
+    alpha_t / beta_{t+1} is about 3, an unguarded recovery loses half a digit
+    per step (oracle.onepass pins this), and the guard must recompute columns."""
+    device()
+    s = np.concatenate([np.linspace(2.0, 1.1, 10), np.linspace(1.0, 0.5, 990)])
+    A, _, _ = inputs.svd_matrix(1000, 1000, s, seed=31)
+    A32 = A.astype(np.float32)
+    q = inputs.start_vector(1000, seed=32)
+    banner("one-pass square, flat bulk 1000x1000 r=10 k=40")
+    ref = gk.partial_svd(A32.astype(np.float64), 10, 40, 1e-6, 40, q, eps_break=1e-6)
+    sigma, U, V, status, stats = run(A32, 10, 40, 1e-6, 40, q, one_pass=True)
+    print("stats", stats, flush=True)
+    assert stats["refreshes"] >= 2
+    assert status == ref["status"] == 0
+    _check_against(ref, sigma, U, V, 40)
+
+
+@pytest.mark.parametrize("shape,r,k,check_every", [((100, 64), 4, 20, 0), ((333, 1000), 5, 30, 4),
+                                                   ((5000, 4), 2, 4, 0), ((1200, 840), 8, 24, 5)])
+def test_onepass_shapes(shape, r, k, check_every):
+    """Fewer rows than workgroups, a wide matrix, n = 4 (k = n: the exact
+    bidiagonalisation), in-cycle checks with restarts."""
+    device()
+    m, n = shape
+    banner(f"one-pass {m}x{n} r={r} k={k} check_every={check_every}")
+    rng = np.random.default_rng(m + n)
+    p = min(m, n)
+    s = np.geomspace(1.0, 1e-3, p)
+    A, _, _ = inputs.svd_matrix(m, n, s, seed=m * 3 + n)
+    A32 = A.astype(np.float32)
+    q = rng.standard_normal(m) + 2.0
+    ref = gk.partial_svd(A32.astype(np.float64), r, k, 1e-6, 200, q, eps_break=1e-6, check_every=check_every)
+    sigma, U, V, status, stats = run(A32, r, k, 1e-6, 200, q, one_pass=True, check_every=check_every)
+    print("stats", stats, flush=True)
+    assert status == ref["status"]
+    _check_against(ref, sigma, U, V, k, align=1 - 1e-4)
+
+
+def test_onepass_rank_deficient():
+    device()
+    banner("one-pass exact rank 6")
+    rng = np.random.default_rng(3)
+    A32 = (rng.standard_normal((400, 6)) @ rng.standard_normal((6, 300))).astype(np.float32)
+    q = rng.standard_normal(400)
+    ref = gk.partial_svd(A32.astype(np.float64), 8, 20, 1e-6, 5, q, eps_break=1e-6)
+    sigma, U, V, status, stats = run(A32, 8, 20, 1e-6, 5, q, one_pass=True)
+    assert ref["status"] == 2 and len(ref["sigma"]) == 6
+    assert status == 2 and stats["returned"] == 6
+    assert np.max(np.abs(sigma[:6] - ref["sigma"])) <= 8 * np.sqrt(20) * U32 * ref["sigma"][0]
+    assert np.all(sigma[6:] == 0.0)
+
+
+def test_onepass_deterministic():
+    device()
+    banner("one-pass determinism")
+    A32, _, _, _ = inputs.lowrank_noise(3000, 1500, 100, 0.9, 1e-6, seed=11, dtype=np.float32)
+    q = inputs.start_vector(3000, seed=12)
+    a = run(A32, 10, 30, 1e-6, 10, q, one_pass=True)
+    b = run(A32, 10, 30, 1e-6, 10, q, one_pass=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_onepass_rejects_other_inputs():
+    device()
+    banner("one-pass argument checks")
+    rng = np.random.default_rng(0)
+    with pytest.raises(gkb.GkbError):
+        gkb.gkb_partial_svd(to_dev(rng.standard_normal((50, 30)).astype(np.float32)), 2, 6, 1e-6, 2, one_pass=True)
+    with pytest.raises(gkb.GkbError):
+        gkb.gkb_partial_svd(to_dev(rng.standard_normal((50, 32))), 2, 6, 1e-6, 2, one_pass=True)
+    with pytest.raises(gkb.GkbError):
+        gkb.gkb_numerical_rank(to_dev(rng.standard_normal((50, 32)).astype(np.float32)), 1e-3, one_pass=True)
+
+
+def test_c2_fullsize_onepass_against_stored_oracle():
+    """50000 x 20000 float32, r=50, k=120 (the benchmark's configuration) with
+    one sweep of A per step, against the stored float64 oracle values
+    (tests/golden/c2_oracle_top50.json, written by
+    tests/golden/make_c2_reference.py)."""
+    import torch
+    device()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_top50.json")))
+    banner("c2 full size 50000x20000 f32 r=50 k=120 one_pass")
+    A32, s, _, _ = inputs.lowrank_noise(50000, 20000, 200, 0.95, 1e-6, seed=2, dtype=np.float32)
+    q = inputs.start_vector(50000, seed=1)
+    Ad = torch.from_numpy(A32).to("cuda:0")
+    sigma, Ut, Vt, status, stats = gkb.gkb_partial_svd(Ad, 50, 120, 1e-6, 20, q1=to_dev(q), one_pass=True)
+    torch.cuda.synchronize()
+    del Ad
+    print("stats", stats, flush=True)
+    assert status == 0 and stats["nconv"] == 50
+    want = np.array(ref["sigma"])
+    bound = 8.0 * np.sqrt(120) * U32 * want[0]
+    err = np.abs(sigma - want)
+    print(f"c2 one-pass sigma max abs err {err.max():.3e} (bound {bound:.3e}); matvecs {stats['matvecs']} "
+          f"(oracle {ref['matvecs']}), refreshes {stats['refreshes']}", flush=True)
+    assert np.all(err <= bound)
+    assert abs(stats["matvecs"] - stats["refreshes"] - ref["matvecs"]) <= 2 * 120
