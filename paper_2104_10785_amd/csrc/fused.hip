@@ -32,13 +32,14 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 // T threads; U = 16-byte column groups per thread (thread t owns groups
-// t, t + T, ...); R rows per step, the next R rows already loading.  The
+// t, t + T, ...); R rows per step, the next D groups of R rows already
+// loading.  The
 // float64 partial of A^T w (4 U doubles per thread) stays in registers; the
 // rows are converted to float64 once for the dot products and again for the
 // update after the barrier, so that only their float32 form stays live across
 // it (fewer registers, more waves per CU).
 // GIVEN_W: w is an input (y = A^T win) and no row needs a reduction.
-template <int T, int U, int R, typename TP, bool GIVEN_W>
+template <int T, int U, int R, int D, typename TP, bool GIVEN_W>
 __global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                   const TP* __restrict__ p, const double* __restrict__ win,
                                                   int64_t rows_per_block, double* __restrict__ w,
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, i
   for (int u = 0; u < U; ++u)
 #pragma unroll
     for (int e = 0; e < 4; ++e) y[u][e] = 0.0;
-  f4 cur[R][U], nxt[R][U];
+  f4 cur[R][U], nxt[R][U], nx2[R][U];
   auto load_rows = [&](int64_t i, f4 (&dst)[R][U]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -79,10 +80,19 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, i
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int u = 0; u < U; ++u) nxt[r][u] = f4{0.f, 0.f, 0.f, 0.f};
+  // a group is loaded only if it will be processed; a stale buffer is
+  // never read (the loop ends first)
   if (r0 < r1) load_rows(r0, cur);
+  if constexpr (D == 2) {
+    if (r0 + R < r1) load_rows(r0 + R, nxt);
+  }
   int par = 0;
   for (int64_t i = r0; i < r1; i += R) {
-    if (i + R < r1) load_rows(i + R, nxt);
+    if constexpr (D == 2) {
+      if (i + 2 * R < r1) load_rows(i + 2 * R, nx2);
+    } else {
+      if (i + R < r1) load_rows(i + R, nxt);
+    }
     double wi[R];
     if constexpr (GIVEN_W) {
 #pragma unroll
@@ -134,7 +144,10 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, i
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int u = 0; u < U; ++u) cur[r][u] = nxt[r][u];
+      for (int u = 0; u < U; ++u) {
+        cur[r][u] = nxt[r][u];
+        if constexpr (D == 2) nxt[r][u] = nx2[r][u];
+      }
   }
   double* yp = ypart + (int64_t)blockIdx.x * ldy;
 #pragma unroll
@@ -170,34 +183,37 @@ __global__ __launch_bounds__(256) void k_fused_reduce(const double* __restrict__
   y[j] = sum_partials(ypart, nb, ldy, j);
 }
 
-template <int T, int U, int R, typename TP, bool GIVEN_W>
+template <int T, int U, int R, int D, typename TP, bool GIVEN_W>
 hipError_t launch_v(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
                     double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st) {
   static bool set = false;
   if (!GIVEN_W && !set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, TP, GIVEN_W>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, D, TP, GIVEN_W>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(FUSED_NMAX * 4));
     if (e != hipSuccess) return e;
     set = true;
   }
   const int nb = fused_blocks(m, n);
   const int64_t rpb = (m + nb - 1) / nb;
-  hipLaunchKernelGGL((k_gemv_fused<T, U, R, TP, GIVEN_W>), dim3(nb), dim3(T), GIVEN_W ? 0 : (size_t)n * 4, st, A,
+  hipLaunchKernelGGL((k_gemv_fused<T, U, R, D, TP, GIVEN_W>), dim3(nb), dim3(T), GIVEN_W ? 0 : (size_t)n * 4, st, A,
                      lda, m, n, p, win, rpb, w, ypart, ldy, flag, run_if);
   return hipGetLastError();
 }
 
-template <int T, int U, int R, typename TP>
+template <int T, int U, int R, int D, typename TP>
 hipError_t launch_u(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
                     double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st) {
-  if (win != nullptr) return launch_v<T, U, R, TP, true>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
-  return launch_v<T, U, R, TP, false>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+  if (win != nullptr)
+    return launch_v<T, U, R, D, TP, true>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+  return launch_v<T, U, R, D, TP, false>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
 }
 
 // Launch shape by row length (measured on MI355X): short rows take several
 // rows per step and two or four workgroups per CU, so that enough bytes are
 // in flight per barrier; long rows take one row per step with up to 1024
-// threads, the per-thread share of A^T w held in registers without spills.
+// threads, the per-thread share of A^T w held in registers without spills,
+// and two rows ahead in flight where the registers allow it (up to 4 groups
+// per thread).
 struct FusedShape {
   int T, U, R, bpc;
 };
@@ -317,16 +333,16 @@ hipError_t launch_gemv_fused(const float* A, int64_t lda, int64_t m, int64_t n, 
                              const int* run_if) {
   const FusedShape fs = fused_shape(n);
   hipError_t e;
-#define GKB_FUSED(T, U, R) e = launch_u<T, U, R, TP>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st)
-  if (fs.T == 128) GKB_FUSED(128, 1, 16);
-  else if (fs.T == 256 && fs.U == 1) GKB_FUSED(256, 1, 8);
-  else if (fs.T == 256 && fs.U == 2) GKB_FUSED(256, 2, 4);
-  else if (fs.T == 256) GKB_FUSED(256, 4, 2);
-  else if (fs.T == 512) GKB_FUSED(512, 4, 1);
-  else if (fs.T == 768) GKB_FUSED(768, 8, 1);
-  else if (fs.U <= 3) GKB_FUSED(1024, 3, 1);
-  else if (fs.U == 4) GKB_FUSED(1024, 4, 1);
-  else GKB_FUSED(1024, 5, 1);
+#define GKB_FUSED(T, U, R, D) e = launch_u<T, U, R, D, TP>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st)
+  if (fs.T == 128) GKB_FUSED(128, 1, 16, 1);
+  else if (fs.T == 256 && fs.U == 1) GKB_FUSED(256, 1, 8, 1);
+  else if (fs.T == 256 && fs.U == 2) GKB_FUSED(256, 2, 4, 1);
+  else if (fs.T == 256) GKB_FUSED(256, 4, 2, 1);
+  else if (fs.T == 512) GKB_FUSED(512, 4, 1, 2);
+  else if (fs.T == 768) GKB_FUSED(768, 8, 1, 1);
+  else if (fs.U <= 3) GKB_FUSED(1024, 3, 1, 2);
+  else if (fs.U == 4) GKB_FUSED(1024, 4, 1, 2);
+  else GKB_FUSED(1024, 5, 1, 1);
 #undef GKB_FUSED
   if (e != hipSuccess || y == nullptr) return e;
   hipLaunchKernelGGL(k_fused_reduce, dim3(nblk(n, 256)), dim3(256), 0, st, ypart, fused_blocks(m, n), ldy, n, y,
