@@ -105,7 +105,7 @@ typedef struct {
                        /* Bases are float64 so that A^T Q matches Q exactly;   */
                        /* U, V are still float32.  Same statuses and stats     */
                        /* (matvecs counts products, two per sweep).            */
-                       /* gkb_partial_svd only.                                 */
+                       /* gkb_partial_svd and gkb_numerical_rank.              */
 } gkb_options;
 
 typedef struct {
@@ -174,6 +174,9 @@ size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options
  *                Golub-Kahan tridiagonal (an independent check).
  *   sigma_out    host, optional, k_max doubles: singular values of B.
  *   nsigma       host, optional: number written to sigma_out (steps done).
+ *   opt          eps_break / eps_relative (breakdown), q1 / seed (start
+ *                vector), one_pass (one sweep of A per step, as for
+ *                gkb_partial_svd); the other fields are not used.
  */
 gkb_status gkb_numerical_rank(const gkb_matrix* A, double tau, int tau_relative, int k_max,
                               const gkb_options* opt, void* workspace, size_t ws_bytes,

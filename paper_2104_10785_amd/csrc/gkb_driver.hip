@@ -725,13 +725,14 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
 template <typename TB>
 gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, const gkb_options& opt,
                     void* workspace, int64_t* rank, int64_t* rank_sturm, double* sigma_out, int* nsigma,
-                    gkb_stats* stats, hipStream_t st) {
+                    gkb_stats* stats, hipStream_t st, bool onepass = false) {
   const double t0 = now_ms();
   Solver<TB> S;
   S.A = {Am->data, Am->m, Am->n, Am->lda, (int)Am->dtype};
   S.st = st;
-  S.L = make_layout(Am->m, Am->n, Am->dtype, k, false, false);
+  S.L = make_layout(Am->m, Am->n, Am->dtype, k, false, false, false, true, onepass);
   S.ws = reinterpret_cast<char*>(workspace);
+  S.onepass = onepass;
   S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
   S.relative = opt.eps_relative ? 1 : 0;
   const double* q1 = opt.q1;
@@ -747,7 +748,7 @@ gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, c
   for (int s0 = 0; s0 < k; s0 += chunk) {
     const int s1 = std::min(k, s0 + chunk);
     for (int s = s0; s < s1; ++s) {
-      rc = S.first_step(s);
+      rc = onepass ? S.onepass_step(s, s, s + 1, s + 1, false) : S.first_step(s);
       if (rc != GKB_OK) return rc;
     }
     if (s1 < k) {
@@ -781,10 +782,16 @@ gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, c
     for (int j = 0; j < np; ++j) sigma_out[j] = s[j];
   if (nsigma) *nsigma = np;
   if (stats) {
+    int refreshes = 0;
+    if (onepass) {
+      GKB_HIP(hipMemcpyAsync(&refreshes, S.refresh() + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+      GKB_HIP(hipStreamSynchronize(st));
+    }
     std::memset(stats, 0, sizeof(*stats));
+    stats->refreshes = refreshes;
     stats->breakdown = pr.breakdown;
     stats->returned = np;
-    stats->matvecs = pr.matvecs;
+    stats->matvecs = pr.matvecs + refreshes;
     stats->sigma1_est = np > 0 ? s[0] : 0.0;
     stats->ms_total = now_ms() - t0;
     stats->ms_host = ms_host;
@@ -857,12 +864,13 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
 }
 
 size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options* opt) {
-  (void)opt;
   if (check_matrix(A) != GKB_OK) return 0;
   const int64_t kmin = std::min(A->m, A->n);
   const int64_t k = k_max ? k_max : kmin;
   if (k < 1 || k > kmin) return 0;
-  return make_layout(A->m, A->n, A->dtype, (int)k, false, false).total;
+  const bool onepass = opt != nullptr && opt->one_pass != 0;
+  if (onepass && (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data))) return 0;
+  return make_layout(A->m, A->n, A->dtype, (int)k, false, false, false, true, onepass).total;
 }
 
 gkb_status gkb_numerical_rank(const gkb_matrix* A, double tau, int tau_relative, int k_max,
@@ -881,10 +889,15 @@ gkb_status gkb_numerical_rank(const gkb_matrix* A, double tau, int tau_relative,
   gkb_default_options(&opt);
   if (opt_in) opt = *opt_in;
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
-  if (opt.one_pass) return fail(GKB_ERR_INVALID, "one_pass is an option of gkb_partial_svd only");
+  if (opt.one_pass && (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data)))
+    return fail(GKB_ERR_INVALID, "one_pass needs a float32 A with n and lda multiples of 4, n <= 24576, "
+                                 "16-byte aligned");
   rc = check_workspace(workspace, ws_bytes, gkb_rank_workspace_size(A, (int)k, &opt));
   if (rc != GKB_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (opt.one_pass)
+    return run_rank<double>(A, tau, tau_relative, (int)k, opt, workspace, rank, rank_sturm, sigma_out, nsigma,
+                            stats, st, true);
   if (A->dtype == GKB_F64)
     return run_rank<double>(A, tau, tau_relative, (int)k, opt, workspace, rank, rank_sturm, sigma_out, nsigma,
                             stats, st);

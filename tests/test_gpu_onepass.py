@@ -115,6 +115,26 @@ def test_onepass_rank_deficient():
     assert np.all(sigma[6:] == 0.0)
 
 
+@pytest.mark.parametrize("l", [1, 5, 37, 100])
+def test_onepass_rank_exact_products(l):
+    """Exact-rank products M N (float32): the one-sweep rank equals l, the
+    oracle's rank and the two-sweep rank; the singular values of B agree with
+    the two-sweep run to the float32 level."""
+    from oracle import rank as orank
+    device()
+    banner(f"one-pass rank of product l={l}")
+    A32 = inputs.product_matrix(600, 400, l, seed=5).astype(np.float32)
+    q = inputs.start_vector(600, seed=2)
+    ref = orank.numerical_rank(A32.astype(np.float64), 1e-5, q)
+    rank, rank_s, sig, status, stats = gkb.gkb_numerical_rank(to_dev(A32), 1e-5, q1=to_dev(q), one_pass=True)
+    rank2, _, sig2, _, _ = gkb.gkb_numerical_rank(to_dev(A32), 1e-5, q1=to_dev(q))
+    print(f"l={l} rank {rank} sturm {rank_s} steps {sig.size} (two-sweep {sig2.size}, oracle {ref['steps']}) "
+          f"recomputed {stats['refreshes']}", flush=True)
+    assert rank == l and rank_s == l and rank2 == l and ref["rank"] == l
+    top = min(l, sig.size, sig2.size)
+    assert np.max(np.abs(sig[:top] - sig2[:top])) <= 8 * np.sqrt(l + 1) * U32 * sig2[0]
+
+
 def test_onepass_deterministic():
     device()
     banner("one-pass determinism")
@@ -134,7 +154,9 @@ def test_onepass_rejects_other_inputs():
     with pytest.raises(gkb.GkbError):
         gkb.gkb_partial_svd(to_dev(rng.standard_normal((50, 32))), 2, 6, 1e-6, 2, one_pass=True)
     with pytest.raises(gkb.GkbError):
-        gkb.gkb_numerical_rank(to_dev(rng.standard_normal((50, 32)).astype(np.float32)), 1e-3, one_pass=True)
+        gkb.gkb_numerical_rank(to_dev(rng.standard_normal((50, 30)).astype(np.float32)), 1e-3, one_pass=True)
+    with pytest.raises(gkb.GkbError):
+        gkb.gkb_numerical_rank(to_dev(rng.standard_normal((50, 32))), 1e-3, one_pass=True)
 
 
 def test_c2_fullsize_onepass_against_stored_oracle():

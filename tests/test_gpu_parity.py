@@ -369,18 +369,21 @@ def test_c3_fullsize_bf16_refined_against_stored_oracle():
     assert err.max() < err_u.max()
 
 
-def test_c2_gapped_rank_fullsize():
+@pytest.mark.parametrize("one_pass", [False, True])
+def test_c2_gapped_rank_fullsize(one_pass):
     """Numerical rank at the gap after index 200 (50000 x 20000 float32, noise
     std 1e-10 so the noise edge ~ 3.7e-8 is far below s_200 = 0.95^200 ~ 3.5e-5;
-    threshold 1e-6 sigma_1): both counts must be exactly 200."""
+    threshold 1e-6 sigma_1): both counts must be exactly 200, with two sweeps
+    of A per step or one."""
     import torch
     device()
-    banner("c2 gapped rank 50000x20000 f32")
+    banner(f"c2 gapped rank 50000x20000 f32 one_pass={one_pass}")
     A32, s, _, _ = inputs.lowrank_noise(50000, 20000, 200, 0.95, 1e-10, seed=2, dtype=np.float32)
     Ad = torch.from_numpy(A32).to("cuda:0")
     del A32
     q = to_dev(inputs.start_vector(50000, seed=1))
-    rank, rank_s, sig, status, st = gkb.gkb_numerical_rank(Ad, 1e-6, k_max=400, q1=q)
-    print(f"gapped rank {rank} sturm {rank_s} steps {len(sig)} breakdown {st['breakdown']}", flush=True)
+    rank, rank_s, sig, status, st = gkb.gkb_numerical_rank(Ad, 1e-6, k_max=400, q1=q, one_pass=one_pass)
+    print(f"gapped rank {rank} sturm {rank_s} steps {len(sig)} breakdown {st['breakdown']} "
+          f"products {st['matvecs']} recomputed {st['refreshes']}", flush=True)
     assert rank == 200 and rank_s == 200
     assert np.max(np.abs(sig[:200] - s) / s) < 1e-3
