@@ -179,30 +179,46 @@ def cpu_baseline(A32, q, budget_s=20.0):
                       f"underestimates the oracle's time); upcast took {t_up:.1f} s"}
 
 
-def bf16_leg(gkb, torch, Ad, qd, stream, steps):
-    """bfloat16 storage + float32 Rayleigh-Ritz refinement of the same matrix."""
+def bf16_leg(gkb, torch, Ad, qd, stream, steps, one_pass=True):
+    """bfloat16 storage + float32 Rayleigh-Ritz refinement of the same matrix;
+    one sweep of the bfloat16 A per step (and two, for comparison)."""
     A16 = gkb.gkb_cast_bf16(Ad)
-    ws = torch.empty(gkb.gkb_workspace_size(A16, R, K, refine=Ad), dtype=torch.uint8, device=Ad.device)
-    run = lambda: gkb.gkb_partial_svd(A16, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
-                                      check_every=CHECK_EVERY, refine=Ad)
-    run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        sig, _, _, status, st = run()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1000.0 / steps
-    un = gkb.gkb_partial_svd(A16, R, K, TOL, RESTARTS, q1=qd, stream=stream, check_every=CHECK_EVERY)[0]
-    out = {"ms": ms, "triplets_per_s": st["nconv"] / (ms / 1000.0), "matvecs": st["matvecs"],
-           "ms_refine": st["ms_refine"], "refined": st["refined"]}
+    ws = torch.empty(max(gkb.gkb_workspace_size(A16, R, K, refine=Ad),
+                         gkb.gkb_workspace_size(A16, R, K, refine=Ad, one_pass=True)),
+                     dtype=torch.uint8, device=Ad.device)
+
+    def run(one):
+        return gkb.gkb_partial_svd(A16, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
+                                   check_every=CHECK_EVERY, refine=Ad, one_pass=one)
+
+    def timed(one):
+        run(one)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = run(one)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1000.0 / steps, res
+
+    ms, (sig, _, _, status, st) = timed(one_pass)
+    ms_other, (sig_o, _, _, _, st_o) = timed(not one_pass)
+    un = gkb.gkb_partial_svd(A16, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream, check_every=CHECK_EVERY,
+                             one_pass=one_pass)[0]
+    out = {"step": "one_sweep" if one_pass else "two_product", "ms": ms,
+           "triplets_per_s": st["nconv"] / (ms / 1000.0), "matvecs": st["matvecs"],
+           "ms_refine": st["ms_refine"], "refined": st["refined"],
+           ("two_product" if one_pass else "one_sweep"): {
+               "ms": ms_other, "triplets_per_s": st_o["nconv"] / (ms_other / 1000.0), "matvecs": st_o["matvecs"]}}
     ref_path = os.path.join(ROOT, "tests", "golden", "c2_oracle_top50.json")
     if os.path.exists(ref_path):
         want = np.array(json.load(open(ref_path))["sigma"])
         e_ref = np.abs(sig - want) / want
         e_un = np.abs(un - want) / want
+        e_o = np.abs(sig_o - want) / want
         out["sigma_rel_err_vs_f64_oracle"] = {
             "unrefined_max": float(e_un.max()), "unrefined_median": float(np.median(e_un)),
             "refined_max": float(e_ref.max()), "refined_median": float(np.median(e_ref)),
+            "refined_max_other_step": float(e_o.max()),
             "refined_per_triplet": [float(x) for x in e_ref]}
     xn = torch.randn(N, dtype=torch.float32, device=Ad.device)
     xm = torch.randn(M, dtype=torch.float32, device=Ad.device)
@@ -211,8 +227,12 @@ def bf16_leg(gkb, torch, Ad, qd, stream, steps):
     mws = torch.empty(gkb.gkb_matvec_workspace_size(A16), dtype=torch.uint8, device=Ad.device)
     ms_n = time_kernel(lambda: gkb.gkb_matvec(A16, xn, 0, y=yn, stream=stream), 20, stream)
     ms_t = time_kernel(lambda: gkb.gkb_matvec(A16, xm, 1, y=ym, workspace=mws, stream=stream), 20, stream)
+    fp, fw, fy, fws = fused_operands(gkb, torch, A16, Ad.device)
+    ms_f = time_kernel(lambda: gkb.gkb_matvec_fused(A16, fp, fw, fy, fws, stream=stream), 20, stream)
     out["gemv_n_bf16_GBps"] = (M * N * 2 + N * 4 + M * 8) / (ms_n * 1e-3) / 1e9
     out["gemv_t_bf16_GBps"] = (M * N * 2 + M * 4 + N * 8) / (ms_t * 1e-3) / 1e9
+    out["gemv_fused_bf16_ms"] = ms_f
+    out["gemv_fused_bf16_GBps"] = (M * N * 2 + N * 4 + M * 8 + N * 8) / (ms_f * 1e-3) / 1e9
     del A16, ws
     return out
 
@@ -476,7 +496,7 @@ def main():
     for leg in [x for x in args.legs.split(",") if x]:
         log(f"leg {leg}")
         if leg == "bf16":
-            legs["bf16_refined"] = bf16_leg(gkb, torch, Ad, qd, stream, args.steps)
+            legs["bf16_refined"] = bf16_leg(gkb, torch, Ad, qd, stream, args.steps, one_pass)
         elif leg == "rank":
             legs["rank_gapped"] = rank_leg(gkb, inputs, torch, dev, stream)
         elif leg == "batched":

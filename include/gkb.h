@@ -96,8 +96,9 @@ typedef struct {
                        /* 0 = test only at the end of a cycle (fixed k, as the */
                        /* paper's Algorithm 2)                                 */
   int one_pass;        /* 1: read A once per step instead of twice (GKB_F32   */
-                       /* with n, lda multiples of 4, n <= 24576, A 16-byte    */
-                       /* aligned; else GKB_ERR_INVALID).  One sweep forms     */
+                       /* or GKB_BF16 with n, lda multiples of 4 or 8,         */
+                       /* n <= 24576, A 16-byte aligned; else                  */
+                       /* GKB_ERR_INVALID).  One sweep forms                   */
                        /* A p and A^T A p in float64; A^T q_{i+1} then follows */
                        /* from eq. (2.2) as (A^T A p - (A^T Q) c) / beta, with */
                        /* c the recurrence and Gram-Schmidt coefficients and   */

@@ -30,9 +30,9 @@ gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, 
 
 /*
  * Both products of a Golub-Kahan step in one sweep of A: w = A p (m doubles)
- * and y = A^T w (n doubles), every sum in float64 (A float32, row-major,
- * lda and n multiples of 4, A 16-byte aligned, n <= 24576; p float32, n
- * entries).  A workgroup streams a range of rows once, reducing each row's
+ * and y = A^T w (n doubles), every sum in float64 (A float32 or bfloat16,
+ * row-major, lda and n multiples of 4 (float32) or 8 (bfloat16), A 16-byte
+ * aligned, n <= 24576; p float32, n entries).  A workgroup streams a range of rows once, reducing each row's
  * dot product before adding the row, scaled by it, into its partial of A^T w;
  * the partials (gkb_matvec_fused_workspace_size bytes) are added in a fixed
  * order.  A^T q of the next Lanczos vector then follows from y and the

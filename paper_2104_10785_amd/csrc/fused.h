@@ -13,11 +13,14 @@ constexpr int64_t FUSED_NMAX = 24576;    // longest row (768 threads x 8 groups 
 // exceeds this fraction of the largest coefficient seen
 constexpr double ONEPASS_TAU = 1e-10;
 
-// true if A (float32, m x n, lda) can take the fused sweep
-bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A);
+// true if A (m x n, lda; dtype 1 = float32, 2 = bfloat16) can take the fused
+// sweep: n and lda multiples of the 16-byte group (4 or 8 elements),
+// n <= FUSED_NMAX, A 16-byte aligned
+bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A, int dtype);
 // number of workgroups (= partial-sum rows) the sweep uses
 int fused_blocks(int64_t m, int64_t n);
 
+// A float32 (dtype 1) or bfloat16 (dtype 2, widened exactly to float32).
 // With win == nullptr: w = A p (float64, m) and the partials of y = A^T w;
 // p is read as float32 (a float64 p is rounded to float32 once, so w and y
 // are the exact products with that float32 vector).  With win != nullptr: the
@@ -26,9 +29,9 @@ int fused_blocks(int64_t m, int64_t n);
 // a fixed order unless y is null.  Skipped when flag[0] != 0, or when run_if
 // is given and run_if[0] == 0.
 template <typename TP>
-hipError_t launch_gemv_fused(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win,
-                             double* w, double* y, double* ypart, int64_t ldy, const int* flag, hipStream_t st,
-                             const int* run_if = nullptr);
+hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, int64_t n, const TP* p,
+                             const double* win, double* w, double* y, double* ypart, int64_t ldy, const int* flag,
+                             hipStream_t st, const int* run_if = nullptr);
 
 // The recovery of A^T q_tq after w = A p - Q[:, 0..t) c_tot has been
 // normalised to beta q_tq, with c_tot[j] = c[j] plus xc[j - x0] for

@@ -39,36 +39,58 @@ __device__ __forceinline__ double wsum(double v) {
 // update after the barrier, so that only their float32 form stays live across
 // it (fewer registers, more waves per CU).
 // GIVEN_W: w is an input (y = A^T win) and no row needs a reduction.
-template <int T, int U, int R, int D, typename TP, bool GIVEN_W>
-__global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+// TA: float (4 per 16-byte group) or bfloat16 (8 per group, widened exactly
+// to float32).
+template <typename TA> struct Elems;
+template <> struct Elems<float> {
+  static constexpr int VN = 4;
+  static constexpr bool F32DOT = false;   // row dot products in float64
+  __device__ __forceinline__ static float at(const f4& v, int e) { return v[e]; }
+};
+template <> struct Elems<bf16> {
+  static constexpr int VN = 8;
+  // per-thread dot products in float32 (as the two-product bfloat16 path
+  // accumulates), then float64 across threads: halves the arithmetic per
+  // element, which bounds this form; A^T w stays float64 and is exact for
+  // whatever w is computed, so the recovery is unaffected
+  static constexpr bool F32DOT = true;
+  __device__ __forceinline__ static float at(const f4& v, int e) {
+    const uint32_t b = __float_as_uint(v[e >> 1]);
+    return __uint_as_float((e & 1) ? (b & 0xffff0000u) : (b << 16));
+  }
+};
+
+template <int T, int U, int R, int D, typename TA, typename TP, bool GIVEN_W>
+__global__ __launch_bounds__(T) void k_gemv_fused(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                   const TP* __restrict__ p, const double* __restrict__ win,
                                                   int64_t rows_per_block, double* __restrict__ w,
                                                   double* __restrict__ ypart, int64_t ldy,
                                                   const int* __restrict__ flag, const int* __restrict__ run_if) {
   constexpr int NWV = T / 64;
+  constexpr int VN = Elems<TA>::VN;
   if (flag != nullptr && flag[0] != 0) return;
   if (run_if != nullptr && run_if[0] == 0) return;
   extern __shared__ float pl[];                  // p as float32, n entries (not GIVEN_W)
   __shared__ double red[2][R][NWV];              // [parity][row][wave]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t ng = n >> 2;                     // 16-byte groups per row
+  const int64_t ng = n / VN;                     // 16-byte groups per row
   if constexpr (!GIVEN_W) {
     for (int64_t j = tid; j < n; j += T) pl[j] = (float)p[j];
     __syncthreads();
   }
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = std::min<int64_t>(m, r0 + rows_per_block);
-  double y[U][4];
+  double y[U][VN];
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) y[u][e] = 0.0;
+    for (int e = 0; e < VN; ++e) y[u][e] = 0.0;
   f4 cur[R][U], nxt[R][U], nx2[R][U];
   auto load_rows = [&](int64_t i, f4 (&dst)[R][U]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const bool ok = i + r < r1;
-      const f4* row = reinterpret_cast<const f4*>(A + (ok ? i + r : r0) * lda);
+      const f4* row = reinterpret_cast<const f4*>(A + (ok ? i + r : r0) * lda);   // 16-byte aligned rows
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t g = tid + (int64_t)u * T;
@@ -99,18 +121,43 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, i
       for (int r = 0; r < R; ++r) wi[r] = i + r < r1 ? win[i + r] : 0.0;
     } else {
       double d[R];
+      if constexpr (Elems<TA>::F32DOT) {
+        float df[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) d[r] = 0.0;
+        for (int r = 0; r < R; ++r) df[r] = 0.f;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t g = tid + (int64_t)u * T;
-        if (g < ng) {
-          const f4 pv = reinterpret_cast<const f4*>(pl)[g];
+        for (int u = 0; u < U; ++u) {
+          const int64_t g = tid + (int64_t)u * T;
+          if (g < ng) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const double pe = (double)pv[e];
+            for (int h = 0; h < VN / 4; ++h) {
+              const f4 pv = reinterpret_cast<const f4*>(pl)[(VN / 4) * g + h];
 #pragma unroll
-            for (int r = 0; r < R; ++r) d[r] += (double)cur[r][u][e] * pe;
+              for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int r = 0; r < R; ++r) df[r] = fmaf(Elems<TA>::at(cur[r][u], 4 * h + e), pv[e], df[r]);
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[r] = (double)df[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[r] = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t g = tid + (int64_t)u * T;
+          if (g < ng) {
+#pragma unroll
+            for (int h = 0; h < VN / 4; ++h) {
+              const f4 pv = reinterpret_cast<const f4*>(pl)[(VN / 4) * g + h];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const double pe = (double)pv[e];
+#pragma unroll
+                for (int r = 0; r < R; ++r) d[r] += (double)Elems<TA>::at(cur[r][u], 4 * h + e) * pe;
+              }
+            }
           }
         }
       }
@@ -140,7 +187,7 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, i
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) y[u][e] += (double)cur[r][u][e] * wi[r];
+        for (int e = 0; e < VN; ++e) y[u][e] += (double)Elems<TA>::at(cur[r][u], e) * wi[r];
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -155,22 +202,47 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const float* __restrict__ A, i
     const int64_t g = tid + (int64_t)u * T;
     if (g < ng)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) yp[4 * g + e] = y[u][e];
+      for (int e = 0; e < VN; ++e) yp[VN * g + e] = y[u][e];
   }
 }
 
-// sum over workgroups b of ypart[b][j], always in the same order
-__device__ __forceinline__ double sum_partials(const double* __restrict__ ypart, int nb, int64_t ldy, int64_t j) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int b = 0;
-  for (; b + 3 < nb; b += 4) {
-    s0 += ypart[(int64_t)b * ldy + j];
-    s1 += ypart[(int64_t)(b + 1) * ldy + j];
-    s2 += ypart[(int64_t)(b + 2) * ldy + j];
-    s3 += ypart[(int64_t)(b + 3) * ldy + j];
+// Column sums of the partials with 256 threads per 64 columns: wave v adds
+// the partial rows [v nb / 4, (v + 1) nb / 4) for column j = lane, and wave 0
+// adds the four sums in wave order (a fixed order).  `extra` (may be null)
+// gives each wave a second per-column sum to reduce the same way, over
+// columns [v t / 4, (v + 1) t / 4) of G weighted by the coefficient of that
+// column (coef(j)).  Returns (sum of partials, sum of extra) on wave 0.
+constexpr int RCOLS = 64;
+
+template <typename CoefF>
+__device__ __forceinline__ void column_sums(const double* __restrict__ ypart, int nb, int64_t ldy, int64_t j, bool in,
+                                            const double* G, int64_t ldg, int t, CoefF coef, double* out_y,
+                                            double* out_g) {
+  __shared__ double ps[2][4][RCOLS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double sy = 0.0, sg = 0.0;
+  if (in) {
+    const int b0 = (int)((int64_t)nb * wave / 4), b1 = (int)((int64_t)nb * (wave + 1) / 4);
+    double s0 = 0.0, s1 = 0.0;
+    int b = b0;
+    for (; b + 1 < b1; b += 2) {
+      s0 += ypart[(int64_t)b * ldy + j];
+      s1 += ypart[(int64_t)(b + 1) * ldy + j];
+    }
+    if (b < b1) s0 += ypart[(int64_t)b * ldy + j];
+    sy = s0 + s1;
+    if (G != nullptr) {
+      const int c0 = t * wave / 4, c1 = t * (wave + 1) / 4;
+      for (int c = c0; c < c1; ++c) sg += G[(int64_t)c * ldg + j] * coef(c);
+    }
   }
-  for (; b < nb; ++b) s0 += ypart[(int64_t)b * ldy + j];
-  return (s0 + s1) + (s2 + s3);
+  ps[0][wave][lane] = sy;
+  ps[1][wave][lane] = sg;
+  __syncthreads();
+  if (wave == 0) {
+    *out_y = ((ps[0][0][lane] + ps[0][1][lane]) + ps[0][2][lane]) + ps[0][3][lane];
+    *out_g = ((ps[1][0][lane] + ps[1][1][lane]) + ps[1][2][lane]) + ps[1][3][lane];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fused_reduce(const double* __restrict__ ypart, int nb, int64_t ldy,
@@ -178,34 +250,35 @@ __global__ __launch_bounds__(256) void k_fused_reduce(const double* __restrict__
                                                       const int* __restrict__ flag, const int* __restrict__ run_if) {
   if (flag != nullptr && flag[0] != 0) return;
   if (run_if != nullptr && run_if[0] == 0) return;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  y[j] = sum_partials(ypart, nb, ldy, j);
+  const int64_t j = (int64_t)blockIdx.x * RCOLS + (threadIdx.x & 63);
+  double sy, sg;
+  column_sums(ypart, nb, ldy, j, j < n, nullptr, 0, 0, [](int) { return 0.0; }, &sy, &sg);
+  if (threadIdx.x < 64 && j < n) y[j] = sy;
 }
 
-template <int T, int U, int R, int D, typename TP, bool GIVEN_W>
-hipError_t launch_v(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
+template <int T, int U, int R, int D, typename TA, typename TP, bool GIVEN_W>
+hipError_t launch_v(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
                     double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st) {
   static bool set = false;
   if (!GIVEN_W && !set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, D, TP, GIVEN_W>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(FUSED_NMAX * 4));
     if (e != hipSuccess) return e;
     set = true;
   }
   const int nb = fused_blocks(m, n);
   const int64_t rpb = (m + nb - 1) / nb;
-  hipLaunchKernelGGL((k_gemv_fused<T, U, R, D, TP, GIVEN_W>), dim3(nb), dim3(T), GIVEN_W ? 0 : (size_t)n * 4, st, A,
+  hipLaunchKernelGGL((k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>), dim3(nb), dim3(T), GIVEN_W ? 0 : (size_t)n * 4, st, A,
                      lda, m, n, p, win, rpb, w, ypart, ldy, flag, run_if);
   return hipGetLastError();
 }
 
-template <int T, int U, int R, int D, typename TP>
-hipError_t launch_u(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
+template <int T, int U, int R, int D, typename TA, typename TP>
+hipError_t launch_u(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
                     double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st) {
   if (win != nullptr)
-    return launch_v<T, U, R, D, TP, true>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
-  return launch_v<T, U, R, D, TP, false>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+    return launch_v<T, U, R, D, TA, TP, true>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+  return launch_v<T, U, R, D, TA, TP, false>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
 }
 
 // Launch shape by row length (measured on MI355X): short rows take several
@@ -270,11 +343,11 @@ __global__ __launch_bounds__(256) void k_onepass_recover(const double* __restric
       err[tq] = e;
     }
   }
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  double acc = 0.0;
-  for (int j = 0; j < t; ++j) acc += G[(int64_t)j * ldg + i] * coef_total(c, j, xc, x0, nx);
-  const double g = (sum_partials(ypart, nb, ldy, i) - acc) / b;
+  const int64_t i = (int64_t)blockIdx.x * RCOLS + (threadIdx.x & 63);
+  double y, acc;
+  column_sums(ypart, nb, ldy, i, i < n, G, ldg, t, [&](int j) { return coef_total(c, j, xc, x0, nx); }, &y, &acc);
+  if (threadIdx.x >= 64 || i >= n) return;
+  const double g = (y - acc) / b;
   G[(int64_t)tq * ldg + i] = g;
   z[i] = g - b * pprev[i];
 }
@@ -302,9 +375,10 @@ __global__ __launch_bounds__(256) void k_onepass_fix(const double* __restrict__ 
                                                      int64_t n, const int* __restrict__ flag,
                                                      const int* __restrict__ refresh) {
   if ((flag != nullptr && flag[0] != 0) || refresh[0] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const double g = sum_partials(ypart, nb, ldy, i);
+  const int64_t i = (int64_t)blockIdx.x * RCOLS + (threadIdx.x & 63);
+  double g, unused;
+  column_sums(ypart, nb, ldy, i, i < n, nullptr, 0, 0, [](int) { return 0.0; }, &g, &unused);
+  if (threadIdx.x >= 64 || i >= n) return;
   G[(int64_t)tq * ldg + i] = g;
   z[i] = g - beta[0] * pprev[i];
 }
@@ -317,8 +391,9 @@ __global__ __launch_bounds__(256) void k_narrow(const double* __restrict__ src, 
 
 }  // namespace
 
-bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A) {
-  return m >= 1 && n >= 4 && n <= FUSED_NMAX && (n & 3) == 0 && (lda & 3) == 0 &&
+bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A, int dtype) {
+  const int64_t vn = dtype == 2 ? 8 : 4;
+  return (dtype == 1 || dtype == 2) && m >= 1 && n >= vn && n <= FUSED_NMAX && n % vn == 0 && lda % vn == 0 &&
          (reinterpret_cast<uintptr_t>(A) & 15) == 0;
 }
 
@@ -328,32 +403,52 @@ int fused_blocks(int64_t m, int64_t n) {
 }
 
 template <typename TP>
-hipError_t launch_gemv_fused(const float* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win,
-                             double* w, double* y, double* ypart, int64_t ldy, const int* flag, hipStream_t st,
-                             const int* run_if) {
+hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, int64_t n, const TP* p,
+                             const double* win, double* w, double* y, double* ypart, int64_t ldy, const int* flag,
+                             hipStream_t st, const int* run_if) {
   const FusedShape fs = fused_shape(n);
   hipError_t e;
-#define GKB_FUSED(T, U, R, D) e = launch_u<T, U, R, D, TP>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st)
-  if (fs.T == 128) GKB_FUSED(128, 1, 16, 1);
-  else if (fs.T == 256 && fs.U == 1) GKB_FUSED(256, 1, 8, 1);
-  else if (fs.T == 256 && fs.U == 2) GKB_FUSED(256, 2, 4, 1);
-  else if (fs.T == 256) GKB_FUSED(256, 4, 2, 1);
-  else if (fs.T == 512) GKB_FUSED(512, 4, 1, 2);
-  else if (fs.T == 768) GKB_FUSED(768, 8, 1, 1);
-  else if (fs.U <= 3) GKB_FUSED(1024, 3, 1, 2);
-  else if (fs.U == 4) GKB_FUSED(1024, 4, 1, 2);
-  else GKB_FUSED(1024, 5, 1, 1);
+  if (dtype == 2) {
+    // bfloat16: half the bytes per row, so a barrier per row would dominate;
+    // several rows per step, 512 threads with the registers this leaves
+    // (measured: n = 20000, 5 groups x 3 rows 4.7 TB/s against 3.0 TB/s for
+    // 1024 threads x 1 row)
+    const bf16* Ab = reinterpret_cast<const bf16*>(A);
+#define GKB_FUSED(T, U, R, D) \
+  e = launch_u<T, U, R, D, bf16, TP>(Ab, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st)
+    if (n <= 1024) GKB_FUSED(128, 1, 16, 1);
+    else if (n <= 2048) GKB_FUSED(256, 1, 8, 1);
+    else if (n <= 4096) GKB_FUSED(256, 2, 4, 1);
+    else if (n <= 8192) GKB_FUSED(512, 2, 4, 1);
+    else if (n <= 16384) GKB_FUSED(512, 4, 3, 1);
+    else if (n <= 20480) GKB_FUSED(512, 5, 3, 1);
+    else GKB_FUSED(512, 6, 2, 1);
 #undef GKB_FUSED
+  } else {
+    const float* Af = reinterpret_cast<const float*>(A);
+#define GKB_FUSED(T, U, R, D) \
+  e = launch_u<T, U, R, D, float, TP>(Af, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st)
+    if (fs.T == 128) GKB_FUSED(128, 1, 16, 1);
+    else if (fs.T == 256 && fs.U == 1) GKB_FUSED(256, 1, 8, 1);
+    else if (fs.T == 256 && fs.U == 2) GKB_FUSED(256, 2, 4, 1);
+    else if (fs.T == 256) GKB_FUSED(256, 4, 2, 1);
+    else if (fs.T == 512) GKB_FUSED(512, 4, 1, 2);
+    else if (fs.T == 768) GKB_FUSED(768, 8, 1, 1);
+    else if (fs.U <= 3) GKB_FUSED(1024, 3, 1, 2);
+    else if (fs.U == 4) GKB_FUSED(1024, 4, 1, 2);
+    else GKB_FUSED(1024, 5, 1, 1);
+#undef GKB_FUSED
+  }
   if (e != hipSuccess || y == nullptr) return e;
-  hipLaunchKernelGGL(k_fused_reduce, dim3(nblk(n, 256)), dim3(256), 0, st, ypart, fused_blocks(m, n), ldy, n, y,
+  hipLaunchKernelGGL(k_fused_reduce, dim3(nblk(n, RCOLS)), dim3(256), 0, st, ypart, fused_blocks(m, n), ldy, n, y,
                      flag, run_if);
   return hipGetLastError();
 }
 
-template hipError_t launch_gemv_fused<float>(const float*, int64_t, int64_t, int64_t, const float*, const double*,
+template hipError_t launch_gemv_fused<float>(const void*, int, int64_t, int64_t, int64_t, const float*, const double*,
                                              double*, double*, double*, int64_t, const int*, hipStream_t,
                                              const int*);
-template hipError_t launch_gemv_fused<double>(const float*, int64_t, int64_t, int64_t, const double*,
+template hipError_t launch_gemv_fused<double>(const void*, int, int64_t, int64_t, int64_t, const double*,
                                               const double*, double*, double*, double*, int64_t, const int*,
                                               hipStream_t, const int*);
 
@@ -361,7 +456,7 @@ hipError_t launch_onepass_recover(const double* ypart, int nb, int64_t ldy, doub
                                   const double* c, const double* xc, int x0, int nx, const double* beta, int tq,
                                   const double* pprev, double* z, int64_t n, double* err, const double* sig,
                                   double eps0, double tau, int* refresh, const int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_onepass_recover, dim3(nblk(n, 256)), dim3(256), 0, st, ypart, nb, ldy, G, ldg, t, c, xc, x0,
+  hipLaunchKernelGGL(k_onepass_recover, dim3(nblk(n, RCOLS)), dim3(256), 0, st, ypart, nb, ldy, G, ldg, t, c, xc, x0,
                      nx, beta, tq, pprev, z, n, err, sig, eps0, tau, refresh, flag);
   return hipGetLastError();
 }
@@ -379,7 +474,7 @@ hipError_t launch_err_restart(const double* src, int nq, double* dst, int l, hip
 hipError_t launch_onepass_fix(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int tq,
                               const double* beta, const double* pprev, double* z, int64_t n, const int* flag,
                               const int* refresh, hipStream_t st) {
-  hipLaunchKernelGGL(k_onepass_fix, dim3(nblk(n, 256)), dim3(256), 0, st, ypart, nb, ldy, G, ldg, tq, beta, pprev,
+  hipLaunchKernelGGL(k_onepass_fix, dim3(nblk(n, RCOLS)), dim3(256), 0, st, ypart, nb, ldy, G, ldg, tq, beta, pprev,
                      z, n, flag, refresh);
   return hipGetLastError();
 }

@@ -262,7 +262,7 @@ struct Solver {
     if (onepass) {
       // z = A^T q_1 with float64 sums, kept as the first column of A^T Q
       if constexpr (std::is_same<TB, double>::value) {
-        GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.lda, A.m, A.n, nullptr, Qc(0), nullptr, z(), ypart(), L.ldn,
+        GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, nullptr, Qc(0), nullptr, z(), ypart(), L.ldn,
                                                flag(), st));
         GKB_HIP(gkb::launch_copy_vec<double>(z(), A.n, GQ(cur), st));
         GKB_HIP(hipMemsetAsync(refresh(), 0, 4 * sizeof(int), st));
@@ -289,7 +289,7 @@ struct Solver {
     return GKB_OK;
   }
 
-  const float* fA() const { return reinterpret_cast<const float*>(A.data); }
+  const void* fA() const { return A.data; }
 
   // The same step with one sweep of A (float32 A, float64 bases).  From
   // p = P[:, pi]: w = A p and y = A^T w in one pass; w loses the recurrence
@@ -305,7 +305,7 @@ struct Solver {
   gkb_status onepass_step(int pi, int qp, int nqc, int qn, bool use_rho) {
     if constexpr (std::is_same<TB, double>::value) {
       const int nb = gkb::fused_blocks(A.m, A.n);
-      GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.lda, A.m, A.n, Pc(pi), nullptr, w(), nullptr, ypart(), L.ldn,
+      GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, Pc(pi), nullptr, w(), nullptr, ypart(), L.ldn,
                                              flag(), st));
       if (use_rho)
         GKB_HIP(gkb::launch_update<TB>(Q(cur), L.ldm, nqc, A.m, w(), rho(), nullptr, flag(), st));
@@ -317,7 +317,7 @@ struct Solver {
                                           use_rho ? rho() : pcoef() + pi, use_rho ? 0 : qp, use_rho ? nqc : 1,
                                           qcoef() + qn, qn, Pc(pi), z(), A.n, err(cur), sig() + nsig, eps0(),
                                           gkb::ONEPASS_TAU, refresh(), flag(), st));
-      GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.lda, A.m, A.n, nullptr, Qc(qn), nullptr, nullptr, ypart(),
+      GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, nullptr, Qc(qn), nullptr, nullptr, ypart(),
                                              L.ldn, flag(), st, refresh()));
       GKB_HIP(gkb::launch_onepass_fix(ypart(), nb, L.ldn, GQ(cur), L.ldn, qn, qcoef() + qn, Pc(pi), z(), A.n, flag(),
                                       refresh(), st));
@@ -477,19 +477,24 @@ bool cholesky_upper(int d, const std::vector<double>& G, std::vector<double>& R)
 //   sigma = s,  V = V_d Yr,  U = W R^{-1} Xr (= A32 V / sigma).
 template <typename TB>
 gkb_status refine_bf16(Solver<TB>& S, const gkb_matrix* Am, const Proj& pr, const Ritz& rz, int r, int d,
-                       double* sigma, TB* U, TB* V, int* refined) {
-  static_assert(sizeof(TB) == 4, "refinement runs on float32 bases");
+                       double* sigma, float* U, float* V, int* refined) {
   hipStream_t st = S.st;
   float* Vd = reinterpret_cast<float*>(S.ws + S.L.Vd);
   float* W = reinterpret_cast<float*>(S.ws + S.L.Wr);
   double* Gpart = reinterpret_cast<double*>(S.ws + S.L.Gpart);
   double* Gd = reinterpret_cast<double*>(S.ws + S.L.G);
   const int64_t m = Am->m, n = Am->n;
-  std::vector<float> Yh;
-  to_colmajor<float>(rz.Y, pr.np, rz.kk, d, Yh);
-  GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(float), hipMemcpyHostToDevice, st));
-  GKB_HIP(gkb::launch_gemm_tall<float>(reinterpret_cast<const float*>(S.P(S.cur)), S.L.ldn, n, pr.np,
-                                       reinterpret_cast<const float*>(S.Ys()), pr.np, d, Vd, S.L.ldn, st));
+  // V_d = P Y_d in the basis precision, then float32 for the refinement products
+  std::vector<TB> Yh;
+  to_colmajor<TB>(rz.Y, pr.np, rz.kk, d, Yh);
+  GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
+  if constexpr (std::is_same<TB, float>::value) {
+    GKB_HIP(gkb::launch_gemm_tall<float>(S.P(S.cur), S.L.ldn, n, pr.np, S.Ys(), pr.np, d, Vd, S.L.ldn, st));
+  } else {
+    double* Vo = reinterpret_cast<double*>(S.ws + S.L.Vo);
+    GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, n, pr.np, S.Ys(), pr.np, d, Vo, S.L.ldn, st));
+    GKB_HIP(gkb::launch_narrow(Vo, S.L.ldn * d, Vd, st));   // rows n..ldn of each column are never read
+  }
   GKB_HIP(gkb::launch_gemm_rm(Am->refine_f32, Am->lda_refine, m, n, Vd, S.L.ldn, d, W, S.L.ldm, st));
   GKB_HIP(gkb::launch_gram(W, S.L.ldm, m, d, Gpart, Gd, st));
   std::vector<double> G((size_t)d * d), R;
@@ -518,20 +523,15 @@ gkb_status refine_bf16(Solver<TB>& S, const gkb_matrix* Am, const Proj& pr, cons
   GKB_HIP(hipMemcpyAsync(S.Xs(), Mh.data(), Mh.size() * sizeof(float), hipMemcpyHostToDevice, st));
   GKB_HIP(hipMemcpyAsync(S.Ys(), Yrh.data(), Yrh.size() * sizeof(float), hipMemcpyHostToDevice, st));
   GKB_HIP(gkb::launch_gemm_tall<float>(Vd, S.L.ldn, n, d, reinterpret_cast<const float*>(S.Ys()), d, r,
-                                       reinterpret_cast<float*>(V), n, st));
+                                       V, n, st));
   GKB_HIP(gkb::launch_gemm_tall<float>(W, S.L.ldm, m, d, reinterpret_cast<const float*>(S.Xs()), d, r,
-                                       reinterpret_cast<float*>(U), m, st));
+                                       U, m, st));
   GKB_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < r; ++i) sigma[i] = sr[i];
   *refined = 1;
   return GKB_OK;
 }
 
-template <>
-gkb_status refine_bf16<double>(Solver<double>&, const gkb_matrix*, const Proj&, const Ritz&, int, int, double*,
-                               double*, double*, int*) {
-  return fail(GKB_ERR_INVALID, "refinement needs a bfloat16 matrix");
-}
 
 // TO: type of U and V (TB, or float for the one-pass step on float64 bases)
 template <typename TB, typename TO = TB>
@@ -666,7 +666,7 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   for (int i = 0; i < r; ++i) sigma[i] = i < r_eff ? rz.s[i] : 0.0;
   int refined = 0;
   double ms_refine = 0.0;
-  if constexpr (!onepass) {
+  if constexpr (std::is_same<TO, float>::value) {
     if (r_eff > 0 && refine) {
       const double tr0 = now_ms();
       int d = opt.refine_dim > 0 ? opt.refine_dim : 2 * r;
@@ -815,7 +815,7 @@ size_t gkb_workspace_size(const gkb_matrix* A, int r, int k, const gkb_options* 
   if (check_matrix(A) != GKB_OK) return 0;
   if (r < 1 || k < r || k > std::min(A->m, A->n)) return 0;
   const bool onepass = opt != nullptr && opt->one_pass != 0;
-  if (onepass && (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data))) return 0;
+  if (onepass && !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype)) return 0;
   return make_layout(A->m, A->n, A->dtype, k, k > r, true, A->dtype == GKB_BF16 && A->refine_f32 != nullptr,
                      true, onepass)
       .total;
@@ -831,11 +831,14 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
   if (k > std::min(A->m, A->n)) return fail(GKB_ERR_INVALID, "need k <= min(m, n)");
   if (!(tol >= 0.0)) return fail(GKB_ERR_INVALID, "need tol >= 0");
   if (max_restarts < 0) return fail(GKB_ERR_INVALID, "need max_restarts >= 0");
-  if (sigma == nullptr || U == nullptr || V == nullptr)
-    return fail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
   gkb_options opt;
   gkb_default_options(&opt);
   if (opt_in) opt = *opt_in;
+  if (opt.one_pass && !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
+    return fail(GKB_ERR_INVALID, "one_pass needs a float32 (bfloat16) A with n and lda multiples of 4 (8), "
+                                 "n <= 24576, 16-byte aligned");
+  if (sigma == nullptr || U == nullptr || V == nullptr)
+    return fail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
   if (opt.keep != 0 && (opt.keep < r || opt.keep >= k))
     return fail(GKB_ERR_INVALID, "need r <= keep < k");
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
@@ -844,11 +847,6 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
   if (A->refine_f32 != nullptr) {
     if (A->dtype != GKB_BF16) return fail(GKB_ERR_INVALID, "refine_f32 is only used with GKB_BF16");
     if (A->lda_refine < A->n) return fail(GKB_ERR_INVALID, "need lda_refine >= n");
-  }
-  if (opt.one_pass) {
-    if (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data))
-      return fail(GKB_ERR_INVALID, "one_pass needs a float32 A with n and lda multiples of 4, n <= 24576, "
-                                   "16-byte aligned");
   }
   rc = check_workspace(workspace, ws_bytes, gkb_workspace_size(A, r, k, &opt));
   if (rc != GKB_OK) return rc;
@@ -869,7 +867,7 @@ size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options
   const int64_t k = k_max ? k_max : kmin;
   if (k < 1 || k > kmin) return 0;
   const bool onepass = opt != nullptr && opt->one_pass != 0;
-  if (onepass && (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data))) return 0;
+  if (onepass && !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype)) return 0;
   return make_layout(A->m, A->n, A->dtype, (int)k, false, false, false, true, onepass).total;
 }
 
@@ -889,9 +887,9 @@ gkb_status gkb_numerical_rank(const gkb_matrix* A, double tau, int tau_relative,
   gkb_default_options(&opt);
   if (opt_in) opt = *opt_in;
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
-  if (opt.one_pass && (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data)))
-    return fail(GKB_ERR_INVALID, "one_pass needs a float32 A with n and lda multiples of 4, n <= 24576, "
-                                 "16-byte aligned");
+  if (opt.one_pass && !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
+    return fail(GKB_ERR_INVALID, "one_pass needs a float32 (bfloat16) A with n and lda multiples of 4 (8), "
+                                 "n <= 24576, 16-byte aligned");
   rc = check_workspace(workspace, ws_bytes, gkb_rank_workspace_size(A, (int)k, &opt));
   if (rc != GKB_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -976,7 +974,7 @@ size_t gkb_matvec_workspace_size(const gkb_matrix* A) {
 }
 
 size_t gkb_matvec_fused_workspace_size(const gkb_matrix* A) {
-  if (check_matrix(A) != GKB_OK || A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data)) return 0;
+  if (check_matrix(A) != GKB_OK || !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype)) return 0;
   return align256((size_t)gkb::fused_blocks(A->m, A->n) * round64(A->n) * 8);
 }
 
@@ -985,13 +983,13 @@ gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, doub
   g_err.clear();
   gkb_status rc = check_matrix(A);
   if (rc != GKB_OK) return rc;
-  if (A->dtype != GKB_F32 || !gkb::fused_ok(A->m, A->n, A->lda, A->data))
-    return fail(GKB_ERR_INVALID, "the fused sweep needs float32 A, lda and n multiples of 4, n <= 24576, "
-                                 "16-byte aligned");
+  if (!gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
+    return fail(GKB_ERR_INVALID, "the fused sweep needs a float32 (bfloat16) A with lda and n multiples of 4 (8), "
+                                 "n <= 24576, 16-byte aligned");
   if (!p || !w || !y) return fail(GKB_ERR_INVALID, "p, w and y must be non-NULL");
   rc = check_workspace(workspace, ws_bytes, gkb_matvec_fused_workspace_size(A));
   if (rc != GKB_OK) return rc;
-  GKB_HIP(gkb::launch_gemv_fused<float>(reinterpret_cast<const float*>(A->data), A->lda, A->m, A->n, p, nullptr,
+  GKB_HIP(gkb::launch_gemv_fused<float>(A->data, (int)A->dtype, A->lda, A->m, A->n, p, nullptr,
                                         w, y, reinterpret_cast<double*>(workspace), round64(A->n), nullptr,
                                         reinterpret_cast<hipStream_t>(stream)));
   return GKB_OK;

@@ -398,7 +398,7 @@ def gkb_gemm_tall(A, B, C_out=None, stream=None):
 
 
 def gkb_matvec_fused(A, p, w=None, y=None, workspace=None, stream=None):
-    """(w, y) = (A p, A^T A p) in one sweep of the float32 device matrix A."""
+    """(w, y) = (A p, A^T A p) in one sweep of the float32 or bfloat16 device matrix A."""
     torch = _torch()
     mat = make_matrix(A)
     L = lib()

@@ -52,6 +52,36 @@ def test_fused_products(shape):
     assert np.array_equal(to_host(w2), w) and np.array_equal(to_host(y2), y)
 
 
+BF16_SHAPES = [(1, 8, 0), (300, 1000, 8), (2000, 2048, 0), (3001, 4096, 0), (1500, 8000, 8), (1200, 16384, 0),
+               (5000, 20000, 8), (777, 24576, 0), (70000, 96, 0)]
+
+
+@pytest.mark.parametrize("shape", BF16_SHAPES)
+def test_fused_products_bf16(shape):
+    """bfloat16 A (8 per 16-byte group, widened exactly): each thread adds its
+    at most 24 products of a row in float32 before the float64 reduction (as
+    the two-product bfloat16 path does), so w carries a float32 bound
+    32 u32 |A||p|; y must be A^T w for the w returned, with float64 sums."""
+    import torch
+    from oracle import bf16 as obf16
+    device()
+    m, n, pad = shape
+    banner(f"fused sweep bf16 {m}x{n} pad={pad}")
+    rng = np.random.default_rng(m + 5 * n + pad)
+    bits = obf16.to_bf16_bits(rng.standard_normal((m, n)).astype(np.float32))
+    A64 = obf16.from_bf16_bits(bits)
+    p = rng.standard_normal(n).astype(np.float32)
+    Ad = to_dev(_padded(bits.view(np.int16), pad)).view(torch.bfloat16)[:, :n]
+    w, y = gkb.gkb_matvec_fused(Ad, to_dev(p))
+    w, y = to_host(w), to_host(y)
+    p64 = p.astype(np.float64)
+    wref = A64 @ p64
+    wabs = np.abs(A64) @ np.abs(p64)
+    assert np.all(np.abs(w - wref) <= (32 * 2.0 ** -24 + n * U64) * wabs + 1e-300)
+    yref = A64.T @ w
+    assert np.all(np.abs(y - yref) <= (m + 1) * U64 * (np.abs(A64).T @ np.abs(w)) + 1e-300)
+
+
 def test_fused_rejects_shapes():
     device()
     banner("fused sweep shape checks")
@@ -62,3 +92,7 @@ def test_fused_rejects_shapes():
     Ad = to_dev(np.ones((10, 8), dtype=np.float64))
     with pytest.raises(gkb.GkbError):
         gkb.gkb_matvec_fused(Ad, to_dev(np.ones(8)))
+    import torch
+    Ab = to_dev(np.ones((10, 12), dtype=np.float32)).to(torch.bfloat16)   # n not a multiple of 8
+    with pytest.raises(gkb.GkbError):
+        gkb.gkb_matvec_fused(Ab, to_dev(np.ones(12, dtype=np.float32)))

@@ -279,9 +279,11 @@ def test_c2_fullsize_f32_against_stored_oracle(check_every):
     assert checks.orth_error(V[:, idx]) < 1e-5 and checks.orth_error(U[:, idx]) < 1e-5
 
 
-def test_bf16_storage_with_refinement_midsize():
+@pytest.mark.parametrize("one_pass", [False, True])
+def test_bf16_storage_with_refinement_midsize(one_pass):
     """bfloat16 storage + float32 Rayleigh-Ritz refinement, per-triplet errors
-    against the float64 oracle on the float32 matrix.
+    against the float64 oracle on the float32 matrix, with two sweeps of the
+    bfloat16 A per step or one.
 
     Unrefined (bfloat16 solve): Weyl, |sigma_i(A16) - sigma_i(A32)| <= ||A16 - A32||_2.
     Refined: the Rayleigh-Ritz values from a subspace at angle ~ ||E||/gap from
@@ -291,8 +293,9 @@ def test_bf16_storage_with_refinement_midsize():
     import torch
     from oracle import bf16 as obf16
     device()
-    m, n, r, k = 6000, 2500, 20, 60
-    banner(f"bf16 + refinement {m}x{n} r={r} k={k}")
+    # the one-sweep form needs n a multiple of 8 for bfloat16 rows
+    m, n, r, k = 6000, (2496 if one_pass else 2500), 20, 60
+    banner(f"bf16 + refinement {m}x{n} r={r} k={k} one_pass={one_pass}")
     A32, s, _, _ = inputs.lowrank_noise(m, n, 200, 0.95, 1e-6, seed=7, dtype=np.float32)
     q = inputs.start_vector(m, seed=8)
     exact = gk.partial_svd(A32.astype(np.float64), 60, 120, 1e-13, 50, q)["sigma"]
@@ -303,8 +306,8 @@ def test_bf16_storage_with_refinement_midsize():
     A32d = torch.from_numpy(A32).to("cuda:0")
     A16d = gkb.gkb_cast_bf16(A32d)
     qd = to_dev(q)
-    sig_u, Ut_u, Vt_u, st_u, stats_u = gkb.gkb_partial_svd(A16d, r, k, 1e-6, 20, q1=qd)
-    sig, Ut, Vt, status, stats = gkb.gkb_partial_svd(A16d, r, k, 1e-6, 20, q1=qd, refine=A32d)
+    sig_u, Ut_u, Vt_u, st_u, stats_u = gkb.gkb_partial_svd(A16d, r, k, 1e-6, 20, q1=qd, one_pass=one_pass)
+    sig, Ut, Vt, status, stats = gkb.gkb_partial_svd(A16d, r, k, 1e-6, 20, q1=qd, refine=A32d, one_pass=one_pass)
     torch.cuda.synchronize()
     assert st_u == 0 and status == 0 and stats["refined"] == 1
     err_un = np.abs(sig_u - exact[:r])
@@ -331,8 +334,10 @@ def test_bf16_storage_with_refinement_midsize():
     assert r2.max() <= 1.05 * r2u.max()
 
 
-def test_c3_fullsize_bf16_refined_against_stored_oracle():
-    """bfloat16 storage of the 50000 x 20000 matrix, float32 refinement; the
+@pytest.mark.parametrize("one_pass", [False, True])
+def test_c3_fullsize_bf16_refined_against_stored_oracle(one_pass):
+    """bfloat16 storage of the 50000 x 20000 matrix (two sweeps of it per step,
+    or one), float32 refinement; the
     refined singular values against the oracle's values for the float32 matrix
     (tests/golden/c2_oracle_top50.json).  Bound: ||E||^2/gap + sqrt(n) u ||A||_F,
     E = A16 - A32 with entries uniform in [-u|a|, u|a|], u = 2^-8, so
@@ -344,14 +349,16 @@ def test_c3_fullsize_bf16_refined_against_stored_oracle():
     import torch
     device()
     ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_top50.json")))
-    banner("c3 full size 50000x20000 bf16 + f32 refinement r=50 k=120 check_every=10")
+    banner(f"c3 full size 50000x20000 bf16 + f32 refinement r=50 k=120 check_every=10 one_pass={one_pass}")
     A32, s, _, _ = inputs.lowrank_noise(50000, 20000, 200, 0.95, 1e-6, seed=2, dtype=np.float32)
     q = inputs.start_vector(50000, seed=1)
     A32d = torch.from_numpy(A32).to("cuda:0")
     A16d = gkb.gkb_cast_bf16(A32d)
     qd = to_dev(q)
-    sig_u, _, _, st_u, stats_u = gkb.gkb_partial_svd(A16d, 50, 120, 1e-6, 20, q1=qd, check_every=10)
-    sig, Ut, Vt, status, stats = gkb.gkb_partial_svd(A16d, 50, 120, 1e-6, 20, q1=qd, check_every=10, refine=A32d)
+    sig_u, _, _, st_u, stats_u = gkb.gkb_partial_svd(A16d, 50, 120, 1e-6, 20, q1=qd, check_every=10,
+                                                     one_pass=one_pass)
+    sig, Ut, Vt, status, stats = gkb.gkb_partial_svd(A16d, 50, 120, 1e-6, 20, q1=qd, check_every=10, refine=A32d,
+                                                     one_pass=one_pass)
     torch.cuda.synchronize()
     del A32d, A16d
     want = np.array(ref["sigma"])
