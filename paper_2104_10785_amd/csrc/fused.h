@@ -27,11 +27,13 @@ int fused_blocks(int64_t m, int64_t n);
 // partials of y = A^T win (p, w unused).  All sums in float64; ypart holds
 // fused_blocks(m, n) x ldy doubles (ldy >= n); y (n doubles) gets their sum in
 // a fixed order unless y is null.  Skipped when flag[0] != 0, or when run_if
-// is given and run_if[0] == 0.
+// is given and run_if[0] == 0.  With qprev given, w = A p - coef[0] qprev
+// (the recurrence term of eq. (2.2)) while y stays A^T (A p).
 template <typename TP>
 hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, int64_t n, const TP* p,
                              const double* win, double* w, double* y, double* ypart, int64_t ldy, const int* flag,
-                             hipStream_t st, const int* run_if = nullptr);
+                             hipStream_t st, const int* run_if = nullptr, const double* qprev = nullptr,
+                             const double* coef = nullptr);
 
 // The recovery of A^T q_tq after w = A p - Q[:, 0..t) c_tot has been
 // normalised to beta q_tq, with c_tot[j] = c[j] plus xc[j - x0] for

@@ -65,7 +65,9 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const TA* __restrict__ A, int6
                                                   const TP* __restrict__ p, const double* __restrict__ win,
                                                   int64_t rows_per_block, double* __restrict__ w,
                                                   double* __restrict__ ypart, int64_t ldy,
-                                                  const int* __restrict__ flag, const int* __restrict__ run_if) {
+                                                  const int* __restrict__ flag, const int* __restrict__ run_if,
+                                                  const double* __restrict__ qprev,
+                                                  const double* __restrict__ coef) {
   constexpr int NWV = T / 64;
   constexpr int VN = Elems<TA>::VN;
   if (flag != nullptr && flag[0] != 0) return;
@@ -173,7 +175,8 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const TA* __restrict__ A, int6
 #pragma unroll
         for (int k = 0; k < NWV; ++k) t += red[par][r][k];
         wi[r] = t;   // rows past r1 were loaded as zeros: their wi is 0
-        if (tid == 0 && i + r < r1) w[i + r] = t;
+        // w gets the recurrence term subtracted (eq. (2.2)); A^T w below uses the plain product
+        if (tid == 0 && i + r < r1) w[i + r] = qprev != nullptr ? t - coef[0] * qprev[i + r] : t;
       }
       par ^= 1;   // the next step writes the other half of red: one barrier per step
       // an empty register constraint: the update below converts the rows anew
@@ -258,7 +261,8 @@ __global__ __launch_bounds__(256) void k_fused_reduce(const double* __restrict__
 
 template <int T, int U, int R, int D, typename TA, typename TP, bool GIVEN_W>
 hipError_t launch_v(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
-                    double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st) {
+                    double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st,
+                    const double* qprev = nullptr, const double* coef = nullptr) {
   static bool set = false;
   if (!GIVEN_W && !set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>),
@@ -269,16 +273,17 @@ hipError_t launch_v(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p,
   const int nb = fused_blocks(m, n);
   const int64_t rpb = (m + nb - 1) / nb;
   hipLaunchKernelGGL((k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>), dim3(nb), dim3(T), GIVEN_W ? 0 : (size_t)n * 4, st, A,
-                     lda, m, n, p, win, rpb, w, ypart, ldy, flag, run_if);
+                     lda, m, n, p, win, rpb, w, ypart, ldy, flag, run_if, qprev, coef);
   return hipGetLastError();
 }
 
 template <int T, int U, int R, int D, typename TA, typename TP>
 hipError_t launch_u(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
-                    double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st) {
+                    double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st,
+                    const double* qprev, const double* coef) {
   if (win != nullptr)
     return launch_v<T, U, R, D, TA, TP, true>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
-  return launch_v<T, U, R, D, TA, TP, false>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+  return launch_v<T, U, R, D, TA, TP, false>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st, qprev, coef);
 }
 
 // Launch shape by row length (measured on MI355X): short rows take several
@@ -405,7 +410,7 @@ int fused_blocks(int64_t m, int64_t n) {
 template <typename TP>
 hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, int64_t n, const TP* p,
                              const double* win, double* w, double* y, double* ypart, int64_t ldy, const int* flag,
-                             hipStream_t st, const int* run_if) {
+                             hipStream_t st, const int* run_if, const double* qprev, const double* coef) {
   const FusedShape fs = fused_shape(n);
   hipError_t e;
   if (dtype == 2) {
@@ -415,7 +420,7 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
     // 1024 threads x 1 row)
     const bf16* Ab = reinterpret_cast<const bf16*>(A);
 #define GKB_FUSED(T, U, R, D) \
-  e = launch_u<T, U, R, D, bf16, TP>(Ab, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st)
+  e = launch_u<T, U, R, D, bf16, TP>(Ab, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st, qprev, coef)
     if (n <= 1024) GKB_FUSED(128, 1, 16, 1);
     else if (n <= 2048) GKB_FUSED(256, 1, 8, 1);
     else if (n <= 4096) GKB_FUSED(256, 2, 4, 1);
@@ -427,7 +432,7 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
   } else {
     const float* Af = reinterpret_cast<const float*>(A);
 #define GKB_FUSED(T, U, R, D) \
-  e = launch_u<T, U, R, D, float, TP>(Af, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st)
+  e = launch_u<T, U, R, D, float, TP>(Af, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st, qprev, coef)
     if (fs.T == 128) GKB_FUSED(128, 1, 16, 1);
     else if (fs.T == 256 && fs.U == 1) GKB_FUSED(256, 1, 8, 1);
     else if (fs.T == 256 && fs.U == 2) GKB_FUSED(256, 2, 4, 1);
@@ -436,6 +441,8 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
     else if (fs.T == 768) GKB_FUSED(768, 8, 1, 1);
     else if (fs.U <= 3) GKB_FUSED(1024, 3, 1, 2);
     else if (fs.U == 4) GKB_FUSED(1024, 4, 1, 2);
+    else if (win != nullptr) e = launch_v<512, 10, 1, 1, float, TP, true>(Af, lda, m, n, p, win, w, ypart, ldy, flag,
+                                                                          run_if, st);   // fewer waves to skip
     else GKB_FUSED(1024, 5, 1, 1);
 #undef GKB_FUSED
   }
@@ -447,10 +454,10 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
 
 template hipError_t launch_gemv_fused<float>(const void*, int, int64_t, int64_t, int64_t, const float*, const double*,
                                              double*, double*, double*, int64_t, const int*, hipStream_t,
-                                             const int*);
+                                             const int*, const double*, const double*);
 template hipError_t launch_gemv_fused<double>(const void*, int, int64_t, int64_t, int64_t, const double*,
                                               const double*, double*, double*, double*, int64_t, const int*,
-                                              hipStream_t, const int*);
+                                              hipStream_t, const int*, const double*, const double*);
 
 hipError_t launch_onepass_recover(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int t,
                                   const double* c, const double* xc, int x0, int nx, const double* beta, int tq,

@@ -305,12 +305,11 @@ struct Solver {
   gkb_status onepass_step(int pi, int qp, int nqc, int qn, bool use_rho) {
     if constexpr (std::is_same<TB, double>::value) {
       const int nb = gkb::fused_blocks(A.m, A.n);
-      GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, Pc(pi), nullptr, w(), nullptr, ypart(), L.ldn,
-                                             flag(), st));
-      if (use_rho)
-        GKB_HIP(gkb::launch_update<TB>(Q(cur), L.ldm, nqc, A.m, w(), rho(), nullptr, flag(), st));
-      else
-        GKB_HIP(gkb::launch_update<TB>(Qc(qp), L.ldm, 1, A.m, w(), pcoef() + pi, nullptr, flag(), st));
+      // w = A p - alpha q_qp in the sweep itself (after a restart, Q~ rho by an update)
+      GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, Pc(pi), nullptr, w(), nullptr, ypart(),
+                                             L.ldn, flag(), st, nullptr, use_rho ? nullptr : Qc(qp),
+                                             use_rho ? nullptr : pcoef() + pi));
+      if (use_rho) GKB_HIP(gkb::launch_update<TB>(Q(cur), L.ldm, nqc, A.m, w(), rho(), nullptr, flag(), st));
       GKB_HIP(cgs2(Q(cur), L.ldm, nqc, A.m, w(), csum()));
       GKB_HIP(normalize(w(), A.m, Qc(qn), qcoef() + qn, 1, 1, qn, true));
       GKB_HIP(gkb::launch_onepass_recover(ypart(), nb, L.ldn, GQ(cur), L.ldn, nqc, csum(),
