@@ -127,4 +127,80 @@ def first_cycle(A: np.ndarray, q: np.ndarray, k: int, eps: gk.BreakThreshold, pa
         alphas.append(alpha)
         P[:, t + 1] = z / alpha
     return (gk.Factorization(P[:, :k], Q[:, : k + 1], bidiag(k + 1, k), alphas[k], P[:, k].copy(), None, matvecs,
-                             {"refreshed": refreshed}), G)
+                             {"refreshed": refreshed, "err": err}), G)
+
+
+def restart_cycle(A: np.ndarray, fac: gk.Factorization, G: np.ndarray, err: np.ndarray, X: np.ndarray,
+                  s: np.ndarray, Y: np.ndarray, l: int, k: int, eps: gk.BreakThreshold, passes: int = 2,
+                  tau: float | None = TAU):
+    """`gk.restart_cycle` with one product sweep per step.
+
+    G holds A^T Q of the previous factorisation (its nq columns) and err their
+    error bounds. The kept columns are Q~ = Q X_l, so A^T Q~ = G X_l, each with
+    the bound sqrt(nq) max(err) (the X columns are orthonormal). The first new
+    step subtracts Q~ rho, so c = rho + h on the kept columns; later steps
+    subtract alpha_j q_{j-1} as in the first cycle. Returns (Factorization, G, err).
+    """
+    m, n = A.shape
+    eps0 = 2.0 ** -52 * np.sqrt(m + n)
+    nq, np_ = fac.H.shape
+    Pn = np.zeros((n, k + 1))
+    Qn = np.zeros((m, k + 1))
+    Gn = np.zeros((n, k + 1))
+    en = np.zeros(k + 1)
+    Pn[:, :l] = fac.P[:, :np_] @ Y[:, :l]
+    Qn[:, :l] = fac.Q[:, :nq] @ X[:, :l]
+    Gn[:, :l] = G[:, :nq] @ X[:, :l]
+    en[:l] = np.sqrt(nq) * np.max(err[:nq])
+    Pn[:, l] = fac.p_res
+    rho = fac.alpha_res * X[nq - 1, :l]
+    H = np.zeros((k, k))
+    H[:l, :l] = np.diag(s[:l])
+    H[:l, l] = rho
+    seen = eps.scale
+    matvecs = 0
+    refreshed: list[int] = []
+    alpha_prev = 0.0
+    for j in range(l, k):
+        w = A @ Pn[:, j]
+        y = A.T @ w
+        matvecs += 2
+        c = np.zeros(j)
+        if j == l:
+            w = w - Qn[:, :l] @ rho
+            c[:l] = rho
+        else:
+            w = w - alpha_prev * Qn[:, j - 1]
+            c[j - 1] = alpha_prev
+        for _ in range(passes):
+            h = Qn[:, :j].T @ w
+            w = w - Qn[:, :j] @ h
+            c += h
+        beta = gk.vnorm(w)
+        if beta <= eps():
+            return (gk.Factorization(Pn[:, : j + 1], Qn[:, :j], H[:j, : j + 1].copy(), 0.0, None, "beta",
+                                     fac.matvecs + matvecs - 1, {"refreshed": refreshed}), Gn[:, :j], en[:j])
+        eps.seen(beta)
+        seen = max(seen, beta)
+        Qn[:, j] = w / beta
+        H[j, j] = beta
+        Gn[:, j] = recover(y, Gn[:, :j], c, beta)
+        en[j] = error_bound(c, en[:j], beta, seen, eps0)
+        if tau is not None and en[j] > tau * seen:
+            Gn[:, j] = A.T @ Qn[:, j]
+            matvecs += 1
+            en[j] = eps0 * seen
+            refreshed.append(j)
+        z = gk.reorthogonalize(Pn[:, : j + 1], Gn[:, j] - beta * Pn[:, j], passes)
+        alpha = gk.vnorm(z)
+        if alpha <= eps():
+            return (gk.Factorization(Pn[:, : j + 1], Qn[:, : j + 1], H[: j + 1, : j + 1].copy(), 0.0, None, "alpha",
+                                     fac.matvecs + matvecs, {"refreshed": refreshed}), Gn[:, : j + 1], en[: j + 1])
+        eps.seen(alpha)
+        seen = max(seen, alpha)
+        Pn[:, j + 1] = z / alpha
+        if j + 1 < k:
+            H[j, j + 1] = alpha
+        alpha_prev = alpha
+    return (gk.Factorization(Pn[:, :k], Qn[:, :k], H, alpha_prev, Pn[:, k].copy(), None, fac.matvecs + matvecs,
+                             {"refreshed": refreshed}), Gn[:, :k], en[:k])

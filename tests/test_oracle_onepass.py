@@ -125,3 +125,30 @@ def test_error_bound_dominates_the_actual_error():
             alpha, beta = fac.H[t, t], fac.H[t + 1, t]
             e = (alpha * e + eps0 * (seen * seen + seen * alpha)) / beta
             assert actual[t + 1] <= 10 * e
+
+
+@pytest.mark.parametrize("decay,seed", [(0.9, 500), (0.99, 160)])
+def test_restart_cycle_matches_two_products(decay, seed):
+    """A thick restart on the one-sweep factorisation: the restarted cycle
+    equals `gk.restart_cycle` on the two-product factorisation, and the stored
+    columns are still A^T Q (A^T Q~ = (A^T Q) X_l for the kept ones)."""
+    A, _ = _matrix(160, 120, decay, seed=seed)
+    q = np.random.default_rng(seed + 1).standard_normal(160)
+    k, l = 24, 10
+    e1 = gk.BreakThreshold(1e-12, True)
+    e2 = gk.BreakThreshold(1e-12, True)
+    f1 = gk.first_cycle(A, q, k, e1)
+    f2, G = onepass.first_cycle(A, q, k, e2)
+    X1, s1, Y1 = gk.ritz(f1.H)
+    X2, s2, Y2 = gk.ritz(f2.H)
+    e1.seen(s1[0])
+    e2.seen(s2[0])
+    r1 = gk.restart_cycle(A, f1, X1, s1, Y1, l, k, e1)
+    r2, G2, err2 = onepass.restart_cycle(A, f2, G, f2.coeffs["err"], X2, s2, Y2, l, k, e2)
+    assert r1.breakdown is None and r2.breakdown is None
+    assert r2.matvecs == r1.matvecs + len(f2.coeffs["refreshed"]) + len(r2.coeffs["refreshed"])
+    assert np.max(np.abs(r1.H - r2.H)) < 1e-10
+    assert np.max(np.abs(gk.ritz(r1.H)[1][:l] - gk.ritz(r2.H)[1][:l])) < 1e-12
+    assert np.max(np.abs(G2 - A.T @ r2.Q)) < onepass.TAU
+    assert np.all(np.linalg.norm(G2 - A.T @ r2.Q, axis=0) <= 10 * err2 + 1e-300)
+    assert checks.relation_error(A, r2.P, r2.Q, r2.H) < 1e-12
