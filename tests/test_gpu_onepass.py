@@ -101,6 +101,24 @@ def test_onepass_shapes(shape, r, k, check_every):
     _check_against(ref, sigma, U, V, k, align=1 - 1e-4)
 
 
+@pytest.mark.parametrize("check_every", [0, 3])
+def test_onepass_many_restarts(check_every):
+    """Thick restarts carry A^T Q~ = (A^T Q) X_l and the error bounds of the kept
+    columns; a slowly converging spectrum forces many of them."""
+    device()
+    banner(f"one-pass 300x100 r=8 k=12 many restarts, check_every={check_every}")
+    s = np.concatenate([np.geomspace(1.0, 0.5, 8), np.geomspace(0.45, 0.01, 92)])
+    A, Q1, Q2 = inputs.svd_matrix(300, 100, s, seed=21)
+    A32 = A.astype(np.float32)
+    q = inputs.start_vector(300, seed=22)
+    ref = gk.partial_svd(A32.astype(np.float64), 8, 12, 1e-8, 200, q, eps_break=1e-6, check_every=check_every)
+    sigma, U, V, status, stats = run(A32, 8, 12, 1e-8, 200, q, one_pass=True, check_every=check_every)
+    print("stats", stats, "oracle restarts", ref["restarts"], flush=True)
+    assert status == ref["status"] == 0
+    assert ref["restarts"] >= 8 and abs(stats["restarts"] - ref["restarts"]) <= 1
+    _check_against(ref, sigma, U, V, 12)
+
+
 def test_onepass_rank_deficient():
     device()
     banner("one-pass exact rank 6")
