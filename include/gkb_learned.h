@@ -11,7 +11,7 @@
  *   z_i = w2 . relu(W1 x_i + b1) + b2,   q = z (normalised by the solver).
  * Training minimises L = 1 - ||U_t^T z||^2 / ||z||^2, the energy of the start
  * vector outside the target left subspace U_t, on pairs produced by the solver
- * itself; the convergence test remains the judge and a random start is the
+ * itself; the convergence test still decides when a solve is done, and a random start is the
  * fallback (the caller re-solves with q ~ N(2,1) if the learned start fails).
  *
  * Layouts (device, float32 unless stated):
