@@ -263,12 +263,12 @@ template <int T, int U, int R, int D, typename TA, typename TP, bool GIVEN_W>
 hipError_t launch_v(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
                     double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st,
                     const double* qprev = nullptr, const double* coef = nullptr) {
-  static bool set = false;
-  if (!GIVEN_W && !set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)(FUSED_NMAX * 4));
-    if (e != hipSuccess) return e;
-    set = true;
+  if constexpr (!GIVEN_W) {
+    // once per process (initialisation of a function-local static is thread-safe)
+    static const hipError_t attr =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)(FUSED_NMAX * 4));
+    if (attr != hipSuccess) return attr;
   }
   const int nb = fused_blocks(m, n);
   const int64_t rpb = (m + nb - 1) / nb;

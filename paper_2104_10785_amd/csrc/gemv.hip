@@ -214,14 +214,14 @@ hipError_t launch_gemv_n_t(const TA* A, int64_t lda, int64_t m, int64_t n, const
 }
 
 int device_cus() {
-  static int cached = 0;
-  if (cached > 0) return cached;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-    cached = cus;
-  else
+  // queried once per process (thread-safe initialisation); 256 if the query fails
+  static const int cached = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      return cus;
     return 256;
+  }();
   return cached;
 }
 

@@ -153,6 +153,24 @@ def test_onepass_rank_exact_products(l):
     assert np.max(np.abs(sig[:top] - sig2[:top])) <= 8 * np.sqrt(l + 1) * U32 * sig2[0]
 
 
+def test_onepass_zero_and_nan():
+    """Degenerate inputs: A = 0 (A^T q_1 = 0 at the start: nothing to return)
+    and a NaN entry (numeric error), as in the two-sweep path."""
+    device()
+    banner("one-pass zero matrix and NaN entry")
+    Z = np.zeros((48, 40), dtype=np.float32)
+    sigma, U, V, status, stats = run(Z, 2, 4, 1e-6, 1, inputs.start_vector(48, seed=1), one_pass=True)
+    assert status == 2 and stats["returned"] == 0 and np.all(sigma == 0)
+    rank, rank_s, sig, st, _ = gkb.gkb_numerical_rank(to_dev(Z), 1e-6, q1=to_dev(inputs.start_vector(48, 1)),
+                                                      one_pass=True)
+    assert rank == 0
+    A = np.ones((64, 32), dtype=np.float32)
+    A[3, 5] = np.nan
+    with pytest.raises(gkb.GkbError) as ei:
+        run(A, 2, 4, 1e-6, 0, np.ones(64), one_pass=True)
+    assert ei.value.status == -3
+
+
 def test_onepass_deterministic():
     device()
     banner("one-pass determinism")
