@@ -51,6 +51,7 @@ typedef enum {
                              /* the rest are the best Ritz approximations     */
   GKB_RANK_DEFICIENT = 2,    /* A has fewer than r singular values above the  */
                              /* breakdown threshold; only those are returned  */
+                             /* (later sigma entries and U, V columns are 0)  */
   GKB_ERR_INVALID = -1,      /* bad argument (see gkb_last_error)             */
   GKB_ERR_HIP = -2,          /* a HIP runtime call failed                     */
   GKB_ERR_NUMERIC = -3,      /* NaN or Inf appeared in a norm                 */

@@ -663,6 +663,11 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   // ---- Ritz vectors: V = P Y_r, U = Q X_r
   const int r_eff = ct.r_eff;
   for (int i = 0; i < r; ++i) sigma[i] = i < r_eff ? rz.s[i] : 0.0;
+  if (r_eff < r) {  // columns past the returned triplets are zero
+    GKB_HIP(hipMemsetAsync(U + (size_t)r_eff * Am->m, 0, (size_t)(r - r_eff) * Am->m * sizeof(TO), st));
+    GKB_HIP(hipMemsetAsync(V + (size_t)r_eff * Am->n, 0, (size_t)(r - r_eff) * Am->n * sizeof(TO), st));
+    if (r_eff == 0) GKB_HIP(hipStreamSynchronize(st));
+  }
   int refined = 0;
   double ms_refine = 0.0;
   if constexpr (std::is_same<TO, float>::value) {

@@ -131,6 +131,7 @@ def test_onepass_rank_deficient():
     assert status == 2 and stats["returned"] == 6
     assert np.max(np.abs(sigma[:6] - ref["sigma"])) <= 8 * np.sqrt(20) * U32 * ref["sigma"][0]
     assert np.all(sigma[6:] == 0.0)
+    assert np.all(U[:, 6:] == 0.0) and np.all(V[:, 6:] == 0.0)
 
 
 @pytest.mark.parametrize("l", [1, 5, 37, 100])
