@@ -386,7 +386,7 @@ def learned_leg(dev):
     evaluate on 101-200 against the random and the heuristic start)."""
     from paper_2104_10785_amd import learned
     out = learned.run(m=20000, n=5000, r=30, k=70, tol=1e-8, t_train=100, t_eval=100, ws=32, hidden=256,
-                      epochs=20, lr=1e-3, check_every=2, seed=3, device=dev, log=log)
+                      epochs=20, lr=1e-3, check_every=2, seed=3, device=dev, log=log, init="heuristic")
     out.pop("per_t", None)
     return out
 

@@ -1,14 +1,15 @@
-// w = A p and y = A^T w in one sweep of A (float32 storage, float64 sums).
+// w = A p and y = A^T w in one sweep of A (float32 or bfloat16 storage,
+// float64 sums), and the small kernels of the one-sweep Golub-Kahan step.
 //
 // A Golub-Kahan step needs A p_t and then A^T q_{t+1}; since q_{t+1} is
 // A p_t minus multiples of earlier q's (eq. (2.2) and the Gram-Schmidt
 // passes), A^T q_{t+1} follows from A^T A p_t and the stored A^T q_j of those
-// earlier vectors.  This kernel streams each row of A once: a workgroup owns a
-// contiguous range of rows, keeps p in LDS, and for each row forms
-// the dot product (float64, reduced across the workgroup in a fixed order)
-// and adds a_i * w_i into its float64 partial of A^T w held in registers,
-// while the next row is already loading.  The partials of
-// all workgroups are added in workgroup order by a second kernel.
+// earlier vectors.  The sweep streams each row of A once: a workgroup owns a
+// contiguous range of rows, keeps p in LDS, and for each row forms the dot
+// product (reduced across the workgroup in a fixed order) and adds a_i * w_i
+// into its float64 partial of A^T w held in registers, while the next rows
+// are already loading.  The partials of all workgroups are added in
+// workgroup order by the consumer (the reduction, recovery or fix-up kernel).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,11 +34,10 @@ __device__ __forceinline__ double wsum(double v) {
 
 // T threads; U = 16-byte column groups per thread (thread t owns groups
 // t, t + T, ...); R rows per step, the next D groups of R rows already
-// loading.  The
-// float64 partial of A^T w (4 U doubles per thread) stays in registers; the
-// rows are converted to float64 once for the dot products and again for the
-// update after the barrier, so that only their float32 form stays live across
-// it (fewer registers, more waves per CU).
+// loading.  The float64 partial of A^T w (VN U doubles per thread) stays in
+// registers; the rows are converted to float64 once for the dot products and
+// again for the update after the barrier, so that only their 16-byte form
+// stays live across it (fewer registers, more waves per CU).
 // GIVEN_W: w is an input (y = A^T win) and no row needs a reduction.
 // TA: float (4 per 16-byte group) or bfloat16 (8 per group, widened exactly
 // to float32).

@@ -48,9 +48,26 @@ class DriftSequence:
         return self.A
 
 
+def _embedded_heuristic_init(ws: int, r: int, n_in: int, hidden: int, seed: int, scale: float):
+    """Initial parameters whose output equals the heuristic start: its 2r hidden
+    units in the first rows (output weights +1 / -1), the other units drawn as
+    in `inputs.mlp_init` times `scale` with zero output weights, so training
+    starts from the heuristic and can only add to it what lowers the loss."""
+    hp, hh = _heuristic_params(ws, r, n_in)
+    base = inputs.mlp_init(n_in, hidden, seed)
+    W1 = base[: hidden * n_in].reshape(hidden, n_in) * scale
+    W1[:hh] = hp[: hh * n_in].reshape(hh, n_in)
+    b1 = np.zeros(hidden, np.float32)
+    w2 = np.zeros(hidden, np.float32)
+    w2[:hh] = hp[hh * n_in + hh: hh * n_in + 2 * hh]
+    return np.concatenate([W1.ravel(), b1, w2, [0.0]]).astype(np.float32)
+
+
 def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t_train=100, t_eval=100,
         ws=32, hidden=256, epochs=20, lr=1e-3, check_every=2, max_restarts=50, seed=3, device="cuda:0",
-        log=None):
+        log=None, init="random"):
+    """init: "random" (He initialisation) or "heuristic" (the heuristic start
+    embedded in the network, see `_embedded_heuristic_init`)."""
     import torch
     say = log or (lambda msg: None)
     t0 = time.time()
@@ -81,7 +98,10 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     say(f"training data: {t_train} solves, mean matvecs {np.mean(train_mv):.1f}, {time.time() - t0:.1f} s")
 
     # ---- training on the device
-    params = torch.from_numpy(inputs.mlp_init(n_in, hidden, seed + 2)).to(device)
+    if init == "heuristic":
+        params = torch.from_numpy(_embedded_heuristic_init(ws, r, n_in, hidden, seed + 2, 0.1)).to(device)
+    else:
+        params = torch.from_numpy(inputs.mlp_init(n_in, hidden, seed + 2)).to(device)
     m1 = torch.zeros_like(params)
     m2 = torch.zeros_like(params)
     grad = torch.empty_like(params)
@@ -142,7 +162,7 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     mv_h = np.array([x["heuristic"] for x in rows], dtype=float)
     out = {
         "m": m, "n": n, "r": r, "k": k, "tol": tol, "t_train": t_train, "t_eval": t_eval, "hidden": hidden,
-        "sketch_width": ws, "epochs": epochs, "check_every": check_every,
+        "sketch_width": ws, "epochs": epochs, "check_every": check_every, "init": init,
         "train_loss_by_epoch": losses, "train_seconds": train_s,
         "matvecs_random": {"mean": mv_r.mean(), "median": float(np.median(mv_r))},
         "matvecs_learned": {"mean": mv_l.mean(), "median": float(np.median(mv_l))},
