@@ -50,6 +50,17 @@ gkb_status gkb_mlp_forward(const float* params, int in, int hidden, const float*
 gkb_status gkb_mlp_loss_grad(const float* params, int in, int hidden, const float* X, int64_t m, const float* Ut,
                              int r, float* grad, double* loss, void* workspace, size_t ws_bytes, void* stream);
 
+/* The same with a choice of loss (kind 0 is the one above).  kind 1: the mean
+   over the target vectors u_j of log tan^2 of the angle between z and u_j,
+   L = (1/r) sum_j log(((1 + d) ||z||^2 - (u_j.z)^2) / ((u_j.z)^2 + d ||z||^2)),
+   d = 1e-6: it rewards a start with a sizeable component along every target
+   vector, which is what the convergence of the Krylov subspace to each of
+   them depends on, rather than the energy inside the subspace as a whole.
+   Same arguments and workspace; GKB_ERR_INVALID for another kind. */
+gkb_status gkb_mlp_loss_grad_kind(const float* params, int in, int hidden, const float* X, int64_t m,
+                                  const float* Ut, int r, int kind, float* grad, double* loss, void* workspace,
+                                  size_t ws_bytes, void* stream);
+
 /* Adam (Kingma and Ba 2015) with bias correction for step >= 1. */
 gkb_status gkb_adam_step(float* params, const float* grad, float* m1, float* m2, int64_t count, double lr,
                          double beta1, double beta2, double eps, int step, void* stream);

@@ -44,20 +44,38 @@ def forward(params, n_in, hidden, X):
     return H @ w2 + b2, H, A
 
 
-def loss(params, n_in, hidden, X, U):
+LOGTAN_DELTA = 1e-6
+
+
+def loss(params, n_in, hidden, X, U, kind=0):
+    """kind 0: energy of z outside span(U), 1 - ||U^T z||^2 / ||z||^2.
+    kind 1: mean over the columns u_j of U of log tan^2(angle(z, u_j)),
+    regularised: log(((1 + d) ||z||^2 - (u_j.z)^2) / ((u_j.z)^2 + d ||z||^2))."""
     z, _, _ = forward(params, n_in, hidden, X)
     c = U.T @ z
-    return 1.0 - float(c @ c) / float(z @ z)
+    zz = float(z @ z)
+    if kind == 0:
+        return 1.0 - float(c @ c) / zz
+    d = LOGTAN_DELTA
+    return float(np.mean(np.log(((1.0 + d) * zz - c * c) / (c * c + d * zz))))
 
 
-def grad(params, n_in, hidden, X, U):
-    """Analytic gradient of `loss` (chain rule through the normalised energy)."""
+def grad(params, n_in, hidden, X, U, kind=0):
+    """Analytic gradient of `loss` (chain rule through the loss in terms of z)."""
     W1, b1, w2, b2 = unpack(params, n_in, hidden)
     z, H, A = forward(params, n_in, hidden, X)
     c = U.T @ z
     zz = float(z @ z)
-    cc = float(c @ c)
-    dz = (2.0 / zz) * (-(U @ c) + (cc / zz) * z)
+    if kind == 0:
+        cc = float(c @ c)
+        dz = (2.0 / zz) * (-(U @ c) + (cc / zz) * z)
+    else:
+        d = LOGTAN_DELTA
+        r = U.shape[1]
+        a = (1.0 + d) * zz - c * c
+        b = c * c + d * zz
+        # d log a_j / dz = (2 (1 + d) z - 2 c_j u_j) / a_j ; d log b_j / dz = (2 c_j u_j + 2 d z) / b_j
+        dz = (np.sum(2.0 * (1.0 + d) / a - 2.0 * d / b) / r) * z - U @ ((2.0 / r) * c * (1.0 / a + 1.0 / b))
     dW2 = H.T @ dz
     db2 = dz.sum()
     dH = np.outer(dz, w2) * (A > 0)

@@ -158,22 +158,46 @@ __global__ __launch_bounds__(256) void k_loss_stats(const float* __restrict__ Ut
   if (threadIdx.x == 0) stats[j] = t;
 }
 
-// dz_i = (2 / zz) (-(U_t c)_i + (cc / zz) z_i); DH[i + k m] = dz_i w2[k] [a_k > 0];
-// block 0 writes loss = 1 - cc / zz.
+// Loss kind 0 (energy outside the target subspace): L = 1 - cc / zz with
+// c = U_t^T z, cc = c.c, zz = z.z; dz_i = (2 / zz) (-(U_t c)_i + (cc / zz) z_i).
+// Loss kind 1 (mean log tan^2 of the angles between z and each target vector,
+// regularised by delta): a_j = (1 + delta) zz - c_j^2, b_j = c_j^2 + delta zz,
+// L = (1/r) sum_j log(a_j / b_j); dz_i = s1 z_i - sum_j U_t[i, j] v_j with
+// s1 = (1/r) sum_j (2 (1 + delta) / a_j - 2 delta / b_j),
+// v_j = (2/r) c_j (1 / a_j + 1 / b_j).
+// DH[i + k m] = dz_i w2[k] [a_k > 0]; block 0 writes the loss.
+constexpr double LOGTAN_DELTA = 1e-6;
+
 __global__ __launch_bounds__(256) void k_mlp_bwd_rows(const float* __restrict__ prm, int in, int hidden,
                                                       const float* __restrict__ X, int64_t m,
                                                       const float* __restrict__ z, const float* __restrict__ Ut, int r,
                                                       const double* __restrict__ stats, float* __restrict__ dz,
-                                                      float* __restrict__ DH, double* __restrict__ loss) {
+                                                      float* __restrict__ DH, double* __restrict__ loss, int kind) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double cc = 0.0;
-  for (int j = 0; j < r; ++j) cc += stats[j] * stats[j];
   const double zz = stats[r];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *loss = zz > 0 ? 1.0 - cc / zz : 1.0;
-  if (i >= m) return;
-  double pz = 0.0;
-  for (int j = 0; j < r; ++j) pz += (double)Ut[(int64_t)j * m + i] * stats[j];
-  const double g = zz > 0 ? (2.0 / zz) * (-pz + (cc / zz) * (double)z[i]) : 0.0;
+  double g = 0.0;
+  if (kind == 0) {
+    double cc = 0.0;
+    for (int j = 0; j < r; ++j) cc += stats[j] * stats[j];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *loss = zz > 0 ? 1.0 - cc / zz : 1.0;
+    if (i >= m) return;
+    double pz = 0.0;
+    for (int j = 0; j < r; ++j) pz += (double)Ut[(int64_t)j * m + i] * stats[j];
+    g = zz > 0 ? (2.0 / zz) * (-pz + (cc / zz) * (double)z[i]) : 0.0;
+  } else {
+    const double dl = LOGTAN_DELTA;
+    double lsum = 0.0, s1 = 0.0, pv = 0.0;
+    for (int j = 0; j < r; ++j) {
+      const double c = stats[j];
+      const double a = (1.0 + dl) * zz - c * c, b = c * c + dl * zz;
+      lsum += log(a / b);
+      s1 += 2.0 * (1.0 + dl) / a - 2.0 * dl / b;
+      if (i < m) pv += (double)Ut[(int64_t)j * m + i] * (2.0 / r) * c * (1.0 / a + 1.0 / b);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *loss = zz > 0 ? lsum / r : 0.0;
+    if (i >= m) return;
+    g = zz > 0 ? (s1 / r) * (double)z[i] - pv : 0.0;
+  }
   const float gz = (float)g;
   dz[i] = gz;
   const float* W1 = prm;
@@ -325,9 +349,16 @@ gkb_status gkb_mlp_forward(const float* params, int in, int hidden, const float*
 
 gkb_status gkb_mlp_loss_grad(const float* params, int in, int hidden, const float* X, int64_t m, const float* Ut,
                              int r, float* grad, double* loss, void* workspace, size_t ws_bytes, void* stream) {
+  return gkb_mlp_loss_grad_kind(params, in, hidden, X, m, Ut, r, 0, grad, loss, workspace, ws_bytes, stream);
+}
+
+gkb_status gkb_mlp_loss_grad_kind(const float* params, int in, int hidden, const float* X, int64_t m,
+                                  const float* Ut, int r, int kind, float* grad, double* loss, void* workspace,
+                                  size_t ws_bytes, void* stream) {
   l_err.clear();
   if (!params || !X || !Ut || !grad || !loss || m < 1 || r < 1 || !shapes_ok(in, hidden))
     return lfail(GKB_ERR_INVALID, "bad loss/gradient arguments");
+  if (kind != 0 && kind != 1) return lfail(GKB_ERR_INVALID, "loss kind must be 0 or 1");
   MlpWs w = mlp_ws(m, hidden, r);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) || ws_bytes < w.total)
     return lfail(GKB_ERR_WORKSPACE, "workspace too small or misaligned");
@@ -345,7 +376,7 @@ gkb_status gkb_mlp_loss_grad(const float* params, int in, int hidden, const floa
   hipLaunchKernelGGL(k_loss_stats, dim3(r + 1), dim3(256), 0, st, Ut, r, z, m, stats);
   L_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mlp_bwd_rows, dim3(nblk(m, 256)), dim3(256), 0, st, params, in, hidden, X, m, z, Ut, r, stats,
-                     dz, DH, loss);
+                     dz, DH, loss, kind);
   L_HIP(hipGetLastError());
   // G1 = X^T DH (XLD x hidden), G2 = H^T dz (hld x 1): sums over the rows on MFMA, split over row ranges
   float* Gpart = reinterpret_cast<float*>(b + w.Gpart);

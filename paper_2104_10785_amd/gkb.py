@@ -76,7 +76,7 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_sparse_plan_destroy", "gkb_sparse_matvec", "gkb_sparse_workspace_size", "gkb_partial_svd_sparse",
            "gkb_sparse_last_error", "gkb_rsgd_workspace_size", "gkb_rsgd_plan_create", "gkb_rsgd_plan_step",
            "gkb_rsgd_plan_info", "gkb_rsgd_plan_destroy", "gkb_rsgd_weights", "gkb_rsgd_last_error",
-           "gkb_matvec_fused_workspace_size", "gkb_matvec_fused"]
+           "gkb_matvec_fused_workspace_size", "gkb_matvec_fused", "gkb_mlp_loss_grad_kind"]
 
 
 def lib():
@@ -217,6 +217,9 @@ def lib():
     L.gkb_matvec_fused.argtypes = [P(GkbMatrix), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.c_void_p]
     L.gkb_matvec_fused.restype = C.c_int
+    L.gkb_mlp_loss_grad_kind.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
+                                         C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.gkb_mlp_loss_grad_kind.restype = C.c_int
     _lib = L
     return L
 
@@ -651,8 +654,9 @@ def gkb_mlp_forward(params, n_in, hidden, X, stream=None):
     return z
 
 
-def gkb_mlp_loss_grad(params, n_in, hidden, X, Ut, grad=None, loss=None, workspace=None, stream=None):
-    """(grad, loss) device tensors for the target left vectors Ut (r x m)."""
+def gkb_mlp_loss_grad(params, n_in, hidden, X, Ut, grad=None, loss=None, workspace=None, stream=None, kind=0):
+    """(grad, loss) device tensors for the target left vectors Ut (r x m); kind 0:
+    energy outside the target subspace, kind 1: mean log tan^2 of the angles."""
     torch = _torch()
     m = X.shape[0]
     r = Ut.shape[0]
@@ -662,10 +666,10 @@ def gkb_mlp_loss_grad(params, n_in, hidden, X, Ut, grad=None, loss=None, workspa
         loss = torch.empty(1, dtype=torch.float64, device=X.device)
     if workspace is None:
         workspace = _workspace(lib().gkb_mlp_workspace_size(m, n_in, hidden, r), X.device)
-    _lcheck(lib().gkb_mlp_loss_grad(C.c_void_p(params.data_ptr()), n_in, hidden, C.c_void_p(X.data_ptr()), m,
-                                    C.c_void_p(Ut.data_ptr()), r, C.c_void_p(grad.data_ptr()),
-                                    C.c_void_p(loss.data_ptr()), C.c_void_p(workspace.data_ptr()), workspace.numel(),
-                                    _stream(stream)))
+    _lcheck(lib().gkb_mlp_loss_grad_kind(C.c_void_p(params.data_ptr()), n_in, hidden, C.c_void_p(X.data_ptr()), m,
+                                         C.c_void_p(Ut.data_ptr()), r, int(kind), C.c_void_p(grad.data_ptr()),
+                                         C.c_void_p(loss.data_ptr()), C.c_void_p(workspace.data_ptr()),
+                                         workspace.numel(), _stream(stream)))
     return grad, loss
 
 

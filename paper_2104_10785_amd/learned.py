@@ -65,9 +65,11 @@ def _embedded_heuristic_init(ws: int, r: int, n_in: int, hidden: int, seed: int,
 
 def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t_train=100, t_eval=100,
         ws=32, hidden=256, epochs=20, lr=1e-3, check_every=2, max_restarts=50, seed=3, device="cuda:0",
-        log=None, init="random"):
+        log=None, init="random", loss_kind=0):
     """init: "random" (He initialisation) or "heuristic" (the heuristic start
-    embedded in the network, see `_embedded_heuristic_init`)."""
+    embedded in the network, see `_embedded_heuristic_init`); loss_kind: 0
+    (energy outside the target subspace) or 1 (mean log tan^2 of the angles
+    to the target vectors), see gkb_mlp_loss_grad_kind."""
     import torch
     say = log or (lambda msg: None)
     t0 = time.time()
@@ -115,7 +117,7 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
         ep_loss = []
         for t in rng.permutation(t_train):
             X, Ut = data[t]
-            gkb.gkb_mlp_loss_grad(params, n_in, hidden, X, Ut, grad=grad, loss=loss, workspace=wsp)
+            gkb.gkb_mlp_loss_grad(params, n_in, hidden, X, Ut, grad=grad, loss=loss, workspace=wsp, kind=loss_kind)
             step += 1
             gkb.gkb_adam_step(params, grad, m1, m2, lr, step)
             ep_loss.append(loss.clone())
@@ -162,7 +164,7 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     mv_h = np.array([x["heuristic"] for x in rows], dtype=float)
     out = {
         "m": m, "n": n, "r": r, "k": k, "tol": tol, "t_train": t_train, "t_eval": t_eval, "hidden": hidden,
-        "sketch_width": ws, "epochs": epochs, "check_every": check_every, "init": init,
+        "sketch_width": ws, "epochs": epochs, "check_every": check_every, "init": init, "loss_kind": loss_kind,
         "train_loss_by_epoch": losses, "train_seconds": train_s,
         "matvecs_random": {"mean": mv_r.mean(), "median": float(np.median(mv_r))},
         "matvecs_learned": {"mean": mv_l.mean(), "median": float(np.median(mv_l))},

@@ -63,6 +63,28 @@ def test_features_forward_loss_grad_adam_vs_oracle(m):
     assert np.max(np.abs(to_host(p) - po)) < 1e-6
 
 
+@pytest.mark.parametrize("m", [1001, 20000])
+def test_logtan_loss_grad_vs_oracle(m):
+    """Loss kind 1 (mean log tan^2 of the angles to the target vectors) and its
+    gradient against the oracle on the same float32 features."""
+    device()
+    banner(f"learned: log-tan loss/grad vs oracle m={m}")
+    S, Up, U, params, n_in, hidden = _setup(m=m)
+    X = gkb.gkb_mlp_features(to_dev(np.ascontiguousarray(S.T)), to_dev(np.ascontiguousarray(Up.T)))
+    Xo32 = to_host(X)[:, : n_in + 1].astype(np.float64)
+    Ud = to_dev(np.ascontiguousarray(U.T))
+    g, L = gkb.gkb_mlp_loss_grad(to_dev(params), n_in, hidden, X, Ud, kind=1)
+    go = mlp.grad(params.astype(np.float64), n_in, hidden, Xo32, U.astype(np.float64), kind=1)
+    Lo = mlp.loss(params.astype(np.float64), n_in, hidden, Xo32, U.astype(np.float64), kind=1)
+    gh = to_host(g)
+    print(f"log-tan loss {to_host(L)[0]:.6f} vs {Lo:.6f}; grad rel err "
+          f"{np.max(np.abs(gh - go)) / np.max(np.abs(go)):.2e}", flush=True)
+    assert abs(to_host(L)[0] - Lo) < 1e-5 * max(1.0, abs(Lo))
+    assert np.max(np.abs(gh - go)) <= 1e-3 * np.max(np.abs(go))
+    with pytest.raises(gkb.GkbError):
+        gkb.gkb_mlp_loss_grad(to_dev(params), n_in, hidden, X, Ud, kind=2)
+
+
 def test_learned_start_beats_random_on_held_out_solves():
     device()
     banner("learned start end to end, 3000x1000, r=8")
