@@ -77,7 +77,32 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const TA* __restrict__ A, int6
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ng = n / VN;                     // 16-byte groups per row
   if constexpr (!GIVEN_W) {
-    for (int64_t j = tid; j < n; j += T) pl[j] = (float)p[j];
+    // each thread stages the p entries of its own column groups (the only
+    // ones it reads back); the loads are independent, so all are in flight
+    // together rather than one round trip per entry
+    constexpr int UC = U < 4 ? U : 4;   // groups per batch of loads (bounds the temporaries)
+#pragma unroll
+    for (int u0 = 0; u0 < (U <= 6 ? U : 0); u0 += UC) {
+      float v[UC][VN];
+#pragma unroll
+      for (int c = 0; c < UC; ++c) {
+        // clamped to an entry in bounds; stored only if the group exists
+        const int64_t g = std::min<int64_t>(tid + (int64_t)(u0 + c) * T, ng - 1);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) v[c][e] = (float)p[VN * g + e];
+      }
+#pragma unroll
+      for (int c = 0; c < UC; ++c) {
+        const int64_t g = tid + (int64_t)(u0 + c) * T;
+        if (u0 + c < U && g < ng)
+#pragma unroll
+          for (int e = 0; e < VN; ++e) pl[VN * g + e] = v[c][e];
+      }
+    }
+    if constexpr (U > 6) {   // the widest shape has no registers to spare: a plain strided copy
+#pragma unroll 8
+      for (int64_t j = tid; j < n; j += T) pl[j] = (float)p[j];
+    }
     __syncthreads();
   }
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
