@@ -164,3 +164,69 @@ def test_oracle_philox_known_answers():
         assert [int(w[0]) for w in words] == v[6:]
     q = philox.start_vector(200000, 3)
     assert abs(q.mean() - 2.0) < 0.01 and abs(q.std() - 1.0) < 0.01
+
+
+def _options(**kw):
+    o = gkb.GkbOptions()
+    gkb.lib().gkb_default_options(C.byref(o))
+    for k2, v in kw.items():
+        setattr(o, k2, v)
+    return o
+
+
+def test_one_pass_validation_and_workspace():
+    """The one-sweep option is checked on the host: float32 needs n and lda
+    multiples of 4, bfloat16 multiples of 8, n <= 24576 and a 16-byte aligned
+    A; float64 is refused.  Its workspace holds float64 bases and A^T Q."""
+    L = gkb.lib()
+    one = _options(one_pass=1)
+    two = _options()
+    sig = (C.c_double * 2)()
+
+    def svd(mat):
+        return L.gkb_partial_svd(C.byref(mat), 2, 4, 1e-6, 0, C.byref(one), None, 0, sig, 0x2000, 0x3000, None,
+                                 None)
+    assert svd(_fake_matrix(n=50)) == -1                            # n % 4
+    assert svd(_fake_matrix(n=52, lda=54)) == -1                    # lda % 4
+    assert svd(_fake_matrix(n=52, data=0x1004)) == -1               # alignment
+    assert svd(_fake_matrix(n=52, dtype=gkb.GKB_F64)) == -1         # float64
+    assert svd(_fake_matrix(n=52, dtype=gkb.GKB_BF16)) == -1        # bfloat16 needs n % 8
+    assert svd(_fake_matrix(m=100, n=24580)) == -1                  # n > 24576
+    assert "one_pass" in gkb.last_error()
+    for bad in (_fake_matrix(n=50), _fake_matrix(n=52, dtype=gkb.GKB_F64), _fake_matrix(n=52, data=0x1004)):
+        assert L.gkb_workspace_size(C.byref(bad), 2, 4, C.byref(one)) == 0
+        assert L.gkb_rank_workspace_size(C.byref(bad), 0, C.byref(one)) == 0
+    good = _fake_matrix(50000, 20000, gkb.GKB_F32)
+    w1 = L.gkb_workspace_size(C.byref(good), 50, 120, C.byref(one))
+    w2 = L.gkb_workspace_size(C.byref(good), 50, 120, C.byref(two))
+    # float64 bases (two copies) + two copies of A^T Q dominate
+    assert w1 > 2 * 121 * (50048 + 20032) * 8 + 2 * 121 * 20032 * 8
+    assert w1 > w2 > 0
+    bf = _fake_matrix(100, 48, gkb.GKB_BF16)
+    assert L.gkb_workspace_size(C.byref(bf), 2, 4, C.byref(one)) > 0
+    # the building block takes the same shapes
+    assert L.gkb_matvec_fused_workspace_size(C.byref(_fake_matrix(n=50))) == 0
+    assert L.gkb_matvec_fused_workspace_size(C.byref(_fake_matrix(n=52))) > 0
+
+
+def test_embedded_heuristic_initialisation_reproduces_the_heuristic():
+    """The network initialised by `_embedded_heuristic_init` computes exactly the
+    heuristic start (its output equals the 2r-unit heuristic network's) for any
+    features, before any training."""
+    from paper_2104_10785_amd import learned
+
+    def forward(params, hidden, X, n_in):
+        W1 = params[: hidden * n_in].reshape(hidden, n_in)
+        b1 = params[hidden * n_in: hidden * n_in + hidden]
+        w2 = params[hidden * n_in + hidden: hidden * n_in + 2 * hidden]
+        return np.maximum(X @ W1.T + b1, 0.0) @ w2 + params[-1]
+    ws, r, hidden = 32, 30, 256
+    n_in = ws + r
+    p = learned._embedded_heuristic_init(ws, r, n_in, hidden, seed=5, scale=0.1).astype(np.float64)
+    hp, hh = learned._heuristic_params(ws, r, n_in)
+    X = np.random.default_rng(0).standard_normal((500, n_in))
+    z = forward(p, hidden, X, n_in)
+    zh = forward(hp.astype(np.float64), hh, X, n_in)
+    assert np.max(np.abs(z - zh)) <= 1e-12 * np.max(np.abs(zh))
+    # the heuristic network is sum_j x_{ws+j}: relu(x) - relu(-x) = x
+    assert np.allclose(zh, X[:, ws:].sum(axis=1))
