@@ -234,6 +234,213 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const TA* __restrict__ A, int6
   }
 }
 
+// LDS writes complete, then the workgroup barrier.  Unlike __syncthreads()
+// this does not order global memory, so the row loads in flight stay in
+// flight across it (every value exchanged at these barriers is in LDS).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Word 3 of a raw buffer resource on gfx9 (32-bit data format, no swizzle).
+constexpr int RSRC_WORD3 = 0x00020000;
+
+// The same sweep, pipelined so that the loads of the next rows overlap the
+// reduction and barrier of the current ones.  The vector memory counter is
+// one in-order counter for loads and stores on this architecture, and the
+// compiler waits for all of it (vmcnt(0)) wherever the number of loads issued
+// after a value is not fixed: a load that some waves skip, a store between
+// loads, two paths into the loop.  So here
+//   - every load is issued: buffer loads whose resource covers exactly the
+//     row's remaining bytes (0 for rows past the range), so groups past the
+//     row end and padding rows read as zeros without touching memory;
+//   - the loop has one path: NB buffers of R rows named statically (the loop
+//     unrolled by NB), the last group of steps padded with zero rows;
+//   - no global store inside the loop: w is staged in LDS and written once at
+//     the end (with the recurrence term of eq. (2.2) subtracted there);
+//   - the per-step barrier orders LDS only (lds_barrier).
+// p is staged zero padded to U T groups, so the dot products need no bounds
+// test.  NB - 1 steps of rows are in flight while one is processed.
+template <int T, int U, int R, int NB, typename TA, typename TP, bool GIVEN_W>
+__global__ __launch_bounds__(T) void k_gemv_fused_pipe(const TA* __restrict__ A, int64_t lda, int m, int64_t n,
+                                                       const TP* __restrict__ p, const double* __restrict__ win,
+                                                       int rows_per_block, double* __restrict__ w,
+                                                       double* __restrict__ ypart, int64_t ldy,
+                                                       const int* __restrict__ flag, const int* __restrict__ run_if,
+                                                       const double* __restrict__ qprev,
+                                                       const double* __restrict__ coef) {
+  static_assert(NB >= 2, "at least one step of rows in flight");
+  constexpr int NWV = T / 64;
+  constexpr int VN = Elems<TA>::VN;
+  if (flag != nullptr && flag[0] != 0) return;
+  if (run_if != nullptr && run_if[0] == 0) return;
+  // p as float32 zero padded to U T groups (not GIVEN_W), then w of the rows
+  extern __shared__ double dyn[];
+  __shared__ double red[2][R][NWV];              // [parity][row][wave]
+  float* pl = reinterpret_cast<float*>(dyn);
+  double* wl = dyn + (GIVEN_W ? 0 : U * T * VN / 2);
+  // the wave index is uniform: scalar, so its LDS addresses take no vector registers
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ng = (int)(n / VN);
+  if constexpr (!GIVEN_W) {
+    // the loads of a batch are independent (in flight together); groups past
+    // the row get zeros
+    constexpr int UC = U < 4 ? U : 4;
+#pragma unroll
+    for (int u0 = 0; u0 < (U <= 6 ? U : 0); u0 += UC) {
+      float v[UC][VN];
+#pragma unroll
+      for (int c = 0; c < UC; ++c) {
+        const int g = std::min(tid + (u0 + c) * T, ng - 1);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) v[c][e] = (float)p[(int64_t)VN * g + e];
+      }
+#pragma unroll
+      for (int c = 0; c < UC; ++c) {
+        const int g = tid + (u0 + c) * T;
+        if (u0 + c < U)
+#pragma unroll
+          for (int e = 0; e < VN; ++e) pl[VN * g + e] = g < ng ? v[c][e] : 0.f;
+      }
+    }
+    if constexpr (U > 6) {
+#pragma unroll 8
+      for (int j = tid; j < U * T * VN; j += T) pl[j] = j < n ? (float)p[j] : 0.f;
+    }
+    __syncthreads();
+  }
+  const int r0 = blockIdx.x * rows_per_block;
+  const int r1 = std::min(m, r0 + rows_per_block);
+  const int nrows = std::max(r1 - r0, 0);
+  const int last = r1 - 1;
+  const int rowbytes = (int)(n * (int64_t)sizeof(TA));
+  const int64_t ldb = lda * (int64_t)sizeof(TA);
+  const char* Ab = reinterpret_cast<const char*>(A);
+  const int off0 = tid * 16;
+  // rows i .. i + R - 1: group u of a row through a resource that starts at
+  // its byte u T 16 and ends at the row's end; only the thread's own offset
+  // (tid 16) is range-checked against it
+  auto load_step = [&](int i, f4 (&dst)[R][U]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool live = i + r <= last;
+      const int ri = __builtin_amdgcn_readfirstlane(std::min(i + r, last));
+      const char* row = Ab + (int64_t)ri * ldb;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int nrec = __builtin_amdgcn_readfirstlane(live ? std::max(rowbytes - u * T * 16, 0) : 0);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)(row + u * T * 16), (short)0, nrec, RSRC_WORD3);
+        // aux 2: nontemporal (A is streamed once)
+        dst[r][u] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, off0, 0, 2));
+      }
+    }
+  };
+  double y[U][VN];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int e = 0; e < VN; ++e) y[u][e] = 0.0;
+  int par = 0;
+  // rows past r1 are zeros: they add nothing, and only their w is not kept
+  auto step = [&](f4 (&rows)[R][U], int i) {
+    double wi[R];
+    if constexpr (GIVEN_W) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) wi[r] = i + r < r1 ? win[i + r] : 0.0;
+    } else {
+      double d[R];
+      if constexpr (Elems<TA>::F32DOT) {
+        float df[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) df[r] = 0.f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int g = tid + u * T;
+#pragma unroll
+          for (int h = 0; h < VN / 4; ++h) {
+            const f4 pv = reinterpret_cast<const f4*>(pl)[(VN / 4) * g + h];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+              for (int r = 0; r < R; ++r) df[r] = fmaf(Elems<TA>::at(rows[r][u], 4 * h + e), pv[e], df[r]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[r] = (double)df[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[r] = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int g = tid + u * T;
+#pragma unroll
+          for (int h = 0; h < VN / 4; ++h) {
+            const f4 pv = reinterpret_cast<const f4*>(pl)[(VN / 4) * g + h];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const double pe = (double)pv[e];
+#pragma unroll
+              for (int r = 0; r < R; ++r) d[r] += (double)Elems<TA>::at(rows[r][u], 4 * h + e) * pe;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        d[r] = wsum(d[r]);
+        if (lane == 0) red[par][r][wave] = d[r];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < NWV; ++k) t += red[par][r][k];
+        wi[r] = t;
+        if (tid == 0 && i + r < r1) wl[i + r - r0] = t;
+      }
+      par ^= 1;   // the next step writes the other half of red: one barrier per step
+      // an empty register constraint: the update below converts the rows anew
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int u = 0; u < U; ++u) asm volatile("" : "+v"(rows[r][u]));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < VN; ++e) y[u][e] += (double)Elems<TA>::at(rows[r][u], e) * wi[r];
+  };
+  f4 B[NB][R][U];
+  if (nrows > 0) {
+#pragma unroll
+    for (int k = 0; k < NB - 1; ++k) load_step(r0 + k * R, B[k]);
+    const int nsteps = (nrows + R - 1) / R;
+    for (int s = 0; s < nsteps; s += NB) {
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        load_step(r0 + (s + k + NB - 1) * R, B[(k + NB - 1) % NB]);
+        step(B[k], r0 + (s + k) * R);
+      }
+    }
+  }
+  if constexpr (!GIVEN_W) {
+    __syncthreads();   // the staged w
+    for (int j = tid; j < nrows; j += T) {
+      const double t = wl[j];
+      w[r0 + j] = qprev != nullptr ? t - coef[0] * qprev[r0 + j] : t;
+    }
+  }
+  double* yp = ypart + (int64_t)blockIdx.x * ldy;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int g = tid + u * T;
+    if (g < ng)
+#pragma unroll
+      for (int e = 0; e < VN; ++e) yp[(int64_t)VN * g + e] = y[u][e];
+  }
+}
+
 // Column sums of the partials with 256 threads per 64 columns: wave v adds
 // the partial rows [v nb / 4, (v + 1) nb / 4) for column j = lane, and wave 0
 // adds the four sums in wave order (a fixed order).  `extra` (may be null)
@@ -332,6 +539,53 @@ FusedShape fused_shape(int64_t n) {
   return {768, 8, 1, 1};
 }
 
+// The pipelined sweep: LDS holds p (padded) and the w of the workgroup's rows.
+constexpr int PIPE_LDS_MAX = 160 * 1024 - 4096;   // dynamic LDS; the rest covers red[][][]
+
+template <int T, int U, int R, int NB, typename TA>
+size_t pipe_lds(int64_t m, int64_t n, bool given_w) {
+  const int nb = fused_blocks(m, n);
+  const int64_t rpb = (m + nb - 1) / nb;
+  return given_w ? 0 : (size_t)U * T * Elems<TA>::VN * 4 + (size_t)rpb * 8;
+}
+
+// true if the pipelined form takes this launch (LDS within one workgroup's
+// share of the CU; the row count in 32 bits)
+template <int T, int U, int R, int NB, typename TA>
+bool pipe_fits(int64_t m, int64_t n, bool given_w) {
+  const int bpc = fused_shape(n).bpc;
+  return m < (int64_t(1) << 30) && n / Elems<TA>::VN <= (int64_t)U * T &&
+         pipe_lds<T, U, R, NB, TA>(m, n, given_w) <= (size_t)std::min(PIPE_LDS_MAX, 160 * 1024 / bpc - 4096);
+}
+
+template <int T, int U, int R, int NB, typename TA, typename TP, bool GIVEN_W>
+hipError_t launch_p(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
+                    double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st,
+                    const double* qprev = nullptr, const double* coef = nullptr) {
+  if (!pipe_fits<T, U, R, NB, TA>(m, n, GIVEN_W)) return hipErrorInvalidValue;
+  if constexpr (!GIVEN_W) {
+    static const hipError_t attr =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused_pipe<T, U, R, NB, TA, TP, GIVEN_W>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, PIPE_LDS_MAX);
+    if (attr != hipSuccess) return attr;
+  }
+  const int nb = fused_blocks(m, n);
+  const int rpb = (int)((m + nb - 1) / nb);
+  const size_t lds = pipe_lds<T, U, R, NB, TA>(m, n, GIVEN_W);
+  hipLaunchKernelGGL((k_gemv_fused_pipe<T, U, R, NB, TA, TP, GIVEN_W>), dim3(nb), dim3(T), lds, st, A, lda, (int)m,
+                     n, p, win, rpb, w, ypart, ldy, flag, run_if, qprev, coef);
+  return hipGetLastError();
+}
+
+template <int T, int U, int R, int NB, typename TA, typename TP>
+hipError_t launch_pu(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
+                     double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st,
+                     const double* qprev, const double* coef) {
+  if (win != nullptr)
+    return launch_p<T, U, R, NB, TA, TP, true>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+  return launch_p<T, U, R, NB, TA, TP, false>(A, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st, qprev, coef);
+}
+
 // Coefficient of column j in w = A p - Q c: the Gram-Schmidt sums c[j] plus
 // the recurrence term xc[j - x0] for x0 <= j < x0 + nx.
 __device__ __forceinline__ double coef_total(const double* __restrict__ c, int j, const double* __restrict__ xc,
@@ -423,8 +677,8 @@ __global__ __launch_bounds__(256) void k_narrow(const double* __restrict__ src, 
 
 bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A, int dtype) {
   const int64_t vn = dtype == 2 ? 8 : 4;
-  return (dtype == 1 || dtype == 2) && m >= 1 && n >= vn && n <= FUSED_NMAX && n % vn == 0 && lda % vn == 0 &&
-         (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  return (dtype == 1 || dtype == 2) && m >= 1 && m < (int64_t(1) << 30) && n >= vn && n <= FUSED_NMAX &&
+         n % vn == 0 && lda % vn == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
 }
 
 int fused_blocks(int64_t m, int64_t n) {
@@ -438,37 +692,60 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
                              hipStream_t st, const int* run_if, const double* qprev, const double* coef) {
   const FusedShape fs = fused_shape(n);
   hipError_t e;
+  const bool gw = win != nullptr;
+  // Shapes measured on MI355X (w = A p and A^T w, float64 p): the pipelined
+  // form where it is faster, the per-row barrier form elsewhere and for the
+  // given-w sweep (w read, no reduction), and wherever the pipelined form's
+  // LDS (p and the staged w of a workgroup's rows) would not fit.
   if (dtype == 2) {
-    // bfloat16: half the bytes per row, so a barrier per row would dominate;
-    // several rows per step, 512 threads with the registers this leaves
-    // (measured: n = 20000, 5 groups x 3 rows 4.7 TB/s against 3.0 TB/s for
-    // 1024 threads x 1 row)
+    // bfloat16: half the bytes per row, so several rows per barrier
     const bf16* Ab = reinterpret_cast<const bf16*>(A);
 #define GKB_FUSED(T, U, R, D) \
   e = launch_u<T, U, R, D, bf16, TP>(Ab, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st, qprev, coef)
-    if (n <= 1024) GKB_FUSED(128, 1, 16, 1);
-    else if (n <= 2048) GKB_FUSED(256, 1, 8, 1);
-    else if (n <= 4096) GKB_FUSED(256, 2, 4, 1);
-    else if (n <= 8192) GKB_FUSED(512, 2, 4, 1);
-    else if (n <= 16384) GKB_FUSED(512, 4, 3, 1);
-    else if (n <= 20480) GKB_FUSED(512, 5, 3, 1);
-    else GKB_FUSED(512, 6, 2, 1);
+#define GKB_PIPE_OR(T, U, R, NB, OT, OU, OR, OD)                                                      \
+  if (!gw && pipe_fits<T, U, R, NB, bf16>(m, n, false))                                               \
+    e = launch_p<T, U, R, NB, bf16, TP, false>(Ab, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st, \
+                                               qprev, coef);                                          \
+  else GKB_FUSED(OT, OU, OR, OD)
+    // (ms, old -> pipelined: n = 1000 2.06 -> 1.64; 2000 1.22 -> 1.01;
+    // 4000 0.99 -> 0.72; 8000 1.01 -> 0.67; 16000 0.83 -> 0.65;
+    // 20000 0.81 -> 0.64; 24576 0.75 -> 0.62, at 2-4 GB of A)
+    if (n <= 1024) { GKB_PIPE_OR(128, 1, 16, 2, 128, 1, 16, 1); }
+    else if (n <= 2048) { GKB_PIPE_OR(256, 1, 8, 2, 256, 1, 8, 1); }
+    else if (n <= 4096) { GKB_PIPE_OR(256, 2, 2, 2, 256, 2, 4, 1); }
+    else if (n <= 8192) { GKB_PIPE_OR(512, 2, 2, 2, 512, 2, 4, 1); }
+    else if (n <= 16384) { GKB_PIPE_OR(512, 4, 2, 2, 512, 4, 3, 1); }
+    else if (n <= 20480) { GKB_PIPE_OR(512, 5, 1, 2, 512, 5, 3, 1); }
+    else { GKB_PIPE_OR(512, 6, 1, 3, 512, 6, 2, 1); }
+#undef GKB_PIPE_OR
 #undef GKB_FUSED
   } else {
     const float* Af = reinterpret_cast<const float*>(A);
 #define GKB_FUSED(T, U, R, D) \
   e = launch_u<T, U, R, D, float, TP>(Af, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st, qprev, coef)
-    if (fs.T == 128) GKB_FUSED(128, 1, 16, 1);
-    else if (fs.T == 256 && fs.U == 1) GKB_FUSED(256, 1, 8, 1);
-    else if (fs.T == 256 && fs.U == 2) GKB_FUSED(256, 2, 4, 1);
-    else if (fs.T == 256) GKB_FUSED(256, 4, 2, 1);
+#define GKB_PIPE_OR(T, U, R, NB, OT, OU, OR, OD)                                                       \
+  if (!gw && pipe_fits<T, U, R, NB, float>(m, n, false))                                               \
+    e = launch_p<T, U, R, NB, float, TP, false>(Af, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st, \
+                                                qprev, coef);                                          \
+  else GKB_FUSED(OT, OU, OR, OD)
+    // (ms, old -> pipelined: 16-byte groups per row <= 128 1.01 -> 0.85;
+    // <= 256 1.11 -> 0.88; <= 512 0.77 -> 0.64; <= 1024 0.67 -> 0.63;
+    // <= 3072 0.67 -> 0.61; <= 4096 0.62 -> 0.61; <= 5120 0.67 -> 0.62, at
+    // 3-4 GB of A; the old form stays at 2048 groups (within the variation
+    // between runs) and 6144 (0.67 against 1.03: the pipelined form spills),
+    // and for the given-w sweep at 5000 groups (512 threads: fewer waves to
+    // skip; 0.63 against 0.64))
+    if (fs.T == 128) { GKB_PIPE_OR(128, 1, 8, 2, 128, 1, 16, 1); }
+    else if (fs.T == 256 && fs.U == 1) { GKB_PIPE_OR(256, 1, 8, 2, 256, 1, 8, 1); }
+    else if (fs.T == 256 && fs.U == 2) { GKB_PIPE_OR(256, 2, 2, 2, 256, 2, 4, 1); }
+    else if (fs.T == 256) { GKB_PIPE_OR(256, 4, 1, 2, 256, 4, 2, 1); }
     else if (fs.T == 512) GKB_FUSED(512, 4, 1, 2);
     else if (fs.T == 768) GKB_FUSED(768, 8, 1, 1);
-    else if (fs.U <= 3) GKB_FUSED(1024, 3, 1, 2);
-    else if (fs.U == 4) GKB_FUSED(1024, 4, 1, 2);
-    else if (win != nullptr) e = launch_v<512, 10, 1, 1, float, TP, true>(Af, lda, m, n, p, win, w, ypart, ldy, flag,
-                                                                          run_if, st);   // fewer waves to skip
-    else GKB_FUSED(1024, 5, 1, 1);
+    else if (fs.U <= 3) { GKB_PIPE_OR(1024, 3, 1, 2, 1024, 3, 1, 2); }
+    else if (fs.U == 4) { GKB_PIPE_OR(512, 8, 1, 2, 1024, 4, 1, 2); }
+    else if (gw) e = launch_v<512, 10, 1, 1, float, TP, true>(Af, lda, m, n, p, win, w, ypart, ldy, flag, run_if, st);
+    else { GKB_PIPE_OR(512, 10, 1, 2, 1024, 5, 1, 1); }
+#undef GKB_PIPE_OR
 #undef GKB_FUSED
   }
   if (e != hipSuccess || y == nullptr) return e;

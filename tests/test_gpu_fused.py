@@ -20,7 +20,10 @@ U64 = 2.0 ** -53
 # with several groups each for long ones), the largest n, padded rows
 SHAPES = [(1, 4, 0), (100, 8, 0), (257, 512, 4), (4000, 1000, 0), (3001, 2044, 0), (20000, 2048, 0),
           (3000, 4096, 4), (2500, 8000, 0), (1500, 12000, 0), (1200, 16380, 0), (5000, 20000, 8),
-          (777, 24576, 0), (70000, 100, 0)]
+          (777, 24576, 0), (70000, 100, 0), (1, 20000, 0), (257, 19996, 4), (3001, 16388, 0),
+          # the pipelined form near its LDS limit (the staged w of 3907 rows per
+          # workgroup), and past it (4883 rows: the per-row barrier form)
+          (4_000_000, 4, 0), (5_000_000, 4, 0)]
 
 
 def _padded(a, pad):
@@ -53,7 +56,7 @@ def test_fused_products(shape):
 
 
 BF16_SHAPES = [(1, 8, 0), (300, 1000, 8), (2000, 2048, 0), (3001, 4096, 0), (1500, 8000, 8), (1200, 16384, 0),
-               (5000, 20000, 8), (777, 24576, 0), (70000, 96, 0)]
+               (5000, 20000, 8), (777, 24576, 0), (70000, 96, 0), (4_000_000, 8, 0), (5_000_000, 8, 0)]
 
 
 @pytest.mark.parametrize("shape", BF16_SHAPES)
