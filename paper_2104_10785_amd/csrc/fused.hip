@@ -8,7 +8,10 @@
 // contiguous range of rows, keeps p in LDS, and for each row forms the dot
 // product (reduced across the workgroup in a fixed order) and adds a_i * w_i
 // into its float64 partial of A^T w held in registers, while the next rows
-// are already loading.  The partials of all workgroups are added in
+// are already loading.  Two forms: the pipelined one (k_gemv_fused_pipe),
+// whose row loads stay in flight across each row's reduction, and the
+// per-row one (k_gemv_fused), kept for the shapes where it measured faster
+// and for the given-w sweep.  The partials of all workgroups are added in
 // workgroup order by the consumer (the reduction, recovery or fix-up kernel).
 #include <hip/hip_runtime.h>
 
@@ -457,18 +460,33 @@ __device__ __forceinline__ void column_sums(const double* __restrict__ ypart, in
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double sy = 0.0, sg = 0.0;
   if (in) {
+    // eight (four) independent sums, so that as many loads are in flight per
+    // wave; combined in a fixed order
     const int b0 = (int)((int64_t)nb * wave / 4), b1 = (int)((int64_t)nb * (wave + 1) / 4);
-    double s0 = 0.0, s1 = 0.0;
+    double s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.0;
     int b = b0;
-    for (; b + 1 < b1; b += 2) {
-      s0 += ypart[(int64_t)b * ldy + j];
-      s1 += ypart[(int64_t)(b + 1) * ldy + j];
+    for (; b + 7 < b1; b += 8) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k] += ypart[(int64_t)(b + k) * ldy + j];
     }
-    if (b < b1) s0 += ypart[(int64_t)b * ldy + j];
-    sy = s0 + s1;
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+      if (b + k < b1) s[k] += ypart[(int64_t)(b + k) * ldy + j];
+    sy = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     if (G != nullptr) {
       const int c0 = t * wave / 4, c1 = t * (wave + 1) / 4;
-      for (int c = c0; c < c1; ++c) sg += G[(int64_t)c * ldg + j] * coef(c);
+      double g[4] = {0.0, 0.0, 0.0, 0.0};
+      int c = c0;
+      for (; c + 3 < c1; c += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g[k] += G[(int64_t)(c + k) * ldg + j] * coef(c + k);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (c + k < c1) g[k] += G[(int64_t)(c + k) * ldg + j] * coef(c + k);
+      sg = (g[0] + g[1]) + (g[2] + g[3]);
     }
   }
   ps[0][wave][lane] = sy;
