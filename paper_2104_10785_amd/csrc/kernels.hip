@@ -359,104 +359,164 @@ __global__ __launch_bounds__(256) void k_sum_slices(const T* __restrict__ P, int
 // ---------------------------------------------------------------- row-major GEMM
 // C (M x N, column-major, ldc) = A (M x K, row-major, lda, float32) *
 // B (K x N, column-major, ldb, float32), on the float32 16x16x4 MFMA.
-// A block (4 waves) computes a 128 x 64 tile of C: wave w owns rows
-// [32w, 32w + 32) (two 16-row MFMA tiles) and the block's 64 columns (four
-// 16-column tiles).  K advances in chunks of 32: the A chunk (128 x 32, each
-// row 128 contiguous bytes) and the B chunk (32 x 64, each column 128
-// contiguous bytes) are staged in LDS with coalesced loads (row stride padded
-// to 36 floats), then read by the MFMAs.  Used for the Rayleigh-Ritz block
-// product W = A V and the sketch S = A Omega.
-constexpr int RM_BM = 128, RM_BN = 64, RM_BK = 32, RM_LD = RM_BK + 4;
+// A block (4 waves) computes a BM x BN tile of C: wave w owns rows
+// [w BM/4, (w + 1) BM/4) (BM/64 16-row MFMA tiles) and the block's BN
+// columns (BN/16 16-column tiles).  K advances in chunks of 32: the chunk in
+// LDS (A: BM rows of 128 contiguous bytes; B: BN columns of 128 contiguous
+// bytes; row stride padded to 36 floats) feeds the MFMAs while the next
+// chunk's loads are in flight into registers.  Tiles: 128 x 64 for N <= 64,
+// 64 x 112 for N <= 112 (one column tile, so A is read once), 64 x 128
+// above.  Used for the Rayleigh-Ritz block product W = A V and the sketch
+// S = A Omega.
+constexpr int RM_BK = 32, RM_LD = RM_BK + 4;
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, int64_t lda, int64_t M, int64_t K,
                                                  const float* __restrict__ B, int64_t ldb, int N,
                                                  float* __restrict__ C, int64_t ldc) {
-  __shared__ float As[RM_BM * RM_LD];
-  __shared__ float Bs[RM_BN * RM_LD];
+  constexpr int TM = BM / 64;                   // 16-row tiles per wave
+  constexpr int TN = BN / 16;                   // 16-column tiles
+  constexpr int NA = BM * 8 / 256;              // float4 of an A chunk per thread
+  constexpr int NB = (BN * 8 + 255) / 256;      // float4 of a B chunk per thread (the last partly idle)
+  static_assert(BM % 64 == 0 && BN % 16 == 0 && (BM * 8) % 256 == 0, "tile shape");
+  __shared__ float As[BM * RM_LD];
+  __shared__ float Bs[BN * RM_LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * RM_BM;
-  const int n0 = blockIdx.y * RM_BN;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
   const int li = lane & 15, lk = lane >> 4;
-  v4f acc[2][4];
+  v4f acc[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
+    for (int b = 0; b < TN; ++b) acc[a][b] = v4f{0, 0, 0, 0};
   const bool avec = ((lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   const bool bvec = ((ldb & 3) == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
-  for (int64_t k0 = 0; k0 < K; k0 += RM_BK) {
-    // A chunk: 128 rows x 32 k = 1024 float4 -> 4 per thread
+  float4 ra[NA], rb[NB];
+  // rows past M and columns past N (and the idle part of the last B slot)
+  // are zeros; the same for every chunk
+  bool oka[NA], okb[NB];
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
+  for (int it = 0; it < NA; ++it) oka[it] = m0 + ((tid + it * 256) >> 3) < M;
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int idx = tid + it * 256;
+    okb[it] = idx < BN * 8 && n0 + (idx >> 3) < N;
+  }
+  // Full 32-wide chunk k0 of aligned operands into registers with no branch
+  // and no use of the values: rows past M and columns past N load row M - 1
+  // / column N - 1 (zeroed when stored to LDS), so the loads stay in flight
+  // through the MFMAs of the current chunk.
+  auto fetch_full = [&](int64_t k0) {
+#pragma unroll
+    for (int it = 0; it < NA; ++it) {
       const int idx = tid + it * 256;
-      const int r = idx >> 3, c4 = (idx & 7) * 4;
-      const int64_t gr = m0 + r, gk = k0 + c4;
+      const uint4 u = ld_stream(A + std::min(m0 + (idx >> 3), M - 1) * lda + k0 + (idx & 7) * 4);
+      ra[it] = make_float4(__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w));
+    }
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int idx = std::min(tid + it * 256, BN * 8 - 1);
+      const int gc = std::min(n0 + (idx >> 3), N - 1);
+      rb[it] = *reinterpret_cast<const float4*>(B + (int64_t)gc * ldb + k0 + (idx & 7) * 4);
+    }
+  };
+  // Any chunk, element by element (zeros past M, N or K): the last partial
+  // chunk, or every chunk of unaligned operands.
+  auto fetch_any = [&](int64_t k0) {
+#pragma unroll
+    for (int it = 0; it < NA; ++it) {
+      const int idx = tid + it * 256;
+      const int64_t gr = m0 + (idx >> 3), gk = k0 + (idx & 7) * 4;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (gr < M) {
         const float* src = A + gr * lda + gk;
-        if (avec && gk + 4 <= K) {
-          const uint4 u = ld_stream(src);
-          v = make_float4(__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w));
-        } else {
-          if (gk < K) v.x = src[0];
-          if (gk + 1 < K) v.y = src[1];
-          if (gk + 2 < K) v.z = src[2];
-          if (gk + 3 < K) v.w = src[3];
-        }
+        if (gk < K) v.x = src[0];
+        if (gk + 1 < K) v.y = src[1];
+        if (gk + 2 < K) v.z = src[2];
+        if (gk + 3 < K) v.w = src[3];
       }
-      float* dst = As + r * RM_LD + c4;
-      dst[0] = v.x;
-      dst[1] = v.y;
-      dst[2] = v.z;
-      dst[3] = v.w;
+      ra[it] = v;
     }
-    // B chunk: 64 columns x 32 k = 512 float4 -> 2 per thread
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < NB; ++it) {
       const int idx = tid + it * 256;
-      const int c = idx >> 3, k4 = (idx & 7) * 4;
-      const int gc = n0 + c;
-      const int64_t gk = k0 + k4;
+      const int gc = n0 + (idx >> 3);
+      const int64_t gk = k0 + (idx & 7) * 4;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gc < N) {
+      if (idx < BN * 8 && gc < N) {
         const float* src = B + (int64_t)gc * ldb + gk;
-        if (bvec && gk + 4 <= K) {
-          v = *reinterpret_cast<const float4*>(src);
-        } else {
-          if (gk < K) v.x = src[0];
-          if (gk + 1 < K) v.y = src[1];
-          if (gk + 2 < K) v.z = src[2];
-          if (gk + 3 < K) v.w = src[3];
-        }
+        if (gk < K) v.x = src[0];
+        if (gk + 1 < K) v.y = src[1];
+        if (gk + 2 < K) v.z = src[2];
+        if (gk + 3 < K) v.w = src[3];
       }
-      float* dst = Bs + c * RM_LD + k4;
-      dst[0] = v.x;
-      dst[1] = v.y;
-      dst[2] = v.z;
-      dst[3] = v.w;
+      rb[it] = v;
     }
-    __syncthreads();
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int it = 0; it < NA; ++it) {
+      const int idx = tid + it * 256;
+      float* dst = As + (idx >> 3) * RM_LD + (idx & 7) * 4;
+      dst[0] = oka[it] ? ra[it].x : 0.f;
+      dst[1] = oka[it] ? ra[it].y : 0.f;
+      dst[2] = oka[it] ? ra[it].z : 0.f;
+      dst[3] = oka[it] ? ra[it].w : 0.f;
+    }
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int idx = tid + it * 256;
+      if (idx < BN * 8) {
+        float* dst = Bs + (idx >> 3) * RM_LD + (idx & 7) * 4;
+        dst[0] = okb[it] ? rb[it].x : 0.f;
+        dst[1] = okb[it] ? rb[it].y : 0.f;
+        dst[2] = okb[it] ? rb[it].z : 0.f;
+        dst[3] = okb[it] ? rb[it].w : 0.f;
+      }
+    }
+  };
+  auto mfma_chunk = [&]() {
 #pragma unroll
     for (int kk = 0; kk < RM_BK; kk += 4) {
-      float a0 = As[(wave * 32 + li) * RM_LD + kk + lk];
-      float a1 = As[(wave * 32 + 16 + li) * RM_LD + kk + lk];
+      float av[TM];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int a = 0; a < TM; ++a) av[a] = As[(wave * (BM / 4) + a * 16 + li) * RM_LD + kk + lk];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
         const float bv = Bs[(b * 16 + li) * RM_LD + kk + lk];
-        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][b], 0, 0, 0);
-        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < TM; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv, acc[a][b], 0, 0, 0);
       }
     }
+  };
+  // full chunks: the next one (the last one again at the end: one spare
+  // chunk load per block) loads while the current one feeds the MFMAs
+  const int64_t kfull = (avec && bvec) ? K / RM_BK * RM_BK : 0;
+  if (kfull > 0) fetch_full(0);
+  for (int64_t k0 = 0; k0 < kfull; k0 += RM_BK) {
+    stash();
+    __syncthreads();
+    fetch_full(std::min(k0 + RM_BK, kfull - RM_BK));
+    __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the MFMAs
+    mfma_chunk();
+    __syncthreads();
+  }
+  for (int64_t k0 = kfull; k0 < K; k0 += RM_BK) {
+    fetch_any(k0);
+    stash();
+    __syncthreads();
+    mfma_chunk();
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < TN; ++b) {
       const int col = n0 + b * 16 + li;
       if (col < N) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t row = m0 + wave * 32 + a * 16 + 4 * lk + v;
+          const int64_t row = m0 + wave * (BM / 4) + a * 16 + 4 * lk + v;
           if (row < M) C[(int64_t)col * ldc + row] = acc[a][b][v];
         }
       }
@@ -664,8 +724,16 @@ hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t m, int64_t n,
 hipError_t launch_gemm_rm(const float* A, int64_t lda, int64_t M, int64_t K, const float* B, int64_t ldb, int N,
                           float* C, int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid(nblocks(M, RM_BM), nblocks(N, RM_BN));
-  hipLaunchKernelGGL(k_gemm_rm, grid, dim3(256), 0, st, A, lda, M, K, B, ldb, N, C, ldc);
+  if (N <= 64) {
+    hipLaunchKernelGGL((k_gemm_rm<128, 64>), dim3(nblocks(M, 128), 1), dim3(256), 0, st, A, lda, M, K, B, ldb, N, C,
+                       ldc);
+  } else if (N <= 112) {
+    hipLaunchKernelGGL((k_gemm_rm<64, 112>), dim3(nblocks(M, 64), 1), dim3(256), 0, st, A, lda, M, K, B, ldb, N, C,
+                       ldc);
+  } else {
+    hipLaunchKernelGGL((k_gemm_rm<64, 128>), dim3(nblocks(M, 64), nblocks(N, 128)), dim3(256), 0, st, A, lda, M, K, B,
+                       ldb, N, C, ldc);
+  }
   return hipGetLastError();
 }
 

@@ -124,7 +124,8 @@ def test_device_start_vector_matches_oracle():
 
 
 @pytest.mark.parametrize("MKN", [(1000, 777, 50), (513, 1, 7), (2000, 1030, 100), (130, 33, 64), (64, 64, 65),
-                                 (20000, 5000, 32)])
+                                 (20000, 5000, 32), (3000, 777, 128), (3001, 800, 129), (20000, 5000, 100),
+                                 (63, 31, 112), (65, 64, 113)])
 @pytest.mark.parametrize("pad", [0, 1])
 def test_gemm_rowmajor(MKN, pad):
     device()
