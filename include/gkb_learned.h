@@ -35,7 +35,8 @@ size_t gkb_mlp_workspace_size(int64_t m, int in, int hidden, int r);
 
 /* Features from the sketch S (m x ws, column-major, leading dimension
    lds >= m: the C output of gkb_gemm_rowmajor) and the previous left vectors
-   Ut_prev (r x m); in = ws + r.  workspace >= r + 1 floats. */
+   Ut_prev (r x m); in = ws + r.  workspace: 8-byte aligned, >= 64 doubles
+   (partial sums of squares of S) + r + 1 floats. */
 gkb_status gkb_mlp_features(const float* S, int64_t lds, int64_t m, int ws, const float* Ut_prev, int r, float* X,
                             void* workspace, size_t ws_bytes, void* stream);
 

@@ -364,12 +364,20 @@ __global__ __launch_bounds__(256) void k_sum_slices(const T* __restrict__ P, int
 // columns (BN/16 16-column tiles).  K advances in chunks of 32: the chunk in
 // LDS (A: BM rows of 128 contiguous bytes; B: BN columns of 128 contiguous
 // bytes; row stride padded to 36 floats) feeds the MFMAs while the next
-// chunk's loads are in flight into registers.  Tiles: 128 x 64 for N <= 64,
-// 64 x 112 for N <= 112 (one column tile, so A is read once), 64 x 128
-// above.  Used for the Rayleigh-Ritz block product W = A V and the sketch
+// chunk's loads are in flight into registers.  Tiles: 64 x 32 for N <= 32
+// with the K range split in two (more workgroups for the narrow sketch),
+// 128 x 64 for N <= 64, 64 x 112 for N <= 112 (one column tile, so A is read
+// once), 64 x 128 above.  Used for the Rayleigh-Ritz block product W = A V and the sketch
 // S = A Omega.
 constexpr int RM_BK = 32, RM_LD = RM_BK + 4;
-template <int BM, int BN>
+// C[col * ldc + row] = 0 for row < M, col < N.
+__global__ __launch_bounds__(256) void k_zero_cols(float* __restrict__ C, int64_t ldc, int64_t M, int N) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t col = e / M, row = e - col * M;
+  C[col * ldc + row] = 0.f;
+}
+template <int BM, int BN, bool SPLIT2>
 __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, int64_t lda, int64_t M, int64_t K,
                                                  const float* __restrict__ B, int64_t ldb, int N,
                                                  float* __restrict__ C, int64_t ldc) {
@@ -384,6 +392,12 @@ __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, in
   const int64_t m0 = (int64_t)blockIdx.x * BM;
   const int n0 = blockIdx.y * BN;
   const int li = lane & 15, lk = lane >> 4;
+  // SPLIT2: workgroup z of 2 takes K range [kb, ke) (the halves split at a
+  // multiple of the chunk width) and adds its product into C, which the launch
+  // has zeroed; two addends on zero give the same sum in either order
+  const int64_t khalf = K / (2 * RM_BK) * RM_BK;
+  const int64_t kb = SPLIT2 && blockIdx.z == 1 ? khalf : 0;
+  const int64_t ke = SPLIT2 && blockIdx.z == 0 ? khalf : K;
   v4f acc[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -430,10 +444,10 @@ __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, in
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (gr < M) {
         const float* src = A + gr * lda + gk;
-        if (gk < K) v.x = src[0];
-        if (gk + 1 < K) v.y = src[1];
-        if (gk + 2 < K) v.z = src[2];
-        if (gk + 3 < K) v.w = src[3];
+        if (gk < ke) v.x = src[0];
+        if (gk + 1 < ke) v.y = src[1];
+        if (gk + 2 < ke) v.z = src[2];
+        if (gk + 3 < ke) v.w = src[3];
       }
       ra[it] = v;
     }
@@ -445,10 +459,10 @@ __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, in
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (idx < BN * 8 && gc < N) {
         const float* src = B + (int64_t)gc * ldb + gk;
-        if (gk < K) v.x = src[0];
-        if (gk + 1 < K) v.y = src[1];
-        if (gk + 2 < K) v.z = src[2];
-        if (gk + 3 < K) v.w = src[3];
+        if (gk < ke) v.x = src[0];
+        if (gk + 1 < ke) v.y = src[1];
+        if (gk + 2 < ke) v.z = src[2];
+        if (gk + 3 < ke) v.w = src[3];
       }
       rb[it] = v;
     }
@@ -491,9 +505,9 @@ __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, in
   };
   // full chunks: the next one (the last one again at the end: one spare
   // chunk load per block) loads while the current one feeds the MFMAs
-  const int64_t kfull = (avec && bvec) ? K / RM_BK * RM_BK : 0;
-  if (kfull > 0) fetch_full(0);
-  for (int64_t k0 = 0; k0 < kfull; k0 += RM_BK) {
+  const int64_t kfull = (avec && bvec) ? kb + (ke - kb) / RM_BK * RM_BK : kb;
+  if (kfull > kb) fetch_full(kb);
+  for (int64_t k0 = kb; k0 < kfull; k0 += RM_BK) {
     stash();
     __syncthreads();
     fetch_full(std::min(k0 + RM_BK, kfull - RM_BK));
@@ -501,7 +515,7 @@ __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, in
     mfma_chunk();
     __syncthreads();
   }
-  for (int64_t k0 = kfull; k0 < K; k0 += RM_BK) {
+  for (int64_t k0 = kfull; k0 < ke; k0 += RM_BK) {
     fetch_any(k0);
     stash();
     __syncthreads();
@@ -517,7 +531,10 @@ __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, in
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t row = m0 + wave * (BM / 4) + a * 16 + 4 * lk + v;
-          if (row < M) C[(int64_t)col * ldc + row] = acc[a][b][v];
+          if (row < M) {
+            if constexpr (SPLIT2) atomicAdd(C + (int64_t)col * ldc + row, acc[a][b][v]);
+            else C[(int64_t)col * ldc + row] = acc[a][b][v];
+          }
         }
       }
     }
@@ -724,14 +741,18 @@ hipError_t launch_cast_bf16(const float* src, int64_t lds, int64_t m, int64_t n,
 hipError_t launch_gemm_rm(const float* A, int64_t lda, int64_t M, int64_t K, const float* B, int64_t ldb, int N,
                           float* C, int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if (N <= 64) {
-    hipLaunchKernelGGL((k_gemm_rm<128, 64>), dim3(nblocks(M, 128), 1), dim3(256), 0, st, A, lda, M, K, B, ldb, N, C,
+  if (N <= 32) {
+    hipLaunchKernelGGL(k_zero_cols, dim3(nblocks(M * N, 256)), dim3(256), 0, st, C, ldc, M, N);
+    hipLaunchKernelGGL((k_gemm_rm<64, 32, true>), dim3(nblocks(M, 64), 1, 2), dim3(256), 0, st, A, lda, M, K, B, ldb, N,
+                       C, ldc);
+  } else if (N <= 64) {
+    hipLaunchKernelGGL((k_gemm_rm<128, 64, false>), dim3(nblocks(M, 128), 1), dim3(256), 0, st, A, lda, M, K, B, ldb, N, C,
                        ldc);
   } else if (N <= 112) {
-    hipLaunchKernelGGL((k_gemm_rm<64, 112>), dim3(nblocks(M, 64), 1), dim3(256), 0, st, A, lda, M, K, B, ldb, N, C,
+    hipLaunchKernelGGL((k_gemm_rm<64, 112, false>), dim3(nblocks(M, 64), 1), dim3(256), 0, st, A, lda, M, K, B, ldb, N, C,
                        ldc);
   } else {
-    hipLaunchKernelGGL((k_gemm_rm<64, 128>), dim3(nblocks(M, 64), nblocks(N, 128)), dim3(256), 0, st, A, lda, M, K, B,
+    hipLaunchKernelGGL((k_gemm_rm<64, 128, false>), dim3(nblocks(M, 64), nblocks(N, 128)), dim3(256), 0, st, A, lda, M, K, B,
                        ldb, N, C, ldc);
   }
   return hipGetLastError();

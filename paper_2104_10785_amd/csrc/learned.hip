@@ -49,11 +49,13 @@ __device__ double bsum256(double v, double* red) {
 }
 
 // Blocks 0..r-1: sign of column j of Ut (r x m, rows contiguous) so that its
-// largest-|.| entry (lowest index on ties) is positive.  Block r: sum of
-// squares of S (m x ws, column-major, leading dimension lds) -> c_S = sqrt(sum / (m ws)).
+// largest-|.| entry (lowest index on ties) is positive.  Blocks r .. r +
+// FS_PARTS - 1: part[b] = sum of squares of rows [b m / FS_PARTS, (b + 1) m /
+// FS_PARTS) of every column of S (m x ws, column-major, leading dimension lds).
+constexpr int FS_PARTS = 64;
 __global__ __launch_bounds__(256) void k_feature_stats(const float* __restrict__ S, int64_t lds, int64_t m, int ws,
                                                        const float* __restrict__ Ut, int r, float* __restrict__ sgn,
-                                                       float* __restrict__ cs) {
+                                                       double* __restrict__ part) {
   __shared__ double red[4];
   __shared__ float bv[256];
   __shared__ int bi[256];
@@ -85,23 +87,39 @@ __global__ __launch_bounds__(256) void k_feature_stats(const float* __restrict__
     }
     if (tid == 0) sgn[blockIdx.x] = u[bi[0]] < 0.f ? -1.f : 1.f;
   } else {
+    const int b = (int)blockIdx.x - r;
+    const int64_t lo = b * m / FS_PARTS, hi = (b + 1) * m / FS_PARTS;
     double ss = 0.0;
     for (int c = 0; c < ws; ++c)
-      for (int64_t i = tid; i < m; i += 256) {
+      for (int64_t i = lo + tid; i < hi; i += 256) {
         const float v = S[(int64_t)c * lds + i];
         ss += (double)v * v;
       }
     const double tot = bsum256(ss, red);
-    if (tid == 0) *cs = (float)sqrt(tot / ((double)m * ws));
+    if (tid == 0) part[b] = tot;
   }
 }
 
+// X[i] = [S_i / c_S, sqrt(m) sgn_j Ut[j, i], 1, 0 ...] with c_S = sqrt(sum of
+// the FS_PARTS partial sums of squares (fixed order) / (m ws)); block 0 also
+// stores c_S in *cs.
 __global__ __launch_bounds__(256) void k_features(const float* __restrict__ S, int64_t lds, int64_t m, int ws,
                                                   const float* __restrict__ Ut, int r, const float* __restrict__ sgn,
-                                                  const float* __restrict__ cs, float* __restrict__ X) {
+                                                  const double* __restrict__ part, float* __restrict__ cs,
+                                                  float* __restrict__ X) {
+  static_assert(FS_PARTS == 64, "one partial per lane");
+  __shared__ float csl;
+  if (threadIdx.x < 64) {
+    const double tot = wsum_d(part[threadIdx.x]);
+    if (threadIdx.x == 0) {
+      csl = (float)sqrt(tot / ((double)m * ws));
+      if (blockIdx.x == 0) *cs = csl;
+    }
+  }
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= m) return;
-  const float inv = *cs > 0.f ? 1.f / *cs : 0.f;
+  const float inv = csl > 0.f ? 1.f / csl : 0.f;
   const float sm = sqrtf((float)m);
   float* xi = X + i * XLD;
   for (int c = 0; c < ws; ++c) xi[c] = S[(int64_t)c * lds + i] * inv;
@@ -110,36 +128,89 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ S, i
   for (int c = ws + r + 1; c < XLD; ++c) xi[c] = 0.f;
 }
 
-// z_i = w2 . relu(W1 x_i + b1) + b2 (one thread per row; parameters read with
-// uniform addresses); optionally H[i * hld + k] = relu(.)_k and H[i*hld + hidden] = 1.
-__global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ prm, int in, int hidden,
-                                                 const float* __restrict__ X, int64_t m, float* __restrict__ z,
-                                                 float* __restrict__ H, int hld) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= m) return;
+// The hidden layer of a workgroup's rows: the units go over the lanes in
+// chunks of NH_CHUNK (lane l: units h0 + 2 l and h0 + 2 l + 1), W1 of the
+// chunk staged in LDS transposed (W1T[c][k]: a lane's two weights of input c
+// are adjacent), b1 and w2 beside it; x_c reaches every lane as a uniform
+// value read from lane c.  a_k = b1[k] + sum_c W1[k][c] x_c with the sum in
+// input order, as one thread per row would form it.
+constexpr int NH_CHUNK = 128;
+struct HiddenLds {
+  float W1T[(XLD - 1) * NH_CHUNK];
+  float b1[NH_CHUNK];
+  float w2[NH_CHUNK];
+};
+
+// Stage units [h0, h0 + NH_CHUNK) (zeros past hidden).  Ends with a barrier.
+__device__ void stage_hidden(const float* __restrict__ prm, int in, int hidden, int h0, HiddenLds& L) {
   const float* W1 = prm;
   const float* b1 = prm + (int64_t)hidden * in;
   const float* w2 = b1 + hidden;
-  const float b2 = w2[hidden];
-  float x[XLD];
-#pragma unroll
-  for (int c = 0; c < XLD; ++c) x[c] = X[i * XLD + c];
-  float acc = b2;
-  for (int k = 0; k < hidden; ++k) {
-    float a = b1[k];
-    const float* wk = W1 + (int64_t)k * in;
-#pragma unroll
-    for (int c = 0; c < XLD - 1; ++c)
-      if (c < in) a += wk[c] * x[c];
-    const float h = a > 0.f ? a : 0.f;
-    acc += w2[k] * h;
-    if (H) H[i * hld + k] = h;
+  const int hc = min(NH_CHUNK, hidden - h0);
+  __syncthreads();   // the previous chunk's readers are done
+  for (int e = threadIdx.x; e < NH_CHUNK * in; e += blockDim.x) {
+    const int kk = e / in, c = e - kk * in;
+    L.W1T[c * NH_CHUNK + kk] = kk < hc ? W1[(int64_t)(h0 + kk) * in + c] : 0.f;
   }
-  if (H) {
-    H[i * hld + hidden] = 1.f;
-    for (int k = hidden + 1; k < hld; ++k) H[i * hld + k] = 0.f;
+  for (int kk = threadIdx.x; kk < NH_CHUNK; kk += blockDim.x) {
+    L.b1[kk] = kk < hc ? b1[h0 + kk] : 0.f;
+    L.w2[kk] = kk < hc ? w2[h0 + kk] : 0.f;
   }
-  z[i] = acc;
+  __syncthreads();
+}
+
+// Pre-activations of this lane's two units of the staged chunk for one row
+// (xv: this lane's entry of the row, lanes 0 .. in - 1 used).
+__device__ __forceinline__ float2 preact(const HiddenLds& L, int in, float xv) {
+  const int lane = threadIdx.x & 63;
+  float a0 = L.b1[2 * lane], a1 = L.b1[2 * lane + 1];
+  const int xi = __float_as_int(xv);
+  for (int c = 0; c < in; ++c) {
+    const float xc = __int_as_float(__builtin_amdgcn_readlane(xi, c));
+    const float2 w = *reinterpret_cast<const float2*>(&L.W1T[c * NH_CHUNK + 2 * lane]);
+    a0 = fmaf(w.x, xc, a0);
+    a1 = fmaf(w.y, xc, a1);
+  }
+  return make_float2(a0, a1);
+}
+
+// z_i = w2 . relu(W1 x_i + b1) + b2 for FW_ROWS rows per workgroup, a wave
+// per row; the hidden-layer sum over each lane's units, then across the wave
+// (butterfly), then over the chunks; optionally H[i * hld + k] = relu(.)_k,
+// H[i * hld + hidden] = 1 and zeros up to hld.
+constexpr int FW_ROWS = 32;
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ prm, int in, int hidden,
+                                                 const float* __restrict__ X, int64_t m, float* __restrict__ z,
+                                                 float* __restrict__ H, int hld) {
+  __shared__ HiddenLds L;
+  __shared__ float zacc[FW_ROWS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * FW_ROWS;
+  const int nr = (int)min<int64_t>(FW_ROWS, m - r0);
+  const float* w2g = prm + (int64_t)hidden * in + hidden;
+  for (int h0 = 0; h0 < hidden; h0 += NH_CHUNK) {
+    stage_hidden(prm, in, hidden, h0, L);
+    for (int rr = wave; rr < nr; rr += 4) {
+      const int64_t i = r0 + rr;
+      const float2 a = preact(L, in, X[i * XLD + lane]);
+      const float h0v = a.x > 0.f ? a.x : 0.f, h1v = a.y > 0.f ? a.y : 0.f;
+      float s = fmaf(L.w2[2 * lane + 1], h1v, L.w2[2 * lane] * h0v);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) zacc[rr] = h0 == 0 ? s : zacc[rr] + s;
+      if (H) {
+        const int k = h0 + 2 * lane;
+        if (k < hidden) H[i * hld + k] = h0v;
+        if (k + 1 < hidden) H[i * hld + k + 1] = h1v;
+      }
+    }
+  }
+  for (int rr = wave; rr < nr; rr += 4) {
+    const int64_t i = r0 + rr;
+    if (lane == 0) z[i] = w2g[hidden] + zacc[rr];
+    if (H)
+      for (int k = hidden + lane; k < hld; k += 64) H[i * hld + k] = k == hidden ? 1.f : 0.f;
+  }
 }
 
 // stats[j] = U_t[:, j] . z for j < r (Ut rows contiguous), stats[r] = ||z||^2.
@@ -168,51 +239,65 @@ __global__ __launch_bounds__(256) void k_loss_stats(const float* __restrict__ Ut
 // DH[i + k m] = dz_i w2[k] [a_k > 0]; block 0 writes the loss.
 constexpr double LOGTAN_DELTA = 1e-6;
 
+// FW_ROWS rows per workgroup: threads 0 .. FW_ROWS - 1 form dL/dz of their
+// row, then a wave per row forms the pre-activations of a chunk of units and
+// DH[i + k m] = dz_i w2[k] [a_k > 0], staged in LDS and written a unit at a
+// time over consecutive rows.
 __global__ __launch_bounds__(256) void k_mlp_bwd_rows(const float* __restrict__ prm, int in, int hidden,
                                                       const float* __restrict__ X, int64_t m,
                                                       const float* __restrict__ z, const float* __restrict__ Ut, int r,
                                                       const double* __restrict__ stats, float* __restrict__ dz,
                                                       float* __restrict__ DH, double* __restrict__ loss, int kind) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ HiddenLds L;
+  __shared__ float gzs[FW_ROWS];
+  __shared__ float dhs[NH_CHUNK * FW_ROWS];   // [unit][row]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * FW_ROWS;
+  const int nr = (int)min<int64_t>(FW_ROWS, m - r0);
   const double zz = stats[r];
-  double g = 0.0;
-  if (kind == 0) {
-    double cc = 0.0;
-    for (int j = 0; j < r; ++j) cc += stats[j] * stats[j];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *loss = zz > 0 ? 1.0 - cc / zz : 1.0;
-    if (i >= m) return;
-    double pz = 0.0;
-    for (int j = 0; j < r; ++j) pz += (double)Ut[(int64_t)j * m + i] * stats[j];
-    g = zz > 0 ? (2.0 / zz) * (-pz + (cc / zz) * (double)z[i]) : 0.0;
-  } else {
-    const double dl = LOGTAN_DELTA;
-    double lsum = 0.0, s1 = 0.0, pv = 0.0;
-    for (int j = 0; j < r; ++j) {
-      const double c = stats[j];
-      const double a = (1.0 + dl) * zz - c * c, b = c * c + dl * zz;
-      lsum += log(a / b);
-      s1 += 2.0 * (1.0 + dl) / a - 2.0 * dl / b;
-      if (i < m) pv += (double)Ut[(int64_t)j * m + i] * (2.0 / r) * c * (1.0 / a + 1.0 / b);
+  if (tid < FW_ROWS) {
+    const int64_t i = r0 + tid;
+    double g = 0.0;
+    if (kind == 0) {
+      double cc = 0.0;
+      for (int j = 0; j < r; ++j) cc += stats[j] * stats[j];
+      if (blockIdx.x == 0 && tid == 0) *loss = zz > 0 ? 1.0 - cc / zz : 1.0;
+      if (i < m) {
+        double pz = 0.0;
+        for (int j = 0; j < r; ++j) pz += (double)Ut[(int64_t)j * m + i] * stats[j];
+        g = zz > 0 ? (2.0 / zz) * (-pz + (cc / zz) * (double)z[i]) : 0.0;
+      }
+    } else {
+      const double dl = LOGTAN_DELTA;
+      double lsum = 0.0, s1 = 0.0, pv = 0.0;
+      for (int j = 0; j < r; ++j) {
+        const double c = stats[j];
+        const double a = (1.0 + dl) * zz - c * c, b = c * c + dl * zz;
+        lsum += log(a / b);
+        s1 += 2.0 * (1.0 + dl) / a - 2.0 * dl / b;
+        if (i < m) pv += (double)Ut[(int64_t)j * m + i] * (2.0 / r) * c * (1.0 / a + 1.0 / b);
+      }
+      if (blockIdx.x == 0 && tid == 0) *loss = zz > 0 ? lsum / r : 0.0;
+      if (i < m) g = zz > 0 ? (s1 / r) * (double)z[i] - pv : 0.0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *loss = zz > 0 ? lsum / r : 0.0;
-    if (i >= m) return;
-    g = zz > 0 ? (s1 / r) * (double)z[i] - pv : 0.0;
+    gzs[tid] = (float)g;
+    if (i < m) dz[i] = (float)g;
   }
-  const float gz = (float)g;
-  dz[i] = gz;
-  const float* W1 = prm;
-  const float* b1 = prm + (int64_t)hidden * in;
-  const float* w2 = b1 + hidden;
-  float x[XLD];
-#pragma unroll
-  for (int c = 0; c < XLD; ++c) x[c] = X[i * XLD + c];
-  for (int k = 0; k < hidden; ++k) {
-    float a = b1[k];
-    const float* wk = W1 + (int64_t)k * in;
-#pragma unroll
-    for (int c = 0; c < XLD - 1; ++c)
-      if (c < in) a += wk[c] * x[c];
-    DH[i + (int64_t)k * m] = a > 0.f ? gz * w2[k] : 0.f;
+  for (int h0 = 0; h0 < hidden; h0 += NH_CHUNK) {
+    stage_hidden(prm, in, hidden, h0, L);   // (its first barrier also publishes gzs)
+    for (int rr = wave; rr < nr; rr += 4) {
+      const int64_t i = r0 + rr;
+      const float2 a = preact(L, in, X[i * XLD + lane]);
+      const float gz = gzs[rr];
+      dhs[(2 * lane) * FW_ROWS + rr] = a.x > 0.f ? gz * L.w2[2 * lane] : 0.f;
+      dhs[(2 * lane + 1) * FW_ROWS + rr] = a.y > 0.f ? gz * L.w2[2 * lane + 1] : 0.f;
+    }
+    __syncthreads();
+    const int hc = min(NH_CHUNK, hidden - h0);
+    for (int e = tid; e < hc * FW_ROWS; e += 256) {
+      const int kk = e / FW_ROWS, rr = e - kk * FW_ROWS;
+      if (rr < nr) DH[(r0 + rr) + (int64_t)(h0 + kk) * m] = dhs[e];
+    }
   }
 }
 
@@ -282,6 +367,8 @@ MlpWs mlp_ws(int64_t m, int hidden, int r) {
   return w;
 }
 
+size_t feature_ws_bytes(int r) { return (size_t)FS_PARTS * 8 + (size_t)(r + 1) * 4; }
+
 thread_local std::string l_err;
 gkb_status lfail(gkb_status s, const char* msg) {
   l_err = msg;
@@ -325,14 +412,16 @@ gkb_status gkb_mlp_features(const float* S, int64_t lds, int64_t m, int ws, cons
   l_err.clear();
   if (!S || !X || m < 1 || ws < 0 || r < 0 || ws + r + 1 > XLD || lds < m || (r > 0 && !Ut_prev))
     return lfail(GKB_ERR_INVALID, "bad feature arguments");
-  if (!workspace || ws_bytes < (size_t)(r + 1) * 4)
-    return lfail(GKB_ERR_WORKSPACE, "workspace too small");
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 7) || ws_bytes < feature_ws_bytes(r))
+    return lfail(GKB_ERR_WORKSPACE, "workspace too small or misaligned");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  float* sgn = reinterpret_cast<float*>(workspace);
+  double* part = reinterpret_cast<double*>(workspace);
+  float* sgn = reinterpret_cast<float*>(part + FS_PARTS);
   float* cs = sgn + r;
-  hipLaunchKernelGGL(k_feature_stats, dim3(r + 1), dim3(256), 0, st, S, lds, m, ws, Ut_prev, r, sgn, cs);
+  hipLaunchKernelGGL(k_feature_stats, dim3(r + FS_PARTS), dim3(256), 0, st, S, lds, m, ws, Ut_prev, r, sgn, part);
   L_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_features, dim3(nblk(m, 256)), dim3(256), 0, st, S, lds, m, ws, Ut_prev, r, sgn, cs, X);
+  hipLaunchKernelGGL(k_features, dim3(nblk(m, 256)), dim3(256), 0, st, S, lds, m, ws, Ut_prev, r, sgn, part, cs,
+                     X);
   L_HIP(hipGetLastError());
   return GKB_OK;
 }
@@ -341,8 +430,8 @@ gkb_status gkb_mlp_forward(const float* params, int in, int hidden, const float*
                            void* stream) {
   l_err.clear();
   if (!params || !X || !z || m < 1 || !shapes_ok(in, hidden)) return lfail(GKB_ERR_INVALID, "bad forward arguments");
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk(m, 256)), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), params, in,
-                     hidden, X, m, z, nullptr, 0);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk(m, FW_ROWS)), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), params,
+                     in, hidden, X, m, z, nullptr, 0);
   L_HIP(hipGetLastError());
   return GKB_OK;
 }
@@ -371,12 +460,12 @@ gkb_status gkb_mlp_loss_grad_kind(const float* params, int in, int hidden, const
   double* stats = reinterpret_cast<double*>(b + w.stats);
   float* G1 = reinterpret_cast<float*>(b + w.G1);
   float* G2 = reinterpret_cast<float*>(b + w.G2);
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk(m, 256)), dim3(256), 0, st, params, in, hidden, X, m, z, H, w.hld);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk(m, FW_ROWS)), dim3(256), 0, st, params, in, hidden, X, m, z, H, w.hld);
   L_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_loss_stats, dim3(r + 1), dim3(256), 0, st, Ut, r, z, m, stats);
   L_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mlp_bwd_rows, dim3(nblk(m, 256)), dim3(256), 0, st, params, in, hidden, X, m, z, Ut, r, stats,
-                     dz, DH, loss, kind);
+  hipLaunchKernelGGL(k_mlp_bwd_rows, dim3(nblk(m, FW_ROWS)), dim3(256), 0, st, params, in, hidden, X, m, z, Ut, r,
+                     stats, dz, DH, loss, kind);
   L_HIP(hipGetLastError());
   // G1 = X^T DH (XLD x hidden), G2 = H^T dz (hld x 1): sums over the rows on MFMA, split over row ranges
   float* Gpart = reinterpret_cast<float*>(b + w.Gpart);

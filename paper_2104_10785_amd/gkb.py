@@ -639,7 +639,7 @@ def gkb_mlp_features(St, Ut_prev, stream=None):
     ws, m = St.shape
     r = Ut_prev.shape[0] if Ut_prev is not None else 0
     X = torch.empty((m, lib().gkb_mlp_feature_stride()), dtype=torch.float32, device=St.device)
-    wk = _workspace(4 * (r + 1) + 256, St.device)
+    wk = _workspace(64 * 8 + 4 * (r + 1) + 256, St.device)
     _lcheck(lib().gkb_mlp_features(C.c_void_p(St.data_ptr()), St.stride(0), m, ws,
                                    C.c_void_p(Ut_prev.data_ptr()) if r else None, r, C.c_void_p(X.data_ptr()),
                                    C.c_void_p(wk.data_ptr()), wk.numel(), _stream(stream)))

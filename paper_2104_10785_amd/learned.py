@@ -130,13 +130,21 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     hparams, hhidden = _heuristic_params(ws, r, n_in)
     hparams = torch.from_numpy(hparams).to(device)
     rows = []
+    def clock():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
     for t in range(t_train + 1, t_train + t_eval + 1):
         seq.advance()
+        c0 = clock()
         X = features(U_prev)
+        c1 = clock()
         # random start
         sig_r, Ut_r, _, st_r, s_r = solve(key=t)
+        c2 = clock()
         # learned start (+1 matvec for the sketch), random fallback
         q_l = gkb.gkb_mlp_start_vector(params, n_in, hidden, X)
+        c3 = clock()
         fallback = False
         try:
             sig_l, Ut_l, _, st_l, s_l = solve(q1=q_l)
@@ -144,6 +152,7 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
             ok = st_l == 0
         except gkb.GkbError:
             ok, mv_l = False, 1
+        c4 = clock()
         if not ok:
             fallback = True
             sig_l, Ut_l, _, st_l, s_l2 = solve(key=t)
@@ -156,6 +165,8 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
         except gkb.GkbError:
             st_h, mv_h = -1, -1
         rows.append({"t": t, "random": s_r["matvecs"], "learned": mv_l, "heuristic": mv_h, "fallback": fallback,
+                     "ms_features": (c1 - c0) * 1e3, "ms_random": (c2 - c1) * 1e3, "ms_network": (c3 - c2) * 1e3,
+                     "ms_learned_solve": (c4 - c3) * 1e3,
                      "status_random": st_r, "status_learned": st_l, "status_heuristic": st_h,
                      "sigma_diff": float(np.max(np.abs(sig_l - sig_r)))})
         U_prev = Ut_l
@@ -170,6 +181,12 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
         "matvecs_learned": {"mean": mv_l.mean(), "median": float(np.median(mv_l))},
         "matvecs_heuristic": {"mean": mv_h.mean(), "median": float(np.median(mv_h))},
         "learned_over_random_ratio_mean": float(np.mean(mv_l / mv_r)),
+        # wall time to tolerance per held-out matrix (device synchronised): the
+        # random start's solve; the learned start's sketch + features + network
+        # + solve (a fallback solve, if any, is not in these figures)
+        "ms_random": float(np.mean([x["ms_random"] for x in rows])),
+        "ms_learned": float(np.mean([x["ms_features"] + x["ms_network"] + x["ms_learned_solve"] for x in rows])),
+        "ms_learned_start": float(np.mean([x["ms_features"] + x["ms_network"] for x in rows])),
         "learned_win_fraction": float(np.mean(mv_l < mv_r)),
         "fallbacks": int(sum(x["fallback"] for x in rows)),
         "max_sigma_diff_learned_vs_random": float(max(x["sigma_diff"] for x in rows)),
