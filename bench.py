@@ -144,13 +144,36 @@ def ritz_gemms(gkb, torch, dev, stream, reps):
     return out
 
 
+def blas_threads():
+    """Threads of the BLAS library numpy runs the oracle's products on."""
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d["num_threads"] for d in threadpool_info() if d.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A32, q, budget_s=20.0):
     """Time the float64 oracle on the host: its first-cycle Golub-Kahan steps on
     the full matrix (exact float64 upcast), as many as fit in about budget_s
     seconds, scaled to a full solve by the oracle's own matvec count for this
     workload (tests/golden/c2_oracle_top50.json, written by oracle code)."""
     from oracle import gk
-    threads = os.cpu_count() or 1
+    threads = blas_threads()
     t0 = time.time()
     A = A32.astype(np.float64)
     t_up = time.time() - t0
@@ -172,7 +195,7 @@ def cpu_baseline(A32, q, budget_s=20.0):
         mv_full, nconv = 1 + 2 * K, R
     est = per_matvec * mv_full
     del A
-    return {"value": nconv / est, "unit": "triplets/s", "cores": threads, "kind": "oracle",
+    return {"value": nconv / est, "unit": "triplets/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"oracle first-cycle Golub-Kahan steps on the full 50000x20000 float64 matrix: "
                       f"{steps} steps ({fac.matvecs} matvecs) in {dt:.2f} s, scaled to the oracle's "
                       f"{mv_full} matvecs for the full solve (CGS2 cost grows with the step, so this "
@@ -394,8 +417,8 @@ def learned_leg(dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
@@ -442,8 +465,11 @@ def main():
     t0 = time.perf_counter()
     nconv = 0
     stats = None
+    per_step = []
     for i in range(args.steps):
-        sigma, Ut, Vt, status, stats = step()
+        ts = time.perf_counter()
+        sigma, Ut, Vt, status, stats = step()   # returns after the stream has completed
+        per_step.append((time.perf_counter() - ts) * 1000.0)
         nconv += stats["nconv"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -518,7 +544,7 @@ def main():
     line = {
         "metric": "converged triplets/s (top-50 partial SVD, tol 1e-6) + matvec HBM GB/s",
         "value": value, "unit": "triplets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": ms_per_step, "ms_per_step_median": float(np.median(per_step)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "gk_partial_svd low-rank(200, 0.95^i)+noise(1e-6) 50000x20000 f32",
                    "r": R, "k": K, "tol": TOL, "max_restarts": RESTARTS, "check_every": args.check_every,
