@@ -209,6 +209,19 @@ gkb_status gkb_host_dense_svd(int nq, int np, const double* H, double* s, double
 int64_t gkb_host_bidiag_count_above(int nq, int np, const double* alpha, const double* beta,
                                     double tau);
 
+/* Host utility (no device work): the screening step of the in-cycle
+ * convergence test.  For the (np + 1) x np lower bidiagonal B of a first
+ * Golub-Kahan cycle (diagonal alpha[0..np) = the alphas, subdiagonal
+ * beta[0..np) = the betas of eq. (2.3)), writes its singular values s (np,
+ * descending) and last[i] = the last entry of the i-th left singular vector
+ * (its sign is that of the pair (u_i, v_i)), which with eq. (2.4) gives the
+ * residual estimate alpha_res |last[i]| without the singular vectors:
+ * rows rotated to upper bidiagonal form, then implicit-shift QR sweeps that
+ * carry that one row, O(np^2).  Returns GKB_OK, GKB_ERR_INVALID (np < 1 or a
+ * NULL pointer) or GKB_ERR_NUMERIC (no convergence or non-finite input).
+ */
+gkb_status gkb_host_bidiag_lastrow(int np, const double* alpha, const double* beta, double* s, double* last);
+
 #ifdef __cplusplus
 }
 #endif

@@ -376,6 +376,39 @@ void convergence(const Proj& pr, const Ritz& rz, int r, double tol, double thr, 
   ct.converged = ct.r_eff == r && ct.nconv == r;
 }
 
+// Screening of an in-cycle test on the first cycle's lower bidiagonal
+// (diagonal pc[0..np), subdiagonal qc[1..np], residual coefficient pc[np]):
+// true only if the test would clearly fail -- the r largest singular values
+// above the breakdown threshold do not number r, or one of them has a
+// residual estimate above 1.01 tol sigma_1 -- so that the dense SVD, which
+// makes every accepting decision, would reject it as well.  Not used when two
+// of the top r + 1 values are within 1e-8 of each other (the individual last
+// components of a cluster are not unique).
+bool screen_fails(int np, const std::vector<double>& pc, const std::vector<double>& qc, int r, double tol,
+                  double thr_fixed, double sig_est, bool relative, double eps) {
+  std::vector<double> alpha(pc.begin(), pc.begin() + np), beta(qc.begin() + 1, qc.begin() + np + 1);
+  std::vector<double> sv(np), last(np);
+  if (!gkb::bidiag_sv_lastrow(np, alpha.data(), beta.data(), sv.data(), last.data())) return false;
+  double seen = sig_est;
+  for (int j = 0; j < np; ++j) seen = std::max({seen, pc[j], qc[j + 1]});
+  seen = std::max(seen, pc[np]);
+  const double thr = relative ? eps * seen : thr_fixed;
+  const int top = std::min(np, r + 1);
+  for (int i = 0; i + 1 < top; ++i)
+    if (sv[i] - sv[i + 1] <= 1e-8 * sv[0]) return false;
+  int avail = 0;
+  for (int i = 0; i < np; ++i)
+    if (sv[i] > thr * (1.0 + 1e-9)) ++avail;
+  int maybe = 0;
+  for (int i = 0; i < np; ++i)
+    if (sv[i] > thr * (1.0 - 1e-9)) ++maybe;
+  if (maybe < r) return true;          // fewer than r values can pass the threshold
+  if (avail < r) return false;         // a value at the threshold: let the dense SVD decide
+  for (int i = 0; i < r; ++i)
+    if (pc[np] * std::fabs(last[i]) > 1.01 * tol * sv[0]) return true;
+  return false;
+}
+
 // Restart data carried into a restarted cycle.
 struct RestartIn {
   int l = 0;
@@ -598,6 +631,18 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
         rc = S.read_back(k + 2, qc, pc, fl);
         if (rc != GKB_OK) return rc;
         if (fl[0] != 0) break;  // breakdown: assembled below
+        if (first) {
+          // screening: singular values and the last row of X alone (O(k^2));
+          // a clearly failing test skips the dense SVD, which decides otherwise
+          const double th0 = now_ms();
+          const bool fails = screen_fails(np_now, pc, qc, r, tol, S.relative ? S.eps * sig_est : S.eps, sig_est,
+                                          S.relative != 0, S.eps);
+          ms_host += now_ms() - th0;
+          if (fails) {
+            ++checks;
+            continue;
+          }
+        }
         Proj part;
         rc = assemble(first, np_now, rs, qc, pc, fl, part);
         if (rc != GKB_OK) return rc;
@@ -968,6 +1013,14 @@ gkb_status gkb_host_dense_svd(int nq, int np, const double* H, double* s, double
 int64_t gkb_host_bidiag_count_above(int nq, int np, const double* alpha, const double* beta, double tau) {
   if (np < 1 || (nq != np && nq != np + 1) || !alpha || (nq > 1 && !beta) || !(tau > 0)) return -1;
   return gkb::bidiag_count_above(nq, np, alpha, beta, tau);
+}
+
+gkb_status gkb_host_bidiag_lastrow(int np, const double* alpha, const double* beta, double* s, double* last) {
+  g_err.clear();
+  if (np < 1 || !alpha || !beta || !s || !last) return fail(GKB_ERR_INVALID, "bad arguments");
+  if (!gkb::bidiag_sv_lastrow(np, alpha, beta, s, last))
+    return fail(GKB_ERR_NUMERIC, "no convergence or non-finite input");
+  return GKB_OK;
 }
 
 // ------------------------------------------------------------ building blocks

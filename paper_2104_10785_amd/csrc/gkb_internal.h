@@ -16,6 +16,12 @@ bool dense_svd(int nq, int np, const double* H, double* s, double* X, double* Y)
 // alpha[0..np) and subdiagonal beta[0..nq-1), nq in {np, np+1}; O(np^2).
 bool bidiag_singular_values(int nq, int np, const double* alpha, const double* beta, double* s);
 
+// Singular values s (descending) of the (np + 1) x np lower bidiagonal with
+// diagonal alpha[0..np) and subdiagonal beta[0..np), and last[i] = the last
+// entry of the i-th left singular vector (up to the common sign of the pair);
+// O(np^2).
+bool bidiag_sv_lastrow(int np, const double* alpha, const double* beta, double* s, double* last);
+
 // #{sigma_i > tau} of the lower bidiagonal (alpha diagonal, beta subdiagonal)
 // by Sylvester inertia of its Golub-Kahan tridiagonal.
 int64_t bidiag_count_above(int nq, int np, const double* alpha, const double* beta, double tau);

@@ -52,7 +52,11 @@ inline void givens(double y, double z, double* c, double* s, double* r) {
     *r = y;
     return;
   }
-  double h = std::hypot(y, z);
+  // sqrt(y^2 + z^2) where the squares cannot overflow (std::hypot, which
+  // guards every input, costs tens of nanoseconds and the sweeps make two
+  // rotations per step)
+  const double big = std::max(std::fabs(y), std::fabs(z));
+  const double h = (big < 1e150 && big > 1e-150) ? std::sqrt(y * y + z * z) : std::hypot(y, z);
   *c = y / h;
   *s = z / h;
   *r = h;
@@ -60,14 +64,15 @@ inline void givens(double y, double z, double* c, double* s, double* r) {
 
 // Implicit-shift QR sweeps on the upper bidiagonal (d[0..N), e[0..N-1)).
 // Rotations are accumulated into the rows of Ut (N x M) and Vt (N x N) when
-// those are non-null.  On return d holds the singular values, sorted
+// those are non-null (Ut may carry any M columns of the left factor, e.g. one
+// row of the left singular vectors, with Vt null).  On return d holds the singular values, sorted
 // descending and non-negative (rows of Ut/Vt permuted and signed to match).
 bool bidiag_qr(int N, double* d, double* e, double* Ut, int M, double* Vt) {
   const bool vec = Ut != nullptr;
   if (N == 1) {
     if (d[0] < 0) {
       d[0] = -d[0];
-      if (vec) Vt[0] = -Vt[0];
+      if (Vt) Vt[0] = -Vt[0];
     }
     return true;
   }
@@ -128,7 +133,7 @@ bool bidiag_qr(int N, double* d, double* e, double* Ut, int M, double* Vt) {
           double c, s, r;
           givens(d[j], xv, &c, &s, &r);
           d[j] = r;
-          if (vec) rot_cols(&Vt[(size_t)j * N], &Vt[(size_t)hi * N], N, c, s);
+          if (Vt) rot_cols(&Vt[(size_t)j * N], &Vt[(size_t)hi * N], N, c, s);
           if (j > lo) {
             xv = -s * e[j - 1];
             e[j - 1] = c * e[j - 1];
@@ -156,7 +161,7 @@ bool bidiag_qr(int N, double* d, double* e, double* Ut, int M, double* Vt) {
       e[kk] = -s * dk + c * ek;
       double bulge = s * dk1;
       d[kk + 1] = c * dk1;
-      if (vec) rot_cols(&Vt[(size_t)kk * N], &Vt[(size_t)(kk + 1) * N], N, c, s);
+      if (Vt) rot_cols(&Vt[(size_t)kk * N], &Vt[(size_t)(kk + 1) * N], N, c, s);
       // left rotation on rows kk, kk+1
       givens(d[kk], bulge, &c, &s, &r);
       d[kk] = r;
@@ -176,7 +181,7 @@ bool bidiag_qr(int N, double* d, double* e, double* Ut, int M, double* Vt) {
   for (int i = 0; i < N; ++i)
     if (d[i] < 0) {
       d[i] = -d[i];
-      if (vec)
+      if (Vt)
         for (int t = 0; t < N; ++t) Vt[(size_t)i * N + t] = -Vt[(size_t)i * N + t];
     }
   for (int i = 0; i < N - 1; ++i) {
@@ -185,10 +190,8 @@ bool bidiag_qr(int N, double* d, double* e, double* Ut, int M, double* Vt) {
       if (d[j] > d[best]) best = j;
     if (best != i) {
       std::swap(d[i], d[best]);
-      if (vec) {
-        std::swap_ranges(&Ut[(size_t)i * M], &Ut[(size_t)i * M] + M, &Ut[(size_t)best * M]);
-        std::swap_ranges(&Vt[(size_t)i * N], &Vt[(size_t)i * N] + N, &Vt[(size_t)best * N]);
-      }
+      if (vec) std::swap_ranges(&Ut[(size_t)i * M], &Ut[(size_t)i * M] + M, &Ut[(size_t)best * M]);
+      if (Vt) std::swap_ranges(&Vt[(size_t)i * N], &Vt[(size_t)i * N] + N, &Vt[(size_t)best * N]);
     }
   }
   return true;
@@ -325,6 +328,36 @@ bool bidiag_singular_values(int nq, int np, const double* alpha, const double* b
   }
   if (!bidiag_qr(np, d.data(), e.data(), nullptr, 0, nullptr)) return false;
   for (int j = 0; j < np; ++j) s[j] = d[j];
+  return true;
+}
+
+bool bidiag_sv_lastrow(int np, const double* alpha, const double* beta, double* s, double* last) {
+  // The (np + 1) x np lower bidiagonal B is G^T [B_up; 0] with G the row
+  // rotations (j, j+1) that make it upper bidiagonal, so the last row of its
+  // left singular vectors is (G e_last)^T [U_up; 0]: G e_last has entries only
+  // at np - 1 (the last rotation's sine) and np.  That one row of left factor
+  // is then carried through the QR sweeps as a single column.
+  if (np <= 0) return true;
+  std::vector<double> d(alpha, alpha + np), e(std::max(np - 1, 1), 0.0), u(np, 0.0);
+  double sn_last = 0.0;
+  for (int j = 0; j < np; ++j) {
+    if (!std::isfinite(d[j]) || !std::isfinite(beta[j])) return false;
+    double c, sn, r;
+    givens(d[j], beta[j], &c, &sn, &r);
+    d[j] = r;
+    if (j + 1 < np) {
+      e[j] = sn * d[j + 1];
+      d[j + 1] = c * d[j + 1];
+    } else {
+      sn_last = sn;
+    }
+  }
+  u[np - 1] = sn_last;
+  if (!bidiag_qr(np, d.data(), e.data(), u.data(), 1, nullptr)) return false;
+  for (int j = 0; j < np; ++j) {
+    s[j] = d[j];
+    last[j] = u[j];
+  }
   return true;
 }
 

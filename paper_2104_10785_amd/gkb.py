@@ -65,7 +65,7 @@ _lib = None
 
 EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_rank_workspace_size",
            "gkb_numerical_rank", "gkb_status_string", "gkb_last_error", "gkb_host_dense_svd",
-           "gkb_host_bidiag_count_above", "gkb_matvec_workspace_size", "gkb_matvec", "gkb_gemm_tall",
+           "gkb_host_bidiag_count_above", "gkb_host_bidiag_lastrow", "gkb_matvec_workspace_size", "gkb_matvec", "gkb_gemm_tall",
            "gkb_cast_bf16", "gkb_start_vector", "gkb_gemm_rowmajor", "gkb_gram_workspace_size", "gkb_gram",
            "gkb_batch_default_options", "gkb_batched_workspace_size", "gkb_batched_plan_create",
            "gkb_batched_plan_run", "gkb_batched_plan_info", "gkb_batched_plan_grid", "gkb_batched_plan_destroy",
@@ -112,6 +112,8 @@ def lib():
     L.gkb_host_dense_svd.restype = C.c_int
     L.gkb_host_bidiag_count_above.argtypes = [C.c_int, C.c_int, P(C.c_double), P(C.c_double), C.c_double]
     L.gkb_host_bidiag_count_above.restype = C.c_int64
+    L.gkb_host_bidiag_lastrow.argtypes = [C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)]
+    L.gkb_host_bidiag_lastrow.restype = C.c_int
     L.gkb_matvec_workspace_size.argtypes = [P(GkbMatrix)]
     L.gkb_matvec_workspace_size.restype = C.c_size_t
     L.gkb_matvec.argtypes = [P(GkbMatrix), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
@@ -449,6 +451,20 @@ def gkb_host_dense_svd(H: np.ndarray):
     _check(lib().gkb_host_dense_svd(nq, np_, H.ctypes.data_as(dp), s.ctypes.data_as(dp), X.ctypes.data_as(dp),
                                     Y.ctypes.data_as(dp)), False)
     return X, s, Y
+
+
+def gkb_host_bidiag_lastrow(alpha, beta):
+    """Singular values and the last row of the left singular vectors of the
+    (n + 1) x n lower bidiagonal with diagonal alpha and subdiagonal beta."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    assert a.shape == b.shape
+    s = np.zeros(a.size)
+    last = np.zeros(a.size)
+    dp = C.POINTER(C.c_double)
+    _check(lib().gkb_host_bidiag_lastrow(a.size, a.ctypes.data_as(dp), b.ctypes.data_as(dp), s.ctypes.data_as(dp),
+                                         last.ctypes.data_as(dp)), False)
+    return s, last
 
 
 def gkb_host_bidiag_count_above(alpha, beta, nq, tau) -> int:

@@ -130,6 +130,31 @@ def test_host_dense_svd_structured():
         assert np.max(np.abs((X * s) @ Y.T - M)) <= 1e-14 * max(sl[0], 1e-300) * 10
 
 
+@pytest.mark.parametrize("n", [1, 2, 5, 50, 70, 121])
+def test_host_bidiag_lastrow_against_lapack(n):
+    """The screening step of the in-cycle test: singular values and the last
+    row of the left singular vectors of a first-cycle lower bidiagonal, against
+    LAPACK's SVD of the same matrix (graded spectrum, distinct values)."""
+    rng = np.random.default_rng(n)
+    alpha = np.geomspace(1.0, 1e-3, n) * (1 + 0.05 * rng.random(n))
+    beta = 0.4 * rng.random(n)
+    B = np.zeros((n + 1, n))
+    B[np.arange(n), np.arange(n)] = alpha
+    B[np.arange(1, n + 1), np.arange(n)] = beta
+    s, last = gkb.gkb_host_bidiag_lastrow(alpha, beta)
+    U, sl, _ = np.linalg.svd(B, full_matrices=False)
+    assert np.max(np.abs(s - sl)) < 1e-13 * sl[0]
+    assert np.max(np.abs(np.abs(last) - np.abs(U[-1]))) < 1e-12
+    # the same numbers as the full host SVD the driver falls back to
+    X, sd, _ = gkb.gkb_host_dense_svd(B)
+    assert np.max(np.abs(np.abs(last) - np.abs(X[-1]))) < 1e-12
+
+
+def test_host_bidiag_lastrow_rejects_nan():
+    with pytest.raises(gkb.GkbError):
+        gkb.gkb_host_bidiag_lastrow([1.0, np.nan], [0.5, 0.5])
+
+
 def test_host_dense_svd_rejects_nan():
     H = np.ones((3, 3))
     H[1, 1] = np.nan
