@@ -182,7 +182,7 @@ __device__ double team_sum_scalar(double x, Team& tm, Lds<BT>& L) {
 // loads (4 rows x 2 vectors in flight).
 // p is in LDS (PLDS, a team's copy) or in global memory.
 template <int BT, bool PLDS>
-__device__ void bgemv_n(const BatchProblem& P, const float* p_, const float* qprev_, double c, double* w_, int lo,
+__device__ __noinline__ void bgemv_n(const BatchProblem& P, const float* p_, const float* qprev_, double c, double* w_, int lo,
                         int hi) {
   constexpr int NW = BT / 64;
   constexpr int R = 4;
@@ -242,7 +242,7 @@ __device__ void bgemv_n(const BatchProblem& P, const float* p_, const float* qpr
 // rows (8 rows in flight per thread), partial sums meet in LDS and are added
 // in group order.
 template <int BT, bool COHERENT = false>
-__device__ void bgemv_t(const BatchProblem& P, const float* q_, const float* pprev_, double c, double* out, int lo,
+__device__ __noinline__ void bgemv_t(const BatchProblem& P, const float* q_, const float* pprev_, double c, double* out, int lo,
                         int hi, Lds<BT>& L) {
   const int tid = threadIdx.x;
   const GMEM float* q = gc(q_);
