@@ -342,15 +342,28 @@ __device__ void team_gemv_t(const BatchProblem& P, const float* q, const float* 
 // ---------------------------------------------------------------- Gram-Schmidt
 // L.h[j] = V[lo:hi, j] . x[lo:hi] for j < t (waves own columns, lanes own rows).
 template <int BT>
-__device__ void bdots(const float* V_, int ldv, int t, int lo, int hi, const double* x_, Lds<BT>& L) {
+__device__ __noinline__ void bdots(const float* V_, int ldv, int t, int lo, int hi, const double* x_, Lds<BT>& L) {
   constexpr int NW = BT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const GMEM float* V = gc(V_);
   const GMEM double* x = gc(x_);
+  constexpr int U = 8;   // rows in flight per lane; the sum keeps its sequential order
   for (int j = wave; j < t; j += NW) {
     const GMEM float* col = V + (int64_t)j * ldv;
     double a = 0.0;
-    for (int i = lo + lane; i < hi; i += 64) a += (double)col[i] * x[i];
+    int i = lo + lane;
+    for (; i + (U - 1) * 64 < hi; i += U * 64) {
+      float v[U];
+      double xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = col[i + u * 64];
+        xv[u] = x[i + u * 64];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) a += (double)v[u] * xv[u];
+    }
+    for (; i < hi; i += 64) a += (double)col[i] * x[i];
     a = wsum(a);
     if (lane == 0) L.h[j] = a;
   }
@@ -359,13 +372,22 @@ __device__ void bdots(const float* V_, int ldv, int t, int lo, int hi, const dou
 
 // x[lo:hi] -= V[lo:hi, 0:t] h; returns the member's part of ||x||^2 after the update.
 template <int BT>
-__device__ double bupdate(const float* V_, int ldv, int t, int lo, int hi, double* x_, const double* h, Lds<BT>& L) {
+__device__ __noinline__ double bupdate(const float* V_, int ldv, int t, int lo, int hi, double* x_, const double* h, Lds<BT>& L) {
   const GMEM float* V = gc(V_);
   GMEM double* x = gw(x_);
   double ss = 0.0;
+  constexpr int U = 8;   // columns in flight per thread; the update keeps its sequential order
   for (int i = lo + threadIdx.x; i < hi; i += BT) {
     double xi = x[i];
-    for (int j = 0; j < t; ++j) xi -= (double)V[(int64_t)j * ldv + i] * h[j];
+    int j = 0;
+    for (; j + U <= t; j += U) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = V[(int64_t)(j + u) * ldv + i];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xi -= (double)v[u] * h[j + u];
+    }
+    for (; j < t; ++j) xi -= (double)V[(int64_t)j * ldv + i] * h[j];
     x[i] = xi;
     ss += xi * xi;
   }
