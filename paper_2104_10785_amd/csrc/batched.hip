@@ -199,7 +199,7 @@ __device__ __noinline__ void bgemv_n(const BatchProblem& P, const float* p_, con
     const GMEM float* rows[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) rows[r] = A + (int64_t)min(i0 + r, hi - 1) * P.lda;
-    float a[R] = {0.f, 0.f, 0.f, 0.f};
+    float a[R] = {};
     int jt = 0;
     if (vec) {
       const int nv = P.n >> 2;
@@ -261,18 +261,19 @@ __device__ __noinline__ void bgemv_t(const BatchProblem& P, const float* q_, con
     const GMEM float* base = gc(P.A) + cg * VN;
     int i = lo + g;
     if (vec) {
-      // 8 rows in flight per thread (128 bytes): enough outstanding loads
+      // TR rows in flight per thread (16 TR bytes): enough outstanding loads
       // per CU to keep streaming when every CU competes for HBM
-      for (; i + 7 * G < hi; i += 8 * G) {
-        f4 a[8];
-        float qq[8];
+      constexpr int TR = 16;
+      for (; i + (TR - 1) * G < hi; i += TR * G) {
+        f4 a[TR];
+        float qq[TR];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < TR; ++u) {
           qq[u] = q[i + u * G];
           a[u] = *(const GMEM f4*)(base + (int64_t)(i + u * G) * P.lda);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < TR; ++u) {
           acc[0] += a[u].x * qq[u];
           acc[1] += a[u].y * qq[u];
           acc[2] += a[u].z * qq[u];
