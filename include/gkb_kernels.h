@@ -58,8 +58,12 @@ gkb_status gkb_gemm_tall(gkb_dtype dtype, const void* A, int64_t lda, int64_t M,
 /*
  * C (M x N, column-major, ldc >= M) = A (M x K, row-major, lda >= K) *
  * B (K x N, column-major, ldb >= K), float32 on the 16x16x4 MFMA with the
- * A and B tiles staged in LDS.  The block product of the Rayleigh-Ritz
- * refinement (W = A V, eq. (5)) and of the sketch A Omega.
+ * A and B tiles staged in LDS (the next K chunk loading during the MFMAs).
+ * The block product of the Rayleigh-Ritz refinement (W = A V, eq. (5)) and
+ * of the sketch A Omega.  C is overwritten and must not overlap A or B.  For
+ * N <= 32 the two halves of the K range are added into C (zeroed first) by
+ * float atomics; with two addends on zero the sum does not depend on their
+ * order, so results are reproducible.  Device pointers owned by the caller.
  */
 gkb_status gkb_gemm_rowmajor(const float* A, int64_t lda, int64_t M, int64_t K, const float* B, int64_t ldb,
                              int N, float* C, int64_t ldc, void* stream);
