@@ -144,6 +144,12 @@ def ritz_gemms(gkb, torch, dev, stream, reps):
     return out
 
 
+def device_info(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", ""), "cus": p.multi_processor_count,
+            "hbm_gib": round(p.total_memory / 2**30, 1), "hip": torch.version.hip}
+
+
 def blas_threads():
     """Threads of the BLAS library numpy runs the oracle's products on."""
     try:
@@ -548,7 +554,9 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "gk_partial_svd low-rank(200, 0.95^i)+noise(1e-6) 50000x20000 f32",
                    "r": R, "k": K, "tol": TOL, "max_restarts": RESTARTS, "check_every": args.check_every,
-                   "step": "one_sweep" if one_pass else "two_product", "parallelism": "single-gpu"},
+                   "step": "one_sweep" if one_pass else "two_product", "parallelism": "single-gpu",
+                   "seed": SEED, "start_seed": QSEED},
+        "device": device_info(torch),
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom_name),
                      "algorithmic_bytes": dom_bytes, "kernel_ms": dom_ms},
