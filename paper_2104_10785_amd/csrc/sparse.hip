@@ -54,18 +54,15 @@ __device__ __forceinline__ float strided_sum(const int32_t* __restrict__ idx, co
   return s;
 }
 
-// Stream blocks: blk[2b] = first row, blk[2b + 1] = row count.
-__global__ __launch_bounds__(SP_T) void k_spmv_stream(const int64_t* __restrict__ ptr,
-                                                       const int32_t* __restrict__ idx,
-                                                       const float* __restrict__ val,
-                                                       const int32_t* __restrict__ blk,
-                                                       const float* __restrict__ x, const float* __restrict__ prev,
-                                                       const double* __restrict__ coef, int cidx,
-                                                       double* __restrict__ y, const int* __restrict__ flag) {
-  if (flag != nullptr && flag[0] != 0) return;
+// Stream block b: blk[2b] = first row, blk[2b + 1] = row count.
+__device__ __forceinline__ void spmv_stream_block(int b, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                  const int32_t* __restrict__ blk, const float* __restrict__ x,
+                                                  const float* __restrict__ prev, const double* __restrict__ coef,
+                                                  int cidx, double* __restrict__ y) {
   __shared__ float prod[SP_BLOCK_NNZ];
   __shared__ int64_t off[SP_SHORT + 1];
-  const int r0 = blk[2 * blockIdx.x], nr = blk[2 * blockIdx.x + 1];
+  const int r0 = blk[2 * b], nr = blk[2 * b + 1];
   for (int t = threadIdx.x; t <= nr; t += SP_T) off[t] = ptr[r0 + t];
   __syncthreads();
   const int64_t e0 = off[0];
@@ -85,24 +82,21 @@ __global__ __launch_bounds__(SP_T) void k_spmv_stream(const int64_t* __restrict_
   }
   __syncthreads();
   if (threadIdx.x < nr) {
-    const int b = (int)(off[threadIdx.x] - e0), e = (int)(off[threadIdx.x + 1] - e0);
+    const int bq = (int)(off[threadIdx.x] - e0), e = (int)(off[threadIdx.x + 1] - e0);
     float s = 0.f;
-    for (int q = b; q < e; ++q) s += prod[q];
+    for (int q = bq; q < e; ++q) s += prod[q];
     const int row = r0 + threadIdx.x;
     y[row] = (double)s - (prev ? coef[cidx] * (double)prev[row] : 0.0);
   }
 }
 
-// Medium rows: one wave per row (4 rows per workgroup).
-__global__ __launch_bounds__(SP_T) void k_spmv_wave(const int64_t* __restrict__ ptr,
-                                                     const int32_t* __restrict__ idx,
-                                                     const float* __restrict__ val,
-                                                     const int32_t* __restrict__ rows, int64_t count,
-                                                     const float* __restrict__ x, const float* __restrict__ prev,
-                                                     const double* __restrict__ coef, int cidx,
-                                                     double* __restrict__ y, const int* __restrict__ flag) {
-  if (flag != nullptr && flag[0] != 0) return;
-  const int64_t w = (int64_t)blockIdx.x * (SP_T / 64) + (threadIdx.x >> 6);
+// Medium rows: one wave per row, 4 rows per workgroup (workgroup b).
+__device__ __forceinline__ void spmv_wave_block(int b, const int64_t* __restrict__ ptr,
+                                                const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                const int32_t* __restrict__ rows, int64_t count,
+                                                const float* __restrict__ x, const float* __restrict__ prev,
+                                                const double* __restrict__ coef, int cidx, double* __restrict__ y) {
+  const int64_t w = (int64_t)b * (SP_T / 64) + (threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   if (w >= count) return;   // uniform over the wave
   const int32_t row = rows[w];
@@ -112,17 +106,13 @@ __global__ __launch_bounds__(SP_T) void k_spmv_wave(const int64_t* __restrict__ 
 
 // Huge rows, step 1: chunk c of row crow[c] covers entries
 // [cbeg[c], min(cbeg[c] + SP_HUGE, end of the row)); part[c] = its sum.
-__global__ __launch_bounds__(SP_T) void k_spmv_chunk(const int64_t* __restrict__ ptr,
-                                                      const int32_t* __restrict__ idx,
-                                                      const float* __restrict__ val,
-                                                      const int32_t* __restrict__ crow,
-                                                      const int64_t* __restrict__ cbeg,
-                                                      const float* __restrict__ x, float* __restrict__ part,
-                                                      const int* __restrict__ flag) {
-  if (flag != nullptr && flag[0] != 0) return;
+__device__ __forceinline__ void spmv_chunk_block(int c, const int64_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                                 const int32_t* __restrict__ crow, const int64_t* __restrict__ cbeg,
+                                                 const float* __restrict__ x, float* __restrict__ part) {
   __shared__ float red[SP_T / 64];
-  const int64_t b = cbeg[blockIdx.x];
-  const int64_t e = std::min<int64_t>(b + SP_HUGE, ptr[crow[blockIdx.x] + 1]);
+  const int64_t b = cbeg[c];
+  const int64_t e = std::min<int64_t>(b + SP_HUGE, ptr[crow[c] + 1]);
   const float s = wave_sum_f(strided_sum(idx, val, x, b + threadIdx.x, e, SP_T));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -130,8 +120,34 @@ __global__ __launch_bounds__(SP_T) void k_spmv_chunk(const int64_t* __restrict__
     float t = 0.f;
 #pragma unroll
     for (int w = 0; w < SP_T / 64; ++w) t += red[w];
-    part[blockIdx.x] = t;
+    part[c] = t;
   }
+}
+
+// All three row classes in one launch, so that their gathers overlap: the
+// first nchunk workgroups take huge-row chunks, the next nwb medium rows (4
+// per workgroup), the rest stream blocks of short rows.  Each row's sum is
+// formed exactly as in its class's own schedule.
+__global__ __launch_bounds__(SP_T) void k_spmv_rows(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                                                    const float* __restrict__ val, const int32_t* __restrict__ crow,
+                                                    const int64_t* __restrict__ cbeg, int nchunk,
+                                                    float* __restrict__ part, const int32_t* __restrict__ wrow,
+                                                    int64_t nwrow, int nwb, const int32_t* __restrict__ sblk,
+                                                    const float* __restrict__ x, const float* __restrict__ prev,
+                                                    const double* __restrict__ coef, int cidx,
+                                                    double* __restrict__ y, const int* __restrict__ flag) {
+  if (flag != nullptr && flag[0] != 0) return;
+  int b = (int)blockIdx.x;
+  if (b < nchunk) {
+    spmv_chunk_block(b, ptr, idx, val, crow, cbeg, x, part);
+    return;
+  }
+  b -= nchunk;
+  if (b < nwb) {
+    spmv_wave_block(b, ptr, idx, val, wrow, nwrow, x, prev, coef, cidx, y);
+    return;
+  }
+  spmv_stream_block(b - nwb, ptr, idx, val, sblk, x, prev, coef, cidx, y);
 }
 
 // Huge rows, step 2: y[row] = sum of its chunk sums in chunk order.
@@ -221,18 +237,14 @@ bool sparse_schedule(SparseDir& D, const std::vector<int64_t>& p, int64_t nnz, s
 
 hipError_t launch_spmv(const SparseDir& D, const float* x, const float* prev, const double* coef, int cidx,
                        double* y, const int* flag, hipStream_t st) {
-  if (D.nsblk > 0)
-    hipLaunchKernelGGL(k_spmv_stream, dim3((unsigned)D.nsblk), dim3(SP_T), 0, st, D.ptr, D.idx, D.val, D.sblk, x,
-                       prev, coef, cidx, y, flag);
-  if (D.nwrow > 0)
-    hipLaunchKernelGGL(k_spmv_wave, dim3(nblk(D.nwrow, SP_T / 64)), dim3(SP_T), 0, st, D.ptr, D.idx, D.val, D.wrow,
-                       D.nwrow, x, prev, coef, cidx, y, flag);
-  if (D.nhrow > 0) {
-    hipLaunchKernelGGL(k_spmv_chunk, dim3((unsigned)D.nchunk), dim3(SP_T), 0, st, D.ptr, D.idx, D.val, D.crow,
-                       D.cbeg, x, D.part, flag);
+  const int nwb = (int)nblk(D.nwrow, SP_T / 64);
+  const int64_t blocks = (int64_t)D.nchunk + nwb + D.nsblk;
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_spmv_rows, dim3((unsigned)blocks), dim3(SP_T), 0, st, D.ptr, D.idx, D.val, D.crow, D.cbeg,
+                       (int)D.nchunk, D.part, D.wrow, D.nwrow, nwb, D.sblk, x, prev, coef, cidx, y, flag);
+  if (D.nhrow > 0)
     hipLaunchKernelGGL(k_spmv_huge_sum, dim3(nblk(D.nhrow, SP_T)), dim3(SP_T), 0, st, D.hrow, D.hfirst, D.nhrow,
                        D.part, prev, coef, cidx, y, flag);
-  }
   return hipGetLastError();
 }
 
