@@ -62,6 +62,7 @@ struct BatchParams {
   int* team_cnt;           // barrier counters, one per team (zeroed before each run)
   int nteams;
   double* team_buf;        // team reduction buffers
+  int outline;             // 1: products and Gram-Schmidt kernels out of line (long rows)
 };
 
 // threads per workgroup: 512 or 1024

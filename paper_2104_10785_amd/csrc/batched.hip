@@ -182,7 +182,7 @@ __device__ double team_sum_scalar(double x, Team& tm, Lds<BT>& L) {
 // loads (4 rows x 2 vectors in flight).
 // p is in LDS (PLDS, a team's copy) or in global memory.
 template <int BT, bool PLDS>
-__device__ __noinline__ void bgemv_n(const BatchProblem& P, const float* p_, const float* qprev_, double c, double* w_, int lo,
+__device__ void bgemv_n_body(const BatchProblem& P, const float* p_, const float* qprev_, double c, double* w_, int lo,
                         int hi) {
   constexpr int NW = BT / 64;
   constexpr int R = 4;
@@ -241,8 +241,8 @@ __device__ __noinline__ void bgemv_n(const BatchProblem& P, const float* p_, con
 // (pprev may be null); threads own 4-column groups, G row groups split the
 // rows (8 rows in flight per thread), partial sums meet in LDS and are added
 // in group order.
-template <int BT, bool COHERENT = false>
-__device__ __noinline__ void bgemv_t(const BatchProblem& P, const float* q_, const float* pprev_, double c, double* out, int lo,
+template <int BT, bool COHERENT, bool DEEP>
+__device__ void bgemv_t_body(const BatchProblem& P, const float* q_, const float* pprev_, double c, double* out, int lo,
                         int hi, Lds<BT>& L) {
   const int tid = threadIdx.x;
   const GMEM float* q = gc(q_);
@@ -263,7 +263,7 @@ __device__ __noinline__ void bgemv_t(const BatchProblem& P, const float* q_, con
     if (vec) {
       // TR rows in flight per thread (16 TR bytes): enough outstanding loads
       // per CU to keep streaming when every CU competes for HBM
-      constexpr int TR = 16;
+      constexpr int TR = DEEP ? 16 : 8;
       for (; i + (TR - 1) * G < hi; i += TR * G) {
         f4 a[TR];
         float qq[TR];
@@ -320,17 +320,46 @@ __device__ __noinline__ void bgemv_t(const BatchProblem& P, const float* q_, con
   }
 }
 
+// The products in two forms: inline, or out of line (OUT), where they get
+// registers of their own instead of sharing the solver's: worth a call's
+// register save and restore when the rows are long enough to stream from HBM
+// (on short, cache-resident problems the calls cost more than they save).
+// Out of line they also keep more loads in flight (DEEP), which inline
+// would only add to the solver's spills.
+template <int BT, bool PLDS>
+__device__ __noinline__ void bgemv_n_ool(const BatchProblem& P, const float* p_, const float* qprev_, double c,
+                                         double* w_, int lo, int hi) {
+  bgemv_n_body<BT, PLDS>(P, p_, qprev_, c, w_, lo, hi);
+}
+template <int BT, bool OUT, bool PLDS>
+__device__ __forceinline__ void bgemv_n(const BatchProblem& P, const float* p_, const float* qprev_, double c,
+                                        double* w_, int lo, int hi) {
+  if constexpr (OUT) bgemv_n_ool<BT, PLDS>(P, p_, qprev_, c, w_, lo, hi);
+  else bgemv_n_body<BT, PLDS>(P, p_, qprev_, c, w_, lo, hi);
+}
+template <int BT, bool COHERENT>
+__device__ __noinline__ void bgemv_t_ool(const BatchProblem& P, const float* q_, const float* pprev_, double c,
+                                         double* out, int lo, int hi, Lds<BT>& L) {
+  bgemv_t_body<BT, COHERENT, true>(P, q_, pprev_, c, out, lo, hi, L);
+}
+template <int BT, bool OUT, bool COHERENT = false>
+__device__ __forceinline__ void bgemv_t(const BatchProblem& P, const float* q_, const float* pprev_, double c,
+                                        double* out, int lo, int hi, Lds<BT>& L) {
+  if constexpr (OUT) bgemv_t_ool<BT, COHERENT>(P, q_, pprev_, c, out, lo, hi, L);
+  else bgemv_t_body<BT, COHERENT, false>(P, q_, pprev_, c, out, lo, hi, L);
+}
+
 // z[j] = (A^T q)[j] - c * pprev[j] for this member's entries j in [plo, phi);
 // q is read on the member's rows [qlo, qhi) only.
-template <int BT>
+template <int BT, bool OUT>
 __device__ void team_gemv_t(const BatchProblem& P, const float* q, const float* pprev, double c, double* z,
                             int qlo, int qhi, int plo, int phi, Team& tm, Lds<BT>& L) {
   if (tm.T == 1) {
-    bgemv_t<BT>(P, q, pprev, c, z, 0, P.m, L);
+    bgemv_t<BT, OUT>(P, q, pprev, c, z, 0, P.m, L);
     return;
   }
   double* mine = tm.zpart + (int64_t)tm.member * P.n;
-  bgemv_t<BT, true>(P, q, nullptr, 0.0, mine, qlo, qhi, L);
+  bgemv_t<BT, OUT, true>(P, q, nullptr, 0.0, mine, qlo, qhi, L);
   team_barrier(tm, L);
   for (int j = plo + threadIdx.x; j < phi; j += BT) {
     double s = 0.0;
@@ -342,13 +371,13 @@ __device__ void team_gemv_t(const BatchProblem& P, const float* q, const float* 
 
 // ---------------------------------------------------------------- Gram-Schmidt
 // L.h[j] = V[lo:hi, j] . x[lo:hi] for j < t (waves own columns, lanes own rows).
-template <int BT>
-__device__ __noinline__ void bdots(const float* V_, int ldv, int t, int lo, int hi, const double* x_, Lds<BT>& L) {
+template <int BT, bool DEEP>
+__device__ void bdots_body(const float* V_, int ldv, int t, int lo, int hi, const double* x_, Lds<BT>& L) {
   constexpr int NW = BT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const GMEM float* V = gc(V_);
   const GMEM double* x = gc(x_);
-  constexpr int U = 8;   // rows in flight per lane; the sum keeps its sequential order
+  constexpr int U = DEEP ? 8 : 1;   // rows in flight per lane; the sum keeps its sequential order
   for (int j = wave; j < t; j += NW) {
     const GMEM float* col = V + (int64_t)j * ldv;
     double a = 0.0;
@@ -372,12 +401,12 @@ __device__ __noinline__ void bdots(const float* V_, int ldv, int t, int lo, int 
 }
 
 // x[lo:hi] -= V[lo:hi, 0:t] h; returns the member's part of ||x||^2 after the update.
-template <int BT>
-__device__ __noinline__ double bupdate(const float* V_, int ldv, int t, int lo, int hi, double* x_, const double* h, Lds<BT>& L) {
+template <int BT, bool DEEP>
+__device__ double bupdate_body(const float* V_, int ldv, int t, int lo, int hi, double* x_, const double* h, Lds<BT>& L) {
   const GMEM float* V = gc(V_);
   GMEM double* x = gw(x_);
   double ss = 0.0;
-  constexpr int U = 8;   // columns in flight per thread; the update keeps its sequential order
+  constexpr int U = DEEP ? 8 : 1;   // columns in flight per thread; the update keeps its sequential order
   for (int i = lo + threadIdx.x; i < hi; i += BT) {
     double xi = x[i];
     int j = 0;
@@ -396,18 +425,40 @@ __device__ __noinline__ double bupdate(const float* V_, int ldv, int t, int lo, 
   return block_sum(ss, L);
 }
 
+template <int BT>
+__device__ __noinline__ void bdots_ool(const float* V_, int ldv, int t, int lo, int hi, const double* x_,
+                                       Lds<BT>& L) {
+  bdots_body<BT, true>(V_, ldv, t, lo, hi, x_, L);
+}
+template <int BT, bool OUT>
+__device__ __forceinline__ void bdots(const float* V_, int ldv, int t, int lo, int hi, const double* x_, Lds<BT>& L) {
+  if constexpr (OUT) bdots_ool<BT>(V_, ldv, t, lo, hi, x_, L);
+  else bdots_body<BT, false>(V_, ldv, t, lo, hi, x_, L);
+}
+template <int BT>
+__device__ __noinline__ double bupdate_ool(const float* V_, int ldv, int t, int lo, int hi, double* x_,
+                                           const double* h, Lds<BT>& L) {
+  return bupdate_body<BT, true>(V_, ldv, t, lo, hi, x_, h, L);
+}
+template <int BT, bool OUT>
+__device__ __forceinline__ double bupdate(const float* V_, int ldv, int t, int lo, int hi, double* x_,
+                                          const double* h, Lds<BT>& L) {
+  if constexpr (OUT) return bupdate_ool<BT>(V_, ldv, t, lo, hi, x_, h, L);
+  else return bupdate_body<BT, false>(V_, ldv, t, lo, hi, x_, h, L);
+}
+
 // Two classical Gram-Schmidt passes of x against V[:, 0:t] on the member's
 // range; returns the team-wide ||x||^2.
-template <int BT>
+template <int BT, bool OUT>
 __device__ double bcgs2(const float* V, int ldv, int t, int lo, int hi, double* x, Team& tm, Lds<BT>& L) {
   double ss;
   if (t > 0) {
-    bdots(V, ldv, t, lo, hi, x, L);
+    bdots<BT, OUT>(V, ldv, t, lo, hi, x, L);
     team_sum(L.h, t, tm, L);
-    bupdate(V, ldv, t, lo, hi, x, L.h, L);
-    bdots(V, ldv, t, lo, hi, x, L);
+    bupdate<BT, OUT>(V, ldv, t, lo, hi, x, L.h, L);
+    bdots<BT, OUT>(V, ldv, t, lo, hi, x, L);
     team_sum(L.h, t, tm, L);
-    ss = bupdate(V, ldv, t, lo, hi, x, L.h, L);
+    ss = bupdate<BT, OUT>(V, ldv, t, lo, hi, x, L.h, L);
   } else {
     ss = 0.0;
     const GMEM double* xg = gc(x);
@@ -600,7 +651,7 @@ __device__ double philox_normal(int64_t i, uint64_t seed) {
 }
 
 // Solve one problem as member `member` of its team (all threads of the workgroup).
-template <int BT>
+template <int BT, bool OUT>
 __device__ void solve_one(const BatchProblem& P, int member, const BatchParams& prm, Lds<BT>& L) {
   const int tid = threadIdx.x;
   const int ldq = P.ldq, ldp = P.ldp;   // basis column strides (multiples of 4: 16-byte aligned columns)
@@ -651,9 +702,9 @@ __device__ void solve_one(const BatchProblem& P, int member, const BatchParams& 
     int np_now = 0;
     bool early = false;
     if (first) {
-      team_gemv_t(P, Qc(0), nullptr, 0.0, z, qlo, qhi, plo, phi, tm, L);
+      team_gemv_t<BT, OUT>(P, Qc(0), nullptr, 0.0, z, qlo, qhi, plo, phi, tm, L);
       ++matvecs;
-      ss = bcgs2(nullptr, ldp, 0, plo, phi, z, tm, L);
+      ss = bcgs2<BT, OUT>(nullptr, ldp, 0, plo, phi, z, tm, L);
       if (!bnormalize(z, plo, phi, ss, 0.0, Pc(0), 2, 0, L, tm.T > 1)) {
         // A^T q1 = 0
         nq = 1;
@@ -672,22 +723,22 @@ __device__ void solve_one(const BatchProblem& P, int member, const BatchParams& 
       const float* qprev = first ? Qc(j) : (j == l ? nullptr : Qc(j - 1));
       const double cprev = (first || j != l) ? L.pc[j] : 0.0;
       if (tm.T > 1)
-        bgemv_n<BT, true>(P, team_load_p(Pc(j), n, L), qprev, cprev, w, qlo, qhi);
+        bgemv_n<BT, OUT, true>(P, team_load_p(Pc(j), n, L), qprev, cprev, w, qlo, qhi);
       else
-        bgemv_n<BT, false>(P, Pc(j), qprev, cprev, w, qlo, qhi);
+        bgemv_n<BT, OUT, false>(P, Pc(j), qprev, cprev, w, qlo, qhi);
       if (!first) {
-        if (j == l) bupdate(Qc(0), ldq, l, qlo, qhi, w, L.rho, L);
+        if (j == l) bupdate<BT, OUT>(Qc(0), ldq, l, qlo, qhi, w, L.rho, L);
       }
       ++matvecs;
-      ss = bcgs2(Qc(0), ldq, qi, qlo, qhi, w, tm, L);
+      ss = bcgs2<BT, OUT>(Qc(0), ldq, qi, qlo, qhi, w, tm, L);
       if (!bnormalize(w, qlo, qhi, ss, prm.relative ? eps * sig : eps, Qc(qi), 1, qi, L)) break;
       const double beta = sqrt(ss);
       if (tid == 0) L.qc[qi] = beta;
       sig = fmax(sig, beta);
       // p side
-      team_gemv_t(P, Qc(qi), Pc(j), beta, z, qlo, qhi, plo, phi, tm, L);
+      team_gemv_t<BT, OUT>(P, Qc(qi), Pc(j), beta, z, qlo, qhi, plo, phi, tm, L);
       ++matvecs;
-      ss = bcgs2(Pc(0), ldp, j + 1, plo, phi, z, tm, L);
+      ss = bcgs2<BT, OUT>(Pc(0), ldp, j + 1, plo, phi, z, tm, L);
       if (!bnormalize(z, plo, phi, ss, prm.relative ? eps * sig : eps, Pc(j + 1), 2, j + 1, L, tm.T > 1)) break;
       const double alpha = sqrt(ss);
       if (tid == 0) L.pc[j + 1] = alpha;
@@ -853,7 +904,7 @@ __device__ void solve_one(const BatchProblem& P, int member, const BatchParams& 
 
 }  // namespace
 
-template <int BT>
+template <int BT, bool OUT>
 __global__ __launch_bounds__(BT) void k_batched_gk(BatchParams prm) {
   extern __shared__ double lds_raw[];
   Lds<BT>& L = *reinterpret_cast<Lds<BT>*>(lds_raw);
@@ -868,7 +919,7 @@ __global__ __launch_bounds__(BT) void k_batched_gk(BatchParams prm) {
     __syncthreads();
     if (p < 0) break;
     const BatchProblem P = prm.problems[p];
-    solve_one(P, mem, prm, L);
+    solve_one<BT, OUT>(P, mem, prm, L);
   }
 }
 
@@ -913,19 +964,28 @@ hipError_t launch_batched(const BatchParams& prm, int grid, int threads, hipStre
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (threads == 512)
-    hipLaunchKernelGGL(k_batched_gk<512>, dim3(grid), dim3(512), sizeof(Lds<512>), st, prm);
-  else
-    hipLaunchKernelGGL(k_batched_gk<1024>, dim3(grid), dim3(1024), sizeof(Lds<1024>), st, prm);
+  if (threads == 512) {
+    if (prm.outline) hipLaunchKernelGGL((k_batched_gk<512, true>), dim3(grid), dim3(512), sizeof(Lds<512>), st, prm);
+    else hipLaunchKernelGGL((k_batched_gk<512, false>), dim3(grid), dim3(512), sizeof(Lds<512>), st, prm);
+  } else {
+    if (prm.outline)
+      hipLaunchKernelGGL((k_batched_gk<1024, true>), dim3(grid), dim3(1024), sizeof(Lds<1024>), st, prm);
+    else hipLaunchKernelGGL((k_batched_gk<1024, false>), dim3(grid), dim3(1024), sizeof(Lds<1024>), st, prm);
+  }
   return hipGetLastError();
 }
 
 hipError_t batched_setup() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batched_gk<512>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Lds<512>));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batched_gk<1024>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Lds<1024>));
+  const void* kernels[4] = {reinterpret_cast<const void*>(&k_batched_gk<512, false>),
+                            reinterpret_cast<const void*>(&k_batched_gk<512, true>),
+                            reinterpret_cast<const void*>(&k_batched_gk<1024, false>),
+                            reinterpret_cast<const void*>(&k_batched_gk<1024, true>)};
+  const int lds[4] = {(int)sizeof(Lds<512>), (int)sizeof(Lds<512>), (int)sizeof(Lds<1024>), (int)sizeof(Lds<1024>)};
+  for (int i = 0; i < 4; ++i) {
+    const hipError_t e = hipFuncSetAttribute(kernels[i], hipFuncAttributeMaxDynamicSharedMemorySize, lds[i]);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace gkb
