@@ -58,7 +58,11 @@ void gkb_batch_default_options(gkb_batch_options* opt);
 size_t gkb_batched_workspace_size(int batch, const gkb_matrix* As, const int* r, const int* k);
 
 /* Validate, upload the problem table into the workspace, capture the launch
-   into a hipGraph.  The plan keeps the workspace and output pointers. */
+   into a hipGraph.  The plan keeps the workspace and output pointers.  The
+   persistent kernel comes in two compiled forms, chosen here from the
+   batch: the row products and Gram-Schmidt kernels out of line (their own
+   registers, more loads in flight) when the problems average at least 2 MB
+   of A, inline otherwise; results are the same either way. */
 gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
                                    int max_restarts, const gkb_batch_options* opt, void* workspace,
                                    size_t ws_bytes, double* sigma, float* U, float* V, void* stream,
