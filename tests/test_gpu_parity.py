@@ -118,6 +118,32 @@ def test_rank_one_and_zero():
     assert rank == 0
 
 
+@pytest.mark.parametrize("shape", [(7, 1, 1), (1, 9, 1), (1, 1, 1), (2, 2, 2), (3, 2, 2)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_degenerate_shapes(shape, dtype):
+    """A single row or column, a 1 x 1 matrix and k = min(m, n) on 2 x 2 and 3 x 2:
+    the recurrence ends after one or two steps (by breakdown or at k = min(m, n))
+    and the triplets are exact; the same status and matvec count as the oracle."""
+    import torch
+    device()
+    m, n, r = shape
+    banner(f"degenerate shape {shape} {dtype}")
+    rng = np.random.default_rng(m * 10 + n)
+    A = rng.standard_normal((m, n))
+    q = inputs.start_vector(m, seed=4)
+    ref = gk.partial_svd(A, r, r, 1e-12, 0, q)
+    sigma, U, V, status, stats = run_gpu(A, r, r, 1e-12 if dtype == "f64" else 1e-6, 0, q,
+                                         dtype=None if dtype == "f64" else torch.float32)
+    assert status == ref["status"] == 0
+    sl = np.linalg.svd(A, compute_uv=False)[:r]
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    assert np.max(np.abs(sigma - sl)) <= tol * sl[0]
+    r1, r2 = checks.triplet_residuals(A, sigma, U, V)
+    assert max(r1.max(), r2.max()) <= 10 * tol * sl[0]
+    if dtype == "f64":
+        assert stats["matvecs"] == ref["matvecs"]
+
+
 def test_rank_deficient_returns_exact_triplets():
     device()
     banner("rank-3 product with r=5")
