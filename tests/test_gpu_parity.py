@@ -144,6 +144,42 @@ def test_degenerate_shapes(shape, dtype):
         assert stats["matvecs"] == ref["matvecs"]
 
 
+@pytest.mark.parametrize("shape", [(9, 4, 2, 4), (1, 8, 1, 1), (4, 4, 4, 4)])
+def test_degenerate_shapes_one_sweep(shape):
+    """The one-sweep step (float32 A, n a multiple of 4) at k = min(m, n): exact
+    triplets, the oracle's status."""
+    import torch
+    device()
+    m, n, r, k = shape
+    banner(f"degenerate shape one-sweep {shape}")
+    rng = np.random.default_rng(m * 10 + n + 1)
+    A = rng.standard_normal((m, n)).astype(np.float32).astype(np.float64)
+    q = inputs.start_vector(m, seed=4)
+    ref = gk.partial_svd(A, r, k, 1e-6, 0, q, eps_break=1e-6)
+    sigma, U, V, status, stats = run_gpu(A, r, k, 1e-6, 0, q, dtype=torch.float32, one_pass=True)
+    assert status == ref["status"] == 0
+    sl = np.linalg.svd(A, compute_uv=False)[:r]
+    assert np.max(np.abs(sigma - sl)) <= 1e-6 * sl[0]
+    r1, r2 = checks.triplet_residuals(A, sigma, U, V)
+    assert max(r1.max(), r2.max()) <= 1e-5 * sl[0]
+
+
+@pytest.mark.parametrize("shape", [(7, 1), (1, 9), (1, 1)])
+def test_rank_degenerate_shapes(shape):
+    """Numerical rank of a single row, a single column and a 1 x 1 matrix (1), and
+    of the zero matrix of that shape (0)."""
+    device()
+    m, n = shape
+    banner(f"rank of degenerate shape {shape}")
+    A = np.random.default_rng(m + 2 * n).standard_normal((m, n))
+    q = to_dev(inputs.start_vector(m, seed=1))
+    rank, rank_s, sig, status, stats = gkb.gkb_numerical_rank(to_dev(A), 1e-6, q1=q)
+    assert rank == rank_s == 1
+    assert abs(sig[0] - np.linalg.norm(A)) <= 1e-13 * np.linalg.norm(A)
+    rank, rank_s, sig, status, stats = gkb.gkb_numerical_rank(to_dev(np.zeros((m, n))), 1e-6, q1=q)
+    assert rank == 0
+
+
 def test_rank_deficient_returns_exact_triplets():
     device()
     banner("rank-3 product with r=5")
