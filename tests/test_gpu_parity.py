@@ -119,7 +119,7 @@ def test_rank_one_and_zero():
 
 
 @pytest.mark.parametrize("shape", [(7, 1, 1), (1, 9, 1), (1, 1, 1), (2, 2, 2), (3, 2, 2)])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_degenerate_shapes(shape, dtype):
     """A single row or column, a 1 x 1 matrix and k = min(m, n) on 2 x 2 and 3 x 2:
     the recurrence ends after one or two steps (by breakdown or at k = min(m, n))
@@ -132,14 +132,29 @@ def test_degenerate_shapes(shape, dtype):
     A = rng.standard_normal((m, n))
     q = inputs.start_vector(m, seed=4)
     ref = gk.partial_svd(A, r, r, 1e-12, 0, q)
-    sigma, U, V, status, stats = run_gpu(A, r, r, 1e-12 if dtype == "f64" else 1e-6, 0, q,
-                                         dtype=None if dtype == "f64" else torch.float32)
+    if dtype == "bf16":   # bfloat16 cycles, float32 Rayleigh-Ritz refinement
+        A32 = to_dev(A).to(torch.float32)
+        sigma, U, V, status, stats = run_gpu(A, r, r, 1e-6, 0, q, dtype=torch.bfloat16, refine=A32)
+        assert stats["refined"] == 1
+    else:
+        sigma, U, V, status, stats = run_gpu(A, r, r, 1e-12 if dtype == "f64" else 1e-6, 0, q,
+                                             dtype=None if dtype == "f64" else torch.float32)
     assert status == ref["status"] == 0
-    sl = np.linalg.svd(A, compute_uv=False)[:r]
+    A32 = A.astype(np.float32).astype(np.float64)
+    sl = np.linalg.svd(A32 if dtype != "f64" else A, compute_uv=False)[:r]
     tol = 1e-13 if dtype == "f64" else 1e-6
-    assert np.max(np.abs(sigma - sl)) <= tol * sl[0]
-    r1, r2 = checks.triplet_residuals(A, sigma, U, V)
-    assert max(r1.max(), r2.max()) <= 10 * tol * sl[0]
+    r1, r2 = checks.triplet_residuals(A32 if dtype != "f64" else A, sigma, U, V)
+    if dtype == "bf16":
+        # the refinement works inside the bfloat16 Krylov subspace: sigma within
+        # ||A16 - A32||_2^2 / sigma_1 + sqrt(n) u32 ||A||_F, A^T u - sigma v within ||A16 - A32||_2
+        A16 = torch.from_numpy(A32).to(torch.bfloat16).to(torch.float64).numpy()
+        dA = np.linalg.norm(A16 - A32, 2)
+        bound = dA ** 2 / sl[0] + np.sqrt(max(m, n)) * 2.0 ** -24 * np.linalg.norm(A32)
+        assert np.max(np.abs(sigma - sl)) <= 2 * bound + 1e-7 * sl[0]
+        assert r1.max() <= 1e-5 * sl[0] and r2.max() <= 2 * dA + 1e-5 * sl[0]
+    else:
+        assert np.max(np.abs(sigma - sl)) <= tol * sl[0]
+        assert max(r1.max(), r2.max()) <= 10 * tol * sl[0]
     if dtype == "f64":
         assert stats["matvecs"] == ref["matvecs"]
 
