@@ -79,3 +79,110 @@ def test_planted_mistake_is_caught(modname, old, new, pin):
     except (ValueError, FloatingPointError, IndexError, np.linalg.LinAlgError, ZeroDivisionError):
         held = False
     assert not held
+
+
+# ------------------------------------------- in-cycle test, refinement, metrics
+def _holds(fn):
+    try:
+        fn()
+        return True
+    except AssertionError:
+        return False
+
+
+def _first_cycle_stop_pin(g, every=1):
+    from tests.test_oracle_checks import check_against_brute_force
+    s = np.geomspace(1.0, 1e-8, 200)
+    A, _, _ = inputs.svd_matrix(400, 200, s, seed=41)
+    return _holds(lambda: check_against_brute_force(A, inputs.start_vector(400, seed=42), s, 5, 60, 1e-10, every,
+                                                    solver=g))
+
+
+def _restart_stop_pin(g):
+    from tests.test_oracle_checks import check_against_brute_force
+    s = inputs.decade_spectrum(1000)
+    A, _, _ = inputs.svd_matrix(2000, 1000, s, seed=0)
+    return _holds(lambda: check_against_brute_force(A, inputs.start_vector(2000, seed=1), s, 10, 30, 1e-10, 1,
+                                                    solver=g))
+
+
+def _sharp_pin(g, case):
+    from tests.test_oracle_checks import sharp_stop_check
+    if case == "first":
+        s = np.geomspace(1.0, 1e-8, 200)
+        A, Q1, Q2 = inputs.svd_matrix(400, 200, s, seed=41)
+        data, r, k, cyc = (A, Q1, Q2, s, inputs.start_vector(400, seed=42)), 5, 60, 0
+    else:
+        s = inputs.decade_spectrum(1000)
+        A, Q1, Q2 = inputs.svd_matrix(2000, 1000, s, seed=0)
+        data, r, k, cyc = (A, Q1, Q2, s, inputs.start_vector(2000, seed=1)), 10, 30, 2
+    return _holds(lambda: sharp_stop_check(data, r, k, cyc, solver=g))
+
+
+def _np_equal_r_pin(g):
+    from tests.test_oracle_checks import check_against_brute_force
+    s = np.concatenate([[4.0, 3.0, 2.0], np.full(57, 1e-9)])
+    A, _, _ = inputs.svd_matrix(90, 60, s, seed=5)
+
+    def run():
+        out, np_ = check_against_brute_force(A, inputs.start_vector(90, seed=6), s, 3, 20, 1e-8, 1, solver=g)
+        assert np_ == 3 and out["checks"] == 1
+    return _holds(run)
+
+
+def _refine_exact_pin(b):
+    import tests.test_oracle_checks as t
+    orig = t.bf16
+    t.bf16 = b
+    try:
+        return _holds(t.test_refined_on_bfloat16_exact_matrix_gives_exact_triplets) and \
+            _holds(t.test_refined_dimension_is_as_stated)
+    finally:
+        t.bf16 = orig
+
+
+def _err_res_pin(c):
+    import tests.test_oracle_checks as t
+    orig = t.checks
+    t.checks = c
+    try:
+        return _holds(t.test_err_res_is_the_eckart_young_tail)
+    finally:
+        t.checks = orig
+
+
+def test_new_pins_hold_for_real_oracle():
+    from oracle import bf16
+    assert _first_cycle_stop_pin(gk) and _first_cycle_stop_pin(gk, 3) and _restart_stop_pin(gk)
+    assert _np_equal_r_pin(gk) and _refine_exact_pin(bf16) and _err_res_pin(checks)
+    assert _sharp_pin(gk, "first") and _sharp_pin(gk, "restart")
+
+
+STOP_MUTATIONS = [
+    # the in-cycle test fed the residual coefficient of the previous step
+    ("oracle.gk", "if stop(H, alpha):", "if stop(H, alphas[-2]):", lambda g: _sharp_pin(g, "first")),
+    ("oracle.gk", "if stop(Hp, alpha):", "if stop(Hp, alpha_prev):", lambda g: _sharp_pin(g, "restart")),
+    # an early stop that returns the previous step's residual coefficient
+    ("oracle.gk", "H, alpha, P[:, np_].copy(), None,", "H, alphas[-2], P[:, np_].copy(), None,",
+     _first_cycle_stop_pin),
+    # the schedule off by one, in either direction
+    ("oracle.gk", "np_ % self.every == 0", "(np_ + 1) % self.every == 0",
+     lambda g: _first_cycle_stop_pin(g, 3)),
+    ("oracle.gk", "np_ >= self.r and", "np_ > self.r and", _np_equal_r_pin),
+    # refinement subspace: wrong default size, wrong Ritz vectors
+    ("oracle.bf16", "else 2 * r", "else r", _refine_exact_pin),
+    ("oracle.bf16", "Vd = fac.P @ Y[:, :d]", "Vd = fac.P[:, :d]", _refine_exact_pin),
+    # the residual metric without the singular values
+    ("oracle.checks", "np.linalg.norm(A - (U * sigma[None, :]) @ V.T)", "np.linalg.norm(A - U @ V.T)",
+     _err_res_pin),
+]
+
+
+@pytest.mark.parametrize("modname,old,new,pin", STOP_MUTATIONS, ids=[m[2][:40] for m in STOP_MUTATIONS])
+def test_planted_stop_refine_metric_mistake_is_caught(modname, old, new, pin):
+    m = mutant(modname, old, new)
+    try:
+        held = pin(m)
+    except (ValueError, FloatingPointError, IndexError, np.linalg.LinAlgError, ZeroDivisionError):
+        held = False
+    assert not held
