@@ -144,6 +144,39 @@ def ritz_gemms(gkb, torch, dev, stream, reps):
     return out
 
 
+def headline_accuracy(sigma, Ut, Vt, check_every):
+    """Per-triplet singular-value error of the timed solve against the float64
+    oracle's solve of the same matrix with the same schedule (stored in
+    tests/golden/c2_oracle_top50.json by an oracle-only script), and the
+    distances of the singular vectors estimated through the oracle's stored
+    32-column Gaussian sketches."""
+    ref_path = os.path.join(ROOT, "tests", "golden", "c2_oracle_top50.json")
+    if not os.path.exists(ref_path):
+        return None
+    from paper_2104_10785_amd import inputs
+    ref_all = json.load(open(ref_path))
+    ref = ref_all["check_every_10"] if check_every == 10 else (ref_all if check_every == 0 else None)
+    if ref is None:
+        return None
+    want = np.array(ref["sigma"])
+    err = np.abs(sigma - want)
+    U = Ut.double().cpu().numpy().T
+    V = Vt.double().cpu().numpy().T
+    om_u = inputs.sketch_matrix(M, 32, 101, dtype=np.float64) / np.sqrt(32)
+    om_v = inputs.sketch_matrix(N, 32, 102, dtype=np.float64) / np.sqrt(32)
+    su, sv = om_u.T @ U, om_v.T @ V
+    ru, rv = np.array(ref["U_sketch"]), np.array(ref["V_sketch"])
+    sign = np.sign(np.sum(su * ru, axis=0) + np.sum(sv * rv, axis=0))
+    sign[sign == 0] = 1.0
+    du = np.linalg.norm(su - ru * sign[None, :], axis=0)
+    dv = np.linalg.norm(sv - rv * sign[None, :], axis=0)
+    return {"oracle_schedule": f"check_every={check_every}", "sigma_abs_err_max": float(err.max()),
+            "sigma_rel_err_max": float(np.max(err / want)), "sigma_rel_err_median": float(np.median(err / want)),
+            "sigma_rel_err_per_triplet": [float(x) for x in err / want],
+            "u_dist_max_sketch": float(du.max()), "v_dist_max_sketch": float(dv.max()),
+            "oracle_matvecs": ref["matvecs"], "oracle_checks": ref["checks"]}
+
+
 def device_info(torch):
     p = torch.cuda.get_device_properties(0)
     return {"name": p.name, "arch": getattr(p, "gcnArchName", ""), "cus": p.multi_processor_count,
@@ -173,39 +206,39 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(A32, q, budget_s=20.0):
-    """Time the float64 oracle on the host: its first-cycle Golub-Kahan steps on
-    the full matrix (exact float64 upcast), as many as fit in about budget_s
-    seconds, scaled to a full solve by the oracle's own matvec count for this
-    workload (tests/golden/c2_oracle_top50.json, written by oracle code)."""
+def cpu_baseline(A32, q, warmup=2, reps=5, check_every=CHECK_EVERY):
+    """Time the float64 oracle on the host, like for like with the GPU solve:
+    full oracle.gk.partial_svd solves of the exact float64 upcast of the same
+    matrix, with the same start vector, r, k, tol, restart limit, breakdown
+    threshold and in-cycle test schedule; `warmup` untimed solves, then `reps`
+    timed ones (mean and median wall time)."""
     from oracle import gk
     threads = blas_threads()
     t0 = time.time()
     A = A32.astype(np.float64)
     t_up = time.time() - t0
-    eps = gk.BreakThreshold(1e-6, True)
-    # calibrate on 2 steps, then run a bounded number
-    t1 = time.time()
-    gk.first_cycle(A, q, 2, eps, 2)
-    per2 = time.time() - t1
-    steps = int(max(2, min(60, budget_s / max(per2 / 2, 1e-3))))
-    t2 = time.time()
-    fac = gk.first_cycle(A, q, steps, gk.BreakThreshold(1e-6, True), 2)
-    dt = time.time() - t2
-    per_matvec = dt / fac.matvecs
-    ref_path = os.path.join(ROOT, "tests", "golden", "c2_oracle_top50.json")
-    if os.path.exists(ref_path):
-        ref = json.load(open(ref_path))
-        mv_full, nconv = ref["matvecs"], ref["nconv"]
-    else:
-        mv_full, nconv = 1 + 2 * K, R
-    est = per_matvec * mv_full
+
+    def solve():
+        return gk.partial_svd(A, R, K, TOL, RESTARTS, q, eps_break=1e-6, check_every=check_every)
+
+    for _ in range(warmup):
+        solve()
+    times = []
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        ref = solve()
+        times.append(time.perf_counter() - t1)
     del A
-    return {"value": nconv / est, "unit": "triplets/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
-            "sample": f"oracle first-cycle Golub-Kahan steps on the full 50000x20000 float64 matrix: "
-                      f"{steps} steps ({fac.matvecs} matvecs) in {dt:.2f} s, scaled to the oracle's "
-                      f"{mv_full} matvecs for the full solve (CGS2 cost grows with the step, so this "
-                      f"underestimates the oracle's time); upcast took {t_up:.1f} s"}
+    mean_s, med_s = float(np.mean(times)), float(np.median(times))
+    return {"value": ref["nconv"] / mean_s, "unit": "triplets/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "s_per_solve_mean": mean_s, "s_per_solve_median": med_s, "s_per_solve": times,
+            "triplets_per_s_median": ref["nconv"] / med_s, "nconv": ref["nconv"], "matvecs": ref["matvecs"],
+            "checks": ref["checks"], "status": ref["status"],
+            "sample": f"{reps} full oracle solves (after {warmup} untimed) of the 50000x20000 workload on the "
+                      f"exact float64 upcast of the same float32 matrix: top {R}, k {K}, tol {TOL}, in-cycle "
+                      f"test every {check_every}, same start vector; numpy/BLAS on {threads} threads; the "
+                      f"upcast ({t_up:.1f} s) is outside the timing"}
 
 
 def bf16_leg(gkb, torch, Ad, qd, stream, steps, one_pass=True):
@@ -328,6 +361,110 @@ def batched_leg(gkb, inputs, torch, dev, stream):
     return out
 
 
+C1_M, C1_N, C1_R, C1_K, C1_TOL, C1_RESTARTS, C1_TAU, C1_RANK = 2000, 1000, 10, 30, 1e-10, 50, 10 ** -6.005, 600
+
+
+def wall_times(fn, warmup, reps, torch=None):
+    """warmup untimed calls, then reps timed ones (ms each; the stream is
+    synchronised inside each timed call when torch is given)."""
+    for _ in range(warmup):
+        out = fn()
+    if torch is not None:
+        torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        if torch is not None:
+            torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1000.0)
+    return ms, out
+
+
+def c1_leg(gkb, inputs, torch, dev, stream, warmup=2, reps=5, oracle=True):
+    """The CPU-sized float64 workload: A = Q1 diag(10^(-i/100)) Q2^T, 2000 x 1000
+    (16 MB, resident in the GPU's caches), top 10 triplets, Krylov dimension
+    30, tol 1e-10, and the numerical rank at tau = 10^-6.005 (rank 600; the
+    literal 1e-6 s_1 lands on s_601).  GPU solve and rank: warmup untimed, reps
+    timed (mean and median).  The float64 oracle runs the same solve and rank on
+    the host with the same inputs and schedule."""
+    from oracle import gk
+    from oracle import rank as orank
+    s = inputs.decade_spectrum(1000)
+    A, _, _ = inputs.svd_matrix(C1_M, C1_N, s, seed=0)
+    q = inputs.start_vector(C1_M, seed=1)
+    Ad = torch.from_numpy(A).to(dev)
+    qd = torch.from_numpy(q).to(dev)
+    ws = torch.empty(gkb.gkb_workspace_size(Ad, C1_R, C1_K), dtype=torch.uint8, device=dev)
+    rws = torch.empty(gkb.gkb_rank_workspace_size(Ad, 0), dtype=torch.uint8, device=dev)
+    solve = lambda: gkb.gkb_partial_svd(Ad, C1_R, C1_K, C1_TOL, C1_RESTARTS, q1=qd, workspace=ws, stream=stream)
+    rank = lambda: gkb.gkb_numerical_rank(Ad, C1_TAU, q1=qd, workspace=rws, stream=stream)
+    ms, (sig, _, _, status, st) = wall_times(solve, warmup, reps, torch)
+    ph = gkb.gkb_partial_svd(Ad, C1_R, C1_K, C1_TOL, C1_RESTARTS, q1=qd, workspace=ws, stream=stream,
+                             phase_timing=True)[4]
+    ms_r, (rk, rk_s, rsig, _, rst) = wall_times(rank, warmup, reps, torch)
+    steps = (st["matvecs"] - 1) / 2
+    out = {"workload": "Q1 diag(10^(-i/100)) Q2^T 2000x1000 f64; top 10, k 30, tol 1e-10; rank at tau 10^-6.005",
+           "solve_ms_mean": float(np.mean(ms)), "solve_ms_median": float(np.median(ms)),
+           "triplets_per_s": st["nconv"] / (np.mean(ms) / 1000.0), "status": status, "matvecs": st["matvecs"],
+           "restarts": st["restarts"], "us_per_step": 1000.0 * float(np.mean(ms)) / steps,
+           "sigma_rel_err_vs_spectrum_max": float(np.max(np.abs(sig - s[:C1_R]) / s[:C1_R])),
+           "phases_ms": {k2: ph[k2] for k2 in ("ms_matvec", "ms_reorth", "ms_sync", "ms_ritz", "ms_other")},
+           "ms_host_svd": st["ms_host"],
+           "rank": rk, "rank_sturm": rk_s, "rank_expected": C1_RANK, "rank_steps": int(rsig.size),
+           "rank_ms_mean": float(np.mean(ms_r)), "rank_ms_median": float(np.median(ms_r)),
+           "rank_us_per_step": 1000.0 * float(np.mean(ms_r)) / max(1, rsig.size),
+           "warmup": warmup, "reps": reps}
+    if oracle:
+        ms_o, ref = wall_times(lambda: gk.partial_svd(A, C1_R, C1_K, C1_TOL, C1_RESTARTS, q), warmup, reps)
+        ms_or, rref = wall_times(lambda: orank.numerical_rank(A, C1_TAU, q), 1, 2)
+        out["oracle"] = {"solve_ms_mean": float(np.mean(ms_o)), "solve_ms_median": float(np.median(ms_o)),
+                         "triplets_per_s": ref["nconv"] / (np.mean(ms_o) / 1000.0), "matvecs": ref["matvecs"],
+                         "rank": rref["rank"], "rank_ms_mean": float(np.mean(ms_or)), "rank_reps": 2,
+                         "cores": blas_threads(), "cpu": cpu_model()}
+        out["sigma_rel_err_vs_oracle_max"] = float(np.max(np.abs(sig - ref["sigma"]) / ref["sigma"]))
+    del Ad, ws, rws
+    return out
+
+
+def f64_leg(gkb, torch, Ad32, qd, stream, reps=3):
+    """The 50000 x 20000 matrix in float64 (the exact upcast of the float32
+    matrix, 8.0 GB): the two products' HBM rate and the float64 partial SVD
+    (two-product step, float64 bases) against the stored float64 oracle run on
+    the same matrix."""
+    Ad = Ad32.double()
+    torch.cuda.synchronize()
+    xn = torch.randn(N, dtype=torch.float64, device=Ad.device)
+    xm = torch.randn(M, dtype=torch.float64, device=Ad.device)
+    yn = torch.empty(M, dtype=torch.float64, device=Ad.device)
+    ym = torch.empty(N, dtype=torch.float64, device=Ad.device)
+    mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=Ad.device)
+    ms_n = time_kernel(lambda: gkb.gkb_matvec(Ad, xn, 0, y=yn, stream=stream), 20, stream)
+    ms_t = time_kernel(lambda: gkb.gkb_matvec(Ad, xm, 1, y=ym, workspace=mws, stream=stream), 20, stream)
+    b_n = M * N * 8 + N * 8 + M * 8
+    b_t = M * N * 8 + M * 8 + N * 8
+    ws = torch.empty(gkb.gkb_workspace_size(Ad, R, K), dtype=torch.uint8, device=Ad.device)
+    solve = lambda: gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
+                                        check_every=CHECK_EVERY)
+    ms, (sig, Ut, Vt, status, st) = wall_times(solve, 1, reps, torch)
+    out = {"workload": "low-rank(200, 0.95^i)+noise(1e-6) 50000x20000 f64 (upcast of the f32 matrix); "
+                       "top 50, k 120, tol 1e-6, checks every 10",
+           "gemv_n_ms": ms_n, "gemv_n_GBps": b_n / (ms_n * 1e-3) / 1e9, "gemv_n_frac": b_n / (ms_n * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "gemv_t_ms": ms_t, "gemv_t_GBps": b_t / (ms_t * 1e-3) / 1e9, "gemv_t_frac": b_t / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "solve_ms_mean": float(np.mean(ms)), "solve_ms_median": float(np.median(ms)),
+           "triplets_per_s": st["nconv"] / (np.mean(ms) / 1000.0), "status": status, "matvecs": st["matvecs"],
+           "checks": st["checks"], "reps": reps}
+    acc = headline_accuracy(sig, Ut, Vt, CHECK_EVERY)
+    if acc:
+        out["sigma_rel_err_vs_f64_oracle_max"] = acc["sigma_rel_err_max"]
+        out["u_dist_max_sketch"] = acc["u_dist_max_sketch"]
+        out["v_dist_max_sketch"] = acc["v_dist_max_sketch"]
+        out["oracle_matvecs"] = acc["oracle_matvecs"]
+    del Ad, ws, mws
+    torch.cuda.empty_cache()
+    return out
+
+
 SPARSE_M, SPARSE_N, SPARSE_NNZ, SPARSE_SEED, SPARSE_QSEED = 1000000, 200000, 50000000, 7, 8
 SPARSE_R, SPARSE_K, SPARSE_EVERY = 20, 60, 5
 
@@ -426,11 +563,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-warmup", type=int, default=2, help="untimed oracle solves before the CPU timing")
+    ap.add_argument("--cpu-reps", type=int, default=5, help="timed full oracle solves (CPU baseline)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
     ap.add_argument("--two-pass", action="store_true",
                     help="time the two-product step (A read twice per step) instead of the one-sweep step")
-    ap.add_argument("--legs", default="bf16,rank,batched,learned,sparse,rsgd",
+    ap.add_argument("--legs", default="c1,f64,bf16,rank,batched,learned,sparse,rsgd",
                     help="extra legs after the main timing (comma list; empty for none)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the two matvec kernels and a 1 GiB copy (for counter runs)")
@@ -482,6 +621,21 @@ def main():
     ms_per_step = dt * 1000.0 / args.steps
     value = nconv / dt
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, stats={stats}")
+
+    # accuracy of the timed solve against the stored float64 oracle (same schedule)
+    accuracy = headline_accuracy(sigma, Ut, Vt, args.check_every)
+
+    # one more solve with HIP events at every phase boundary (not timed above)
+    ph = gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
+                             check_every=args.check_every, one_pass=one_pass, phase_timing=True)[4]
+    phase_keys = ("ms_matvec", "ms_reorth", "ms_sync", "ms_ritz", "ms_other")
+    phases = {k2: ph[k2] for k2 in phase_keys}
+    phases["sum"] = sum(phases.values())
+    phases["ms_total"] = ph["ms_total"]
+    phases["bytes_A"] = ph["bytes_A"]
+    phases["A_GBps_over_matvec_phase"] = ph["bytes_A"] / (ph["ms_matvec"] * 1e-3) / 1e9
+    phases["per_step_us"] = {k2: 1000.0 * ph[k2] / max(1, ph["krylov_dim"]) for k2 in ("ms_matvec", "ms_reorth")}
+    log(f"phases: {phases}")
 
     # the same solve with the test only at the end of the cycle (fixed k = 120)
     t1 = time.perf_counter()
@@ -539,12 +693,16 @@ def main():
             legs["sparse"] = sparse_leg(gkb, inputs, torch, dev, stream, args.steps)
         elif leg == "rsgd":
             legs["rsgd"] = rsgd_leg(gkb, inputs, torch, dev, stream)
+        elif leg == "c1":
+            legs["c1_f64"] = c1_leg(gkb, inputs, torch, dev, stream, oracle=not args.no_cpu_baseline)
+        elif leg == "f64":
+            legs["f64_large"] = f64_leg(gkb, torch, Ad, qd, stream)
         log(f"leg {leg} done: {json.dumps(legs)[-300:]}")
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(A32, q)
+        log(f"timing the CPU oracle: {args.cpu_warmup} + {args.cpu_reps} full solves")
+        cpu = cpu_baseline(A32, q, args.cpu_warmup, args.cpu_reps, args.check_every)
         log(f"cpu baseline: {cpu}")
 
     line = {
@@ -567,6 +725,8 @@ def main():
                   "recomputed_columns": stats["refreshes"],
                   "krylov_dim": stats["krylov_dim"], "checks": stats["checks"],
                   "ms_host_svd": stats["ms_host"], "sigma1": float(sigma[0]), "sigma50": float(sigma[-1])},
+        "phases": phases,
+        "accuracy_vs_f64_oracle": accuracy,
         "fixed_k_solve": {"ms": fixed_ms, "triplets_per_s": fixed[4]["nconv"] / (fixed_ms / 1000.0),
                           "matvecs": fixed[4]["matvecs"]},
         ("two_product_solve" if one_pass else "one_sweep_solve"): {

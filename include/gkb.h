@@ -108,6 +108,12 @@ typedef struct {
                        /* U, V are still float32.  Same statuses and stats     */
                        /* (matvecs counts products, two per sweep).            */
                        /* gkb_partial_svd and gkb_numerical_rank.              */
+  int phase_timing;    /* 1: time the device phases with HIP events recorded   */
+                       /* on `stream` at every phase boundary (a few events    */
+                       /* per Golub-Kahan step, read at each host              */
+                       /* synchronisation) and fill the ms_matvec ...          */
+                       /* ms_other fields of gkb_stats; 0 (default): no events */
+                       /* (those fields are then 0)                            */
 } gkb_options;
 
 typedef struct {
@@ -128,6 +134,22 @@ typedef struct {
   int refreshes;       /* one_pass: A^T q columns recomputed by a direct sweep */
                        /* because their error bound grew too large (counted    */
                        /* in matvecs as well)                                  */
+  /* Device time per phase (opt.phase_timing = 1), from consecutive events on  */
+  /* the stream, so the five add up to the span from the start vector to the  */
+  /* last Ritz vector (ms_total less the host's launch time before the first  */
+  /* and after the last event).                                               */
+  double ms_matvec;    /* products with A and A^T (the one-sweep pair, the     */
+                       /* recovery of A^T q and any direct recomputation)      */
+  double ms_reorth;    /* Gram-Schmidt passes, norms, normalisation            */
+  double ms_sync;      /* coefficient read-back and the device idle while the  */
+                       /* host runs the small SVDs and uploads X, Y            */
+  double ms_ritz;      /* restart and Ritz-vector GEMMs (and the bfloat16      */
+                       /* refinement)                                          */
+  double ms_other;     /* start vector and cycle set-up                        */
+  double bytes_A;      /* algorithmic bytes of A streamed: passes over A (two  */
+                       /* per step, one per sweep with one_pass, plus          */
+                       /* recomputed columns and the start) x the bytes of A   */
+                       /* (nonzero values and column indices for sparse A)     */
 } gkb_stats;
 
 /* Fill *opt with the defaults above. */

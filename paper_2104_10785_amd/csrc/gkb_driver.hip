@@ -149,6 +149,64 @@ double now_ms() {
       .count();
 }
 
+// Device time per phase from HIP events recorded on the solver's stream at each
+// phase boundary: the interval between two consecutive events belongs to the
+// phase the first one opened.  Completed intervals are read after every host
+// synchronisation and their events reused, so a solve holds a few dozen events.
+enum Phase { PH_MATVEC = 0, PH_REORTH, PH_SYNC, PH_RITZ, PH_OTHER, PH_COUNT };
+
+struct PhaseTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev, spare;
+  std::vector<int> ph;
+  double ms[PH_COUNT] = {0, 0, 0, 0, 0};
+
+  hipError_t mark(int phase, hipStream_t st) {
+    if (!on || (!ph.empty() && ph.back() == phase)) return hipSuccess;
+    hipEvent_t e;
+    if (!spare.empty()) {
+      e = spare.back();
+      spare.pop_back();
+    } else {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+    }
+    hipError_t r = hipEventRecord(e, st);
+    if (r != hipSuccess) {
+      spare.push_back(e);
+      return r;
+    }
+    ev.push_back(e);
+    ph.push_back(phase);
+    return hipSuccess;
+  }
+  // Only after the stream has been synchronised: every recorded event is complete.
+  hipError_t collect() {
+    if (!on || ev.size() < 2) return hipSuccess;
+    for (size_t i = 0; i + 1 < ev.size(); ++i) {
+      float t = 0.0f;
+      hipError_t r = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      if (r != hipSuccess) return r;
+      ms[ph[i]] += t;
+      spare.push_back(ev[i]);
+    }
+    ev.erase(ev.begin(), ev.end() - 1);
+    ph.erase(ph.begin(), ph.end() - 1);
+    return hipSuccess;
+  }
+  void fill(gkb_stats* stats) const {
+    stats->ms_matvec = ms[PH_MATVEC];
+    stats->ms_reorth = ms[PH_REORTH];
+    stats->ms_sync = ms[PH_SYNC];
+    stats->ms_ritz = ms[PH_RITZ];
+    stats->ms_other = ms[PH_OTHER];
+  }
+  ~PhaseTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+  }
+};
+
 // Projected matrix of one cycle, as read back from the device.
 struct Proj {
   int nq = 0, np = 0;
@@ -197,6 +255,16 @@ struct Solver {
   int* refresh() { return reinterpret_cast<int*>(ws + L.refresh); }
   double eps0() const { return std::ldexp(1.0, -52) * std::sqrt((double)(A.m + A.n)); }
   bool onepass = false;  // dense float32 A, float64 bases, one sweep of A per step
+  PhaseTimer pt;         // per-phase device time (opt.phase_timing)
+  int64_t a_passes = 0;  // full passes over A launched (a skipped direct sweep not counted)
+
+  hipError_t mark(int phase) { return pt.mark(phase, st); }
+  // algorithmic bytes of one pass over A: every element once (dense), every
+  // stored value and its column index once (sparse)
+  double bytes_per_pass() const {
+    if (sp) return (double)sp->nnz * (sizeof(float) + sizeof(int32_t));
+    return (double)A.m * (double)A.n * elem_bytes((gkb_dtype)A.dtype);
+  }
 
   // w = A p - coef[cidx] qprev and z = A^T q - coef[cidx] pprev (dense or sparse A)
   hipError_t prod_n(const TB* p, const TB* qprev, const double* coef, int cidx, double* out) {
@@ -245,20 +313,25 @@ struct Solver {
   gkb_status read_back(int ncoef, std::vector<double>& qc, std::vector<double>& pc, int* fl) {
     qc.assign(ncoef, 0.0);
     pc.assign(ncoef, 0.0);
+    GKB_HIP(mark(PH_SYNC));
     GKB_HIP(hipMemcpyAsync(qc.data(), qcoef(), ncoef * sizeof(double), hipMemcpyDeviceToHost, st));
     GKB_HIP(hipMemcpyAsync(pc.data(), pcoef(), ncoef * sizeof(double), hipMemcpyDeviceToHost, st));
     GKB_HIP(hipMemcpyAsync(fl, flag(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     GKB_HIP(hipStreamSynchronize(st));
+    GKB_HIP(pt.collect());
     return GKB_OK;
   }
 
   // Start: Q[:,0] = q/||q||, z = A^T q_1, P[:,0] = z/||z||.
   gkb_status start(const double* q1) {
     nsig = 0;
+    GKB_HIP(mark(PH_OTHER));
     GKB_HIP(gkb::launch_init_cycle(flag(), sig(), 0.0, st));
     GKB_HIP(hipMemcpyAsync(w(), q1, (size_t)A.m * sizeof(double), hipMemcpyDeviceToDevice, st));
     GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.m, w(), h(), normpart(), flag(), st));
     GKB_HIP(normalize(w(), A.m, Qc(0), qcoef(), 0, 1, 0, false));
+    GKB_HIP(mark(PH_MATVEC));
+    ++a_passes;
     if (onepass) {
       // z = A^T q_1 with float64 sums, kept as the first column of A^T Q
       if constexpr (std::is_same<TB, double>::value) {
@@ -270,6 +343,7 @@ struct Solver {
     } else {
       GKB_HIP(prod_t(Qc(0), nullptr, nullptr, 0, z()));
     }
+    GKB_HIP(mark(PH_REORTH));
     GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.n, z(), h(), normpart(), flag(), st));
     GKB_HIP(normalize(z(), A.n, Pc(0), pcoef(), 1, 2, 0, false));
     if (onepass) GKB_HIP(gkb::launch_err_set(err(cur), 0, sig() + nsig, eps0(), flag(), st));
@@ -280,12 +354,35 @@ struct Solver {
   //   w = A p_s - alpha_s q_s -> CGS2 vs Q[0..s] -> q_{s+1}, beta
   //   z = A^T q_{s+1} - beta p_s -> CGS2 vs P[0..s] -> p_{s+1}, alpha
   gkb_status first_step(int s) {
+    GKB_HIP(mark(PH_MATVEC));
     GKB_HIP(prod_n(Pc(s), Qc(s), pcoef(), s, w()));
+    GKB_HIP(mark(PH_REORTH));
     GKB_HIP(cgs2(Q(cur), L.ldm, s + 1, A.m, w()));
     GKB_HIP(normalize(w(), A.m, Qc(s + 1), qcoef() + s + 1, 1, 1, s + 1, true));
+    GKB_HIP(mark(PH_MATVEC));
     GKB_HIP(prod_t(Qc(s + 1), Pc(s), qcoef(), s + 1, z()));
+    GKB_HIP(mark(PH_REORTH));
     GKB_HIP(cgs2(P(cur), L.ldn, s + 1, A.n, z()));
     GKB_HIP(normalize(z(), A.n, Pc(s + 1), pcoef() + s + 1, 1, 2, s + 1, true));
+    a_passes += 2;
+    return GKB_OK;
+  }
+
+  // A restarted cycle's step j (two products): w = A p_j - (j == l ? Q~ rho :
+  // alpha_j q_{j-1}), CGS2 vs Q[0..j), q_j; z = A^T q_j - beta p_j, CGS2 vs P[0..j], p_{j+1}.
+  gkb_status restart_step(int j, int l) {
+    GKB_HIP(mark(PH_MATVEC));
+    GKB_HIP(prod_n(Pc(j), j == l ? nullptr : Qc(j - 1), pcoef(), j, w()));
+    GKB_HIP(mark(PH_REORTH));
+    if (j == l) GKB_HIP(gkb::launch_update<TB>(Q(cur), L.ldm, l, A.m, w(), rho(), nullptr, flag(), st));
+    GKB_HIP(cgs2(Q(cur), L.ldm, j, A.m, w()));
+    GKB_HIP(normalize(w(), A.m, Qc(j), qcoef() + j, 1, 1, j, true));
+    GKB_HIP(mark(PH_MATVEC));
+    GKB_HIP(prod_t(Qc(j), Pc(j), qcoef(), j, z()));
+    GKB_HIP(mark(PH_REORTH));
+    GKB_HIP(cgs2(P(cur), L.ldn, j + 1, A.n, z()));
+    GKB_HIP(normalize(z(), A.n, Pc(j + 1), pcoef() + j + 1, 1, 2, j + 1, true));
+    a_passes += 2;
     return GKB_OK;
   }
 
@@ -306,12 +403,16 @@ struct Solver {
     if constexpr (std::is_same<TB, double>::value) {
       const int nb = gkb::fused_blocks(A.m, A.n);
       // w = A p - alpha q_qp in the sweep itself (after a restart, Q~ rho by an update)
+      GKB_HIP(mark(PH_MATVEC));
       GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, Pc(pi), nullptr, w(), nullptr, ypart(),
                                              L.ldn, flag(), st, nullptr, use_rho ? nullptr : Qc(qp),
                                              use_rho ? nullptr : pcoef() + pi));
+      ++a_passes;
+      GKB_HIP(mark(PH_REORTH));
       if (use_rho) GKB_HIP(gkb::launch_update<TB>(Q(cur), L.ldm, nqc, A.m, w(), rho(), nullptr, flag(), st));
       GKB_HIP(cgs2(Q(cur), L.ldm, nqc, A.m, w(), csum()));
       GKB_HIP(normalize(w(), A.m, Qc(qn), qcoef() + qn, 1, 1, qn, true));
+      GKB_HIP(mark(PH_MATVEC));
       GKB_HIP(gkb::launch_onepass_recover(ypart(), nb, L.ldn, GQ(cur), L.ldn, nqc, csum(),
                                           use_rho ? rho() : pcoef() + pi, use_rho ? 0 : qp, use_rho ? nqc : 1,
                                           qcoef() + qn, qn, Pc(pi), z(), A.n, err(cur), sig() + nsig, eps0(),
@@ -320,6 +421,7 @@ struct Solver {
                                              L.ldn, flag(), st, refresh()));
       GKB_HIP(gkb::launch_onepass_fix(ypart(), nb, L.ldn, GQ(cur), L.ldn, qn, qcoef() + qn, Pc(pi), z(), A.n, flag(),
                                       refresh(), st));
+      GKB_HIP(mark(PH_REORTH));
       GKB_HIP(cgs2(P(cur), L.ldn, pi + 1, A.n, z()));
       GKB_HIP(normalize(z(), A.n, Pc(pi + 1), pcoef() + pi + 1, 1, 2, pi + 1, true));
       return GKB_OK;
@@ -586,7 +688,9 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
   S.onepass = onepass;
   S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
   S.relative = opt.eps_relative ? 1 : 0;
+  S.pt.on = opt.phase_timing != 0;
   const double* q1 = opt.q1;
+  GKB_HIP(S.mark(PH_OTHER));
   if (q1 == nullptr) {
     GKB_HIP(gkb::launch_philox_start(S.q1buf(), Am->m, opt.seed, st));
     q1 = S.q1buf();
@@ -616,15 +720,8 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
         rc = S.first_step(j);
         if (rc != GKB_OK) return rc;
       } else {
-        // w = A p_j - (j == l ? Q~ rho : alpha_j q_{j-1})
-        GKB_HIP(S.prod_n(S.Pc(j), j == l ? nullptr : S.Qc(j - 1), S.pcoef(), j, S.w()));
-        if (j == l)
-          GKB_HIP(gkb::launch_update<TB>(S.Q(S.cur), S.L.ldm, l, Am->m, S.w(), S.rho(), nullptr, S.flag(), st));
-        GKB_HIP(S.cgs2(S.Q(S.cur), S.L.ldm, j, Am->m, S.w()));
-        GKB_HIP(S.normalize(S.w(), Am->m, S.Qc(j), S.qcoef() + j, 1, 1, j, true));
-        GKB_HIP(S.prod_t(S.Qc(j), S.Pc(j), S.qcoef(), j, S.z()));
-        GKB_HIP(S.cgs2(S.P(S.cur), S.L.ldn, j + 1, Am->n, S.z()));
-        GKB_HIP(S.normalize(S.z(), Am->n, S.Pc(j + 1), S.pcoef() + j + 1, 1, 2, j + 1, true));
+        rc = S.restart_step(j, l);
+        if (rc != GKB_OK) return rc;
       }
       const int np_now = j + 1;
       if (every > 0 && np_now < k && np_now >= r && np_now % every == 0) {
@@ -687,6 +784,7 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     GKB_HIP(hipMemcpyAsync(S.Xs(), Xh.data(), Xh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
     GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
     GKB_HIP(hipMemcpyAsync(S.rho(), rs.rho.data(), l * sizeof(double), hipMemcpyHostToDevice, st));
+    GKB_HIP(S.mark(PH_RITZ));
     const int nb = 1 - S.cur;
     GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, S.Ys(), pr.np, l, S.P(nb), S.L.ldn,
                                       st));
@@ -701,11 +799,13 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     }
     S.cur = nb;
     S.nsig = 0;
+    GKB_HIP(S.mark(PH_OTHER));
     GKB_HIP(gkb::launch_init_cycle(S.flag(), S.sig(), sig_est, st));
     ++restarts;
     first = false;
   }
   // ---- Ritz vectors: V = P Y_r, U = Q X_r
+  GKB_HIP(S.mark(PH_RITZ));
   const int r_eff = ct.r_eff;
   for (int i = 0; i < r; ++i) sigma[i] = i < r_eff ? rz.s[i] : 0.0;
   if (r_eff < r) {  // columns past the returned triplets are zero
@@ -744,6 +844,11 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     }
     GKB_HIP(hipStreamSynchronize(st));
   }
+  if (S.pt.on) {  // close the last interval
+    GKB_HIP(S.mark(PH_OTHER));
+    GKB_HIP(hipStreamSynchronize(st));
+    GKB_HIP(S.pt.collect());
+  }
   if (stats) {
     stats->nconv = ct.nconv;
     stats->restarts = restarts;
@@ -756,6 +861,7 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     }
     stats->refreshes = refreshes;
     stats->matvecs = matvecs + refreshes;
+    stats->bytes_A = (double)(S.a_passes + refreshes) * S.bytes_per_pass();
     double mr = 0.0;
     for (int i = 0; i < r_eff; ++i) mr = std::max(mr, ct.res[i]);
     stats->max_res_est = mr;
@@ -766,6 +872,7 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     stats->krylov_dim = pr.np;
     stats->refined = refined;
     stats->ms_refine = ms_refine;
+    S.pt.fill(stats);
   }
   if (r_eff < r) return GKB_RANK_DEFICIENT;
   return ct.nconv == r ? GKB_OK : GKB_NOT_CONVERGED;
@@ -784,7 +891,9 @@ gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, c
   S.onepass = onepass;
   S.eps = opt.eps_break > 0 ? opt.eps_break : (Am->dtype == GKB_F64 ? 1e-12 : 1e-6);
   S.relative = opt.eps_relative ? 1 : 0;
+  S.pt.on = opt.phase_timing != 0;
   const double* q1 = opt.q1;
+  GKB_HIP(S.mark(PH_OTHER));
   if (q1 == nullptr) {
     GKB_HIP(gkb::launch_philox_start(S.q1buf(), Am->m, opt.seed, st));
     q1 = S.q1buf();
@@ -841,9 +950,11 @@ gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, c
     stats->breakdown = pr.breakdown;
     stats->returned = np;
     stats->matvecs = pr.matvecs + refreshes;
+    stats->bytes_A = (double)(S.a_passes + refreshes) * S.bytes_per_pass();
     stats->sigma1_est = np > 0 ? s[0] : 0.0;
     stats->ms_total = now_ms() - t0;
     stats->ms_host = ms_host;
+    S.pt.fill(stats);
   }
   return GKB_OK;
 }

@@ -35,7 +35,7 @@ class GkbMatrix(C.Structure):
 class GkbOptions(C.Structure):
     _fields_ = [("keep", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
                 ("q1", C.c_void_p), ("seed", C.c_uint64), ("refine_dim", C.c_int), ("check_every", C.c_int),
-                ("one_pass", C.c_int)]
+                ("one_pass", C.c_int), ("phase_timing", C.c_int)]
 
 
 class GkbBatchOptions(C.Structure):
@@ -55,7 +55,9 @@ class GkbStats(C.Structure):
                 ("matvecs", C.c_int64), ("max_res_est", C.c_double), ("sigma1_est", C.c_double),
                 ("ms_total", C.c_double), ("ms_host", C.c_double), ("checks", C.c_int),
                 ("krylov_dim", C.c_int), ("refined", C.c_int), ("ms_refine", C.c_double),
-                ("refreshes", C.c_int)]
+                ("refreshes", C.c_int), ("ms_matvec", C.c_double), ("ms_reorth", C.c_double),
+                ("ms_sync", C.c_double), ("ms_ritz", C.c_double), ("ms_other", C.c_double),
+                ("bytes_A", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -279,7 +281,7 @@ def _stream(stream):
 
 
 def make_options(q1=None, seed=0, keep=0, eps_break=0.0, eps_relative=True, refine_dim=0,
-                 check_every=0, one_pass=False) -> GkbOptions:
+                 check_every=0, one_pass=False, phase_timing=False) -> GkbOptions:
     o = GkbOptions()
     lib().gkb_default_options(C.byref(o))
     o.keep = keep
@@ -289,6 +291,7 @@ def make_options(q1=None, seed=0, keep=0, eps_break=0.0, eps_relative=True, refi
     o.refine_dim = refine_dim
     o.check_every = check_every
     o.one_pass = 1 if one_pass else 0
+    o.phase_timing = 1 if phase_timing else 0
     if q1 is not None:
         if q1.dtype != _torch().float64 or not q1.is_cuda or not q1.is_contiguous():
             raise ValueError("q1 must be a contiguous float64 device tensor")

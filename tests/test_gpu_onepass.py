@@ -6,9 +6,13 @@ upcast of the same float32 matrix with the same start vector; the one-pass
 path computes the same factorisation (see oracle.onepass and its pins), so
 the Ritz values must agree to the float32 storage level: the only float32
 rounding left is that of p before the product (float64 bases, float64 sums),
-which perturbs the relations of eq. (2.4) by about u32 ||A||, hence the
-sigma bound 8 sqrt(k) u32 sigma_1 (Weyl).  Vectors are compared with the
-sign-invariant alignment metric of Figure 1.
+a relative perturbation of about u32 of each p.  To first order a
+perturbation E moves a simple singular value by u_i^T E v_i; the roundings of
+the k steps have no common direction, so their projections on one singular
+pair stay at the scale of one of them: tolerance u32 sigma_1 (measured
+0.002-0.04 u32 sigma_1).  The norm-wise bound 8 sqrt(k) u32 sigma_1 (Weyl,
+one u32 ||A|| per step) is kept as a sanity check.  Vectors are compared with
+the sign-invariant alignment metric of Figure 1.
 """
 import json
 import os
@@ -19,7 +23,7 @@ import pytest
 from oracle import checks, gk
 from paper_2104_10785_amd import gkb, inputs
 
-from .gpu_util import banner, device, to_dev, to_host
+from .gpu_util import banner, device, sketch_distances, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +38,12 @@ def run(A32, r, k, tol, restarts, q, **kw):
 
 
 def _check_against(ref, sigma, U, V, k, align=1 - 1e-5):
-    bound = 8.0 * np.sqrt(k) * U32 * ref["sigma"][0]
+    loose = 8.0 * np.sqrt(k) * U32 * ref["sigma"][0]
+    tight = U32 * ref["sigma"][0]
     err = np.abs(sigma - ref["sigma"])
-    print(f"one-pass sigma max abs err {err.max():.3e} (bound {bound:.3e})", flush=True)
-    assert np.all(err <= bound)
+    print(f"one-pass sigma max abs err {err.max():.3e} = {err.max() / tight:.4f} u32 sigma_1 "
+          f"(norm-wise bound {loose:.3e})", flush=True)
+    assert np.all(err <= tight) and np.all(err <= loose)
     al = checks.alignment(ref["U"], ref["V"], U, V)
     print(f"one-pass alignment min {al.min():.9f}", flush=True)
     assert np.min(al) >= align
@@ -129,7 +135,7 @@ def test_onepass_rank_deficient():
     sigma, U, V, status, stats = run(A32, 8, 20, 1e-6, 5, q, one_pass=True)
     assert ref["status"] == 2 and len(ref["sigma"]) == 6
     assert status == 2 and stats["returned"] == 6
-    assert np.max(np.abs(sigma[:6] - ref["sigma"])) <= 8 * np.sqrt(20) * U32 * ref["sigma"][0]
+    assert np.max(np.abs(sigma[:6] - ref["sigma"])) <= U32 * ref["sigma"][0]
     assert np.all(sigma[6:] == 0.0)
     assert np.all(U[:, 6:] == 0.0) and np.all(V[:, 6:] == 0.0)
 
@@ -204,7 +210,8 @@ def test_c2_fullsize_onepass_against_stored_oracle(check_every):
     tests/golden/make_c2_reference.py)."""
     import torch
     device()
-    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_top50.json")))
+    ref_all = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_top50.json")))
+    ref = ref_all if check_every == 0 else ref_all["check_every_10"]
     banner(f"c2 full size 50000x20000 f32 r=50 k=120 one_pass check_every={check_every}")
     A32, s, _, _ = inputs.lowrank_noise(50000, 20000, 200, 0.95, 1e-6, seed=2, dtype=np.float32)
     q = inputs.start_vector(50000, seed=1)
@@ -216,13 +223,16 @@ def test_c2_fullsize_onepass_against_stored_oracle(check_every):
     print("stats", stats, flush=True)
     assert status == 0 and stats["nconv"] == 50
     want = np.array(ref["sigma"])
-    bound = 8.0 * np.sqrt(120) * U32 * want[0]
+    loose = 8.0 * np.sqrt(120) * U32 * want[0]
+    tight = U32 * want[0]
     err = np.abs(sigma - want)
-    print(f"c2 one-pass sigma max abs err {err.max():.3e} (bound {bound:.3e}); matvecs {stats['matvecs']} "
-          f"(oracle {ref['matvecs']}), refreshes {stats['refreshes']}", flush=True)
-    assert np.all(err <= bound)
-    if check_every == 0:
-        assert abs(stats["matvecs"] - stats["refreshes"] - ref["matvecs"]) <= 2 * 120
+    print(f"c2 one-pass sigma max abs err {err.max():.3e} = {err.max() / tight:.4f} u32 sigma_1 "
+          f"(norm-wise {loose:.3e}); matvecs {stats['matvecs']} (oracle {ref['matvecs']}), "
+          f"refreshes {stats['refreshes']}, checks {stats['checks']} (oracle {ref['checks']})", flush=True)
+    assert np.all(err <= tight) and np.all(err <= loose)
+    # one sweep = two products; a recomputed column adds one direct product
+    assert stats["matvecs"] - stats["refreshes"] == ref["matvecs"]
+    assert stats["checks"] == ref["checks"] and stats["krylov_dim"] == ref["krylov_dim"]
     U = to_host(Ut).T.astype(np.float64)
     V = to_host(Vt).T.astype(np.float64)
     idx = [0, 1, 24, 48, 49]
@@ -237,3 +247,11 @@ def test_c2_fullsize_onepass_against_stored_oracle(check_every):
     r2 = np.linalg.norm(ATU - V[:, idx] * sigma[idx][None, :], axis=0)
     print(f"c2 one-pass residuals ||Av-su|| {r1.max():.3e} ||A^T u - s v|| {r2.max():.3e}", flush=True)
     assert np.max(r1) <= 1e-6 * want[0] and np.max(r2) <= 2e-6 * want[0]
+    # singular vectors against the oracle's, through its stored sketches
+    sp = np.concatenate([want, [s[50]]])
+    gaps = np.minimum(np.abs(np.diff(np.concatenate([[np.inf], sp])))[:50], np.abs(np.diff(sp)))
+    du, dv = sketch_distances(ref, U, V)
+    vt = 1.5 * np.sqrt(2.0) * tight / gaps
+    print(f"c2 one-pass vector distances (sketch): u max {du.max():.3e}, v max {dv.max():.3e}; "
+          f"max ratio to tolerance {np.max(np.maximum(du, dv) / vt):.3f}", flush=True)
+    assert np.all(du <= vt) and np.all(dv <= vt)
