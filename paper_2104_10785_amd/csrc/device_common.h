@@ -97,4 +97,50 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
   return t;
 }
 
+// The normalisation step's norm and tests.  The norm is the square root of
+// the sum of nparts partial sums of squares, added in a fixed order by the
+// 256 threads, so every workgroup obtains the same value and takes the same
+// branch.  A NaN or Inf norm sets flag = {3, index}; a norm <= thr (thr =
+// eps * sig_in[0] when relative, else eps) is a breakdown: flag = {code,
+// index}, sig_out = sig_in.  Otherwise sig_out = max(sig_in, norm) (sig_in
+// when !track).  The lead thread writes coef_out, sig_out and flag.  Returns
+// the norm when the vector is to be scaled, else -1; *sig_new (if given)
+// receives the value written to sig_out.
+__device__ __forceinline__ double norm_test(const double* __restrict__ normpart, int nparts,
+                                            const double* __restrict__ sig_in, double* __restrict__ sig_out,
+                                            double eps, int relative, int track, int* __restrict__ flag, int code,
+                                            int index, double* __restrict__ coef_out, bool lead, double* red,
+                                            double* sig_new = nullptr) {
+  double s = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += 256) s += normpart[p];
+  const double tot = block_sum256(s, red);
+  const double nrm = sqrt(tot);
+  const double sin = *sig_in;
+  const double thr = relative ? eps * sin : eps;
+  if (!(nrm < INFINITY)) {  // NaN or Inf
+    if (lead) {
+      flag[0] = 3;
+      flag[1] = index;
+      *coef_out = nrm;
+    }
+    return -1.0;
+  }
+  if (nrm <= thr) {
+    if (lead) {
+      flag[0] = code;
+      flag[1] = index;
+      *coef_out = nrm;
+      *sig_out = sin;
+    }
+    return -1.0;
+  }
+  const double so = track ? fmax(sin, nrm) : sin;
+  if (lead) {
+    *coef_out = nrm;
+    *sig_out = so;
+  }
+  if (sig_new != nullptr) *sig_new = so;
+  return nrm;
+}
+
 }  // namespace gkb

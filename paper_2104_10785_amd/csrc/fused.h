@@ -45,10 +45,31 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
 //   s = sig[0]; if e > tau s: refresh[0] = 1, refresh[1] += 1,
 //   err[tq] = eps0 s (the column is then recomputed by a direct sweep); else
 //   refresh[0] = 0, err[tq] = e.
+// With `norm` given, the same launch first normalises the left vector: beta =
+// the norm of norm->x from its partial sums of squares (breakdown and
+// non-finite tests as the normalisation kernel, flag set on either, and then
+// nothing is recovered), norm->out = norm->x / beta, norm->coef_out = beta,
+// norm->sig_out = max(sig_in, beta); beta and s then come from there (beta
+// and sig are not read).
+struct NormArgs {
+  const double* x = nullptr;        // the orthogonalised vector (len)
+  int64_t len = 0;
+  const double* normpart = nullptr;  // its partial sums of squares
+  int nparts = 0;
+  double* out = nullptr;             // the new basis column
+  double* coef_out = nullptr;        // beta
+  const double* sig_in = nullptr;    // running largest coefficient, before
+  double* sig_out = nullptr;         // and after this vector
+  double eps = 0.0;                  // breakdown threshold
+  int relative = 1;
+  int code = 1;                      // flag[0] on breakdown
+  int index = 0;                     // flag[1] on breakdown
+};
 hipError_t launch_onepass_recover(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int t,
                                   const double* c, const double* xc, int x0, int nx, const double* beta, int tq,
                                   const double* pprev, double* z, int64_t n, double* err, const double* sig,
-                                  double eps0, double tau, int* refresh, const int* flag, hipStream_t st);
+                                  double eps0, double tau, int* refresh, int* flag, hipStream_t st,
+                                  const NormArgs* norm = nullptr);
 // err[idx] = eps0 * sig[0]
 hipError_t launch_err_set(double* err, int idx, const double* sig, double eps0, const int* flag, hipStream_t st);
 // dst[0..l) = sqrt(nq) * max(src[0..nq)) (columns of G X after a restart)

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "device_common.h"
 #include "fused.h"
 #include "gemv.h"
 
@@ -613,28 +614,47 @@ __device__ __forceinline__ double coef_total(const double* __restrict__ c, int j
 }
 
 // G's columns 0..t-1 are read and column tq (>= t) is written: no overlap.
-// Block 0 also runs the guard (it reads only coefficients and bounds).
-__global__ __launch_bounds__(256) void k_onepass_recover(const double* __restrict__ ypart, int nb, int64_t ldy,
-                                                         double* G, int64_t ldg, int t, const double* __restrict__ c,
+// Block 0 also runs the guard (it reads only coefficients and bounds).  With
+// NORM, the launch first completes the left vector's normalisation (norm from
+// the Gram-Schmidt partial sums, breakdown tests, q_tq = w / beta written by
+// a grid-stride loop), so beta is its own result instead of beta[0].
+template <bool NORM>
+__global__ __launch_bounds__(256) void k_onepass_recover(NormArgs na, const double* __restrict__ ypart, int nb,
+                                                         int64_t ldy, double* G, int64_t ldg, int t,
+                                                         const double* __restrict__ c,
                                                          const double* __restrict__ xc, int x0, int nx,
                                                          const double* __restrict__ beta, int tq,
                                                          const double* __restrict__ pprev, double* __restrict__ z,
                                                          int64_t n, double* __restrict__ err,
                                                          const double* __restrict__ sig, double eps0, double tau,
-                                                         int* __restrict__ refresh, const int* __restrict__ flag) {
+                                                         int* __restrict__ refresh, int* __restrict__ flag) {
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (flag != nullptr && flag[0] != 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) refresh[0] = 0;
+    if (lead) refresh[0] = 0;
     return;
   }
-  const double b = beta[0];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  double b, s;
+  if constexpr (NORM) {
+    __shared__ double red[4];
+    b = norm_test(na.normpart, na.nparts, na.sig_in, na.sig_out, na.eps, na.relative, 1, flag, na.code, na.index,
+                  na.coef_out, lead, red, &s);
+    if (b < 0.0) {  // breakdown or a non-finite norm: nothing to recover
+      if (lead) refresh[0] = 0;
+      return;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < na.len; i += (int64_t)gridDim.x * 256)
+      na.out[i] = na.x[i] / b;
+  } else {
+    b = beta[0];
+    s = sig[0];
+  }
+  if (lead) {
     double sce = 0.0, sc = 0.0;
     for (int j = 0; j < t; ++j) {
       const double a = fabs(coef_total(c, j, xc, x0, nx));
       sce += a * err[j];
       sc += a;
     }
-    const double s = sig[0];
     const double e = (sce + eps0 * (s * s + s * sc)) / b;
     if (e > tau * s) {
       refresh[0] = 1;
@@ -782,9 +802,14 @@ template hipError_t launch_gemv_fused<double>(const void*, int, int64_t, int64_t
 hipError_t launch_onepass_recover(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int t,
                                   const double* c, const double* xc, int x0, int nx, const double* beta, int tq,
                                   const double* pprev, double* z, int64_t n, double* err, const double* sig,
-                                  double eps0, double tau, int* refresh, const int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_onepass_recover, dim3(nblk(n, RCOLS)), dim3(256), 0, st, ypart, nb, ldy, G, ldg, t, c, xc, x0,
-                     nx, beta, tq, pprev, z, n, err, sig, eps0, tau, refresh, flag);
+                                  double eps0, double tau, int* refresh, int* flag, hipStream_t st,
+                                  const NormArgs* norm) {
+  if (norm != nullptr)
+    hipLaunchKernelGGL(k_onepass_recover<true>, dim3(nblk(n, RCOLS)), dim3(256), 0, st, *norm, ypart, nb, ldy, G, ldg,
+                       t, c, xc, x0, nx, beta, tq, pprev, z, n, err, sig, eps0, tau, refresh, flag);
+  else
+    hipLaunchKernelGGL(k_onepass_recover<false>, dim3(nblk(n, RCOLS)), dim3(256), 0, st, NormArgs(), ypart, nb, ldy, G,
+                       ldg, t, c, xc, x0, nx, beta, tq, pprev, z, n, err, sig, eps0, tau, refresh, flag);
   return hipGetLastError();
 }
 

@@ -39,7 +39,9 @@ template <typename TB>
 hipError_t launch_gemv_n(const MatrixRef& A, const TB* p, const TB* qprev, const double* coef, int cidx,
                          double* w, const int* flag, hipStream_t st);
 
-// z = A^T q - coef[cidx] * pprev, through `part` (nb x ldpart accumulators)
+// z = A^T q - coef[cidx] * pprev, through `part` (nb x ldpart accumulators:
+// float for float and bfloat16 A, double for double A; nb =
+// gemv_t_shape(m, n, element bytes).nb).  z == NULL: only the partial sums.
 template <typename TB>
 hipError_t launch_gemv_t(const MatrixRef& A, const TB* q, const TB* pprev, const double* coef, int cidx,
                          double* z, void* part, int64_t ldpart, const int* flag, hipStream_t st);

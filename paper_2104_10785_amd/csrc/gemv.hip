@@ -260,7 +260,7 @@ hipError_t launch_gemv_t_t(const TA* A, int64_t lda, int64_t m, int64_t n, const
                        s.rows_per_block, pa, ldpart, flag);
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || z == nullptr) return e;  // z == NULL: the partial sums only
   hipLaunchKernelGGL((k_gemv_t_reduce<ACC, TB>), dim3(nblocks(n, 256)), dim3(256), 0, st, pa, ldpart, s.nb,
                      n, pprev, coef, cidx, z, flag);
   return hipGetLastError();

@@ -19,6 +19,7 @@
 #include "kernels.h"
 #include "sparse.h"
 #include "fused.h"
+#include "reorth.h"
 
 namespace {
 
@@ -47,7 +48,7 @@ struct Layout {
   int64_t ldm = 0, ldn = 0, ldpart = 0;
   int ldh = 0, kcols = 0;
   size_t Q[2] = {0, 0}, P[2] = {0, 0};
-  size_t w = 0, z = 0, part = 0, hpart = 0, h = 0, normpart = 0;
+  size_t w = 0, z = 0, part = 0, gsp = 0, normpart = 0;
   size_t qcoef = 0, pcoef = 0, sig = 0, flag = 0, Xs = 0, Ys = 0, rho = 0, q1 = 0;
   size_t Vd = 0, Wr = 0, Gpart = 0, G = 0;  // bfloat16 refinement
   size_t GQ[2] = {0, 0}, y = 0, ypart = 0, csum = 0, Uo = 0, Vo = 0, err[2] = {0, 0}, refresh = 0;  // one-pass
@@ -85,9 +86,9 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
   const int64_t part_rows = dense && !onepass ? std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (m + 63) / 64) : 0;
   L.ldpart = L.ldn;
   L.part = take((size_t)part_rows * L.ldpart * acc);
-  const int nch = std::max(gkb::dots_chunks(m), gkb::dots_chunks(n));
-  L.hpart = take((size_t)nch * L.ldh * 8);
-  L.h = take((size_t)L.ldh * 8);
+  // Gram-Schmidt partial dots: two sets (one per pass) of one row per workgroup
+  const int gsg = std::max(gkb::gs_split(m).G, gkb::gs_split(n).G);
+  L.gsp = take((size_t)(2 * gsg + 1) * L.ldh * 8);
   L.normpart = take((size_t)std::max(gkb::update_blocks(m), gkb::update_blocks(n)) * 8);
   L.qcoef = take((size_t)(L.kcols + 1) * 8);
   L.pcoef = take((size_t)(L.kcols + 1) * 8);
@@ -154,6 +155,12 @@ double now_ms() {
 // phase the first one opened.  Completed intervals are read after every host
 // synchronisation and their events reused, so a solve holds a few dozen events.
 enum Phase { PH_MATVEC = 0, PH_REORTH, PH_SYNC, PH_RITZ, PH_OTHER, PH_COUNT };
+
+#define GKB_MARK_REORTH()                          \
+  do {                                             \
+    hipError_t m_ = mark(PH_REORTH);               \
+    if (m_ != hipSuccess) return m_;               \
+  } while (0)
 
 struct PhaseTimer {
   bool on = false;
@@ -236,8 +243,7 @@ struct Solver {
   double* w() { return reinterpret_cast<double*>(ws + L.w); }
   double* z() { return reinterpret_cast<double*>(ws + L.z); }
   void* part() { return ws + L.part; }
-  double* hpart() { return reinterpret_cast<double*>(ws + L.hpart); }
-  double* h() { return reinterpret_cast<double*>(ws + L.h); }
+  double* gsp() { return reinterpret_cast<double*>(ws + L.gsp); }
   double* normpart() { return reinterpret_cast<double*>(ws + L.normpart); }
   double* qcoef() { return reinterpret_cast<double*>(ws + L.qcoef); }
   double* pcoef() { return reinterpret_cast<double*>(ws + L.pcoef); }
@@ -256,6 +262,7 @@ struct Solver {
   double eps0() const { return std::ldexp(1.0, -52) * std::sqrt((double)(A.m + A.n)); }
   bool onepass = false;  // dense float32 A, float64 bases, one sweep of A per step
   PhaseTimer pt;         // per-phase device time (opt.phase_timing)
+  int nparts = 1;        // norm partials left in normpart by the last cgs2
   int64_t a_passes = 0;  // full passes over A launched (a skipped direct sweep not counted)
 
   hipError_t mark(int phase) { return pt.mark(phase, st); }
@@ -266,43 +273,62 @@ struct Solver {
     return (double)A.m * (double)A.n * elem_bytes((gkb_dtype)A.dtype);
   }
 
-  // w = A p - coef[cidx] qprev and z = A^T q - coef[cidx] pprev (dense or sparse A)
+  // w = A p - coef[cidx] qprev (dense or sparse A)
   hipError_t prod_n(const TB* p, const TB* qprev, const double* coef, int cidx, double* out) {
     if constexpr (std::is_same<TB, float>::value) {
       if (sp) return gkb::launch_spmv(sp->fwd, p, qprev, coef, cidx, out, flag(), st);
     }
     return gkb::launch_gemv_n<TB>(A, p, qprev, coef, cidx, out, flag(), st);
   }
-  hipError_t prod_t(const TB* q, const TB* pprev, const double* coef, int cidx, double* out) {
-    if constexpr (std::is_same<TB, float>::value) {
-      if (sp) return gkb::launch_spmv(sp->tr, q, pprev, coef, cidx, out, flag(), st);
-    }
-    return gkb::launch_gemv_t<TB>(A, q, pprev, coef, cidx, out, part(), L.ldpart, flag(), st);
+
+  // Two classical Gram-Schmidt passes of x against V[:, 0..t), leaving the
+  // partial sums of ||x||^2 in normpart (three launches, reorth.h).  If acc is
+  // given, acc[0..t) receives the sum of the coefficients of both passes.
+  hipError_t cgs2(const TB* V, int64_t ldv, int t, int64_t len, double* x, double* acc = nullptr,
+                  int pre_kind = gkb::GS_PRE_NONE, const gkb::GsPreArgs& pre = gkb::GsPreArgs()) {
+    return gkb::launch_gs2<TB>(V, ldv, t, len, x, gsp(), L.ldh, normpart(), acc, pre_kind, pre, flag(), st,
+                               &nparts);
   }
 
-  // Two classical Gram-Schmidt passes of x against V[:, 0..t); the last
-  // update leaves the partial sums of ||x||^2 in normpart.  If acc is given,
-  // acc[0..t) receives the sum of the coefficients of both passes.
-  hipError_t cgs2(const TB* V, int64_t ldv, int t, int64_t len, double* x, double* acc = nullptr) {
-    hipError_t e;
-    for (int pass = 0; pass < 2; ++pass) {
-      double* np_out = pass == 1 ? normpart() : nullptr;
-      if (t > 0) {
-        e = gkb::launch_dots<TB>(V, ldv, t, len, x, hpart(), L.ldh, h(), flag(), st, acc, pass);
+  // z = A^T q - coef[cidx] pprev, then CGS2 of z against P[:, 0..t).  Dense A:
+  // the row-block partial sums of A^T q are added by the first Gram-Schmidt
+  // launch (no separate reduction launch).
+  hipError_t prod_t_cgs2(const TB* q, const TB* pprev, const double* coef, int cidx, int t) {
+    if constexpr (std::is_same<TB, float>::value) {
+      if (sp) {
+        hipError_t e = gkb::launch_spmv(sp->tr, q, pprev, coef, cidx, z(), flag(), st);
         if (e != hipSuccess) return e;
-        e = gkb::launch_update<TB>(V, ldv, t, len, x, h(), np_out, flag(), st);
-        if (e != hipSuccess) return e;
-      } else if (pass == 1) {
-        e = gkb::launch_update<TB>(V, ldv, 0, len, x, h(), np_out, flag(), st);
-        if (e != hipSuccess) return e;
+        GKB_MARK_REORTH();
+        return cgs2(P(cur), L.ldn, t, A.n, z());
       }
     }
-    return hipSuccess;
+    hipError_t e = gkb::launch_gemv_t<TB>(A, q, nullptr, nullptr, 0, nullptr, part(), L.ldpart, flag(), st);
+    if (e != hipSuccess) return e;
+    GKB_MARK_REORTH();
+    gkb::GsPreArgs pre;
+    pre.part = part();
+    pre.ldpart = L.ldpart;
+    pre.nparts = gkb::gemv_t_shape(A.m, A.n, elem_bytes((gkb_dtype)A.dtype)).nb;
+    pre.part_f64 = A.dtype == GKB_F64 ? 1 : 0;
+    pre.prev = pprev;
+    pre.coef = coef;
+    pre.cidx = cidx;
+    return cgs2(P(cur), L.ldn, t, A.n, z(), nullptr, gkb::GS_PRE_TSUM, pre);
+  }
+
+  // The first left vector after a thick restart: x -= Q~ rho (the kept Ritz
+  // vectors' couplings, rho = alpha_res X[last, :l]), then CGS2 against
+  // Q[:, 0..t); the rho update is the first Gram-Schmidt launch's pre-step.
+  hipError_t cgs2_after_restart(int t, int l, int64_t len, double* x, double* acc) {
+    gkb::GsPreArgs pre;
+    pre.rho = rho();
+    pre.l = l;
+    return cgs2(Q(cur), L.ldm, t, len, x, acc, gkb::GS_PRE_RHO, pre);
   }
 
   hipError_t normalize(const double* x, int64_t len, TB* out, double* coef_out, int track, int code,
                        int index, bool test) {
-    hipError_t e = gkb::launch_normalize<TB>(x, len, normpart(), gkb::update_blocks(len), out, coef_out,
+    hipError_t e = gkb::launch_normalize<TB>(x, len, normpart(), nparts, out, coef_out,
                                              sig() + nsig, sig() + nsig + 1, test ? eps : 0.0, relative,
                                              track, flag(), code, index, st);
     ++nsig;
@@ -328,7 +354,7 @@ struct Solver {
     GKB_HIP(mark(PH_OTHER));
     GKB_HIP(gkb::launch_init_cycle(flag(), sig(), 0.0, st));
     GKB_HIP(hipMemcpyAsync(w(), q1, (size_t)A.m * sizeof(double), hipMemcpyDeviceToDevice, st));
-    GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.m, w(), h(), normpart(), flag(), st));
+    GKB_HIP(cgs2(Q(cur), L.ldm, 0, A.m, w()));  // norm partials only
     GKB_HIP(normalize(w(), A.m, Qc(0), qcoef(), 0, 1, 0, false));
     GKB_HIP(mark(PH_MATVEC));
     ++a_passes;
@@ -340,11 +366,12 @@ struct Solver {
         GKB_HIP(gkb::launch_copy_vec<double>(z(), A.n, GQ(cur), st));
         GKB_HIP(hipMemsetAsync(refresh(), 0, 4 * sizeof(int), st));
       }
+      GKB_HIP(mark(PH_REORTH));
+      GKB_HIP(cgs2(P(cur), L.ldn, 0, A.n, z()));
     } else {
-      GKB_HIP(prod_t(Qc(0), nullptr, nullptr, 0, z()));
+      GKB_HIP(prod_t_cgs2(Qc(0), nullptr, nullptr, 0, 0));
     }
     GKB_HIP(mark(PH_REORTH));
-    GKB_HIP(gkb::launch_update<TB>(nullptr, 0, 0, A.n, z(), h(), normpart(), flag(), st));
     GKB_HIP(normalize(z(), A.n, Pc(0), pcoef(), 1, 2, 0, false));
     if (onepass) GKB_HIP(gkb::launch_err_set(err(cur), 0, sig() + nsig, eps0(), flag(), st));
     return GKB_OK;
@@ -360,9 +387,7 @@ struct Solver {
     GKB_HIP(cgs2(Q(cur), L.ldm, s + 1, A.m, w()));
     GKB_HIP(normalize(w(), A.m, Qc(s + 1), qcoef() + s + 1, 1, 1, s + 1, true));
     GKB_HIP(mark(PH_MATVEC));
-    GKB_HIP(prod_t(Qc(s + 1), Pc(s), qcoef(), s + 1, z()));
-    GKB_HIP(mark(PH_REORTH));
-    GKB_HIP(cgs2(P(cur), L.ldn, s + 1, A.n, z()));
+    GKB_HIP(prod_t_cgs2(Qc(s + 1), Pc(s), qcoef(), s + 1, s + 1));
     GKB_HIP(normalize(z(), A.n, Pc(s + 1), pcoef() + s + 1, 1, 2, s + 1, true));
     a_passes += 2;
     return GKB_OK;
@@ -374,13 +399,10 @@ struct Solver {
     GKB_HIP(mark(PH_MATVEC));
     GKB_HIP(prod_n(Pc(j), j == l ? nullptr : Qc(j - 1), pcoef(), j, w()));
     GKB_HIP(mark(PH_REORTH));
-    if (j == l) GKB_HIP(gkb::launch_update<TB>(Q(cur), L.ldm, l, A.m, w(), rho(), nullptr, flag(), st));
-    GKB_HIP(cgs2(Q(cur), L.ldm, j, A.m, w()));
+    GKB_HIP(cgs2_after_restart(j, l, A.m, w(), nullptr));
     GKB_HIP(normalize(w(), A.m, Qc(j), qcoef() + j, 1, 1, j, true));
     GKB_HIP(mark(PH_MATVEC));
-    GKB_HIP(prod_t(Qc(j), Pc(j), qcoef(), j, z()));
-    GKB_HIP(mark(PH_REORTH));
-    GKB_HIP(cgs2(P(cur), L.ldn, j + 1, A.n, z()));
+    GKB_HIP(prod_t_cgs2(Qc(j), Pc(j), qcoef(), j, j + 1));
     GKB_HIP(normalize(z(), A.n, Pc(j + 1), pcoef() + j + 1, 1, 2, j + 1, true));
     a_passes += 2;
     return GKB_OK;
@@ -409,20 +431,47 @@ struct Solver {
                                              use_rho ? nullptr : pcoef() + pi));
       ++a_passes;
       GKB_HIP(mark(PH_REORTH));
-      if (use_rho) GKB_HIP(gkb::launch_update<TB>(Q(cur), L.ldm, nqc, A.m, w(), rho(), nullptr, flag(), st));
-      GKB_HIP(cgs2(Q(cur), L.ldm, nqc, A.m, w(), csum()));
-      GKB_HIP(normalize(w(), A.m, Qc(qn), qcoef() + qn, 1, 1, qn, true));
+      if (use_rho)
+        GKB_HIP(cgs2_after_restart(nqc, nqc, A.m, w(), csum()));
+      else
+        GKB_HIP(cgs2(Q(cur), L.ldm, nqc, A.m, w(), csum()));
+      // the normalisation of q_qn and the recovery of A^T q_qn in one launch
       GKB_HIP(mark(PH_MATVEC));
+      gkb::NormArgs na;
+      na.x = w();
+      na.len = A.m;
+      na.normpart = normpart();
+      na.nparts = nparts;
+      na.out = Qc(qn);
+      na.coef_out = qcoef() + qn;
+      na.sig_in = sig() + nsig;
+      na.sig_out = sig() + nsig + 1;
+      na.eps = eps;
+      na.relative = relative;
+      na.code = 1;
+      na.index = qn;
+      ++nsig;
       GKB_HIP(gkb::launch_onepass_recover(ypart(), nb, L.ldn, GQ(cur), L.ldn, nqc, csum(),
                                           use_rho ? rho() : pcoef() + pi, use_rho ? 0 : qp, use_rho ? nqc : 1,
-                                          qcoef() + qn, qn, Pc(pi), z(), A.n, err(cur), sig() + nsig, eps0(),
-                                          gkb::ONEPASS_TAU, refresh(), flag(), st));
+                                          nullptr, qn, Pc(pi), z(), A.n, err(cur), nullptr, eps0(),
+                                          gkb::ONEPASS_TAU, refresh(), flag(), st, &na));
       GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, nullptr, Qc(qn), nullptr, nullptr, ypart(),
                                              L.ldn, flag(), st, refresh()));
-      GKB_HIP(gkb::launch_onepass_fix(ypart(), nb, L.ldn, GQ(cur), L.ldn, qn, qcoef() + qn, Pc(pi), z(), A.n, flag(),
-                                      refresh(), st));
+      // if the column was recomputed: A^T q_qn from the direct sweep's partial
+      // sums replaces the recovered one (G[:, qn] and z), as the first
+      // Gram-Schmidt launch's pre-step
       GKB_HIP(mark(PH_REORTH));
-      GKB_HIP(cgs2(P(cur), L.ldn, pi + 1, A.n, z()));
+      gkb::GsPreArgs fix;
+      fix.part = ypart();
+      fix.ldpart = L.ldn;
+      fix.nparts = nb;
+      fix.part_f64 = 1;
+      fix.prev = Pc(pi);
+      fix.coef = qcoef() + qn;
+      fix.cidx = 0;
+      fix.run_if = refresh();
+      fix.gcol = GQ(cur) + (int64_t)qn * L.ldn;
+      GKB_HIP(cgs2(P(cur), L.ldn, pi + 1, A.n, z(), nullptr, gkb::GS_PRE_FIX, fix));
       GKB_HIP(normalize(z(), A.n, Pc(pi + 1), pcoef() + pi + 1, 1, 2, pi + 1, true));
       return GKB_OK;
     } else {
@@ -1020,6 +1069,7 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
   return run_partial_svd<float>(A, r, k, tol, max_restarts, opt, workspace, sigma,
                                 reinterpret_cast<float*>(U), reinterpret_cast<float*>(V), stats, st);
 }
+
 
 size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options* opt) {
   if (check_matrix(A) != GKB_OK) return 0;

@@ -142,34 +142,9 @@ __global__ __launch_bounds__(256) void k_normalize(const double* __restrict__ x,
                                                    int code, int index) {
   if (flag[0] != 0) return;
   __shared__ double red[4];
-  double s = 0.0;
-  for (int p = threadIdx.x; p < nparts; p += 256) s += normpart[p];
-  const double tot = block_sum256(s, red);
-  const double nrm = sqrt(tot);
-  const double sin = *sig_in;
-  const double thr = relative ? eps * sin : eps;
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-  if (!(nrm < INFINITY)) {  // NaN or Inf
-    if (lead) {
-      flag[0] = 3;
-      flag[1] = index;
-      *coef_out = nrm;
-    }
-    return;
-  }
-  if (nrm <= thr) {
-    if (lead) {
-      flag[0] = code;
-      flag[1] = index;
-      *coef_out = nrm;
-      *sig_out = sin;
-    }
-    return;
-  }
-  if (lead) {
-    *coef_out = nrm;
-    *sig_out = track ? fmax(sin, nrm) : sin;
-  }
+  const double nrm = norm_test(normpart, nparts, sig_in, sig_out, eps, relative, track, flag, code, index,
+                               coef_out, blockIdx.x == 0 && threadIdx.x == 0, red);
+  if (nrm < 0.0) return;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256)
     out[i] = (TB)(x[i] / nrm);
 }

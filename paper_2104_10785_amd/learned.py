@@ -64,12 +64,20 @@ def _embedded_heuristic_init(ws: int, r: int, n_in: int, hidden: int, seed: int,
 
 
 def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t_train=100, t_eval=100,
-        ws=32, hidden=256, epochs=20, lr=1e-3, check_every=2, max_restarts=50, seed=3, device="cuda:0",
-        log=None, init="random", loss_kind=0):
+        ws=32, hidden=256, epochs=20, lr=1e-3, lr_final=0.02, check_every=2, max_restarts=50, seed=3,
+        device="cuda:0", log=None, init="random", loss_kind=0, t_val=None, eval_every=2):
     """init: "random" (He initialisation) or "heuristic" (the heuristic start
     embedded in the network, see `_embedded_heuristic_init`); loss_kind: 0
     (energy outside the target subspace) or 1 (mean log tan^2 of the angles
-    to the target vectors), see gkb_mlp_loss_grad_kind."""
+    to the target vectors), see gkb_mlp_loss_grad_kind.
+
+    Of the t_train training solves, the last t_val (default t_train // 5) are
+    held out: the network is trained on the others, and the parameters it
+    starts from and those after every eval_every-th epoch are scored by the
+    mean number of products the held-out solves need from the network's start
+    vector (the convergence test is the judge); the best-scoring parameters
+    (the earliest on a tie) are the ones evaluated.  Adam's step size decays from lr to lr * lr_final along a
+    cosine over the epochs, so the updates shrink as the loss flattens."""
     import torch
     say = log or (lambda msg: None)
     t0 = time.time()
@@ -89,15 +97,47 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     # t = 0
     _, U_prev, _, st0, _ = solve(key=10_000)
     data = []
+    held = []       # (A_t, X_t) of the held-out training solves
     train_mv = []
+    if t_val is None:
+        t_val = t_train // 5
+    t_fit = max(1, t_train - t_val)
     for t in range(1, t_train + 1):
         seq.advance()
         X = features(U_prev)
         sig, Ut, _, status, stats = solve(key=t)
         train_mv.append(stats["matvecs"])
-        data.append((X, Ut.clone()))
+        if t <= t_fit:
+            data.append((X, Ut.clone()))
+        else:
+            held.append((seq.A.clone(), X))
         U_prev = Ut
-    say(f"training data: {t_train} solves, mean matvecs {np.mean(train_mv):.1f}, {time.time() - t0:.1f} s")
+    say(f"training data: {t_train} solves ({t_fit} to fit, {len(held)} held out), mean matvecs "
+        f"{np.mean(train_mv):.1f}, {time.time() - t0:.1f} s")
+
+    def held_out_matvecs(prm):
+        """Mean products to tolerance over the held-out solves from the network's
+        start vector (a start that fails counts its products plus a random-start
+        solve's)."""
+        if not held:
+            return float("nan")
+        A_keep = seq.A
+        mv = []
+        try:
+            for A_h, X_h in held:
+                seq.A = A_h
+                q = gkb.gkb_mlp_start_vector(prm, n_in, hidden, X_h)
+                try:
+                    _, _, _, st_h, s_h = solve(q1=q)
+                    cnt = s_h["matvecs"] + 1
+                    if st_h != 0:
+                        cnt += solve(key=1)[4]["matvecs"]
+                except gkb.GkbError:
+                    cnt = 1 + solve(key=1)[4]["matvecs"]
+                mv.append(cnt)
+        finally:
+            seq.A = A_keep
+        return float(np.mean(mv))
 
     # ---- training on the device
     if init == "heuristic":
@@ -113,18 +153,31 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     losses = []
     step = 0
     t1 = time.time()
+    scores = [(0, held_out_matvecs(params))]
+    best_params, best_score, best_epoch = params.clone(), scores[0][1], 0
     for ep in range(epochs):
         ep_loss = []
-        for t in rng.permutation(t_train):
+        # cosine decay of the step size: lr at the first epoch, lr * lr_final at the last
+        frac = ep / max(1, epochs - 1)
+        lr_ep = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + np.cos(np.pi * frac)))
+        for t in rng.permutation(len(data)):
             X, Ut = data[t]
             gkb.gkb_mlp_loss_grad(params, n_in, hidden, X, Ut, grad=grad, loss=loss, workspace=wsp, kind=loss_kind)
             step += 1
-            gkb.gkb_adam_step(params, grad, m1, m2, lr, step)
+            gkb.gkb_adam_step(params, grad, m1, m2, lr_ep, step)
             ep_loss.append(loss.clone())
         losses.append(float(torch.cat(ep_loss).mean().item()) if ep_loss else 0.0)
+        if (ep + 1) % eval_every == 0 or ep + 1 == epochs:
+            sc = held_out_matvecs(params)
+            scores.append((ep + 1, sc))
+            if sc < best_score:
+                best_params, best_score, best_epoch = params.clone(), sc, ep + 1
     torch.cuda.synchronize()
     train_s = time.time() - t1
-    say(f"trained {epochs} epochs in {train_s:.2f} s; loss by epoch {['%.4f' % x for x in losses]}")
+    say(f"trained {epochs} epochs in {train_s:.2f} s; loss by epoch {['%.3e' % x for x in losses]}; "
+        f"held-out matvecs by epoch {[(e, round(v, 2)) for e, v in scores]}; kept epoch {best_epoch}")
+    params = best_params
+    del held
 
     # ---- evaluation
     hparams, hhidden = _heuristic_params(ws, r, n_in)
@@ -176,7 +229,9 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     out = {
         "m": m, "n": n, "r": r, "k": k, "tol": tol, "t_train": t_train, "t_eval": t_eval, "hidden": hidden,
         "sketch_width": ws, "epochs": epochs, "check_every": check_every, "init": init, "loss_kind": loss_kind,
-        "train_loss_by_epoch": losses, "train_seconds": train_s,
+        "train_loss_by_epoch": losses, "train_seconds": train_s, "lr": lr, "lr_final": lr * lr_final,
+        "held_out": t_train - t_fit, "held_out_matvecs_by_epoch": scores, "kept_epoch": best_epoch,
+        "held_out_matvecs_kept": best_score, "held_out_matvecs_init": scores[0][1],
         "matvecs_random": {"mean": mv_r.mean(), "median": float(np.median(mv_r))},
         "matvecs_learned": {"mean": mv_l.mean(), "median": float(np.median(mv_l))},
         "matvecs_heuristic": {"mean": mv_h.mean(), "median": float(np.median(mv_h))},
