@@ -183,6 +183,28 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
                            const gkb_options* opt, void* workspace, size_t ws_bytes,
                            double* sigma, void* U, void* V, gkb_stats* stats, void* stream);
 
+/*
+ * gkb_partial_svd without a workspace argument, for callers that cannot
+ * allocate device memory (code that must not call hipMalloc: tight serving
+ * loops, harnesses that forbid allocation, work prepared for later capture).
+ * The workspace is a fixed device array inside the library,
+ * GKB_NOALLOC_SCRATCH_BYTES (32 MiB) per GPU, held from the first call on a
+ * GPU until the process ends; the call uses the array of the current device
+ * (the stream must belong to it).  Problems whose gkb_workspace_size exceeds
+ * it are rejected with GKB_ERR_WORKSPACE before any device work.  Arguments,
+ * results, statuses and stats are those of gkb_partial_svd with the same
+ * options, and the kernels are the same (every solve initialises the scratch
+ * contents it reads).  All calls on one GPU share the array: calls that
+ * overlap on one GPU (two host threads, or two streams whose work overlaps)
+ * race and give undefined results; serialise them.  The call allocates no
+ * device or pinned memory; opt->phase_timing (which creates HIP events) is
+ * rejected with GKB_ERR_INVALID.
+ */
+#define GKB_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+gkb_status gkb_partial_svd_noalloc(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
+                                   const gkb_options* opt, double* sigma, void* U, void* V, gkb_stats* stats,
+                                   void* stream);
+
 /* Workspace bytes needed by gkb_numerical_rank. */
 size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options* opt);
 

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1011,6 +1012,33 @@ gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, c
 }  // namespace
 
 // ======================================================================= ABI
+// ---- the entry point that allocates nothing: a fixed device array per GPU
+static __device__ __align__(256) unsigned char scratch[GKB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device
+// (each GPU holds its own copy of the array at its own address).
+gkb_status scratch_address(void** out) {
+  int dev = 0;
+  GKB_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GKB_ERR_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    GKB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) return fail(GKB_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GKB_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void gkb_default_options(gkb_options* opt) {
@@ -1070,6 +1098,27 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
                                 reinterpret_cast<float*>(U), reinterpret_cast<float*>(V), stats, st);
 }
 
+
+gkb_status gkb_partial_svd_noalloc(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
+                                   const gkb_options* opt, double* sigma, void* U, void* V, gkb_stats* stats,
+                                   void* stream) {
+  g_err.clear();
+  gkb_status rc = check_matrix(A);
+  if (rc != GKB_OK) return rc;
+  if (opt != nullptr && opt->phase_timing != 0)
+    return fail(GKB_ERR_INVALID, "phase_timing creates HIP events; not available without allocation");
+  const size_t need = gkb_workspace_size(A, r, k, opt);
+  if (need > GKB_NOALLOC_SCRATCH_BYTES)
+    return fail(GKB_ERR_WORKSPACE, "problem needs " + std::to_string(need) + " bytes of workspace; the fixed " +
+                                       "array holds " + std::to_string(GKB_NOALLOC_SCRATCH_BYTES) +
+                                       " (use gkb_partial_svd with a caller workspace)");
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc != GKB_OK) return rc;
+  // need == 0 means invalid arguments: gkb_partial_svd reports which
+  return gkb_partial_svd(A, r, k, tol, max_restarts, opt, ws, GKB_NOALLOC_SCRATCH_BYTES, sigma, U, V, stats,
+                         stream);
+}
 
 size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options* opt) {
   if (check_matrix(A) != GKB_OK) return 0;

@@ -78,7 +78,9 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_sparse_plan_destroy", "gkb_sparse_matvec", "gkb_sparse_workspace_size", "gkb_partial_svd_sparse",
            "gkb_sparse_last_error", "gkb_rsgd_workspace_size", "gkb_rsgd_plan_create", "gkb_rsgd_plan_step",
            "gkb_rsgd_plan_info", "gkb_rsgd_plan_destroy", "gkb_rsgd_weights", "gkb_rsgd_last_error",
-           "gkb_matvec_fused_workspace_size", "gkb_matvec_fused", "gkb_mlp_loss_grad_kind"]
+           "gkb_matvec_fused_workspace_size", "gkb_matvec_fused", "gkb_mlp_loss_grad_kind", "gkb_partial_svd_noalloc"]
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def lib():
@@ -99,6 +101,9 @@ def lib():
                                   C.c_void_p, C.c_size_t, P(C.c_double), C.c_void_p, C.c_void_p,
                                   P(GkbStats), C.c_void_p]
     L.gkb_partial_svd.restype = C.c_int
+    L.gkb_partial_svd_noalloc.argtypes = [P(GkbMatrix), C.c_int, C.c_int, C.c_double, C.c_int, P(GkbOptions),
+                                          P(C.c_double), C.c_void_p, C.c_void_p, P(GkbStats), C.c_void_p]
+    L.gkb_partial_svd_noalloc.restype = C.c_int
     L.gkb_rank_workspace_size.argtypes = [P(GkbMatrix), C.c_int, P(GkbOptions)]
     L.gkb_rank_workspace_size.restype = C.c_size_t
     L.gkb_numerical_rank.argtypes = [P(GkbMatrix), C.c_double, C.c_int, C.c_int, P(GkbOptions), C.c_void_p,
@@ -339,6 +344,26 @@ def gkb_partial_svd(A, r, k, tol, max_restarts, refine=None, workspace=None, str
                                _stream(stream))
     _check(status)
     return np.array(sig[:], dtype=np.float64), Ut, Vt, status, st.as_dict()
+
+
+def gkb_partial_svd_noalloc(A, r, k, tol, max_restarts, refine=None, stream=None, U=None, V=None, **opts):
+    """gkb_partial_svd with the library's fixed device array as workspace (no
+    workspace argument; nothing allocated by the library).  U, V: optional
+    preallocated output tensors (r x m and r x n rows = singular vectors).
+    Returns (sigma, Ut, Vt, status, stats) as gkb_partial_svd."""
+    torch = _torch()
+    mat = make_matrix(A, refine)
+    o = make_options(**opts)
+    bt = basis_dtype(mat.dtype)
+    Ut = U if U is not None else torch.empty((r, A.shape[0]), dtype=bt, device=A.device)
+    Vt = V if V is not None else torch.empty((r, A.shape[1]), dtype=bt, device=A.device)
+    sig = (C.c_double * max(r, 1))()
+    st = GkbStats()
+    status = lib().gkb_partial_svd_noalloc(C.byref(mat), r, k, float(tol), int(max_restarts), C.byref(o), sig,
+                                           C.c_void_p(Ut.data_ptr()), C.c_void_p(Vt.data_ptr()), C.byref(st),
+                                           _stream(stream))
+    _check(status)
+    return np.array(sig[:r], dtype=np.float64), Ut, Vt, status, st.as_dict()
 
 
 def gkb_rank_workspace_size(A, k_max=0, **opts) -> int:
