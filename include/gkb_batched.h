@@ -48,6 +48,10 @@ typedef struct {
   int threads;              /* workgroup size, 512 or 1024; 0 = 1024               */
   int max_team;             /* largest team of workgroups on one problem (1..8);   */
                             /*    0 = 8, 1 = every problem on one workgroup         */
+  int form;                 /* compiled form of the products and Gram-Schmidt     */
+                            /*    kernels: 0 = by size (out of line when the      */
+                            /*    problems average >= 2 MB of A), 1 = inline,      */
+                            /*    2 = out of line.  Same results either way.       */
 } gkb_batch_options;
 
 typedef struct gkb_batch_plan_s* gkb_batch_plan;

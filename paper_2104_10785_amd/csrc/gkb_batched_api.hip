@@ -154,6 +154,7 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   if (opt.threads != 0 && opt.threads != 512 && opt.threads != 1024)
     return bfail(GKB_ERR_INVALID, "threads must be 0, 512 or 1024");
   if (opt.max_team < 0) return bfail(GKB_ERR_INVALID, "max_team must be >= 0");
+  if (opt.form < 0 || opt.form > 2) return bfail(GKB_ERR_INVALID, "form must be 0, 1 or 2");
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -272,7 +273,7 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   {
     double abytes = 0.0;
     for (int i = 0; i < batch; ++i) abytes += 4.0 * plan->table[i].m * plan->table[i].n;
-    prm.outline = abytes / batch >= OUTLINE_MIN_BYTES ? 1 : 0;
+    prm.outline = opt.form == 1 ? 0 : (opt.form == 2 ? 1 : (abytes / batch >= OUTLINE_MIN_BYTES ? 1 : 0));
   }
   prm.pool = reinterpret_cast<float*>(ws + L.pool);
   prm.work = reinterpret_cast<double*>(ws + L.work);

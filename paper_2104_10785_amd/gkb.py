@@ -41,7 +41,7 @@ class GkbOptions(C.Structure):
 class GkbBatchOptions(C.Structure):
     _fields_ = [("check_every", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
                 ("seed", C.c_uint64), ("q1_packed", C.c_void_p), ("workgroups", C.c_int), ("no_graph", C.c_int),
-                ("threads", C.c_int), ("max_team", C.c_int)]
+                ("threads", C.c_int), ("max_team", C.c_int), ("form", C.c_int)]
 
 
 class GkbCsr(C.Structure):
@@ -543,7 +543,8 @@ class BatchPlan:
     """
 
     def __init__(self, As, r, k, tol, max_restarts, check_every=0, seed=0, q1=None, workgroups=0,
-                 no_graph=False, eps_break=0.0, threads=0, stream=None, tune=False, tune_cache=None, max_team=0):
+                 no_graph=False, eps_break=0.0, threads=0, stream=None, tune=False, tune_cache=None, max_team=0,
+                 form=0):
         torch = _torch()
         L = lib()
         self.batch = len(As)
@@ -570,6 +571,7 @@ class BatchPlan:
         o.eps_break = eps_break
         o.threads = threads
         o.max_team = max_team
+        o.form = form
         self.q1 = q1
         if q1 is not None:
             o.q1_packed = q1.data_ptr()

@@ -115,6 +115,36 @@ def test_batched_graph_replays_match_eager():
     graph.close()
 
 
+def test_batched_inline_and_outline_forms_agree():
+    """The two compiled forms of the persistent kernel (products and
+    Gram-Schmidt kernels inline, or out of line with deeper loads) give bitwise
+    the same results, statuses and counts; the batch includes problems large
+    enough to be solved by teams of workgroups."""
+    device()
+    mats, rs, ks = small_batch(8, seed=31)
+    for j, (m, n) in enumerate([(2100, 900), (1600, 700)]):
+        mats.append(inputs.svd_matrix(m, n, np.geomspace(1, 1e-3, n), seed=40 + j)[0].astype(np.float32))
+        rs.append(10)
+        ks.append(30)
+    banner("batched inline vs out-of-line forms, with teams")
+    Ad = [to_dev(A) for A in mats]
+    out = []
+    for form in (1, 2):
+        plan = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=3, check_every=5, form=form)
+        plan.run()
+        info = plan.info()
+        res = [(s.copy(), to_host(u), to_host(v)) for s, u, v in plan.results()]
+        out.append((info, res))
+        plan.close()
+    (i1, r1), (i2, r2) = out
+    assert np.array_equal(i1, i2)
+    assert i1[8, 0] == 2 and np.all(np.delete(i1[:, 0], 8) == 0)  # problem 8: the rank-deficient product
+    for (s1, u1, v1), (s2, u2, v2) in zip(r1, r2):
+        assert np.array_equal(s1, s2) and np.array_equal(u1, u2) and np.array_equal(v1, v2)
+    with pytest.raises(gkb.GkbError):
+        gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, form=3)
+
+
 def test_batched_validation():
     device()
     banner("batched validation")
