@@ -98,8 +98,9 @@ typedef struct {
                        /* paper's Algorithm 2)                                 */
   int one_pass;        /* 1: read A once per step instead of twice (GKB_F32   */
                        /* or GKB_BF16 with n, lda multiples of 4 or 8,         */
-                       /* n <= 24576, A 16-byte aligned; else                  */
-                       /* GKB_ERR_INVALID).  One sweep forms                   */
+                       /* n <= 24576, A 16-byte aligned; for any other A,      */
+                       /* including sparse A, the two-product step runs and    */
+                       /* stats.one_pass_used is 0).  One sweep forms          */
                        /* A p and A^T A p in float64; A^T q_{i+1} then follows */
                        /* from eq. (2.2) as (A^T A p - (A^T Q) c) / beta, with */
                        /* c the recurrence and Gram-Schmidt coefficients and   */
@@ -150,6 +151,8 @@ typedef struct {
                        /* per step, one per sweep with one_pass, plus          */
                        /* recomputed columns and the start) x the bytes of A   */
                        /* (nonzero values and column indices for sparse A)     */
+  int one_pass_used;   /* 1 if the one-sweep step ran (opt.one_pass and an A   */
+                       /* it supports), 0 for the two-product step             */
 } gkb_stats;
 
 /* Fill *opt with the defaults above. */

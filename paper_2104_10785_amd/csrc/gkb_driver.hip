@@ -137,6 +137,13 @@ gkb_status check_matrix(const gkb_matrix* A) {
   return GKB_OK;
 }
 
+// The one-sweep step runs on dense float32 or bfloat16 A whose rows the sweep
+// kernels hold (n <= 24576, n and lda multiples of the 16-byte group, A
+// 16-byte aligned); elsewhere a one_pass request runs the two-product step.
+bool one_pass_available(const gkb_matrix* A) {
+  return gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype);
+}
+
 gkb_status check_workspace(void* ws, size_t bytes, size_t need) {
   if (ws == nullptr) return fail(GKB_ERR_WORKSPACE, "workspace is NULL");
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
@@ -922,6 +929,7 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     stats->krylov_dim = pr.np;
     stats->refined = refined;
     stats->ms_refine = ms_refine;
+    stats->one_pass_used = onepass ? 1 : 0;
     S.pt.fill(stats);
   }
   if (r_eff < r) return GKB_RANK_DEFICIENT;
@@ -1004,6 +1012,7 @@ gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, c
     stats->sigma1_est = np > 0 ? s[0] : 0.0;
     stats->ms_total = now_ms() - t0;
     stats->ms_host = ms_host;
+    stats->one_pass_used = onepass ? 1 : 0;
     S.pt.fill(stats);
   }
   return GKB_OK;
@@ -1051,8 +1060,7 @@ void gkb_default_options(gkb_options* opt) {
 size_t gkb_workspace_size(const gkb_matrix* A, int r, int k, const gkb_options* opt) {
   if (check_matrix(A) != GKB_OK) return 0;
   if (r < 1 || k < r || k > std::min(A->m, A->n)) return 0;
-  const bool onepass = opt != nullptr && opt->one_pass != 0;
-  if (onepass && !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype)) return 0;
+  const bool onepass = opt != nullptr && opt->one_pass != 0 && one_pass_available(A);
   return make_layout(A->m, A->n, A->dtype, k, k > r, true, A->dtype == GKB_BF16 && A->refine_f32 != nullptr,
                      true, onepass)
       .total;
@@ -1071,9 +1079,7 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
   gkb_options opt;
   gkb_default_options(&opt);
   if (opt_in) opt = *opt_in;
-  if (opt.one_pass && !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
-    return fail(GKB_ERR_INVALID, "one_pass needs a float32 (bfloat16) A with n and lda multiples of 4 (8), "
-                                 "n <= 24576, 16-byte aligned");
+  if (opt.one_pass && !one_pass_available(A)) opt.one_pass = 0;  // the two-product step instead
   if (sigma == nullptr || U == nullptr || V == nullptr)
     return fail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
   if (opt.keep != 0 && (opt.keep < r || opt.keep >= k))
@@ -1125,8 +1131,7 @@ size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options
   const int64_t kmin = std::min(A->m, A->n);
   const int64_t k = k_max ? k_max : kmin;
   if (k < 1 || k > kmin) return 0;
-  const bool onepass = opt != nullptr && opt->one_pass != 0;
-  if (onepass && !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype)) return 0;
+  const bool onepass = opt != nullptr && opt->one_pass != 0 && one_pass_available(A);
   return make_layout(A->m, A->n, A->dtype, (int)k, false, false, false, true, onepass).total;
 }
 
@@ -1146,9 +1151,7 @@ gkb_status gkb_numerical_rank(const gkb_matrix* A, double tau, int tau_relative,
   gkb_default_options(&opt);
   if (opt_in) opt = *opt_in;
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
-  if (opt.one_pass && !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
-    return fail(GKB_ERR_INVALID, "one_pass needs a float32 (bfloat16) A with n and lda multiples of 4 (8), "
-                                 "n <= 24576, 16-byte aligned");
+  if (opt.one_pass && !one_pass_available(A)) opt.one_pass = 0;  // the two-product step instead
   rc = check_workspace(workspace, ws_bytes, gkb_rank_workspace_size(A, (int)k, &opt));
   if (rc != GKB_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -1184,7 +1187,7 @@ gkb_status gkb_partial_svd_sparse(gkb_sparse_plan plan, int r, int k, double tol
   if (opt.keep != 0 && (opt.keep < r || opt.keep >= k)) return fail(GKB_ERR_INVALID, "need r <= keep < k");
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
   if (opt.check_every < 0) return fail(GKB_ERR_INVALID, "need check_every >= 0");
-  if (opt.one_pass) return fail(GKB_ERR_INVALID, "one_pass needs a dense float32 A");
+  opt.one_pass = 0;  // sparse A: always the two CSR products (stats.one_pass_used = 0)
   gkb_status rc = check_workspace(workspace, ws_bytes, gkb_sparse_workspace_size(plan, r, k));
   if (rc != GKB_OK) return rc;
   // the dense descriptor only carries the shape and the float32 basis type

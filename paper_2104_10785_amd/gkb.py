@@ -57,7 +57,7 @@ class GkbStats(C.Structure):
                 ("krylov_dim", C.c_int), ("refined", C.c_int), ("ms_refine", C.c_double),
                 ("refreshes", C.c_int), ("ms_matvec", C.c_double), ("ms_reorth", C.c_double),
                 ("ms_sync", C.c_double), ("ms_ritz", C.c_double), ("ms_other", C.c_double),
-                ("bytes_A", C.c_double)]
+                ("bytes_A", C.c_double), ("one_pass_used", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -199,10 +199,12 @@ def _options(**kw):
     return o
 
 
-def test_one_pass_validation_and_workspace():
-    """The one-sweep option is checked on the host: float32 needs n and lda
-    multiples of 4, bfloat16 multiples of 8, n <= 24576 and a 16-byte aligned
-    A; float64 is refused.  Its workspace holds float64 bases and A^T Q."""
+def test_one_pass_availability_and_workspace():
+    """The one-sweep step needs float32 with n and lda multiples of 4 (bfloat16:
+    8), n <= 24576 and a 16-byte aligned A; for any other A a one_pass request
+    takes the two-product step, so it passes the option checks (and here stops
+    at the missing workspace) and its workspace is the two-product one.  The
+    one-sweep workspace holds float64 bases and A^T Q."""
     L = gkb.lib()
     one = _options(one_pass=1)
     two = _options()
@@ -211,16 +213,18 @@ def test_one_pass_validation_and_workspace():
     def svd(mat):
         return L.gkb_partial_svd(C.byref(mat), 2, 4, 1e-6, 0, C.byref(one), None, 0, sig, 0x2000, 0x3000, None,
                                  None)
-    assert svd(_fake_matrix(n=50)) == -1                            # n % 4
-    assert svd(_fake_matrix(n=52, lda=54)) == -1                    # lda % 4
-    assert svd(_fake_matrix(n=52, data=0x1004)) == -1               # alignment
-    assert svd(_fake_matrix(n=52, dtype=gkb.GKB_F64)) == -1         # float64
-    assert svd(_fake_matrix(n=52, dtype=gkb.GKB_BF16)) == -1        # bfloat16 needs n % 8
-    assert svd(_fake_matrix(m=100, n=24580)) == -1                  # n > 24576
-    assert "one_pass" in gkb.last_error()
-    for bad in (_fake_matrix(n=50), _fake_matrix(n=52, dtype=gkb.GKB_F64), _fake_matrix(n=52, data=0x1004)):
-        assert L.gkb_workspace_size(C.byref(bad), 2, 4, C.byref(one)) == 0
-        assert L.gkb_rank_workspace_size(C.byref(bad), 0, C.byref(one)) == 0
+    others = [_fake_matrix(n=50),                       # n % 4
+              _fake_matrix(n=52, lda=54),               # lda % 4
+              _fake_matrix(n=52, data=0x1004),          # alignment
+              _fake_matrix(n=52, dtype=gkb.GKB_F64),    # float64
+              _fake_matrix(n=52, dtype=gkb.GKB_BF16),   # bfloat16 needs n % 8
+              _fake_matrix(m=100, n=24580)]             # n > 24576
+    for bad in others:
+        assert svd(bad) == -4 and "workspace" in gkb.last_error()
+        assert L.gkb_workspace_size(C.byref(bad), 2, 4, C.byref(one)) == \
+            L.gkb_workspace_size(C.byref(bad), 2, 4, C.byref(two)) > 0
+        assert L.gkb_rank_workspace_size(C.byref(bad), 0, C.byref(one)) == \
+            L.gkb_rank_workspace_size(C.byref(bad), 0, C.byref(two)) > 0
     good = _fake_matrix(50000, 20000, gkb.GKB_F32)
     w1 = L.gkb_workspace_size(C.byref(good), 50, 120, C.byref(one))
     w2 = L.gkb_workspace_size(C.byref(good), 50, 120, C.byref(two))

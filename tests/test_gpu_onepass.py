@@ -188,18 +188,29 @@ def test_onepass_deterministic():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
-def test_onepass_rejects_other_inputs():
+def test_onepass_falls_back_to_two_products():
+    """Where the one-sweep step is not available (n not a multiple of 4, a
+    float64 A, rows longer than the sweep holds) a one_pass request runs the
+    two-product step: bitwise the same results as without the request, and
+    stats say which step ran."""
     device()
-    banner("one-pass argument checks")
+    banner("one-pass fallback to the two-product step")
     rng = np.random.default_rng(0)
-    with pytest.raises(gkb.GkbError):
-        gkb.gkb_partial_svd(to_dev(rng.standard_normal((50, 30)).astype(np.float32)), 2, 6, 1e-6, 2, one_pass=True)
-    with pytest.raises(gkb.GkbError):
-        gkb.gkb_partial_svd(to_dev(rng.standard_normal((50, 32))), 2, 6, 1e-6, 2, one_pass=True)
-    with pytest.raises(gkb.GkbError):
-        gkb.gkb_numerical_rank(to_dev(rng.standard_normal((50, 30)).astype(np.float32)), 1e-3, one_pass=True)
-    with pytest.raises(gkb.GkbError):
-        gkb.gkb_numerical_rank(to_dev(rng.standard_normal((50, 32))), 1e-3, one_pass=True)
+    cases = [rng.standard_normal((50, 30)).astype(np.float32), rng.standard_normal((50, 32)),
+             rng.standard_normal((40, 24580)).astype(np.float32)]
+    for A in cases:
+        Ad = to_dev(A)
+        q = to_dev(rng.standard_normal(A.shape[0]))
+        a = gkb.gkb_partial_svd(Ad, 2, 6, 1e-6, 2, q1=q, one_pass=True)
+        b = gkb.gkb_partial_svd(Ad, 2, 6, 1e-6, 2, q1=q)
+        assert a[4]["one_pass_used"] == 0 and b[4]["one_pass_used"] == 0
+        assert a[3] == b[3] and np.array_equal(a[0], b[0])
+        assert np.array_equal(to_host(a[1]), to_host(b[1])) and np.array_equal(to_host(a[2]), to_host(b[2]))
+        ra = gkb.gkb_numerical_rank(Ad, 1e-3, q1=q, one_pass=True)
+        rb = gkb.gkb_numerical_rank(Ad, 1e-3, q1=q)
+        assert ra[0] == rb[0] and np.array_equal(ra[2], rb[2]) and ra[4]["one_pass_used"] == 0
+    A = rng.standard_normal((64, 48)).astype(np.float32)
+    assert gkb.gkb_partial_svd(to_dev(A), 2, 6, 1e-6, 2, one_pass=True)[4]["one_pass_used"] == 1
 
 
 @pytest.mark.parametrize("check_every", [0, 10])
