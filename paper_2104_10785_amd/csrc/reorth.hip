@@ -37,6 +37,7 @@ namespace {
 
 constexpr int GS_T = 256;                 // threads per workgroup
 constexpr int GS_HCH = 1024;              // coefficients held in LDS at a time
+constexpr int GS_COLS = 32;               // columns per workgroup in the first launch's dots
 constexpr size_t GS_STAGE_BYTES = 120 * 1024;  // basis slice staged in LDS up to this size
 constexpr size_t GS_LDS_MAX = 160 * 1024;
 // below GS_WIDE_G slices, a pass with more than GS_WIDE_WORK basis entries per
@@ -124,15 +125,17 @@ __device__ void gs_update(const TB* __restrict__ V, int64_t ldv, const TB* Vs, i
   __syncthreads();
 }
 
-// Pout[j] = sum over the slice rows of V[j][i] xs[i], j < t: wave w takes
-// columns w*8 .. w*8+7, then +32; lanes stride the rows, two rows per lane at a
-// time, so sixteen loads per lane are in flight; one wave reduction per column.
+// Pout[j] = sum over the slice rows of V[j][i] xs[i], jb <= j < je (default
+// all t): wave w takes columns jb + w*8 .. jb + w*8+7, then +32; lanes stride
+// the rows, two rows per lane at a time, so sixteen loads per lane are in
+// flight; one wave reduction per column.
 template <typename TB, bool STAGED>
 __device__ void gs_dots(const TB* __restrict__ V, int64_t ldv, const TB* Vs, int t, int64_t r0, int nr,
-                        const double* xs, double* __restrict__ Pout) {
+                        const double* xs, double* __restrict__ Pout, int jb = 0, int je = -1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j0 = wave * 8; j0 < t; j0 += 32) {
-    const int nj = min(8, t - j0);
+  if (je < 0) je = t;
+  for (int j0 = jb + wave * 8; j0 < je; j0 += 32) {
+    const int nj = min(8, je - j0);
     double a[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) a[c] = 0.0;
@@ -190,23 +193,28 @@ __global__ __launch_bounds__(GS_T) void k_gs_first(const TB* __restrict__ V, int
   double* hs = xs + rows;
   double* cp = hs + GS_HCH + 256;
   const Slice S = slice_of(len, rows);
+  // blockIdx.y: a block of 32 columns of the dots; every column block forms the
+  // slice (the same values), the first one writes it back
+  const bool writer = blockIdx.y == 0;
   const bool sum_parts = PRE == GS_PRE_TSUM || (PRE == GS_PRE_FIX && run_if[0] != 0);
   for (int i = threadIdx.x; i < S.nr; i += GS_T) {
     const int64_t gi = S.r0 + i;
     double v;
     if (sum_parts) {
-      // the row-block partial sums of A^T q, added as four interleaved sums
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int b = 0;
-      for (; b + 4 <= nparts; b += 4) {
-        s0 += (double)part[(int64_t)b * ldpart + gi];
-        s1 += (double)part[(int64_t)(b + 1) * ldpart + gi];
-        s2 += (double)part[(int64_t)(b + 2) * ldpart + gi];
-        s3 += (double)part[(int64_t)(b + 3) * ldpart + gi];
+      // the row-block partial sums of A^T q, added as eight interleaved sums
+      // (eight loads in flight per thread), combined in a fixed order
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = 0.0;
+      for (int b = 0; b < nparts; b += 8) {
+        double pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pv[u] = b + u < nparts ? (double)part[(int64_t)(b + u) * ldpart + gi] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += pv[u];
       }
-      for (; b < nparts; ++b) s0 += (double)part[(int64_t)b * ldpart + gi];
-      v = (s0 + s1) + (s2 + s3);
-      if (PRE == GS_PRE_FIX) gcol[gi] = v;
+      v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+      if (PRE == GS_PRE_FIX && writer) gcol[gi] = v;
       if (prev != nullptr) v -= coef[cidx] * (double)prev[gi];
     } else {
       v = x[gi];
@@ -218,10 +226,11 @@ __global__ __launch_bounds__(GS_T) void k_gs_first(const TB* __restrict__ V, int
   }
   __syncthreads();
   if constexpr (PRE == GS_PRE_RHO) gs_update<TB, false>(V, ldv, nullptr, 0, l, S.r0, S.nr, xs, hs, cp);
-  if (PRE == GS_PRE_RHO || sum_parts) {
+  if (writer && (PRE == GS_PRE_RHO || sum_parts)) {
     for (int i = threadIdx.x; i < S.nr; i += GS_T) x[S.r0 + i] = xs[i];
   }
-  gs_dots<TB, false>(V, ldv, nullptr, t, S.r0, S.nr, xs, P1 + (int64_t)blockIdx.x * ldh);
+  const int jb = blockIdx.y * GS_COLS;
+  gs_dots<TB, false>(V, ldv, nullptr, t, S.r0, S.nr, xs, P1 + (int64_t)blockIdx.x * ldh, jb, min(t, jb + GS_COLS));
 }
 
 // Middle launch: slice -= V h1, then the partial dots P2 of the updated slice.
@@ -239,11 +248,22 @@ __global__ __launch_bounds__(GS_T) void k_gs_mid(const TB* __restrict__ V, int64
   const Slice S = slice_of(len, rows);
   for (int i = threadIdx.x; i < S.nr; i += GS_T) xs[i] = x[S.r0 + i];
   if constexpr (STAGED) {
+    // the basis slice into LDS, eight loads in flight per thread
     const int64_t tot = (int64_t)t * S.nr;
-    for (int64_t e = threadIdx.x; e < tot; e += GS_T) {
-      const int j = (int)(e / S.nr);
-      const int i = (int)(e - (int64_t)j * S.nr);
-      Vs[e] = V[(int64_t)j * ldv + S.r0 + i];
+    for (int64_t e0 = threadIdx.x; e0 < tot; e0 += 8 * GS_T) {
+      TB vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = e0 + (int64_t)u * GS_T;
+        const int j = (int)(e / S.nr);
+        const int i = (int)(e - (int64_t)j * S.nr);
+        vv[u] = e < tot ? V[(int64_t)j * ldv + S.r0 + i] : (TB)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = e0 + (int64_t)u * GS_T;
+        if (e < tot) Vs[e] = vv[u];
+      }
     }
   }
   for (int c0 = 0; c0 < t; c0 += GS_HCH) {
@@ -304,7 +324,8 @@ hipError_t launch_first(const TB* V, int64_t ldv, int t, int64_t len, const GsSp
   auto kern = k_gs_first<TB, TP, PRE>;
   static const hipError_t attr = allow_lds(kern);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(s.G), dim3(GS_T), gs_lds_base(s.rows), st, V, ldv, t, len, s.rows, x, P1, ldh,
+  const unsigned cb = (unsigned)std::max(1, (t + GS_COLS - 1) / GS_COLS);
+  hipLaunchKernelGGL(kern, dim3(s.G, cb), dim3(GS_T), gs_lds_base(s.rows), st, V, ldv, t, len, s.rows, x, P1, ldh,
                      pre.rho, pre.l, reinterpret_cast<const TP*>(pre.part), pre.ldpart, pre.nparts,
                      reinterpret_cast<const TB*>(pre.prev), pre.coef, pre.cidx, pre.run_if, pre.gcol, flag);
   return hipGetLastError();
