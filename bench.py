@@ -105,23 +105,34 @@ def fused_operands(gkb, torch, Ad, dev):
     return p, w, y, ws
 
 
-def kernels_only(gkb, torch, Ad, dev, stream, reps):
+def kernels_only(gkb, torch, Ad, dev, stream, reps, f64=False):
     """The A-streaming kernels alone (reps launches each: A p, A^T q, and the
     one-sweep pair A p, A^T A p) and a plain 1 GiB device copy (3 launches)
-    whose counter readings calibrate the traffic figures."""
+    whose counter readings calibrate the traffic figures.  f64: the same
+    matrix upcast to float64 (8.0 GB), the two products only (the one-sweep
+    pair holds float32 or bfloat16 rows)."""
+    if f64:
+        Ad = Ad.double()
     mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=dev)
     xn, xm, yn, ym = matvec_operands(torch, Ad, dev)
+    if f64:
+        xn, xm = xn.double(), xm.double()
     ms_n = time_kernel(lambda: gkb.gkb_matvec(Ad, xn, 0, y=yn, stream=stream), reps, stream)
     ms_t = time_kernel(lambda: gkb.gkb_matvec(Ad, xm, 1, y=ym, workspace=mws, stream=stream), reps, stream)
-    fp, fw, fy, fws = fused_operands(gkb, torch, Ad, dev)
-    ms_f = time_kernel(lambda: gkb.gkb_matvec_fused(Ad, fp, fw, fy, fws, stream=stream), reps, stream)
-    ritz = ritz_gemms(gkb, torch, dev, stream, reps)
+    ms_f, ritz = None, None
+    if not f64:
+        fp, fw, fy, fws = fused_operands(gkb, torch, Ad, dev)
+        ms_f = time_kernel(lambda: gkb.gkb_matvec_fused(Ad, fp, fw, fy, fws, stream=stream), reps, stream)
+        ritz = ritz_gemms(gkb, torch, dev, stream, reps)
     src = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"kernels_only": True, "gemv_n_ms": ms_n, "gemv_t_ms": ms_t, "gemv_fused_ms": ms_f,
+    es = Ad.element_size()
+    print(json.dumps({"kernels_only": True, "dtype": "f64" if f64 else "f32", "gemv_n_ms": ms_n, "gemv_t_ms": ms_t,
+                      "gemv_n_GBps": (M * N * es + N * es + M * 8) / (ms_n * 1e-3) / 1e9,
+                      "gemv_t_GBps": (M * N * es + M * es + N * 8) / (ms_t * 1e-3) / 1e9, "gemv_fused_ms": ms_f,
                       "reps": reps, "ritz_gemms": ritz, "copy_bytes": 2 ** 30,
                       "source_digest": kernel_source_digest("gemv_n"),
                       "fused_source_digest": kernel_source_digest("gemv_fused")}), flush=True)
@@ -574,6 +585,7 @@ def main():
                     help="extra legs after the main timing (comma list; empty for none)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the two matvec kernels and a 1 GiB copy (for counter runs)")
+    ap.add_argument("--f64", action="store_true", help="with --kernels-only: the float64 upcast of the matrix")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the Golub-Kahan path on a single "
@@ -597,7 +609,7 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     if args.kernels_only:
-        kernels_only(gkb, torch, Ad, dev, stream, args.kernel_reps)
+        kernels_only(gkb, torch, Ad, dev, stream, args.kernel_reps, f64=args.f64)
         return
 
     def step(check_every=args.check_every, one_pass=one_pass):
