@@ -87,9 +87,10 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
   const int64_t part_rows = dense && !onepass ? std::min<int64_t>(gkb::GEMV_T_MAX_BLOCKS, (m + 63) / 64) : 0;
   L.ldpart = L.ldn;
   L.part = take((size_t)part_rows * L.ldpart * acc);
-  // Gram-Schmidt partial dots: two sets (one per pass) of one row per workgroup
-  const int gsg = std::max(gkb::gs_split(m).G, gkb::gs_split(n).G);
-  L.gsp = take((size_t)(2 * gsg + 1) * L.ldh * 8);
+  // Gram-Schmidt partial dots (two sets of one row per slice, or the column-spread
+  // form's chunk partials) and the reduced coefficients
+  const int64_t gsr = std::max(gkb::gs_partial_rows(m), gkb::gs_partial_rows(n));
+  L.gsp = take((size_t)gsr * L.ldh * 8);
   L.normpart = take((size_t)std::max(gkb::update_blocks(m), gkb::update_blocks(n)) * 8);
   L.qcoef = take((size_t)(L.kcols + 1) * 8);
   L.pcoef = take((size_t)(L.kcols + 1) * 8);

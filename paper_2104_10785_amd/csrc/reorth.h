@@ -21,6 +21,10 @@ struct GsSplit {
   int64_t rows;
 };
 GsSplit gs_split(int64_t len);
+// Rows of ldh doubles launch_gs2 needs in gsp for a vector of length len:
+// two sets of slice partials or the column-spread form's chunk partials,
+// whichever is larger, plus one row for the reduced coefficients.
+int64_t gs_partial_rows(int64_t len);
 
 // What the first launch does before its dot products.
 enum GsPre {
@@ -53,8 +57,8 @@ struct GsPreArgs {
 //           basis slice staged in LDS when it fits: read once for both uses)
 //   reduce: h2 = sum of P2
 //   last:   slice -= V h2, npart[b] = sum of x^2 over workgroup b's slice
-// acc (optional): acc[0..t) = h1 + h2.  gsp: (2 x gs_split(len).G + 1) x ldh
-// doubles (ldh >= t).  Every launch returns
+// acc (optional): acc[0..t) = h1 + h2.  gsp: gs_partial_rows(len) x ldh doubles
+// (ldh >= t).  Every launch returns
 // at once when flag[0] != 0.  t = 0: only the pre-step and the norm partials.
 // *nparts (if given) receives the number of norm partials written to npart
 // (what the normalisation must add up): gs_split(len).G, or update_blocks(len)

@@ -33,6 +33,10 @@ GsSplit gs_split(int64_t len) {
   return s;
 }
 
+int64_t gs_partial_rows(int64_t len) {
+  return std::max<int64_t>(2 * (int64_t)gs_split(len).G, dots_chunks(len)) + 1;
+}
+
 namespace {
 
 constexpr int GS_T = 256;                 // threads per workgroup
@@ -44,6 +48,12 @@ constexpr size_t GS_LDS_MAX = 160 * 1024;
 // slice spreads its columns over workgroups instead (see launch_gs2)
 constexpr int GS_WIDE_G = 64;
 constexpr int GS_SHORT_G = 16;  // fewer slices than this: always the column-spread kernels
+// longer slices than this (vectors over 256 x 512 entries): the column-spread
+// kernels too, whose dots run over many more workgroups; a slice's dots and
+// update would run as long chains of dependent loads in its four waves
+// (measured: the sparse 1000000 x 200000 solve, slices of 3907 and 782 rows,
+// 103 ms against 75 ms)
+constexpr int64_t GS_SLICE_MAX = 512;
 constexpr int64_t GS_WIDE_WORK = 32768;
 
 // LDS of a launch: the slice (rows doubles), a chunk of coefficients, the
@@ -363,15 +373,18 @@ hipError_t launch_gs2(const TB* V, int64_t ldv, int t, int64_t len, double* x, d
   if (gs_lds_base(s.rows) > GS_LDS_MAX) return hipErrorInvalidValue;
   double* P1 = gsp;
   double* P2 = gsp + (int64_t)s.G * ldh;
-  double* h = gsp + (int64_t)2 * s.G * ldh;  // the reduced coefficients of the current pass
+  double* h = gsp + (gs_partial_rows(len) - 1) * ldh;  // the reduced coefficients of the current pass
   hipError_t e = hipSuccess;
-  if (t > 0 && (s.G < GS_SHORT_G || (s.G < GS_WIDE_G && (int64_t)t * s.rows > GS_WIDE_WORK))) {
-    // A short vector (few slices), or few slices and many columns: a slice's
-    // dot products would run one after another in a few waves, so the passes
-    // use the kernels that spread the columns over workgroups (dots over row
+  const bool spread = s.G < GS_SHORT_G || s.rows > GS_SLICE_MAX ||
+                      (s.G < GS_WIDE_G && (int64_t)t * s.rows > GS_WIDE_WORK);
+  if (t > 0 && spread) {
+    // A short vector (few slices), a long one (long slices), or few slices and
+    // many columns: a slice's dot products would run one after another in a
+    // few waves, so the passes use the kernels that spread the columns over
+    // workgroups (dots over row
     // chunks x column blocks, a reduction, an update per 64 rows, the second
-    // update leaving the norm partials, one per 64 rows).  dots_chunks(len)
-    // equals gs_split(len).G here, so P1 holds the chunk partials.
+    // update leaving the norm partials, one per 64 rows).  P1 holds the
+    // dots_chunks(len) chunk partials (gs_partial_rows counts them), h follows.
     if (pre_kind != GS_PRE_NONE) {
       e = pre_kind == GS_PRE_RHO
               ? launch_first<TB, double, GS_PRE_RHO>(V, ldv, 0, len, s, x, P1, ldh, pre, flag, st)

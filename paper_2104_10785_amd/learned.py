@@ -65,7 +65,7 @@ def _embedded_heuristic_init(ws: int, r: int, n_in: int, hidden: int, seed: int,
 
 def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t_train=100, t_eval=100,
         ws=32, hidden=256, epochs=20, lr=1e-3, lr_final=0.02, check_every=2, max_restarts=50, seed=3,
-        device="cuda:0", log=None, init="random", loss_kind=0, t_val=None, eval_every=2):
+        device="cuda:0", log=None, init="random", loss_kind=0, t_val=None, eval_every=2, prev="U"):
     """init: "random" (He initialisation) or "heuristic" (the heuristic start
     embedded in the network, see `_embedded_heuristic_init`); loss_kind: 0
     (energy outside the target subspace) or 1 (mean log tan^2 of the angles
@@ -77,7 +77,16 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     mean number of products the held-out solves need from the network's start
     vector (the convergence test is the judge); the best-scoring parameters
     (the earliest on a tie) are the ones evaluated.  Adam's step size decays from lr to lr * lr_final along a
-    cosine over the epochs, so the updates shrink as the loss flattens."""
+    cosine over the epochs, so the updates shrink as the loss flattens.
+
+    prev: what the network gets besides the sketch.  "U": the previous left
+    vectors U_{t-1} (their span drifts away from the target's, so no function
+    of them alone reaches the current vectors).  "AV": the previous right
+    vectors taken through the current matrix, A_t V_{t-1} (one more block
+    product, counted as one more matvec like the sketch): since A_t v_j(t-1) =
+    sigma_j u_j(t) + O(drift), these columns already point into span(U_t).
+    The heuristic start (sum of the previous left vectors, no extra product)
+    is reported either way; with "AV" also the sum of the A_t V_{t-1} columns."""
     import torch
     say = log or (lambda msg: None)
     t0 = time.time()
@@ -90,12 +99,16 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
         return gkb.gkb_partial_svd(seq.A, r, k, tol, max_restarts, q1=q1, seed=key, workspace=ws_svd,
                                    check_every=check_every)
 
-    def features(U_prev):
+    extra = 1 if prev == "AV" else 0   # block products besides the sketch
+
+    def features(U_prev, V_prev):
         St = gkb.gkb_gemm_rowmajor(seq.A, omega_t)   # (ws, m) = m x ws column-major
+        if prev == "AV":
+            return gkb.gkb_mlp_features(St, gkb.gkb_gemm_rowmajor(seq.A, V_prev))
         return gkb.gkb_mlp_features(St, U_prev)
 
     # t = 0
-    _, U_prev, _, st0, _ = solve(key=10_000)
+    _, U_prev, V_prev, st0, _ = solve(key=10_000)
     data = []
     held = []       # (A_t, X_t) of the held-out training solves
     train_mv = []
@@ -104,14 +117,14 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     t_fit = max(1, t_train - t_val)
     for t in range(1, t_train + 1):
         seq.advance()
-        X = features(U_prev)
-        sig, Ut, _, status, stats = solve(key=t)
+        X = features(U_prev, V_prev)
+        sig, Ut, Vt, status, stats = solve(key=t)
         train_mv.append(stats["matvecs"])
         if t <= t_fit:
             data.append((X, Ut.clone()))
         else:
             held.append((seq.A.clone(), X))
-        U_prev = Ut
+        U_prev, V_prev = Ut, Vt
     say(f"training data: {t_train} solves ({t_fit} to fit, {len(held)} held out), mean matvecs "
         f"{np.mean(train_mv):.1f}, {time.time() - t0:.1f} s")
 
@@ -129,11 +142,11 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
                 q = gkb.gkb_mlp_start_vector(prm, n_in, hidden, X_h)
                 try:
                     _, _, _, st_h, s_h = solve(q1=q)
-                    cnt = s_h["matvecs"] + 1
+                    cnt = s_h["matvecs"] + 1 + extra
                     if st_h != 0:
                         cnt += solve(key=1)[4]["matvecs"]
                 except gkb.GkbError:
-                    cnt = 1 + solve(key=1)[4]["matvecs"]
+                    cnt = 1 + extra + solve(key=1)[4]["matvecs"]
                 mv.append(cnt)
         finally:
             seq.A = A_keep
@@ -190,39 +203,47 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     for t in range(t_train + 1, t_train + t_eval + 1):
         seq.advance()
         c0 = clock()
-        X = features(U_prev)
+        X = features(U_prev, V_prev)
         c1 = clock()
         # random start
         sig_r, Ut_r, _, st_r, s_r = solve(key=t)
         c2 = clock()
-        # learned start (+1 matvec for the sketch), random fallback
+        # learned start (+1 matvec for the sketch, +1 for A_t V_{t-1}), random fallback
         q_l = gkb.gkb_mlp_start_vector(params, n_in, hidden, X)
         c3 = clock()
         fallback = False
         try:
-            sig_l, Ut_l, _, st_l, s_l = solve(q1=q_l)
-            mv_l = s_l["matvecs"] + 1
+            sig_l, Ut_l, Vt_l, st_l, s_l = solve(q1=q_l)
+            mv_l = s_l["matvecs"] + 1 + extra
             ok = st_l == 0
         except gkb.GkbError:
-            ok, mv_l = False, 1
+            ok, mv_l = False, 1 + extra
         c4 = clock()
         if not ok:
             fallback = True
-            sig_l, Ut_l, _, st_l, s_l2 = solve(key=t)
+            sig_l, Ut_l, Vt_l, st_l, s_l2 = solve(key=t)
             mv_l += s_l2["matvecs"]
-        # heuristic start
-        q_h = gkb.gkb_mlp_start_vector(hparams, n_in, hhidden, X)
+        # heuristic start: the previous left vectors summed (no extra product)
+        XU = X if prev == "U" else gkb.gkb_mlp_features(gkb.gkb_gemm_rowmajor(seq.A, omega_t), U_prev)
+        q_h = gkb.gkb_mlp_start_vector(hparams, n_in, hhidden, XU)
         try:
             sig_h, _, _, st_h, s_h = solve(q1=q_h)
             mv_h = s_h["matvecs"]
         except gkb.GkbError:
             st_h, mv_h = -1, -1
-        rows.append({"t": t, "random": s_r["matvecs"], "learned": mv_l, "heuristic": mv_h, "fallback": fallback,
+        mv_hav = None
+        if prev == "AV":  # the A_t V_{t-1} columns summed (the heuristic on the network's inputs)
+            try:
+                mv_hav = solve(q1=gkb.gkb_mlp_start_vector(hparams, n_in, hhidden, X))[4]["matvecs"] + extra
+            except gkb.GkbError:
+                mv_hav = -1
+        rows.append({"t": t, "random": s_r["matvecs"], "learned": mv_l, "heuristic": mv_h, "heuristic_av": mv_hav,
+                     "fallback": fallback,
                      "ms_features": (c1 - c0) * 1e3, "ms_random": (c2 - c1) * 1e3, "ms_network": (c3 - c2) * 1e3,
                      "ms_learned_solve": (c4 - c3) * 1e3,
                      "status_random": st_r, "status_learned": st_l, "status_heuristic": st_h,
                      "sigma_diff": float(np.max(np.abs(sig_l - sig_r)))})
-        U_prev = Ut_l
+        U_prev, V_prev = Ut_l, Vt_l
     mv_r = np.array([x["random"] for x in rows], dtype=float)
     mv_l = np.array([x["learned"] for x in rows], dtype=float)
     mv_h = np.array([x["heuristic"] for x in rows], dtype=float)
@@ -235,6 +256,7 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
         "matvecs_random": {"mean": mv_r.mean(), "median": float(np.median(mv_r))},
         "matvecs_learned": {"mean": mv_l.mean(), "median": float(np.median(mv_l))},
         "matvecs_heuristic": {"mean": mv_h.mean(), "median": float(np.median(mv_h))},
+        "prev": prev, "extra_block_products": extra,
         "learned_over_random_ratio_mean": float(np.mean(mv_l / mv_r)),
         # wall time to tolerance per held-out matrix (device synchronised): the
         # random start's solve; the learned start's sketch + features + network
@@ -248,4 +270,7 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
         "seconds": time.time() - t0,
         "per_t": rows,
     }
+    if prev == "AV":
+        mv_ha = np.array([x["heuristic_av"] for x in rows], dtype=float)
+        out["matvecs_heuristic_av"] = {"mean": mv_ha.mean(), "median": float(np.median(mv_ha))}
     return out
