@@ -398,8 +398,10 @@ def c1_leg(gkb, inputs, torch, dev, stream, warmup=2, reps=5, oracle=True):
     30, tol 1e-10, and the numerical rank at tau = 10^-6.005 relative to
     sigma_1, i.e. 10^-6.015 (rank 601: the log-midpoint between s_601 and
     s_602; the literal 1e-6 s_1 lands on s_601).  GPU solve and rank: warmup untimed, reps
-    timed (mean and median).  The float64 oracle runs the same solve and rank on
-    the host with the same inputs and schedule."""
+    timed (mean and median), directly and through a solve plan (the
+    stretches between host synchronisations replayed as HIP graphs).  The
+    float64 oracle runs the same solve and rank on the host with the same
+    inputs and schedule."""
     from oracle import gk
     from oracle import rank as orank
     s = inputs.decade_spectrum(1000)
@@ -414,6 +416,9 @@ def c1_leg(gkb, inputs, torch, dev, stream, warmup=2, reps=5, oracle=True):
     ms, (sig, _, _, status, st) = wall_times(solve, warmup, reps, torch)
     ph = gkb.gkb_partial_svd(Ad, C1_R, C1_K, C1_TOL, C1_RESTARTS, q1=qd, workspace=ws, stream=stream,
                              phase_timing=True)[4]
+    plan = gkb.SvdPlan(Ad, C1_R, C1_K, C1_TOL, C1_RESTARTS, workspace=ws, q1=qd)
+    ms_p, (sig_p, _, _, _, st_p) = wall_times(lambda: plan.run(stream=stream), warmup, reps, torch)
+    plan.close()
     ms_r, (rk, rk_s, rsig, _, rst) = wall_times(rank, warmup, reps, torch)
     steps = (st["matvecs"] - 1) / 2
     out = {"workload": "Q1 diag(10^(-i/100)) Q2^T 2000x1000 f64; top 10, k 30, tol 1e-10; rank at tau 10^-6.005 sigma_1",
@@ -423,6 +428,9 @@ def c1_leg(gkb, inputs, torch, dev, stream, warmup=2, reps=5, oracle=True):
            "sigma_rel_err_vs_spectrum_max": float(np.max(np.abs(sig - s[:C1_R]) / s[:C1_R])),
            "phases_ms": {k2: ph[k2] for k2 in ("ms_matvec", "ms_reorth", "ms_sync", "ms_ritz", "ms_other")},
            "ms_host_svd": st["ms_host"],
+           "plan_solve_ms_mean": float(np.mean(ms_p)), "plan_solve_ms_median": float(np.median(ms_p)),
+           "plan_triplets_per_s": st_p["nconv"] / (np.mean(ms_p) / 1000.0),
+           "plan_same_sigma": bool(np.array_equal(sig_p, sig)),
            "rank": rk, "rank_sturm": rk_s, "rank_expected": C1_RANK, "rank_steps": int(rsig.size),
            "rank_ms_mean": float(np.mean(ms_r)), "rank_ms_median": float(np.median(ms_r)),
            "rank_us_per_step": 1000.0 * float(np.mean(ms_r)) / max(1, rsig.size),

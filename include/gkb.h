@@ -208,6 +208,35 @@ gkb_status gkb_partial_svd_noalloc(const gkb_matrix* A, int r, int k, double tol
                                    const gkb_options* opt, double* sigma, void* U, void* V, gkb_stats* stats,
                                    void* stream);
 
+/*
+ * Plans: repeated solves of one matrix buffer (the same A pointer, shape and
+ * type, the same workspace and options; the contents of A may change between
+ * solves, as in a sequence of slowly changing matrices).  The device work
+ * between two host synchronisations of a solve -- the Golub-Kahan steps of a
+ * cycle up to the next convergence test (Algorithm 1 inside Algorithm 2) --
+ * is captured as a HIP graph the first time a solve reaches it and replayed by
+ * later solves, so a solve launches one graph per stretch instead of a dozen
+ * kernels per step; host decisions (tests, restarts) are as in
+ * gkb_partial_svd, whose results a plan reproduces bitwise.
+ *   gkb_svd_plan_create  checks the arguments as gkb_partial_svd does (the
+ *                        workspace stays the caller's and must outlive the
+ *                        plan); opt->phase_timing is not available
+ *                        (GKB_ERR_INVALID).  Creates one HIP stream (for the
+ *                        captures).
+ *   gkb_svd_plan_run     one solve: q1 (device, m doubles) replaces the
+ *                        start vector of the options when non-NULL; sigma,
+ *                        U, V, stats and statuses as gkb_partial_svd.  The
+ *                        graphs launch on `stream`.  Not thread-safe for one
+ *                        plan.
+ *   gkb_svd_plan_destroy releases the graphs and the stream (NULL allowed).
+ */
+typedef struct gkb_svd_plan_s* gkb_svd_plan;
+gkb_status gkb_svd_plan_create(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
+                               const gkb_options* opt, void* workspace, size_t ws_bytes, gkb_svd_plan* plan);
+gkb_status gkb_svd_plan_run(gkb_svd_plan plan, const double* q1, double* sigma, void* U, void* V,
+                            gkb_stats* stats, void* stream);
+void gkb_svd_plan_destroy(gkb_svd_plan plan);
+
 /* Workspace bytes needed by gkb_numerical_rank. */
 size_t gkb_rank_workspace_size(const gkb_matrix* A, int k_max, const gkb_options* opt);
 

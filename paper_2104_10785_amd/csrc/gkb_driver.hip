@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -726,10 +728,74 @@ gkb_status refine_bf16(Solver<TB>& S, const gkb_matrix* Am, const Proj& pr, cons
 
 
 // TO: type of U and V (TB, or float for the one-pass step on float64 bases)
+// Device work between two host synchronisations of a solve -- the Golub-Kahan
+// steps of one stretch of a cycle -- captured once as a HIP graph and replayed
+// by later solves with the same matrix, workspace and options (a plan).  A
+// stretch is keyed by (first cycle or not, first step, end step, current basis
+// copy); replaying it advances the host-side counters the launches would have
+// advanced.
+struct SegmentGraphs {
+  struct Seg {
+    hipGraphExec_t exec = nullptr;
+    int64_t passes = 0;
+    int nsig = 0;
+    int nparts = 1;
+  };
+  hipStream_t capture = nullptr;  // stream the stretches are captured on
+  std::map<std::tuple<int, int, int, int>, Seg> segs;
+  ~SegmentGraphs() {
+    for (auto& kv : segs)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (capture) (void)hipStreamDestroy(capture);
+  }
+};
+
+// Launch steps [j0, j1) through the cache: replay the captured graph, or
+// capture the launches on the cache's stream, instantiate, then replay.
+template <typename TB, typename F>
+gkb_status run_segment(Solver<TB>& S, SegmentGraphs& G, int first, int j0, int j1, F&& steps) {
+  // the bases are double-buffered across restarts: the launches also depend on
+  // which copy is current
+  const auto key = std::make_tuple(first, j0, j1, S.cur);
+  auto it = G.segs.find(key);
+  if (it == G.segs.end()) {
+    SegmentGraphs::Seg seg;
+    const int64_t p0 = S.a_passes;
+    const int n0 = S.nsig;
+    hipStream_t user = S.st;
+    S.st = G.capture;
+    GKB_HIP(hipStreamBeginCapture(G.capture, hipStreamCaptureModeThreadLocal));
+    const gkb_status rc = steps(j0, j1);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(G.capture, &graph);
+    S.st = user;
+    if (rc != GKB_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    GKB_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&seg.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    GKB_HIP(ei);
+    seg.passes = S.a_passes - p0;
+    seg.nsig = S.nsig - n0;
+    seg.nparts = S.nparts;
+    S.a_passes = p0;
+    S.nsig = n0;
+    it = G.segs.emplace(key, seg).first;
+  }
+  GKB_HIP(hipGraphLaunch(it->second.exec, S.st));
+  S.a_passes += it->second.passes;
+  S.nsig += it->second.nsig;
+  S.nparts = it->second.nparts;
+  return GKB_OK;
+}
+
 template <typename TB, typename TO = TB>
 gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int max_restarts,
                            const gkb_options& opt, void* workspace, double* sigma, TO* U, TO* V,
-                           gkb_stats* stats, hipStream_t st, const gkb::SparseRef* sp = nullptr) {
+                           gkb_stats* stats, hipStream_t st, const gkb::SparseRef* sp = nullptr,
+                           SegmentGraphs* graphs = nullptr) {
   constexpr bool onepass = !std::is_same<TB, TO>::value;
   const double t0 = now_ms();
   double ms_host = 0.0;
@@ -770,18 +836,33 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     // ---- one cycle: steps jstart..k-1, with optional in-cycle checks
     const int jstart = first ? 0 : l;
     bool early = false;
-    for (int j = jstart; j < k; ++j) {
-      if (onepass) {
-        rc = first ? S.onepass_step(j, j, j + 1, j + 1, false) : S.onepass_step(j, j - 1, j, j, j == l);
-        if (rc != GKB_OK) return rc;
-      } else if (first) {
-        rc = S.first_step(j);
-        if (rc != GKB_OK) return rc;
-      } else {
-        rc = S.restart_step(j, l);
-        if (rc != GKB_OK) return rc;
+    // steps j0 .. j1-1 of this cycle (device work only)
+    auto steps = [&](int j0, int j1) -> gkb_status {
+      for (int j = j0; j < j1; ++j) {
+        gkb_status e;
+        if (onepass)
+          e = first ? S.onepass_step(j, j, j + 1, j + 1, false) : S.onepass_step(j, j - 1, j, j, j == l);
+        else if (first)
+          e = S.first_step(j);
+        else
+          e = S.restart_step(j, l);
+        if (e != GKB_OK) return e;
       }
-      const int np_now = j + 1;
+      return GKB_OK;
+    };
+    for (int j = jstart; j < k;) {
+      // the stretch up to the next in-cycle test (or the cycle end)
+      int jend = k;
+      if (every > 0)
+        for (int np = j + 1; np < k; ++np)
+          if (np >= r && np % every == 0) {
+            jend = np;
+            break;
+          }
+      rc = graphs ? run_segment(S, *graphs, first ? 1 : 0, j, jend, steps) : steps(j, jend);
+      if (rc != GKB_OK) return rc;
+      j = jend;
+      const int np_now = j;
       if (every > 0 && np_now < k && np_now >= r && np_now % every == 0) {
         rc = S.read_back(k + 2, qc, pc, fl);
         if (rc != GKB_OK) return rc;
@@ -1021,6 +1102,27 @@ gkb_status run_rank(const gkb_matrix* Am, double tau, int tau_relative, int k, c
 
 }  // namespace
 
+// Argument checks of gkb_partial_svd (and of a plan); fills opt (defaults,
+// one_pass dropped where the sweep is unavailable).
+gkb_status validate_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts, const gkb_options* opt_in,
+                        void* workspace, size_t ws_bytes, gkb_options& opt);
+
+// The solve behind gkb_partial_svd and plans (arguments already checked).
+gkb_status dispatch_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts, const gkb_options& opt,
+                        void* workspace, double* sigma, void* U, void* V, gkb_stats* stats, hipStream_t st,
+                        SegmentGraphs* graphs) {
+  if (opt.one_pass)
+    return run_partial_svd<double, float>(A, r, k, tol, max_restarts, opt, workspace, sigma,
+                                          reinterpret_cast<float*>(U), reinterpret_cast<float*>(V), stats, st,
+                                          nullptr, graphs);
+  if (A->dtype == GKB_F64)
+    return run_partial_svd<double>(A, r, k, tol, max_restarts, opt, workspace, sigma,
+                                   reinterpret_cast<double*>(U), reinterpret_cast<double*>(V), stats, st, nullptr,
+                                   graphs);
+  return run_partial_svd<float>(A, r, k, tol, max_restarts, opt, workspace, sigma, reinterpret_cast<float*>(U),
+                                reinterpret_cast<float*>(V), stats, st, nullptr, graphs);
+}
+
 // ======================================================================= ABI
 // ---- the entry point that allocates nothing: a fixed device array per GPU
 static __device__ __align__(256) unsigned char scratch[GKB_NOALLOC_SCRATCH_BYTES];
@@ -1067,22 +1169,19 @@ size_t gkb_workspace_size(const gkb_matrix* A, int r, int k, const gkb_options* 
       .total;
 }
 
-gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
-                           const gkb_options* opt_in, void* workspace, size_t ws_bytes, double* sigma,
-                           void* U, void* V, gkb_stats* stats, void* stream) {
-  g_err.clear();
+}  // extern "C"
+
+gkb_status validate_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts, const gkb_options* opt_in,
+                        void* workspace, size_t ws_bytes, gkb_options& opt) {
   gkb_status rc = check_matrix(A);
   if (rc != GKB_OK) return rc;
   if (r < 1 || r > k) return fail(GKB_ERR_INVALID, "need 1 <= r <= k");
   if (k > std::min(A->m, A->n)) return fail(GKB_ERR_INVALID, "need k <= min(m, n)");
   if (!(tol >= 0.0)) return fail(GKB_ERR_INVALID, "need tol >= 0");
   if (max_restarts < 0) return fail(GKB_ERR_INVALID, "need max_restarts >= 0");
-  gkb_options opt;
   gkb_default_options(&opt);
   if (opt_in) opt = *opt_in;
   if (opt.one_pass && !one_pass_available(A)) opt.one_pass = 0;  // the two-product step instead
-  if (sigma == nullptr || U == nullptr || V == nullptr)
-    return fail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
   if (opt.keep != 0 && (opt.keep < r || opt.keep >= k))
     return fail(GKB_ERR_INVALID, "need r <= keep < k");
   if (opt.eps_break < 0) return fail(GKB_ERR_INVALID, "need eps_break >= 0");
@@ -1092,19 +1191,74 @@ gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int ma
     if (A->dtype != GKB_BF16) return fail(GKB_ERR_INVALID, "refine_f32 is only used with GKB_BF16");
     if (A->lda_refine < A->n) return fail(GKB_ERR_INVALID, "need lda_refine >= n");
   }
-  rc = check_workspace(workspace, ws_bytes, gkb_workspace_size(A, r, k, &opt));
-  if (rc != GKB_OK) return rc;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (opt.one_pass)
-    return run_partial_svd<double, float>(A, r, k, tol, max_restarts, opt, workspace, sigma,
-                                          reinterpret_cast<float*>(U), reinterpret_cast<float*>(V), stats, st);
-  if (A->dtype == GKB_F64)
-    return run_partial_svd<double>(A, r, k, tol, max_restarts, opt, workspace, sigma,
-                                   reinterpret_cast<double*>(U), reinterpret_cast<double*>(V), stats, st);
-  return run_partial_svd<float>(A, r, k, tol, max_restarts, opt, workspace, sigma,
-                                reinterpret_cast<float*>(U), reinterpret_cast<float*>(V), stats, st);
+  return check_workspace(workspace, ws_bytes, gkb_workspace_size(A, r, k, &opt));
 }
 
+extern "C" {
+
+gkb_status gkb_partial_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
+                           const gkb_options* opt_in, void* workspace, size_t ws_bytes, double* sigma,
+                           void* U, void* V, gkb_stats* stats, void* stream) {
+  g_err.clear();
+  if (sigma == nullptr || U == nullptr || V == nullptr)
+    return fail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
+  gkb_options opt;
+  gkb_status rc = validate_svd(A, r, k, tol, max_restarts, opt_in, workspace, ws_bytes, opt);
+  if (rc != GKB_OK) return rc;
+  return dispatch_svd(A, r, k, tol, max_restarts, opt, workspace, sigma, U, V, stats,
+                      reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+// ---- plans: repeated solves of one matrix buffer with graph-captured stretches
+struct gkb_svd_plan_s {
+  gkb_matrix A;
+  int r = 0, k = 0, max_restarts = 0;
+  double tol = 0.0;
+  gkb_options opt;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  SegmentGraphs graphs;
+};
+
+gkb_status gkb_svd_plan_create(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
+                               const gkb_options* opt_in, void* workspace, size_t ws_bytes, gkb_svd_plan* plan) {
+  g_err.clear();
+  if (plan == nullptr) return fail(GKB_ERR_INVALID, "plan must be non-NULL");
+  *plan = nullptr;
+  gkb_options opt;
+  gkb_status rc = validate_svd(A, r, k, tol, max_restarts, opt_in, workspace, ws_bytes, opt);
+  if (rc != GKB_OK) return rc;
+  if (opt.phase_timing) return fail(GKB_ERR_INVALID, "phase_timing is not available with a plan");
+  auto* p = new gkb_svd_plan_s();
+  p->A = *A;
+  p->r = r;
+  p->k = k;
+  p->tol = tol;
+  p->max_restarts = max_restarts;
+  p->opt = opt;
+  p->ws = workspace;
+  p->ws_bytes = ws_bytes;
+  if (hipStreamCreateWithFlags(&p->graphs.capture, hipStreamNonBlocking) != hipSuccess) {
+    delete p;
+    return fail(GKB_ERR_HIP, "hipStreamCreateWithFlags failed");
+  }
+  *plan = p;
+  return GKB_OK;
+}
+
+gkb_status gkb_svd_plan_run(gkb_svd_plan plan, const double* q1, double* sigma, void* U, void* V, gkb_stats* stats,
+                            void* stream) {
+  g_err.clear();
+  if (plan == nullptr) return fail(GKB_ERR_INVALID, "plan is NULL");
+  if (sigma == nullptr || U == nullptr || V == nullptr)
+    return fail(GKB_ERR_INVALID, "sigma, U and V must be non-NULL");
+  gkb_options opt = plan->opt;
+  if (q1 != nullptr) opt.q1 = q1;
+  return dispatch_svd(&plan->A, plan->r, plan->k, plan->tol, plan->max_restarts, opt, plan->ws, sigma, U, V, stats,
+                      reinterpret_cast<hipStream_t>(stream), &plan->graphs);
+}
+
+void gkb_svd_plan_destroy(gkb_svd_plan plan) { delete plan; }
 
 gkb_status gkb_partial_svd_noalloc(const gkb_matrix* A, int r, int k, double tol, int max_restarts,
                                    const gkb_options* opt, double* sigma, void* U, void* V, gkb_stats* stats,

@@ -78,7 +78,8 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_sparse_plan_destroy", "gkb_sparse_matvec", "gkb_sparse_workspace_size", "gkb_partial_svd_sparse",
            "gkb_sparse_last_error", "gkb_rsgd_workspace_size", "gkb_rsgd_plan_create", "gkb_rsgd_plan_step",
            "gkb_rsgd_plan_info", "gkb_rsgd_plan_destroy", "gkb_rsgd_weights", "gkb_rsgd_last_error",
-           "gkb_matvec_fused_workspace_size", "gkb_matvec_fused", "gkb_mlp_loss_grad_kind", "gkb_partial_svd_noalloc"]
+           "gkb_matvec_fused_workspace_size", "gkb_matvec_fused", "gkb_mlp_loss_grad_kind", "gkb_partial_svd_noalloc",
+           "gkb_svd_plan_create", "gkb_svd_plan_run", "gkb_svd_plan_destroy"]
 
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
@@ -104,6 +105,14 @@ def lib():
     L.gkb_partial_svd_noalloc.argtypes = [P(GkbMatrix), C.c_int, C.c_int, C.c_double, C.c_int, P(GkbOptions),
                                           P(C.c_double), C.c_void_p, C.c_void_p, P(GkbStats), C.c_void_p]
     L.gkb_partial_svd_noalloc.restype = C.c_int
+    L.gkb_svd_plan_create.argtypes = [P(GkbMatrix), C.c_int, C.c_int, C.c_double, C.c_int, P(GkbOptions),
+                                      C.c_void_p, C.c_size_t, P(C.c_void_p)]
+    L.gkb_svd_plan_create.restype = C.c_int
+    L.gkb_svd_plan_run.argtypes = [C.c_void_p, C.c_void_p, P(C.c_double), C.c_void_p, C.c_void_p, P(GkbStats),
+                                   C.c_void_p]
+    L.gkb_svd_plan_run.restype = C.c_int
+    L.gkb_svd_plan_destroy.argtypes = [C.c_void_p]
+    L.gkb_svd_plan_destroy.restype = None
     L.gkb_rank_workspace_size.argtypes = [P(GkbMatrix), C.c_int, P(GkbOptions)]
     L.gkb_rank_workspace_size.restype = C.c_size_t
     L.gkb_numerical_rank.argtypes = [P(GkbMatrix), C.c_double, C.c_int, C.c_int, P(GkbOptions), C.c_void_p,
@@ -364,6 +373,53 @@ def gkb_partial_svd_noalloc(A, r, k, tol, max_restarts, refine=None, stream=None
                                            _stream(stream))
     _check(status)
     return np.array(sig[:r], dtype=np.float64), Ut, Vt, status, st.as_dict()
+
+
+class SvdPlan:
+    """Repeated partial SVDs of one device matrix buffer (gkb_svd_plan_*): the
+    stretches of device work between host synchronisations are captured as
+    HIP graphs on the first solve that reaches them and replayed afterwards.
+    A may be modified in place between solves; results equal gkb_partial_svd's."""
+
+    def __init__(self, A, r, k, tol, max_restarts, refine=None, workspace=None, **opts):
+        torch = _torch()
+        self.A, self.r, self.refine = A, r, refine
+        self.mat = make_matrix(A, refine)
+        self.opts = make_options(**opts)
+        L = lib()
+        need = L.gkb_workspace_size(C.byref(self.mat), r, k, C.byref(self.opts))
+        self.ws = workspace if workspace is not None else _workspace(max(need, 256), A.device)
+        plan = C.c_void_p()
+        _check(L.gkb_svd_plan_create(C.byref(self.mat), r, k, float(tol), int(max_restarts), C.byref(self.opts),
+                                     C.c_void_p(self.ws.data_ptr()), self.ws.numel(), C.byref(plan)), False)
+        self.plan = plan
+        bt = basis_dtype(self.mat.dtype)
+        self.Ut = torch.empty((r, A.shape[0]), dtype=bt, device=A.device)
+        self.Vt = torch.empty((r, A.shape[1]), dtype=bt, device=A.device)
+
+    def run(self, q1=None, stream=None):
+        """One solve; returns (sigma, Ut, Vt, status, stats) like gkb_partial_svd
+        (Ut, Vt are the plan's output tensors, overwritten by the next run)."""
+        if q1 is not None and (q1.dtype != _torch().float64 or not q1.is_cuda or not q1.is_contiguous()):
+            raise ValueError("q1 must be a contiguous float64 device tensor")
+        sig = (C.c_double * self.r)()
+        st = GkbStats()
+        status = lib().gkb_svd_plan_run(self.plan, C.c_void_p(q1.data_ptr()) if q1 is not None else None, sig,
+                                        C.c_void_p(self.Ut.data_ptr()), C.c_void_p(self.Vt.data_ptr()),
+                                        C.byref(st), _stream(stream))
+        _check(status)
+        return np.array(sig[:], dtype=np.float64), self.Ut, self.Vt, status, st.as_dict()
+
+    def close(self):
+        if self.plan:
+            lib().gkb_svd_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gkb_rank_workspace_size(A, k_max=0, **opts) -> int:

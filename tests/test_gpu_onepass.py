@@ -266,3 +266,21 @@ def test_c2_fullsize_onepass_against_stored_oracle(check_every):
     print(f"c2 one-pass vector distances (sketch): u max {du.max():.3e}, v max {dv.max():.3e}; "
           f"max ratio to tolerance {np.max(np.maximum(du, dv) / vt):.3f}", flush=True)
     assert np.all(du <= vt) and np.all(dv <= vt)
+
+
+@pytest.mark.parametrize("shape", [(2000, 30000), (600, 80000)])
+def test_onepass_request_on_rows_wider_than_the_sweep(shape):
+    """Rows of 30000 and 80000 entries are wider than the sweep holds (24576):
+    the one_pass request runs the two-product step (stats say so), with the
+    float32 tolerance against the float64 oracle on the exact upcast."""
+    device()
+    m, n = shape
+    banner(f"one_pass request on {m}x{n} f32 (wider than the sweep)")
+    A32, s, _, _ = inputs.lowrank_noise(m, n, 100, 0.9, 1e-6, seed=m + n, dtype=np.float32)
+    q = inputs.start_vector(m, seed=3)
+    ref = gk.partial_svd(A32.astype(np.float64), 6, 24, 1e-6, 20, q, eps_break=1e-6)
+    sigma, U, V, status, stats = run(A32, 6, 24, 1e-6, 20, q, one_pass=True)
+    print("stats", stats, flush=True)
+    assert stats["one_pass_used"] == 0
+    assert status == ref["status"] == 0
+    _check_against(ref, sigma, U, V, 24)
