@@ -105,22 +105,31 @@ def fused_operands(gkb, torch, Ad, dev):
     return p, w, y, ws
 
 
-def kernels_only(gkb, torch, Ad, dev, stream, reps, f64=False):
+def kernels_only(gkb, torch, Ad, dev, stream, reps, f64=False, bf16=False, unaligned=False):
     """The A-streaming kernels alone (reps launches each: A p, A^T q, and the
     one-sweep pair A p, A^T A p) and a plain 1 GiB device copy (3 launches)
     whose counter readings calibrate the traffic figures.  f64: the same
     matrix upcast to float64 (8.0 GB), the two products only (the one-sweep
-    pair holds float32 or bfloat16 rows)."""
+    pair holds float32 or bfloat16 rows).  bf16: the matrix rounded to
+    bfloat16 (2.0 GB).  unaligned: the float32 matrix copied into rows of
+    n + 1 elements (lda = 20001: rows not 16-byte aligned), the two products
+    only."""
     if f64:
         Ad = Ad.double()
+    elif bf16:
+        Ad = gkb.gkb_cast_bf16(Ad)
+    elif unaligned:
+        buf = torch.zeros((M, N + 1), dtype=torch.float32, device=dev)
+        buf[:, :N].copy_(Ad)
+        Ad = buf[:, :N]
     mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=dev)
     xn, xm, yn, ym = matvec_operands(torch, Ad, dev)
-    if f64:
+    if Ad.dtype == torch.float64:
         xn, xm = xn.double(), xm.double()
     ms_n = time_kernel(lambda: gkb.gkb_matvec(Ad, xn, 0, y=yn, stream=stream), reps, stream)
     ms_t = time_kernel(lambda: gkb.gkb_matvec(Ad, xm, 1, y=ym, workspace=mws, stream=stream), reps, stream)
     ms_f, ritz = None, None
-    if not f64:
+    if not (f64 or unaligned):   # the one-sweep pair takes aligned float32 or bfloat16 rows only
         fp, fw, fy, fws = fused_operands(gkb, torch, Ad, dev)
         ms_f = time_kernel(lambda: gkb.gkb_matvec_fused(Ad, fp, fw, fy, fws, stream=stream), reps, stream)
         ritz = ritz_gemms(gkb, torch, dev, stream, reps)
@@ -130,9 +139,12 @@ def kernels_only(gkb, torch, Ad, dev, stream, reps, f64=False):
         dst.copy_(src)
     torch.cuda.synchronize()
     es = Ad.element_size()
-    print(json.dumps({"kernels_only": True, "dtype": "f64" if f64 else "f32", "gemv_n_ms": ms_n, "gemv_t_ms": ms_t,
-                      "gemv_n_GBps": (M * N * es + N * es + M * 8) / (ms_n * 1e-3) / 1e9,
-                      "gemv_t_GBps": (M * N * es + M * es + N * 8) / (ms_t * 1e-3) / 1e9, "gemv_fused_ms": ms_f,
+    vs = 8 if Ad.dtype == torch.float64 else 4   # input vector element (basis type)
+    dname = "f64" if Ad.dtype == torch.float64 else ("bf16" if bf16 else ("f32_lda20001" if unaligned else "f32"))
+    print(json.dumps({"kernels_only": True, "dtype": dname, "gemv_n_ms": ms_n, "gemv_t_ms": ms_t,
+                      "gemv_n_GBps": (M * N * es + N * vs + M * 8) / (ms_n * 1e-3) / 1e9,
+                      "gemv_t_GBps": (M * N * es + M * vs + N * 8) / (ms_t * 1e-3) / 1e9, "gemv_fused_ms": ms_f,
+                      "gemv_fused_GBps": None if ms_f is None else (M * N * es + N * 4 + M * 8 + N * 8) / (ms_f * 1e-3) / 1e9,
                       "reps": reps, "ritz_gemms": ritz, "copy_bytes": 2 ** 30,
                       "source_digest": kernel_source_digest("gemv_n"),
                       "fused_source_digest": kernel_source_digest("gemv_fused")}), flush=True)
@@ -594,6 +606,9 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the two matvec kernels and a 1 GiB copy (for counter runs)")
     ap.add_argument("--f64", action="store_true", help="with --kernels-only: the float64 upcast of the matrix")
+    ap.add_argument("--bf16", action="store_true", help="with --kernels-only: the bfloat16 rounding of the matrix")
+    ap.add_argument("--unaligned", action="store_true",
+                    help="with --kernels-only: the float32 matrix in rows of n + 1 elements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the Golub-Kahan path on a single "
@@ -617,7 +632,8 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     if args.kernels_only:
-        kernels_only(gkb, torch, Ad, dev, stream, args.kernel_reps, f64=args.f64)
+        kernels_only(gkb, torch, Ad, dev, stream, args.kernel_reps, f64=args.f64, bf16=args.bf16,
+                     unaligned=args.unaligned)
         return
 
     def step(check_every=args.check_every, one_pass=one_pass):
