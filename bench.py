@@ -502,10 +502,14 @@ SPARSE_R, SPARSE_K, SPARSE_EVERY = 20, 60, 5
 
 
 def sparse_leg(gkb, inputs, torch, dev, stream, steps):
-    """Sparse A (CSR of A and of A^T, power-law degrees): the partial SVD and the
-    two binned CSR products, timed with HIP events on the launch stream."""
+    """Sparse A (CSR of A and of A^T, power-law degrees): the partial SVD through
+    the column-panel products, and both products in the panel layout and in
+    the binned CSR form, timed with HIP events on the launch stream."""
     S = inputs.sparse_powerlaw(SPARSE_M, SPARSE_N, SPARSE_NNZ, seed=SPARSE_SEED)
+    t0 = time.perf_counter()
     plan = gkb.SparsePlan(SPARSE_M, SPARSE_N, S, device=dev, stream=stream)
+    plan_s = time.perf_counter() - t0
+    csr_plan = gkb.SparsePlan(SPARSE_M, SPARSE_N, S, device=dev, stream=stream, panels=False)
     del S
     q = torch.from_numpy(inputs.start_vector(SPARSE_M, seed=SPARSE_QSEED)).to(dev)
     ws = torch.empty(plan.workspace_size(SPARSE_R, SPARSE_K), dtype=torch.uint8, device=dev)
@@ -524,16 +528,29 @@ def sparse_leg(gkb, inputs, torch, dev, stream, steps):
     ym = torch.empty(SPARSE_N, dtype=torch.float64, device=dev)
     ms_n = time_kernel(lambda: plan.matvec(xn, 0, y=yn, stream=stream), 20, stream)
     ms_t = time_kernel(lambda: plan.matvec(xm, 1, y=ym, stream=stream), 20, stream)
-    # algorithmic bytes: every (index, value) pair once, the offsets, the output
-    # (float64) and the input vector once
+    csr_n = time_kernel(lambda: csr_plan.matvec(xn, 0, y=yn, stream=stream), 20, stream)
+    csr_t = time_kernel(lambda: csr_plan.matvec(xm, 1, y=ym, stream=stream), 20, stream)
+    # algorithmic bytes: the caller's CSR once (index and value of every entry,
+    # the offsets), the output (float64) and the input vector once
     b_n = SPARSE_NNZ * 8 + (SPARSE_M + 1) * 8 + SPARSE_M * 8 + SPARSE_N * 4
     b_t = SPARSE_NNZ * 8 + (SPARSE_N + 1) * 8 + SPARSE_N * 8 + SPARSE_M * 4
+    # bytes the panel products move: 6 per entry, 4 per row and panel of offsets,
+    # the per-panel row sums written and read back (4 + 4), the output and input
+    pw = 28672
+    npn, npt = -(-SPARSE_N // pw), -(-SPARSE_M // pw)
+    p_n = SPARSE_NNZ * 6 + npn * (SPARSE_M + 1) * 4 + 8 * npn * SPARSE_M + SPARSE_M * 8 + SPARSE_N * 4
+    p_t = SPARSE_NNZ * 6 + npt * (SPARSE_N + 1) * 4 + 8 * npt * SPARSE_N + SPARSE_N * 8 + SPARSE_M * 4
     out = {"workload": f"sparse power-law {SPARSE_M}x{SPARSE_N}, nnz {SPARSE_NNZ}, f32 CSR + CSR of A^T; "
                        f"top {SPARSE_R}, k {SPARSE_K}, tol 1e-6, checks every {SPARSE_EVERY}",
            "ms": ms, "triplets_per_s": st["nconv"] / (ms / 1000.0), "status": status, "matvecs": st["matvecs"],
-           "restarts": st["restarts"], "spmv_ms": ms_n, "spmv_GBps": b_n / (ms_n * 1e-3) / 1e9,
-           "spmv_t_ms": ms_t, "spmv_t_GBps": b_t / (ms_t * 1e-3) / 1e9, "sigma1": float(sig[0])}
+           "restarts": st["restarts"], "layout": "column panels" if plan.panels == 3 else f"panels mask {plan.panels}",
+           "plan_s": plan_s, "spmv_ms": ms_n, "spmv_GBps": b_n / (ms_n * 1e-3) / 1e9,
+           "spmv_t_ms": ms_t, "spmv_t_GBps": b_t / (ms_t * 1e-3) / 1e9,
+           "panel_bytes_GBps": [p_n / (ms_n * 1e-3) / 1e9, p_t / (ms_t * 1e-3) / 1e9],
+           "csr_spmv_ms": csr_n, "csr_spmv_t_ms": csr_t, "csr_spmv_GBps": b_n / (csr_n * 1e-3) / 1e9,
+           "csr_spmv_t_GBps": b_t / (csr_t * 1e-3) / 1e9, "sigma1": float(sig[0])}
     plan.close()
+    csr_plan.close()
     return out
 
 

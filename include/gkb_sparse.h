@@ -45,12 +45,34 @@ typedef struct gkb_sparse_plan_s* gkb_sparse_plan;
 /* Device bytes the plan needs for its row bins (0 if A is invalid). */
 size_t gkb_sparse_plan_workspace_size(const gkb_csr* A);
 
+/* Device bytes of a plan that also keeps A and A^T in column panels (0 if A
+   is invalid): the columns cut into panels of 28672, each panel stored as the
+   CSR matrix of its columns with 16-bit panel-relative indices (6 bytes per
+   entry), its row offsets (4 bytes per row and panel) and per-panel row sums
+   (4 bytes per row and panel).  A workgroup holds one panel of the input
+   vector in LDS while it streams that panel's entries, so the products read
+   the input vector from LDS instead of gathering it from memory.  A
+   direction is kept in panels when it has one panel or at most 4 row
+   segments per entry (rows x panels <= 4 nnz), and nnz < 2^31 - 1; otherwise
+   it keeps the CSR products. */
+size_t gkb_sparse_panel_workspace_size(const gkb_csr* A);
+
 /* Validate A, bin the rows of A and A^T on the device (row_ptr, col_ptr must
    be non-decreasing from 0 to nnz), and read the bin sizes back (one
-   synchronisation of `stream`).  ws must be 256-byte aligned. */
+   synchronisation of `stream`).  ws must be 256-byte aligned.  With at least
+   gkb_sparse_panel_workspace_size(A) bytes the plan also builds the column
+   panels on the host from copies of the arrays (one more synchronisation per
+   direction) and the products of those directions run through them (their
+   CSR arrays are not read again).  The panel products add each row's
+   entries of a panel in their CSR order and the panel sums in panel order:
+   a different, equally fixed order than the CSR products (results differ
+   from theirs by rounding only). */
 gkb_status gkb_sparse_plan_create(const gkb_csr* A, void* ws, size_t ws_bytes, void* stream,
                                   gkb_sparse_plan* plan);
 void gkb_sparse_plan_destroy(gkb_sparse_plan plan);
+
+/* Which products run through column panels: bit 0 A p, bit 1 A^T q. */
+int gkb_sparse_plan_panels(gkb_sparse_plan plan);
 
 /* y = A x (trans = 0; x length n, y length m) or y = A^T x (trans = 1):
    x float32, y float64, both device; float32 products summed per row in a

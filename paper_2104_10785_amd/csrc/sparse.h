@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/gkb_sparse.h"
+#include "sparse_panels.h"
 
 namespace gkb {
 
@@ -21,6 +22,23 @@ constexpr int SP_HUGE = 4096;     // rows longer than this are split into chunks
 //  * wave rows: rows of SP_SHORT + 1 .. SP_HUGE entries, one wave each;
 //  * huge rows: longer rows, cut into chunks of SP_HUGE entries whose partial
 //    sums are added in chunk order.
+// A direction's column-panel layout on the device (sparse_panels.h).
+struct PanelDev {
+  int64_t R = 0, C = 0;
+  int np = 0;
+  const uint16_t* pidx = nullptr;
+  const float* pval = nullptr;
+  const int32_t* poff = nullptr;   // np x (R + 1)
+  const int64_t* pbase = nullptr;  // np + 1
+  const PnDesc* jobs = nullptr;
+  const PnDesc* sblk = nullptr;
+  const PnDesc* witem = nullptr;
+  const PnDesc* segs = nullptr;
+  int64_t njobs = 0, nsegs = 0;
+  float* slot = nullptr;           // chunk sums
+  float* partial = nullptr;        // np x R row sums per panel (np > 1)
+};
+
 struct SparseDir {
   const int64_t* ptr = nullptr;
   const int32_t* idx = nullptr;
@@ -34,6 +52,8 @@ struct SparseDir {
   int64_t* cbeg = nullptr;     // nchunk: first entry of each chunk
   float* part = nullptr;       // nchunk partial sums
   int64_t nsblk = 0, nwrow = 0, nhrow = 0, nchunk = 0;
+  bool panels = false;         // products through the column-panel layout
+  PanelDev pn;
 };
 
 struct SparseRef {
@@ -43,6 +63,12 @@ struct SparseRef {
 
 // upper bound of the device bytes of one direction's schedule
 size_t sparse_dir_bytes(int64_t rows, int64_t nnz);
+// Place a built panel layout in device memory at w (at most
+// panel_bytes_bound bytes, 256-byte aligned) and fill P; synchronises st.
+hipError_t place_panels(const PanelLayout& L, char* w, PanelDev& P, hipStream_t st);
+// the panel products: what launch_spmv computes, through P
+hipError_t launch_panels(const PanelDev& P, const float* x, const float* prev, const double* coef, int cidx,
+                         double* y, const int* flag, hipStream_t st);
 // y[row] = sum_j val[j] x[idx[j]] - coef[cidx] * prev[row] for every row
 // (prev may be null); skipped when flag[0] != 0
 hipError_t launch_spmv(const SparseDir& D, const float* x, const float* prev, const double* coef, int cidx,

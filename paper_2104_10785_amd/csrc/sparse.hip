@@ -237,6 +237,7 @@ bool sparse_schedule(SparseDir& D, const std::vector<int64_t>& p, int64_t nnz, s
 
 hipError_t launch_spmv(const SparseDir& D, const float* x, const float* prev, const double* coef, int cidx,
                        double* y, const int* flag, hipStream_t st) {
+  if (D.panels) return launch_panels(D.pn, x, prev, coef, cidx, y, flag, st);
   const int nwb = (int)nblk(D.nwrow, SP_T / 64);
   const int64_t blocks = (int64_t)D.nchunk + nwb + D.nsblk;
   if (blocks > 0)
@@ -276,6 +277,12 @@ static gkb_status check_csr(const gkb_csr* A) {
 size_t gkb_sparse_plan_workspace_size(const gkb_csr* A) {
   if (check_csr(A) != GKB_OK) return 0;
   return gkb::sparse_dir_bytes(A->m, A->nnz) + gkb::sparse_dir_bytes(A->n, A->nnz) + 256;
+}
+
+size_t gkb_sparse_panel_workspace_size(const gkb_csr* A) {
+  const size_t base = gkb_sparse_plan_workspace_size(A);
+  if (base == 0) return 0;
+  return base + gkb::panel_bytes_bound(A->m, A->n, A->nnz) + gkb::panel_bytes_bound(A->n, A->m, A->nnz);
 }
 
 namespace {
@@ -386,11 +393,50 @@ gkb_status gkb_sparse_plan_create(const gkb_csr* A, void* ws, size_t ws_bytes, v
     delete plan;
     return sfail(GKB_ERR_INVALID, "column indices must lie in [0, n) and row indices of A^T in [0, m)");
   }
+  // column panels, for the directions whose shape suits them, when the
+  // workspace holds them (the bound of gkb_sparse_panel_workspace_size)
+  if (ws_bytes >= gkb_sparse_panel_workspace_size(A)) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      delete plan;
+      return sfail(GKB_ERR_HIP, "querying the device failed");
+    }
+    const int32_t* didx[2] = {A->col_idx, A->row_idx};
+    const float* dval[2] = {A->val, A->val_t};
+    for (int d = 0; d < 2; ++d) {
+      gkb::SparseDir& D = *dirs[d];
+      const size_t bound = gkb::panel_bytes_bound(D.rows, D.cols, A->nnz);
+      if (bound == 0) continue;
+      std::vector<int32_t> hidx((size_t)A->nnz);
+      std::vector<float> hval((size_t)A->nnz);
+      if (A->nnz > 0 &&
+          (hipMemcpyAsync(hidx.data(), didx[d], hidx.size() * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+           hipMemcpyAsync(hval.data(), dval[d], hval.size() * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+           hipStreamSynchronize(st) != hipSuccess)) {
+        delete plan;
+        return sfail(GKB_ERR_HIP, "reading the entries failed");
+      }
+      gkb::PanelLayout L;
+      gkb::build_panels(D.rows, D.cols, A->nnz, offs[d]->data(), hidx.data(), hval.data(), 2 * cus, L);
+      if (gkb::place_panels(L, w, D.pn, st) != hipSuccess) {
+        delete plan;
+        return sfail(GKB_ERR_HIP, "uploading the panel layout failed");
+      }
+      D.panels = true;
+      w += bound;
+    }
+  }
   *out = plan;
   return GKB_OK;
 }
 
 void gkb_sparse_plan_destroy(gkb_sparse_plan plan) { delete plan; }
+
+int gkb_sparse_plan_panels(gkb_sparse_plan plan) {
+  if (!plan) return 0;
+  return (plan->ref.fwd.panels ? 1 : 0) | (plan->ref.tr.panels ? 2 : 0);
+}
 
 gkb_status gkb_sparse_matvec(gkb_sparse_plan plan, int trans, const float* x, double* y, void* stream) {
   s_err.clear();

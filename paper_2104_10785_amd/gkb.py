@@ -74,8 +74,8 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_partial_svd_batched", "gkb_batched_last_error", "gkb_batched_autotune",
            "gkb_mlp_param_count", "gkb_mlp_feature_stride", "gkb_mlp_workspace_size", "gkb_mlp_features",
            "gkb_mlp_forward", "gkb_mlp_loss_grad", "gkb_adam_step", "gkb_mlp_start_vector",
-           "gkb_learned_last_error", "gkb_sparse_plan_workspace_size", "gkb_sparse_plan_create",
-           "gkb_sparse_plan_destroy", "gkb_sparse_matvec", "gkb_sparse_workspace_size", "gkb_partial_svd_sparse",
+           "gkb_learned_last_error", "gkb_sparse_plan_workspace_size", "gkb_sparse_panel_workspace_size",
+           "gkb_sparse_plan_create", "gkb_sparse_plan_destroy", "gkb_sparse_plan_panels", "gkb_sparse_matvec", "gkb_sparse_workspace_size", "gkb_partial_svd_sparse",
            "gkb_sparse_last_error", "gkb_rsgd_workspace_size", "gkb_rsgd_plan_create", "gkb_rsgd_plan_step",
            "gkb_rsgd_plan_info", "gkb_rsgd_plan_destroy", "gkb_rsgd_weights", "gkb_rsgd_last_error",
            "gkb_matvec_fused_workspace_size", "gkb_matvec_fused", "gkb_mlp_loss_grad_kind", "gkb_partial_svd_noalloc",
@@ -200,6 +200,10 @@ def lib():
     L.gkb_learned_last_error.restype = C.c_char_p
     L.gkb_sparse_plan_workspace_size.argtypes = [P(GkbCsr)]
     L.gkb_sparse_plan_workspace_size.restype = C.c_size_t
+    L.gkb_sparse_panel_workspace_size.argtypes = [P(GkbCsr)]
+    L.gkb_sparse_panel_workspace_size.restype = C.c_size_t
+    L.gkb_sparse_plan_panels.argtypes = [C.c_void_p]
+    L.gkb_sparse_plan_panels.restype = C.c_int
     L.gkb_sparse_plan_create.argtypes = [P(GkbCsr), C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_void_p)]
     L.gkb_sparse_plan_create.restype = C.c_int
     L.gkb_sparse_plan_destroy.argtypes = [C.c_void_p]
@@ -795,9 +799,12 @@ def gkb_mlp_start_vector(params, n_in, hidden, X, stream=None):
 class SparsePlan:
     """A sparse float32 matrix on the device (CSR of A and of A^T) with its row
     bins (gkb_sparse_plan_*).  `arrays` holds row_ptr (int64), col_idx (int32),
-    val (float32), col_ptr, row_idx, val_t as numpy arrays or device tensors."""
+    val (float32), col_ptr, row_idx, val_t as numpy arrays or device tensors.
+    panels=True gives the plan the workspace of the column-panel layout
+    (gkb_sparse_panel_workspace_size); `self.panels` says which products use
+    it (bit 0: A p, bit 1: A^T q)."""
 
-    def __init__(self, m, n, arrays, device="cuda:0", stream=None):
+    def __init__(self, m, n, arrays, device="cuda:0", stream=None, panels=True):
         torch = _torch()
         self.m, self.n = int(m), int(n)
         self.t = {}
@@ -812,7 +819,7 @@ class SparsePlan:
                                                        ("row_ptr", "col_idx", "val", "col_ptr", "row_idx", "val_t")])
         self.device = torch.device(device)
         L = lib()
-        need = L.gkb_sparse_plan_workspace_size(C.byref(self.csr))
+        need = (L.gkb_sparse_panel_workspace_size if panels else L.gkb_sparse_plan_workspace_size)(C.byref(self.csr))
         if need == 0:
             raise GkbError(-1, "invalid sparse matrix")
         self.ws = _workspace(need, self.device)
@@ -822,6 +829,7 @@ class SparsePlan:
         if st != 0:
             raise GkbError(st, L.gkb_sparse_last_error().decode())
         self.plan = plan
+        self.panels = int(L.gkb_sparse_plan_panels(plan))
 
     def matvec(self, x, trans=0, y=None, stream=None):
         """y = A x (trans 0) or A^T x (trans 1); x float32, y float64 device tensors."""

@@ -48,15 +48,22 @@ CASES = {
     "long_rows": lambda: one_long_row(2500, 3000, seed=4),
     "huge_row": lambda: one_long_row(600, 10000, seed=6),
     "empty": lambda: empty_matrix(300, 200),
+    # several column panels (28672 columns each) in A p, in A^T q, and a full
+    # row of 70000 entries whose panel segments are cut into chunks
+    "multipanel": lambda: inputs.sparse_powerlaw(300, 100000, 60000, seed=9),
+    "multipanel_tall": lambda: inputs.sparse_powerlaw(100000, 300, 400000, seed=10),
+    "multipanel_long": lambda: one_long_row(600, 70000, seed=12),
 }
 
 
+@pytest.mark.parametrize("layout", ["csr", "panels"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_sparse_matvec(name):
+def test_sparse_matvec(name, layout):
     device()
     S = CASES[name]()
-    banner(f"sparse matvec {name} {S['m']}x{S['n']} nnz={S['nnz']}")
-    plan = gkb.SparsePlan(S["m"], S["n"], S)
+    banner(f"sparse matvec {name} {S['m']}x{S['n']} nnz={S['nnz']} {layout}")
+    plan = gkb.SparsePlan(S["m"], S["n"], S, panels=layout == "panels")
+    assert plan.panels == (3 if layout == "panels" else 0), plan.panels
     A = csr_of(S)
     rng = np.random.default_rng(7)
     for trans in (0, 1):
@@ -64,8 +71,15 @@ def test_sparse_matvec(name):
         y = to_host(plan.matvec(to_dev(x), trans))
         M = A.T if trans else A
         ref = M @ x.astype(np.float64)
-        lens = np.diff(M.tocsr().indptr)
-        bound = (lens + 1) * U32 * (abs(M) @ np.abs(x.astype(np.float64))) + 1e-300
+        # recursive-summation bound over the stored entries (duplicates
+        # included): (length + 1) u32 sum_j |val_j x_idx_j| per row
+        ptr, idx, val = ((S["col_ptr"], S["row_idx"], S["val_t"]) if trans else
+                         (S["row_ptr"], S["col_idx"], S["val"]))
+        lens = np.diff(ptr)
+        rows = np.repeat(np.arange(lens.size), lens)
+        absum = np.bincount(rows, weights=np.abs(val.astype(np.float64) * x[idx].astype(np.float64)),
+                            minlength=lens.size)
+        bound = (lens + 1) * U32 * absum + 1e-300
         assert np.all(np.abs(y - ref) <= bound), (trans, np.max(np.abs(y - ref) - bound))
         y2 = to_host(plan.matvec(to_dev(x), trans))
         assert np.array_equal(y, y2)
@@ -98,18 +112,21 @@ def bound32(A):
     return np.sqrt(max(A.shape)) * U32 * sp.linalg.norm(A)
 
 
-@pytest.mark.parametrize("name,r,k,check_every", [("powerlaw", 10, 40, 0), ("powerlaw", 10, 40, 5),
-                                                  ("wide", 6, 30, 3), ("permuted_diagonal", 5, 20, 0),
-                                                  ("long_rows", 8, 30, 4), ("huge_row", 6, 25, 0)])
-def test_sparse_partial_svd_against_oracle(name, r, k, check_every):
+@pytest.mark.parametrize("name,r,k,check_every,layout", [
+    ("powerlaw", 10, 40, 0, "panels"), ("powerlaw", 10, 40, 5, "panels"), ("powerlaw", 10, 40, 5, "csr"),
+    ("wide", 6, 30, 3, "panels"), ("permuted_diagonal", 5, 20, 0, "panels"), ("long_rows", 8, 30, 4, "panels"),
+    ("huge_row", 6, 25, 0, "panels"), ("huge_row", 6, 25, 0, "csr"), ("multipanel", 6, 30, 0, "panels"),
+    ("multipanel_tall", 6, 30, 5, "panels"), ("multipanel_long", 6, 25, 0, "panels")])
+def test_sparse_partial_svd_against_oracle(name, r, k, check_every, layout):
     import scipy.sparse.linalg  # noqa: F401  (sp.linalg.norm)
     device()
     S = CASES[name]()
-    banner(f"sparse partial svd {name} r={r} k={k} check_every={check_every}")
+    banner(f"sparse partial svd {name} r={r} k={k} check_every={check_every} {layout}")
     A = csr_of(S)
     q = inputs.start_vector(S["m"], seed=11)
     ref = gk.partial_svd(A, r, k, 1e-6, 30, q, eps_break=1e-6, check_every=check_every)
-    plan = gkb.SparsePlan(S["m"], S["n"], S)
+    plan = gkb.SparsePlan(S["m"], S["n"], S, panels=layout == "panels")
+    assert plan.panels == (3 if layout == "panels" else 0), plan.panels
     sig, Ut, Vt, status, st = plan.partial_svd(r, k, 1e-6, 30, q1=to_dev(q), check_every=check_every)
     ne = ref["sigma"].size
     assert status == ref["status"], (status, ref["status"])
@@ -145,6 +162,7 @@ def test_sparse_fullsize_against_stored_oracle():
     banner("sparse full size 1000000x200000 nnz 5e7, r=20 k=60 check_every=5")
     S = inputs.sparse_powerlaw(1000000, 200000, 50000000, seed=7)
     plan = gkb.SparsePlan(1000000, 200000, S)
+    assert plan.panels == 3, plan.panels
     q = inputs.start_vector(1000000, seed=8)
     sig, Ut, Vt, status, st = plan.partial_svd(20, 60, 1e-6, 50, q1=to_dev(q), check_every=5)
     A = csr_of(S)
