@@ -418,7 +418,7 @@ gkb_status gkb_sparse_plan_create(const gkb_csr* A, void* ws, size_t ws_bytes, v
         return sfail(GKB_ERR_HIP, "reading the entries failed");
       }
       gkb::PanelLayout L;
-      gkb::build_panels(D.rows, D.cols, A->nnz, offs[d]->data(), hidx.data(), hval.data(), 2 * cus, L);
+      gkb::build_panels(D.rows, D.cols, A->nnz, offs[d]->data(), hidx.data(), hval.data(), cus, L);
       if (gkb::place_panels(L, w, D.pn, st) != hipSuccess) {
         delete plan;
         return sfail(GKB_ERR_HIP, "uploading the panel layout failed");

@@ -40,6 +40,7 @@ constexpr int PN_BIG = 4096;     // longer segments are cut into wave items
 constexpr int PN_ROWS = 1023;    // rows of a stream block (thread t adds row t)
 constexpr int PN_CHUNK = 4096;   // entries of a wave item
 constexpr int PN_JOB_MIN = 8192; // smallest job cost worth a panel load
+constexpr int PN_JOB_ITEMS = 256; // items of a job at most (its descriptors sit in LDS)
 
 // 16-byte descriptor (read on the device as one int4)
 struct PnDesc {
@@ -55,8 +56,8 @@ struct PanelLayout {
   int np = 0;                      // panels
   std::vector<int64_t> pbase;      // np + 1: first entry of each panel
   std::vector<int32_t> poff;       // np x (R + 1): row offsets within each panel
-  std::vector<uint16_t> pidx;      // nnz column indices relative to the panel
-  std::vector<float> pval;         // nnz values
+  std::vector<uint16_t> pidx;      // nnz column indices relative to the panel (+ one padding entry)
+  std::vector<float> pval;         // nnz values (+ one padding entry)
   std::vector<PnDesc> jobs, sblk, witem, segs;
   int64_t nslot = 0;
 };
@@ -72,7 +73,7 @@ size_t panel_bytes_bound(int64_t R, int64_t C, int64_t nnz);
 
 // Build the layout from host copies of the CSR arrays (ptr validated by the
 // caller: non-decreasing from 0 to nnz; idx in [0, C)).  target_jobs: about
-// how many jobs to cut the work into (twice the compute units).
+// how many jobs to cut the work into (the compute units: one workgroup each).
 void build_panels(int64_t R, int64_t C, int64_t nnz, const int64_t* ptr, const int32_t* idx, const float* val,
                   int target_jobs, PanelLayout& L);
 

@@ -16,7 +16,11 @@ namespace {
 
 constexpr int PN_EPT = PN_BLK / PN_T;                               // entries per thread in a stream block (8)
 constexpr int PN_LONG = PN_BLK / (PN_SHORT + 1) + 1;                // long rows a block can hold
-constexpr int PN_LDS = (PN_W + PN_BLK + PN_ROWS + 1 + 1 + PN_LONG) * 4;   // x panel, products, row offsets, long rows
+// the job's item descriptors (and four empty ones after them), x panel,
+// products, row offsets, long-row count and list
+constexpr int PN_DSC = PN_JOB_ITEMS + 4;
+constexpr int PN_LDS = PN_DSC * 16 + (PN_W + PN_BLK + PN_ROWS + 1 + 1 + PN_LONG) * 4;
+constexpr int PN_XV = (PN_W / 4 + PN_T - 1) / PN_T;                 // float4 of the x panel per thread
 constexpr int PN_WAVE_LOADS = 8;                                     // entries per lane in flight (wave items)
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -34,15 +38,105 @@ __device__ __forceinline__ void put_row(const PanelDev& P, int b, int64_t row, f
     y[row] = (double)s - (prev ? coef[cidx] * (double)prev[row] : 0.0);
 }
 
+// One stream block's operands in registers: its descriptor, thread t's row
+// offset and thread t's entries (t + u PN_T, u < PN_EPT).
+struct BlkRegs {
+  PnDesc d;
+  int o;
+  uint32_t ii[PN_EPT];
+  float vv[PN_EPT];
+};
+
+// Every load is issued unconditionally (indices clamped into the block, the
+// values of lanes past its end zeroed afterwards), so that the compiler can
+// count the loads in flight exactly and wait for one block's loads only.  An
+// empty block reads the entry at its start, which the layout pads.
+__device__ __forceinline__ void blk_load(BlkRegs& B, const PnDesc* dsc, int s, const int32_t* __restrict__ po,
+                                         const uint16_t* __restrict__ ci, const float* __restrict__ cv, int t) {
+  B.d = dsc[s];
+  B.o = po[B.d.a + min(t, B.d.b)];
+#pragma unroll
+  for (int u = 0; u < PN_EPT; ++u) {
+    const int q = t + u * PN_T;
+    const int qc = q < B.d.d ? q : 0;
+    B.ii[u] = ci[B.d.c + qc];
+    B.vv[u] = cv[B.d.c + qc];
+  }
+}
+
+// Block s (operands in B): products into LDS, then B receives block s + 2
+// (an empty descriptor past the job's end), then the row sums.
+__device__ __forceinline__ void blk_step(BlkRegs& B, int s, const PnDesc* dsc,
+                                         const int32_t* __restrict__ po, const uint16_t* __restrict__ ci,
+                                         const float* __restrict__ cv, const float* xs, float* prod, int* off,
+                                         int* nlong, int* lrow, const PanelDev& P, int b,
+                                         const float* __restrict__ prev, const double* __restrict__ coef, int cidx,
+                                         double* __restrict__ y, int t) {
+  if (t <= B.d.b) off[t] = B.o - B.d.c;
+  float pr[PN_EPT];
+#pragma unroll
+  for (int u = 0; u < PN_EPT; ++u) pr[u] = B.vv[u] * xs[B.ii[u]];
+#pragma unroll
+  for (int u = 0; u < PN_EPT; ++u) {
+    const int q = t + u * PN_T;
+    if (q < B.d.d) prod[q] = pr[u];
+  }
+  const PnDesc dc = B.d;
+  blk_load(B, dsc, s + 2, po, ci, cv, t);
+  if (t == 0) *nlong = 0;
+  __syncthreads();
+  // short rows: a thread each, in entry order with eight LDS reads in flight;
+  // long rows are listed for the waves (the list order varies, each long
+  // row's sum does not)
+  if (t < dc.b) {
+    const int lo = off[t], hi = off[t + 1];
+    if (hi - lo <= PN_SHORT) {
+      float acc = 0.f;
+      int q = lo;
+      for (; q + 8 <= hi; q += 8) {
+        float pk[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pk[k] = prod[q + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += pk[k];
+      }
+      for (; q < hi; ++q) acc += prod[q];
+      put_row(P, b, (int64_t)dc.a + t, acc, prev, coef, cidx, y);
+    } else {
+      lrow[atomicAdd(nlong, 1)] = t;
+    }
+  }
+  __syncthreads();
+  const int nl = *nlong;
+  for (int i = t >> 6; i < nl; i += PN_T / 64) {
+    const int rt = lrow[i], l = t & 63;
+    const int hi = off[rt + 1];
+    float acc = 0.f;
+    int q = off[rt] + l;
+    for (; q + 192 < hi; q += 256) {
+      const float p0 = prod[q], p1 = prod[q + 64], p2 = prod[q + 128], p3 = prod[q + 192];
+      acc += p0;
+      acc += p1;
+      acc += p2;
+      acc += p3;
+    }
+    for (; q < hi; q += 64) acc += prod[q];
+    acc = wave_sum(acc);
+    if (l == 0) put_row(P, b, (int64_t)dc.a + rt, acc, prev, coef, cidx, y);
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(PN_T) void k_panel_main(PanelDev P, const float* __restrict__ x,
                                                       const float* __restrict__ prev, const double* __restrict__ coef,
                                                       int cidx, double* __restrict__ y, const int* __restrict__ flag) {
-  extern __shared__ float lds[];
-  float* xs = lds;                                   // PN_W
-  float* prod = lds + PN_W;                          // PN_BLK
-  int* off = reinterpret_cast<int*>(prod + PN_BLK);  // PN_ROWS + 1
-  int* nlong = off + PN_ROWS + 1;                    // 1
-  int* lrow = nlong + 1;                             // PN_LONG
+  extern __shared__ float4 lds4[];
+  PnDesc* dsc = reinterpret_cast<PnDesc*>(lds4);                       // PN_DSC
+  float* xs = reinterpret_cast<float*>(lds4 + PN_DSC);                 // PN_W
+  float* prod = xs + PN_W;                                             // PN_BLK
+  int* off = reinterpret_cast<int*>(prod + PN_BLK);                    // PN_ROWS + 1
+  int* nlong = off + PN_ROWS + 1;                                      // 1
+  int* lrow = nlong + 1;                                               // PN_LONG
   if (flag != nullptr && flag[0] != 0) return;
   const PnDesc J = P.jobs[blockIdx.x];
   const int b = J.a;
@@ -52,87 +146,51 @@ __global__ __launch_bounds__(PN_T) void k_panel_main(PanelDev P, const float* __
   const int64_t base = P.pbase[b];
   const uint16_t* __restrict__ ci = P.pidx + base;
   const float* __restrict__ cv = P.pval + base;
-  // stream blocks {first row, rows, first entry, entries}: the first block's
-  // offsets and entries are loaded before the panel of x, each next block's
-  // while the rows of the current one are added
-  const int32_t* __restrict__ po = P.poff + (int64_t)b * (P.R + 1);
-  const PnDesc* sd = P.sblk + J.c;
-  PnDesc d = {0, 0, 0, 0};
-  int o = 0;
-  uint32_t ii[PN_EPT];
-  float vv[PN_EPT];
-  if (J.b == 0) {
-    d = sd[0];
-    o = t <= d.b ? po[d.a + t] : 0;
-#pragma unroll
-    for (int u = 0; u < PN_EPT; ++u) {
-      const int q = t + u * PN_T;
-      ii[u] = q < d.d ? ci[d.c + q] : 0u;
-      vv[u] = q < d.d ? cv[d.c + q] : 0.f;
-    }
-  }
+  // the job's item descriptors and the panel of x into LDS, every load
+  // issued before the first wait
+  const PnDesc* jd = (J.b == 0 ? P.sblk : P.witem) + J.c;
+  const int4 dl = t < J.d ? reinterpret_cast<const int4*>(jd)[t] : make_int4(0, 0, 0, 0);   // J.d <= PN_JOB_ITEMS
   const float* xp = x + c0;
   if ((reinterpret_cast<uintptr_t>(xp) & 15) == 0) {
     const int n4 = pw >> 2;
     const float4* x4 = reinterpret_cast<const float4*>(xp);
-    for (int i = t; i < n4; i += PN_T) reinterpret_cast<float4*>(xs)[i] = x4[i];
+    float4 xv[PN_XV];
+#pragma unroll
+    for (int k = 0; k < PN_XV; ++k) {
+      const int i = t + k * PN_T;
+      xv[k] = i < n4 ? x4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < PN_XV; ++k) {
+      const int i = t + k * PN_T;
+      if (i < n4) reinterpret_cast<float4*>(xs)[i] = xv[k];
+    }
     for (int i = (n4 << 2) + t; i < pw; i += PN_T) xs[i] = xp[i];
   } else {
     for (int i = t; i < pw; i += PN_T) xs[i] = xp[i];
   }
+  if (t < J.d + 4) reinterpret_cast<int4*>(dsc)[t] = dl;
   __syncthreads();
 
+  // stream blocks {first row, rows, first entry, entries}: block s + 2's
+  // offsets and entries are loaded while the rows of block s are added (two
+  // register sets).  The loads and steps run unconditionally (on the empty
+  // descriptors past the job's end), so that the waits for block s never
+  // cover block s + 1's loads.
   if (J.b == 0) {
-    for (int s = 0; s < J.d; ++s) {
-      if (t <= d.b) off[t] = o - d.c;
-#pragma unroll
-      for (int u = 0; u < PN_EPT; ++u) {
-        const int q = t + u * PN_T;
-        if (q < d.d) prod[q] = vv[u] * xs[ii[u]];
-      }
-      const PnDesc dc = d;
-      if (s + 1 < J.d) {
-        d = sd[s + 1];
-        o = t <= d.b ? po[d.a + t] : 0;
-#pragma unroll
-        for (int u = 0; u < PN_EPT; ++u) {
-          const int q = t + u * PN_T;
-          ii[u] = q < d.d ? ci[d.c + q] : 0u;
-          vv[u] = q < d.d ? cv[d.c + q] : 0.f;
-        }
-      }
-      if (t == 0) *nlong = 0;
-      __syncthreads();
-      // short rows: a thread each; long rows are listed for the waves (the
-      // list order varies, each long row's sum does not)
-      if (t < dc.b) {
-        const int lo = off[t], hi = off[t + 1];
-        if (hi - lo <= PN_SHORT) {
-          float acc = 0.f;
-          for (int q = lo; q < hi; ++q) acc += prod[q];
-          put_row(P, b, (int64_t)dc.a + t, acc, prev, coef, cidx, y);
-        } else {
-          lrow[atomicAdd(nlong, 1)] = t;
-        }
-      }
-      __syncthreads();
-      const int nl = *nlong;
-      for (int i = t >> 6; i < nl; i += PN_T / 64) {
-        const int rt = lrow[i], l = t & 63;
-        const int hi = off[rt + 1];
-        float acc = 0.f;
-        for (int q = off[rt] + l; q < hi; q += 64) acc += prod[q];
-        acc = wave_sum(acc);
-        if (l == 0) put_row(P, b, (int64_t)dc.a + rt, acc, prev, coef, cidx, y);
-      }
-      __syncthreads();
+    const int32_t* __restrict__ po = P.poff + (int64_t)b * (P.R + 1);
+    BlkRegs A, B;
+    blk_load(A, dsc, 0, po, ci, cv, t);
+    blk_load(B, dsc, 1, po, ci, cv, t);
+    for (int s = 0; s < J.d; s += 2) {
+      blk_step(A, s, dsc, po, ci, cv, xs, prod, off, nlong, lrow, P, b, prev, coef, cidx, y, t);
+      blk_step(B, s + 1, dsc, po, ci, cv, xs, prod, off, nlong, lrow, P, b, prev, coef, cidx, y, t);
     }
   } else {
     // wave items {row, first entry, entries, chunk-sum slot}: a wave each
-    const PnDesc* wd = P.witem + J.c;
     const int w = t >> 6, l = t & 63;
     for (int i = w; i < J.d; i += PN_T / 64) {
-      const PnDesc it = wd[i];
+      const PnDesc it = dsc[i];
       const uint16_t* __restrict__ ic = ci + it.b;
       const float* __restrict__ vc = cv + it.b;
       float s = 0.f;

@@ -43,7 +43,9 @@ size_t panel_bytes_bound(int64_t R, int64_t C, int64_t nnz) {
   if (!panels_suit(R, C, nnz)) return 0;
   const int64_t np = npanels(C);
   const Bounds b = bounds(R, C, nnz);
-  size_t s = a256((size_t)nnz * 2) + a256((size_t)nnz * 4) + a256((size_t)np * (R + 1) * 4) + a256((size_t)(np + 1) * 8);
+  // pidx and pval hold one padding entry past the end
+  size_t s = a256((size_t)(nnz + 1) * 2) + a256((size_t)(nnz + 1) * 4) + a256((size_t)np * (R + 1) * 4) +
+             a256((size_t)(np + 1) * 8);
   s += a256((size_t)b.jobs * 16) + a256((size_t)b.sblk * 16) + a256((size_t)b.witem * 16) + a256((size_t)b.segs * 16);
   s += a256((size_t)b.witem * 4);                        // chunk-sum slots
   if (np > 1) s += a256((size_t)np * R * 4);             // per-panel row sums
@@ -69,8 +71,8 @@ void build_panels(int64_t R, int64_t C, int64_t nnz, const int64_t* ptr, const i
     L.pbase[b + 1] = L.pbase[b] + po[R];
   }
   // entries, panel by panel, each row's entries in their CSR order
-  L.pidx.resize((size_t)nnz);
-  L.pval.resize((size_t)nnz);
+  L.pidx.assign((size_t)nnz + 1, 0);   // one padding entry: an empty block's clamped read
+  L.pval.assign((size_t)nnz + 1, 0.f);
   std::vector<int32_t> cur(L.poff);
   for (int64_t r = 0; r < R; ++r)
     for (int64_t j = ptr[r]; j < ptr[r + 1]; ++j) {
@@ -79,29 +81,17 @@ void build_panels(int64_t R, int64_t C, int64_t nnz, const int64_t* ptr, const i
       L.pidx[pos] = (uint16_t)(idx[j] - b * PN_W);
       L.pval[pos] = val[j];
     }
-  // items and jobs
-  const int64_t total = nnz + 2 * (int64_t)np * R;
-  const int64_t E = std::max<int64_t>(PN_JOB_MIN, total / std::max(target_jobs, 1));
+  // items, panel by panel
   L.jobs.clear();
   L.sblk.clear();
   L.witem.clear();
   L.segs.clear();
   L.nslot = 0;
-  auto cut = [&](int b, int kind, size_t first, const std::vector<PnDesc>& items) {
-    int64_t acc = 0;
-    size_t j0 = first;
-    for (size_t i = first; i < items.size(); ++i) {
-      acc += kind == 0 ? (int64_t)items[i].d + 2 * items[i].b : (int64_t)items[i].c + 64;
-      if (acc >= E || i + 1 == items.size()) {
-        L.jobs.push_back({b, kind, (int32_t)j0, (int32_t)(i + 1 - j0)});
-        j0 = i + 1;
-        acc = 0;
-      }
-    }
-  };
+  std::vector<size_t> s_first(np + 1), w_first(np + 1);
   for (int b = 0; b < np; ++b) {
     const int32_t* po = L.poff.data() + (size_t)b * R1;
-    const size_t s0 = L.sblk.size(), w0 = L.witem.size();
+    s_first[b] = L.sblk.size();
+    w_first[b] = L.witem.size();
     int32_t r0 = 0, nr = 0, e0 = 0, ecnt = 0;
     auto flush = [&]() {
       if (nr > 0) L.sblk.push_back({r0, nr, e0, ecnt});
@@ -128,8 +118,58 @@ void build_panels(int64_t R, int64_t C, int64_t nnz, const int64_t* ptr, const i
       }
     }
     flush();
-    cut(b, 0, s0, L.sblk);
-    cut(b, 1, w0, L.witem);
+  }
+  s_first[np] = L.sblk.size();
+  w_first[np] = L.witem.size();
+  // jobs: each panel's stream blocks and wave items cut into parts of about
+  // equal cost (entries + 2 per row, entries + 64 per wave item), the number
+  // of parts in proportion to the cost, so that all jobs together number
+  // about target_jobs (one workgroup per compute unit: a single round)
+  auto scost = [](const PnDesc& d) { return (int64_t)d.d + 2 * (int64_t)d.b; };
+  auto wcost = [](const PnDesc& d) { return (int64_t)d.c + 64; };
+  std::vector<int64_t> cs(np, 0), cw(np, 0), ks(np, 0), kw(np, 0);
+  int64_t total_s = 0, total_w = 0;
+  for (int b = 0; b < np; ++b) {
+    for (size_t i = s_first[b]; i < s_first[b + 1]; ++i) cs[b] += scost(L.sblk[i]);
+    for (size_t i = w_first[b]; i < w_first[b + 1]; ++i) cw[b] += wcost(L.witem[i]);
+    total_s += cs[b];
+    total_w += cw[b];
+  }
+  // wave items first (one job per panel that has any, more in proportion to
+  // their share of the cost), the rest of the target to the stream blocks
+  const int64_t target = std::max(target_jobs, 1);
+  auto parts = [](int64_t cost, int64_t share_of, int64_t of, size_t items) -> int64_t {
+    if (items == 0) return 0;
+    const int64_t k = of > 0 ? (int64_t)((__int128)cost * share_of / of) : 1;
+    return std::max<int64_t>(1, std::min<int64_t>({k, cost / PN_JOB_MIN + 1, (int64_t)items}));
+  };
+  int64_t used = 0;
+  for (int b = 0; b < np; ++b) {
+    kw[b] = parts(cw[b], target * total_w / std::max<int64_t>(total_s + total_w, 1), total_w,
+                  w_first[b + 1] - w_first[b]);
+    used += kw[b];
+  }
+  const int64_t rest = std::max<int64_t>(target - used, 1);
+  for (int b = 0; b < np; ++b) ks[b] = parts(cs[b], rest, total_s, s_first[b + 1] - s_first[b]);
+  auto cut = [&](int b, int kind, size_t first, size_t last, int64_t cost, int64_t k,
+                 int64_t (*c)(const PnDesc&), const std::vector<PnDesc>& items) {
+    // part j closes once the cumulative cost reaches (j + 1) cost / k, or at
+    // PN_JOB_ITEMS items
+    int64_t acc = 0, j = 0;
+    size_t j0 = first;
+    for (size_t i = first; i < last; ++i) {
+      acc += c(items[i]);
+      const bool full = (__int128)acc * k >= (__int128)(j + 1) * cost;
+      if (full || i + 1 - j0 == (size_t)PN_JOB_ITEMS || i + 1 == last) {
+        L.jobs.push_back({b, kind, (int32_t)j0, (int32_t)(i + 1 - j0)});
+        j0 = i + 1;
+        while ((__int128)acc * k >= (__int128)(j + 1) * cost && j < k) ++j;
+      }
+    }
+  };
+  for (int b = 0; b < np; ++b) {
+    cut(b, 0, s_first[b], s_first[b + 1], cs[b], ks[b], scost, L.sblk);
+    cut(b, 1, w_first[b], w_first[b + 1], cw[b], kw[b], wcost, L.witem);
   }
 }
 
