@@ -554,6 +554,33 @@ def sparse_leg(gkb, inputs, torch, dev, stream, steps):
     return out
 
 
+def sparse_kernels_only(gkb, inputs, torch, dev, stream, reps):
+    """The sparse products alone on the 1000000 x 200000, 5e7-entry workload
+    (reps launches each of A p and A^T q through the column panels and through
+    the CSR kernels) and a plain 1 GiB device copy (3 launches) whose counter
+    readings calibrate the traffic figures."""
+    S = inputs.sparse_powerlaw(SPARSE_M, SPARSE_N, SPARSE_NNZ, seed=SPARSE_SEED)
+    plan = gkb.SparsePlan(SPARSE_M, SPARSE_N, S, device=dev, stream=stream)
+    csr_plan = gkb.SparsePlan(SPARSE_M, SPARSE_N, S, device=dev, stream=stream, panels=False)
+    del S
+    xn = torch.randn(SPARSE_N, dtype=torch.float32, device=dev)
+    xm = torch.randn(SPARSE_M, dtype=torch.float32, device=dev)
+    yn = torch.empty(SPARSE_M, dtype=torch.float64, device=dev)
+    ym = torch.empty(SPARSE_N, dtype=torch.float64, device=dev)
+    out = {"kernels_only": True, "sparse": True, "reps": reps, "panels": plan.panels}
+    for name, p in (("panels", plan), ("csr", csr_plan)):
+        out[name + "_n_ms"] = time_kernel(lambda: p.matvec(xn, 0, y=yn, stream=stream), reps, stream)
+        out[name + "_t_ms"] = time_kernel(lambda: p.matvec(xm, 1, y=ym, stream=stream), reps, stream)
+    src = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
+    plan.close()
+    csr_plan.close()
+
+
 RSGD_D1, RSGD_D2, RSGD_R, RSGD_B, RSGD_ETA, RSGD_LAM = 784, 256, 5, 64, 2.0, 1e-3
 
 
@@ -626,6 +653,8 @@ def main():
     ap.add_argument("--bf16", action="store_true", help="with --kernels-only: the bfloat16 rounding of the matrix")
     ap.add_argument("--unaligned", action="store_true",
                     help="with --kernels-only: the float32 matrix in rows of n + 1 elements")
+    ap.add_argument("--sparse", action="store_true",
+                    help="with --kernels-only: the sparse products (column panels and CSR) instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the Golub-Kahan path on a single "
@@ -636,6 +665,9 @@ def main():
     from paper_2104_10785_amd import gkb, inputs
 
     dev = torch.device("cuda:0")
+    if args.kernels_only and args.sparse:
+        sparse_kernels_only(gkb, inputs, torch, dev, torch.cuda.current_stream(), args.kernel_reps)
+        return
     log("generating 50000x20000 float32 low-rank-plus-noise matrix")
     t0 = time.time()
     A32, s, _, _ = inputs.lowrank_noise(M, N, RANK, DECAY, NOISE, seed=SEED, dtype=np.float32)
