@@ -72,7 +72,6 @@ struct Lds {
   float tpart[4 * BT];         // gemv_t row-group partial sums
   float pvec[BATCH_TEAM_NMAX]; // a team's current p (read from the coherence point)
   int perm[KMAX];
-  int ord[KMAX + 1];
   int rotated;
   int problem;
   int member;
@@ -491,7 +490,9 @@ __device__ const float* team_load_p(const float* p, int n, Lds<BT>& L) {
 // One-sided Jacobi SVD of the nq x np matrix in L.Hs (columns), accumulating
 // the right rotations in L.Vs; afterwards sv[c] = column norms and perm sorts
 // them descending (ties by index).  Pairs follow the round-robin ordering so
-// each round's pairs are disjoint; one wave per pair.
+// each round's pairs are disjoint; one wave per pair.  The ordering: player 0
+// stays, players 1 .. N-1 move one seat on each round, and seat c meets seat
+// N - 1 - c; the seat of a player is computed, not stored.
 template <int BT>
 __device__ void bjacobi(int nq, int np, Lds<BT>& L) {
   constexpr int NW = BT / 64;
@@ -500,14 +501,16 @@ __device__ void bjacobi(int nq, int np, Lds<BT>& L) {
   __syncthreads();
   for (int c = tid; c < np; c += BT) L.Vs[c * KMAX + c] = 1.0;
   const int N = (np + 1) & ~1;  // even number of players (index np is a bye)
+  // the player in seat c after `round` moves
+  auto seat = [N](int c, int round) { return c == 0 ? 0 : 1 + ((c - 1 - round) % (N - 1) + (N - 1)) % (N - 1); };
   for (int s = 0; s < 60; ++s) {
     if (tid == 0) L.rotated = 0;
-    for (int c = tid; c < N; c += BT) L.ord[c] = c;
     __syncthreads();
     for (int round = 0; round < N - 1; ++round) {
       for (int pr = wave; pr < N / 2; pr += NW) {
-        const int i = min(L.ord[pr], L.ord[N - 1 - pr]);
-        const int j = max(L.ord[pr], L.ord[N - 1 - pr]);
+        const int pa = seat(pr, round), pb = seat(N - 1 - pr, round);
+        const int i = min(pa, pb);
+        const int j = max(pa, pb);
         if (j >= np) continue;
         double* hi = L.Hs + i * HLD;
         double* hj = L.Hs + j * HLD;
@@ -538,13 +541,6 @@ __device__ void bjacobi(int nq, int np, Lds<BT>& L) {
           }
           if (lane == 0) L.rotated = 1;
         }
-      }
-      __syncthreads();
-      // rotate players 1..N-1 (player 0 fixed)
-      if (tid == 0) {
-        const int last = L.ord[N - 1];
-        for (int c = N - 1; c > 1; --c) L.ord[c] = L.ord[c - 1];
-        L.ord[1] = last;
       }
       __syncthreads();
     }
