@@ -52,6 +52,15 @@ typedef struct {
                             /*    kernels: 0 = by size (out of line when the      */
                             /*    problems average >= 2 MB of A), 1 = inline,      */
                             /*    2 = out of line.  Same results either way.       */
+  const double* cost_estimate; /* host, batch doubles or NULL: expected cost of     */
+                            /*    each problem on one workgroup (any unit, e.g.    */
+                            /*    gkb_batched_plan_work of a run of this batch).   */
+                            /*    NULL: m n k.  The schedule splits the costliest  */
+                            /*    problems over teams of workgroups and starts the */
+                            /*    largest per-member cost first.  Team sizes change */
+                            /*    how a problem's sums are split, so results can   */
+                            /*    differ from another schedule's by rounding.      */
+                            /*    Read during plan creation only.                  */
 } gkb_batch_options;
 
 typedef struct gkb_batch_plan_s* gkb_batch_plan;
@@ -77,6 +86,13 @@ gkb_status gkb_batched_plan_run(gkb_batch_plan plan, void* stream);
 
 /* Copy the per-problem info of the last completed run to the host (synchronises `stream`). */
 gkb_status gkb_batched_plan_info(gkb_batch_plan plan, int* info, void* stream);
+
+/* Per problem, the wall-clock time (ms, from the device clock) that its first
+   workgroup spent on it in the last completed run, times its team size: an
+   estimate of its cost on one workgroup, for gkb_batch_options.cost_estimate
+   of a later plan of the same batch.  work_ms: host, batch doubles
+   (synchronises `stream`). */
+gkb_status gkb_batched_plan_work(gkb_batch_plan plan, double* work_ms, void* stream);
 
 /* Persistent grid size chosen for the plan. */
 int gkb_batched_plan_grid(gkb_batch_plan plan);

@@ -49,6 +49,7 @@ struct BatchParams {
   float* V;
   double* sigma;
   int* info;          // 4 ints per problem: status, nconv, restarts, matvecs
+  unsigned long long* ticks;  // per problem: device wall-clock ticks its first member spent on it
   const double* q1;   // packed start vectors or null (Philox with seed + index)
   uint64_t seed;
   double eps_break;

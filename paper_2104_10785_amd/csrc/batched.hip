@@ -649,6 +649,7 @@ __device__ double philox_normal(int64_t i, uint64_t seed) {
 // Solve one problem as member `member` of its team (all threads of the workgroup).
 template <int BT, bool OUT>
 __device__ void solve_one(const BatchProblem& P, int member, const BatchParams& prm, Lds<BT>& L) {
+  const unsigned long long t_start = wall_clock64();
   const int tid = threadIdx.x;
   const int ldq = P.ldq, ldp = P.ldp;   // basis column strides (multiples of 4: 16-byte aligned columns)
   float* Qb[2] = {prm.pool + P.offQ, prm.pool + P.offQ + (int64_t)(P.k + 1) * ldq};
@@ -894,6 +895,7 @@ __device__ void solve_one(const BatchProblem& P, int member, const BatchParams& 
     prm.info[4 * pi + 1] = nconv;
     prm.info[4 * pi + 2] = restarts;
     prm.info[4 * pi + 3] = (int)matvecs;
+    prm.ticks[pi] = wall_clock64() - t_start;
   }
   __syncthreads();
 }

@@ -37,7 +37,8 @@ constexpr int TEAM_MAX = 8;   // largest team of workgroups on one problem
 constexpr double OUTLINE_MIN_BYTES = 2.0 * (1 << 20);   // average A bytes per problem for out-of-line products
 
 struct Layout {
-  size_t problems = 0, order = 0, member = 0, counter = 0, info = 0, pool = 0, work = 0, stage_tab = 0, stage = 0,
+  size_t problems = 0, order = 0, member = 0, counter = 0, info = 0, ticks = 0, pool = 0, work = 0, stage_tab = 0,
+         stage = 0,
          team_cnt = 0, team_buf = 0, total = 0;
   size_t pool_floats = 0, work_doubles = 0, stage_floats = 0, team_doubles = 0;
   int nstage = 0;
@@ -85,6 +86,7 @@ Layout layout(int batch, const gkb_matrix* As, const int* k) {
   L.member = take(sizeof(int) * batch * TEAM_MAX);
   L.counter = take(sizeof(int));
   L.info = take(sizeof(int) * 4 * batch);
+  L.ticks = take(sizeof(unsigned long long) * batch);
   for (int i = 0; i < batch; ++i) {
     L.pool_floats += (size_t)2 * (k[i] + 1) * (round4(As[i].m) + round4(As[i].n));
     L.work_doubles += (size_t)(As[i].m + As[i].n);
@@ -116,6 +118,8 @@ struct gkb_batch_plan_s {
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;
   int* info_dev = nullptr;
+  unsigned long long* ticks_dev = nullptr;
+  double ticks_per_ms = 1e5;   // device wall clock (kHz)
   bool no_graph = false;
   int threads = 1024;
 };
@@ -155,10 +159,15 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
     return bfail(GKB_ERR_INVALID, "threads must be 0, 512 or 1024");
   if (opt.max_team < 0) return bfail(GKB_ERR_INVALID, "max_team must be >= 0");
   if (opt.form < 0 || opt.form > 2) return bfail(GKB_ERR_INVALID, "form must be 0, 1 or 2");
-  int dev = 0, cus = 0;
+  int dev = 0, cus = 0, clock_khz = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
     return bfail(GKB_ERR_HIP, "cannot query the device");
+  if (opt.cost_estimate)
+    for (int i = 0; i < batch; ++i)
+      if (!(opt.cost_estimate[i] >= 0.0) || !std::isfinite(opt.cost_estimate[i]))
+        return bfail(GKB_ERR_INVALID, "cost estimates must be finite and >= 0");
   Layout L = layout(batch, As, k);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0 || ws_bytes < L.total)
     return bfail(GKB_ERR_WORKSPACE, "workspace missing, misaligned or too small (need " +
@@ -216,7 +225,7 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   // persistent grid: one workgroup per compute unit unless asked otherwise
   plan->threads = opt.threads ? opt.threads : 1024;
   plan->grid = opt.workgroups > 0 ? opt.workgroups : cus;
-  // Teams: a problem whose estimated cost (m n k) exceeds half of the average
+  // Teams: a problem whose estimated cost (m n k, or the caller's estimate) exceeds half of the average
   // per-workgroup share of the whole batch is split over
   // T = ceil(cost / (share / 2)) workgroups (at most max_team, the grid, m / 256
   // and n / 64), so that no single problem outlasts the rest of the batch.
@@ -224,7 +233,8 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   std::vector<double> cost(batch);
   double total = 0.0;
   for (int i = 0; i < batch; ++i) {
-    cost[i] = (double)plan->table[i].m * plan->table[i].n * plan->table[i].k;
+    cost[i] = opt.cost_estimate ? std::max(opt.cost_estimate[i], 1e-30)
+                                : (double)plan->table[i].m * plan->table[i].n * plan->table[i].k;
     total += cost[i];
   }
   const double half_share = 0.5 * total / plan->grid;
@@ -281,6 +291,7 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   prm.V = V;
   prm.sigma = sigma;
   prm.info = reinterpret_cast<int*>(ws + L.info);
+  prm.ticks = reinterpret_cast<unsigned long long*>(ws + L.ticks);
   prm.q1 = opt.q1_packed;
   prm.seed = opt.seed;
   prm.eps_break = opt.eps_break > 0 ? opt.eps_break : 1e-6;
@@ -292,6 +303,8 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   prm.nstage = (int)stage.size();
   prm.stage_rows = stage_rows;
   plan->info_dev = prm.info;
+  plan->ticks_dev = prm.ticks;
+  plan->ticks_per_ms = clock_khz > 0 ? (double)clock_khz : 1e5;
   auto cleanup = [&](gkb_status s) {
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
@@ -348,6 +361,19 @@ gkb_status gkb_batched_plan_info(gkb_batch_plan plan, int* info, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   B_HIP(hipMemcpyAsync(info, plan->info_dev, sizeof(int) * 4 * plan->batch, hipMemcpyDeviceToHost, st));
   B_HIP(hipStreamSynchronize(st));
+  return GKB_OK;
+}
+
+gkb_status gkb_batched_plan_work(gkb_batch_plan plan, double* work_ms, void* stream) {
+  b_err.clear();
+  if (!plan || !work_ms) return bfail(GKB_ERR_INVALID, "invalid plan or output pointer");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<unsigned long long> ticks((size_t)plan->batch);
+  B_HIP(hipMemcpyAsync(ticks.data(), plan->ticks_dev, sizeof(unsigned long long) * plan->batch,
+                       hipMemcpyDeviceToHost, st));
+  B_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < plan->batch; ++i)
+    work_ms[i] = (double)ticks[i] / plan->ticks_per_ms * plan->table[i].team;
   return GKB_OK;
 }
 

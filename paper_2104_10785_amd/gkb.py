@@ -41,7 +41,8 @@ class GkbOptions(C.Structure):
 class GkbBatchOptions(C.Structure):
     _fields_ = [("check_every", C.c_int), ("eps_relative", C.c_int), ("eps_break", C.c_double),
                 ("seed", C.c_uint64), ("q1_packed", C.c_void_p), ("workgroups", C.c_int), ("no_graph", C.c_int),
-                ("threads", C.c_int), ("max_team", C.c_int), ("form", C.c_int)]
+                ("threads", C.c_int), ("max_team", C.c_int), ("form", C.c_int),
+                ("cost_estimate", C.c_void_p)]
 
 
 class GkbCsr(C.Structure):
@@ -71,7 +72,7 @@ EXPORTS = ["gkb_default_options", "gkb_workspace_size", "gkb_partial_svd", "gkb_
            "gkb_cast_bf16", "gkb_start_vector", "gkb_gemm_rowmajor", "gkb_gram_workspace_size", "gkb_gram",
            "gkb_batch_default_options", "gkb_batched_workspace_size", "gkb_batched_plan_create",
            "gkb_batched_plan_run", "gkb_batched_plan_info", "gkb_batched_plan_grid", "gkb_batched_plan_destroy",
-           "gkb_partial_svd_batched", "gkb_batched_last_error", "gkb_batched_autotune",
+           "gkb_partial_svd_batched", "gkb_batched_last_error", "gkb_batched_autotune", "gkb_batched_plan_work",
            "gkb_mlp_param_count", "gkb_mlp_feature_stride", "gkb_mlp_workspace_size", "gkb_mlp_features",
            "gkb_mlp_forward", "gkb_mlp_loss_grad", "gkb_adam_step", "gkb_mlp_start_vector",
            "gkb_learned_last_error", "gkb_sparse_plan_workspace_size", "gkb_sparse_panel_workspace_size",
@@ -170,6 +171,8 @@ def lib():
                                           P(GkbBatchOptions), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                           C.c_void_p, P(C.c_int), C.c_void_p]
     L.gkb_partial_svd_batched.restype = C.c_int
+    L.gkb_batched_plan_work.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gkb_batched_plan_work.restype = C.c_int
     L.gkb_batched_autotune.argtypes = [C.c_int, P(GkbMatrix), P(C.c_int), P(C.c_int), C.c_double, C.c_int,
                                        P(GkbBatchOptions), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, P(C.c_int), P(C.c_int), P(C.c_double), P(C.c_int)]
@@ -604,7 +607,7 @@ class BatchPlan:
 
     def __init__(self, As, r, k, tol, max_restarts, check_every=0, seed=0, q1=None, workgroups=0,
                  no_graph=False, eps_break=0.0, threads=0, stream=None, tune=False, tune_cache=None, max_team=0,
-                 form=0):
+                 form=0, cost_estimate=None):
         torch = _torch()
         L = lib()
         self.batch = len(As)
@@ -637,9 +640,29 @@ class BatchPlan:
             o.q1_packed = q1.data_ptr()
         self.opts = o
         self.tuning = None
+        self.plan = None
+        if tune and cost_estimate is None:
+            # calibration: one run with the default schedule measures what
+            # each problem costs on one workgroup; that weighs the schedule
+            self._create(tol, max_restarts, stream)
+            self.run(stream)
+            cost_estimate = self.work(stream)
+            self.close()
+        self.cost_estimate = None
+        if cost_estimate is not None:
+            if len(cost_estimate) != self.batch:
+                raise ValueError("cost_estimate needs one value per problem")
+            self.cost_estimate = (C.c_double * self.batch)(*[float(x) for x in cost_estimate])
+            o.cost_estimate = C.cast(self.cost_estimate, C.c_void_p)
         if tune:
             self.tuning = self._autotune(tol, max_restarts, stream, tune_cache)
             o.threads, o.workgroups = self.tuning["threads"], self.tuning["workgroups"]
+            self.tuning["measured_costs"] = self.cost_estimate is not None
+        self._create(tol, max_restarts, stream)
+
+    def _create(self, tol, max_restarts, stream):
+        L = lib()
+        o = self.opts
         plan = C.c_void_p()
         st = L.gkb_batched_plan_create(self.batch, self.mats, self.r_arr, self.k_arr, float(tol), int(max_restarts),
                                        C.byref(o), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
@@ -714,6 +737,15 @@ class BatchPlan:
             os_ += rr
             ou += m * rr
             ov += n * rr
+        return out
+
+    def work(self, stream=None):
+        """Per problem: ms its first workgroup spent on it in the last run, times
+        its team size (gkb_batched_plan_work)."""
+        out = np.zeros(self.batch, dtype=np.float64)
+        st = lib().gkb_batched_plan_work(self.plan, out.ctypes.data_as(C.c_void_p), _stream(stream))
+        if st != 0:
+            raise GkbError(st, lib().gkb_batched_last_error().decode())
         return out
 
     def close(self):

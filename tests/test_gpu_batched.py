@@ -145,6 +145,44 @@ def test_batched_inline_and_outline_forms_agree():
         gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, form=3)
 
 
+def test_batched_schedule_from_measured_work():
+    """A plan whose schedule is weighed by each problem's measured cost from a
+    first run (teams for the slowly converging problems) solves every problem
+    as the oracle does; bad estimates are refused."""
+    import torch
+    device()
+    mats, rs, ks = small_batch(10, seed=41)
+    # two larger problems, one converging slowly (ratio 0.97), one fast
+    for j, (m, n, rho) in enumerate([(2400, 1000, 0.97), (2000, 900, 0.7)]):
+        mats.append(inputs.svd_matrix(m, n, rho ** np.arange(n), seed=50 + j)[0].astype(np.float32))
+        rs.append(8)
+        ks.append(26)
+    banner("batched schedule weighed by measured work")
+    qs = [inputs.start_vector(A.shape[0], seed=300 + i) for i, A in enumerate(mats)]
+    Ad = [to_dev(A) for A in mats]
+    q1 = to_dev(np.concatenate(qs))
+    first = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, check_every=5, q1=q1)
+    first.run()
+    work = first.work()
+    first.close()
+    assert np.all(work > 0) and work.shape == (len(mats),)
+    print(f"  measured work (ms on one workgroup): {np.round(work, 3).tolist()}", flush=True)
+    plan = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, check_every=5, q1=q1, cost_estimate=work)
+    plan.run()
+    info = plan.info()
+    res = plan.results()
+    torch.cuda.synchronize()
+    worst = check_against_oracle(mats, rs, ks, res, info, qs, 5)
+    print(f"  weighted schedule: max rel sigma err vs oracle {worst:.3e}", flush=True)
+    plan.close()
+    with pytest.raises(ValueError):
+        gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, cost_estimate=work[:-1])
+    bad = work.copy()
+    bad[3] = np.nan
+    with pytest.raises(gkb.GkbError):
+        gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, cost_estimate=bad)
+
+
 def test_batched_validation():
     device()
     banner("batched validation")
@@ -166,6 +204,7 @@ def test_batched_autotuner_picks_a_valid_config(tmp_path):
     plan = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=9, tune=True, tune_cache=cache)
     t = plan.tuning
     assert t["threads"] in (512, 1024) and t["workgroups"] > 0 and not t["cached"]
+    assert t["measured_costs"]
     assert len(t["times_ms"]) == 3 and min(x for x in t["times_ms"] if x > 0) > 0
     plan.run()
     info = plan.info()
