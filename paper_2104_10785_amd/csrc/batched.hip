@@ -198,6 +198,9 @@ __device__ void bgemv_n_body(const BatchProblem& P, const float* p_, const float
     const GMEM float* rows[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) rows[r] = A + (int64_t)min(i0 + r, hi - 1) * P.lda;
+    // lane r < R fetches qprev of row i0 + r now, so that writing the row's
+    // result after its reduction does not wait for a load
+    const float qp = (qprev_ != nullptr && lane < R && i0 + lane < hi) ? qprev[i0 + lane] : 0.f;
     float a[R] = {};
     int jt = 0;
     if (vec) {
@@ -230,7 +233,7 @@ __device__ void bgemv_n_body(const BatchProblem& P, const float* p_, const float
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double sr = wsum((double)a[r]);
-      if (lane == 0 && i0 + r < hi) w[i0 + r] = sr - (qprev_ ? c * (double)qprev[i0 + r] : 0.0);
+      if (lane == r && i0 + r < hi) w[i0 + r] = sr - (qprev_ ? c * (double)qp : 0.0);
     }
   }
   __syncthreads();
