@@ -657,8 +657,8 @@ def main():
                     help="with --kernels-only: the sparse products (column panels and CSR) instead")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the Golub-Kahan path on a single "
-              "MI355X (multi-GPU sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        print("bench.py measures one GPU only: the Golub-Kahan path runs on a single MI355X; "
+              "sharding across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -75,7 +75,7 @@ def run(m=20000, n=5000, r=30, k=70, tol=1e-8, ratio=0.97, rank=4, scale=1e-3, t
     held out: the network is trained on the others, and the parameters it
     starts from and those after every eval_every-th epoch are scored by the
     mean number of products the held-out solves need from the network's start
-    vector (the convergence test is the judge); the best-scoring parameters
+    vector (the convergence test decides); the best-scoring parameters
     (the earliest on a tie) are the ones evaluated.  Adam's step size decays from lr to lr * lr_final along a
     cosine over the epochs, so the updates shrink as the loss flattens.
 
