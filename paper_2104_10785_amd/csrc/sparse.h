@@ -34,6 +34,7 @@ struct PanelDev {
   const PnDesc* sblk = nullptr;
   const PnDesc* witem = nullptr;
   const PnDesc* segs = nullptr;
+  const int32_t* lrow = nullptr;   // long rows of the stream blocks
   int64_t njobs = 0, nsegs = 0;
   float* slot = nullptr;           // chunk sums
   float* partial = nullptr;        // np x R row sums per panel (np > 1)

@@ -15,9 +15,9 @@
 //  * stream blocks: runs of consecutive rows whose segments in the panel hold
 //    at most PN_BIG entries, at most PN_BLK entries and PN_ROWS rows per block.
 //    The block's products go to LDS; a row of at most PN_SHORT entries is
-//    added by one thread in entry order, a longer one by a wave (lane l adds
-//    entries l, l + 64, ... in order, the 64 lane sums meet in a fixed
-//    butterfly);
+//    added by one thread in entry order, a longer one (listed with the block)
+//    by a wave (lane l adds entries l, l + 64, ... in order, the 64 lane sums
+//    meet in a fixed butterfly);
 //  * wave items: a segment of more than PN_BIG entries, in chunks of at most
 //    PN_CHUNK entries (one wave per chunk, summed like a long row), each chunk
 //    with a chunk-sum slot; the slots are added in chunk order afterwards.
@@ -35,8 +35,8 @@ namespace gkb {
 constexpr int PN_W = 28672;      // columns per panel (112 KB of float32 x)
 constexpr int PN_T = 1024;       // threads of a panel workgroup
 constexpr int PN_SHORT = 32;     // rows of a stream block up to this length are added by one thread
-constexpr int PN_BLK = 8192;     // entries of a stream block (8 per thread)
-constexpr int PN_BIG = 4096;     // longer segments are cut into wave items
+constexpr int PN_BLK = 4096;     // entries of a stream block (4 per thread)
+constexpr int PN_BIG = 2048;     // longer segments are cut into wave items
 constexpr int PN_ROWS = 1023;    // rows of a stream block (thread t adds row t)
 constexpr int PN_CHUNK = 4096;   // entries of a wave item
 constexpr int PN_JOB_MIN = 8192; // smallest job cost worth a panel load
@@ -48,7 +48,8 @@ struct PnDesc {
 };
 
 // job: {panel, kind (0 stream blocks, 1 wave items), first item, item count}
-// stream block: {first row, rows, first entry (relative to the panel), entries}
+// stream block: {first row, rows | entries << 10 | long rows << 23, first entry
+//                (relative to the panel), first long row in lrow}
 // wave item: {row, first entry (relative to the panel), entries, chunk-sum slot}
 // chunked segment: {panel, row, first slot, slots}
 struct PanelLayout {
@@ -59,8 +60,15 @@ struct PanelLayout {
   std::vector<uint16_t> pidx;      // nnz column indices relative to the panel (+ one padding entry)
   std::vector<float> pval;         // nnz values (+ one padding entry)
   std::vector<PnDesc> jobs, sblk, witem, segs;
+  std::vector<int32_t> lrow;       // per stream block, its rows of more than PN_SHORT entries
+                                   // (row within the block), + one padding entry
   int64_t nslot = 0;
 };
+
+// Fields of a stream block's second descriptor word.
+inline int32_t pn_pack(int32_t rows, int32_t entries, int32_t longs) { return rows | entries << 10 | longs << 23; }
+static_assert(PN_ROWS < (1 << 10) && PN_BLK < (1 << 13) && PN_BLK / (PN_SHORT + 1) < (1 << 8),
+              "stream block fields do not fit their bits");
 
 // Whether the panel layout is used for a matrix of this shape: one panel, or
 // at most 4 row segments (including empty ones) per stored entry, panels of

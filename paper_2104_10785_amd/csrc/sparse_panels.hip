@@ -14,12 +14,14 @@ namespace gkb {
 
 namespace {
 
-constexpr int PN_EPT = PN_BLK / PN_T;                               // entries per thread in a stream block (8)
-constexpr int PN_LONG = PN_BLK / (PN_SHORT + 1) + 1;                // long rows a block can hold
-// the job's item descriptors (and four empty ones after them), x panel,
-// products, row offsets, long-row count and list
+constexpr int PN_EPT = PN_BLK / PN_T;                               // entries per thread in a stream block (4)
+constexpr int PN_LONG = 128;                                        // long rows a block can hold
+static_assert(PN_BLK / (PN_SHORT + 1) <= PN_LONG, "long-row list too short");
+// the job's item descriptors (and four empty ones after them), x panel, and
+// two buffers of products, row offsets and long-row lists
 constexpr int PN_DSC = PN_JOB_ITEMS + 4;
-constexpr int PN_LDS = PN_DSC * 16 + (PN_W + PN_BLK + PN_ROWS + 1 + 1 + PN_LONG) * 4;
+constexpr int PN_LDS = PN_DSC * 16 + (PN_W + 2 * (PN_BLK + PN_ROWS + 1 + PN_LONG)) * 4;
+static_assert(PN_LDS <= 160 * 1024, "panel workgroup LDS above the compute unit's 160 KB");
 constexpr int PN_XV = (PN_W / 4 + PN_T - 1) / PN_T;                 // float4 of the x panel per thread
 constexpr int PN_WAVE_LOADS = 8;                                     // entries per lane in flight (wave items)
 
@@ -39,92 +41,102 @@ __device__ __forceinline__ void put_row(const PanelDev& P, int b, int64_t row, f
 }
 
 // One stream block's operands in registers: its descriptor, thread t's row
-// offset and thread t's entries (t + u PN_T, u < PN_EPT).
+// offset, thread t's entry of the block's long-row list and thread t's
+// entries (t + u PN_T, u < PN_EPT).
 struct BlkRegs {
   PnDesc d;
-  int o;
+  int o, lr;
   uint32_t ii[PN_EPT];
   float vv[PN_EPT];
 };
 
+__device__ __forceinline__ int blk_rows(const PnDesc& d) { return d.b & 1023; }
+__device__ __forceinline__ int blk_entries(const PnDesc& d) { return (d.b >> 10) & 8191; }
+__device__ __forceinline__ int blk_longs(const PnDesc& d) { return d.b >> 23; }
+
 // Every load is issued unconditionally (indices clamped into the block, the
 // values of lanes past its end zeroed afterwards), so that the compiler can
 // count the loads in flight exactly and wait for one block's loads only.  An
-// empty block reads the entry at its start, which the layout pads.
+// empty block reads the entry at its start and the padding of the long-row
+// list.
 __device__ __forceinline__ void blk_load(BlkRegs& B, const PnDesc* dsc, int s, const int32_t* __restrict__ po,
-                                         const uint16_t* __restrict__ ci, const float* __restrict__ cv, int t) {
+                                         const int32_t* __restrict__ lrow, const uint16_t* __restrict__ ci,
+                                         const float* __restrict__ cv, int t) {
   B.d = dsc[s];
-  B.o = po[B.d.a + min(t, B.d.b)];
+  const int nr = blk_rows(B.d), cnt = blk_entries(B.d), lc = blk_longs(B.d);
+  B.o = po[B.d.a + min(t, nr)];
+  B.lr = lrow[B.d.d + min(t, max(lc - 1, 0))];
 #pragma unroll
   for (int u = 0; u < PN_EPT; ++u) {
     const int q = t + u * PN_T;
-    const int qc = q < B.d.d ? q : 0;
+    const int qc = q < cnt ? q : 0;
     B.ii[u] = ci[B.d.c + qc];
     B.vv[u] = cv[B.d.c + qc];
   }
 }
 
-// Block s (operands in B): products into LDS, then B receives block s + 2
-// (an empty descriptor past the job's end), then the row sums.
-__device__ __forceinline__ void blk_step(BlkRegs& B, int s, const PnDesc* dsc,
-                                         const int32_t* __restrict__ po, const uint16_t* __restrict__ ci,
+// Block s (operands in B) on LDS buffer K: its offsets, long-row list and
+// products into the buffer, then B receives block s + 2 (an empty descriptor
+// past the job's end), then one barrier, then the row sums: rows of at most
+// PN_SHORT entries by their thread, the listed long rows by the waves.  Block
+// s + 1 uses the other buffer, and the barrier of block s + 1 comes after
+// every thread's sums of block s, so one barrier per block suffices.
+template <int K>
+__device__ __forceinline__ void blk_step(BlkRegs& B, int s, const PnDesc* dsc, const int32_t* __restrict__ po,
+                                         const int32_t* __restrict__ lrow, const uint16_t* __restrict__ ci,
                                          const float* __restrict__ cv, const float* xs, float* prod, int* off,
-                                         int* nlong, int* lrow, const PanelDev& P, int b,
-                                         const float* __restrict__ prev, const double* __restrict__ coef, int cidx,
-                                         double* __restrict__ y, int t) {
-  if (t <= B.d.b) off[t] = B.o - B.d.c;
+                                         int* lst, const PanelDev& P, int b, const float* __restrict__ prev,
+                                         const double* __restrict__ coef, int cidx, double* __restrict__ y, int t) {
+  float* pk = prod + K * PN_BLK;
+  int* ok = off + K * (PN_ROWS + 1);
+  int* lk = lst + K * PN_LONG;
+  const int nr = blk_rows(B.d), cnt = blk_entries(B.d), lc = blk_longs(B.d);
+  if (t <= nr) ok[t] = B.o - B.d.c;
+  if (t < lc) lk[t] = B.lr;
   float pr[PN_EPT];
 #pragma unroll
   for (int u = 0; u < PN_EPT; ++u) pr[u] = B.vv[u] * xs[B.ii[u]];
 #pragma unroll
   for (int u = 0; u < PN_EPT; ++u) {
     const int q = t + u * PN_T;
-    if (q < B.d.d) prod[q] = pr[u];
+    if (q < cnt) pk[q] = pr[u];
   }
-  const PnDesc dc = B.d;
-  blk_load(B, dsc, s + 2, po, ci, cv, t);
-  if (t == 0) *nlong = 0;
+  const int r0 = B.d.a;
+  blk_load(B, dsc, s + 2, po, lrow, ci, cv, t);
   __syncthreads();
-  // short rows: a thread each, in entry order with eight LDS reads in flight;
-  // long rows are listed for the waves (the list order varies, each long
-  // row's sum does not)
-  if (t < dc.b) {
-    const int lo = off[t], hi = off[t + 1];
+  if (t < nr) {
+    const int lo = ok[t], hi = ok[t + 1];
     if (hi - lo <= PN_SHORT) {
+      // in entry order; eight LDS reads in flight per batch
       float acc = 0.f;
       int q = lo;
       for (; q + 8 <= hi; q += 8) {
-        float pk[8];
+        float pb[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) pk[k] = prod[q + k];
+        for (int k = 0; k < 8; ++k) pb[k] = pk[q + k];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc += pk[k];
+        for (int k = 0; k < 8; ++k) acc += pb[k];
       }
-      for (; q < hi; ++q) acc += prod[q];
-      put_row(P, b, (int64_t)dc.a + t, acc, prev, coef, cidx, y);
-    } else {
-      lrow[atomicAdd(nlong, 1)] = t;
+      for (; q < hi; ++q) acc += pk[q];
+      put_row(P, b, (int64_t)r0 + t, acc, prev, coef, cidx, y);
     }
   }
-  __syncthreads();
-  const int nl = *nlong;
-  for (int i = t >> 6; i < nl; i += PN_T / 64) {
-    const int rt = lrow[i], l = t & 63;
-    const int hi = off[rt + 1];
+  for (int i = t >> 6; i < lc; i += PN_T / 64) {
+    const int rt = lk[i], l = t & 63;
+    const int hi = ok[rt + 1];
     float acc = 0.f;
-    int q = off[rt] + l;
+    int q = ok[rt] + l;
     for (; q + 192 < hi; q += 256) {
-      const float p0 = prod[q], p1 = prod[q + 64], p2 = prod[q + 128], p3 = prod[q + 192];
+      const float p0 = pk[q], p1 = pk[q + 64], p2 = pk[q + 128], p3 = pk[q + 192];
       acc += p0;
       acc += p1;
       acc += p2;
       acc += p3;
     }
-    for (; q < hi; q += 64) acc += prod[q];
+    for (; q < hi; q += 64) acc += pk[q];
     acc = wave_sum(acc);
-    if (l == 0) put_row(P, b, (int64_t)dc.a + rt, acc, prev, coef, cidx, y);
+    if (l == 0) put_row(P, b, (int64_t)r0 + rt, acc, prev, coef, cidx, y);
   }
-  __syncthreads();
 }
 
 __global__ __launch_bounds__(PN_T) void k_panel_main(PanelDev P, const float* __restrict__ x,
@@ -133,10 +145,9 @@ __global__ __launch_bounds__(PN_T) void k_panel_main(PanelDev P, const float* __
   extern __shared__ float4 lds4[];
   PnDesc* dsc = reinterpret_cast<PnDesc*>(lds4);                       // PN_DSC
   float* xs = reinterpret_cast<float*>(lds4 + PN_DSC);                 // PN_W
-  float* prod = xs + PN_W;                                             // PN_BLK
-  int* off = reinterpret_cast<int*>(prod + PN_BLK);                    // PN_ROWS + 1
-  int* nlong = off + PN_ROWS + 1;                                      // 1
-  int* lrow = nlong + 1;                                               // PN_LONG
+  float* prod = xs + PN_W;                                             // 2 x PN_BLK
+  int* off = reinterpret_cast<int*>(prod + 2 * PN_BLK);                // 2 x (PN_ROWS + 1)
+  int* lst = off + 2 * (PN_ROWS + 1);                                  // 2 x PN_LONG
   if (flag != nullptr && flag[0] != 0) return;
   const PnDesc J = P.jobs[blockIdx.x];
   const int b = J.a;
@@ -180,11 +191,11 @@ __global__ __launch_bounds__(PN_T) void k_panel_main(PanelDev P, const float* __
   if (J.b == 0) {
     const int32_t* __restrict__ po = P.poff + (int64_t)b * (P.R + 1);
     BlkRegs A, B;
-    blk_load(A, dsc, 0, po, ci, cv, t);
-    blk_load(B, dsc, 1, po, ci, cv, t);
+    blk_load(A, dsc, 0, po, P.lrow, ci, cv, t);
+    blk_load(B, dsc, 1, po, P.lrow, ci, cv, t);
     for (int s = 0; s < J.d; s += 2) {
-      blk_step(A, s, dsc, po, ci, cv, xs, prod, off, nlong, lrow, P, b, prev, coef, cidx, y, t);
-      blk_step(B, s + 1, dsc, po, ci, cv, xs, prod, off, nlong, lrow, P, b, prev, coef, cidx, y, t);
+      blk_step<0>(A, s, dsc, po, P.lrow, ci, cv, xs, prod, off, lst, P, b, prev, coef, cidx, y, t);
+      blk_step<1>(B, s + 1, dsc, po, P.lrow, ci, cv, xs, prod, off, lst, P, b, prev, coef, cidx, y, t);
     }
   } else {
     // wave items {row, first entry, entries, chunk-sum slot}: a wave each
@@ -262,6 +273,7 @@ hipError_t place_panels(const PanelLayout& L, char* w, PanelDev& P, hipStream_t 
   P.sblk = reinterpret_cast<const PnDesc*>(put(L.sblk.data(), L.sblk.size() * 16));
   P.witem = reinterpret_cast<const PnDesc*>(put(L.witem.data(), L.witem.size() * 16));
   P.segs = reinterpret_cast<const PnDesc*>(put(L.segs.data(), L.segs.size() * 16));
+  P.lrow = reinterpret_cast<const int32_t*>(put(L.lrow.data(), L.lrow.size() * 4));
   P.njobs = (int64_t)L.jobs.size();
   P.nsegs = (int64_t)L.segs.size();
   P.slot = reinterpret_cast<float*>(w);

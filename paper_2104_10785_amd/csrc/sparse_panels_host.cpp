@@ -18,13 +18,14 @@ int64_t npanels(int64_t C) { return (C + PN_W - 1) / PN_W; }
 // than PN_BIG entries follows, or at the end of a panel; such a segment of L
 // entries gives at most 1 + L / PN_CHUNK chunks).
 struct Bounds {
-  int64_t sblk, witem, segs, jobs;
+  int64_t sblk, witem, segs, jobs, lrow;
 };
 Bounds bounds(int64_t R, int64_t C, int64_t nnz) {
   const int64_t np = npanels(C);
   Bounds b;
   const int64_t nbig = nnz / (PN_BIG + 1);
   b.sblk = nnz / (PN_BLK - PN_BIG) + np * R / PN_ROWS + nbig + np + 1;
+  b.lrow = nnz / (PN_SHORT + 1) + 1;
   b.witem = nbig + nnz / PN_CHUNK + 1;
   b.segs = nbig + 1;
   b.jobs = b.sblk + b.witem;   // every job holds at least one item
@@ -48,6 +49,7 @@ size_t panel_bytes_bound(int64_t R, int64_t C, int64_t nnz) {
              a256((size_t)(np + 1) * 8);
   s += a256((size_t)b.jobs * 16) + a256((size_t)b.sblk * 16) + a256((size_t)b.witem * 16) + a256((size_t)b.segs * 16);
   s += a256((size_t)b.witem * 4);                        // chunk-sum slots
+  s += a256((size_t)(b.lrow + 1) * 4);                   // long rows of the stream blocks
   if (np > 1) s += a256((size_t)np * R * 4);             // per-panel row sums
   return s + 256;
 }
@@ -86,6 +88,7 @@ void build_panels(int64_t R, int64_t C, int64_t nnz, const int64_t* ptr, const i
   L.sblk.clear();
   L.witem.clear();
   L.segs.clear();
+  L.lrow.clear();
   L.nslot = 0;
   std::vector<size_t> s_first(np + 1), w_first(np + 1);
   for (int b = 0; b < np; ++b) {
@@ -93,9 +96,14 @@ void build_panels(int64_t R, int64_t C, int64_t nnz, const int64_t* ptr, const i
     s_first[b] = L.sblk.size();
     w_first[b] = L.witem.size();
     int32_t r0 = 0, nr = 0, e0 = 0, ecnt = 0;
+    std::vector<int32_t> longs;
     auto flush = [&]() {
-      if (nr > 0) L.sblk.push_back({r0, nr, e0, ecnt});
+      if (nr > 0) {
+        L.sblk.push_back({r0, pn_pack(nr, ecnt, (int32_t)longs.size()), e0, (int32_t)L.lrow.size()});
+        L.lrow.insert(L.lrow.end(), longs.begin(), longs.end());
+      }
       nr = 0;
+      longs.clear();
     };
     for (int64_t r = 0; r < R; ++r) {
       const int32_t s = po[r], len = po[r + 1] - po[r];
@@ -106,6 +114,7 @@ void build_panels(int64_t R, int64_t C, int64_t nnz, const int64_t* ptr, const i
           e0 = s;
           ecnt = 0;
         }
+        if (len > PN_SHORT) longs.push_back(nr);
         ++nr;
         ecnt += len;
       } else {
@@ -121,11 +130,12 @@ void build_panels(int64_t R, int64_t C, int64_t nnz, const int64_t* ptr, const i
   }
   s_first[np] = L.sblk.size();
   w_first[np] = L.witem.size();
+  L.lrow.push_back(0);   // padding: an empty block's clamped read
   // jobs: each panel's stream blocks and wave items cut into parts of about
   // equal cost (entries + 2 per row, entries + 64 per wave item), the number
   // of parts in proportion to the cost, so that all jobs together number
   // about target_jobs (one workgroup per compute unit: a single round)
-  auto scost = [](const PnDesc& d) { return (int64_t)d.d + 2 * (int64_t)d.b; };
+  auto scost = [](const PnDesc& d) { return (int64_t)((d.b >> 10) & 8191) + 2 * (int64_t)(d.b & 1023); };
   auto wcost = [](const PnDesc& d) { return (int64_t)d.c + 64; };
   std::vector<int64_t> cs(np, 0), cw(np, 0), ks(np, 0), kw(np, 0);
   int64_t total_s = 0, total_w = 0;
