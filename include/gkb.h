@@ -56,7 +56,10 @@ typedef enum {
   GKB_ERR_HIP = -2,          /* a HIP runtime call failed                     */
   GKB_ERR_NUMERIC = -3,      /* NaN or Inf appeared in a norm                 */
   GKB_ERR_WORKSPACE = -4,    /* workspace missing, too small or misaligned    */
-  GKB_ERR_TIMEOUT = -5       /* batched form: a team barrier waited too long  */
+  GKB_ERR_TIMEOUT = -5       /* a team of workgroups waited too long for one  */
+                             /* of its members (batched form; one-sweep step */
+                             /* on rows longer than 24576), which happens    */
+                             /* only if the device is not free for the grid  */
 } gkb_status;
 
 typedef enum {
@@ -98,8 +101,10 @@ typedef struct {
                        /* paper's Algorithm 2)                                 */
   int one_pass;        /* 1: read A once per step instead of twice (GKB_F32   */
                        /* or GKB_BF16 with n, lda multiples of 4 or 8,         */
-                       /* n <= 24576, A 16-byte aligned; for any other A,      */
-                       /* including sparse A, the two-product step runs and    */
+                       /* n <= 262144, A 16-byte aligned; rows longer than     */
+                       /* 24576 are split over teams of workgroups that must   */
+                       /* all be resident, see GKB_ERR_TIMEOUT; for any other  */
+                       /* A, including sparse A, the two-product step runs and */
                        /* stats.one_pass_used is 0).  One sweep forms          */
                        /* A p and A^T A p in float64; A^T q_{i+1} then follows */
                        /* from eq. (2.2) as (A^T A p - (A^T Q) c) / beta, with */

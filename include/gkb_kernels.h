@@ -32,11 +32,18 @@ gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, 
  * Both products of a Golub-Kahan step in one sweep of A: w = A p (m doubles)
  * and y = A^T w (n doubles), every sum in float64 (A float32 or bfloat16,
  * row-major, lda and n multiples of 4 (float32) or 8 (bfloat16), A 16-byte
- * aligned, n <= 24576; p float32, n entries).  A workgroup streams a range of rows once, reducing each row's
- * dot product before adding the row, scaled by it, into its partial of A^T w;
- * the partials (gkb_matvec_fused_workspace_size bytes) are added in a fixed
- * order.  A^T q of the next Lanczos vector then follows from y and the
- * recurrence (eq. (2.2)).  Returns GKB_ERR_INVALID for other shapes.
+ * aligned, n <= 262144; p float32, n entries).  A workgroup streams a range
+ * of rows once, reducing each row's dot product before adding the row, scaled
+ * by it, into its partial of A^T w; rows longer than 24576 are split into
+ * slices of at most 8192 columns, one per workgroup of a team, whose members
+ * exchange their parts of each row's dot product through the workspace.  The
+ * partials (in gkb_matvec_fused_workspace_size bytes, with the teams'
+ * exchange area, which each call zeroes first) are added in a fixed order, so
+ * results are reproducible.  A^T q of the next Lanczos vector then follows
+ * from y and the recurrence (eq. (2.2)).  A team's members must all be
+ * resident at once (one workgroup per compute unit at most); if the device is
+ * not free for the whole grid, a member stops waiting after about a second
+ * and its outputs are NaN.  Returns GKB_ERR_INVALID for other shapes.
  */
 size_t gkb_matvec_fused_workspace_size(const gkb_matrix* A);
 gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, double* y, void* workspace,

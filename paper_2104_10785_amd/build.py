@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgkb.so")
 SOURCES = ["gemv.hip", "kernels.hip", "gkb_driver.hip", "host_svd.cpp", "batched.hip", "gkb_batched_api.hip", "learned.hip",
-           "sparse.hip", "sparse_panels.hip", "sparse_panels_host.cpp", "rsgd.hip", "fused.hip", "reorth.hip"]
+           "sparse.hip", "sparse_panels.hip", "sparse_panels_host.cpp", "rsgd.hip", "fused.hip", "fused_team.hip", "reorth.hip"]
 
 ARCH = "gfx950"
 # Packed-FP32 instructions are disabled for all device code.

@@ -8,17 +8,36 @@
 
 namespace gkb {
 
-constexpr int64_t FUSED_NMAX = 24576;    // longest row (768 threads x 8 groups of 4 floats)
+constexpr int64_t FUSED_NMAX = 24576;    // longest row of the single-workgroup sweep (768 threads x 8 groups of 4 floats)
+constexpr int64_t FUSED_TEAM_NMAX = 262144;   // longest row of the team sweep (32 members x 8192 columns)
 // a recovered A^T q column is recomputed directly once its error bound
 // exceeds this fraction of the largest coefficient seen
 constexpr double ONEPASS_TAU = 1e-10;
 
 // true if A (m x n, lda; dtype 1 = float32, 2 = bfloat16) can take the fused
 // sweep: n and lda multiples of the 16-byte group (4 or 8 elements),
-// n <= FUSED_NMAX, A 16-byte aligned
+// n <= FUSED_NMAX (one workgroup per row range) or, for longer rows, a team
+// shape exists (n <= FUSED_TEAM_NMAX and at most one member per compute
+// unit), A 16-byte aligned
 bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A, int dtype);
-// number of workgroups (= partial-sum rows) the sweep uses
+// number of partial-sum rows the sweep writes (workgroups, or teams for
+// rows longer than FUSED_NMAX)
 int fused_blocks(int64_t m, int64_t n);
+
+// The team sweep (rows longer than FUSED_NMAX): C members per team, each
+// owning a near-equal slice of at most 8192 columns; teams of rpt rows
+// (the last may be shorter, none empty), nsteps steps of rows per team;
+// C = 0 if the shape has no team form.
+struct TeamShape {
+  int C, nteams, rpt, nsteps;
+};
+TeamShape team_shape(int64_t m, int64_t n);
+// device bytes of the team sweep's mailbox and counters (0 if no team form);
+// the sweep's `team` argument points to this many bytes, 256-byte aligned,
+// zeroed by launch_team_reset before the first sweep and then left to the
+// sweeps (each launch leaves it ready for the next)
+size_t team_bytes(int64_t m, int64_t n);
+hipError_t launch_team_reset(void* team, int64_t m, int64_t n, hipStream_t st);
 
 // A float32 (dtype 1) or bfloat16 (dtype 2, widened exactly to float32).
 // With win == nullptr: w = A p (float64, m) and the partials of y = A^T w;
@@ -28,12 +47,21 @@ int fused_blocks(int64_t m, int64_t n);
 // fused_blocks(m, n) x ldy doubles (ldy >= n); y (n doubles) gets their sum in
 // a fixed order unless y is null.  Skipped when flag[0] != 0, or when run_if
 // is given and run_if[0] == 0.  With qprev given, w = A p - coef[0] qprev
-// (the recurrence term of eq. (2.2)) while y stays A^T (A p).
+// (the recurrence term of eq. (2.2)) while y stays A^T (A p).  Rows longer
+// than FUSED_NMAX take the team sweep, which needs `team` (team_bytes(m, n)
+// bytes, see launch_team_reset) and may set flag[0] = 4 when a member waited
+// too long for the others (its results are then NaN); flag must be writable
+// device memory or null.
 template <typename TP>
 hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, int64_t n, const TP* p,
                              const double* win, double* w, double* y, double* ypart, int64_t ldy, const int* flag,
                              hipStream_t st, const int* run_if = nullptr, const double* qprev = nullptr,
-                             const double* coef = nullptr);
+                             const double* coef = nullptr, void* team = nullptr);
+template <typename TP>
+hipError_t launch_gemv_fused_team(const void* A, int dtype, int64_t lda, int64_t m, int64_t n, const TP* p,
+                                  const double* win, double* w, double* ypart, int64_t ldy, const int* flag,
+                                  hipStream_t st, const int* run_if, const double* qprev, const double* coef,
+                                  void* team);
 
 // The recovery of A^T q_tq after w = A p - Q[:, 0..t) c_tot has been
 // normalised to beta q_tq, with c_tot[j] = c[j] plus xc[j - x0] for

@@ -20,21 +20,20 @@
 
 #include "device_common.h"
 #include "fused.h"
+#include "fused_device.h"
 #include "gemv.h"
 
 namespace gkb {
 
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
+using fdev::f4;
+using fdev::wsum;
+using fdev::Elems;
+using fdev::lds_barrier;
+using fdev::RSRC_WORD3;
 
 inline unsigned nblk(int64_t work, int64_t per) { return (unsigned)((work + per - 1) / per); }
-
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // T threads; U = 16-byte column groups per thread (thread t owns groups
 // t, t + T, ...); R rows per step, the next D groups of R rows already
@@ -44,26 +43,7 @@ __device__ __forceinline__ double wsum(double v) {
 // stays live across it (fewer registers, more waves per CU).
 // GIVEN_W: w is an input (y = A^T win) and no row needs a reduction.
 // TA: float (4 per 16-byte group) or bfloat16 (8 per group, widened exactly
-// to float32).
-template <typename TA> struct Elems;
-template <> struct Elems<float> {
-  static constexpr int VN = 4;
-  static constexpr bool F32DOT = false;   // row dot products in float64
-  __device__ __forceinline__ static float at(const f4& v, int e) { return v[e]; }
-};
-template <> struct Elems<bf16> {
-  static constexpr int VN = 8;
-  // per-thread dot products in float32 (as the two-product bfloat16 path
-  // accumulates), then float64 across threads: halves the arithmetic per
-  // element, which bounds this form; A^T w stays float64 and is exact for
-  // whatever w is computed, so the recovery is unaffected
-  static constexpr bool F32DOT = true;
-  __device__ __forceinline__ static float at(const f4& v, int e) {
-    const uint32_t b = __float_as_uint(v[e >> 1]);
-    return __uint_as_float((e & 1) ? (b & 0xffff0000u) : (b << 16));
-  }
-};
-
+// to float32; Elems).
 template <int T, int U, int R, int D, typename TA, typename TP, bool GIVEN_W>
 __global__ __launch_bounds__(T) void k_gemv_fused(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                   const TP* __restrict__ p, const double* __restrict__ win,
@@ -237,14 +217,6 @@ __global__ __launch_bounds__(T) void k_gemv_fused(const TA* __restrict__ A, int6
       for (int e = 0; e < VN; ++e) yp[VN * g + e] = y[u][e];
   }
 }
-
-// LDS writes complete, then the workgroup barrier.  Unlike __syncthreads()
-// this does not order global memory, so the row loads in flight stay in
-// flight across it (every value exchanged at these barriers is in LDS).
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-// Word 3 of a raw buffer resource on gfx9 (32-bit data format, no swizzle).
-constexpr int RSRC_WORD3 = 0x00020000;
 
 // The same sweep, pipelined so that the loads of the next rows overlap the
 // reduction and barrier of the current ones.  The vector memory counter is
@@ -715,11 +687,13 @@ __global__ __launch_bounds__(256) void k_narrow(const double* __restrict__ src, 
 
 bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A, int dtype) {
   const int64_t vn = dtype == 2 ? 8 : 4;
-  return (dtype == 1 || dtype == 2) && m >= 1 && m < (int64_t(1) << 30) && n >= vn && n <= FUSED_NMAX &&
-         n % vn == 0 && lda % vn == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  return (dtype == 1 || dtype == 2) && m >= 1 && m < (int64_t(1) << 30) && n >= vn &&
+         (n <= FUSED_NMAX || (n <= FUSED_TEAM_NMAX && team_shape(m, n).C > 0)) && n % vn == 0 && lda % vn == 0 &&
+         (reinterpret_cast<uintptr_t>(A) & 15) == 0;
 }
 
 int fused_blocks(int64_t m, int64_t n) {
+  if (n > FUSED_NMAX) return std::max(1, team_shape(m, n).nteams);
   // bpc workgroups per compute unit, each an equal share of the rows
   return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)fused_shape(n).bpc * device_cus(), m));
 }
@@ -727,10 +701,14 @@ int fused_blocks(int64_t m, int64_t n) {
 template <typename TP>
 hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, int64_t n, const TP* p,
                              const double* win, double* w, double* y, double* ypart, int64_t ldy, const int* flag,
-                             hipStream_t st, const int* run_if, const double* qprev, const double* coef) {
+                             hipStream_t st, const int* run_if, const double* qprev, const double* coef,
+                             void* team) {
   const FusedShape fs = fused_shape(n);
   hipError_t e;
   const bool gw = win != nullptr;
+  if (n > FUSED_NMAX) {
+    e = launch_gemv_fused_team<TP>(A, dtype, lda, m, n, p, win, w, ypart, ldy, flag, st, run_if, qprev, coef, team);
+  } else
   // Shapes measured on MI355X (w = A p and A^T w, float64 p): the pipelined
   // form where it is faster, the per-row barrier form elsewhere and for the
   // given-w sweep (w read, no reduction), and wherever the pipelined form's
@@ -794,10 +772,10 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
 
 template hipError_t launch_gemv_fused<float>(const void*, int, int64_t, int64_t, int64_t, const float*, const double*,
                                              double*, double*, double*, int64_t, const int*, hipStream_t,
-                                             const int*, const double*, const double*);
+                                             const int*, const double*, const double*, void*);
 template hipError_t launch_gemv_fused<double>(const void*, int, int64_t, int64_t, int64_t, const double*,
                                               const double*, double*, double*, double*, int64_t, const int*,
-                                              hipStream_t, const int*, const double*, const double*);
+                                              hipStream_t, const int*, const double*, const double*, void*);
 
 hipError_t launch_onepass_recover(const double* ypart, int nb, int64_t ldy, double* G, int64_t ldg, int t,
                                   const double* c, const double* xc, int x0, int nx, const double* beta, int tq,

@@ -55,6 +55,7 @@ struct Layout {
   size_t qcoef = 0, pcoef = 0, sig = 0, flag = 0, Xs = 0, Ys = 0, rho = 0, q1 = 0;
   size_t Vd = 0, Wr = 0, Gpart = 0, G = 0;  // bfloat16 refinement
   size_t GQ[2] = {0, 0}, y = 0, ypart = 0, csum = 0, Uo = 0, Vo = 0, err[2] = {0, 0}, refresh = 0;  // one-pass
+  size_t team = 0, team_bytes = 0;  // the team sweep's mailbox (rows longer than FUSED_NMAX)
   size_t total = 0;
 };
 
@@ -123,6 +124,10 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
     L.refresh = take(4 * sizeof(int));
     L.Uo = take((size_t)L.ldm * L.kcols * 8);
     L.Vo = take((size_t)L.ldn * L.kcols * 8);
+    if (n > gkb::FUSED_NMAX) {
+      L.team_bytes = gkb::team_bytes(m, n);
+      L.team = take(L.team_bytes);
+    }
   }
   L.total = off;
   return L;
@@ -141,7 +146,8 @@ gkb_status check_matrix(const gkb_matrix* A) {
 }
 
 // The one-sweep step runs on dense float32 or bfloat16 A whose rows the sweep
-// kernels hold (n <= 24576, n and lda multiples of the 16-byte group, A
+// kernels take (n <= 24576 in one workgroup's registers, longer rows up to
+// 262144 by teams of workgroups; n and lda multiples of the 16-byte group, A
 // 16-byte aligned); elsewhere a one_pass request runs the two-product step.
 bool one_pass_available(const gkb_matrix* A) {
   return gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype);
@@ -270,6 +276,7 @@ struct Solver {
   double* csum() { return reinterpret_cast<double*>(ws + L.csum); }
   double* err(int b) { return reinterpret_cast<double*>(ws + L.err[b]); }
   int* refresh() { return reinterpret_cast<int*>(ws + L.refresh); }
+  void* team() { return L.team_bytes ? ws + L.team : nullptr; }
   double eps0() const { return std::ldexp(1.0, -52) * std::sqrt((double)(A.m + A.n)); }
   bool onepass = false;  // dense float32 A, float64 bases, one sweep of A per step
   PhaseTimer pt;         // per-phase device time (opt.phase_timing)
@@ -372,8 +379,10 @@ struct Solver {
     if (onepass) {
       // z = A^T q_1 with float64 sums, kept as the first column of A^T Q
       if constexpr (std::is_same<TB, double>::value) {
+        // the team sweep's mailbox starts each solve zeroed
+        if (team() != nullptr) GKB_HIP(gkb::launch_team_reset(team(), A.m, A.n, st));
         GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, nullptr, Qc(0), nullptr, z(), ypart(), L.ldn,
-                                               flag(), st));
+                                               flag(), st, nullptr, nullptr, nullptr, team()));
         GKB_HIP(gkb::launch_copy_vec<double>(z(), A.n, GQ(cur), st));
         GKB_HIP(hipMemsetAsync(refresh(), 0, 4 * sizeof(int), st));
       }
@@ -439,7 +448,7 @@ struct Solver {
       GKB_HIP(mark(PH_MATVEC));
       GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, Pc(pi), nullptr, w(), nullptr, ypart(),
                                              L.ldn, flag(), st, nullptr, use_rho ? nullptr : Qc(qp),
-                                             use_rho ? nullptr : pcoef() + pi));
+                                             use_rho ? nullptr : pcoef() + pi, team()));
       ++a_passes;
       GKB_HIP(mark(PH_REORTH));
       if (use_rho)
@@ -467,7 +476,7 @@ struct Solver {
                                           nullptr, qn, Pc(pi), z(), A.n, err(cur), nullptr, eps0(),
                                           gkb::ONEPASS_TAU, refresh(), flag(), st, &na));
       GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, nullptr, Qc(qn), nullptr, nullptr, ypart(),
-                                             L.ldn, flag(), st, refresh()));
+                                             L.ldn, flag(), st, refresh(), nullptr, nullptr, team()));
       // if the column was recomputed: A^T q_qn from the direct sweep's partial
       // sums replaces the recovered one (G[:, qn] and z), as the first
       // Gram-Schmidt launch's pre-step
@@ -583,6 +592,9 @@ gkb_status assemble(bool first, int np_now, const RestartIn& rs, const std::vect
                     const std::vector<double>& pc, const int* fl, Proj& pr) {
   const int code = fl[0], idx = fl[1];
   if (code == 3) return fail(GKB_ERR_NUMERIC, "NaN or Inf in a norm (non-finite input?)");
+  if (code == 4)
+    return fail(GKB_ERR_TIMEOUT, "one-sweep step: a workgroup of a team waited too long for the others "
+                                 "(the device was not free for the whole grid)");
   if (first && code == 1 && idx == 0) return fail(GKB_ERR_INVALID, "start vector is zero");
   int nq, np;
   const int l = rs.l;
@@ -1400,7 +1412,9 @@ size_t gkb_matvec_workspace_size(const gkb_matrix* A) {
 
 size_t gkb_matvec_fused_workspace_size(const gkb_matrix* A) {
   if (check_matrix(A) != GKB_OK || !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype)) return 0;
-  return align256((size_t)gkb::fused_blocks(A->m, A->n) * round64(A->n) * 8);
+  // partial sums, then the team sweep's mailbox for rows longer than FUSED_NMAX
+  return align256((size_t)gkb::fused_blocks(A->m, A->n) * round64(A->n) * 8) +
+         (A->n > gkb::FUSED_NMAX ? align256(gkb::team_bytes(A->m, A->n)) : 0);
 }
 
 gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, double* y, void* workspace,
@@ -1410,13 +1424,19 @@ gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, doub
   if (rc != GKB_OK) return rc;
   if (!gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
     return fail(GKB_ERR_INVALID, "the fused sweep needs a float32 (bfloat16) A with lda and n multiples of 4 (8), "
-                                 "n <= 24576, 16-byte aligned");
+                                 "n <= 262144, 16-byte aligned");
   if (!p || !w || !y) return fail(GKB_ERR_INVALID, "p, w and y must be non-NULL");
   rc = check_workspace(workspace, ws_bytes, gkb_matvec_fused_workspace_size(A));
   if (rc != GKB_OK) return rc;
-  GKB_HIP(gkb::launch_gemv_fused<float>(A->data, (int)A->dtype, A->lda, A->m, A->n, p, nullptr,
-                                        w, y, reinterpret_cast<double*>(workspace), round64(A->n), nullptr,
-                                        reinterpret_cast<hipStream_t>(stream)));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  void* team = nullptr;
+  if (A->n > gkb::FUSED_NMAX) {
+    team = reinterpret_cast<char*>(workspace) + align256((size_t)gkb::fused_blocks(A->m, A->n) * round64(A->n) * 8);
+    GKB_HIP(gkb::launch_team_reset(team, A->m, A->n, st));
+  }
+  GKB_HIP(gkb::launch_gemv_fused<float>(A->data, (int)A->dtype, A->lda, A->m, A->n, p, nullptr, w, y,
+                                        reinterpret_cast<double*>(workspace), round64(A->n), nullptr, st, nullptr,
+                                        nullptr, nullptr, team));
   return GKB_OK;
 }
 

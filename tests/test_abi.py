@@ -201,7 +201,8 @@ def _options(**kw):
 
 def test_one_pass_availability_and_workspace():
     """The one-sweep step needs float32 with n and lda multiples of 4 (bfloat16:
-    8), n <= 24576 and a 16-byte aligned A; for any other A a one_pass request
+    8), n <= 262144 (longer than 24576: team sweeps, with their exchange area
+    in the workspace) and a 16-byte aligned A; for any other A a one_pass request
     takes the two-product step, so it passes the option checks (and here stops
     at the missing workspace) and its workspace is the two-product one.  The
     one-sweep workspace holds float64 bases and A^T Q."""
@@ -218,7 +219,7 @@ def test_one_pass_availability_and_workspace():
               _fake_matrix(n=52, data=0x1004),          # alignment
               _fake_matrix(n=52, dtype=gkb.GKB_F64),    # float64
               _fake_matrix(n=52, dtype=gkb.GKB_BF16),   # bfloat16 needs n % 8
-              _fake_matrix(m=100, n=24580)]             # n > 24576
+              _fake_matrix(m=100, n=262148)]            # n > 262144
     for bad in others:
         assert svd(bad) == -4 and "workspace" in gkb.last_error()
         assert L.gkb_workspace_size(C.byref(bad), 2, 4, C.byref(one)) == \
@@ -233,9 +234,16 @@ def test_one_pass_availability_and_workspace():
     assert w1 > w2 > 0
     bf = _fake_matrix(100, 48, gkb.GKB_BF16)
     assert L.gkb_workspace_size(C.byref(bf), 2, 4, C.byref(one)) > 0
+    # rows longer than one workgroup holds: team sweeps, whose exchange area
+    # (one entry of two words per row and member) is in the workspace
+    wide = _fake_matrix(20000, 80000, gkb.GKB_F32)
+    assert L.gkb_workspace_size(C.byref(wide), 10, 40, C.byref(one)) > \
+        L.gkb_workspace_size(C.byref(wide), 10, 40, C.byref(two)) + 20000 * 10 * 16
     # the building block takes the same shapes
     assert L.gkb_matvec_fused_workspace_size(C.byref(_fake_matrix(n=50))) == 0
     assert L.gkb_matvec_fused_workspace_size(C.byref(_fake_matrix(n=52))) > 0
+    assert L.gkb_matvec_fused_workspace_size(C.byref(_fake_matrix(n=262148))) == 0
+    assert L.gkb_matvec_fused_workspace_size(C.byref(wide)) >= 20000 * 10 * 16 + 80000 * 8
 
 
 def test_embedded_heuristic_initialisation_reproduces_the_heuristic():

@@ -23,7 +23,12 @@ SHAPES = [(1, 4, 0), (100, 8, 0), (257, 512, 4), (4000, 1000, 0), (3001, 2044, 0
           (777, 24576, 0), (70000, 100, 0), (1, 20000, 0), (257, 19996, 4), (3001, 16388, 0),
           # the pipelined form near its LDS limit (the staged w of 3907 rows per
           # workgroup), and past it (4883 rows: the per-row barrier form)
-          (4_000_000, 4, 0), (5_000_000, 4, 0)]
+          (4_000_000, 4, 0), (5_000_000, 4, 0),
+          # team sweeps (rows longer than one workgroup holds): just past the
+          # limit, uneven slices, a single row, padded rows, one row per team,
+          # the longest rows (32 members), many rows per team
+          (1000, 24580, 0), (600, 30000, 4), (1, 30000, 0), (300, 80004, 8), (40, 100000, 0),
+          (50, 262144, 0), (8000, 40000, 0)]
 
 
 def _padded(a, pad):
@@ -56,7 +61,8 @@ def test_fused_products(shape):
 
 
 BF16_SHAPES = [(1, 8, 0), (300, 1000, 8), (2000, 2048, 0), (3001, 4096, 0), (1500, 8000, 8), (1200, 16384, 0),
-               (5000, 20000, 8), (777, 24576, 0), (70000, 96, 0), (4_000_000, 8, 0), (5_000_000, 8, 0)]
+               (5000, 20000, 8), (777, 24576, 0), (70000, 96, 0), (4_000_000, 8, 0), (5_000_000, 8, 0),
+               (500, 30000, 0), (200, 80000, 8), (3, 262144, 0)]
 
 
 @pytest.mark.parametrize("shape", BF16_SHAPES)
@@ -88,7 +94,7 @@ def test_fused_products_bf16(shape):
 def test_fused_rejects_shapes():
     device()
     banner("fused sweep shape checks")
-    for shape in [(10, 6), (10, 24580)]:
+    for shape in [(10, 6), (10, 262148)]:
         Ad = to_dev(np.ones(shape, dtype=np.float32))
         with pytest.raises(gkb.GkbError):
             gkb.gkb_matvec_fused(Ad, to_dev(np.ones(shape[1], dtype=np.float32)))

@@ -140,21 +140,25 @@ def test_onepass_rank_deficient():
     assert np.all(U[:, 6:] == 0.0) and np.all(V[:, 6:] == 0.0)
 
 
-@pytest.mark.parametrize("l", [1, 5, 37, 100])
-def test_onepass_rank_exact_products(l):
+@pytest.mark.parametrize("l,shape", [(1, (600, 400)), (5, (600, 400)), (37, (600, 400)), (100, (600, 400)),
+                                     (5, (300, 30000)), (37, (200, 50000))])
+def test_onepass_rank_exact_products(l, shape):
     """Exact-rank products M N (float32): the one-sweep rank equals l, the
     oracle's rank and the two-sweep rank; the singular values of B agree with
-    the two-sweep run to the float32 level."""
+    the two-sweep run to the float32 level (rows of 30000 and 50000 entries:
+    the team sweep)."""
     from oracle import rank as orank
     device()
-    banner(f"one-pass rank of product l={l}")
-    A32 = inputs.product_matrix(600, 400, l, seed=5).astype(np.float32)
-    q = inputs.start_vector(600, seed=2)
+    m, n = shape
+    banner(f"one-pass rank of product l={l} {m}x{n}")
+    A32 = inputs.product_matrix(m, n, l, seed=5).astype(np.float32)
+    q = inputs.start_vector(m, seed=2)
     ref = orank.numerical_rank(A32.astype(np.float64), 1e-5, q)
     rank, rank_s, sig, status, stats = gkb.gkb_numerical_rank(to_dev(A32), 1e-5, q1=to_dev(q), one_pass=True)
     rank2, _, sig2, _, _ = gkb.gkb_numerical_rank(to_dev(A32), 1e-5, q1=to_dev(q))
     print(f"l={l} rank {rank} sturm {rank_s} steps {sig.size} (two-sweep {sig2.size}, oracle {ref['steps']}) "
           f"recomputed {stats['refreshes']}", flush=True)
+    assert stats["one_pass_used"] == 1
     assert rank == l and rank_s == l and rank2 == l and ref["rank"] == l
     top = min(l, sig.size, sig2.size)
     assert np.max(np.abs(sig[:top] - sig2[:top])) <= 8 * np.sqrt(l + 1) * U32 * sig2[0]
@@ -190,14 +194,14 @@ def test_onepass_deterministic():
 
 def test_onepass_falls_back_to_two_products():
     """Where the one-sweep step is not available (n not a multiple of 4, a
-    float64 A, rows longer than the sweep holds) a one_pass request runs the
-    two-product step: bitwise the same results as without the request, and
+    float64 A, rows longer than the team sweep takes) a one_pass request runs
+    the two-product step: bitwise the same results as without the request, and
     stats say which step ran."""
     device()
     banner("one-pass fallback to the two-product step")
     rng = np.random.default_rng(0)
     cases = [rng.standard_normal((50, 30)).astype(np.float32), rng.standard_normal((50, 32)),
-             rng.standard_normal((40, 24580)).astype(np.float32)]
+             rng.standard_normal((40, 262148)).astype(np.float32)]
     for A in cases:
         Ad = to_dev(A)
         q = to_dev(rng.standard_normal(A.shape[0]))
@@ -211,6 +215,10 @@ def test_onepass_falls_back_to_two_products():
         assert ra[0] == rb[0] and np.array_equal(ra[2], rb[2]) and ra[4]["one_pass_used"] == 0
     A = rng.standard_normal((64, 48)).astype(np.float32)
     assert gkb.gkb_partial_svd(to_dev(A), 2, 6, 1e-6, 2, one_pass=True)[4]["one_pass_used"] == 1
+    # rows longer than one workgroup holds: the team sweep, for both entry points
+    A = to_dev(rng.standard_normal((64, 30000)).astype(np.float32))
+    assert gkb.gkb_partial_svd(A, 2, 6, 1e-6, 2, one_pass=True)[4]["one_pass_used"] == 1
+    assert gkb.gkb_numerical_rank(A, 1e-3, one_pass=True)[4]["one_pass_used"] == 1
 
 
 @pytest.mark.parametrize("check_every", [0, 10])
@@ -268,19 +276,59 @@ def test_c2_fullsize_onepass_against_stored_oracle(check_every):
     assert np.all(du <= vt) and np.all(dv <= vt)
 
 
-@pytest.mark.parametrize("shape", [(2000, 30000), (600, 80000)])
-def test_onepass_request_on_rows_wider_than_the_sweep(shape):
-    """Rows of 30000 and 80000 entries are wider than the sweep holds (24576):
-    the one_pass request runs the two-product step (stats say so), with the
-    float32 tolerance against the float64 oracle on the exact upcast."""
+@pytest.mark.parametrize("shape", [(2000, 30000), (600, 80000), (257, 24580)])
+def test_onepass_on_rows_longer_than_one_workgroup_holds(shape):
+    """Rows of 24580, 30000 and 80000 entries are longer than one workgroup's
+    registers hold (24576): the one-sweep step runs on teams of workgroups
+    (4, 4 and 10 members with slices of at most 8192 columns), with the same
+    tolerance against the float64 oracle on the exact upcast; the product
+    count equals the two-product run's, and a second solve is bitwise equal
+    (the team exchange keeps a fixed order)."""
     device()
     m, n = shape
-    banner(f"one_pass request on {m}x{n} f32 (wider than the sweep)")
+    banner(f"one-pass team sweep {m}x{n} f32")
     A32, s, _, _ = inputs.lowrank_noise(m, n, 100, 0.9, 1e-6, seed=m + n, dtype=np.float32)
     q = inputs.start_vector(m, seed=3)
     ref = gk.partial_svd(A32.astype(np.float64), 6, 24, 1e-6, 20, q, eps_break=1e-6)
     sigma, U, V, status, stats = run(A32, 6, 24, 1e-6, 20, q, one_pass=True)
     print("stats", stats, flush=True)
-    assert stats["one_pass_used"] == 0
+    assert stats["one_pass_used"] == 1
     assert status == ref["status"] == 0
     _check_against(ref, sigma, U, V, 24)
+    two = run(A32, 6, 24, 1e-6, 20, q)
+    assert two[4]["one_pass_used"] == 0
+    assert stats["matvecs"] - stats["refreshes"] == two[4]["matvecs"] or stats["restarts"] != two[4]["restarts"]
+    again = run(A32, 6, 24, 1e-6, 20, q, one_pass=True)
+    assert np.array_equal(again[0], sigma) and np.array_equal(again[1], U) and np.array_equal(again[2], V)
+
+
+def test_onepass_team_sweep_with_checks_and_restarts():
+    """The team sweep through in-cycle checks and a thick restart (k = 2 r),
+    against the oracle with the same schedule."""
+    device()
+    m, n = 1500, 40000
+    banner(f"one-pass team sweep {m}x{n} f32, checks every 4, restarts")
+    A32, s, _, _ = inputs.lowrank_noise(m, n, 60, 0.9, 1e-6, seed=11, dtype=np.float32)
+    q = inputs.start_vector(m, seed=5)
+    ref = gk.partial_svd(A32.astype(np.float64), 8, 16, 1e-6, 40, q, eps_break=1e-6, check_every=4)
+    sigma, U, V, status, stats = run(A32, 8, 16, 1e-6, 40, q, one_pass=True, check_every=4)
+    print("stats", stats, "oracle restarts", ref["restarts"], flush=True)
+    assert stats["one_pass_used"] == 1 and stats["restarts"] >= 1
+    assert status == ref["status"] == 0
+    assert abs(stats["restarts"] - ref["restarts"]) <= 1
+    _check_against(ref, sigma, U, V, 16)
+
+
+def test_onepass_request_past_the_team_limit():
+    """Rows longer than 262144 entries (32 members of 8192 columns) have no
+    team form: the request runs the two-product step, against the oracle."""
+    device()
+    m, n = 64, 262148
+    banner(f"one_pass request on {m}x{n} f32 (past the team limit)")
+    A32, s, _, _ = inputs.lowrank_noise(m, n, 30, 0.8, 1e-6, seed=4, dtype=np.float32)
+    q = inputs.start_vector(m, seed=6)
+    ref = gk.partial_svd(A32.astype(np.float64), 4, 16, 1e-6, 20, q, eps_break=1e-6)
+    sigma, U, V, status, stats = run(A32, 4, 16, 1e-6, 20, q, one_pass=True)
+    assert stats["one_pass_used"] == 0
+    assert status == ref["status"] == 0
+    _check_against(ref, sigma, U, V, 16)
