@@ -497,6 +497,97 @@ def f64_leg(gkb, torch, Ad32, qd, stream, reps=3):
     return out
 
 
+WIDE_M, WIDE_N, WIDE_SEED = 50000, 40000, 5
+
+
+def wide_matrix(torch, dev):
+    """The 50000 x 40000 float32 low-rank(200, 0.95^i) + noise(1e-6) matrix,
+    formed on the device (U, V from QR of seeded Gaussian blocks); returns it
+    and the generator (for the vectors drawn after it)."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(WIDE_SEED)
+    Uq, _ = torch.linalg.qr(torch.randn(WIDE_M, RANK, generator=g, device=dev, dtype=torch.float64))
+    Vq, _ = torch.linalg.qr(torch.randn(WIDE_N, RANK, generator=g, device=dev, dtype=torch.float64))
+    s = DECAY ** torch.arange(RANK, device=dev, dtype=torch.float64)
+    Ad = ((Uq * s) @ Vq.T).float()
+    del Uq, Vq
+    Ad += NOISE * torch.randn(WIDE_M, WIDE_N, generator=g, device=dev, dtype=torch.float32)
+    torch.cuda.synchronize()
+    return Ad, g
+
+
+def wide_kernels_only(gkb, torch, dev, stream, reps):
+    """The team sweep on the 50000 x 40000 float32 matrix alone (reps
+    launches), the two products on it, and a plain 1 GiB device copy (3
+    launches) whose counter readings calibrate the traffic figures."""
+    Ad, g = wide_matrix(torch, dev)
+    m, n = WIDE_M, WIDE_N
+    p = torch.randn(n, generator=g, device=dev, dtype=torch.float32)
+    xm = torch.randn(m, generator=g, device=dev, dtype=torch.float32)
+    w = torch.empty(m, dtype=torch.float64, device=dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    fws = torch.empty(gkb.lib().gkb_matvec_fused_workspace_size(gkb.C.byref(gkb.make_matrix(Ad))),
+                      dtype=torch.uint8, device=dev)
+    mws = torch.empty(gkb.gkb_matvec_workspace_size(Ad), dtype=torch.uint8, device=dev)
+    ms_f = time_kernel(lambda: gkb.gkb_matvec_fused(Ad, p, w, y, workspace=fws, stream=stream), reps, stream)
+    ms_n = time_kernel(lambda: gkb.gkb_matvec(Ad, p, 0, y=w, stream=stream), reps, stream)
+    ms_t = time_kernel(lambda: gkb.gkb_matvec(Ad, xm, 1, y=y, workspace=mws, stream=stream), reps, stream)
+    src = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    b_f = m * n * 4 + n * 4 + m * 8 + n * 8
+    print(json.dumps({"kernels_only": True, "dtype": "f32", "shape": [m, n], "team_sweep_ms": ms_f,
+                      "team_sweep_GBps": b_f / (ms_f * 1e-3) / 1e9, "gemv_n_ms": ms_n, "gemv_t_ms": ms_t,
+                      "gemv_n_GBps": (m * n * 4 + n * 4 + m * 8) / (ms_n * 1e-3) / 1e9,
+                      "gemv_t_GBps": (m * n * 4 + m * 4 + n * 8) / (ms_t * 1e-3) / 1e9, "reps": reps,
+                      "copy_bytes": 2 ** 30}), flush=True)
+
+
+def wide_leg(gkb, torch, qd, stream, reps=3):
+    """A 50000 x 40000 float32 matrix (8.0 GB; rows longer than one workgroup
+    of the sweep holds): low-rank(200, 0.95^i) + noise(1e-6), formed on the
+    device from a seeded generator (U, V orthonormal from QR of Gaussian
+    blocks), the headline's solve settings.  The one-sweep solve (team sweep)
+    against the two-product solve of the same matrix: time, products, and the
+    largest relative difference of their singular values; the team sweep's
+    own rate."""
+    dev = qd.device
+    m, n = WIDE_M, WIDE_N
+    Ad, g = wide_matrix(torch, dev)
+    p = torch.randn(n, generator=g, device=dev, dtype=torch.float32)
+    w = torch.empty(m, dtype=torch.float64, device=dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    fws = torch.empty(gkb.lib().gkb_matvec_fused_workspace_size(gkb.C.byref(gkb.make_matrix(Ad))),
+                      dtype=torch.uint8, device=dev)
+    ms_sweep = time_kernel(lambda: gkb.gkb_matvec_fused(Ad, p, w, y, workspace=fws, stream=stream), 20, stream)
+    b_sweep = m * n * 4 + n * 4 + m * 8 + n * 8
+    ws = torch.empty(max(gkb.gkb_workspace_size(Ad, R, K), gkb.gkb_workspace_size(Ad, R, K, one_pass=True)),
+                     dtype=torch.uint8, device=dev)
+    out = {"workload": "low-rank(200, 0.95^i)+noise(1e-6) 50000x40000 f32 (device generator, seed 5); "
+                       "top 50, k 120, tol 1e-6, checks every 10",
+           "team_sweep_ms": ms_sweep, "team_sweep_GBps": b_sweep / (ms_sweep * 1e-3) / 1e9,
+           "team_sweep_frac": b_sweep / (ms_sweep * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    q = torch.ones(m, dtype=torch.float64, device=dev) + 0.5 * torch.randn(m, generator=g, device=dev,
+                                                                            dtype=torch.float64)
+    sig = {}
+    for name, one in (("one_sweep", True), ("two_product", False)):
+        solve = lambda: gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=q, workspace=ws, stream=stream,
+                                            check_every=CHECK_EVERY, one_pass=one)
+        ms, (sg, Ut, Vt, status, st) = wall_times(solve, 1, reps, torch)
+        sig[name] = sg
+        out[name] = {"solve_ms_mean": float(np.mean(ms)), "solve_ms_median": float(np.median(ms)),
+                     "triplets_per_s": st["nconv"] / (np.mean(ms) / 1000.0), "status": status,
+                     "matvecs": st["matvecs"], "one_pass_used": st["one_pass_used"], "restarts": st["restarts"]}
+        del Ut, Vt
+    out["sigma_rel_diff_one_vs_two_max"] = float(np.max(np.abs(sig["one_sweep"] - sig["two_product"]) /
+                                                        sig["two_product"][0]))
+    del Ad, ws, fws
+    torch.cuda.empty_cache()
+    return out
+
+
 SPARSE_M, SPARSE_N, SPARSE_NNZ, SPARSE_SEED, SPARSE_QSEED = 1000000, 200000, 50000000, 7, 8
 SPARSE_R, SPARSE_K, SPARSE_EVERY = 20, 60, 5
 
@@ -645,7 +736,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=CHECK_EVERY)
     ap.add_argument("--two-pass", action="store_true",
                     help="time the two-product step (A read twice per step) instead of the one-sweep step")
-    ap.add_argument("--legs", default="c1,f64,bf16,rank,batched,learned,sparse,rsgd",
+    ap.add_argument("--legs", default="c1,f64,wide,bf16,rank,batched,learned,sparse,rsgd",
                     help="extra legs after the main timing (comma list; empty for none)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="time only the two matvec kernels and a 1 GiB copy (for counter runs)")
@@ -655,6 +746,8 @@ def main():
                     help="with --kernels-only: the float32 matrix in rows of n + 1 elements")
     ap.add_argument("--sparse", action="store_true",
                     help="with --kernels-only: the sparse products (column panels and CSR) instead")
+    ap.add_argument("--wide", action="store_true",
+                    help="with --kernels-only: the team sweep and the two products on the 50000 x 40000 matrix")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Golub-Kahan path runs on a single MI355X; "
@@ -667,6 +760,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.kernels_only and args.sparse:
         sparse_kernels_only(gkb, inputs, torch, dev, torch.cuda.current_stream(), args.kernel_reps)
+        return
+    if args.kernels_only and args.wide:
+        wide_kernels_only(gkb, torch, dev, torch.cuda.current_stream(), args.kernel_reps)
         return
     log("generating 50000x20000 float32 low-rank-plus-noise matrix")
     t0 = time.time()
@@ -783,6 +879,8 @@ def main():
             legs["c1_f64"] = c1_leg(gkb, inputs, torch, dev, stream, oracle=not args.no_cpu_baseline)
         elif leg == "f64":
             legs["f64_large"] = f64_leg(gkb, torch, Ad, qd, stream)
+        elif leg == "wide":
+            legs["wide_f32"] = wide_leg(gkb, torch, qd, stream)
         log(f"leg {leg} done: {json.dumps(legs)[-300:]}")
 
     cpu = None
