@@ -463,7 +463,8 @@ def f64_leg(gkb, torch, Ad32, qd, stream, reps=3):
     """The 50000 x 20000 matrix in float64 (the exact upcast of the float32
     matrix, 8.0 GB): the two products' HBM rate and the float64 partial SVD
     (two-product step, float64 bases) against the stored float64 oracle run on
-    the same matrix."""
+    the same matrix; beside it the one-sweep solve (team sweep on float64
+    rows) and its largest singular-value difference from the two-product one."""
     Ad = Ad32.double()
     torch.cuda.synchronize()
     xn = torch.randn(N, dtype=torch.float64, device=Ad.device)
@@ -475,7 +476,12 @@ def f64_leg(gkb, torch, Ad32, qd, stream, reps=3):
     ms_t = time_kernel(lambda: gkb.gkb_matvec(Ad, xm, 1, y=ym, workspace=mws, stream=stream), 20, stream)
     b_n = M * N * 8 + N * 8 + M * 8
     b_t = M * N * 8 + M * 8 + N * 8
-    ws = torch.empty(gkb.gkb_workspace_size(Ad, R, K), dtype=torch.uint8, device=Ad.device)
+    ws = torch.empty(max(gkb.gkb_workspace_size(Ad, R, K), gkb.gkb_workspace_size(Ad, R, K, one_pass=True)),
+                     dtype=torch.uint8, device=Ad.device)
+    solve1 = lambda: gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
+                                         check_every=CHECK_EVERY, one_pass=True)
+    ms1, (sig1, Ut1, Vt1, status1, st1) = wall_times(solve1, 1, reps, torch)
+    del Ut1, Vt1
     solve = lambda: gkb.gkb_partial_svd(Ad, R, K, TOL, RESTARTS, q1=qd, workspace=ws, stream=stream,
                                         check_every=CHECK_EVERY)
     ms, (sig, Ut, Vt, status, st) = wall_times(solve, 1, reps, torch)
@@ -485,7 +491,12 @@ def f64_leg(gkb, torch, Ad32, qd, stream, reps=3):
            "gemv_t_ms": ms_t, "gemv_t_GBps": b_t / (ms_t * 1e-3) / 1e9, "gemv_t_frac": b_t / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "solve_ms_mean": float(np.mean(ms)), "solve_ms_median": float(np.median(ms)),
            "triplets_per_s": st["nconv"] / (np.mean(ms) / 1000.0), "status": status, "matvecs": st["matvecs"],
-           "checks": st["checks"], "reps": reps}
+           "checks": st["checks"], "reps": reps,
+           "one_sweep": {"solve_ms_mean": float(np.mean(ms1)), "solve_ms_median": float(np.median(ms1)),
+                         "triplets_per_s": st1["nconv"] / (np.mean(ms1) / 1000.0), "status": status1,
+                         "matvecs": st1["matvecs"], "refreshes": st1["refreshes"],
+                         "one_pass_used": st1["one_pass_used"],
+                         "sigma_rel_diff_vs_two_product_max": float(np.max(np.abs(sig1 - sig)) / sig[0])}}
     acc = headline_accuracy(sig, Ut, Vt, CHECK_EVERY)
     if acc:
         out["sigma_rel_err_vs_f64_oracle_max"] = acc["sigma_rel_err_max"]

@@ -101,9 +101,11 @@ typedef struct {
                        /* paper's Algorithm 2)                                 */
   int one_pass;        /* 1: read A once per step instead of twice (GKB_F32   */
                        /* or GKB_BF16 with n, lda multiples of 4 or 8,         */
-                       /* n <= 262144, A 16-byte aligned; rows longer than     */
-                       /* 24576 are split over teams of workgroups that must   */
-                       /* all be resident, see GKB_ERR_TIMEOUT; for any other  */
+                       /* n <= 262144, or GKB_F64 with n, lda even,            */
+                       /* n <= 131072; A 16-byte aligned; float64 rows and     */
+                       /* rows longer than 24576 are split over teams of       */
+                       /* workgroups that must all be resident, see            */
+                       /* GKB_ERR_TIMEOUT; for any other                       */
                        /* A, including sparse A, the two-product step runs and */
                        /* stats.one_pass_used is 0).  One sweep forms          */
                        /* A p and A^T A p in float64; A^T q_{i+1} then follows */
@@ -111,7 +113,12 @@ typedef struct {
                        /* c the recurrence and Gram-Schmidt coefficients and   */
                        /* A^T Q kept in float64 (n x (k + 1) more workspace).  */
                        /* Bases are float64 so that A^T Q matches Q exactly;   */
-                       /* U, V are still float32.  Same statuses and stats     */
+                       /* U, V keep A's class (float32, or float64 for         */
+                       /* GKB_F64).  A recovered A^T q column is recomputed    */
+                       /* directly once its error bound passes 1e-10 sigma_1,  */
+                       /* so with GKB_F64 the results carry errors up to about */
+                       /* sqrt(k) 1e-10 sigma_1 (the two-product step: the     */
+                       /* float64 rounding level).  Same statuses and stats    */
                        /* (matvecs counts products, two per sweep).            */
                        /* gkb_partial_svd and gkb_numerical_rank.              */
   int phase_timing;    /* 1: time the device phases with HIP events recorded   */

@@ -10,46 +10,50 @@ namespace gkb {
 
 constexpr int64_t FUSED_NMAX = 24576;    // longest row of the single-workgroup sweep (768 threads x 8 groups of 4 floats)
 constexpr int64_t FUSED_TEAM_NMAX = 262144;   // longest row of the team sweep (32 members x 8192 columns)
+constexpr int64_t FUSED_TEAM_NMAX_F64 = 131072;   // the same for float64 rows (32 members x 4096 columns)
 // a recovered A^T q column is recomputed directly once its error bound
 // exceeds this fraction of the largest coefficient seen
 constexpr double ONEPASS_TAU = 1e-10;
 
-// true if A (m x n, lda; dtype 1 = float32, 2 = bfloat16) can take the fused
-// sweep: n and lda multiples of the 16-byte group (4 or 8 elements),
-// n <= FUSED_NMAX (one workgroup per row range) or, for longer rows, a team
-// shape exists (n <= FUSED_TEAM_NMAX and at most one member per compute
-// unit), A 16-byte aligned
+// true if A (m x n, lda; dtype 0 = float64, 1 = float32, 2 = bfloat16) can
+// take the fused sweep: n and lda multiples of the 16-byte group (2, 4 or 8
+// elements), A 16-byte aligned, and either float32 or bfloat16 rows of at
+// most FUSED_NMAX (one workgroup per row range) or a team shape (rows longer
+// than that, or float64 rows: n <= FUSED_TEAM_NMAX, FUSED_TEAM_NMAX_F64 for
+// float64, and at most one member per compute unit)
 bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A, int dtype);
-// number of partial-sum rows the sweep writes (workgroups, or teams for
-// rows longer than FUSED_NMAX)
-int fused_blocks(int64_t m, int64_t n);
+// whether the sweep of this row length and type is the team form
+inline bool team_form(int64_t n, int dtype) { return dtype == 0 || n > FUSED_NMAX; }
+// number of partial-sum rows the sweep writes (workgroups, or teams)
+int fused_blocks(int64_t m, int64_t n, int dtype);
 
-// The team sweep (rows longer than FUSED_NMAX): C members per team, each
-// owning a near-equal slice of at most 8192 columns; teams of rpt rows
-// (the last may be shorter, none empty), nsteps steps of rows per team;
-// C = 0 if the shape has no team form.
+// The team sweep: C members per team, each owning a near-equal slice of at
+// most 8192 columns (4096 for float64: 32 KB of a row either way); teams of
+// rpt rows (the last may be shorter, none empty), nsteps steps of rows per
+// team; C = 0 if the shape has no team form.
 struct TeamShape {
   int C, nteams, rpt, nsteps;
 };
-TeamShape team_shape(int64_t m, int64_t n);
+TeamShape team_shape(int64_t m, int64_t n, int dtype);
 // device bytes of the team sweep's mailbox and counters (0 if no team form);
 // the sweep's `team` argument points to this many bytes, 256-byte aligned,
 // zeroed by launch_team_reset before the first sweep and then left to the
 // sweeps (each launch leaves it ready for the next)
-size_t team_bytes(int64_t m, int64_t n);
-hipError_t launch_team_reset(void* team, int64_t m, int64_t n, hipStream_t st);
+size_t team_bytes(int64_t m, int64_t n, int dtype);
+hipError_t launch_team_reset(void* team, int64_t m, int64_t n, int dtype, hipStream_t st);
 
-// A float32 (dtype 1) or bfloat16 (dtype 2, widened exactly to float32).
-// With win == nullptr: w = A p (float64, m) and the partials of y = A^T w;
-// p is read as float32 (a float64 p is rounded to float32 once, so w and y
-// are the exact products with that float32 vector).  With win != nullptr: the
+// A float32 (dtype 1), bfloat16 (dtype 2, widened exactly to float32) or
+// float64 (dtype 0, team sweep only).  With win == nullptr: w = A p (float64,
+// m) and the partials of y = A^T w; for float32 and bfloat16 A, p is read as
+// float32 (a float64 p is rounded to float32 once, so w and y are the exact
+// products with that float32 vector); for float64 A, p is read as it is.  With win != nullptr: the
 // partials of y = A^T win (p, w unused).  All sums in float64; ypart holds
-// fused_blocks(m, n) x ldy doubles (ldy >= n); y (n doubles) gets their sum in
+// fused_blocks(m, n, dtype) x ldy doubles (ldy >= n); y (n doubles) gets their sum in
 // a fixed order unless y is null.  Skipped when flag[0] != 0, or when run_if
 // is given and run_if[0] == 0.  With qprev given, w = A p - coef[0] qprev
-// (the recurrence term of eq. (2.2)) while y stays A^T (A p).  Rows longer
-// than FUSED_NMAX take the team sweep, which needs `team` (team_bytes(m, n)
-// bytes, see launch_team_reset) and may set flag[0] = 4 when a member waited
+// (the recurrence term of eq. (2.2)) while y stays A^T (A p).  The team form
+// (team_form) needs `team` (team_bytes(m, n, dtype) bytes, see
+// launch_team_reset) and may set flag[0] = 4 when a member waited
 // too long for the others (its results are then NaN); flag must be writable
 // device memory or null.
 template <typename TP>

@@ -493,7 +493,7 @@ hipError_t launch_v(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(FUSED_NMAX * 4));
     if (attr != hipSuccess) return attr;
   }
-  const int nb = fused_blocks(m, n);
+  const int nb = fused_blocks(m, n, 1);
   const int64_t rpb = (m + nb - 1) / nb;
   hipLaunchKernelGGL((k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>), dim3(nb), dim3(T), GIVEN_W ? 0 : (size_t)n * 4, st, A,
                      lda, m, n, p, win, rpb, w, ypart, ldy, flag, run_if, qprev, coef);
@@ -535,7 +535,7 @@ constexpr int PIPE_LDS_MAX = 160 * 1024 - 4096;   // dynamic LDS; the rest cover
 
 template <int T, int U, int R, int NB, typename TA>
 size_t pipe_lds(int64_t m, int64_t n, bool given_w) {
-  const int nb = fused_blocks(m, n);
+  const int nb = fused_blocks(m, n, 1);
   const int64_t rpb = (m + nb - 1) / nb;
   return given_w ? 0 : (size_t)U * T * Elems<TA>::VN * 4 + (size_t)rpb * 8;
 }
@@ -560,7 +560,7 @@ hipError_t launch_p(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p,
                             hipFuncAttributeMaxDynamicSharedMemorySize, PIPE_LDS_MAX);
     if (attr != hipSuccess) return attr;
   }
-  const int nb = fused_blocks(m, n);
+  const int nb = fused_blocks(m, n, 1);
   const int rpb = (int)((m + nb - 1) / nb);
   const size_t lds = pipe_lds<T, U, R, NB, TA>(m, n, GIVEN_W);
   hipLaunchKernelGGL((k_gemv_fused_pipe<T, U, R, NB, TA, TP, GIVEN_W>), dim3(nb), dim3(T), lds, st, A, lda, (int)m,
@@ -686,14 +686,17 @@ __global__ __launch_bounds__(256) void k_narrow(const double* __restrict__ src, 
 }  // namespace
 
 bool fused_ok(int64_t m, int64_t n, int64_t lda, const void* A, int dtype) {
-  const int64_t vn = dtype == 2 ? 8 : 4;
-  return (dtype == 1 || dtype == 2) && m >= 1 && m < (int64_t(1) << 30) && n >= vn &&
-         (n <= FUSED_NMAX || (n <= FUSED_TEAM_NMAX && team_shape(m, n).C > 0)) && n % vn == 0 && lda % vn == 0 &&
-         (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  if (dtype < 0 || dtype > 2) return false;
+  const int64_t vn = dtype == 2 ? 8 : (dtype == 1 ? 4 : 2);
+  if (m < 1 || m >= (int64_t(1) << 30) || n < vn || n % vn != 0 || lda % vn != 0 ||
+      (reinterpret_cast<uintptr_t>(A) & 15) != 0)
+    return false;
+  if (!team_form(n, dtype)) return true;
+  return n <= (dtype == 0 ? FUSED_TEAM_NMAX_F64 : FUSED_TEAM_NMAX) && team_shape(m, n, dtype).C > 0;
 }
 
-int fused_blocks(int64_t m, int64_t n) {
-  if (n > FUSED_NMAX) return std::max(1, team_shape(m, n).nteams);
+int fused_blocks(int64_t m, int64_t n, int dtype) {
+  if (team_form(n, dtype)) return std::max(1, team_shape(m, n, dtype).nteams);
   // bpc workgroups per compute unit, each an equal share of the rows
   return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)fused_shape(n).bpc * device_cus(), m));
 }
@@ -706,7 +709,7 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
   const FusedShape fs = fused_shape(n);
   hipError_t e;
   const bool gw = win != nullptr;
-  if (n > FUSED_NMAX) {
+  if (team_form(n, dtype)) {
     e = launch_gemv_fused_team<TP>(A, dtype, lda, m, n, p, win, w, ypart, ldy, flag, st, run_if, qprev, coef, team);
   } else
   // Shapes measured on MI355X (w = A p and A^T w, float64 p): the pipelined
@@ -765,7 +768,7 @@ hipError_t launch_gemv_fused(const void* A, int dtype, int64_t lda, int64_t m, i
 #undef GKB_FUSED
   }
   if (e != hipSuccess || y == nullptr) return e;
-  hipLaunchKernelGGL(k_fused_reduce, dim3(nblk(n, RCOLS)), dim3(256), 0, st, ypart, fused_blocks(m, n), ldy, n, y,
+  hipLaunchKernelGGL(k_fused_reduce, dim3(nblk(n, RCOLS)), dim3(256), 0, st, ypart, fused_blocks(m, n, dtype), ldy, n, y,
                      flag, run_if);
   return hipGetLastError();
 }

@@ -13,6 +13,7 @@ namespace gkb {
 namespace fdev {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -43,9 +44,14 @@ __device__ __forceinline__ double wsum_dpp(double v) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// A row is read as 16-byte groups: 4 float32 or 8 bfloat16 elements (the
-// latter widened exactly to float32).
+// A row is read as 16-byte groups: 4 float32, 8 bfloat16 (widened exactly
+// to float32) or 2 float64 elements.
 template <typename TA> struct Elems;
+template <> struct Elems<double> {
+  static constexpr int VN = 2;
+  static constexpr bool F32DOT = false;
+  __device__ __forceinline__ static double at(const f4& v, int e) { return __builtin_bit_cast(d2, v)[e]; }
+};
 template <> struct Elems<float> {
   static constexpr int VN = 4;
   static constexpr bool F32DOT = false;   // row dot products in float64

@@ -4,8 +4,8 @@
 //
 // The single-workgroup sweep keeps its float64 partial of A^T w in registers,
 // which bounds the row length.  Here the 16-byte column groups are cut into C
-// near-equal slices of at most TM_T TM_U groups (8192 columns), and C
-// workgroups -- a team -- share a range of rows.  Member c streams its slice
+// near-equal slices of at most 8192 columns (4096 for float64 rows, which
+// only this form takes), and C workgroups -- a team -- share a range of rows.  Member c streams its slice
 // of each row, forms the slice's part of the row's dot product with p
 // (reduced across the workgroup in a fixed order) and publishes it; once all
 // C parts of a row are in, every member adds them in member order (so every
@@ -47,6 +47,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "device_common.h"
 #include "fused.h"
@@ -68,11 +69,13 @@ constexpr int TM_R = 1;            // rows per step
 constexpr int TM_NB = 3;           // steps of rows in flight (two loading ahead)
 constexpr int TM_D = 5;            // steps between a step's parts and their use
 constexpr int TM_CMAX = 32;        // members per team (C R parts per step, one per lane)
-constexpr int TM_SLICE = 8192;     // columns per member at most
+constexpr int TM_SLICE = 8192;     // columns per member at most (4096 for float64: 32 KB of a row)
 constexpr long TM_SPIN_LIMIT = 1L << 20;
 static_assert(TM_CMAX * TM_R <= 64, "a step's parts are read one per lane");
 
-template <typename TA> constexpr int tm_u() { return TM_SLICE / (TM_T * Elems<TA>::VN); }
+template <typename TA> constexpr int tm_slice() { return sizeof(TA) == 8 ? TM_SLICE / 2 : TM_SLICE; }
+template <typename TA> constexpr int tm_u() { return tm_slice<TA>() / (TM_T * Elems<TA>::VN); }
+template <typename TA> constexpr int tm_dtype() { return sizeof(TA) == 8 ? 0 : (sizeof(TA) == 2 ? 2 : 1); }
 
 __device__ __forceinline__ uint64_t ld_dev(const uint64_t* p) {
   return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -121,11 +124,13 @@ __global__ __launch_bounds__(T) void k_gemv_fused_team(const TA* __restrict__ A,
   __shared__ double red[2][R][NWV];                              // [parity][row][wave]
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t tag = GIVEN_W ? 0u : __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-  // the slice of p as float32, zero padded to U T groups (the dot products
-  // read it from LDS)
-  extern __shared__ float pl[];
+  // the slice of p, zero padded to U T groups (the dot products read it from
+  // LDS): float32 for float32 and bfloat16 rows, as it is for float64 rows
+  using PL = typename std::conditional<sizeof(TA) == 8, double, float>::type;
+  extern __shared__ __align__(16) unsigned char pl_raw[];
+  PL* pl = reinterpret_cast<PL*>(pl_raw);
   if constexpr (!GIVEN_W) {
-    for (int j = tid; j < U * T * VN; j += T) pl[j] = j < sg * VN ? (float)p[(int64_t)g0 * VN + j] : 0.f;
+    for (int j = tid; j < U * T * VN; j += T) pl[j] = j < sg * VN ? (PL)p[(int64_t)g0 * VN + j] : (PL)0;
     __syncthreads();
   }
   const int r0 = team * rpt;
@@ -199,6 +204,17 @@ __global__ __launch_bounds__(T) void k_gemv_fused_team(const TA* __restrict__ A,
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) d[r] = (double)df[r];
+    } else if constexpr (sizeof(TA) == 8) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r] = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const fdev::d2 pv = reinterpret_cast<const fdev::d2*>(pl)[tid + u * T];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+          for (int r = 0; r < R; ++r) d[r] += Elems<TA>::at(rows[r][u], e) * pv[e];
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < R; ++r) d[r] = 0.0;
@@ -358,11 +374,11 @@ hipError_t launch_team_t(const TA* A, int64_t lda, int64_t m, int64_t n, const T
                          double* ypart, int64_t ldy, const int* flag, const int* run_if, const double* qprev,
                          const double* coef, void* team, hipStream_t st) {
   constexpr int U = tm_u<TA>();
-  const TeamShape ts = team_shape(m, n);
+  const TeamShape ts = team_shape(m, n, tm_dtype<TA>());
   if (ts.C == 0 || team == nullptr) return hipErrorInvalidValue;
   uint32_t* ctr = reinterpret_cast<uint32_t*>(team);
   uint64_t* mbox = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(team) + 256);
-  const size_t lds = GIVEN_W ? 0 : (size_t)U * TM_T * Elems<TA>::VN * sizeof(float);
+  const size_t lds = GIVEN_W ? 0 : (size_t)U * TM_T * Elems<TA>::VN * (sizeof(TA) == 8 ? 8 : 4);
   hipLaunchKernelGGL((k_gemv_fused_team<TM_T, U, TM_R, TM_NB, TM_D, TA, TP, GIVEN_W>), dim3(ts.nteams * ts.C),
                      dim3(TM_T), lds, st, A, lda, (int)m, n, p, win, ts.C, ts.rpt, ts.nsteps, w, ypart, ldy,
                      const_cast<int*>(flag), run_if, qprev, coef, mbox, ctr);
@@ -371,11 +387,12 @@ hipError_t launch_team_t(const TA* A, int64_t lda, int64_t m, int64_t n, const T
 
 }  // namespace
 
-TeamShape team_shape(int64_t m, int64_t n) {
-  // C = ceil(n / TM_SLICE) members: near-equal slices of the 16-byte groups
-  // then hold at most TM_SLICE columns for either element size
+TeamShape team_shape(int64_t m, int64_t n, int dtype) {
+  // C = ceil(n / slice) members: near-equal slices of the 16-byte groups then
+  // hold at most `slice` columns
   TeamShape ts{0, 0, 0, 0};
-  const int64_t C = (n + TM_SLICE - 1) / TM_SLICE;
+  const int64_t slice = dtype == 0 ? TM_SLICE / 2 : TM_SLICE;
+  const int64_t C = (n + slice - 1) / slice;
   const int slots = device_cus();   // one member per compute unit
   if (m < 1 || n < 1 || C > TM_CMAX || C > slots) return ts;
   const int64_t want = std::max<int64_t>(1, std::min<int64_t>(slots / C, (m + TM_R - 1) / TM_R));
@@ -387,14 +404,14 @@ TeamShape team_shape(int64_t m, int64_t n) {
   return ts;
 }
 
-size_t team_bytes(int64_t m, int64_t n) {
-  const TeamShape ts = team_shape(m, n);
+size_t team_bytes(int64_t m, int64_t n, int dtype) {
+  const TeamShape ts = team_shape(m, n, dtype);
   if (ts.C == 0) return 0;
   return 256 + (size_t)ts.nteams * ts.nsteps * ts.C * TM_R * 2 * sizeof(uint64_t);
 }
 
-hipError_t launch_team_reset(void* team, int64_t m, int64_t n, hipStream_t st) {
-  const size_t bytes = team_bytes(m, n);
+hipError_t launch_team_reset(void* team, int64_t m, int64_t n, int dtype, hipStream_t st) {
+  const size_t bytes = team_bytes(m, n, dtype);
   if (bytes == 0 || team == nullptr) return hipErrorInvalidValue;
   const int64_t words = (int64_t)(bytes / 8);
   const unsigned blocks = (unsigned)std::min<int64_t>((words + 255) / 256, 1024);
@@ -407,6 +424,14 @@ hipError_t launch_gemv_fused_team(const void* A, int dtype, int64_t lda, int64_t
                                   const double* win, double* w, double* ypart, int64_t ldy, const int* flag,
                                   hipStream_t st, const int* run_if, const double* qprev, const double* coef,
                                   void* team) {
+  if (dtype == 0) {
+    const double* Ad = reinterpret_cast<const double*>(A);
+    return win != nullptr
+               ? launch_team_t<double, TP, true>(Ad, lda, m, n, p, win, w, ypart, ldy, flag, run_if, qprev, coef, team,
+                                                 st)
+               : launch_team_t<double, TP, false>(Ad, lda, m, n, p, win, w, ypart, ldy, flag, run_if, qprev, coef,
+                                                  team, st);
+  }
   if (dtype == 2) {
     const bf16* Ab = reinterpret_cast<const bf16*>(A);
     return win != nullptr

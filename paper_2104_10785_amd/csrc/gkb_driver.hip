@@ -117,15 +117,17 @@ Layout make_layout(int64_t m, int64_t n, gkb_dtype dt, int k, bool restart, bool
     L.GQ[0] = take((size_t)L.kcols * L.ldn * 8);
     L.GQ[1] = restart ? take((size_t)L.kcols * L.ldn * 8) : L.GQ[0];
     L.y = take((size_t)L.ldn * 8);
-    L.ypart = take((size_t)gkb::fused_blocks(m, n) * L.ldn * 8);
+    L.ypart = take((size_t)gkb::fused_blocks(m, n, (int)dt) * L.ldn * 8);
     L.csum = take((size_t)L.ldh * 8);
     L.err[0] = take((size_t)L.ldh * 8);
     L.err[1] = take((size_t)L.ldh * 8);
     L.refresh = take(4 * sizeof(int));
-    L.Uo = take((size_t)L.ldm * L.kcols * 8);
-    L.Vo = take((size_t)L.ldn * L.kcols * 8);
-    if (n > gkb::FUSED_NMAX) {
-      L.team_bytes = gkb::team_bytes(m, n);
+    if (dt != GKB_F64) {   // float64 A: the Ritz vectors go straight to U, V
+      L.Uo = take((size_t)L.ldm * L.kcols * 8);
+      L.Vo = take((size_t)L.ldn * L.kcols * 8);
+    }
+    if (gkb::team_form(n, (int)dt)) {
+      L.team_bytes = gkb::team_bytes(m, n, (int)dt);
       L.team = take(L.team_bytes);
     }
   }
@@ -145,10 +147,11 @@ gkb_status check_matrix(const gkb_matrix* A) {
   return GKB_OK;
 }
 
-// The one-sweep step runs on dense float32 or bfloat16 A whose rows the sweep
-// kernels take (n <= 24576 in one workgroup's registers, longer rows up to
-// 262144 by teams of workgroups; n and lda multiples of the 16-byte group, A
-// 16-byte aligned); elsewhere a one_pass request runs the two-product step.
+// The one-sweep step runs on dense A whose rows the sweep kernels take:
+// float32 or bfloat16 rows of n <= 24576 in one workgroup's registers, longer
+// ones up to 262144 by teams of workgroups, float64 rows up to 131072 by
+// teams; n and lda multiples of the 16-byte group, A 16-byte aligned;
+// elsewhere a one_pass request runs the two-product step.
 bool one_pass_available(const gkb_matrix* A) {
   return gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype);
 }
@@ -380,7 +383,7 @@ struct Solver {
       // z = A^T q_1 with float64 sums, kept as the first column of A^T Q
       if constexpr (std::is_same<TB, double>::value) {
         // the team sweep's mailbox starts each solve zeroed
-        if (team() != nullptr) GKB_HIP(gkb::launch_team_reset(team(), A.m, A.n, st));
+        if (team() != nullptr) GKB_HIP(gkb::launch_team_reset(team(), A.m, A.n, A.dtype, st));
         GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, nullptr, Qc(0), nullptr, z(), ypart(), L.ldn,
                                                flag(), st, nullptr, nullptr, nullptr, team()));
         GKB_HIP(gkb::launch_copy_vec<double>(z(), A.n, GQ(cur), st));
@@ -443,7 +446,7 @@ struct Solver {
   // direct sweep A^T q_qn instead (skipped on the device otherwise).
   gkb_status onepass_step(int pi, int qp, int nqc, int qn, bool use_rho) {
     if constexpr (std::is_same<TB, double>::value) {
-      const int nb = gkb::fused_blocks(A.m, A.n);
+      const int nb = gkb::fused_blocks(A.m, A.n, A.dtype);
       // w = A p - alpha q_qp in the sweep itself (after a restart, Q~ rho by an update)
       GKB_HIP(mark(PH_MATVEC));
       GKB_HIP(gkb::launch_gemv_fused<double>(fA(), A.dtype, A.lda, A.m, A.n, Pc(pi), nullptr, w(), nullptr, ypart(),
@@ -803,12 +806,14 @@ gkb_status run_segment(Solver<TB>& S, SegmentGraphs& G, int first, int j0, int j
   return GKB_OK;
 }
 
-template <typename TB, typename TO = TB>
+// ONEPASS: the one-sweep step (float64 bases; U, V float32 for float32 and
+// bfloat16 A, float64 for float64 A)
+template <typename TB, typename TO = TB, bool ONEPASS = !std::is_same<TB, TO>::value>
 gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int max_restarts,
                            const gkb_options& opt, void* workspace, double* sigma, TO* U, TO* V,
                            gkb_stats* stats, hipStream_t st, const gkb::SparseRef* sp = nullptr,
                            SegmentGraphs* graphs = nullptr) {
-  constexpr bool onepass = !std::is_same<TB, TO>::value;
+  constexpr bool onepass = ONEPASS;
   const double t0 = now_ms();
   double ms_host = 0.0;
   Solver<TB> S;
@@ -982,7 +987,7 @@ gkb_status run_partial_svd(const gkb_matrix* Am, int r, int k, double tol, int m
     to_colmajor<TB>(rz.Y, pr.np, rz.kk, r_eff, Yh);
     GKB_HIP(hipMemcpyAsync(S.Xs(), Xh.data(), Xh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
     GKB_HIP(hipMemcpyAsync(S.Ys(), Yh.data(), Yh.size() * sizeof(TB), hipMemcpyHostToDevice, st));
-    if constexpr (onepass) {
+    if constexpr (onepass && !std::is_same<TO, double>::value) {
       double* Vo = reinterpret_cast<double*>(S.ws + S.L.Vo);
       double* Uo = reinterpret_cast<double*>(S.ws + S.L.Uo);
       GKB_HIP(gkb::launch_gemm_tall<TB>(S.P(S.cur), S.L.ldn, Am->n, pr.np, S.Ys(), pr.np, r_eff, Vo, Am->n, st));
@@ -1123,6 +1128,10 @@ gkb_status validate_svd(const gkb_matrix* A, int r, int k, double tol, int max_r
 gkb_status dispatch_svd(const gkb_matrix* A, int r, int k, double tol, int max_restarts, const gkb_options& opt,
                         void* workspace, double* sigma, void* U, void* V, gkb_stats* stats, hipStream_t st,
                         SegmentGraphs* graphs) {
+  if (opt.one_pass && A->dtype == GKB_F64)
+    return run_partial_svd<double, double, true>(A, r, k, tol, max_restarts, opt, workspace, sigma,
+                                                 reinterpret_cast<double*>(U), reinterpret_cast<double*>(V), stats,
+                                                 st, nullptr, graphs);
   if (opt.one_pass)
     return run_partial_svd<double, float>(A, r, k, tol, max_restarts, opt, workspace, sigma,
                                           reinterpret_cast<float*>(U), reinterpret_cast<float*>(V), stats, st,
@@ -1411,10 +1420,11 @@ size_t gkb_matvec_workspace_size(const gkb_matrix* A) {
 }
 
 size_t gkb_matvec_fused_workspace_size(const gkb_matrix* A) {
-  if (check_matrix(A) != GKB_OK || !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype)) return 0;
+  if (check_matrix(A) != GKB_OK || A->dtype == GKB_F64 || !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
+    return 0;
   // partial sums, then the team sweep's mailbox for rows longer than FUSED_NMAX
-  return align256((size_t)gkb::fused_blocks(A->m, A->n) * round64(A->n) * 8) +
-         (A->n > gkb::FUSED_NMAX ? align256(gkb::team_bytes(A->m, A->n)) : 0);
+  return align256((size_t)gkb::fused_blocks(A->m, A->n, (int)A->dtype) * round64(A->n) * 8) +
+         (gkb::team_form(A->n, (int)A->dtype) ? align256(gkb::team_bytes(A->m, A->n, (int)A->dtype)) : 0);
 }
 
 gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, double* y, void* workspace,
@@ -1422,7 +1432,7 @@ gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, doub
   g_err.clear();
   gkb_status rc = check_matrix(A);
   if (rc != GKB_OK) return rc;
-  if (!gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
+  if (A->dtype == GKB_F64 || !gkb::fused_ok(A->m, A->n, A->lda, A->data, (int)A->dtype))
     return fail(GKB_ERR_INVALID, "the fused sweep needs a float32 (bfloat16) A with lda and n multiples of 4 (8), "
                                  "n <= 262144, 16-byte aligned");
   if (!p || !w || !y) return fail(GKB_ERR_INVALID, "p, w and y must be non-NULL");
@@ -1430,9 +1440,10 @@ gkb_status gkb_matvec_fused(const gkb_matrix* A, const float* p, double* w, doub
   if (rc != GKB_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   void* team = nullptr;
-  if (A->n > gkb::FUSED_NMAX) {
-    team = reinterpret_cast<char*>(workspace) + align256((size_t)gkb::fused_blocks(A->m, A->n) * round64(A->n) * 8);
-    GKB_HIP(gkb::launch_team_reset(team, A->m, A->n, st));
+  if (gkb::team_form(A->n, (int)A->dtype)) {
+    team = reinterpret_cast<char*>(workspace) +
+           align256((size_t)gkb::fused_blocks(A->m, A->n, (int)A->dtype) * round64(A->n) * 8);
+    GKB_HIP(gkb::launch_team_reset(team, A->m, A->n, (int)A->dtype, st));
   }
   GKB_HIP(gkb::launch_gemv_fused<float>(A->data, (int)A->dtype, A->lda, A->m, A->n, p, nullptr, w, y,
                                         reinterpret_cast<double*>(workspace), round64(A->n), nullptr, st, nullptr,

@@ -201,8 +201,9 @@ def _options(**kw):
 
 def test_one_pass_availability_and_workspace():
     """The one-sweep step needs float32 with n and lda multiples of 4 (bfloat16:
-    8), n <= 262144 (longer than 24576: team sweeps, with their exchange area
-    in the workspace) and a 16-byte aligned A; for any other A a one_pass request
+    8, float64: 2), n <= 262144 (float64: 131072; float32 rows longer than 24576
+    and all float64 rows: team sweeps, with their exchange area in the
+    workspace) and a 16-byte aligned A; for any other A a one_pass request
     takes the two-product step, so it passes the option checks (and here stops
     at the missing workspace) and its workspace is the two-product one.  The
     one-sweep workspace holds float64 bases and A^T Q."""
@@ -217,7 +218,8 @@ def test_one_pass_availability_and_workspace():
     others = [_fake_matrix(n=50),                       # n % 4
               _fake_matrix(n=52, lda=54),               # lda % 4
               _fake_matrix(n=52, data=0x1004),          # alignment
-              _fake_matrix(n=52, dtype=gkb.GKB_F64),    # float64
+              _fake_matrix(n=51, dtype=gkb.GKB_F64),    # float64 needs n % 2
+              _fake_matrix(n=131074, dtype=gkb.GKB_F64),  # float64 n > 131072
               _fake_matrix(n=52, dtype=gkb.GKB_BF16),   # bfloat16 needs n % 8
               _fake_matrix(m=100, n=262148)]            # n > 262144
     for bad in others:
@@ -243,6 +245,11 @@ def test_one_pass_availability_and_workspace():
     assert L.gkb_matvec_fused_workspace_size(C.byref(_fake_matrix(n=50))) == 0
     assert L.gkb_matvec_fused_workspace_size(C.byref(_fake_matrix(n=52))) > 0
     assert L.gkb_matvec_fused_workspace_size(C.byref(_fake_matrix(n=262148))) == 0
+    # float64 A: the one-sweep step through teams, but not the float32-input building block
+    f64 = _fake_matrix(2000, 1000, gkb.GKB_F64)
+    assert L.gkb_workspace_size(C.byref(f64), 10, 30, C.byref(one)) > \
+        L.gkb_workspace_size(C.byref(f64), 10, 30, C.byref(two)) > 0
+    assert L.gkb_matvec_fused_workspace_size(C.byref(f64)) == 0
     assert L.gkb_matvec_fused_workspace_size(C.byref(wide)) >= 20000 * 10 * 16 + 80000 * 8
 
 

@@ -194,13 +194,13 @@ def test_onepass_deterministic():
 
 def test_onepass_falls_back_to_two_products():
     """Where the one-sweep step is not available (n not a multiple of 4, a
-    float64 A, rows longer than the team sweep takes) a one_pass request runs
+    float64 A of odd n, rows longer than the team sweep takes) a one_pass request runs
     the two-product step: bitwise the same results as without the request, and
     stats say which step ran."""
     device()
     banner("one-pass fallback to the two-product step")
     rng = np.random.default_rng(0)
-    cases = [rng.standard_normal((50, 30)).astype(np.float32), rng.standard_normal((50, 32)),
+    cases = [rng.standard_normal((50, 30)).astype(np.float32), rng.standard_normal((50, 31)),
              rng.standard_normal((40, 262148)).astype(np.float32)]
     for A in cases:
         Ad = to_dev(A)
@@ -332,3 +332,77 @@ def test_onepass_request_past_the_team_limit():
     assert stats["one_pass_used"] == 0
     assert status == ref["status"] == 0
     _check_against(ref, sigma, U, V, 16)
+
+
+ONEPASS_TAU = 1e-10   # the recovery guard: a column past tau sigma_1 is recomputed directly
+
+
+def _check_f64(ref, sigma, U, V, k):
+    """float64 A: every stored A^T q column is within ONEPASS_TAU sigma_1 of the
+    exact one (or recomputed), so the factorisation is that of A + E with
+    ||E|| <= sqrt(k) tau sigma_1 (one column error per step) and, by Weyl,
+    each singular value moves by at most that much."""
+    bound = np.sqrt(k) * ONEPASS_TAU * ref["sigma"][0]
+    err = np.abs(sigma - ref["sigma"])
+    print(f"float64 one-pass sigma max abs err {err.max():.3e} ({err.max() / ref['sigma'][0]:.2e} sigma_1; "
+          f"bound {bound:.3e})", flush=True)
+    assert np.all(err <= bound)
+    al = checks.alignment(ref["U"], ref["V"], U, V)
+    print(f"float64 one-pass alignment min {al.min():.12f}", flush=True)
+    assert np.min(al) >= 1 - 1e-8
+
+
+@pytest.mark.parametrize("shape", [(3000, 1500), (400, 20000)])
+def test_onepass_float64(shape):
+    """float64 A through the team sweep (4096-column slices: 1 and 5 members),
+    against the float64 oracle: the singular values within the recovery bound,
+    the same product count as the two-product run, U and V float64."""
+    import torch
+    device()
+    m, n = shape
+    banner(f"one-pass float64 {m}x{n}")
+    A, s, _, _ = inputs.lowrank_noise(m, n, 100, 0.9, 1e-6, seed=m + n, dtype=np.float64)
+    q = inputs.start_vector(m, seed=9)
+    ref = gk.partial_svd(A, 10, 30, 1e-6, 20, q, eps_break=1e-12)
+    sigma, Ut, Vt, status, stats = gkb.gkb_partial_svd(to_dev(A), 10, 30, 1e-6, 20, q1=to_dev(q), one_pass=True)
+    torch.cuda.synchronize()
+    print("stats", stats, flush=True)
+    assert stats["one_pass_used"] == 1 and Ut.dtype == torch.float64
+    assert status == ref["status"] == 0
+    _check_f64(ref, sigma, to_host(Ut).T, to_host(Vt).T, 30)
+    two = gkb.gkb_partial_svd(to_dev(A), 10, 30, 1e-6, 20, q1=to_dev(q))
+    assert two[4]["one_pass_used"] == 0
+    assert stats["matvecs"] - stats["refreshes"] == two[4]["matvecs"] or stats["restarts"] != two[4]["restarts"]
+
+
+def test_onepass_float64_cpu_sized_config():
+    """The CPU-sized float64 workload (2000 x 1000, Q1 diag(10^(-i/100)) Q2^T,
+    top 10, k 30, tol 1e-10) with the one-sweep step: the singular values
+    within the recovery bound of the prescribed spectrum and of the oracle."""
+    device()
+    banner("one-pass float64 2000x1000 prescribed spectrum")
+    s = inputs.decade_spectrum(1000)
+    A, _, _ = inputs.svd_matrix(2000, 1000, s, seed=0)
+    q = inputs.start_vector(2000, seed=2)
+    ref = gk.partial_svd(A, 10, 30, 1e-10, 50, q, eps_break=1e-12)
+    sigma, U, V, status, stats = run(A, 10, 30, 1e-10, 50, q, one_pass=True)
+    print("stats", stats, "oracle restarts", ref["restarts"], flush=True)
+    assert stats["one_pass_used"] == 1 and status == ref["status"] == 0
+    _check_f64(ref, sigma, U, V, 30)
+    assert np.max(np.abs(sigma - s[:10])) <= np.sqrt(30) * ONEPASS_TAU * s[0]
+
+
+@pytest.mark.parametrize("l", [5, 37])
+def test_onepass_float64_rank(l):
+    """Exact-rank float64 products through the one-sweep rank: rank l, as the
+    oracle and the two-product rank."""
+    from oracle import rank as orank
+    device()
+    banner(f"one-pass float64 rank l={l}")
+    A = inputs.product_matrix(600, 400, l, seed=7)
+    q = inputs.start_vector(600, seed=3)
+    ref = orank.numerical_rank(A, 1e-8, q)
+    rank, rank_s, sig, status, stats = gkb.gkb_numerical_rank(to_dev(A), 1e-8, q1=to_dev(q), one_pass=True)
+    rank2, _, _, _, st2 = gkb.gkb_numerical_rank(to_dev(A), 1e-8, q1=to_dev(q))
+    assert stats["one_pass_used"] == 1 and st2["one_pass_used"] == 0
+    assert rank == l and rank_s == l and rank2 == l and ref["rank"] == l
