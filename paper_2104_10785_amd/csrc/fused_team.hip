@@ -125,12 +125,16 @@ __global__ __launch_bounds__(T) void k_gemv_fused_team(const TA* __restrict__ A,
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t tag = GIVEN_W ? 0u : __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
   // the slice of p, zero padded to U T groups (the dot products read it from
-  // LDS): float32 for float32 and bfloat16 rows, as it is for float64 rows
-  using PL = typename std::conditional<sizeof(TA) == 8, double, float>::type;
+  // LDS): float32 for bfloat16 rows (float32 dot products), float64 otherwise
+  // (for float32 rows: p rounded to float32 once, then widened exactly, so
+  // the dot products convert only the row's elements)
+  using PL = typename std::conditional<Elems<TA>::F32DOT, float, double>::type;
   extern __shared__ __align__(16) unsigned char pl_raw[];
   PL* pl = reinterpret_cast<PL*>(pl_raw);
   if constexpr (!GIVEN_W) {
-    for (int j = tid; j < U * T * VN; j += T) pl[j] = j < sg * VN ? (PL)p[(int64_t)g0 * VN + j] : (PL)0;
+    for (int j = tid; j < U * T * VN; j += T)
+      pl[j] = j < sg * VN ? (sizeof(TA) == 8 ? (PL)p[(int64_t)g0 * VN + j] : (PL)(float)p[(int64_t)g0 * VN + j])
+                          : (PL)0;
     __syncthreads();
   }
   const int r0 = team * rpt;
@@ -216,21 +220,19 @@ __global__ __launch_bounds__(T) void k_gemv_fused_team(const TA* __restrict__ A,
           for (int r = 0; r < R; ++r) d[r] += Elems<TA>::at(rows[r][u], e) * pv[e];
       }
     } else {
+      // float32 rows: p in LDS as float64 (two 16-byte reads per group)
 #pragma unroll
       for (int r = 0; r < R; ++r) d[r] = 0.0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int g = tid + u * T;
+        const fdev::d2 p0 = reinterpret_cast<const fdev::d2*>(pl)[2 * g];
+        const fdev::d2 p1 = reinterpret_cast<const fdev::d2*>(pl)[2 * g + 1];
+        const double pe[4] = {p0[0], p0[1], p1[0], p1[1]};
 #pragma unroll
-        for (int h = 0; h < VN / 4; ++h) {
-          const f4 pv = reinterpret_cast<const f4*>(pl)[(VN / 4) * g + h];
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const double pe = (double)pv[e];
-#pragma unroll
-            for (int r = 0; r < R; ++r) d[r] += (double)Elems<TA>::at(rows[r][u], 4 * h + e) * pe;
-          }
-        }
+          for (int r = 0; r < R; ++r) d[r] += (double)Elems<TA>::at(rows[r][u], e) * pe[e];
       }
     }
 #pragma unroll
@@ -378,7 +380,13 @@ hipError_t launch_team_t(const TA* A, int64_t lda, int64_t m, int64_t n, const T
   if (ts.C == 0 || team == nullptr) return hipErrorInvalidValue;
   uint32_t* ctr = reinterpret_cast<uint32_t*>(team);
   uint64_t* mbox = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(team) + 256);
-  const size_t lds = GIVEN_W ? 0 : (size_t)U * TM_T * Elems<TA>::VN * (sizeof(TA) == 8 ? 8 : 4);
+  const size_t lds = GIVEN_W ? 0 : (size_t)U * TM_T * Elems<TA>::VN * (Elems<TA>::F32DOT ? 4 : 8);
+  if constexpr (!GIVEN_W) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_gemv_fused_team<TM_T, U, TM_R, TM_NB, TM_D, TA, TP, GIVEN_W>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+  }
   hipLaunchKernelGGL((k_gemv_fused_team<TM_T, U, TM_R, TM_NB, TM_D, TA, TP, GIVEN_W>), dim3(ts.nteams * ts.C),
                      dim3(TM_T), lds, st, A, lda, (int)m, n, p, win, ts.C, ts.rpt, ts.nsteps, w, ypart, ldy,
                      const_cast<int*>(flag), run_if, qprev, coef, mbox, ctr);
