@@ -1,16 +1,17 @@
 // One sweep of A for both products of a Golub-Kahan step on rows longer than
-// the single-workgroup sweep holds (n > FUSED_NMAX): a team of workgroups per
-// range of rows, each member owning a slice of the columns.
+// the single-workgroup sweep holds (n > FUSED_NMAX), and on float64 rows: a
+// team of workgroups per range of rows, each member owning a slice of the
+// columns.
 //
 // The single-workgroup sweep keeps its float64 partial of A^T w in registers,
 // which bounds the row length.  Here the 16-byte column groups are cut into C
-// near-equal slices of at most 8192 columns (4096 for float64 rows, which
-// only this form takes), and C workgroups -- a team -- share a range of rows.  Member c streams its slice
-// of each row, forms the slice's part of the row's dot product with p
-// (reduced across the workgroup in a fixed order) and publishes it; once all
-// C parts of a row are in, every member adds them in member order (so every
-// member holds the same w_i) and adds a_i[slice] w_i into its float64 partial
-// of A^T w.  The team's partial is one row of the partial-sum array, which
+// near-equal slices of at most 8192 columns (4096 for float64 rows: 32 KB of
+// a row either way), and C workgroups -- a team -- share a range of rows.
+// Member c streams its slice of each row, forms the slice's part of the row's
+// dot product with p (reduced across the workgroup in a fixed order) and
+// publishes it; once all C parts of a row are in, every member adds them in
+// member order (so every member holds the same w_i) and adds a_i[slice] w_i
+// into its float64 partial of A^T w.  The team's partial is one row of the partial-sum array, which
 // the consumers add in team order, as they add the workgroups' partials of
 // the single-workgroup sweep.
 //
@@ -39,8 +40,8 @@
 // so every wave runs the same instruction stream.
 //
 // Members of a team must run at the same time: the grid has at most one
-// workgroup per compute unit and the kernel's registers allow one per CU, so
-// the whole grid is resident once the device is free.  A wait is bounded
+// workgroup per compute unit and every CU holds at least one of them, so the
+// whole grid is resident once the device is free.  A wait is bounded
 // (TM_SPIN_LIMIT polls, about a second); on a timeout the flag is set to 4,
 // the member's outputs are set to NaN, and the wave stops waiting.
 #include <hip/hip_runtime.h>
