@@ -21,14 +21,21 @@ def _same(a, b):
         assert a[4][key] == b[4][key], key
 
 
-@pytest.mark.parametrize("case", ["f64_restarts", "f64_checks", "f32_one_pass_checks", "f32_two_product"])
+@pytest.mark.parametrize("case", ["f64_restarts", "f64_checks", "f32_one_pass_checks", "f32_two_product",
+                                  "f64_one_pass_restarts", "f32_team_one_pass_checks"])
 def test_plan_matches_direct_solves(case):
+    """The last two cases capture the team sweep (float64 rows; 30000-column
+    float32 rows): its mailbox generation lives on the device, so replays
+    advance it as the direct solves do."""
     import torch
     device()
     if case.startswith("f64"):
         s = inputs.decade_spectrum(1000)
         A, _, _ = inputs.svd_matrix(2000, 1000, s, seed=0)
-        r, k, tol, every, one_pass = 10, 30, 1e-10, (5 if case == "f64_checks" else 0), False
+        r, k, tol, every, one_pass = 10, 30, 1e-10, (5 if case == "f64_checks" else 0), "one_pass" in case
+    elif case == "f32_team_one_pass_checks":
+        A, _, _, _ = inputs.lowrank_noise(1500, 30000, 60, 0.9, 1e-6, seed=11, dtype=np.float32)
+        r, k, tol, every, one_pass = 8, 24, 1e-6, 4, True
     else:
         A, _, _, _ = inputs.lowrank_noise(6000, 2500, 200, 0.95, 1e-6, seed=7, dtype=np.float32)
         r, k, tol, every, one_pass = 20, 60, 1e-6, (5 if "checks" in case else 0), case.endswith("checks")
