@@ -38,7 +38,8 @@ TRAFFIC = {
     "gemv_n": ("gemv_c2_f32_hbm_traffic.md", ["paper_2104_10785_amd/csrc/gemv.hip", "paper_2104_10785_amd/csrc/gemv.h",
                                               "paper_2104_10785_amd/csrc/device_common.h"]),
     "gemv_fused": ("gemv_fused_c2_f32_hbm_traffic.md", ["paper_2104_10785_amd/csrc/fused.hip",
-                                                        "paper_2104_10785_amd/csrc/fused.h"]),
+                                                        "paper_2104_10785_amd/csrc/fused.h",
+                                                        "paper_2104_10785_amd/csrc/fused_device.h"]),
 }
 TRAFFIC["gemv_t"] = TRAFFIC["gemv_n"]
 
