@@ -9,7 +9,7 @@
 namespace gkb {
 
 constexpr int64_t FUSED_NMAX = 24576;    // longest row of the single-workgroup sweep (768 threads x 8 groups of 4 floats)
-constexpr int64_t FUSED_TEAM_NMAX = 262144;   // longest row of the team sweep (32 members x 8192 columns)
+constexpr int64_t FUSED_TEAM_NMAX = 262144;   // longest float32 or bfloat16 row of the team sweep (32 x 8192 columns)
 constexpr int64_t FUSED_TEAM_NMAX_F64 = 131072;   // the same for float64 rows (32 members x 4096 columns)
 // a recovered A^T q column is recomputed directly once its error bound
 // exceeds this fraction of the largest coefficient seen
@@ -28,7 +28,8 @@ inline bool team_form(int64_t n, int dtype) { return dtype == 0 || n > FUSED_NMA
 int fused_blocks(int64_t m, int64_t n, int dtype);
 
 // The team sweep: C members per team, each owning a near-equal slice of at
-// most 8192 columns (4096 for float64: 32 KB of a row either way); teams of
+// most 8192 columns (4096 for float64, 16384 for bfloat16: 32 KB of a row in
+// each case); teams of
 // rpt rows (the last may be shorter, none empty), nsteps steps of rows per
 // team; C = 0 if the shape has no team form.
 struct TeamShape {

@@ -5,8 +5,9 @@
 //
 // The single-workgroup sweep keeps its float64 partial of A^T w in registers,
 // which bounds the row length.  Here the 16-byte column groups are cut into C
-// near-equal slices of at most 8192 columns (4096 for float64 rows: 32 KB of
-// a row either way), and C workgroups -- a team -- share a range of rows.
+// near-equal slices of at most 8192 columns (4096 for float64 rows, 16384
+// for bfloat16: 32 KB of a row in each case), and C workgroups -- a team --
+// share a range of rows.
 // Member c streams its slice of each row, forms the slice's part of the row's
 // dot product with p (reduced across the workgroup in a fixed order) and
 // publishes it; once all C parts of a row are in, every member adds them in
@@ -67,16 +68,21 @@ using fdev::wsum_dpp;
 
 constexpr int TM_T = 512;          // threads per member
 constexpr int TM_R = 1;            // rows per step
-constexpr int TM_NB = 3;           // steps of rows in flight (two loading ahead)
-constexpr int TM_D = 5;            // steps between a step's parts and their use
 constexpr int TM_CMAX = 32;        // members per team (C R parts per step, one per lane)
-constexpr int TM_SLICE = 8192;     // columns per member at most (4096 for float64: 32 KB of a row)
 constexpr long TM_SPIN_LIMIT = 1L << 20;
 static_assert(TM_CMAX * TM_R <= 64, "a step's parts are read one per lane");
 
-template <typename TA> constexpr int tm_slice() { return sizeof(TA) == 8 ? TM_SLICE / 2 : TM_SLICE; }
-template <typename TA> constexpr int tm_u() { return tm_slice<TA>() / (TM_T * Elems<TA>::VN); }
+// Per element type: columns per member at most (32 KB of a row per step:
+// 8192 float32, 4096 float64, 16384 bfloat16), steps of rows in flight (NB)
+// and steps between a step's parts and their use (D), as measured; the
+// bfloat16 form holds twice the partial sums per thread, so one step fewer
+// in flight.
+constexpr int slice_cols(int dtype) { return dtype == 0 ? 4096 : (dtype == 2 ? 16384 : 8192); }
 template <typename TA> constexpr int tm_dtype() { return sizeof(TA) == 8 ? 0 : (sizeof(TA) == 2 ? 2 : 1); }
+template <typename TA> constexpr int tm_slice() { return slice_cols(tm_dtype<TA>()); }
+template <typename TA> constexpr int tm_u() { return tm_slice<TA>() / (TM_T * Elems<TA>::VN); }
+template <typename TA> constexpr int tm_nb() { return sizeof(TA) == 2 ? 2 : 3; }
+template <typename TA> constexpr int tm_d() { return 5; }
 
 __device__ __forceinline__ uint64_t ld_dev(const uint64_t* p) {
   return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -376,7 +382,7 @@ template <typename TA, typename TP, bool GIVEN_W>
 hipError_t launch_team_t(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p, const double* win, double* w,
                          double* ypart, int64_t ldy, const int* flag, const int* run_if, const double* qprev,
                          const double* coef, void* team, hipStream_t st) {
-  constexpr int U = tm_u<TA>();
+  constexpr int U = tm_u<TA>(), NB = tm_nb<TA>(), D = tm_d<TA>();
   const TeamShape ts = team_shape(m, n, tm_dtype<TA>());
   if (ts.C == 0 || team == nullptr) return hipErrorInvalidValue;
   uint32_t* ctr = reinterpret_cast<uint32_t*>(team);
@@ -384,11 +390,11 @@ hipError_t launch_team_t(const TA* A, int64_t lda, int64_t m, int64_t n, const T
   const size_t lds = GIVEN_W ? 0 : (size_t)U * TM_T * Elems<TA>::VN * (Elems<TA>::F32DOT ? 4 : 8);
   if constexpr (!GIVEN_W) {
     static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_gemv_fused_team<TM_T, U, TM_R, TM_NB, TM_D, TA, TP, GIVEN_W>),
+        reinterpret_cast<const void*>(&k_gemv_fused_team<TM_T, U, TM_R, NB, D, TA, TP, GIVEN_W>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess) return attr;
   }
-  hipLaunchKernelGGL((k_gemv_fused_team<TM_T, U, TM_R, TM_NB, TM_D, TA, TP, GIVEN_W>), dim3(ts.nteams * ts.C),
+  hipLaunchKernelGGL((k_gemv_fused_team<TM_T, U, TM_R, NB, D, TA, TP, GIVEN_W>), dim3(ts.nteams * ts.C),
                      dim3(TM_T), lds, st, A, lda, (int)m, n, p, win, ts.C, ts.rpt, ts.nsteps, w, ypart, ldy,
                      const_cast<int*>(flag), run_if, qprev, coef, mbox, ctr);
   return hipGetLastError();
@@ -400,7 +406,7 @@ TeamShape team_shape(int64_t m, int64_t n, int dtype) {
   // C = ceil(n / slice) members: near-equal slices of the 16-byte groups then
   // hold at most `slice` columns
   TeamShape ts{0, 0, 0, 0};
-  const int64_t slice = dtype == 0 ? TM_SLICE / 2 : TM_SLICE;
+  const int64_t slice = slice_cols(dtype);
   const int64_t C = (n + slice - 1) / slice;
   const int slots = device_cus();   // one member per compute unit
   if (m < 1 || n < 1 || C > TM_CMAX || C > slots) return ts;
