@@ -35,8 +35,10 @@ gkb_status gkb_matvec(const gkb_matrix* A, int trans, const void* x, double* y, 
  * aligned, n <= 262144; p float32, n entries).  A workgroup streams a range
  * of rows once, reducing each row's dot product before adding the row, scaled
  * by it, into its partial of A^T w; rows longer than 24576 are split into
- * slices of at most 8192 columns, one per workgroup of a team, whose members
- * exchange their parts of each row's dot product through the workspace.  The
+ * slices of at most 8192 (float32) or 16384 (bfloat16) columns, one per
+ * workgroup of a team, whose members exchange their parts of each row's dot
+ * product through the workspace.  float64 A is rejected here (p is float32);
+ * the solvers' one_pass option takes it.  The
  * partials (in gkb_matvec_fused_workspace_size bytes, with the teams'
  * exchange area, which each call zeroes first) are added in a fixed order, so
  * results are reproducible.  A^T q of the next Lanczos vector then follows
