@@ -44,11 +44,15 @@
 // workgroup per compute unit and every CU holds at least one of them, so the
 // whole grid is resident once the device is free.  A wait is bounded
 // (TM_SPIN_LIMIT polls, about a second); on a timeout the flag is set to 4,
-// the member's outputs are set to NaN, and the wave stops waiting.
+// the member's outputs are set to NaN, and the wave stops waiting.  For
+// tests of that path the environment variable GKB_TEAM_STALL_POLLS = P > 0
+// makes every wait time out after P polls: readers then look for a tag that
+// no member writes (every kernel still runs to its end).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <type_traits>
 
 #include "device_common.h"
@@ -104,6 +108,8 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 // member's slice), R rows per step.  GIVEN_W: y = A^T win (no dot products,
 // no exchange; win is loaded with the rows).  ctr[0]: generation, ctr[1]:
 // workgroups finished in this launch; mbox: teams x nsteps x C x R x 2 words.
+// spin_limit bounds each wait; readers accept the launch's tag + skew
+// (skew 0 except in tests of the timeout path).
 template <int T, int U, int R, int NB, int D, typename TA, typename TP, bool GIVEN_W>
 __global__ __launch_bounds__(T) void k_gemv_fused_team(const TA* __restrict__ A, int64_t lda, int m, int64_t n,
                                                        const TP* __restrict__ p, const double* __restrict__ win,
@@ -112,7 +118,7 @@ __global__ __launch_bounds__(T) void k_gemv_fused_team(const TA* __restrict__ A,
                                                        const int* __restrict__ run_if,
                                                        const double* __restrict__ qprev,
                                                        const double* __restrict__ coef, uint64_t* mbox,
-                                                       uint32_t* ctr) {
+                                                       uint32_t* ctr, long spin_limit, uint32_t skew) {
   constexpr int DD = GIVEN_W ? 0 : D;
   constexpr int K = NB + DD;   // row buffers
   // a step's words are loaded LL iterations before they are checked, before
@@ -131,6 +137,7 @@ __global__ __launch_bounds__(T) void k_gemv_fused_team(const TA* __restrict__ A,
   __shared__ double red[2][R][NWV];                              // [parity][row][wave]
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t tag = GIVEN_W ? 0u : __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+  const uint32_t expect = tag + skew;   // the tag a reader takes
   // the slice of p, zero padded to U T groups (the dot products read it from
   // LDS): float32 for bfloat16 rows (float32 dot products), float64 otherwise
   // (for float32 rows: p rounded to float32 once, then widened exactly, so
@@ -272,16 +279,16 @@ __global__ __launch_bounds__(T) void k_gemv_fused_team(const TA* __restrict__ A,
   // w of step s from its parts (lane l < C R holds entry l = c R + r), added
   // in member order; waits (bounded) for parts not yet in
   auto gather = [&](uint64_t (&mw)[2], int s, double (&wi)[R]) {
-    bool ok = lane >= CR || ((uint32_t)mw[0] == tag && (uint32_t)mw[1] == tag);
+    bool ok = lane >= CR || ((uint32_t)mw[0] == expect && (uint32_t)mw[1] == expect);
     if (!failed && __builtin_amdgcn_ballot_w64(!ok) != 0) {
       // every exit follows the test of the words just loaded, so no poll is
       // left in flight where this path rejoins the one that did not wait
       for (long polls = 0;; ++polls) {
         __builtin_amdgcn_s_sleep(2);
         mail_load(s, mw);
-        ok = lane >= CR || ((uint32_t)mw[0] == tag && (uint32_t)mw[1] == tag);
+        ok = lane >= CR || ((uint32_t)mw[0] == expect && (uint32_t)mw[1] == expect);
         if (__builtin_amdgcn_ballot_w64(!ok) == 0) break;
-        if (polls == TM_SPIN_LIMIT) {
+        if (polls >= spin_limit) {
           failed = true;
           break;
         }
@@ -387,6 +394,15 @@ hipError_t launch_team_t(const TA* A, int64_t lda, int64_t m, int64_t n, const T
   if (ts.C == 0 || team == nullptr) return hipErrorInvalidValue;
   uint32_t* ctr = reinterpret_cast<uint32_t*>(team);
   uint64_t* mbox = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(team) + 256);
+  long spin_limit = TM_SPIN_LIMIT;
+  uint32_t skew = 0;
+  if (const char* e = std::getenv("GKB_TEAM_STALL_POLLS")) {   // test of the timeout path
+    const long polls = std::atol(e);
+    if (polls > 0) {
+      spin_limit = polls;
+      skew = 1;
+    }
+  }
   const size_t lds = GIVEN_W ? 0 : (size_t)U * TM_T * Elems<TA>::VN * (Elems<TA>::F32DOT ? 4 : 8);
   if constexpr (!GIVEN_W) {
     static const hipError_t attr = hipFuncSetAttribute(
@@ -396,7 +412,7 @@ hipError_t launch_team_t(const TA* A, int64_t lda, int64_t m, int64_t n, const T
   }
   hipLaunchKernelGGL((k_gemv_fused_team<TM_T, U, TM_R, NB, D, TA, TP, GIVEN_W>), dim3(ts.nteams * ts.C),
                      dim3(TM_T), lds, st, A, lda, (int)m, n, p, win, ts.C, ts.rpt, ts.nsteps, w, ypart, ldy,
-                     const_cast<int*>(flag), run_if, qprev, coef, mbox, ctr);
+                     const_cast<int*>(flag), run_if, qprev, coef, mbox, ctr, spin_limit, skew);
   return hipGetLastError();
 }
 

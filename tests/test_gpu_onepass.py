@@ -406,3 +406,29 @@ def test_onepass_float64_rank(l):
     rank2, _, _, _, st2 = gkb.gkb_numerical_rank(to_dev(A), 1e-8, q1=to_dev(q))
     assert stats["one_pass_used"] == 1 and st2["one_pass_used"] == 0
     assert rank == l and rank_s == l and rank2 == l and ref["rank"] == l
+
+
+def test_team_sweep_timeout_path(monkeypatch):
+    """The team sweep's bounded wait, forced from the host: with
+    GKB_TEAM_STALL_POLLS set every wait gives up after a few polls (as when a
+    member never runs) while every kernel runs to its end.  The solve returns
+    GKB_ERR_TIMEOUT, the product pair returns NaN; without the setting the
+    next solve on the same matrix is normal (the mailbox is reset per solve)."""
+    import torch
+    device()
+    banner("team sweep timeout path (forced from the host)")
+    A32, s, _, _ = inputs.lowrank_noise(300, 30000, 40, 0.9, 1e-6, seed=21, dtype=np.float32)
+    q = inputs.start_vector(300, seed=4)
+    Ad = to_dev(A32)
+    monkeypatch.setenv("GKB_TEAM_STALL_POLLS", "8")
+    with pytest.raises(gkb.GkbError) as ei:
+        gkb.gkb_partial_svd(Ad, 4, 12, 1e-6, 5, q1=to_dev(q), one_pass=True)
+    assert ei.value.status == -5
+    w, y = gkb.gkb_matvec_fused(Ad, to_dev(np.ones(30000, dtype=np.float32)))
+    torch.cuda.synchronize()
+    assert torch.isnan(w).all().item() and torch.isnan(y).all().item()
+    monkeypatch.delenv("GKB_TEAM_STALL_POLLS")
+    ref = gk.partial_svd(A32.astype(np.float64), 4, 12, 1e-6, 5, q, eps_break=1e-6)
+    sigma, U, V, status, stats = run(A32, 4, 12, 1e-6, 5, q, one_pass=True)
+    assert status == ref["status"] == 0 and stats["one_pass_used"] == 1
+    _check_against(ref, sigma, U, V, 12)
