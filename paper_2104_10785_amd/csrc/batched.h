@@ -64,7 +64,16 @@ struct BatchParams {
   int nteams;
   double* team_buf;        // team reduction buffers
   int outline;             // 1: products and Gram-Schmidt kernels out of line (long rows)
+  long spin_limit;         // polls of a team barrier before it gives up (BATCH_TEAM_SPIN_LIMIT)
+  int barrier_skew;        // 0; 1 only in tests of the timeout path (no barrier can be met)
 };
+
+// Bound on the polls of a team barrier (each poll sleeps ~100 cycles and
+// reads one counter: about 10 s in all).  The environment variable
+// GKB_BATCH_STALL_POLLS = P > 0, read when a plan is made, sets the bound to
+// P and the barrier skew to 1, so every team barrier times out (for tests of
+// that path; every kernel still runs to its end).
+constexpr long BATCH_TEAM_SPIN_LIMIT = 1L << 23;
 
 // threads per workgroup: 512 or 1024
 size_t batched_lds_bytes(int threads);

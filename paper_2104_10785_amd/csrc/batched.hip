@@ -30,9 +30,6 @@ namespace {
 constexpr int KMAX = BATCH_KMAX;   // max Krylov dimension
 constexpr int HLD = KMAX + 2;      // LDS leading dimension of H columns
 constexpr int SLD = KMAX + 4;      // per-member stride of the small team reduction buffers
-// Bound on the polls of a team barrier (each poll sleeps ~100 cycles and
-// reads the counter from memory): about 10 s, far beyond any legitimate wait.
-constexpr long TEAM_SPIN_LIMIT = 1L << 23;
 
 // Pointers taken from the problem table are generic; the hot loops cast them
 // to the global (or LDS) address space so that the compiler emits global
@@ -104,6 +101,8 @@ struct Team {
   double* small;   // 2 x T x SLD partial dots / norms (alternating regions)
   int nbar;        // barriers this member has passed
   int parity;
+  long spin_limit; // polls before a barrier gives up (BatchParams)
+  int skew;        // added to a barrier's target (0; 1 only in tests of the timeout path)
 };
 
 // Data that members exchange (partial sums, the entries of p) is written and
@@ -135,11 +134,11 @@ __device__ void team_barrier(Team& tm, Lds<BT>& L) {
   ++tm.nbar;
   if (threadIdx.x == 0 && !L.team_fail) {
     __hip_atomic_fetch_add(tm.cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int target = tm.nbar * tm.T;
+    const int target = tm.nbar * tm.T + tm.skew;
     long polls = 0;
     while (__hip_atomic_load(tm.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
-      if (++polls > TEAM_SPIN_LIMIT) {
+      if (++polls > tm.spin_limit) {
         L.team_fail = 1;
         break;
       }
@@ -668,6 +667,8 @@ __device__ void solve_one(const BatchProblem& P, int member, const BatchParams& 
   tm.small = tm.zpart + (int64_t)P.team * n;
   tm.nbar = 0;
   tm.parity = 0;
+  tm.spin_limit = prm.spin_limit;
+  tm.skew = prm.barrier_skew;
   const int qlo = (int)((int64_t)member * m / tm.T), qhi = (int)((int64_t)(member + 1) * m / tm.T);
   const int plo = (int)((int64_t)member * n / tm.T), phi = (int)((int64_t)(member + 1) * n / tm.T);
   int cur = 0;
@@ -880,6 +881,8 @@ __device__ void solve_one(const BatchProblem& P, int member, const BatchParams& 
     }
     __syncthreads();
   }
+  // a team barrier that timed out voids the solve, whichever way it ended
+  if (L.team_fail) status = GKB_ERR_TIMEOUT;
   // ---------------- outputs (each member its rows of U and entries of V)
   const int pi = P.index;
   if (status == 0 && np > 0) {

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -302,6 +303,15 @@ gkb_status gkb_batched_plan_create(int batch, const gkb_matrix* As, const int* r
   prm.stage = reinterpret_cast<const gkb::StageCopy*>(ws + L.stage_tab);
   prm.nstage = (int)stage.size();
   prm.stage_rows = stage_rows;
+  prm.spin_limit = gkb::BATCH_TEAM_SPIN_LIMIT;
+  prm.barrier_skew = 0;
+  if (const char* e = std::getenv("GKB_BATCH_STALL_POLLS")) {   // test of the timeout path
+    const long polls = std::atol(e);
+    if (polls > 0) {
+      prm.spin_limit = polls;
+      prm.barrier_skew = 1;
+    }
+  }
   plan->info_dev = prm.info;
   plan->ticks_dev = prm.ticks;
   plan->ticks_per_ms = clock_khz > 0 ? (double)clock_khz : 1e5;

@@ -261,3 +261,40 @@ def test_batched_fullsize_sample_against_oracle():
               f"restarts {info[i, 2]} vs oracle {ref['restarts']}", flush=True)
         assert err <= bound32(A)
     plan.close()
+
+
+def test_batched_team_timeout_path(monkeypatch):
+    """The team barrier's bounded wait, forced from the host: a plan made with
+    GKB_BATCH_STALL_POLLS set gives every team barrier a target no team meets
+    and a few polls, so every problem solved by a team ends with
+    GKB_ERR_TIMEOUT while every kernel runs to its end; problems solved by
+    one workgroup are unaffected (bitwise equal to a normal plan's), and a
+    plan made without the setting solves every problem."""
+    device()
+    mats, rs, ks = small_batch(8, seed=31)
+    for j, (m, n) in enumerate([(2100, 900), (1600, 700)]):
+        mats.append(inputs.svd_matrix(m, n, np.geomspace(1, 1e-3, n), seed=40 + j)[0].astype(np.float32))
+        rs.append(10)
+        ks.append(30)
+    banner("batched team barrier timeout path (forced from the host)")
+    Ad = [to_dev(A) for A in mats]
+
+    def solve():
+        plan = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=3, check_every=5)
+        plan.run()
+        info = plan.info()
+        res = [(s.copy(), to_host(u), to_host(v)) for s, u, v in plan.results()]
+        plan.close()
+        return info, res
+
+    monkeypatch.setenv("GKB_BATCH_STALL_POLLS", "16")
+    i_stall, r_stall = solve()
+    monkeypatch.delenv("GKB_BATCH_STALL_POLLS")
+    i_ok, r_ok = solve()
+    print("statuses with stalled barriers", i_stall[:, 0].tolist(), "normal", i_ok[:, 0].tolist(), flush=True)
+    assert np.all(i_ok[:, 0] != -5) and np.all(np.isin(i_ok[:, 0], [0, 2]))
+    timed_out = i_stall[:, 0] == -5
+    assert timed_out[-2:].all()   # the two largest problems are solved by teams
+    for j in np.flatnonzero(~timed_out):
+        assert np.array_equal(i_stall[j], i_ok[j])
+        assert all(np.array_equal(a, b) for a, b in zip(r_stall[j], r_ok[j]))
