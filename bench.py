@@ -379,6 +379,7 @@ def batched_leg(gkb, inputs, torch, dev, stream):
            "A_bytes_GB": sum(sp["m"] * sp["n"] * 4 for sp in specs) / 1e9,
            "streamed_GBps": byts / (ms * 1e-3) / 1e9,
            "threads": plan.tuning["threads"], "workgroups": plan.tuning["workgroups"],
+           "form": "out of line" if plan.tuning["form"] == 2 else "inline", "max_team": plan.tuning["max_team"],
            "autotune_ms": plan.tuning["times_ms"]}
     plan.close()
     del As

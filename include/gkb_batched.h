@@ -100,19 +100,24 @@ int gkb_batched_plan_grid(gkb_batch_plan plan);
 void gkb_batched_plan_destroy(gkb_batch_plan plan);
 
 /*
- * Project autotuner for the batched launch: times every candidate
- * (workgroup size 512 or 1024, 1 or 2 workgroups per compute unit where the
- * LDS allows) on this batch with hipEvents on `stream`, after one untimed run
- * each, and returns the fastest in *best_threads / *best_workgroups.
- * times_ms (optional, *ncand entries) receives every candidate's time, in the
- * order (1024, 1/CU), (512, 1/CU), (512, 2/CU).  The outputs are written by
- * the runs.  Callers cache the choice (the Python binding keeps a JSON cache
- * keyed by device and batch shape).
+ * Project autotuner for the batched launch: times every candidate on this
+ * batch with hipEvents on `stream`, after one untimed run each, and returns
+ * the fastest.  Candidates: launch shape (workgroup size 1024 with one
+ * workgroup per compute unit, 512 with one, 512 with two, where the LDS
+ * allows) x compiled form (inline, out of line; only opt->form if it is
+ * non-zero) x team limit (8, 4; only opt->max_team if it is non-zero).
+ * The fastest goes to *best_threads, *best_workgroups, *best_form and
+ * *best_max_team (the last two may be NULL).  times_ms (optional, room for 12)
+ * receives every candidate's time, -1 for a shape the LDS does not allow, in
+ * the order shape, then form, then team limit; *ncand their count.  The
+ * outputs are written by the runs.  Callers cache the choice (the Python
+ * binding keeps a JSON cache keyed by device and batch shape).
  */
 gkb_status gkb_batched_autotune(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
                                 int max_restarts, const gkb_batch_options* opt, void* workspace,
                                 size_t ws_bytes, double* sigma, float* U, float* V, void* stream,
-                                int* best_threads, int* best_workgroups, double* times_ms, int* ncand);
+                                int* best_threads, int* best_workgroups, int* best_form, int* best_max_team,
+                                double* times_ms, int* ncand);
 
 /* One call: plan, run, info (host, 4 * batch ints, may be NULL), destroy. */
 gkb_status gkb_partial_svd_batched(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,

@@ -400,7 +400,8 @@ void gkb_batched_plan_destroy(gkb_batch_plan plan) {
 gkb_status gkb_batched_autotune(int batch, const gkb_matrix* As, const int* r, const int* k, double tol,
                                 int max_restarts, const gkb_batch_options* opt_in, void* workspace,
                                 size_t ws_bytes, double* sigma, float* U, float* V, void* stream,
-                                int* best_threads, int* best_workgroups, double* times_ms, int* ncand) {
+                                int* best_threads, int* best_workgroups, int* best_form, int* best_max_team,
+                                double* times_ms, int* ncand) {
   b_err.clear();
   if (!best_threads || !best_workgroups) return bfail(GKB_ERR_INVALID, "output pointers are NULL");
   gkb_batch_options opt;
@@ -417,6 +418,8 @@ gkb_status gkb_batched_autotune(int batch, const gkb_matrix* As, const int* r, c
   }
   const int cand_threads[3] = {1024, 512, 512};
   const int cand_per_cu[3] = {1, 1, 2};
+  const int forms[2] = {1, 2}, teams[2] = {8, 4};
+  const int nform = opt.form != 0 ? 1 : 2, nteam = opt.max_team != 0 ? 1 : 2;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   B_HIP(hipEventCreate(&e0));
@@ -424,13 +427,16 @@ gkb_status gkb_batched_autotune(int batch, const gkb_matrix* As, const int* r, c
   double best = 1e300;
   int n = 0;
   gkb_status rc = GKB_OK;
-  for (int c = 0; c < 3; ++c) {
+  for (int cf = 0; cf < 3 * nform * nteam && rc == GKB_OK; ++cf) {
+    const int c = cf / (nform * nteam), f = (cf / nteam) % nform, tm = cf % nteam;
     double t = -1.0;
     if (gkb::batched_lds_bytes(cand_threads[c]) * cand_per_cu[c] <= lds_max) {
       gkb_batch_options o = opt;
       o.threads = cand_threads[c];
       o.workgroups = cus * cand_per_cu[c];
       o.no_graph = 1;
+      if (opt.form == 0) o.form = forms[f];
+      if (opt.max_team == 0) o.max_team = teams[tm];
       gkb_batch_plan plan = nullptr;
       rc = gkb_batched_plan_create(batch, As, r, k, tol, max_restarts, &o, workspace, ws_bytes, sigma, U, V,
                                    stream, &plan);
@@ -449,6 +455,8 @@ gkb_status gkb_batched_autotune(int batch, const gkb_matrix* As, const int* r, c
         best = t;
         *best_threads = cand_threads[c];
         *best_workgroups = o.workgroups;
+        if (best_form) *best_form = o.form;
+        if (best_max_team) *best_max_team = o.max_team;
       }
     }
     if (times_ms) times_ms[n] = t;

@@ -175,7 +175,8 @@ def lib():
     L.gkb_batched_plan_work.restype = C.c_int
     L.gkb_batched_autotune.argtypes = [C.c_int, P(GkbMatrix), P(C.c_int), P(C.c_int), C.c_double, C.c_int,
                                        P(GkbBatchOptions), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
-                                       C.c_void_p, C.c_void_p, P(C.c_int), P(C.c_int), P(C.c_double), P(C.c_int)]
+                                       C.c_void_p, C.c_void_p, P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_int),
+                                       P(C.c_double), P(C.c_int)]
     L.gkb_batched_autotune.restype = C.c_int
     L.gkb_batched_last_error.argtypes = []
     L.gkb_batched_last_error.restype = C.c_char_p
@@ -657,6 +658,7 @@ class BatchPlan:
         if tune:
             self.tuning = self._autotune(tol, max_restarts, stream, tune_cache)
             o.threads, o.workgroups = self.tuning["threads"], self.tuning["workgroups"]
+            o.form, o.max_team = self.tuning["form"], self.tuning["max_team"]
             self.tuning["measured_costs"] = self.cost_estimate is not None
         self._create(tol, max_restarts, stream)
 
@@ -689,19 +691,20 @@ class BatchPlan:
                 cache = json.load(open(cache_path))
             except (OSError, ValueError):
                 cache = {}
-        if key in cache:
+        if key in cache and "form" in cache[key]:
             return dict(cache[key], cached=True)
         L = lib()
-        bt, bw, n = C.c_int(), C.c_int(), C.c_int()
-        times = (C.c_double * 8)()
+        bt, bw, bf, bm, n = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        times = (C.c_double * 12)()
         st = L.gkb_batched_autotune(self.batch, self.mats, self.r_arr, self.k_arr, float(tol), int(max_restarts),
                                     C.byref(self.opts), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
                                     C.c_void_p(self.sigma.data_ptr()), C.c_void_p(self.U.data_ptr()),
-                                    C.c_void_p(self.V.data_ptr()), _stream(stream), C.byref(bt), C.byref(bw), times,
-                                    C.byref(n))
+                                    C.c_void_p(self.V.data_ptr()), _stream(stream), C.byref(bt), C.byref(bw),
+                                    C.byref(bf), C.byref(bm), times, C.byref(n))
         if st != 0:
             raise GkbError(st, L.gkb_batched_last_error().decode())
-        res = {"threads": bt.value, "workgroups": bw.value, "times_ms": list(times[: n.value])}
+        res = {"threads": bt.value, "workgroups": bw.value, "form": bf.value, "max_team": bm.value,
+               "times_ms": list(times[: n.value])}
         if cache_path:
             cache[key] = res
             tmp = cache_path + ".tmp"

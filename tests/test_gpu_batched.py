@@ -204,8 +204,15 @@ def test_batched_autotuner_picks_a_valid_config(tmp_path):
     plan = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=9, tune=True, tune_cache=cache)
     t = plan.tuning
     assert t["threads"] in (512, 1024) and t["workgroups"] > 0 and not t["cached"]
+    assert t["form"] in (1, 2) and t["max_team"] in (4, 8)
     assert t["measured_costs"]
-    assert len(t["times_ms"]) == 3 and min(x for x in t["times_ms"] if x > 0) > 0
+    # launch shape x compiled form x team limit
+    assert len(t["times_ms"]) == 12 and min(x for x in t["times_ms"] if x > 0) > 0
+    # the choice is the fastest candidate (order: shape, form, team limit)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    shape = [(1024, 1), (512, 1), (512, 2)].index((t["threads"], t["workgroups"] // cus))
+    chosen = t["times_ms"][shape * 4 + (t["form"] - 1) * 2 + (0 if t["max_team"] == 8 else 1)]
+    assert chosen == min(x for x in t["times_ms"] if x > 0)
     plan.run()
     info = plan.info()
     res = plan.results()
@@ -214,7 +221,7 @@ def test_batched_autotuner_picks_a_valid_config(tmp_path):
     plan.close()
     # second plan on the same shapes reads the cache
     plan2 = gkb.BatchPlan(Ad, rs, ks, 1e-6, 20, seed=9, tune=True, tune_cache=cache)
-    assert plan2.tuning["cached"] and plan2.tuning["threads"] == t["threads"]
+    assert plan2.tuning["cached"] and plan2.tuning["threads"] == t["threads"] and plan2.tuning["form"] == t["form"]
     assert json.load(open(cache))
     plan2.close()
     # both workgroup sizes give the same results (per-problem work is identical)
