@@ -241,7 +241,11 @@ def test_batched_fullsize_sample_against_oracle():
     """The 512-problem batch (m in [500, 4000], n in [200, 2000], geometric
     spectra rho in [0.8, 0.99], r in [5, 20], k = min(n, 2r + 10)) solved in one
     launch; 6 problems (largest, smallest, and 4 drawn at random) re-solved by
-    the oracle."""
+    the oracle.  Every problem is also checked against what its construction
+    fixes at any size: its singular values are rho^(j-1), moved by at most
+    u32 ||A||_F by the float32 rounding (Weyl), and a converged triplet's
+    residuals bound its distance to them; the residuals themselves and the
+    orthonormality of U and V are formed on the device in float64."""
     import torch
     device()
     banner("batched 512 problems full configuration")
@@ -255,6 +259,29 @@ def test_batched_fullsize_sample_against_oracle():
     info = plan.info()
     res = plan.results()
     assert np.all(info[:, 0] == 0), np.unique(info[:, 0], return_counts=True)
+    tol = 1e-6
+    worst = [0.0, 0.0, 0.0]
+    for i, (sp, A, (sig, Ut, Vt)) in enumerate(zip(specs, As, res)):
+        r = rs[i]
+        assert sig.shape == (r,) and np.all(np.diff(sig) <= 0), (i, sig)
+        A64 = A.double()
+        fro = float(torch.linalg.norm(A64))
+        b32 = np.sqrt(max(sp["m"], sp["n"])) * U32 * fro
+        want = sp["rho"] ** np.arange(r, dtype=np.float64)
+        U = Ut.double().T.contiguous()
+        V = Vt.double().T.contiguous()
+        sd = torch.from_numpy(sig).to(A.device)
+        r1 = torch.linalg.norm(A64 @ V - U * sd[None, :], dim=0).max().item()
+        r2 = torch.linalg.norm(A64.T.contiguous() @ U - V * sd[None, :], dim=0).max().item()
+        eye = torch.eye(r, dtype=torch.float64, device=A.device)
+        orth = max(torch.linalg.norm(U.T @ U - eye).item(), torch.linalg.norm(V.T @ V - eye).item())
+        err = float(np.max(np.abs(sig - want)))
+        assert r1 <= 100 * b32 and r2 <= tol * sig[0] + 100 * b32, (i, r1, r2, b32)
+        assert err <= 2 * tol * want[0] + b32, (i, err, b32)
+        assert orth <= 1e-5, (i, orth)
+        worst = [max(worst[0], err), max(worst[1], r2), max(worst[2], orth)]
+    print(f"  all 512: sigma vs rho^(j-1) {worst[0]:.2e}, residual {worst[1]:.2e}, orthogonality {worst[2]:.2e}",
+          flush=True)
     sizes = np.array([sp["m"] * sp["n"] for sp in specs])
     rng = np.random.default_rng(0)
     pick = sorted(set([int(np.argmax(sizes)), int(np.argmin(sizes))] + list(rng.choice(512, 4, replace=False))))
