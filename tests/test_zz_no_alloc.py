@@ -1,8 +1,9 @@
 """gkb_partial_svd_noalloc (the library's fixed device array as workspace)
 against gkb_partial_svd with a caller workspace: same kernels, same layout,
 so the results must be bitwise equal; two calls in a row, the second on a
-smaller problem (the array keeps the first call's contents), plus the
-rejection of a problem whose workspace exceeds the array."""
+smaller problem (the array keeps the first call's contents), the one-sweep
+step on both the single-workgroup and the team sweep, plus the rejection of
+a problem whose workspace exceeds the array."""
 import numpy as np
 import pytest
 
@@ -55,6 +56,19 @@ def test_noalloc_matches_workspace_entry_point():
     # and the one-sweep step on the smaller problem
     ref3, got3 = _both(A2, 5, 20, 1e-6, 30, q2, one_pass=True)
     _same(ref3, got3)
+    # the one-sweep step through the team sweep, whose mailbox is part of the
+    # workspace: float64 rows, then float32 rows longer than one workgroup holds
+    A4, _, _ = inputs.svd_matrix(800, 500, np.geomspace(1.0, 1e-3, 500), seed=45)
+    q4 = inputs.start_vector(800, seed=46)
+    A5, _, _, _ = inputs.lowrank_noise(200, 24580, 40, 0.9, 1e-6, seed=47, dtype=np.float32)
+    q5 = inputs.start_vector(200, seed=48)
+    for name, Ax, qx, r, k in (("800x500 f64", A4, q4, 5, 20), ("200x24580 f32", A5, q5, 3, 12)):
+        need = gkb.gkb_workspace_size(to_dev(Ax), r, k, one_pass=True)
+        banner(f"no-alloc {name} one-sweep (team sweep) r={r} k={k} (workspace {need} bytes)")
+        assert 0 < need <= gkb.NOALLOC_SCRATCH_BYTES
+        ref4, got4 = _both(Ax, r, k, 1e-6, 30, qx, one_pass=True)
+        assert ref4[4]["one_pass_used"] == 1 and got4[4]["one_pass_used"] == 1
+        _same(ref4, got4)
 
 
 def test_noalloc_rejects_too_large():
