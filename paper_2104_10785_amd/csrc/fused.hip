@@ -22,6 +22,7 @@
 #include "fused.h"
 #include "fused_device.h"
 #include "gemv.h"
+#include "lds_attr.h"
 
 namespace gkb {
 
@@ -487,10 +488,9 @@ hipError_t launch_v(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p,
                     double* ypart, int64_t ldy, const int* flag, const int* run_if, hipStream_t st,
                     const double* qprev = nullptr, const double* coef = nullptr) {
   if constexpr (!GIVEN_W) {
-    // once per process (initialisation of a function-local static is thread-safe)
-    static const hipError_t attr =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)(FUSED_NMAX * 4));
+    const hipError_t attr =
+        allow_dynamic_lds(reinterpret_cast<const void*>(&k_gemv_fused<T, U, R, D, TA, TP, GIVEN_W>),
+                          (int)(FUSED_NMAX * 4));
     if (attr != hipSuccess) return attr;
   }
   const int nb = fused_blocks(m, n, 1);
@@ -555,9 +555,9 @@ hipError_t launch_p(const TA* A, int64_t lda, int64_t m, int64_t n, const TP* p,
                     const double* qprev = nullptr, const double* coef = nullptr) {
   if (!pipe_fits<T, U, R, NB, TA>(m, n, GIVEN_W)) return hipErrorInvalidValue;
   if constexpr (!GIVEN_W) {
-    static const hipError_t attr =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemv_fused_pipe<T, U, R, NB, TA, TP, GIVEN_W>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, PIPE_LDS_MAX);
+    const hipError_t attr =
+        allow_dynamic_lds(reinterpret_cast<const void*>(&k_gemv_fused_pipe<T, U, R, NB, TA, TP, GIVEN_W>),
+                          PIPE_LDS_MAX);
     if (attr != hipSuccess) return attr;
   }
   const int nb = fused_blocks(m, n, 1);

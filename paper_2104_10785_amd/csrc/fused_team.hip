@@ -59,6 +59,7 @@
 #include "fused.h"
 #include "fused_device.h"
 #include "gemv.h"
+#include "lds_attr.h"
 
 namespace gkb {
 
@@ -405,9 +406,8 @@ hipError_t launch_team_t(const TA* A, int64_t lda, int64_t m, int64_t n, const T
   }
   const size_t lds = GIVEN_W ? 0 : (size_t)U * TM_T * Elems<TA>::VN * (Elems<TA>::F32DOT ? 4 : 8);
   if constexpr (!GIVEN_W) {
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_gemv_fused_team<TM_T, U, TM_R, NB, D, TA, TP, GIVEN_W>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t attr = allow_dynamic_lds(
+        reinterpret_cast<const void*>(&k_gemv_fused_team<TM_T, U, TM_R, NB, D, TA, TP, GIVEN_W>), (int)lds);
     if (attr != hipSuccess) return attr;
   }
   hipLaunchKernelGGL((k_gemv_fused_team<TM_T, U, TM_R, NB, D, TA, TP, GIVEN_W>), dim3(ts.nteams * ts.C),

@@ -20,6 +20,7 @@
 
 #include "device_common.h"
 #include "kernels.h"
+#include "lds_attr.h"
 #include "reorth.h"
 
 namespace gkb {
@@ -320,19 +321,18 @@ __global__ __launch_bounds__(GS_T) void k_gs_last(const TB* __restrict__ V, int6
   if (threadIdx.x == 0) npart[blockIdx.x] = tot;
 }
 
-// Allow launches of this kernel to use up to GS_LDS_MAX bytes of LDS (once per
-// process; the initialisation of a function-local static is thread-safe).
+// Allow launches of this kernel to use up to GS_LDS_MAX bytes of LDS on the
+// current device.
 template <typename K>
 hipError_t allow_lds(K kernel) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)GS_LDS_MAX);
+  return allow_dynamic_lds(reinterpret_cast<const void*>(kernel), (int)GS_LDS_MAX);
 }
 
 template <typename TB, typename TP, int PRE>
 hipError_t launch_first(const TB* V, int64_t ldv, int t, int64_t len, const GsSplit& s, double* x, double* P1,
                         int ldh, const GsPreArgs& pre, const int* flag, hipStream_t st) {
   auto kern = k_gs_first<TB, TP, PRE>;
-  static const hipError_t attr = allow_lds(kern);
+  const hipError_t attr = allow_lds(kern);
   if (attr != hipSuccess) return attr;
   const unsigned cb = (unsigned)std::max(1, (t + GS_COLS - 1) / GS_COLS);
   hipLaunchKernelGGL(kern, dim3(s.G, cb), dim3(GS_T), gs_lds_base(s.rows), st, V, ldv, t, len, s.rows, x, P1, ldh,
@@ -345,7 +345,7 @@ template <typename TB, bool STAGED>
 hipError_t launch_mid(const TB* V, int64_t ldv, int t, int64_t len, const GsSplit& s, double* x, const double* h1,
                       double* P2, int ldh, const int* flag, hipStream_t st) {
   auto kern = k_gs_mid<TB, STAGED>;
-  static const hipError_t attr = allow_lds(kern);
+  const hipError_t attr = allow_lds(kern);
   if (attr != hipSuccess) return attr;
   const size_t lds = gs_lds_base(s.rows) + (STAGED ? (size_t)t * s.rows * sizeof(TB) : 0);
   hipLaunchKernelGGL(kern, dim3(s.G), dim3(GS_T), lds, st, V, ldv, t, len, s.rows, x, h1, P2, ldh, flag);
@@ -426,7 +426,7 @@ hipError_t launch_gs2(const TB* V, int64_t ldv, int t, int64_t len, double* x, d
     }
   }
   auto kern = k_gs_last<TB>;
-  static const hipError_t attr = allow_lds(kern);
+  const hipError_t attr = allow_lds(kern);
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(kern, dim3(s.G), dim3(GS_T), gs_lds_base(s.rows), st, V, ldv, t, len, s.rows, x, h, npart,
                      flag);
