@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 
 #include "device_common.h"
@@ -214,15 +215,20 @@ hipError_t launch_gemv_n_t(const TA* A, int64_t lda, int64_t m, int64_t n, const
 }
 
 int device_cus() {
-  // queried once per process (thread-safe initialisation); 256 if the query fails
-  static const int cached = [] {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      return cus;
-    return 256;
-  }();
-  return cached;
+  // queried once per device (a partitioned GPU exposes fewer compute units);
+  // 256 if the query fails
+  constexpr int kDevs = 64;
+  static std::atomic<int> cached[kDevs];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev >= 0 && dev < kDevs) {
+    const int c = cached[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  if (dev >= 0 && dev < kDevs) cached[dev].store(cus, std::memory_order_relaxed);
+  return cus;
 }
 
 GemvTShape gemv_t_shape(int64_t m, int64_t n, int dtype_bytes) {
