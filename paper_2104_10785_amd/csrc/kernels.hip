@@ -520,6 +520,7 @@ __global__ __launch_bounds__(256) void k_gemm_rm(const float* __restrict__ A, in
 // tile (a0.., b0..) per block, W column-major float32 (m x d, ldw), products
 // and sums in float64 on the 16x16x4 MFMA.  Chunk = GRAM_ROWS rows.
 constexpr int GRAM_ROWS = 2048;
+constexpr int GRAM_U = 8;
 __global__ __launch_bounds__(64) void k_gram(const float* __restrict__ W, int64_t ldw, int64_t m, int d,
                                              double* __restrict__ Gpart, int64_t ldg) {
   const int lane = threadIdx.x;
@@ -531,11 +532,19 @@ __global__ __launch_bounds__(64) void k_gram(const float* __restrict__ W, int64_
   if (r1 > m) r1 = m;
   v4d acc = {0, 0, 0, 0};
   const int ca = a0 + li, cb = b0 + li;
-  for (int64_t i0 = r0; i0 < r1; i0 += 4) {
-    const int64_t i = i0 + lk;
-    const double av = (i < r1 && ca < d) ? (double)W[(int64_t)ca * ldw + i] : 0.0;
-    const double bv = (i < r1 && cb < d) ? (double)W[(int64_t)cb * ldw + i] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  // GRAM_U groups of 4 rows loaded before their MFMAs (one memory round trip
+  // per GRAM_U groups); one accumulator, so the products are added in row
+  // order; rows past r1 contribute exact zeros
+  for (int64_t i0 = r0; i0 < r1; i0 += 4 * GRAM_U) {
+    double av[GRAM_U], bv[GRAM_U];
+#pragma unroll
+    for (int u = 0; u < GRAM_U; ++u) {
+      const int64_t i = i0 + 4 * u + lk;
+      av[u] = (i < r1 && ca < d) ? (double)W[(int64_t)ca * ldw + i] : 0.0;
+      bv[u] = (i < r1 && cb < d) ? (double)W[(int64_t)cb * ldw + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < GRAM_U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
   }
   // float64 layout: element v of lane l is row 4v + l/16, column l % 16
 #pragma unroll
