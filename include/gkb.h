@@ -59,7 +59,11 @@ typedef enum {
   GKB_ERR_TIMEOUT = -5       /* a team of workgroups waited too long for one  */
                              /* of its members (batched form; one-sweep step */
                              /* on rows longer than 24576), which happens    */
-                             /* only if the device is not free for the grid  */
+                             /* only if the device is not free for the grid. */
+                             /* For tests of this path only, the environment */
+                             /* variable GKB_TEAM_STALL_POLLS = P > 0 (read  */
+                             /* at every team-sweep launch) makes each wait  */
+                             /* give up after P polls: leave it unset.       */
 } gkb_status;
 
 typedef enum {

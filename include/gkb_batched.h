@@ -15,7 +15,10 @@
  * first copied into zero-padded rows inside the workspace.  The queue reset,
  * the copy and the solver are captured once into a hipGraph per plan and
  * replayed by gkb_batched_plan_run.  A team barrier that waits too long
- * (about 10 s) ends that problem with info status GKB_ERR_TIMEOUT.
+ * (about 10 s) ends that problem with info status GKB_ERR_TIMEOUT.  For tests
+ * of that path only, the environment variable GKB_BATCH_STALL_POLLS = P > 0,
+ * read when a plan is created, gives that plan's team barriers a target no
+ * team meets and a limit of P polls: leave it unset.
  *
  * Problems: GKB_F32, row-major, device pointers, 1 <= r <= k <= min(m, n),
  * k <= 64.  Outputs are packed in problem order:
