@@ -1,17 +1,19 @@
 """Benchmark: partial SVD of the large float32 low-rank-plus-noise matrix.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-    python bench.py --kernels-only      # only the two matvecs and a 1 GiB copy
+    python bench.py --kernels-only      # only the product kernels, the Ritz GEMMs and a 1 GiB copy
 
 Workload: A = U_f diag(0.95^i)_{i=1..200} V_f^T + E, 50000 x 20000 float32,
 E iid N(0, (1e-6)^2) (synthetic, seeded); top 50 triplets, Krylov dimension
-120, tol 1e-6, up to 20 restarts.  One step = one gkb_partial_svd call (start
-vector, Golub-Kahan cycles with CGS2, host small SVDs, restarts, Ritz GEMMs),
-with A already resident in HBM.
+120, tol 1e-6, up to 20 restarts, in-cycle convergence tests every 10
+vectors.  One step = one gkb_partial_svd call (start vector, Golub-Kahan
+cycles with one sweep of A per step -- --two-pass for the two-product step --
+and CGS2, host small SVDs, restarts, Ritz GEMMs), with A already resident in
+HBM.
 
 Prints one JSON line: converged triplets per second (whole job), the
-roofline of the dominant kernel (the A-streaming matvecs), and the CPU oracle
-timed on a bounded sample of the same workload.
+roofline of the dominant kernel (the one-sweep product pair), the float64
+CPU oracle's full solves of the same workload, and the extra legs.
 """
 import argparse
 import hashlib
